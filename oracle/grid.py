@@ -1,0 +1,36 @@
+"""Uniform cell-centred pressure grid over an extended rectangular box
+(Sec. 2.3, double discretisation, Fig. 1; staggered placement as used with
+Neumann walls in Sec. 3.3).  Test infrastructure only."""
+from __future__ import annotations
+
+import dataclasses
+from typing import Tuple
+
+import numpy as np
+
+
+@dataclasses.dataclass(frozen=True)
+class Grid:
+    d: int
+    n: Tuple[int, ...]      # cells per axis
+    h: Tuple[float, ...]    # spacing per axis; box is [0, n_a h_a]
+
+    @property
+    def G(self) -> int:
+        return int(np.prod(self.n))
+
+    @property
+    def shape_zyx(self):
+        """numpy array shape with x fastest (C order)."""
+        return tuple(reversed(self.n))
+
+    def centres(self) -> np.ndarray:
+        """[G, d] cell centres (i_a + 1/2) h_a, flat index x-fastest."""
+        idx = np.indices(self.shape_zyx)
+        out = np.empty((self.G, self.d), dtype=np.float64)
+        for a in range(self.d):
+            out[:, a] = (idx[self.d - 1 - a].reshape(-1) + 0.5) * self.h[a]
+        return out
+
+    def to_array(self, flat: np.ndarray) -> np.ndarray:
+        return flat.reshape(self.shape_zyx)

@@ -1,0 +1,107 @@
+"""Pressure Poisson solve on the extended box (Sec. 2.3).
+
+The three-step transform algorithm of Sec. 2.3: forward 1D transforms along
+every axis, division by the eigenvalues (the sum of the 1D eigenvalues), and
+backward 1D transforms.  Readings (the paper delegates the choice of
+transform and eigenvalues to a table of Fuka 2015 that is not reproduced):
+
+  * grid: staggered / cell-centred (the grid used with Neumann walls in
+    Sec. 3.3);
+  * boundary condition: the homogeneous Neumann condition, Eq. (7), on every
+    box face, discretised with mirror ghosts phi_{-1} = phi_0,
+    phi_n = phi_{n-1};
+  * method: central finite differences (the variant used for the reported
+    timings of Sec. 3.2).  The mirror-ghost 3-point operator is diagonalised
+    by the DCT-II, with eigenvalues -(4/h^2) sin^2(pi k / (2n));
+  * zero mode: with Neumann walls everywhere the operator is singular; the
+    mean of the right-hand side (the compatibility defect) is removed and
+    reported, and the solution is taken with zero mean (the mode-0
+    coefficient is set to zero).  Fixing the pressure at one point
+    (Sec. 2.3, reference method; Sec. 3.1: zero at the left-bottom corner)
+    is an output gauge applied afterwards.
+
+Test infrastructure only.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.fft as sfft
+
+from .grid import Grid
+
+
+def eigenvalues(grid: Grid) -> np.ndarray:
+    """Sum of the 1D eigenvalues -(4/h_a^2) sin^2(pi k_a / (2 n_a)), as an
+    array of the grid's (z, y, x) shape."""
+    lam = np.zeros(grid.shape_zyx)
+    for a in range(grid.d):
+        k = np.arange(grid.n[a], dtype=np.float64)
+        la = -(4.0 / (grid.h[a] ** 2)) * np.sin(np.pi * k / (2.0 * grid.n[a])) ** 2
+        shape = [1] * grid.d
+        shape[grid.d - 1 - a] = grid.n[a]
+        lam = lam + la.reshape(shape)
+    return lam
+
+
+def solve(grid: Grid, b: np.ndarray, workers: int = -1):
+    """phi with L_h phi = b - mean(b) and mean(phi) = 0.  b: flat [G].
+    Returns (phi flat [G], bmean)."""
+    bm = float(np.mean(b))
+    B = grid.to_array(b - bm)
+    Bh = sfft.dctn(B, type=2, workers=workers)
+    lam = eigenvalues(grid)
+    lam.flat[0] = 1.0
+    Ph = Bh / lam
+    Ph.flat[0] = 0.0
+    phi = sfft.idctn(Ph, type=2, workers=workers)
+    return np.ascontiguousarray(phi).reshape(-1), bm
+
+
+def laplacian(grid: Grid, phi: np.ndarray) -> np.ndarray:
+    """Mirror-ghost central-difference Laplacian (the operator solve()
+    inverts).  phi flat [G] -> flat [G]."""
+    P = grid.to_array(phi)
+    out = np.zeros_like(P)
+    for a in range(grid.d):
+        ax = grid.d - 1 - a
+        lo = np.concatenate([np.take(P, [0], axis=ax), P], axis=ax)
+        hi = np.concatenate([P, np.take(P, [grid.n[a] - 1], axis=ax)], axis=ax)
+        up = np.take(hi, np.arange(1, grid.n[a] + 1), axis=ax)
+        dn = np.take(lo, np.arange(0, grid.n[a]), axis=ax)
+        out = out + (up - 2.0 * P + dn) / (grid.h[a] ** 2)
+    return out.reshape(-1)
+
+
+def laplacian_dense(grid: Grid) -> np.ndarray:
+    """The same operator as a dense [G, G] matrix, assembled cell by cell
+    (for tiny grids only)."""
+    G = grid.G
+    L = np.zeros((G, G))
+    strides = [int(np.prod(grid.n[:a])) for a in range(grid.d)]
+    for p in range(G):
+        rem = p
+        coords = []
+        for a in range(grid.d):
+            coords.append(rem % grid.n[a])
+            rem //= grid.n[a]
+        for a in range(grid.d):
+            inv = 1.0 / grid.h[a] ** 2
+            for step in (-1, 1):
+                c = coords[a] + step
+                q = p if (c < 0 or c >= grid.n[a]) else p + step * strides[a]
+                L[p, q] += inv
+                L[p, p] -= inv
+    return L
+
+
+def solve_bordered(grid: Grid, b: np.ndarray):
+    """Dense LU of [[L, 1], [1^T, 0]] [phi; mu] = [b; 0].  mu equals mean(b)
+    and phi has zero mean.  Tiny grids only."""
+    G = grid.G
+    K = np.zeros((G + 1, G + 1))
+    K[:G, :G] = laplacian_dense(grid)
+    K[:G, G] = 1.0
+    K[G, :G] = 1.0
+    rhs = np.concatenate([b, [0.0]])
+    sol = np.linalg.solve(K, rhs)
+    return sol[:G], float(sol[G])

@@ -1,0 +1,107 @@
+"""Pins for oracle.poisson against the mathematics of the Neumann-box
+problem (Sec. 2.3, Eq. 7): discrete eigenfunctions, the dense bordered
+system on tiny grids (an independent LU solve of the same operator, also at
+sizes that are not powers of two and with anisotropic spacing), the
+residual of the solved problem, and an exact rational solve."""
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from oracle import Grid, poisson
+
+
+def _eigvec(grid, ks):
+    idx = np.indices(grid.shape_zyx)
+    v = np.ones(grid.shape_zyx)
+    lam = 0.0
+    for a in range(grid.d):
+        i = idx[grid.d - 1 - a]
+        v = v * np.cos(np.pi * ks[a] * (i + 0.5) / grid.n[a])
+        lam += -(4.0 / grid.h[a] ** 2) * np.sin(np.pi * ks[a] / (2 * grid.n[a])) ** 2
+    return v.reshape(-1), lam
+
+
+@pytest.mark.parametrize("n,h,ks", [
+    ((64, 64), (1 / 64, 1 / 64), (3, 5)),
+    ((32, 16), (0.1, 0.03), (31, 1)),
+    ((16, 8, 32), (1 / 16, 0.2, 0.01), (2, 7, 9)),
+])
+def test_eigenfunctions(n, h, ks):
+    grid = Grid(len(n), n, h)
+    v, lam = _eigvec(grid, ks)
+    phi, bm = poisson.solve(grid, v)
+    assert abs(bm) < 1e-14
+    np.testing.assert_allclose(phi, v / lam, rtol=0, atol=1e-13 * np.abs(v / lam).max())
+    # the mirror-ghost operator has exactly these eigenpairs
+    np.testing.assert_allclose(poisson.laplacian(grid, v), lam * v, atol=1e-12 * abs(lam))
+
+
+def test_constant_rhs_gives_zero():
+    grid = Grid(2, (8, 16), (0.1, 0.2))
+    phi, bm = poisson.solve(grid, np.full(128, 3.5))
+    assert bm == pytest.approx(3.5, rel=1e-15)
+    assert np.max(np.abs(phi)) < 1e-13
+
+
+@pytest.mark.parametrize("n,h", [((3, 5), (0.3, 0.2)), ((8, 8), (1 / 8, 1 / 8)),
+                                 ((4, 4, 4), (0.25, 0.25, 0.25)),
+                                 ((2, 3, 5), (0.5, 0.1, 0.7))])
+def test_bordered_lu(rng, n, h):
+    grid = Grid(len(n), n, h)
+    b = rng.normal(size=grid.G)
+    phi, bm = poisson.solve(grid, b)
+    phi2, mu = poisson.solve_bordered(grid, b)
+    assert mu == pytest.approx(np.mean(b), abs=1e-13)
+    assert bm == pytest.approx(mu, abs=1e-13)
+    np.testing.assert_allclose(phi, phi2, atol=1e-12 * np.abs(phi2).max())
+    assert abs(phi.mean()) < 1e-13 * np.abs(phi).max()
+
+
+def test_dense_operator_matches_stencil(rng):
+    grid = Grid(3, (3, 4, 5), (0.2, 0.3, 0.5))
+    v = rng.normal(size=grid.G)
+    np.testing.assert_allclose(poisson.laplacian_dense(grid) @ v, poisson.laplacian(grid, v),
+                               atol=1e-12 * np.abs(v).max() / 0.04)
+
+
+@pytest.mark.parametrize("n", [(64, 64), (16, 16, 16), (48, 40)])
+def test_residual_vanishes(rng, n):
+    """The FD divergence of the FD gradient of phi equals the compatible RHS."""
+    grid = Grid(len(n), n, tuple(1.0 / v for v in n))
+    b = rng.normal(size=grid.G) + 0.7
+    phi, bm = poisson.solve(grid, b)
+    r = (b - bm) - poisson.laplacian(grid, phi)
+    assert np.linalg.norm(r) / np.linalg.norm(b - bm) < 1e-13
+
+
+def _exact_solve(grid, b):
+    """Gaussian elimination in rationals on the bordered system."""
+    L = poisson.laplacian_dense(grid)
+    G = grid.G
+    K = [[Fraction(0)] * (G + 2) for _ in range(G + 1)]
+    for i in range(G):
+        for j in range(G):
+            K[i][j] = Fraction(L[i, j]).limit_denominator(10 ** 6)
+        K[i][G] = Fraction(1)
+        K[i][G + 1] = b[i]
+    for j in range(G):
+        K[G][j] = Fraction(1)
+    n = G + 1
+    for c in range(n):
+        p = next(r for r in range(c, n) if K[r][c] != 0)
+        K[c], K[p] = K[p], K[c]
+        for r in range(n):
+            if r != c and K[r][c] != 0:
+                f = K[r][c] / K[c][c]
+                K[r] = [a - f * bb for a, bb in zip(K[r], K[c])]
+    return [K[i][G + 1] / K[i][i] for i in range(n)]
+
+
+def test_exact_rational_tiny():
+    grid = Grid(2, (3, 2), (1.0, 0.5))
+    b = [Fraction(v) for v in (1, -2, 3, 5, 0, -4)]
+    sol = _exact_solve(grid, b)
+    phi, bm = poisson.solve(grid, np.array([float(v) for v in b]))
+    assert bm == pytest.approx(float(sol[-1]), abs=1e-15)
+    np.testing.assert_allclose(phi, [float(v) for v in sol[:-1]], atol=1e-14)
