@@ -1,0 +1,245 @@
+#!/usr/bin/env python3
+"""Benchmark of the hybrid pressure-correction sub-step on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--size 2048]
+
+Workload (the 2D workload the throughput metric is quoted on): a 2048^2
+cell-centred pressure grid on the unit square, 4.2M jittered-lattice nodes
+(seeded jitter +-0.3h), a cylinder of radius 0.05 at (0.3, 0.5) whose
+interior lattice nodes are virtual points and whose surface carries the
+boundary points, 16-neighbour second-order WLS stencils with Gaussian
+weights, a random 32-mode velocity field, Neumann box.  The stencils are
+built once (timed separately, not part of a step); a step is one complete
+pressure-correction sub-step (RHS transfer, IB-force iterations of Poisson
+solve + gradient at the IB + force update, final gradient and projection)
+from a zero IB force, with all inputs resident in HBM.
+
+One JSON line is printed: grid-points/s of the float64 sub-step, p50/p99
+step latency, the float32 and float32+float64-defect-correction variants,
+per-kernel HIP-event timings with the roofline of the dominant kernel, and
+the CPU oracle timed on this host on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import statistics
+import sys
+import time
+
+import numpy as np
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--size", type=int, default=2048)
+    ap.add_argument("--modes", default="f64,f32,mixed")
+    ap.add_argument("--kernel-reps", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-size", type=int, default=1024)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a plain device copy of known size (counter scaling)")
+    return ap.parse_args()
+
+
+# ---- algorithmic bytes ---------------------------------------------------------
+def bytes_div_all(G, M, k, d, s):
+    """idx (4 B) + d coefficients per stencil entry, b written once, u read once."""
+    return G * (k * (4 + d * s) + s) + M * d * s
+
+
+def bytes_solve_pass(G, s_in, s_out):
+    return G * (s_in + s_out)
+
+
+def bytes_solve(G, d, s):
+    return (2 * d - 1) * bytes_solve_pass(G, s, s)
+
+
+def bytes_grad_project(G, M, bn, d, s):
+    """coefficients + block corner per node, u* read, u^{n+1} written, phi read once."""
+    return M * (bn * d * s + 4 + 2 * d * s) + G * s
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this library runs the sub-step on one GPU; "
+                                   "--gpus above 1 is not supported (see the sharding "
+                                   "design notes)", "n_gpus": args.gpus}))
+        sys.exit(2)
+    import torch
+    from paper_2304_14690_amd import inputs, pcorr as pc
+
+    torch.cuda.init()
+    dev = torch.cuda.current_device()
+    stream = torch.cuda.current_stream()
+    N = args.size
+    t0 = time.perf_counter()
+    case = inputs.config2(N)
+    t_gen = time.perf_counter() - t0
+    G, M, d = case.G, case.M, case.d
+    plan = pc.Plan(d, case.n, case.h)
+    x = torch.from_numpy(case.x).cuda()
+    kind = torch.from_numpy(case.kind).cuda()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    geom = pc.wls_build(plan, x, kind, case.k_grid, case.k_node, want_f32=True)
+    torch.cuda.synchronize()
+    t_build = time.perf_counter() - t0
+
+    modes = [m for m in args.modes.split(",") if m]
+    results = {}
+    for mname in modes:
+        mode = pc.MODES[mname]
+        dtype = torch.float32 if mode == pc.PC_F32 else torch.float64
+        u = torch.from_numpy(case.u).to(dtype).cuda()
+        uo = torch.empty_like(u)
+        p = torch.empty(G, dtype=dtype, device="cuda")
+        ws = pc.Workspace(plan, geom, mode)
+        stats = None
+        for _ in range(args.warmup):
+            _, stats = pc.pressure_correct(geom, plan, mode, u, 1.0, uo, p, ws=ws)
+        torch.cuda.synchronize()
+        lat = []
+        torch.cuda.synchronize()
+        t_start = time.perf_counter()
+        for _ in range(args.steps):
+            ts = time.perf_counter()
+            _, stats = pc.pressure_correct(geom, plan, mode, u, 1.0, uo, p, ws=ws)
+            torch.cuda.synchronize()
+            lat.append(time.perf_counter() - ts)
+        torch.cuda.synchronize()
+        total = time.perf_counter() - t_start
+        ms = 1e3 * total / args.steps
+        lat_ms = sorted(1e3 * v for v in lat)
+        results[mname] = {
+            "value": G / (total / args.steps),
+            "ms_per_step": ms,
+            "p50_ms": float(np.percentile(lat_ms, 50)),
+            "p99_ms": float(np.percentile(lat_ms, 99)),
+            "n_it": stats["n_it"],
+            "converged": stats["converged"],
+        }
+        del ws
+
+    # ---- per-kernel HIP-event timings (same kernels, same launch shapes) ----------
+    def time_launches(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps * 1e-3  # seconds per launch
+
+    u64 = torch.from_numpy(case.u).cuda()
+    b64 = torch.empty(G, dtype=torch.float64, device="cuda")
+    phi64 = torch.empty(G, dtype=torch.float64, device="cuda")
+    gr64 = torch.empty((d, M), dtype=torch.float64, device="cuda")
+    pc.div_to_grid(geom, u64, b64)
+    pc.poisson_fft_solve(plan, b64, phi64, pc.PC_F64)
+    reps = args.kernel_reps
+    t_div = time_launches(lambda: pc.div_to_grid(geom, u64, b64), reps)
+    t_solve = time_launches(lambda: pc.poisson_fft_solve(plan, b64, phi64, pc.PC_F64), reps)
+    t_grad = time_launches(lambda: pc.grad_to_nodes(geom, phi64, gr64), reps)
+    k, bn = geom.k_grid, geom.bn
+    kern = {
+        "div_to_grid": {"bytes": bytes_div_all(G, M, k, d, 8), "s": t_div, "launches_per_step": 1},
+        "poisson_fft_solve": {"bytes": bytes_solve(G, d, 8), "s": t_solve,
+                              "launches_per_step": results.get("f64", {}).get("n_it", 1)},
+        "grad_to_nodes": {"bytes": bytes_grad_project(G, M, bn, d, 8) - M * d * 8, "s": t_grad,
+                          "launches_per_step": 1},
+    }
+    for v in kern.values():
+        v["GBs"] = v["bytes"] / v["s"] / 1e9
+        v["frac"] = v["GBs"] / HBM_PEAK_GBS
+        v["us"] = v["s"] * 1e6
+    dom = max(kern, key=lambda n: kern[n]["s"] * kern[n]["launches_per_step"])
+    roof = {"bound": "hbm", "achieved": round(kern[dom]["GBs"], 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(kern[dom]["frac"], 4), "traffic": None,
+            "kernel": dom, "bytes_per_launch": kern[dom]["bytes"],
+            "avg_launch_us": round(kern[dom]["us"], 2)}
+
+    if args.copy_probe:
+        src = torch.empty(1 << 27, dtype=torch.float64, device="cuda")  # 1 GiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+
+    # ---- CPU oracle on a bounded sample ----------------------------------------------
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(args.cpu_size)
+
+    f64 = results.get("f64") or next(iter(results.values()))
+    out = {
+        "metric": "pressure-correction grid-pts/s (float64 sub-step, 2048^2)",
+        "value": f64["value"],
+        "unit": "grid-pts/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": f64["ms_per_step"],
+        "p50_ms": f64["p50_ms"],
+        "p99_ms": f64["p99_ms"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"2D {N}^2 grid, {M} jittered nodes, cylinder r=0.05 at "
+                               f"(0.3,0.5), 16-NN WLS, 32-mode velocity, Neumann box, "
+                               f"cold IB start", "G": G, "M": M, "k": k,
+                   "n_it": f64["n_it"], "build_s": round(t_build, 3),
+                   "gen_s": round(t_gen, 3)},
+        "modes": results,
+        "kernels": {n: {kk: (round(vv, 4) if isinstance(vv, float) else vv)
+                        for kk, vv in v.items()} for n, v in kern.items()},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "device": torch.cuda.get_device_name(dev),
+    }
+    print(json.dumps(out))
+
+
+def cpu_baseline(N):
+    """The float64 oracle's sub-step on this host: the same workload at N^2
+    (same obstacle, stencil size and modes), stencils built first and not
+    timed, median of three timed sub-steps."""
+    import oracle
+    from oracle import projection as P
+    from paper_2304_14690_amd import inputs
+    cores = len(os.sched_getaffinity(0))
+    c = inputs.config2(N)
+    grid = oracle.Grid(c.d, c.n, c.h)
+    t0 = time.perf_counter()
+    st = P.build_stencils(grid, c.x.T.copy(), c.kind, c.k_grid, c.k_node, workers=cores)
+    t_build = time.perf_counter() - t0
+    u = c.u.T.copy()
+    times = []
+    n_it = None
+    for _ in range(3):
+        t0 = time.perf_counter()
+        r = P.pressure_correct(st, u)
+        times.append(time.perf_counter() - t0)
+        n_it = r["n_it"]
+    t = statistics.median(times)
+    return {"value": c.G / t, "unit": "grid-pts/s", "cores": cores, "kind": "oracle",
+            "sample": f"config-2 workload at {N}^2 ({c.M} nodes), float64 oracle sub-step, "
+                      f"median of 3, n_it={n_it}; stencil build {t_build:.1f}s not timed",
+            "s_per_step": t}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,278 @@
+/*
+ * pcorr.h -- C ABI of the MI355X hybrid pressure-correction library.
+ *
+ * The library implements the pressure-correction sub-step of the hybrid
+ * projection method of J. Fang, "A fast hybrid pressure-correction algorithm
+ * for simulating incompressible flows by projection methods" (arXiv
+ * 2304.14690), Sec. 2.2-2.3:
+ *
+ *   u^{n+1} = u* - (3/2) dt grad p + dt f~                  (Eq. 18)
+ *   f~      = -u* / dt + (3/2) grad p  on boundary/virtual points, 0 elsewhere
+ *                                                           (Eq. 19)
+ *   lap p   = (2/(3 dt)) div u* + (2/3) div f~              (Eq. 20)
+ *
+ * solved on a uniform cell-centred pressure grid covering an extended box,
+ * with the divergence and the gradient carried between the scattered
+ * velocity points ("nodes") and the grid by second-order weighted least
+ * squares (Sec. 2.2, Eqs. 9-17), the Poisson equation solved directly by
+ * cosine transforms (Sec. 2.3, the three-step transform algorithm, with the
+ * homogeneous Neumann condition of Eq. 7 on every box face), and the
+ * immersed-boundary force found by the fixed-point iteration of Sec. 2.3.
+ *
+ * Internally the library works with phi = (3 dt / 2) p and g = dt f~, for
+ * which Eqs. 18-20 read u^{n+1} = u* - grad phi + g, lap phi = div(u* + g),
+ * g = -u* + grad phi on boundary and virtual points.
+ *
+ * Conventions shared by every entry point
+ *   - Every call returns an int status: PC_OK (0), a negative PC_ERR_* code,
+ *     or a positive PC_WARN_* code.  pc_last_error() gives a thread-local
+ *     message for the last failing call of the calling thread.  No C++
+ *     exception crosses the ABI.
+ *   - Pointers named *_dev are device pointers (HBM of the current HIP
+ *     device), at least 16-byte aligned; the caller owns them and the library
+ *     never frees them.  Host structs (opts, stats) are read or written
+ *     during the call only.
+ *   - `stream` is a hipStream_t (NULL = the null stream).  Calls only
+ *     enqueue work on it, except where a call says it synchronises.
+ *   - Node fields are structure-of-arrays [d][M] (component a of node n at
+ *     a*M + n).  Grid fields are [G] with G = n0*n1(*n2), x fastest: cell
+ *     (i, j, k) at i + n0*(j + n1*k), centred at ((i+1/2) h0, (j+1/2) h1,
+ *     (k+1/2) h2); the box is [0, n0 h0] x [0, n1 h1] (x [0, n2 h2]).
+ *   - Node kinds: PC_KIND_F (velocity point), PC_KIND_B (boundary point on
+ *     the obstacle surface), PC_KIND_V (virtual point inside the obstacle).
+ *     The provisional velocity at virtual points must be zero (Sec. 2.3:
+ *     the frozen fluid inside the immersed boundary).
+ *   - The library-owned handles (pc_plan, pc_geom, pc_workspace) hold device
+ *     memory on the device that was current at creation; use them with that
+ *     device current.  Handles are not thread-safe; calls that share a
+ *     workspace must not overlap.
+ */
+#ifndef PCORR_H
+#define PCORR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define PC_OK 0
+#define PC_WARN_IB_NOT_CONVERGED 1   /* max_it reached before the criterion */
+#define PC_ERR_INVALID_ARG (-1)      /* null pointer, bad enum, k too small  */
+#define PC_ERR_UNSUPPORTED_SIZE (-2) /* n not a power of two in [8, 4096],   */
+                                     /* d not 2 or 3, k above the maximum    */
+#define PC_ERR_ALIGN (-3)            /* device pointer not 16-byte aligned   */
+#define PC_ERR_OOM (-4)              /* device allocation failed             */
+#define PC_ERR_SINGULAR_STENCIL (-5) /* a WLS normal matrix is singular      */
+#define PC_ERR_HIP (-6)              /* a HIP runtime call failed            */
+#define PC_ERR_NO_DEVICE (-7)        /* no HIP device is visible             */
+
+/* ---- precision modes ---------------------------------------------------- */
+#define PC_F64 1   /* all arithmetic and storage in float64                  */
+#define PC_F32 2   /* fields, stencils and transforms in float32             */
+#define PC_MIXED 3 /* float64 fields and transfers; transforms in float32    */
+                   /* followed by float64 defect-correction sweeps          */
+
+/* ---- subsets ------------------------------------------------------------ */
+#define PC_ALL 0
+#define PC_NEAR_IB 1 /* grid points whose stencil holds a B or V node        */
+#define PC_IB 2      /* boundary and virtual nodes, in ascending node order  */
+
+#define PC_KIND_F 0
+#define PC_KIND_B 1
+#define PC_KIND_V 2
+
+#define PC_MAX_K_GRID 32 /* largest grid-point stencil                      */
+#define PC_MAX_K_NODE 64 /* largest node stencil block (m^d)                */
+
+typedef struct pc_plan pc_plan;           /* grid + transform tables         */
+typedef struct pc_geom pc_geom;           /* WLS stencils of one node cloud  */
+typedef struct pc_workspace pc_workspace; /* scratch of one in-flight solve  */
+
+/* Options of pc_wls_build (Sec. 2.2).  Zero fields take the default. */
+typedef struct pc_wls_opts {
+  int32_t k_grid;    /* nodes per grid-point stencil (default 16)           */
+  int32_t k_node;    /* grid points per node stencil (default 16 in 2D,     */
+                     /* 27 in 3D)                                           */
+  double eps;        /* Gaussian shape parameter of Eq. 17 (default 6.3)    */
+  double support;    /* support radius in mean spacings (default 3)         */
+  double delta;      /* mean point spacing (default: the grid spacing, or   */
+                     /* the geometric mean of the per-axis spacings)        */
+  int32_t dtype_mask;/* PC_F64 and/or PC_F32 stencil copies to keep; bit    */
+                     /* (1 << mode) for each mode; 0 = float64 only         */
+  int32_t reserved;
+} pc_wls_opts;
+
+/* Options of the IB-force iteration (Sec. 2.3). */
+typedef struct pc_ib_opts {
+  double tol;        /* criterion tolerance (default 1e-3)                  */
+  int32_t max_it;    /* iteration cap (default 50)                          */
+  int32_t fixed_it;  /* > 0: run exactly this many iterations               */
+  int32_t sweeps;    /* PC_MIXED defect-correction sweeps (default 2)       */
+  int32_t gauge;     /* 0: zero-mean pressure; 1: zero at the first cell    */
+} pc_ib_opts;
+
+typedef struct pc_stats {
+  int32_t n_it;      /* IB iterations run                                   */
+  int32_t converged; /* 1 if the criterion was met                          */
+  double bmean;      /* mean of the last right-hand side (removed; the      */
+                     /* compatibility defect of the Neumann problem)        */
+  double ib_num;     /* last criterion numerator  sum (|g|-|g_old|)^2       */
+  double ib_den;     /* last criterion denominator sum |g_old|^2            */
+} pc_stats;
+
+/* ---- library ------------------------------------------------------------ */
+
+/* ABI version (major*100 + minor). */
+int pc_version(void);
+
+/* Copies the calling thread's last error message into buf (NUL-terminated,
+ * truncated to n bytes).  Returns the message length. */
+int pc_last_error(char* buf, size_t n);
+
+/* ---- plan: grid and transform tables ------------------------------------ */
+
+/* Creates the plan of a d-dimensional cell-centred grid with n[a] cells of
+ * spacing h[a] per axis (Sec. 2.3, Fig. 1: the uniform pressure grid over
+ * the extended rectangle).  Builds, in float64 on the host, the twiddle
+ * tables of the cosine transforms and the 1D eigenvalues
+ * -(4/h_a^2) sin^2(pi k / (2 n_a)) of the mirror-ghost central-difference
+ * Laplacian (homogeneous Neumann condition, Eq. 7), and uploads them (plus
+ * float32 copies).  n[a] must be a power of two in [8, 4096].  Synchronises
+ * `stream`.  Release with pc_plan_destroy. */
+int pc_plan_create(int d, const int32_t* n, const double* h, void* stream, pc_plan** out);
+int pc_plan_destroy(pc_plan* plan);
+
+/* ---- a3 + a4 (+ a8): the Poisson solve ---------------------------------- */
+
+/* Solves lap_h phi = b - mean(b) with mean(phi) = 0 on the plan's grid
+ * (Sec. 2.3: forward transforms along each axis, division by the sum of the
+ * 1D eigenvalues, backward transforms; the zero mode is dropped and the
+ * compatibility defect mean(b) removed).
+ *   mode PC_F64:   b_dev, phi_dev float64 [G].
+ *   mode PC_F32:   b_dev, phi_dev float32 [G].
+ *   mode PC_MIXED: b_dev, phi_dev float64 [G]; transforms in float32 with
+ *                  `sweeps` float64 defect-correction sweeps
+ *                  r = b - mean(b) - lap_h phi, phi += solve32(r).
+ * b_dev and phi_dev may alias (in-place).  bmean_dev (nullable) receives
+ * mean(b) as one float64.  ws: a workspace of this plan (nullable: the
+ * plan's own, which makes concurrent calls on the plan race). */
+int pc_poisson_fft_solve(const pc_plan* plan, int mode, const void* b_dev, void* phi_dev,
+                         int sweeps, double* bmean_dev, pc_workspace* ws, void* stream);
+
+/* ---- a1: stencils -------------------------------------------------------- */
+
+/* Builds the WLS stencils of one node cloud (Sec. 2.2; computed once per
+ * geometry, last paragraph of Sec. 2.2):
+ *   - every grid point takes its k_grid nearest nodes (key (d^2, node
+ *     index), d^2 = ((dx*dx) + dy*dy) + dz*dz rounded term by term);
+ *   - every node takes the k_node nearest grid points (same key, flat grid
+ *     index) inside the block of the m = ceil(k_node^(1/d)) grid lines
+ *     nearest to it along each axis, clamped inside the box;
+ *   - for each target, the Eq. 16 polynomial vector (10 terms in 3D) in
+ *     coordinates scaled by the support radius h_t = max(support*delta,
+ *     r_k), the Eq. 17 weights exp(-eps r^2/h_t^2), C = sum w q q^T
+ *     (Eq. 14) and the first-derivative rows of C^-1 A (Eq. 13);
+ *   - the lists of boundary/virtual nodes and of grid points near them.
+ * xyz_dev: float64 [d][M] node positions; kind_dev: uint8 [M].
+ * Synchronises `stream`.  Returns PC_ERR_SINGULAR_STENCIL if any normal
+ * matrix has a squared pivot ratio below 1e-12 (e.g. collinear nodes).
+ * Release with pc_geom_destroy. */
+int pc_wls_build(const pc_plan* plan, const double* xyz_dev, const uint8_t* kind_dev, int64_t M,
+                 const pc_wls_opts* opts, void* stream, pc_geom** out);
+int pc_geom_destroy(pc_geom* geom);
+
+/* Sizes of a geometry: counts[0] = M, [1] = number of B+V nodes, [2] =
+ * number of near-IB grid points, [3] = k_grid, [4] = k_node block size
+ * m^d, [5] = device bytes held by the geometry. */
+int pc_geom_info(const pc_geom* geom, int64_t* counts6);
+
+/* Copies the stencils out (for inspection and tests).
+ *   grid_idx_dev  int32   [k_grid][G]      node index, ascending (d^2, idx)
+ *   grid_coef_dev float64 [d][k_grid][G]   derivative coefficients
+ *   node_base_dev int32   [M]              flat grid index of the block's
+ *                                          low corner
+ *   node_coef_dev float64 [d][m^d][M]      coefficients in block order
+ *                                          (x fastest); 0 for block points
+ *                                          outside the k_node selection
+ *   ib_dev        int32   [n_ib]           boundary+virtual node indices
+ *   near_dev      int32   [n_near]         near-IB grid points
+ * Any pointer may be NULL. */
+int pc_geom_export(const pc_geom* geom, int32_t* grid_idx_dev, double* grid_coef_dev,
+                   int32_t* node_base_dev, double* node_coef_dev, int32_t* ib_dev,
+                   int32_t* near_dev, void* stream);
+
+/* ---- a2: right-hand side -------------------------------------------------- */
+
+/* b = WLS divergence of v at the grid points (Sec. 2.3, Eq. 20 right-hand
+ * side, with v = u* + g):  b_p = sum_a sum_i c^a_{p,i} v_a[idx_{p,i}].
+ *   subset PC_ALL:     v_dev [d][M], writes b_dev[G].
+ *   subset PC_NEAR_IB: v_dev [d][n_ib] holds values at the B+V nodes only
+ *                      (zero assumed elsewhere) and the result is ADDED to
+ *                      b_dev at the near-IB grid points (Sec. 2.3: after the
+ *                      first iteration only these points see the force).
+ * dtype PC_F64 or PC_F32 selects float64 or float32 fields and stencils. */
+int pc_div_to_grid(const pc_geom* geom, int dtype, const void* v_dev, void* b_dev, int subset,
+                   void* stream);
+
+/* ---- a5: gradient transfer ----------------------------------------------- */
+
+/* grad = WLS gradient of phi at the nodes (Sec. 2.3):
+ * grad_a(n) = sum_j c^a_{n,j} phi[src_{n,j}].
+ *   subset PC_ALL: grad_dev [d][M];  subset PC_IB: grad_dev [d][n_ib] at the
+ *   boundary and virtual nodes in ascending node order. */
+int pc_grad_to_nodes(const pc_geom* geom, int dtype, const void* phi_dev, void* grad_dev,
+                     int subset, void* stream);
+
+/* ---- a6: one IB-force update ----------------------------------------------- */
+
+/* g_new = -u* + grad at the B+V nodes (Eq. 19 times dt); sums the criterion
+ * of Sec. 2.3, num = sum (|g_new| - |g_old|)^2 and den = sum |g_old|^2, into
+ * sums_dev[0..1] (float64, deterministic order), sets *conv_dev = 1 if
+ * num < tol * den or num == 0 (else 0), and overwrites g_dev with g_new.
+ * u_dev [d][M] (dtype); grad_ib_dev, g_dev [d][n_ib] (dtype). */
+int pc_ib_update(const pc_geom* geom, int dtype, const void* u_dev, const void* grad_ib_dev,
+                 void* g_dev, double tol, double* sums_dev, int32_t* conv_dev, void* stream);
+
+/* ---- a7: projection ---------------------------------------------------------- */
+
+/* u_out = u* - grad + g (Eq. 18 with phi, g): u* - grad on velocity points
+ * and exactly 0 on boundary and virtual points, where Eq. 19 cancels it.
+ * u_dev, grad_dev, u_out_dev [d][M] (dtype).  u_out may alias u. */
+int pc_project(const pc_geom* geom, int dtype, const void* u_dev, const void* grad_dev,
+               void* u_out_dev, void* stream);
+
+/* ---- the whole sub-step ------------------------------------------------------ */
+
+/* Workspace for pc_pressure_correct / pc_poisson_fft_solve in `mode` on this
+ * plan and geometry (geom may be NULL for solve-only use). */
+int pc_workspace_create(const pc_plan* plan, const pc_geom* geom, int mode, pc_workspace** out);
+int pc_workspace_destroy(pc_workspace* ws);
+/* Device bytes a workspace of this mode would hold. */
+int64_t pc_workspace_bytes(const pc_plan* plan, const pc_geom* geom, int mode);
+
+/* One pressure-correction sub-step (Sec. 2.3): b_u = div u*; loop { RHS
+ * update near the IB; Poisson solve; grad phi at B+V; IB-force update;
+ * criterion } ; final grad phi at all nodes and the projection of Eq. 18;
+ * p = 2 phi / (3 dt).
+ *   mode PC_F64 / PC_MIXED: u_dev, u_out_dev [d][M] and p_dev [G] float64.
+ *   mode PC_F32:            the same arrays in float32.
+ *   g_inout_dev (nullable) [d][n_ib] in the field dtype: the warm start of
+ *   the IB force times dt (Sec. 2.3: taken from the previous time step) and
+ *   its final value.  NULL starts from zero.
+ *   stats (nullable) is filled after the call synchronises `stream`.
+ * Synchronises `stream` once per IB iteration to read the 4-byte
+ * convergence flag (not when fixed_it > 0).  Returns PC_WARN_IB_NOT_CONVERGED
+ * when max_it is reached first. */
+int pc_pressure_correct(const pc_geom* geom, const pc_plan* plan, int mode, const void* u_dev,
+                        double dt, void* u_out_dev, void* p_dev, void* g_inout_dev,
+                        const pc_ib_opts* opts, pc_stats* stats, pc_workspace* ws,
+                        void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PCORR_H */

@@ -1,0 +1,282 @@
+// C ABI entry points of libpcorr: errors, plans, workspaces and the Poisson
+// solve.  Geometry entry points live in pc_wls.hip, the transfers and the
+// whole sub-step in pc_step.hip.
+#include <cmath>
+#include <cstring>
+
+#include "pc_internal.h"
+
+namespace pc {
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+int fail(int code, const std::string& msg) {
+  set_error(msg);
+  return code;
+}
+
+int dev_alloc(void** p, size_t bytes, const char* what) {
+  *p = nullptr;
+  if (bytes == 0) return PC_OK;
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    *p = nullptr;
+    return fail(PC_ERR_OOM, std::string("hipMalloc failed for ") + what + " (" +
+                                std::to_string(bytes) + " bytes): " + hipGetErrorString(e));
+  }
+  return PC_OK;
+}
+
+void dev_free(void* p) {
+  if (p) (void)hipFree(p);
+}
+
+namespace {
+
+bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+
+// Host float64 tables of one axis, written at `dst` (reals) in the order
+// twH[H] (complex), tN[H+1] (complex), t4N[H+1] (complex), lam[N].
+size_t axis_table_reals(int N) {
+  int H = N / 2;
+  return 2 * (size_t)H + 2 * (size_t)(H + 1) * 2 + (size_t)N;
+}
+
+void fill_axis_tables(int N, double h, std::vector<double>& out) {
+  const long double PI = 3.141592653589793238462643383279502884L;
+  int H = N / 2;
+  out.clear();
+  out.reserve(axis_table_reals(N));
+  for (int j = 0; j < H; ++j) {
+    long double a = 2.0L * PI * (long double)j / (long double)H;
+    out.push_back((double)cosl(a));
+    out.push_back((double)-sinl(a));
+  }
+  for (int k = 0; k <= H; ++k) {
+    long double a = 2.0L * PI * (long double)k / (long double)N;
+    out.push_back((double)cosl(a));
+    out.push_back((double)-sinl(a));
+  }
+  for (int k = 0; k <= H; ++k) {
+    long double a = PI * (long double)k / (2.0L * (long double)N);
+    out.push_back((double)cosl(a));
+    out.push_back((double)-sinl(a));
+  }
+  for (int k = 0; k < N; ++k) {
+    long double sn = sinl(PI * (long double)k / (2.0L * (long double)N));
+    out.push_back((double)(-(4.0L / ((long double)h * (long double)h)) * sn * sn));
+  }
+}
+
+template <typename T>
+void set_axis_ptrs(AxisTables<T>& A, T* base, int N) {
+  int H = N / 2;
+  A.twH = reinterpret_cast<const cplx<T>*>(base);
+  A.tN = reinterpret_cast<const cplx<T>*>(base + 2 * (size_t)H);
+  A.t4N = reinterpret_cast<const cplx<T>*>(base + 2 * (size_t)H + 2 * (size_t)(H + 1));
+  A.lam = base + 2 * (size_t)H + 4 * (size_t)(H + 1);
+}
+
+int check_mode(int mode) {
+  if (mode != PC_F64 && mode != PC_F32 && mode != PC_MIXED)
+    return fail(PC_ERR_INVALID_ARG, "mode must be PC_F64, PC_F32 or PC_MIXED");
+  return PC_OK;
+}
+
+}  // namespace
+
+int ensure_plan_ws(const pc_plan* P, pc_workspace** ws) {
+  if (*ws) return PC_OK;
+  pc_plan* mp = const_cast<pc_plan*>(P);
+  if (!mp->own_ws) PC_TRY(pc_workspace_create(P, nullptr, PC_MIXED, &mp->own_ws));
+  *ws = mp->own_ws;
+  return PC_OK;
+}
+
+}  // namespace pc
+
+using namespace pc;
+
+extern "C" {
+
+int pc_version(void) { return 100; }
+
+int pc_last_error(char* buf, size_t n) {
+  const std::string& m = g_last_error;
+  if (buf && n) {
+    size_t c = m.size() < n - 1 ? m.size() : n - 1;
+    std::memcpy(buf, m.data(), c);
+    buf[c] = '\0';
+  }
+  return (int)m.size();
+}
+
+int pc_plan_create(int d, const int32_t* n, const double* h, void* stream, pc_plan** out) {
+  if (!out || !n || !h) return fail(PC_ERR_INVALID_ARG, "pc_plan_create: null argument");
+  *out = nullptr;
+  if (d != 2 && d != 3) return fail(PC_ERR_UNSUPPORTED_SIZE, "d must be 2 or 3");
+  for (int a = 0; a < d; ++a) {
+    if (!is_pow2(n[a]) || n[a] < 8 || n[a] > 4096)
+      return fail(PC_ERR_UNSUPPORTED_SIZE, "n[a] must be a power of two in [8, 4096]");
+    if (!(h[a] > 0.0) || !std::isfinite(h[a]))
+      return fail(PC_ERR_INVALID_ARG, "h[a] must be positive and finite");
+  }
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
+    (void)hipGetLastError();
+    return fail(PC_ERR_NO_DEVICE, "no HIP device visible");
+  }
+  pc_plan* P = new pc_plan();
+  std::memset(P, 0, sizeof(*P));
+  P->d = d;
+  P->G = 1;
+  for (int a = 0; a < 3; ++a) {
+    P->n[a] = a < d ? n[a] : 1;
+    P->h[a] = a < d ? h[a] : 1.0;
+    P->G *= P->n[a];
+  }
+  if (hipGetDevice(&P->device) != hipSuccess) {
+    delete P;
+    return fail(PC_ERR_HIP, "hipGetDevice failed");
+  }
+  std::vector<double> all, one;
+  size_t offs[3];
+  for (int a = 0; a < d; ++a) {
+    offs[a] = all.size();
+    fill_axis_tables(P->n[a], P->h[a], one);
+    all.insert(all.end(), one.begin(), one.end());
+  }
+  std::vector<float> all32(all.size());
+  for (size_t i = 0; i < all.size(); ++i) all32[i] = (float)all[i];
+  int rc = dev_alloc(&P->tab64, all.size() * sizeof(double), "plan tables");
+  if (rc == PC_OK) rc = dev_alloc(&P->tab32, all32.size() * sizeof(float), "plan tables");
+  if (rc != PC_OK) {
+    pc_plan_destroy(P);
+    return rc;
+  }
+  hipStream_t s = as_stream(stream);
+  hipError_t e = hipMemcpyAsync(P->tab64, all.data(), all.size() * sizeof(double),
+                                hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(P->tab32, all32.data(), all32.size() * sizeof(float),
+                       hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    pc_plan_destroy(P);
+    return fail(PC_ERR_HIP, std::string("plan upload: ") + hipGetErrorString(e));
+  }
+  for (int a = 0; a < d; ++a) {
+    set_axis_ptrs(P->ax64[a], reinterpret_cast<double*>(P->tab64) + offs[a], P->n[a]);
+    set_axis_ptrs(P->ax32[a], reinterpret_cast<float*>(P->tab32) + offs[a], P->n[a]);
+  }
+  *out = P;
+  return PC_OK;
+}
+
+int pc_plan_destroy(pc_plan* P) {
+  if (!P) return PC_OK;
+  if (P->own_ws) pc_workspace_destroy(P->own_ws);
+  dev_free(P->tab64);
+  dev_free(P->tab32);
+  delete P;
+  return PC_OK;
+}
+
+int64_t pc_workspace_bytes(const pc_plan* P, const pc_geom* g, int mode) {
+  if (!P || check_mode(mode) != PC_OK) return -1;
+  size_t s = mode == PC_F32 ? 4 : 8;
+  int64_t bytes = 0;
+  auto add = [&](int64_t b) { bytes += (b + 255) / 256 * 256; };
+  if (g) {
+    add(P->G * (int64_t)s);              // b
+    add(P->G * (int64_t)s);              // phi
+    add(g->n_near * (int64_t)s);         // bnear
+    add(3 * (int64_t)g->d * g->n_ib * (int64_t)s);  // uib, gib, gradib
+  }
+  if (mode == PC_MIXED) add(P->G * 4);   // w32
+  add(1024 * 8);                         // partials
+  add(16 * 8);                           // scalars
+  add(16 * 4);                           // flags
+  return bytes;
+}
+
+int pc_workspace_create(const pc_plan* P, const pc_geom* g, int mode, pc_workspace** out) {
+  if (!P || !out) return fail(PC_ERR_INVALID_ARG, "pc_workspace_create: null argument");
+  *out = nullptr;
+  PC_TRY(check_mode(mode));
+  if (g && (g->G != P->G || g->d != P->d))
+    return fail(PC_ERR_INVALID_ARG, "geometry and plan grids differ");
+  pc_workspace* W = new pc_workspace();
+  std::memset(W, 0, sizeof(*W));
+  W->plan = P;
+  W->geom = g;
+  W->mode = mode;
+  W->nblk = 1024;
+  (void)hipGetDevice(&W->device);
+  W->bytes = pc_workspace_bytes(P, g, mode);
+  int rc = dev_alloc(&W->block, (size_t)W->bytes, "workspace");
+  if (rc != PC_OK) {
+    delete W;
+    return rc;
+  }
+  size_t s = mode == PC_F32 ? 4 : 8;
+  char* cur = reinterpret_cast<char*>(W->block);
+  auto take = [&](int64_t b) {
+    char* p = cur;
+    cur += (b + 255) / 256 * 256;
+    return (void*)p;
+  };
+  if (g) {
+    W->b = take(P->G * (int64_t)s);
+    W->phi = take(P->G * (int64_t)s);
+    W->bnear = take(g->n_near * (int64_t)s);
+    W->uib = take((int64_t)g->d * g->n_ib * (int64_t)s);
+    W->gib = take((int64_t)g->d * g->n_ib * (int64_t)s);
+    W->gradib = take((int64_t)g->d * g->n_ib * (int64_t)s);
+  }
+  if (mode == PC_MIXED) W->w32 = reinterpret_cast<float*>(take(P->G * 4));
+  W->partial = reinterpret_cast<double*>(take(1024 * 8));
+  W->scal = reinterpret_cast<double*>(take(16 * 8));
+  W->flag = reinterpret_cast<int32_t*>(take(16 * 4));
+  if (hipHostMalloc((void**)&W->hscal, 16 * 8 + 16 * 4, hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    dev_free(W->block);
+    delete W;
+    return fail(PC_ERR_OOM, "pinned host scalars");
+  }
+  W->hflag = reinterpret_cast<int32_t*>(W->hscal + 16);
+  *out = W;
+  return PC_OK;
+}
+
+int pc_workspace_destroy(pc_workspace* W) {
+  if (!W) return PC_OK;
+  dev_free(W->block);
+  if (W->hscal) (void)hipHostFree(W->hscal);
+  delete W;
+  return PC_OK;
+}
+
+int pc_poisson_fft_solve(const pc_plan* P, int mode, const void* b, void* phi, int sweeps,
+                         double* bmean_dev, pc_workspace* ws, void* stream) {
+  if (!P || !b || !phi) return fail(PC_ERR_INVALID_ARG, "pc_poisson_fft_solve: null argument");
+  PC_TRY(check_mode(mode));
+  if (!aligned16(b) || !aligned16(phi)) return fail(PC_ERR_ALIGN, "fields must be 16-byte aligned");
+  if (sweeps < 0 || sweeps > 16) return fail(PC_ERR_INVALID_ARG, "sweeps must be in [0, 16]");
+  hipStream_t s = as_stream(stream);
+  if (mode == PC_F64)
+    return solve_f64(P, (const double*)b, (double*)phi, bmean_dev, ws, s);
+  if (mode == PC_F32) return solve_f32(P, (const float*)b, (float*)phi, bmean_dev, ws, s);
+  if (b == phi) return fail(PC_ERR_INVALID_ARG, "PC_MIXED needs b and phi to be distinct");
+  if (ws && ws->mode != PC_MIXED)
+    return fail(PC_ERR_INVALID_ARG, "PC_MIXED needs a workspace created for PC_MIXED");
+  PC_TRY(ensure_plan_ws(P, &ws));
+  return solve_mixed(P, (const double*)b, (double*)phi, sweeps, bmean_dev, ws, s);
+}
+
+}  // extern "C"

@@ -1,0 +1,150 @@
+// Internal declarations shared by the HIP translation units of libpcorr.
+// Not part of the ABI (see include/pcorr.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "pcorr.h"
+
+namespace pc {
+
+// ---- error handling --------------------------------------------------------
+void set_error(const std::string& msg);
+int fail(int code, const std::string& msg);
+
+#define PC_HIP_CHECK(expr)                                                       \
+  do {                                                                           \
+    hipError_t e_ = (expr);                                                      \
+    if (e_ != hipSuccess)                                                        \
+      return ::pc::fail(PC_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+#define PC_TRY(expr)          \
+  do {                        \
+    int rc_ = (expr);         \
+    if (rc_ < 0) return rc_;  \
+  } while (0)
+
+inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+inline bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+int dev_alloc(void** p, size_t bytes, const char* what);
+void dev_free(void* p);
+
+// ---- device-side small complex --------------------------------------------
+template <typename T>
+struct cplx {
+  T re, im;
+};
+
+// ---- per-axis transform tables (device) ------------------------------------
+// For an axis of N cells (H = N/2):
+//   twH[j]  = exp(-2 pi i j / H),      j = 0..H-1   (half-length FFT)
+//   tN[k]   = exp(-2 pi i k / N),      k = 0..H     (real-FFT split)
+//   t4N[k]  = exp(-i pi k / (2N)),     k = 0..H     (cosine-transform shift)
+//   lam[k]  = -(4 / h^2) sin^2(pi k / (2N)), k = 0..N-1
+template <typename T>
+struct AxisTables {
+  const cplx<T>* twH;
+  const cplx<T>* tN;
+  const cplx<T>* t4N;
+  const T* lam;
+};
+
+}  // namespace pc
+
+// ---- opaque handle bodies ----------------------------------------------------
+struct pc_plan {
+  int d;
+  int32_t n[3];
+  double h[3];
+  int64_t G;
+  int device;
+  // one allocation per precision holding all axis tables
+  void* tab64;
+  void* tab32;
+  pc::AxisTables<double> ax64[3];
+  pc::AxisTables<float> ax32[3];
+  pc_workspace* own_ws;  // lazily created default workspace (solve-only)
+};
+
+struct pc_geom {
+  int d;
+  int64_t M, G;
+  int32_t n[3];
+  double h[3];
+  int k_grid;   // stencil size of grid targets
+  int k_node;   // selected entries of node stencils
+  int m_node;   // block lines per axis; block size bn = m^d
+  int bn;
+  int64_t n_ib, n_near, n_near_entries;
+  int device;
+  bool has32;
+  // grid-target stencils
+  int32_t* gidx;   // [k_grid][G]
+  double* gcoef;   // [d][k_grid][G]
+  float* gcoef32;  // [d][k_grid][G] or null
+  // node stencils (block order)
+  int32_t* nbase;   // [M]
+  double* ncoef;    // [d][bn][M]
+  float* ncoef32;   // [d][bn][M] or null
+  // IB lists
+  int32_t* ib;          // [n_ib] node index
+  int32_t* near;        // [n_near] grid index
+  // compact near-IB stencils: for near point q, entries e in [nptr[q], nptr[q+1])
+  int32_t* nptr;        // [n_near+1]
+  int32_t* nslot;       // [n_near_entries] ib slot
+  double* ncoefib;      // [d][n_near_entries]
+  float* ncoefib32;
+  // compact node stencils of the B+V nodes
+  int32_t* ibbase;      // [n_ib]
+  double* ibcoef;       // [d][bn][n_ib]
+  float* ibcoef32;
+  int64_t bytes;
+  pc_workspace* own_ws;
+};
+
+struct pc_workspace {
+  const pc_plan* plan;
+  const pc_geom* geom;
+  int mode;
+  int device;
+  int64_t bytes;
+  void* block;       // single allocation; the pointers below point into it
+  void* b;           // [G] field dtype  (right-hand side)
+  void* phi;         // [G] field dtype
+  float* w32;        // [G] float32 transform buffer (MIXED)
+  void* bnear;       // [n_near] field dtype: b_u at the near points
+  void* uib;         // [d][n_ib] field dtype: u* at B+V nodes
+  void* gib;         // [d][n_ib] field dtype: IB force (times dt)
+  void* gradib;      // [d][n_ib] field dtype
+  double* partial;   // reduction partials
+  double* scal;      // small float64 scalars: [0] bmean, [1] num, [2] den, [3] mean phi
+  int32_t* flag;     // [0] converged flag
+  int32_t* hflag;    // pinned host mirror of the flag
+  double* hscal;     // pinned host mirror of scal
+  int nblk;          // partial-sum blocks
+};
+
+namespace pc {
+// ---- solve (pc_solve.hip) ---------------------------------------------------
+// Solves sigma * lap_h x = b - mean(b), mean(x) = 0 (sigma = 1: phi;
+// sigma = 3 dt / 2: the pressure itself).
+int solve_f64(const pc_plan* P, const double* b, double* phi, double* bmean_dev,
+              pc_workspace* ws, hipStream_t s, double sigma = 1.0);
+int solve_f32(const pc_plan* P, const float* b, float* phi, double* bmean_dev,
+              pc_workspace* ws, hipStream_t s, double sigma = 1.0);
+int solve_mixed(const pc_plan* P, const double* b, double* phi, int sweeps, double* bmean_dev,
+                pc_workspace* ws, hipStream_t s, double sigma = 1.0);
+int ensure_plan_ws(const pc_plan* P, pc_workspace** ws);
+// deterministic mean of a float64 grid field into out_dev[0]
+int mean_f64(const double* x, int64_t n, double* partial, int nblk, double* out_dev,
+             hipStream_t s);
+int fill_zero(void* p, size_t bytes, hipStream_t s);
+}  // namespace pc

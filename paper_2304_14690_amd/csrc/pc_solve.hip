@@ -1,0 +1,657 @@
+// Neumann-box Poisson solve by cosine transforms (Sec. 2.3, three-step
+// transform algorithm; homogeneous Neumann condition of Eq. 7 on every box
+// face, cell-centred grid, central-difference eigenvalues).
+//
+// Each 1D cosine transform of length N is computed through a complex FFT of
+// length H = N/2 (Makhoul's even/odd reordering, the real-FFT split and a
+// quarter-sample shift), staged in LDS:
+//   DCT-II   X[k] = 2 sum_n x[n] cos(pi k (2n+1) / (2N))
+//   inverse  x = DCT-III(X) / (2N), the exact inverse of the above.
+// One kernel launch transforms every line of the grid along one axis.  A
+// workgroup holds C lines; along x the lines are whole rows, along y/z the C
+// lines are adjacent in x so that each global access touches C contiguous
+// elements.  The last axis fuses forward transform, division by the summed
+// eigenvalues and inverse transform in registers, so a 2D solve is three
+// passes over the grid and a 3D solve five.
+#include <cmath>
+
+#include "pc_internal.h"
+
+namespace pc {
+
+namespace {
+
+constexpr int XCDS = 8;
+
+// Workgroup -> tile map that gives each XCD (own L2) a contiguous range of
+// tiles, so tiles that share cache lines meet in the same L2.
+__device__ __forceinline__ int xcd_tile(int b, int nb) {
+  if (nb % XCDS != 0) return b;
+  return (b % XCDS) * (nb / XCDS) + b / XCDS;
+}
+
+template <typename T>
+__device__ __forceinline__ cplx<T> cmul(cplx<T> a, cplx<T> b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename T>
+__device__ __forceinline__ cplx<T> cmulc(cplx<T> a, cplx<T> b) {  // a * conj(b)
+  return {a.re * b.re + a.im * b.im, a.im * b.re - a.re * b.im};
+}
+template <typename T>
+__device__ __forceinline__ cplx<T> cadd(cplx<T> a, cplx<T> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename T>
+__device__ __forceinline__ cplx<T> csub(cplx<T> a, cplx<T> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename T>
+__device__ __forceinline__ cplx<T> conj_(cplx<T> a) { return {a.re, -a.im}; }
+
+// Position of x[n] in Makhoul's reordering v: v[m] = x[2m], v[N-1-m] = x[2m+1].
+__device__ __forceinline__ int mk_pos(int n, int N) { return (n & 1) ? (N - 1 - (n >> 1)) : (n >> 1); }
+
+enum { OP_FWD = 0, OP_INV = 1, OP_FDI = 2 };
+enum { LD_PLAIN = 0, LD_RESID = 1 };
+enum { ST_PLAIN = 0, ST_ACCUM = 1 };
+
+template <typename TC>
+struct LineArgs {
+  const void* in;       // TI*
+  void* out;            // TO*
+  const double* rb;     // residual loader: b
+  const double* rphi;   // residual loader / accumulating store: phi
+  const double* sub;    // nullable: float64 scalar subtracted on load
+  int N, logH;
+  int pad;              // LDS line padding in reals (0 or 2)
+  int C;                // lines per tile
+  int tx;               // tiles along x (strided axes)
+  int axis;             // 0, 1, 2
+  int d;
+  int32_t n0, n1, n2;
+  double ih2[3];        // 1/h^2 (residual)
+  int64_t stride;       // element stride along the axis
+  AxisTables<TC> tab;   // tables of this axis
+  const TC* lam0;       // FDI: eigenvalues of axis 0 (indexed by i)
+  const TC* lam1;       // FDI in 3D: eigenvalues of axis 1 (indexed by j)
+  TC outscale;          // store scale
+  TC lscale;            // FDI: eigenvalues are multiplied by this (sigma)
+  double rscale;        // residual: r = b - rscale * lap_h phi
+  double* bmean;        // FDI: receives X(0)/prod(2N_a) from the zero line
+  double meannorm;
+};
+
+// Global offset of element n of line c in tile t.
+template <typename TC>
+__device__ __forceinline__ int64_t line_base(const LineArgs<TC>& A, int t, int c, int* i_out,
+                                             int* o_out) {
+  if (A.axis == 0) {
+    int64_t l = (int64_t)t * A.C + c;
+    *i_out = 0;
+    *o_out = (int)l;
+    return l * A.N;
+  }
+  int i = (t % A.tx) * A.C + c;
+  int o = t / A.tx;
+  *i_out = i;
+  *o_out = o;
+  if (A.axis == 1) return (int64_t)i + (int64_t)o * A.n0 * A.n1;  // o = k
+  return (int64_t)i + (int64_t)o * A.n0;                          // axis 2: o = j
+}
+
+// Residual r = b - lap_h phi at flat index p (mirror ghosts), float64.
+__device__ __forceinline__ double resid_at(const double* __restrict__ b,
+                                           const double* __restrict__ phi, int64_t p, int d,
+                                           int32_t n0, int32_t n1, int32_t n2, const double* ih2,
+                                           double rscale) {
+  int64_t s1 = n0, s2 = (int64_t)n0 * n1;
+  int i = (int)(p % n0);
+  int j = (int)((p / n0) % n1);
+  int k = d == 3 ? (int)(p / s2) : 0;
+  double c = phi[p];
+  double xm = i > 0 ? phi[p - 1] : c;
+  double xp = i < n0 - 1 ? phi[p + 1] : c;
+  double ym = j > 0 ? phi[p - s1] : c;
+  double yp = j < n1 - 1 ? phi[p + s1] : c;
+  double lap = ((xp - c) - (c - xm)) * ih2[0] + ((yp - c) - (c - ym)) * ih2[1];
+  if (d == 3) {
+    double zm = k > 0 ? phi[p - s2] : c;
+    double zp = k < n2 - 1 ? phi[p + s2] : c;
+    lap += ((zp - c) - (c - zm)) * ih2[2];
+  }
+  return b[p] - rscale * lap;
+}
+
+// Radix-4 / radix-2 Stockham FFT of the C lines held in LDS (complex view,
+// line c at zc + c*ls).  B butterflies per thread per radix-4 stage.
+template <typename TC, int B, bool INV>
+__device__ __forceinline__ void fft_lds(cplx<TC>* zc, int ls, int C, int H, int logH,
+                                        const cplx<TC>* __restrict__ twH, int tid, int nthr) {
+  int L = 1;
+  int rem = logH;
+  while (rem > 0) {
+    if (rem >= 2) {
+      const int nb = H >> 2;  // butterflies per line
+      cplx<TC> a[B][4];
+      int pos[B];
+      int lc[B];
+#pragma unroll
+      for (int b = 0; b < B; ++b) {
+        int bi = tid + b * nthr;
+        lc[b] = -1;
+        if (bi < C * nb) {
+          int c = bi / nb;
+          int j = bi - c * nb;
+          int k = j & (L - 1);
+          cplx<TC>* z = zc + c * ls;
+          int tstep = (H / (L * 4)) * k;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) a[b][r] = z[j + r * nb];
+#pragma unroll
+          for (int r = 1; r < 4; ++r) {
+            cplx<TC> w = twH[tstep * r];
+            a[b][r] = INV ? cmulc(a[b][r], w) : cmul(a[b][r], w);
+          }
+          cplx<TC> t0 = cadd(a[b][0], a[b][2]), t1 = csub(a[b][0], a[b][2]);
+          cplx<TC> t2 = cadd(a[b][1], a[b][3]), t3 = csub(a[b][1], a[b][3]);
+          // -i*t3 (forward) or +i*t3 (inverse)
+          cplx<TC> it3 = INV ? cplx<TC>{-t3.im, t3.re} : cplx<TC>{t3.im, -t3.re};
+          a[b][0] = cadd(t0, t2);
+          a[b][2] = csub(t0, t2);
+          a[b][1] = cadd(t1, it3);
+          a[b][3] = csub(t1, it3);
+          lc[b] = c;
+          pos[b] = (j - k) * 4 + k;
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int b = 0; b < B; ++b) {
+        if (lc[b] >= 0) {
+          cplx<TC>* z = zc + lc[b] * ls;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) z[pos[b] + r * L] = a[b][r];
+        }
+      }
+      __syncthreads();
+      L <<= 2;
+      rem -= 2;
+    } else {
+      const int nb = H >> 1;
+      cplx<TC> a[2 * B][2];
+      int pos[2 * B];
+      int lc[2 * B];
+#pragma unroll
+      for (int b = 0; b < 2 * B; ++b) {
+        int bi = tid + b * nthr;
+        lc[b] = -1;
+        if (bi < C * nb) {
+          int c = bi / nb;
+          int j = bi - c * nb;
+          int k = j & (L - 1);
+          cplx<TC>* z = zc + c * ls;
+          cplx<TC> x0 = z[j], x1 = z[j + nb];
+          cplx<TC> w = twH[(H / (L * 2)) * k];
+          x1 = INV ? cmulc(x1, w) : cmul(x1, w);
+          a[b][0] = cadd(x0, x1);
+          a[b][1] = csub(x0, x1);
+          lc[b] = c;
+          pos[b] = (j - k) * 2 + k;
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int b = 0; b < 2 * B; ++b) {
+        if (lc[b] >= 0) {
+          cplx<TC>* z = zc + lc[b] * ls;
+          z[pos[b]] = a[b][0];
+          z[pos[b] + L] = a[b][1];
+        }
+      }
+      __syncthreads();
+      L <<= 1;
+      rem -= 1;
+    }
+  }
+}
+
+// Forward post-processing of pair k (0 <= k <= H/2) of one line: from the
+// half-length FFT Z produce X[k], X[N-k], X[H-k], X[H+k].
+template <typename TC>
+__device__ __forceinline__ void post_pair(const cplx<TC>* z, int k, int N, int H,
+                                          const AxisTables<TC>& T, TC* xk, TC* xnk, TC* xhk,
+                                          TC* xhpk) {
+  cplx<TC> Zk = z[k];
+  cplx<TC> Zc = conj_(z[(H - k) & (H - 1)]);
+  cplx<TC> E = {(Zk.re + Zc.re) * TC(0.5), (Zk.im + Zc.im) * TC(0.5)};
+  cplx<TC> D = {(Zk.re - Zc.re) * TC(0.5), (Zk.im - Zc.im) * TC(0.5)};
+  cplx<TC> O = {D.im, -D.re};  // -i * D
+  cplx<TC> WO = cmul(T.tN[k], O);
+  cplx<TC> Vk = cadd(E, WO);
+  cplx<TC> Vj = conj_(csub(E, WO));  // V[H-k]
+  cplx<TC> Y = cmul(T.t4N[k], Vk);
+  cplx<TC> Yj = cmul(T.t4N[H - k], Vj);
+  *xk = TC(2) * Y.re;
+  *xnk = TC(-2) * Y.im;   // X[N-k] (meaningless for k = 0)
+  *xhk = TC(2) * Yj.re;   // X[H-k]
+  *xhpk = TC(-2) * Yj.im; // X[H+k] = X[N-(H-k)]
+}
+
+// Inverse pre-processing of pair k: from X[k], X[N-k], X[H-k], X[H+k]
+// (X[N] = 0) produce Z[k] and Z[H-k] of the half-length inverse FFT.
+template <typename TC>
+__device__ __forceinline__ void pre_pair(TC xk, TC xnk, TC xhk, TC xhpk, int k, int H,
+                                         const AxisTables<TC>& T, cplx<TC>* Zk, cplx<TC>* Zhk) {
+  cplx<TC> Yk = {xk * TC(0.5), -xnk * TC(0.5)};
+  cplx<TC> Yj = {xhk * TC(0.5), -xhpk * TC(0.5)};
+  cplx<TC> Vk = cmulc(Yk, T.t4N[k]);
+  cplx<TC> Vj = cmulc(Yj, T.t4N[H - k]);
+  cplx<TC> Vjc = conj_(Vj);
+  cplx<TC> E = {(Vk.re + Vjc.re) * TC(0.5), (Vk.im + Vjc.im) * TC(0.5)};
+  cplx<TC> D = {(Vk.re - Vjc.re) * TC(0.5), (Vk.im - Vjc.im) * TC(0.5)};
+  cplx<TC> O = cmulc(D, T.tN[k]);
+  *Zk = {E.re - O.im, E.im + O.re};      // E + i O
+  *Zhk = {E.re + O.im, -E.im + O.re};    // conj(E) + i conj(O)
+}
+
+template <typename TC, typename TI, typename TO, int OP, int LD, int ST, int B>
+__global__ void __launch_bounds__(1024) dct_lines(LineArgs<TC> A) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  TC* s = reinterpret_cast<TC*>(smem_raw);
+  const int N = A.N, H = N >> 1, C = A.C;
+  const int ls = N + A.pad;  // line stride in LDS (reals)
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int t = A.axis == 0 ? blockIdx.x : xcd_tile(blockIdx.x, gridDim.x);
+  const TI* __restrict__ in = reinterpret_cast<const TI*>(A.in);
+  TO* __restrict__ out = reinterpret_cast<TO*>(A.out);
+
+  // ---- load ----------------------------------------------------------------
+  for (int e = tid; e < C * N; e += nthr) {
+    int c, n;
+    if (A.axis == 0) { c = e / N; n = e - c * N; } else { n = e / C; c = e - n * C; }
+    int i, o;
+    int64_t p = line_base(A, t, c, &i, &o) + (int64_t)n * A.stride;
+    TC v;
+    if (LD == LD_RESID) {
+      double r = resid_at(A.rb, A.rphi, p, A.d, A.n0, A.n1, A.n2, A.ih2, A.rscale);
+      if (A.sub) r -= *A.sub;
+      v = (TC)r;
+    } else if (A.sub) {
+      v = (TC)((double)in[p] - *A.sub);
+    } else {
+      v = (TC)in[p];
+    }
+    int q = (OP == OP_INV) ? n : mk_pos(n, N);
+    s[c * ls + q] = v;
+  }
+  __syncthreads();
+
+  cplx<TC>* zc = reinterpret_cast<cplx<TC>*>(s);
+  const int lsc = ls >> 1;
+  const int npair = H / 2 + 1;
+
+  if (OP == OP_INV) {
+    // pre-process pairs into Z (in place through registers)
+    constexpr int PB = 2 * B + 1;  // pairs per thread: C*(H/2+1) <= (2B+1)*nthr
+    cplx<TC> zk[PB], zh[PB];
+    int ck[PB], kk[PB];
+#pragma unroll
+    for (int b = 0; b < PB; ++b) {
+      int w = tid + b * nthr;
+      ck[b] = -1;
+      if (w < C * npair) {
+        int c = w / npair, k = w - c * npair;
+        const TC* x = s + c * ls;
+        TC xk = x[k], xnk = k ? x[N - k] : TC(0), xhk = x[H - k], xhpk = x[H + k];
+        pre_pair(xk, xnk, xhk, xhpk, k, H, A.tab, &zk[b], &zh[b]);
+        ck[b] = c;
+        kk[b] = k;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < PB; ++b) {
+      if (ck[b] >= 0) {
+        cplx<TC>* z = zc + ck[b] * lsc;
+        int k = kk[b];
+        z[k] = zk[b];
+        if (k != 0 && k != H - k) z[H - k] = zh[b];
+      }
+    }
+    __syncthreads();
+    fft_lds<TC, B, true>(zc, lsc, C, H, A.logH, A.tab.twH, tid, nthr);
+  } else {
+    fft_lds<TC, B, false>(zc, lsc, C, H, A.logH, A.tab.twH, tid, nthr);
+    constexpr int PB = 2 * B + 1;
+    TC xa[PB], xb[PB], xc[PB], xd[PB];
+    int ck[PB], kk[PB];
+#pragma unroll
+    for (int b = 0; b < PB; ++b) {
+      int w = tid + b * nthr;
+      ck[b] = -1;
+      if (w < C * npair) {
+        int c = w / npair, k = w - c * npair;
+        post_pair(zc + c * lsc, k, N, H, A.tab, &xa[b], &xb[b], &xc[b], &xd[b]);
+        ck[b] = c;
+        kk[b] = k;
+      }
+    }
+    if (OP == OP_FDI) {
+      // divide by the summed eigenvalues, then inverse pre-processing
+      cplx<TC> zk[PB], zh[PB];
+#pragma unroll
+      for (int b = 0; b < PB; ++b) {
+        if (ck[b] >= 0) {
+          int c = ck[b], k = kk[b];
+          int i, o;
+          (void)line_base(A, t, c, &i, &o);
+          TC rest = A.lam0[i];
+          if (A.lam1) rest += A.lam1[o];
+          const TC* lam = A.tab.lam;
+          const TC ls_ = A.lscale;
+          TC l0 = (rest + lam[k]) * ls_, l1 = (rest + lam[(N - k) & (N - 1)]) * ls_,
+             l2 = (rest + lam[H - k]) * ls_, l3 = (rest + lam[H + k]) * ls_;
+          if (k == 0) {
+            if (rest == TC(0) && A.bmean) *A.bmean = (double)xa[b] * A.meannorm;
+            l1 = TC(1);
+          }
+          TC y0 = l0 != TC(0) ? xa[b] / l0 : TC(0);
+          TC y1 = xb[b] / l1;
+          TC y2 = xc[b] / l2;
+          TC y3 = xd[b] / l3;
+          if (k == 0) y1 = TC(0);
+          pre_pair(y0, y1, y2, y3, k, H, A.tab, &zk[b], &zh[b]);
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int b = 0; b < PB; ++b) {
+        if (ck[b] >= 0) {
+          cplx<TC>* z = zc + ck[b] * lsc;
+          int k = kk[b];
+          z[k] = zk[b];
+          if (k != 0 && k != H - k) z[H - k] = zh[b];
+        }
+      }
+      __syncthreads();
+      fft_lds<TC, B, true>(zc, lsc, C, H, A.logH, A.tab.twH, tid, nthr);
+    } else {
+      __syncthreads();
+#pragma unroll
+      for (int b = 0; b < PB; ++b) {
+        if (ck[b] >= 0) {
+          TC* x = s + ck[b] * ls;
+          int k = kk[b];
+          x[k] = xa[b];
+          if (k != 0) x[N - k] = xb[b];
+          if (k != H / 2 || H == 1) x[H - k] = xc[b];
+          if (k != 0 && k != H / 2) x[H + k] = xd[b];
+        }
+      }
+      __syncthreads();
+    }
+  }
+
+  // ---- store ----------------------------------------------------------------
+  for (int e = tid; e < C * N; e += nthr) {
+    int c, n;
+    if (A.axis == 0) { c = e / N; n = e - c * N; } else { n = e / C; c = e - n * C; }
+    int i, o;
+    int64_t p = line_base(A, t, c, &i, &o) + (int64_t)n * A.stride;
+    int q = (OP == OP_FWD) ? n : mk_pos(n, N);
+    TC v = s[c * ls + q] * A.outscale;
+    if (ST == ST_ACCUM) {
+      reinterpret_cast<double*>(A.out)[p] = A.rphi[p] + (double)v;
+    } else {
+      out[p] = (TO)v;
+    }
+  }
+}
+
+// ---- deterministic mean ----------------------------------------------------
+__global__ void __launch_bounds__(256) partial_sum_f64(const double* __restrict__ x, int64_t n,
+                                                       double* __restrict__ part) {
+  __shared__ double red[256];
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    acc += x[i];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void __launch_bounds__(256) finish_mean(const double* __restrict__ part, int nblk,
+                                                   double scale, double* __restrict__ out) {
+  __shared__ double red[256];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < nblk; i += 256) acc += part[i];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = red[0] * scale;
+}
+
+__global__ void __launch_bounds__(256) sub_scalar_f64(double* __restrict__ x, int64_t n,
+                                                      const double* __restrict__ m) {
+  double mv = m[0];
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    x[i] -= mv;
+}
+
+__global__ void __launch_bounds__(256) zero_bytes(uint32_t* __restrict__ p, int64_t nwords) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < nwords;
+       i += (int64_t)gridDim.x * 256)
+    p[i] = 0u;
+}
+
+int g_lds_limit = 0;
+
+int lds_limit() {
+  if (g_lds_limit == 0) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 65536;
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess ||
+        v <= 0)
+      v = 65536;
+    g_lds_limit = v;
+  }
+  return g_lds_limit;
+}
+
+// Chooses lines per tile and threads for one pass.
+template <typename TC>
+void tile_shape(int axis, int N, int lines_x, int* C, int* nthr, int* B) {
+  const int H = N / 2;
+  const int lim = lds_limit();
+  int c;
+  if (axis == 0) {
+    c = 1024 / H;  // aim for C*H/4 = 256 threads
+    if (c < 1) c = 1;
+    while (c > lines_x) c >>= 1;
+  } else {
+    c = (int)(128 / sizeof(TC));  // 128-byte row segments
+    while (c > 1 && (size_t)c * N * sizeof(TC) > (size_t)lim / 2) c >>= 1;
+    while (c > lines_x) c >>= 1;
+  }
+  while (c > 1 && (size_t)c * N * sizeof(TC) > (size_t)lim) c >>= 1;
+  int want = c * H / 4;
+  if (want < 64) want = 64;
+  int t = want > 1024 ? 1024 : want;
+  int b = (c * H / 4 + t - 1) / t;
+  if (b < 1) b = 1;
+  *C = c;
+  *nthr = t;
+  *B = b;
+}
+
+template <typename TC, typename TI, typename TO, int OP, int LD, int ST>
+int launch_pass(const pc_plan* P, int axis, const TI* in, TO* out, const AxisTables<TC>* tabs,
+                const double* rb, const double* rphi, double* bmean, hipStream_t s,
+                const double* sub = nullptr, double sigma = 1.0) {
+  LineArgs<TC> A{};
+  A.sub = sub;
+  A.lscale = (TC)sigma;
+  A.rscale = sigma;
+  A.in = in;
+  A.out = out;
+  A.rb = rb;
+  A.rphi = rphi;
+  A.N = P->n[axis];
+  int H = A.N / 2;
+  int logH = 0;
+  while ((1 << logH) < H) ++logH;
+  A.logH = logH;
+  A.axis = axis;
+  A.d = P->d;
+  A.n0 = P->n[0];
+  A.n1 = P->n[1];
+  A.n2 = P->d == 3 ? P->n[2] : 1;
+  for (int a = 0; a < 3; ++a) A.ih2[a] = a < P->d ? 1.0 / (P->h[a] * P->h[a]) : 0.0;
+  A.stride = axis == 0 ? 1 : (axis == 1 ? (int64_t)P->n[0] : (int64_t)P->n[0] * P->n[1]);
+  A.tab = tabs[axis];
+  A.lam0 = tabs[0].lam;
+  A.lam1 = (P->d == 3 && axis == 2) ? tabs[1].lam : nullptr;
+  A.outscale = (OP == OP_FWD) ? TC(1) : TC(1.0 / (double)H);
+  A.bmean = bmean;
+  double norm = 1.0;
+  for (int a = 0; a < P->d; ++a) norm *= 2.0 * P->n[a];
+  A.meannorm = 1.0 / norm;
+  int C, nthr, B;
+  int64_t lines = P->G / A.N;
+  tile_shape<TC>(axis, A.N, axis == 0 ? (int)std::min<int64_t>(lines, 1 << 20) : P->n[0], &C,
+                 &nthr, &B);
+  A.C = C;
+  if (C > nthr) return fail(PC_ERR_UNSUPPORTED_SIZE, "transform tile has more lines than threads");
+  int ntile;
+  if (axis == 0) {
+    ntile = (int)((lines + C - 1) / C);
+    if (lines % C) return fail(PC_ERR_UNSUPPORTED_SIZE, "row count not a multiple of the tile");
+  } else {
+    A.tx = P->n[0] / C;
+    ntile = (int)(lines / C);
+  }
+  // pad each LDS line by one complex when it fits (fewer bank conflicts)
+  A.pad = ((size_t)C * (A.N + 2) * sizeof(TC) <= (size_t)lds_limit()) ? 2 : 0;
+  size_t lds = (size_t)C * (A.N + A.pad) * sizeof(TC);
+  dim3 grid(ntile), block(nthr);
+  const void* fn;
+  switch (B) {
+    case 1: fn = (const void*)dct_lines<TC, TI, TO, OP, LD, ST, 1>; break;
+    case 2: fn = (const void*)dct_lines<TC, TI, TO, OP, LD, ST, 2>; break;
+    case 4: fn = (const void*)dct_lines<TC, TI, TO, OP, LD, ST, 4>; break;
+    default: return fail(PC_ERR_UNSUPPORTED_SIZE, "transform tile shape");
+  }
+  if (lds > 65536)
+    PC_HIP_CHECK(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  switch (B) {
+    case 1:
+      hipLaunchKernelGGL((dct_lines<TC, TI, TO, OP, LD, ST, 1>), grid, block, lds, s, A);
+      break;
+    case 2:
+      hipLaunchKernelGGL((dct_lines<TC, TI, TO, OP, LD, ST, 2>), grid, block, lds, s, A);
+      break;
+    default:
+      hipLaunchKernelGGL((dct_lines<TC, TI, TO, OP, LD, ST, 4>), grid, block, lds, s, A);
+      break;
+  }
+  PC_HIP_CHECK(hipGetLastError());
+  return PC_OK;
+}
+
+// Full solve with compute type TC from TI input to TO output.  Forward
+// along axes 0..d-2, fused forward/divide/inverse on axis d-1, inverse back.
+// The first pass may compute the float64 residual on the fly (LD) and the
+// last pass may accumulate into float64 phi (ST).
+template <typename TC, typename TI, typename TO, int LD, int ST>
+int solve_passes(const pc_plan* P, const AxisTables<TC>* tabs, const TI* in, TO* out,
+                 TC* work, const double* rb, const double* rphi, double* bmean, hipStream_t s,
+                 const double* sub = nullptr, double sigma = 1.0) {
+  if (P->d == 2) {
+    PC_TRY((launch_pass<TC, TI, TC, OP_FWD, LD, ST_PLAIN>(P, 0, in, work, tabs, rb, rphi, nullptr, s,
+                                                          sub, sigma)));
+    PC_TRY((launch_pass<TC, TC, TC, OP_FDI, LD_PLAIN, ST_PLAIN>(P, 1, work, work, tabs, nullptr,
+                                                                nullptr, bmean, s, nullptr,
+                                                                sigma)));
+    PC_TRY((launch_pass<TC, TC, TO, OP_INV, LD_PLAIN, ST>(P, 0, work, out, tabs, nullptr, rphi,
+                                                          nullptr, s)));
+  } else {
+    PC_TRY((launch_pass<TC, TI, TC, OP_FWD, LD, ST_PLAIN>(P, 0, in, work, tabs, rb, rphi, nullptr, s,
+                                                          sub, sigma)));
+    PC_TRY((launch_pass<TC, TC, TC, OP_FWD, LD_PLAIN, ST_PLAIN>(P, 1, work, work, tabs, nullptr,
+                                                                nullptr, nullptr, s)));
+    PC_TRY((launch_pass<TC, TC, TC, OP_FDI, LD_PLAIN, ST_PLAIN>(P, 2, work, work, tabs, nullptr,
+                                                                nullptr, bmean, s, nullptr,
+                                                                sigma)));
+    PC_TRY((launch_pass<TC, TC, TC, OP_INV, LD_PLAIN, ST_PLAIN>(P, 1, work, work, tabs, nullptr,
+                                                                nullptr, nullptr, s)));
+    PC_TRY((launch_pass<TC, TC, TO, OP_INV, LD_PLAIN, ST>(P, 0, work, out, tabs, nullptr, rphi,
+                                                          nullptr, s)));
+  }
+  return PC_OK;
+}
+
+}  // namespace
+
+int fill_zero(void* p, size_t bytes, hipStream_t s) {
+  if (bytes == 0) return PC_OK;
+  if (bytes % 4) return fail(PC_ERR_INVALID_ARG, "fill_zero size");
+  int64_t nw = (int64_t)(bytes / 4);
+  int nb = (int)std::min<int64_t>(4096, (nw + 255) / 256);
+  hipLaunchKernelGGL(zero_bytes, dim3(nb), dim3(256), 0, s, reinterpret_cast<uint32_t*>(p), nw);
+  PC_HIP_CHECK(hipGetLastError());
+  return PC_OK;
+}
+
+int mean_f64(const double* x, int64_t n, double* partial, int nblk, double* out_dev,
+             hipStream_t s) {
+  hipLaunchKernelGGL(partial_sum_f64, dim3(nblk), dim3(256), 0, s, x, n, partial);
+  hipLaunchKernelGGL(finish_mean, dim3(1), dim3(256), 0, s, partial, nblk, 1.0 / (double)n,
+                     out_dev);
+  PC_HIP_CHECK(hipGetLastError());
+  return PC_OK;
+}
+
+int solve_f64(const pc_plan* P, const double* b, double* phi, double* bmean_dev, pc_workspace*,
+              hipStream_t s, double sigma) {
+  return solve_passes<double, double, double, LD_PLAIN, ST_PLAIN>(
+      P, P->ax64, b, phi, phi, nullptr, nullptr, bmean_dev, s, nullptr, sigma);
+}
+
+int solve_f32(const pc_plan* P, const float* b, float* phi, double* bmean_dev, pc_workspace*,
+              hipStream_t s, double sigma) {
+  return solve_passes<float, float, float, LD_PLAIN, ST_PLAIN>(
+      P, P->ax32, b, phi, phi, nullptr, nullptr, bmean_dev, s, nullptr, sigma);
+}
+
+// Defect correction: bbar = mean(b) in float64; phi0 = S32(b - bbar); then
+// `sweeps` times r = (b - bbar) - lap_h phi (float64, fused into the first
+// pass), phi += S32(r) (accumulated in float64 in the last pass); finally
+// mean(phi) is removed in float64.  The mean is taken out in float64 before
+// each conversion to float32: left in, the compatibility defect would
+// dominate the float32 rounding of the much smaller residual.
+int solve_mixed(const pc_plan* P, const double* b, double* phi, int sweeps, double* bmean_dev,
+                pc_workspace* ws, hipStream_t s, double sigma) {
+  if (!ws || !ws->w32) return fail(PC_ERR_INVALID_ARG, "mixed solve needs a MIXED workspace");
+  float* w = ws->w32;
+  double* bm = bmean_dev ? bmean_dev : ws->scal;
+  PC_TRY(mean_f64(b, P->G, ws->partial, ws->nblk, bm, s));
+  PC_TRY((solve_passes<float, double, double, LD_PLAIN, ST_PLAIN>(P, P->ax32, b, phi, w, nullptr,
+                                                                  nullptr, nullptr, s, bm, sigma)));
+  for (int it = 0; it < sweeps; ++it) {
+    PC_TRY((solve_passes<float, double, double, LD_RESID, ST_ACCUM>(P, P->ax32, b, phi, w, b, phi,
+                                                                    nullptr, s, bm, sigma)));
+  }
+  PC_TRY(mean_f64(phi, P->G, ws->partial, ws->nblk, ws->scal + 3, s));
+  int nb = (int)std::min<int64_t>(8192, (P->G + 255) / 256);
+  hipLaunchKernelGGL(sub_scalar_f64, dim3(nb), dim3(256), 0, s, phi, P->G,
+                     (const double*)(ws->scal + 3));
+  PC_HIP_CHECK(hipGetLastError());
+  return PC_OK;
+}
+
+}  // namespace pc

@@ -1,0 +1,648 @@
+// Transfers between nodes and grid and the whole pressure-correction
+// sub-step (Sec. 2.3).
+//
+//   div_to_grid   b_p = sum_a sum_i c^a_{p,i} v_a[idx_{p,i}]      (RHS of Eq. 20)
+//   grad_to_nodes G_a(n) = sum_j c^a_{n,j} phi[src_{n,j}]          (Eqs. 18-19)
+//   ib_update     g = -u* + G at the B+V nodes, criterion sums      (Eq. 19)
+//   project       u^{n+1} = u* - G on F, exactly 0 on B+V          (Eq. 18)
+//
+// The gathers are one thread per target.  Stencil arrays are laid out
+// [entry][target] so that a wavefront reads 64 consecutive targets of one
+// entry in one coalesced access; they are streamed with non-temporal loads so
+// that the gathered field values (re-read by neighbouring targets) keep the
+// caches.  In float32 mode the sums are taken relative to the value at the
+// first stencil entry: the derivative rows annihilate constants, and the
+// differences avoid the cancellation of sum_i c_i v_i (|c| ~ 1/h) in float32.
+#include <cmath>
+#include <cstring>
+
+#include "pc_internal.h"
+
+namespace pc {
+namespace {
+
+constexpr int XCDS = 8;
+
+__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nb) {
+  if (nb % XCDS != 0) return b;
+  return (b % XCDS) * (nb / XCDS) + b / XCDS;
+}
+
+template <typename T>
+__device__ __forceinline__ T ldnt(const T* p) {
+  return __builtin_nontemporal_load(p);
+}
+
+constexpr int TPB = 256;
+
+// ---- div_to_grid (all grid points) -------------------------------------------
+template <typename T, int D, int K, bool LOCALREF>
+__global__ void __launch_bounds__(TPB) k_div_all(const int32_t* __restrict__ gidx,
+                                                 const T* __restrict__ gcoef, int64_t G, int krt,
+                                                 const T* __restrict__ v, int64_t M,
+                                                 T* __restrict__ b) {
+  const int k = K > 0 ? K : krt;
+  const int64_t p = xcd_block(blockIdx.x, gridDim.x) * TPB + threadIdx.x;
+  if (p >= G) return;
+  T acc = T(0);
+  T ref[D];
+  if (LOCALREF) {
+    int j0 = ldnt(gidx + p);
+#pragma unroll
+    for (int a = 0; a < D; ++a) ref[a] = v[a * M + j0];
+  }
+#pragma unroll 4
+  for (int i = 0; i < k; ++i) {
+    int j = ldnt(gidx + (int64_t)i * G + p);
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      T c = ldnt(gcoef + ((int64_t)a * k + i) * G + p);
+      T val = v[a * M + j];
+      if (LOCALREF) val -= ref[a];
+      acc += c * val;
+    }
+  }
+  b[p] = acc;
+}
+
+// ---- div_to_grid near the IB: b[near[q]] = base[q] (or b) + D(g) -----------
+template <typename T, int D, bool ADD>
+__global__ void __launch_bounds__(TPB) k_div_near(const int32_t* __restrict__ near, int64_t nnear,
+                                                  const int32_t* __restrict__ nptr,
+                                                  const int32_t* __restrict__ nslot,
+                                                  const T* __restrict__ ncoef, int64_t nent,
+                                                  const T* __restrict__ gib, int64_t nib,
+                                                  const T* __restrict__ base, T* __restrict__ b) {
+  int64_t q = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  if (q >= nnear) return;
+  T acc = T(0);
+  for (int e = nptr[q]; e < nptr[q + 1]; ++e) {
+    int s = nslot[e];
+#pragma unroll
+    for (int a = 0; a < D; ++a) acc += ncoef[a * nent + e] * gib[a * nib + s];
+  }
+  int64_t p = near[q];
+  if (ADD)
+    b[p] += acc;
+  else
+    b[p] = base[q] + acc;
+}
+
+// ---- grad_to_nodes (all nodes), optionally fused with the projection ---------
+struct BlockOffsets {
+  int32_t off[PC_MAX_K_NODE];
+};
+
+template <typename T, int D, int BN, bool LOCALREF, bool PROJECT>
+__global__ void __launch_bounds__(TPB) k_grad_all(const int32_t* __restrict__ nbase,
+                                                  const T* __restrict__ ncoef, int64_t M,
+                                                  int bnrt, BlockOffsets bo,
+                                                  const T* __restrict__ phi, T scale,
+                                                  const T* __restrict__ u,
+                                                  T* __restrict__ out) {
+  const int bn = BN > 0 ? BN : bnrt;
+  const int64_t n = xcd_block(blockIdx.x, gridDim.x) * TPB + threadIdx.x;
+  if (n >= M) return;
+  const int64_t base = ldnt(nbase + n);
+  T acc[D];
+#pragma unroll
+  for (int a = 0; a < D; ++a) acc[a] = T(0);
+  T ref = LOCALREF ? phi[base + bo.off[0]] : T(0);
+#pragma unroll 9
+  for (int o = 0; o < bn; ++o) {
+    T f = phi[base + bo.off[o]];
+    if (LOCALREF) f -= ref;
+#pragma unroll
+    for (int a = 0; a < D; ++a) acc[a] += ldnt(ncoef + ((int64_t)a * bn + o) * M + n) * f;
+  }
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    if (PROJECT)
+      out[a * M + n] = u[a * M + n] - scale * acc[a];
+    else
+      out[a * M + n] = scale * acc[a];
+  }
+}
+
+// ---- grad at the B+V nodes (compact stencils) ---------------------------------
+template <typename T, int D, bool LOCALREF>
+__global__ void __launch_bounds__(TPB) k_grad_ib(const int32_t* __restrict__ ibbase,
+                                                 const T* __restrict__ ibcoef, int64_t nib, int bn,
+                                                 BlockOffsets bo, const T* __restrict__ phi,
+                                                 T scale, T* __restrict__ out) {
+  const int64_t s = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  if (s >= nib) return;
+  const int64_t base = ibbase[s];
+  T acc[D];
+#pragma unroll
+  for (int a = 0; a < D; ++a) acc[a] = T(0);
+  T ref = LOCALREF ? phi[base + bo.off[0]] : T(0);
+  for (int o = 0; o < bn; ++o) {
+    T f = phi[base + bo.off[o]];
+    if (LOCALREF) f -= ref;
+#pragma unroll
+    for (int a = 0; a < D; ++a) acc[a] += ibcoef[((int64_t)a * bn + o) * nib + s] * f;
+  }
+#pragma unroll
+  for (int a = 0; a < D; ++a) out[a * nib + s] = scale * acc[a];
+}
+
+// ---- gathers / scatters on the IB list ------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(TPB) k_gather_ib(const int32_t* __restrict__ ib, int64_t nib,
+                                                   int d, const T* __restrict__ u, int64_t M,
+                                                   T* __restrict__ uib) {
+  int64_t s = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  if (s >= nib) return;
+  int64_t n = ib[s];
+  for (int a = 0; a < d; ++a) uib[a * nib + s] = u[a * M + n];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(TPB) k_zero_ib(const int32_t* __restrict__ ib, int64_t nib,
+                                                 int d, int64_t M, T* __restrict__ out) {
+  int64_t s = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  if (s >= nib) return;
+  int64_t n = ib[s];
+  for (int a = 0; a < d; ++a) out[a * M + n] = T(0);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(TPB) k_gather_near(const int32_t* __restrict__ near,
+                                                     int64_t nnear, const T* __restrict__ b,
+                                                     T* __restrict__ bnear) {
+  int64_t q = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  if (q < nnear) bnear[q] = b[near[q]];
+}
+
+// ---- IB-force update with deterministic criterion sums ----------------------------
+constexpr int IB_BLOCKS = 256;
+
+template <typename T, int D>
+__global__ void __launch_bounds__(TPB) k_ib_update(const T* __restrict__ uib,
+                                                   const T* __restrict__ grad, T* __restrict__ g,
+                                                   int64_t nib, double* __restrict__ part) {
+  __shared__ double rn[TPB], rd[TPB];
+  double num = 0.0, den = 0.0;
+  for (int64_t s = (int64_t)blockIdx.x * TPB + threadIdx.x; s < nib;
+       s += (int64_t)gridDim.x * TPB) {
+    double mn = 0.0, mo = 0.0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      T gn = -uib[a * nib + s] + grad[a * nib + s];
+      T go = g[a * nib + s];
+      mn += (double)gn * (double)gn;
+      mo += (double)go * (double)go;
+      g[a * nib + s] = gn;
+    }
+    double dm = sqrt(mn) - sqrt(mo);
+    num += dm * dm;
+    den += mo;
+  }
+  rn[threadIdx.x] = num;
+  rd[threadIdx.x] = den;
+  __syncthreads();
+  for (int w = TPB / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      rn[threadIdx.x] += rn[threadIdx.x + w];
+      rd[threadIdx.x] += rd[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = rn[0];
+    part[2 * blockIdx.x + 1] = rd[0];
+  }
+}
+
+__global__ void __launch_bounds__(TPB) k_ib_finish(const double* __restrict__ part, int nblk,
+                                                   double tol, double* __restrict__ sums,
+                                                   int32_t* __restrict__ conv) {
+  __shared__ double rn[TPB], rd[TPB];
+  double num = 0.0, den = 0.0;
+  for (int i = threadIdx.x; i < nblk; i += TPB) {
+    num += part[2 * i];
+    den += part[2 * i + 1];
+  }
+  rn[threadIdx.x] = num;
+  rd[threadIdx.x] = den;
+  __syncthreads();
+  for (int w = TPB / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      rn[threadIdx.x] += rn[threadIdx.x + w];
+      rd[threadIdx.x] += rd[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    sums[0] = rn[0];
+    sums[1] = rd[0];
+    conv[0] = (rn[0] < tol * rd[0] || rn[0] == 0.0) ? 1 : 0;
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(TPB) k_project(const T* __restrict__ u, const T* __restrict__ grad,
+                                                 int64_t n, T* __restrict__ out) {
+  int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  if (i < n) out[i] = u[i] - grad[i];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(TPB) k_sub_first(T* __restrict__ x, int64_t n) {
+  // gauge: subtract the value at the first cell (read once per thread before
+  // any write of this launch can reach it: element 0 is written last)
+  T v0 = x[0];
+  int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  if (i > 0 && i < n) x[i] -= v0;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(1) k_zero_first(T* __restrict__ x) {
+  x[0] = T(0);
+}
+
+unsigned nblk(int64_t n) { return (unsigned)((n + TPB - 1) / TPB); }
+
+BlockOffsets block_offsets(const pc_geom* g) {
+  BlockOffsets bo;
+  std::memset(&bo, 0, sizeof(bo));
+  const int m = g->m_node;
+  for (int o = 0; o < g->bn; ++o) {
+    int ox = o % m, oy = (o / m) % m, oz = o / (m * m);
+    bo.off[o] = ox + g->n[0] * (oy + g->n[1] * (g->d == 3 ? oz : 0));
+  }
+  return bo;
+}
+
+int check_dtype(const pc_geom* g, int dtype) {
+  if (dtype != PC_F64 && dtype != PC_F32)
+    return fail(PC_ERR_INVALID_ARG, "dtype must be PC_F64 or PC_F32");
+  if (dtype == PC_F32 && !g->has32)
+    return fail(PC_ERR_INVALID_ARG, "geometry was built without float32 stencils");
+  return PC_OK;
+}
+
+// ---- launch helpers ---------------------------------------------------------------
+template <typename T>
+int launch_div_all(const pc_geom* g, const T* gcoef, const T* v, T* b, hipStream_t s) {
+  const bool lr = sizeof(T) == 4;
+  dim3 grid(nblk(g->G)), block(TPB);
+#define DIVL(D, K)                                                                           \
+  do {                                                                                      \
+    if (lr)                                                                                 \
+      hipLaunchKernelGGL((k_div_all<T, D, K, true>), grid, block, 0, s, g->gidx, gcoef, g->G, \
+                         g->k_grid, v, g->M, b);                                           \
+    else                                                                                    \
+      hipLaunchKernelGGL((k_div_all<T, D, K, false>), grid, block, 0, s, g->gidx, gcoef, g->G, \
+                         g->k_grid, v, g->M, b);                                           \
+  } while (0)
+  if (g->d == 2) {
+    if (g->k_grid == 16) DIVL(2, 16);
+    else if (g->k_grid == 12) DIVL(2, 12);
+    else DIVL(2, 0);
+  } else {
+    if (g->k_grid == 27) DIVL(3, 27);
+    else DIVL(3, 0);
+  }
+#undef DIVL
+  PC_HIP_CHECK(hipGetLastError());
+  return PC_OK;
+}
+
+template <typename T>
+int launch_div_near(const pc_geom* g, const T* ncoefib, const T* gib, const T* base, T* b,
+                    bool add, hipStream_t s) {
+  if (g->n_near == 0) return PC_OK;
+  dim3 grid(nblk(g->n_near)), block(TPB);
+#define DNL(D, ADD)                                                                          \
+  hipLaunchKernelGGL((k_div_near<T, D, ADD>), grid, block, 0, s, g->near, g->n_near, g->nptr, \
+                     g->nslot, ncoefib, g->n_near_entries, gib, g->n_ib, base, b)
+  if (g->d == 2) {
+    if (add) DNL(2, true); else DNL(2, false);
+  } else {
+    if (add) DNL(3, true); else DNL(3, false);
+  }
+#undef DNL
+  PC_HIP_CHECK(hipGetLastError());
+  return PC_OK;
+}
+
+template <typename T, bool PROJECT>
+int launch_grad_all(const pc_geom* g, const T* ncoef, const T* phi, T scale, const T* u, T* out,
+                    hipStream_t s) {
+  const bool lr = sizeof(T) == 4;
+  BlockOffsets bo = block_offsets(g);
+  dim3 grid(nblk(g->M)), block(TPB);
+#define GRL(D, BN)                                                                            \
+  do {                                                                                       \
+    if (lr)                                                                                  \
+      hipLaunchKernelGGL((k_grad_all<T, D, BN, true, PROJECT>), grid, block, 0, s, g->nbase,  \
+                         ncoef, g->M, g->bn, bo, phi, scale, u, out);                        \
+    else                                                                                     \
+      hipLaunchKernelGGL((k_grad_all<T, D, BN, false, PROJECT>), grid, block, 0, s, g->nbase, \
+                         ncoef, g->M, g->bn, bo, phi, scale, u, out);                        \
+  } while (0)
+  if (g->d == 2) {
+    if (g->bn == 16) GRL(2, 16);
+    else GRL(2, 0);
+  } else {
+    if (g->bn == 27) GRL(3, 27);
+    else GRL(3, 0);
+  }
+#undef GRL
+  PC_HIP_CHECK(hipGetLastError());
+  return PC_OK;
+}
+
+template <typename T>
+int launch_grad_ib(const pc_geom* g, const T* ibcoef, const T* phi, T scale, T* out,
+                   hipStream_t s) {
+  if (g->n_ib == 0) return PC_OK;
+  const bool lr = sizeof(T) == 4;
+  BlockOffsets bo = block_offsets(g);
+  dim3 grid(nblk(g->n_ib)), block(TPB);
+  if (g->d == 2) {
+    if (lr)
+      hipLaunchKernelGGL((k_grad_ib<T, 2, true>), grid, block, 0, s, g->ibbase, ibcoef, g->n_ib,
+                         g->bn, bo, phi, scale, out);
+    else
+      hipLaunchKernelGGL((k_grad_ib<T, 2, false>), grid, block, 0, s, g->ibbase, ibcoef, g->n_ib,
+                         g->bn, bo, phi, scale, out);
+  } else {
+    if (lr)
+      hipLaunchKernelGGL((k_grad_ib<T, 3, true>), grid, block, 0, s, g->ibbase, ibcoef, g->n_ib,
+                         g->bn, bo, phi, scale, out);
+    else
+      hipLaunchKernelGGL((k_grad_ib<T, 3, false>), grid, block, 0, s, g->ibbase, ibcoef, g->n_ib,
+                         g->bn, bo, phi, scale, out);
+  }
+  PC_HIP_CHECK(hipGetLastError());
+  return PC_OK;
+}
+
+template <typename T>
+int launch_ib_update(const pc_geom* g, const T* uib, const T* grad, T* gib, double tol,
+                     double* part, double* sums, int32_t* conv, hipStream_t s) {
+  int nb = (int)std::min<int64_t>(IB_BLOCKS, std::max<int64_t>(1, nblk(g->n_ib)));
+  if (g->d == 2)
+    hipLaunchKernelGGL((k_ib_update<T, 2>), dim3(nb), dim3(TPB), 0, s, uib, grad, gib, g->n_ib, part);
+  else
+    hipLaunchKernelGGL((k_ib_update<T, 3>), dim3(nb), dim3(TPB), 0, s, uib, grad, gib, g->n_ib, part);
+  hipLaunchKernelGGL(k_ib_finish, dim3(1), dim3(TPB), 0, s, (const double*)part, nb, tol, sums,
+                     conv);
+  PC_HIP_CHECK(hipGetLastError());
+  return PC_OK;
+}
+
+template <typename T>
+int launch_zero_ib(const pc_geom* g, T* out, hipStream_t s) {
+  if (g->n_ib == 0) return PC_OK;
+  hipLaunchKernelGGL(k_zero_ib<T>, dim3(nblk(g->n_ib)), dim3(TPB), 0, s, g->ib, g->n_ib, g->d,
+                     g->M, out);
+  PC_HIP_CHECK(hipGetLastError());
+  return PC_OK;
+}
+
+template <typename T>
+const T* gc(const pc_geom* g) {
+  if constexpr (sizeof(T) == 8) return g->gcoef; else return g->gcoef32;
+}
+template <typename T>
+const T* nc(const pc_geom* g) {
+  if constexpr (sizeof(T) == 8) return g->ncoef; else return g->ncoef32;
+}
+template <typename T>
+const T* nci(const pc_geom* g) {
+  if constexpr (sizeof(T) == 8) return g->ncoefib; else return g->ncoefib32;
+}
+template <typename T>
+const T* ibc(const pc_geom* g) {
+  if constexpr (sizeof(T) == 8) return g->ibcoef; else return g->ibcoef32;
+}
+
+// ---- the sub-step ---------------------------------------------------------------------
+template <typename T>
+int pressure_correct_t(const pc_geom* g, const pc_plan* P, int mode, const T* u, double dt,
+                       T* u_out, T* p_out, T* g_io, const pc_ib_opts* o, pc_stats* st,
+                       pc_workspace* W, hipStream_t s) {
+  const double tol = o && o->tol > 0.0 ? o->tol : 1e-3;
+  const int max_it = o && o->max_it > 0 ? o->max_it : 50;
+  const int fixed_it = o ? o->fixed_it : 0;
+  const int sweeps = o && o->sweeps > 0 ? o->sweeps : 2;
+  const int gauge = o ? o->gauge : 0;
+  // the solve returns p = phi / sigma directly; the gradient of phi is
+  // sigma * grad p
+  const double sigma = 1.5 * dt;
+  T* b = reinterpret_cast<T*>(W->b);
+  T* p = p_out;
+  T* bnear = reinterpret_cast<T*>(W->bnear);
+  T* uib = reinterpret_cast<T*>(W->uib);
+  T* gib = reinterpret_cast<T*>(W->gib);
+  T* gradib = reinterpret_cast<T*>(W->gradib);
+  const int64_t nib = g->n_ib;
+
+  if (nib) {
+    hipLaunchKernelGGL(k_gather_ib<T>, dim3(nblk(nib)), dim3(TPB), 0, s, g->ib, nib, g->d, u, g->M,
+                       uib);
+    if (g_io)
+      PC_HIP_CHECK(hipMemcpyAsync(gib, g_io, (size_t)g->d * nib * sizeof(T),
+                                  hipMemcpyDeviceToDevice, s));
+    else
+      PC_TRY(fill_zero(gib, (size_t)g->d * nib * sizeof(T), s));
+  }
+  PC_TRY(launch_div_all<T>(g, gc<T>(g), u, b, s));
+  if (g->n_near)
+    hipLaunchKernelGGL(k_gather_near<T>, dim3(nblk(g->n_near)), dim3(TPB), 0, s, g->near, g->n_near,
+                       (const T*)b, bnear);
+  PC_TRY(fill_zero(W->flag, 16 * 4, s));
+
+  int it = 0;
+  bool converged = nib == 0;
+  while (true) {
+    ++it;
+    if (it > 1 || g_io) PC_TRY(launch_div_near<T>(g, nci<T>(g), gib, bnear, b, false, s));
+    if (mode == PC_F64)
+      PC_TRY(solve_f64(P, (const double*)b, (double*)p, W->scal, W, s, sigma));
+    else if (mode == PC_F32)
+      PC_TRY(solve_f32(P, (const float*)b, (float*)p, W->scal, W, s, sigma));
+    else
+      PC_TRY(solve_mixed(P, (const double*)b, (double*)p, sweeps, W->scal, W, s, sigma));
+    if (nib == 0) break;
+    PC_TRY(launch_grad_ib<T>(g, ibc<T>(g), p, (T)sigma, gradib, s));
+    PC_TRY(launch_ib_update<T>(g, uib, gradib, gib, tol, W->partial, W->scal + 1, W->flag, s));
+    if (fixed_it > 0) {
+      if (it >= fixed_it) break;
+      continue;
+    }
+    PC_HIP_CHECK(hipMemcpyAsync(W->hflag, W->flag, 4, hipMemcpyDeviceToHost, s));
+    PC_HIP_CHECK(hipStreamSynchronize(s));
+    if (W->hflag[0]) {
+      converged = true;
+      break;
+    }
+    if (it >= max_it) break;
+  }
+  PC_TRY((launch_grad_all<T, true>(g, nc<T>(g), p, (T)sigma, u, u_out, s)));
+  PC_TRY(launch_zero_ib<T>(g, u_out, s));
+  if (g_io && nib)
+    PC_HIP_CHECK(hipMemcpyAsync(g_io, gib, (size_t)g->d * nib * sizeof(T), hipMemcpyDeviceToDevice, s));
+  if (gauge == 1) {
+    hipLaunchKernelGGL(k_sub_first<T>, dim3(nblk(P->G)), dim3(TPB), 0, s, p, P->G);
+    hipLaunchKernelGGL(k_zero_first<T>, dim3(1), dim3(1), 0, s, p);
+    PC_HIP_CHECK(hipGetLastError());
+  }
+  if (st) {
+    PC_HIP_CHECK(hipMemcpyAsync(W->hscal, W->scal, 16 * 8, hipMemcpyDeviceToHost, s));
+    PC_HIP_CHECK(hipMemcpyAsync(W->hflag, W->flag, 4, hipMemcpyDeviceToHost, s));
+    PC_HIP_CHECK(hipStreamSynchronize(s));
+    st->n_it = it;
+    st->converged = (nib == 0 || W->hflag[0]) ? 1 : 0;
+    st->bmean = W->hscal[0];
+    st->ib_num = W->hscal[1];
+    st->ib_den = W->hscal[2];
+    converged = st->converged;
+  }
+  if (fixed_it > 0) return PC_OK;
+  return converged ? PC_OK : PC_WARN_IB_NOT_CONVERGED;
+}
+
+int check_fields(const void* a, const void* b = nullptr, const void* c = nullptr) {
+  if (!a) return fail(PC_ERR_INVALID_ARG, "null field");
+  for (const void* p : {a, b, c})
+    if (p && !aligned16(p)) return fail(PC_ERR_ALIGN, "fields must be 16-byte aligned");
+  return PC_OK;
+}
+
+}  // namespace
+}  // namespace pc
+
+using namespace pc;
+
+extern "C" {
+
+int pc_div_to_grid(const pc_geom* g, int dtype, const void* v, void* b, int subset,
+                   void* stream) {
+  if (!g || !v || !b) return fail(PC_ERR_INVALID_ARG, "pc_div_to_grid: null argument");
+  PC_TRY(check_dtype(g, dtype));
+  PC_TRY(check_fields(v, b));
+  hipStream_t s = as_stream(stream);
+  if (subset == PC_ALL) {
+    if (dtype == PC_F64) return launch_div_all<double>(g, g->gcoef, (const double*)v, (double*)b, s);
+    return launch_div_all<float>(g, g->gcoef32, (const float*)v, (float*)b, s);
+  }
+  if (subset == PC_NEAR_IB) {
+    if (dtype == PC_F64)
+      return launch_div_near<double>(g, g->ncoefib, (const double*)v, nullptr, (double*)b, true, s);
+    return launch_div_near<float>(g, g->ncoefib32, (const float*)v, nullptr, (float*)b, true, s);
+  }
+  return fail(PC_ERR_INVALID_ARG, "subset must be PC_ALL or PC_NEAR_IB");
+}
+
+int pc_grad_to_nodes(const pc_geom* g, int dtype, const void* phi, void* grad, int subset,
+                     void* stream) {
+  if (!g || !phi || !grad) return fail(PC_ERR_INVALID_ARG, "pc_grad_to_nodes: null argument");
+  PC_TRY(check_dtype(g, dtype));
+  PC_TRY(check_fields(phi, grad));
+  hipStream_t s = as_stream(stream);
+  if (subset == PC_ALL) {
+    if (dtype == PC_F64)
+      return launch_grad_all<double, false>(g, g->ncoef, (const double*)phi, 1.0, nullptr,
+                                            (double*)grad, s);
+    return launch_grad_all<float, false>(g, g->ncoef32, (const float*)phi, 1.0f, nullptr,
+                                         (float*)grad, s);
+  }
+  if (subset == PC_IB) {
+    if (dtype == PC_F64)
+      return launch_grad_ib<double>(g, g->ibcoef, (const double*)phi, 1.0, (double*)grad, s);
+    return launch_grad_ib<float>(g, g->ibcoef32, (const float*)phi, 1.0f, (float*)grad, s);
+  }
+  return fail(PC_ERR_INVALID_ARG, "subset must be PC_ALL or PC_IB");
+}
+
+int pc_ib_update(const pc_geom* g, int dtype, const void* u, const void* grad_ib, void* gib,
+                 double tol, double* sums, int32_t* conv, void* stream) {
+  if (!g || !u || !grad_ib || !gib || !sums || !conv)
+    return fail(PC_ERR_INVALID_ARG, "pc_ib_update: null argument");
+  PC_TRY(check_dtype(g, dtype));
+  PC_TRY(check_fields(u, grad_ib, gib));
+  if (g->n_ib == 0) return PC_OK;
+  hipStream_t s = as_stream(stream);
+  size_t es = dtype == PC_F64 ? 8 : 4;
+  // scratch: compact u* and the partial sums
+  void* tmp = nullptr;
+  PC_TRY(dev_alloc(&tmp, (size_t)g->d * g->n_ib * es + 2 * IB_BLOCKS * 8 + 256, "ib scratch"));
+  double* part = reinterpret_cast<double*>(tmp);
+  void* uib = reinterpret_cast<char*>(tmp) + 2 * IB_BLOCKS * 8 + 256;
+  int rc;
+  if (dtype == PC_F64) {
+    hipLaunchKernelGGL(k_gather_ib<double>, dim3(nblk(g->n_ib)), dim3(TPB), 0, s, g->ib, g->n_ib,
+                       g->d, (const double*)u, g->M, (double*)uib);
+    rc = launch_ib_update<double>(g, (const double*)uib, (const double*)grad_ib, (double*)gib, tol,
+                                  part, sums, conv, s);
+  } else {
+    hipLaunchKernelGGL(k_gather_ib<float>, dim3(nblk(g->n_ib)), dim3(TPB), 0, s, g->ib, g->n_ib,
+                       g->d, (const float*)u, g->M, (float*)uib);
+    rc = launch_ib_update<float>(g, (const float*)uib, (const float*)grad_ib, (float*)gib, tol,
+                                 part, sums, conv, s);
+  }
+  (void)hipStreamSynchronize(s);
+  dev_free(tmp);
+  return rc;
+}
+
+int pc_project(const pc_geom* g, int dtype, const void* u, const void* grad, void* u_out,
+               void* stream) {
+  if (!g || !u || !grad || !u_out) return fail(PC_ERR_INVALID_ARG, "pc_project: null argument");
+  if (dtype != PC_F64 && dtype != PC_F32) return fail(PC_ERR_INVALID_ARG, "dtype");
+  PC_TRY(check_fields(u, grad, u_out));
+  hipStream_t s = as_stream(stream);
+  // u_out = u - grad on every node, then exactly 0 on the B+V nodes
+  int64_t n = (int64_t)g->d * g->M;
+  if (dtype == PC_F64) {
+    hipLaunchKernelGGL((k_project<double>), dim3(nblk(n)), dim3(TPB), 0, s, (const double*)u,
+                       (const double*)grad, n, (double*)u_out);
+    PC_HIP_CHECK(hipGetLastError());
+    return launch_zero_ib<double>(g, (double*)u_out, s);
+  }
+  hipLaunchKernelGGL((k_project<float>), dim3(nblk(n)), dim3(TPB), 0, s, (const float*)u,
+                     (const float*)grad, n, (float*)u_out);
+  PC_HIP_CHECK(hipGetLastError());
+  return launch_zero_ib<float>(g, (float*)u_out, s);
+}
+
+int pc_pressure_correct(const pc_geom* g, const pc_plan* P, int mode, const void* u, double dt,
+                        void* u_out, void* p, void* g_io, const pc_ib_opts* o, pc_stats* st,
+                        pc_workspace* ws, void* stream) {
+  if (!g || !P || !u || !u_out || !p)
+    return fail(PC_ERR_INVALID_ARG, "pc_pressure_correct: null argument");
+  if (mode != PC_F64 && mode != PC_F32 && mode != PC_MIXED)
+    return fail(PC_ERR_INVALID_ARG, "mode must be PC_F64, PC_F32 or PC_MIXED");
+  if (g->G != P->G || g->d != P->d) return fail(PC_ERR_INVALID_ARG, "plan and geometry differ");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(PC_ERR_INVALID_ARG, "dt must be positive");
+  if (mode == PC_F32 && !g->has32)
+    return fail(PC_ERR_INVALID_ARG, "geometry was built without float32 stencils");
+  PC_TRY(check_fields(u, u_out, p));
+  if (g_io && !aligned16(g_io)) return fail(PC_ERR_ALIGN, "g must be 16-byte aligned");
+  if (u == u_out) return fail(PC_ERR_INVALID_ARG, "u_out must not alias u");
+  if (ws) {
+    if (ws->mode != mode || ws->geom != g || ws->plan != P)
+      return fail(PC_ERR_INVALID_ARG, "workspace was created for another mode/plan/geometry");
+  } else {
+    pc_geom* mg = const_cast<pc_geom*>(g);
+    if (mg->own_ws && (mg->own_ws->mode != mode || mg->own_ws->plan != P)) {
+      pc_workspace_destroy(mg->own_ws);
+      mg->own_ws = nullptr;
+    }
+    if (!mg->own_ws) PC_TRY(pc_workspace_create(P, g, mode, &mg->own_ws));
+    ws = mg->own_ws;
+  }
+  hipStream_t s = as_stream(stream);
+  if (mode == PC_F32)
+    return pressure_correct_t<float>(g, P, mode, (const float*)u, dt, (float*)u_out, (float*)p,
+                                     (float*)g_io, o, st, ws, s);
+  return pressure_correct_t<double>(g, P, mode, (const double*)u, dt, (double*)u_out, (double*)p,
+                                    (double*)g_io, o, st, ws, s);
+}
+
+}  // extern "C"

@@ -1,0 +1,853 @@
+// WLS stencils of one node cloud (Sec. 2.2), computed once per geometry
+// ("the coefficients only need to be calculated once", last paragraph of
+// Sec. 2.2):
+//   * a cell list of the nodes over the pressure-grid cells (the paper's
+//     linked-list neighbour search, here a counting sort);
+//   * for every grid point, its k_grid nearest nodes by the key (d^2, node
+//     index) with d^2 = ((dx*dx) + dy*dy) + dz*dz rounded term by term,
+//     found by scanning rings of cells until no unscanned cell can hold a
+//     closer node;
+//   * for every node, the k_node nearest grid points by (d^2, flat index)
+//     within the block of the m grid lines nearest to it along each axis
+//     (block clamped inside the box);
+//   * per target, the Eq. 16 polynomial vector (10 terms in 3D) in
+//     coordinates scaled by h_t = max(support*delta, r_k), the Gaussian
+//     weights of Eq. 17, C = sum w q q^T (Eq. 14), its Cholesky factor, and
+//     the first-derivative rows of C^-1 A (Eq. 13): c_{a,i} = w_i (C^-1 q_i)_a
+//     / h_t, all in float64;
+//   * the boundary/virtual node list, the grid points whose stencil holds
+//     one of them, and compact copies of the stencils the IB iteration uses.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "pc_internal.h"
+
+namespace pc {
+namespace {
+
+constexpr int KMAX = PC_MAX_K_GRID;   // grid-target stencil capacity
+constexpr int BNMAX = PC_MAX_K_NODE;  // node block capacity
+constexpr double SINGULAR_RATIO = 1e-12;
+
+// ---- exact squared distance (no contraction) --------------------------------
+__device__ __forceinline__ double sq_sum2(double dx, double dy) {
+#pragma clang fp contract(off)
+  double a = dx * dx;
+  double b = dy * dy;
+  return a + b;
+}
+__device__ __forceinline__ double sq_sum3(double dx, double dy, double dz) {
+#pragma clang fp contract(off)
+  double a = dx * dx;
+  double b = dy * dy;
+  double c = dz * dz;
+  return (a + b) + c;
+}
+
+__device__ __forceinline__ bool key_lt(double d1, int i1, double d2, int i2) {
+  return d1 < d2 || (d1 == d2 && i1 < i2);
+}
+
+// Eq. 16 polynomial vector (2D: 6 terms; 3D: 10 terms) of scaled offsets.
+template <int D>
+__device__ __forceinline__ void basis(const double* xi, double* q) {
+  if (D == 2) {
+    q[0] = 1.0; q[1] = xi[0]; q[2] = xi[1];
+    q[3] = 0.5 * xi[0] * xi[0]; q[4] = xi[0] * xi[1]; q[5] = 0.5 * xi[1] * xi[1];
+  } else {
+    q[0] = 1.0; q[1] = xi[0]; q[2] = xi[1]; q[3] = xi[2];
+    q[4] = 0.5 * xi[0] * xi[0]; q[5] = xi[0] * xi[1]; q[6] = xi[0] * xi[2];
+    q[7] = 0.5 * xi[1] * xi[1]; q[8] = xi[1] * xi[2]; q[9] = 0.5 * xi[2] * xi[2];
+  }
+}
+
+// Packed lower-triangular index of (r, c), r >= c.
+__host__ __device__ constexpr int tri(int r, int c) { return r * (r + 1) / 2 + c; }
+
+// In-place Cholesky of the packed symmetric matrix A (m x m).  Returns the
+// ratio min(L_jj^2) / max(L_jj^2) (0 if a pivot is not positive).
+template <int MU>
+__device__ __forceinline__ double cholesky(double* A) {
+  double pmin = 1e300, pmax = 0.0;
+#pragma unroll
+  for (int j = 0; j < MU; ++j) {
+    double s = A[tri(j, j)];
+#pragma unroll
+    for (int k = 0; k < j; ++k) s -= A[tri(j, k)] * A[tri(j, k)];
+    if (!(s > 0.0)) return 0.0;
+    pmin = fmin(pmin, s);
+    pmax = fmax(pmax, s);
+    double l = sqrt(s);
+    A[tri(j, j)] = l;
+    double il = 1.0 / l;
+#pragma unroll
+    for (int r = j + 1; r < MU; ++r) {
+      double t = A[tri(r, j)];
+#pragma unroll
+      for (int k = 0; k < j; ++k) t -= A[tri(r, k)] * A[tri(j, k)];
+      A[tri(r, j)] = t * il;
+    }
+  }
+  return pmin / pmax;
+}
+
+// Solves (L L^T) y = e_col for the Cholesky factor L (packed).
+template <int MU>
+__device__ __forceinline__ void chol_unit_solve(const double* L, int col, double* y) {
+#pragma unroll
+  for (int r = 0; r < MU; ++r) {
+    double t = (r == col) ? 1.0 : 0.0;
+#pragma unroll
+    for (int k = 0; k < r; ++k) t -= L[tri(r, k)] * y[k];
+    y[r] = t / L[tri(r, r)];
+  }
+#pragma unroll
+  for (int r = MU - 1; r >= 0; --r) {
+    double t = y[r];
+#pragma unroll
+    for (int k = r + 1; k < MU; ++k) t -= L[tri(k, r)] * y[k];
+    y[r] = t / L[tri(r, r)];
+  }
+}
+
+struct GridDesc {
+  int32_t n[3];
+  double h[3];
+  int64_t G;
+};
+
+// ---- cell list ------------------------------------------------------------
+template <int D>
+__device__ __forceinline__ int64_t cell_of(const double* __restrict__ xyz, int64_t M, int64_t n,
+                                           const GridDesc& g) {
+  int64_t c = 0, stride = 1;
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    double t = floor(xyz[a * M + n] / g.h[a]);
+    int64_t ci = (int64_t)fmin(fmax(t, 0.0), (double)(g.n[a] - 1));
+    c += ci * stride;
+    stride *= g.n[a];
+  }
+  return c;
+}
+
+template <int D>
+__global__ void __launch_bounds__(256) k_cell_count(const double* __restrict__ xyz, int64_t M,
+                                                    GridDesc g, int32_t* __restrict__ count) {
+  int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (n >= M) return;
+  atomicAdd(&count[cell_of<D>(xyz, M, n, g)], 1);
+}
+
+template <int D>
+__global__ void __launch_bounds__(256) k_cell_fill(const double* __restrict__ xyz, int64_t M,
+                                                   GridDesc g, const int32_t* __restrict__ start,
+                                                   int32_t* __restrict__ cursor,
+                                                   int32_t* __restrict__ sorted) {
+  int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (n >= M) return;
+  int64_t c = cell_of<D>(xyz, M, n, g);
+  int slot = atomicAdd(&cursor[c], 1);
+  sorted[start[c] + slot] = (int32_t)n;
+}
+
+// Exclusive scan of int32 counts (n elements) into out (n+1 elements), in
+// three launches: block sums, a one-block scan of the sums, block rescans.
+constexpr int SCAN_B = 1024;
+
+__global__ void __launch_bounds__(SCAN_B) k_scan_blocksum(const int32_t* __restrict__ in,
+                                                          int64_t n, int64_t* __restrict__ bsum) {
+  __shared__ int64_t red[SCAN_B];
+  int64_t i = (int64_t)blockIdx.x * SCAN_B + threadIdx.x;
+  red[threadIdx.x] = i < n ? in[i] : 0;
+  __syncthreads();
+  for (int w = SCAN_B / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) bsum[blockIdx.x] = red[0];
+}
+
+__global__ void __launch_bounds__(SCAN_B) k_scan_sums(int64_t* __restrict__ bsum, int64_t nb) {
+  __shared__ int64_t buf[SCAN_B];
+  int64_t carry = 0;
+  for (int64_t base = 0; base < nb; base += SCAN_B) {
+    int64_t i = base + threadIdx.x;
+    int64_t v = i < nb ? bsum[i] : 0;
+    buf[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = 1; off < SCAN_B; off <<= 1) {
+      int64_t t = (int)threadIdx.x >= off ? buf[threadIdx.x - off] : 0;
+      __syncthreads();
+      buf[threadIdx.x] += t;
+      __syncthreads();
+    }
+    if (i < nb) bsum[i] = carry + buf[threadIdx.x] - v;  // exclusive
+    int64_t tot = buf[SCAN_B - 1];
+    __syncthreads();
+    carry += tot;
+  }
+}
+
+__global__ void __launch_bounds__(SCAN_B) k_scan_apply(const int32_t* __restrict__ in, int64_t n,
+                                                       const int64_t* __restrict__ boff,
+                                                       int32_t* __restrict__ out) {
+  __shared__ int64_t buf[SCAN_B];
+  int64_t i = (int64_t)blockIdx.x * SCAN_B + threadIdx.x;
+  int64_t v = i < n ? in[i] : 0;
+  buf[threadIdx.x] = v;
+  __syncthreads();
+  for (int off = 1; off < SCAN_B; off <<= 1) {
+    int64_t t = (int)threadIdx.x >= off ? buf[threadIdx.x - off] : 0;
+    __syncthreads();
+    buf[threadIdx.x] += t;
+    __syncthreads();
+  }
+  int64_t incl = boff[blockIdx.x] + buf[threadIdx.x];
+  if (i < n) out[i] = (int32_t)(incl - v);
+  if (i == n - 1) out[n] = (int32_t)incl;
+}
+
+// ---- grid-target stencils ---------------------------------------------------
+struct GridStencilArgs {
+  const double* xyz;
+  int64_t M;
+  GridDesc g;
+  const int32_t* start;   // [G+1]
+  const int32_t* sorted;  // [M]
+  int k;
+  double eps, hsup;       // hsup = support * delta
+  int32_t* gidx;          // [k][G]
+  double* gcoef;          // [d][k][G]
+  float* gcoef32;
+  int32_t* bad;           // singular flag
+};
+
+template <int D>
+__global__ void __launch_bounds__(64) k_grid_stencils(GridStencilArgs A) {
+  constexpr int MU = D == 2 ? 6 : 10;
+  const int64_t p = (int64_t)blockIdx.x * 64 + threadIdx.x;
+  if (p >= A.g.G) return;
+  const int k = A.k;
+  int ci[3] = {0, 0, 0};
+  {
+    int64_t r = p;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      ci[a] = (int)(r % A.g.n[a]);
+      r /= A.g.n[a];
+    }
+  }
+  double xt[3];
+#pragma unroll
+  for (int a = 0; a < D; ++a) xt[a] = ((double)ci[a] + 0.5) * A.g.h[a];
+  double hmin = A.g.h[0];
+#pragma unroll
+  for (int a = 1; a < D; ++a) hmin = fmin(hmin, A.g.h[a]);
+
+  // kept list in descending key order: L[0] is the worst kept
+  double ld[KMAX];
+  int li[KMAX];
+#pragma unroll
+  for (int j = 0; j < KMAX; ++j) {
+    ld[j] = INFINITY;
+    li[j] = 0x7fffffff;
+  }
+  int found = 0;
+  int nmax = A.g.n[0];
+#pragma unroll
+  for (int a = 1; a < D; ++a) nmax = max(nmax, (int)A.g.n[a]);
+  for (int R = 0; R <= nmax; ++R) {
+    // cells at Chebyshev distance exactly R from the target's cell
+    int lo[3], hi[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      lo[a] = a < D ? ci[a] - R : 0;
+      hi[a] = a < D ? ci[a] + R : 0;
+    }
+    for (int cz = lo[2]; cz <= hi[2]; ++cz) {
+      if (D == 3 && (cz < 0 || cz >= A.g.n[2])) continue;
+      for (int cy = lo[1]; cy <= hi[1]; ++cy) {
+        if (cy < 0 || cy >= A.g.n[1]) continue;
+        bool yz_edge = (cy == lo[1] || cy == hi[1]) || (D == 3 && (cz == lo[2] || cz == hi[2]));
+        int step = (yz_edge || R == 0) ? 1 : 2 * R;
+        for (int cx = lo[0]; cx <= hi[0]; cx += step) {
+          if (cx < 0 || cx >= A.g.n[0]) continue;
+          int64_t c = cx + (int64_t)A.g.n[0] * (cy + (int64_t)A.g.n[1] * cz);
+          int s0 = A.start[c], s1 = A.start[c + 1];
+          for (int s = s0; s < s1; ++s) {
+            int nid = A.sorted[s];
+            double dx = A.xyz[nid] - xt[0];
+            double dy = A.xyz[A.M + nid] - xt[1];
+            double d2 = D == 2 ? sq_sum2(dx, dy) : sq_sum3(dx, dy, A.xyz[2 * A.M + nid] - xt[2]);
+            ++found;
+            if (key_lt(d2, nid, ld[0], li[0])) {
+              ld[0] = d2;
+              li[0] = nid;
+#pragma unroll
+              for (int j = 0; j + 1 < KMAX; ++j) {
+                if (j + 1 < k && key_lt(ld[j], li[j], ld[j + 1], li[j + 1])) {
+                  double td = ld[j];
+                  ld[j] = ld[j + 1];
+                  ld[j + 1] = td;
+                  int ti = li[j];
+                  li[j] = li[j + 1];
+                  li[j + 1] = ti;
+                }
+              }
+            }
+          }
+        }
+      }
+    }
+    // every unscanned node lies at least (R + 1/2) hmin away
+    double bound = (R + 0.5) * hmin;
+    if (found >= k && ld[0] < bound * bound * (1.0 - 1e-12)) break;
+  }
+  if (found < k) {
+    atomicOr(A.bad, 2);
+    return;
+  }
+  // ---- WLS (Eqs. 13-17) ----
+  const double rk = sqrt(ld[0]);
+  const double ht = fmax(A.hsup, rk);
+  const double iht = 1.0 / ht;
+  double Cm[MU * (MU + 1) / 2];
+#pragma unroll
+  for (int j = 0; j < MU * (MU + 1) / 2; ++j) Cm[j] = 0.0;
+#pragma unroll
+  for (int j = 0; j < KMAX; ++j) {
+    if (j < k) {
+      int nid = li[j];
+      double xi[3];
+#pragma unroll
+      for (int a = 0; a < D; ++a) xi[a] = (A.xyz[a * A.M + nid] - xt[a]) / ht;
+      double w = exp((-A.eps * ld[j]) / (ht * ht));
+      double q[MU];
+      basis<D>(xi, q);
+#pragma unroll
+      for (int r = 0; r < MU; ++r) {
+        double wq = w * q[r];
+#pragma unroll
+        for (int c = 0; c <= r; ++c) Cm[tri(r, c)] += wq * q[c];
+      }
+    }
+  }
+  double ratio = cholesky<MU>(Cm);
+  if (!(ratio >= SINGULAR_RATIO)) {
+    atomicOr(A.bad, 1);
+    return;
+  }
+  double y[D][MU];
+#pragma unroll
+  for (int a = 0; a < D; ++a) chol_unit_solve<MU>(Cm, 1 + a, y[a]);
+  const int64_t G = A.g.G;
+#pragma unroll
+  for (int j = 0; j < KMAX; ++j) {
+    if (j < k) {
+      int pos = k - 1 - j;  // ascending key order
+      int nid = li[j];
+      double xi[3];
+#pragma unroll
+      for (int a = 0; a < D; ++a) xi[a] = (A.xyz[a * A.M + nid] - xt[a]) / ht;
+      double w = exp((-A.eps * ld[j]) / (ht * ht));
+      double q[MU];
+      basis<D>(xi, q);
+      A.gidx[(int64_t)pos * G + p] = nid;
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        double t = 0.0;
+#pragma unroll
+        for (int r = 0; r < MU; ++r) t += y[a][r] * q[r];
+        double cval = w * t * iht;
+        A.gcoef[((int64_t)a * k + pos) * G + p] = cval;
+        if (A.gcoef32) A.gcoef32[((int64_t)a * k + pos) * G + p] = (float)cval;
+      }
+    }
+  }
+}
+
+// ---- node-target stencils ------------------------------------------------------
+struct NodeStencilArgs {
+  const double* xyz;
+  int64_t M;
+  GridDesc g;
+  int m, bn, k;
+  double eps, hsup;
+  int32_t* nbase;   // [M]
+  double* ncoef;    // [d][bn][M]
+  float* ncoef32;
+  int32_t* bad;
+};
+
+template <int D>
+__global__ void __launch_bounds__(64) k_node_stencils(NodeStencilArgs A) {
+  constexpr int MU = D == 2 ? 6 : 10;
+  const int64_t n = (int64_t)blockIdx.x * 64 + threadIdx.x;
+  if (n >= A.M) return;
+  const int m = A.m, bn = A.bn, k = A.k;
+  double x[3];
+  int base[3] = {0, 0, 0};
+  int64_t flat0 = 0, stride = 1;
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    x[a] = A.xyz[a * A.M + n];
+    double lo = floor(x[a] / A.g.h[a] - (0.5 * m - 0.5));
+    lo = fmin(fmax(lo, 0.0), (double)(A.g.n[a] - m));
+    base[a] = (int)lo;
+    flat0 += (int64_t)base[a] * stride;
+    stride *= A.g.n[a];
+  }
+  // squared distances of the block points
+  double d2[BNMAX];
+  int64_t fl[BNMAX];
+#pragma unroll
+  for (int o = 0; o < BNMAX; ++o) {
+    d2[o] = INFINITY;
+    fl[o] = 0;
+    if (o < bn) {
+      int oc[3] = {o % m, (o / m) % m, o / (m * m)};
+      double dd[3];
+      int64_t f = 0, st = 1;
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        int cc = base[a] + oc[a];
+        dd[a] = ((double)cc + 0.5) * A.g.h[a] - x[a];
+        f += (int64_t)cc * st;
+        st *= A.g.n[a];
+      }
+      d2[o] = D == 2 ? sq_sum2(dd[0], dd[1]) : sq_sum3(dd[0], dd[1], dd[2]);
+      fl[o] = f;
+    }
+  }
+  // selection: the k smallest (d^2, flat index) keys of the block
+  bool sel[BNMAX];
+  double rk2 = 0.0;
+#pragma unroll
+  for (int o = 0; o < BNMAX; ++o) {
+    sel[o] = false;
+    if (o < bn) {
+      int rank = 0;
+      if (k < bn) {
+#pragma unroll
+        for (int q = 0; q < BNMAX; ++q)
+          if (q < bn && key_lt(d2[q], (int)fl[q], d2[o], (int)fl[o])) ++rank;
+      }
+      sel[o] = rank < k;
+      if (sel[o]) rk2 = fmax(rk2, d2[o]);
+    }
+  }
+  const double ht = fmax(A.hsup, sqrt(rk2));
+  const double iht = 1.0 / ht;
+  double Cm[MU * (MU + 1) / 2];
+#pragma unroll
+  for (int j = 0; j < MU * (MU + 1) / 2; ++j) Cm[j] = 0.0;
+#pragma unroll
+  for (int o = 0; o < BNMAX; ++o) {
+    if (o < bn && sel[o]) {
+      int oc[3] = {o % m, (o / m) % m, o / (m * m)};
+      double xi[3];
+#pragma unroll
+      for (int a = 0; a < D; ++a) xi[a] = ((((double)(base[a] + oc[a]) + 0.5) * A.g.h[a]) - x[a]) / ht;
+      double w = exp((-A.eps * d2[o]) / (ht * ht));
+      double q[MU];
+      basis<D>(xi, q);
+#pragma unroll
+      for (int r = 0; r < MU; ++r) {
+        double wq = w * q[r];
+#pragma unroll
+        for (int c = 0; c <= r; ++c) Cm[tri(r, c)] += wq * q[c];
+      }
+    }
+  }
+  double ratio = cholesky<MU>(Cm);
+  if (!(ratio >= SINGULAR_RATIO)) {
+    atomicOr(A.bad, 1);
+    return;
+  }
+  double y[D][MU];
+#pragma unroll
+  for (int a = 0; a < D; ++a) chol_unit_solve<MU>(Cm, 1 + a, y[a]);
+  A.nbase[n] = (int32_t)flat0;
+  const int64_t M = A.M;
+#pragma unroll
+  for (int o = 0; o < BNMAX; ++o) {
+    if (o < bn) {
+      double cv[3] = {0.0, 0.0, 0.0};
+      if (sel[o]) {
+        int oc[3] = {o % m, (o / m) % m, o / (m * m)};
+        double xi[3];
+#pragma unroll
+        for (int a = 0; a < D; ++a)
+          xi[a] = ((((double)(base[a] + oc[a]) + 0.5) * A.g.h[a]) - x[a]) / ht;
+        double w = exp((-A.eps * d2[o]) / (ht * ht));
+        double q[MU];
+        basis<D>(xi, q);
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+          double t = 0.0;
+#pragma unroll
+          for (int r = 0; r < MU; ++r) t += y[a][r] * q[r];
+          cv[a] = w * t * iht;
+        }
+      }
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        A.ncoef[((int64_t)a * bn + o) * M + n] = cv[a];
+        if (A.ncoef32) A.ncoef32[((int64_t)a * bn + o) * M + n] = (float)cv[a];
+      }
+    }
+  }
+}
+
+// ---- IB lists ------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_near_flags(const int32_t* __restrict__ gidx, int64_t G,
+                                                    int k, const uint8_t* __restrict__ kind,
+                                                    uint8_t* __restrict__ flag) {
+  int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (p >= G) return;
+  int cnt = 0;
+  for (int i = 0; i < k; ++i) cnt += kind[gidx[(int64_t)i * G + p]] != PC_KIND_F;
+  flag[p] = (uint8_t)(cnt > 255 ? 255 : cnt);
+}
+
+__global__ void __launch_bounds__(256) k_slot_map(const int32_t* __restrict__ ib, int64_t nib,
+                                                  int32_t* __restrict__ slot) {
+  int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (s < nib) slot[ib[s]] = (int32_t)s;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_near_fill(const int32_t* __restrict__ near, int64_t nnear,
+                                                   const int32_t* __restrict__ nptr,
+                                                   const int32_t* __restrict__ gidx,
+                                                   const T* __restrict__ gcoef, int64_t G, int k,
+                                                   int d, const int32_t* __restrict__ slot,
+                                                   int64_t nent, int32_t* __restrict__ nslot,
+                                                   T* __restrict__ ncoefib) {
+  int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (q >= nnear) return;
+  int64_t p = near[q];
+  int e = nptr[q];
+  for (int i = 0; i < k; ++i) {
+    int nid = gidx[(int64_t)i * G + p];
+    int s = slot[nid];
+    if (s >= 0) {
+      nslot[e] = s;
+      for (int a = 0; a < d; ++a) ncoefib[(int64_t)a * nent + e] = gcoef[((int64_t)a * k + i) * G + p];
+      ++e;
+    }
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_ib_gather(const int32_t* __restrict__ ib, int64_t nib,
+                                                   const int32_t* __restrict__ nbase,
+                                                   const T* __restrict__ ncoef, int64_t M,
+                                                   int rows, int32_t* __restrict__ ibbase,
+                                                   T* __restrict__ ibcoef) {
+  int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (s >= nib) return;
+  int64_t nid = ib[s];
+  if (ibbase) ibbase[s] = nbase[nid];
+  for (int r = 0; r < rows; ++r) ibcoef[(int64_t)r * nib + s] = ncoef[(int64_t)r * M + nid];
+}
+
+int scan_exclusive(const int32_t* in, int64_t n, int32_t* out, hipStream_t s) {
+  int64_t nb = (n + SCAN_B - 1) / SCAN_B;
+  int64_t* bsum = nullptr;
+  PC_TRY(dev_alloc((void**)&bsum, (size_t)nb * sizeof(int64_t), "scan sums"));
+  hipLaunchKernelGGL(k_scan_blocksum, dim3((unsigned)nb), dim3(SCAN_B), 0, s, in, n, bsum);
+  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(SCAN_B), 0, s, bsum, nb);
+  hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(SCAN_B), 0, s, in, n, bsum, out);
+  hipError_t e = hipStreamSynchronize(s);
+  dev_free(bsum);
+  if (e != hipSuccess) return fail(PC_ERR_HIP, std::string("scan: ") + hipGetErrorString(e));
+  return PC_OK;
+}
+
+unsigned nblocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+void geom_free(pc_geom* g) {
+  if (!g) return;
+  void* ptrs[] = {g->gidx, g->gcoef, g->gcoef32, g->nbase, g->ncoef, g->ncoef32, g->ib,
+                  g->near, g->nptr, g->nslot, g->ncoefib, g->ncoefib32, g->ibbase, g->ibcoef,
+                  g->ibcoef32};
+  for (void* p : ptrs) dev_free(p);
+}
+
+struct Scratch {
+  std::vector<void*> ptrs;
+  ~Scratch() {
+    for (void* p : ptrs) dev_free(p);
+  }
+  int alloc(void** p, size_t bytes, const char* what) {
+    int rc = dev_alloc(p, bytes, what);
+    if (rc == PC_OK) ptrs.push_back(*p);
+    return rc;
+  }
+};
+
+int build(const pc_plan* P, const double* xyz, const uint8_t* kind, int64_t M,
+          const pc_wls_opts* o, hipStream_t s, pc_geom* g) {
+  const int d = P->d;
+  const int MU = d == 2 ? 6 : 10;
+  int k_grid = o && o->k_grid ? o->k_grid : 16;
+  int k_node = o && o->k_node ? o->k_node : (d == 2 ? 16 : 27);
+  double eps = o && o->eps != 0.0 ? o->eps : 6.3;
+  double support = o && o->support != 0.0 ? o->support : 3.0;
+  double delta = o ? o->delta : 0.0;
+  bool want32 = o && (o->dtype_mask & 1);
+  if (k_grid < MU || k_node < MU)
+    return fail(PC_ERR_INVALID_ARG, "k_grid and k_node must be at least the number of unknowns");
+  if (k_grid > KMAX) return fail(PC_ERR_UNSUPPORTED_SIZE, "k_grid above PC_MAX_K_GRID");
+  if (M < k_grid) return fail(PC_ERR_INVALID_ARG, "fewer nodes than k_grid");
+  if (M > INT32_MAX - 1) return fail(PC_ERR_UNSUPPORTED_SIZE, "more than 2^31-2 nodes");
+  int m = 1;
+  while ((int)std::pow(m, d) < k_node) ++m;
+  if (m < 3) m = 3;  // a quadratic fit needs three lines per axis
+  int bn = 1;
+  for (int a = 0; a < d; ++a) bn *= m;
+  if (bn > BNMAX) return fail(PC_ERR_UNSUPPORTED_SIZE, "k_node block above PC_MAX_K_NODE");
+  for (int a = 0; a < d; ++a)
+    if (P->n[a] < m) return fail(PC_ERR_UNSUPPORTED_SIZE, "grid smaller than the node block");
+  if (!(eps > 0.0) || !(support > 0.0) || delta < 0.0)
+    return fail(PC_ERR_INVALID_ARG, "eps and support must be positive, delta non-negative");
+  if (delta == 0.0) {
+    bool iso = true;
+    for (int a = 1; a < d; ++a) iso = iso && P->h[a] == P->h[0];
+    if (iso) {
+      delta = P->h[0];
+    } else {
+      double prod = 1.0;
+      for (int a = 0; a < d; ++a) prod *= P->h[a];
+      delta = std::pow(prod, 1.0 / d);
+    }
+  }
+  const int64_t G = P->G;
+  g->d = d;
+  g->M = M;
+  g->G = G;
+  for (int a = 0; a < 3; ++a) {
+    g->n[a] = P->n[a];
+    g->h[a] = P->h[a];
+  }
+  g->k_grid = k_grid;
+  g->k_node = k_node;
+  g->m_node = m;
+  g->bn = bn;
+  g->has32 = want32;
+  GridDesc gd;
+  for (int a = 0; a < 3; ++a) {
+    gd.n[a] = P->n[a];
+    gd.h[a] = P->h[a];
+  }
+  gd.G = G;
+
+  Scratch tmp;
+  int32_t *count, *start, *cursor, *sorted, *bad;
+  PC_TRY(tmp.alloc((void**)&count, (size_t)G * 4, "cell counts"));
+  PC_TRY(tmp.alloc((void**)&start, (size_t)(G + 1) * 4, "cell starts"));
+  PC_TRY(tmp.alloc((void**)&cursor, (size_t)G * 4, "cell cursors"));
+  PC_TRY(tmp.alloc((void**)&sorted, (size_t)M * 4, "sorted nodes"));
+  PC_TRY(tmp.alloc((void**)&bad, 256, "flags"));
+  PC_TRY(fill_zero(count, (size_t)G * 4, s));
+  PC_TRY(fill_zero(cursor, (size_t)G * 4, s));
+  PC_TRY(fill_zero(bad, 256, s));
+  if (d == 2)
+    hipLaunchKernelGGL(k_cell_count<2>, dim3(nblocks(M, 256)), dim3(256), 0, s, xyz, M, gd, count);
+  else
+    hipLaunchKernelGGL(k_cell_count<3>, dim3(nblocks(M, 256)), dim3(256), 0, s, xyz, M, gd, count);
+  PC_HIP_CHECK(hipGetLastError());
+  PC_TRY(scan_exclusive(count, G, start, s));
+  if (d == 2)
+    hipLaunchKernelGGL(k_cell_fill<2>, dim3(nblocks(M, 256)), dim3(256), 0, s, xyz, M, gd, start,
+                       cursor, sorted);
+  else
+    hipLaunchKernelGGL(k_cell_fill<3>, dim3(nblocks(M, 256)), dim3(256), 0, s, xyz, M, gd, start,
+                       cursor, sorted);
+  PC_HIP_CHECK(hipGetLastError());
+
+  // grid-target stencils
+  PC_TRY(dev_alloc((void**)&g->gidx, (size_t)k_grid * G * 4, "grid stencil indices"));
+  PC_TRY(dev_alloc((void**)&g->gcoef, (size_t)d * k_grid * G * 8, "grid stencil coefficients"));
+  if (want32)
+    PC_TRY(dev_alloc((void**)&g->gcoef32, (size_t)d * k_grid * G * 4, "grid stencil f32"));
+  GridStencilArgs ga{xyz, M, gd, start, sorted, k_grid, eps, support * delta, g->gidx, g->gcoef,
+                     g->gcoef32, bad};
+  if (d == 2)
+    hipLaunchKernelGGL(k_grid_stencils<2>, dim3(nblocks(G, 64)), dim3(64), 0, s, ga);
+  else
+    hipLaunchKernelGGL(k_grid_stencils<3>, dim3(nblocks(G, 64)), dim3(64), 0, s, ga);
+  PC_HIP_CHECK(hipGetLastError());
+
+  // node-target stencils
+  PC_TRY(dev_alloc((void**)&g->nbase, (size_t)M * 4, "node stencil bases"));
+  PC_TRY(dev_alloc((void**)&g->ncoef, (size_t)d * bn * M * 8, "node stencil coefficients"));
+  if (want32) PC_TRY(dev_alloc((void**)&g->ncoef32, (size_t)d * bn * M * 4, "node stencil f32"));
+  NodeStencilArgs na{xyz, M, gd, m, bn, k_node, eps, support * delta, g->nbase, g->ncoef,
+                     g->ncoef32, bad};
+  if (d == 2)
+    hipLaunchKernelGGL(k_node_stencils<2>, dim3(nblocks(M, 64)), dim3(64), 0, s, na);
+  else
+    hipLaunchKernelGGL(k_node_stencils<3>, dim3(nblocks(M, 64)), dim3(64), 0, s, na);
+  PC_HIP_CHECK(hipGetLastError());
+
+  int32_t hbad = 0;
+  PC_HIP_CHECK(hipMemcpyAsync(&hbad, bad, 4, hipMemcpyDeviceToHost, s));
+  PC_HIP_CHECK(hipStreamSynchronize(s));
+  if (hbad & 2) return fail(PC_ERR_INVALID_ARG, "a grid point found fewer than k_grid nodes");
+  if (hbad & 1)
+    return fail(PC_ERR_SINGULAR_STENCIL, "a WLS normal matrix is singular (squared pivot ratio "
+                                         "below 1e-12)");
+
+  // boundary + virtual node list (ascending)
+  std::vector<uint8_t> hkind((size_t)M);
+  PC_HIP_CHECK(hipMemcpy(hkind.data(), kind, (size_t)M, hipMemcpyDeviceToHost));
+  std::vector<int32_t> hib;
+  for (int64_t n = 0; n < M; ++n) {
+    if (hkind[n] > PC_KIND_V) return fail(PC_ERR_INVALID_ARG, "node kind must be 0, 1 or 2");
+    if (hkind[n] != PC_KIND_F) hib.push_back((int32_t)n);
+  }
+  g->n_ib = (int64_t)hib.size();
+  // near-IB grid points and their compact stencils
+  uint8_t* nflag;
+  PC_TRY(tmp.alloc((void**)&nflag, (size_t)G, "near flags"));
+  hipLaunchKernelGGL(k_near_flags, dim3(nblocks(G, 256)), dim3(256), 0, s, g->gidx, G, k_grid,
+                     kind, nflag);
+  PC_HIP_CHECK(hipGetLastError());
+  std::vector<uint8_t> hflag((size_t)G);
+  PC_HIP_CHECK(hipMemcpyAsync(hflag.data(), nflag, (size_t)G, hipMemcpyDeviceToHost, s));
+  PC_HIP_CHECK(hipStreamSynchronize(s));
+  std::vector<int32_t> hnear, hptr(1, 0);
+  for (int64_t p = 0; p < G; ++p) {
+    if (hflag[p]) {
+      hnear.push_back((int32_t)p);
+      hptr.push_back(hptr.back() + hflag[p]);
+    }
+  }
+  g->n_near = (int64_t)hnear.size();
+  g->n_near_entries = hptr.back();
+  if (g->n_ib) {
+    PC_TRY(dev_alloc((void**)&g->ib, (size_t)g->n_ib * 4, "IB list"));
+    PC_HIP_CHECK(hipMemcpy(g->ib, hib.data(), (size_t)g->n_ib * 4, hipMemcpyHostToDevice));
+  }
+  if (g->n_near) {
+    PC_TRY(dev_alloc((void**)&g->near, (size_t)g->n_near * 4, "near list"));
+    PC_TRY(dev_alloc((void**)&g->nptr, (size_t)(g->n_near + 1) * 4, "near offsets"));
+    PC_TRY(dev_alloc((void**)&g->nslot, (size_t)g->n_near_entries * 4, "near slots"));
+    PC_TRY(dev_alloc((void**)&g->ncoefib, (size_t)d * g->n_near_entries * 8, "near coefs"));
+    if (want32)
+      PC_TRY(dev_alloc((void**)&g->ncoefib32, (size_t)d * g->n_near_entries * 4, "near coefs"));
+    PC_HIP_CHECK(hipMemcpy(g->near, hnear.data(), (size_t)g->n_near * 4, hipMemcpyHostToDevice));
+    PC_HIP_CHECK(hipMemcpy(g->nptr, hptr.data(), (size_t)(g->n_near + 1) * 4, hipMemcpyHostToDevice));
+    int32_t* slot;
+    PC_TRY(tmp.alloc((void**)&slot, (size_t)M * 4, "slot map"));
+    PC_HIP_CHECK(hipMemsetAsync(slot, 0xff, (size_t)M * 4, s));
+    hipLaunchKernelGGL(k_slot_map, dim3(nblocks(g->n_ib, 256)), dim3(256), 0, s, g->ib, g->n_ib,
+                       slot);
+    hipLaunchKernelGGL(k_near_fill<double>, dim3(nblocks(g->n_near, 256)), dim3(256), 0, s,
+                       g->near, g->n_near, g->nptr, g->gidx, g->gcoef, G, k_grid, d, slot,
+                       g->n_near_entries, g->nslot, g->ncoefib);
+    if (want32)
+      hipLaunchKernelGGL(k_near_fill<float>, dim3(nblocks(g->n_near, 256)), dim3(256), 0, s,
+                         g->near, g->n_near, g->nptr, g->gidx, g->gcoef32, G, k_grid, d, slot,
+                         g->n_near_entries, g->nslot, g->ncoefib32);
+    PC_HIP_CHECK(hipGetLastError());
+  }
+  if (g->n_ib) {
+    PC_TRY(dev_alloc((void**)&g->ibbase, (size_t)g->n_ib * 4, "IB bases"));
+    PC_TRY(dev_alloc((void**)&g->ibcoef, (size_t)d * bn * g->n_ib * 8, "IB coefs"));
+    hipLaunchKernelGGL(k_ib_gather<double>, dim3(nblocks(g->n_ib, 256)), dim3(256), 0, s, g->ib,
+                       g->n_ib, g->nbase, g->ncoef, M, d * bn, g->ibbase, g->ibcoef);
+    if (want32) {
+      PC_TRY(dev_alloc((void**)&g->ibcoef32, (size_t)d * bn * g->n_ib * 4, "IB coefs"));
+      hipLaunchKernelGGL(k_ib_gather<float>, dim3(nblocks(g->n_ib, 256)), dim3(256), 0, s, g->ib,
+                         g->n_ib, g->nbase, g->ncoef32, M, d * bn, (int32_t*)nullptr, g->ibcoef32);
+    }
+    PC_HIP_CHECK(hipGetLastError());
+  }
+  PC_HIP_CHECK(hipStreamSynchronize(s));
+  int64_t bytes = (int64_t)k_grid * G * 4 + (int64_t)d * k_grid * G * 8 + M * 4 +
+                  (int64_t)d * bn * M * 8 + g->n_ib * 4 + g->n_near * 8 + 4 +
+                  g->n_near_entries * (4 + 8 * d) + g->n_ib * (4 + 8 * (int64_t)d * bn);
+  if (want32)
+    bytes += (int64_t)d * k_grid * G * 4 + (int64_t)d * bn * M * 4 +
+             g->n_near_entries * 4 * d + g->n_ib * 4 * (int64_t)d * bn;
+  g->bytes = bytes;
+  return PC_OK;
+}
+
+}  // namespace
+}  // namespace pc
+
+using namespace pc;
+
+extern "C" {
+
+int pc_wls_build(const pc_plan* P, const double* xyz, const uint8_t* kind, int64_t M,
+                 const pc_wls_opts* opts, void* stream, pc_geom** out) {
+  if (!P || !xyz || !kind || !out) return fail(PC_ERR_INVALID_ARG, "pc_wls_build: null argument");
+  *out = nullptr;
+  if (M <= 0) return fail(PC_ERR_INVALID_ARG, "M must be positive");
+  if (!aligned16(xyz)) return fail(PC_ERR_ALIGN, "positions must be 16-byte aligned");
+  pc_geom* g = new pc_geom();
+  std::memset(g, 0, sizeof(*g));
+  (void)hipGetDevice(&g->device);
+  int rc = build(P, xyz, kind, M, opts, as_stream(stream), g);
+  if (rc != PC_OK) {
+    std::string keep;
+    {
+      char buf[1024];
+      pc_last_error(buf, sizeof(buf));
+      keep = buf;
+    }
+    (void)hipStreamSynchronize(as_stream(stream));
+    geom_free(g);
+    delete g;
+    set_error(keep);
+    return rc;
+  }
+  *out = g;
+  return PC_OK;
+}
+
+int pc_geom_destroy(pc_geom* g) {
+  if (!g) return PC_OK;
+  if (g->own_ws) pc_workspace_destroy(g->own_ws);
+  geom_free(g);
+  delete g;
+  return PC_OK;
+}
+
+int pc_geom_info(const pc_geom* g, int64_t* c) {
+  if (!g || !c) return fail(PC_ERR_INVALID_ARG, "pc_geom_info: null argument");
+  c[0] = g->M;
+  c[1] = g->n_ib;
+  c[2] = g->n_near;
+  c[3] = g->k_grid;
+  c[4] = g->bn;
+  c[5] = g->bytes;
+  return PC_OK;
+}
+
+int pc_geom_export(const pc_geom* g, int32_t* gidx, double* gcoef, int32_t* nbase,
+                   double* ncoef, int32_t* ib, int32_t* near, void* stream) {
+  if (!g) return fail(PC_ERR_INVALID_ARG, "pc_geom_export: null geometry");
+  hipStream_t s = as_stream(stream);
+  auto cp = [&](void* dst, const void* src, size_t bytes) -> int {
+    if (dst && src && bytes)
+      PC_HIP_CHECK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, s));
+    return PC_OK;
+  };
+  PC_TRY(cp(gidx, g->gidx, (size_t)g->k_grid * g->G * 4));
+  PC_TRY(cp(gcoef, g->gcoef, (size_t)g->d * g->k_grid * g->G * 8));
+  PC_TRY(cp(nbase, g->nbase, (size_t)g->M * 4));
+  PC_TRY(cp(ncoef, g->ncoef, (size_t)g->d * g->bn * g->M * 8));
+  PC_TRY(cp(ib, g->ib, (size_t)g->n_ib * 4));
+  PC_TRY(cp(near, g->near, (size_t)g->n_near * 4));
+  return PC_OK;
+}
+
+}  // extern "C"

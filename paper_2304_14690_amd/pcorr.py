@@ -1,0 +1,285 @@
+"""Thin Python binding of libpcorr (include/pcorr.h).
+
+Argument marshalling only: every step of the pressure-correction path runs
+in the HIP kernels of libpcorr.so.  Tensors are torch CUDA tensors (device
+memory of the current HIP device); the HIP stream defaults to torch's current
+stream.  The functions keep the C names without the `pc_` prefix.  There is
+no CPU fallback: if the library is not built, importing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpcorr.so")
+
+PC_OK = 0
+PC_WARN_IB_NOT_CONVERGED = 1
+PC_ERR_INVALID_ARG = -1
+PC_ERR_UNSUPPORTED_SIZE = -2
+PC_ERR_ALIGN = -3
+PC_ERR_OOM = -4
+PC_ERR_SINGULAR_STENCIL = -5
+PC_ERR_HIP = -6
+PC_ERR_NO_DEVICE = -7
+
+PC_F64, PC_F32, PC_MIXED = 1, 2, 3
+PC_ALL, PC_NEAR_IB, PC_IB = 0, 1, 2
+PC_KIND_F, PC_KIND_B, PC_KIND_V = 0, 1, 2
+
+MODES = {"f64": PC_F64, "f32": PC_F32, "mixed": PC_MIXED}
+
+# every symbol include/pcorr.h declares
+EXPORTS = [
+    "pc_version", "pc_last_error", "pc_plan_create", "pc_plan_destroy",
+    "pc_poisson_fft_solve", "pc_wls_build", "pc_geom_destroy", "pc_geom_info",
+    "pc_geom_export", "pc_div_to_grid", "pc_grad_to_nodes", "pc_ib_update", "pc_project",
+    "pc_workspace_create", "pc_workspace_destroy", "pc_workspace_bytes",
+    "pc_pressure_correct",
+]
+
+
+class PcError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"libpcorr error {code}: {msg}")
+        self.code = code
+
+
+class WlsOpts(ctypes.Structure):
+    _fields_ = [("k_grid", ctypes.c_int32), ("k_node", ctypes.c_int32),
+                ("eps", ctypes.c_double), ("support", ctypes.c_double),
+                ("delta", ctypes.c_double), ("dtype_mask", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class IbOpts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("max_it", ctypes.c_int32),
+                ("fixed_it", ctypes.c_int32), ("sweeps", ctypes.c_int32),
+                ("gauge", ctypes.c_int32)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("n_it", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("bmean", ctypes.c_double), ("ib_num", ctypes.c_double),
+                ("ib_den", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2304_14690_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    sig = {
+        "pc_version": ([], ctypes.c_int),
+        "pc_last_error": ([ctypes.c_char_p, ctypes.c_size_t], ctypes.c_int),
+        "pc_plan_create": ([ctypes.c_int, vp, vp, vp, ctypes.POINTER(vp)], ctypes.c_int),
+        "pc_plan_destroy": ([vp], ctypes.c_int),
+        "pc_poisson_fft_solve": ([vp, ctypes.c_int, vp, vp, ctypes.c_int, vp, vp, vp],
+                                 ctypes.c_int),
+        "pc_wls_build": ([vp, vp, vp, i64, ctypes.POINTER(WlsOpts), vp, ctypes.POINTER(vp)],
+                         ctypes.c_int),
+        "pc_geom_destroy": ([vp], ctypes.c_int),
+        "pc_geom_info": ([vp, ctypes.POINTER(i64)], ctypes.c_int),
+        "pc_geom_export": ([vp, vp, vp, vp, vp, vp, vp, vp], ctypes.c_int),
+        "pc_div_to_grid": ([vp, ctypes.c_int, vp, vp, ctypes.c_int, vp], ctypes.c_int),
+        "pc_grad_to_nodes": ([vp, ctypes.c_int, vp, vp, ctypes.c_int, vp], ctypes.c_int),
+        "pc_ib_update": ([vp, ctypes.c_int, vp, vp, vp, dbl, vp, vp, vp], ctypes.c_int),
+        "pc_project": ([vp, ctypes.c_int, vp, vp, vp, vp], ctypes.c_int),
+        "pc_workspace_create": ([vp, vp, ctypes.c_int, ctypes.POINTER(vp)], ctypes.c_int),
+        "pc_workspace_destroy": ([vp], ctypes.c_int),
+        "pc_workspace_bytes": ([vp, vp, ctypes.c_int], i64),
+        "pc_pressure_correct": ([vp, vp, ctypes.c_int, vp, dbl, vp, vp, vp,
+                                 ctypes.POINTER(IbOpts), ctypes.POINTER(Stats), vp, vp],
+                                ctypes.c_int),
+    }
+    for name, (args, res) in sig.items():
+        if hasattr(lib, name):
+            f = getattr(lib, name)
+            f.argtypes = args
+            f.restype = res
+    return lib
+
+
+_lib = _load()
+
+
+def lib():
+    return _lib
+
+
+def last_error() -> str:
+    buf = ctypes.create_string_buffer(1024)
+    _lib.pc_last_error(buf, 1024)
+    return buf.value.decode(errors="replace")
+
+
+def _check(rc: int) -> int:
+    if rc < 0:
+        raise PcError(rc, last_error())
+    return rc
+
+
+def _stream(stream):
+    if stream is None:
+        if not torch.cuda.is_available():
+            return None  # the library then reports that no device is visible
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, torch.cuda.Stream):
+        return stream.cuda_stream
+    return int(stream)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return t.data_ptr()
+
+
+def _dtype_code(t: torch.Tensor) -> int:
+    if t.dtype == torch.float64:
+        return PC_F64
+    if t.dtype == torch.float32:
+        return PC_F32
+    raise ValueError(f"unsupported dtype {t.dtype}")
+
+
+class Plan:
+    """Grid and transform tables (pc_plan)."""
+
+    def __init__(self, d: int, n: Sequence[int], h: Sequence[float], stream=None):
+        nn = (ctypes.c_int32 * 3)(*(list(n) + [1] * (3 - len(n))))
+        hh = (ctypes.c_double * 3)(*(list(h) + [1.0] * (3 - len(h))))
+        out = ctypes.c_void_p()
+        _check(_lib.pc_plan_create(d, ctypes.addressof(nn), ctypes.addressof(hh),
+                                   _stream(stream), ctypes.byref(out)))
+        self.h_ = out
+        self.d, self.n, self.h = d, tuple(n), tuple(h)
+        self.G = 1
+        for v in n:
+            self.G *= v
+
+    def __del__(self):
+        if getattr(self, "h_", None) and _lib is not None:
+            _lib.pc_plan_destroy(self.h_)
+            self.h_ = None
+
+
+class Geometry:
+    """WLS stencils of one node cloud (pc_geom)."""
+
+    def __init__(self, handle, plan: Plan):
+        self.h_ = handle
+        self.plan = plan
+        info = (ctypes.c_int64 * 6)()
+        _check(_lib.pc_geom_info(self.h_, info))
+        self.M, self.n_ib, self.n_near, self.k_grid, self.bn, self.bytes = (int(v) for v in info)
+
+    def __del__(self):
+        if getattr(self, "h_", None) and _lib is not None:
+            _lib.pc_geom_destroy(self.h_)
+            self.h_ = None
+
+
+class Workspace:
+    def __init__(self, plan: Plan, geom: Optional[Geometry], mode: int):
+        out = ctypes.c_void_p()
+        _check(_lib.pc_workspace_create(plan.h_, geom.h_ if geom else None, mode,
+                                        ctypes.byref(out)))
+        self.h_ = out
+        self.plan, self.geom, self.mode = plan, geom, mode
+
+    def __del__(self):
+        if getattr(self, "h_", None) and _lib is not None:
+            _lib.pc_workspace_destroy(self.h_)
+            self.h_ = None
+
+
+def version() -> int:
+    return _lib.pc_version()
+
+
+def plan_create(d, n, h, stream=None) -> Plan:
+    return Plan(d, n, h, stream)
+
+
+def workspace_create(plan: Plan, geom: Optional[Geometry], mode: int) -> Workspace:
+    return Workspace(plan, geom, mode)
+
+
+def workspace_bytes(plan: Plan, geom: Optional[Geometry], mode: int) -> int:
+    return int(_lib.pc_workspace_bytes(plan.h_, geom.h_ if geom else None, mode))
+
+
+def poisson_fft_solve(plan: Plan, b: torch.Tensor, phi: torch.Tensor, mode: int = PC_F64,
+                      sweeps: int = 2, bmean: Optional[torch.Tensor] = None,
+                      ws: Optional[Workspace] = None, stream=None) -> int:
+    return _check(_lib.pc_poisson_fft_solve(plan.h_, mode, _ptr(b), _ptr(phi), sweeps,
+                                            _ptr(bmean), ws.h_ if ws else None,
+                                            _stream(stream)))
+
+
+def wls_build(plan: Plan, xyz: torch.Tensor, kind: torch.Tensor, k_grid: int = 0,
+              k_node: int = 0, eps: float = 0.0, support: float = 0.0, delta: float = 0.0,
+              want_f32: bool = False, stream=None) -> Geometry:
+    assert xyz.dtype == torch.float64 and kind.dtype == torch.uint8
+    opts = WlsOpts(k_grid, k_node, eps, support, delta, 1 if want_f32 else 0, 0)
+    out = ctypes.c_void_p()
+    _check(_lib.pc_wls_build(plan.h_, _ptr(xyz), _ptr(kind), kind.numel(), ctypes.byref(opts),
+                             _stream(stream), ctypes.byref(out)))
+    return Geometry(out, plan)
+
+
+def geom_export(geom: Geometry, grid_idx=None, grid_coef=None, node_base=None,
+                node_coef=None, ib=None, near=None, stream=None) -> int:
+    return _check(_lib.pc_geom_export(geom.h_, _ptr(grid_idx), _ptr(grid_coef),
+                                      _ptr(node_base), _ptr(node_coef), _ptr(ib), _ptr(near),
+                                      _stream(stream)))
+
+
+def div_to_grid(geom: Geometry, v: torch.Tensor, b: torch.Tensor, subset: int = PC_ALL,
+                stream=None) -> int:
+    return _check(_lib.pc_div_to_grid(geom.h_, _dtype_code(v), _ptr(v), _ptr(b), subset,
+                                      _stream(stream)))
+
+
+def grad_to_nodes(geom: Geometry, phi: torch.Tensor, grad: torch.Tensor, subset: int = PC_ALL,
+                  stream=None) -> int:
+    return _check(_lib.pc_grad_to_nodes(geom.h_, _dtype_code(phi), _ptr(phi), _ptr(grad),
+                                        subset, _stream(stream)))
+
+
+def ib_update(geom: Geometry, u: torch.Tensor, grad_ib: torch.Tensor, g: torch.Tensor,
+              tol: float, sums: torch.Tensor, conv: torch.Tensor, stream=None) -> int:
+    return _check(_lib.pc_ib_update(geom.h_, _dtype_code(u), _ptr(u), _ptr(grad_ib), _ptr(g),
+                                    tol, _ptr(sums), _ptr(conv), _stream(stream)))
+
+
+def project(geom: Geometry, u: torch.Tensor, grad: torch.Tensor, u_out: torch.Tensor,
+            stream=None) -> int:
+    return _check(_lib.pc_project(geom.h_, _dtype_code(u), _ptr(u), _ptr(grad), _ptr(u_out),
+                                  _stream(stream)))
+
+
+def pressure_correct(geom: Geometry, plan: Plan, mode: int, u: torch.Tensor, dt: float,
+                     u_out: torch.Tensor, p: torch.Tensor, g: Optional[torch.Tensor] = None,
+                     tol: float = 1e-3, max_it: int = 50, fixed_it: int = 0, sweeps: int = 2,
+                     gauge: int = 0, ws: Optional[Workspace] = None, stream=None,
+                     want_stats: bool = True):
+    opts = IbOpts(tol, max_it, fixed_it, sweeps, gauge)
+    st = Stats()
+    rc = _check(_lib.pc_pressure_correct(geom.h_, plan.h_, mode, _ptr(u), dt, _ptr(u_out),
+                                         _ptr(p), _ptr(g), ctypes.byref(opts),
+                                         ctypes.byref(st) if want_stats else None,
+                                         ws.h_ if ws else None, _stream(stream)))
+    return rc, st.as_dict()

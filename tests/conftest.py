@@ -17,3 +17,19 @@ def pytest_configure(config):
 def rng():
     import numpy as np
     return np.random.Generator(np.random.PCG64(12345))
+
+
+def pytest_collection_modifyitems(config, items):
+    """GPU tests need a visible HIP device; without one they are skipped
+    (the CPU suite selects -m "not gpu" anyway)."""
+    try:
+        import torch
+        have = torch.cuda.is_available()
+    except Exception:  # pragma: no cover
+        have = False
+    if have:
+        return
+    skip = pytest.mark.skip(reason="no GPU visible")
+    for it in items:
+        if "gpu" in it.keywords:
+            it.add_marker(skip)
