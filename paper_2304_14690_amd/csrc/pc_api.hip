@@ -1,6 +1,7 @@
 // C ABI entry points of libpcorr: errors, plans, workspaces and the Poisson
 // solve.  Geometry entry points live in pc_wls.hip, the transfers and the
 // whole sub-step in pc_step.hip.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 
@@ -80,6 +81,14 @@ void set_axis_ptrs(AxisTables<T>& A, T* base, int N) {
   A.tN = reinterpret_cast<const cplx<T>*>(base + 2 * (size_t)H);
   A.t4N = reinterpret_cast<const cplx<T>*>(base + 2 * (size_t)H + 2 * (size_t)(H + 1));
   A.lam = base + 2 * (size_t)H + 4 * (size_t)(H + 1);
+}
+
+// Reduction partials: 1024 blocks for grid means, two per 256-node block of
+// the IB update.
+int64_t partial_doubles(const pc_geom* g) {
+  int64_t n = 1024;
+  if (g) n = std::max<int64_t>(n, 2 * ((g->n_ib + 255) / 256));
+  return n;
 }
 
 int check_mode(int mode) {
@@ -199,7 +208,7 @@ int64_t pc_workspace_bytes(const pc_plan* P, const pc_geom* g, int mode) {
     add(3 * (int64_t)g->d * g->n_ib * (int64_t)s);  // uib, gib, gradib
   }
   if (mode == PC_MIXED) add(P->G * 4);   // w32
-  add(1024 * 8);                         // partials
+  add(8 * partial_doubles(g));           // partials
   add(16 * 8);                           // scalars
   add(16 * 4);                           // flags
   return bytes;
@@ -240,7 +249,7 @@ int pc_workspace_create(const pc_plan* P, const pc_geom* g, int mode, pc_workspa
     W->gradib = take((int64_t)g->d * g->n_ib * (int64_t)s);
   }
   if (mode == PC_MIXED) W->w32 = reinterpret_cast<float*>(take(P->G * 4));
-  W->partial = reinterpret_cast<double*>(take(1024 * 8));
+  W->partial = reinterpret_cast<double*>(take(8 * partial_doubles(g)));
   W->scal = reinterpret_cast<double*>(take(16 * 8));
   W->flag = reinterpret_cast<int32_t*>(take(16 * 4));
   if (hipHostMalloc((void**)&W->hscal, 16 * 8 + 16 * 4, hipHostMallocDefault) != hipSuccess) {
@@ -250,12 +259,21 @@ int pc_workspace_create(const pc_plan* P, const pc_geom* g, int mode, pc_workspa
     return fail(PC_ERR_OOM, "pinned host scalars");
   }
   W->hflag = reinterpret_cast<int32_t*>(W->hscal + 16);
+  for (int i = 0; i < 2; ++i) {
+    if (hipEventCreateWithFlags(&W->ev[i], hipEventDisableTiming) != hipSuccess) {
+      (void)hipGetLastError();
+      pc_workspace_destroy(W);
+      return fail(PC_ERR_HIP, "hipEventCreate failed");
+    }
+  }
   *out = W;
   return PC_OK;
 }
 
 int pc_workspace_destroy(pc_workspace* W) {
   if (!W) return PC_OK;
+  for (int i = 0; i < 2; ++i)
+    if (W->ev[i]) (void)hipEventDestroy(W->ev[i]);
   dev_free(W->block);
   if (W->hscal) (void)hipHostFree(W->hscal);
   delete W;

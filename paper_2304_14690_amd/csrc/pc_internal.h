@@ -97,10 +97,12 @@ struct pc_geom {
   // IB lists
   int32_t* ib;          // [n_ib] node index
   int32_t* near;        // [n_near] grid index
-  // compact near-IB stencils: for near point q, entries e in [nptr[q], nptr[q+1])
-  int32_t* nptr;        // [n_near+1]
-  int32_t* nslot;       // [n_near_entries] ib slot
-  double* ncoefib;      // [d][n_near_entries]
+  // near-IB stencils restricted to their B+V entries, ELL layout of width
+  // near_w: entry e of near point q at e*n_near + q (slot -1 / coefficient 0
+  // past the point's last entry)
+  int near_w;
+  int32_t* nslot;       // [near_w][n_near] ib slot
+  double* ncoefib;      // [d][near_w][n_near]
   float* ncoefib32;
   // compact node stencils of the B+V nodes
   int32_t* ibbase;      // [n_ib]
@@ -130,21 +132,27 @@ struct pc_workspace {
   int32_t* hflag;    // pinned host mirror of the flag
   double* hscal;     // pinned host mirror of scal
   int nblk;          // partial-sum blocks
+  hipEvent_t ev[2];  // convergence-flag copies of alternate iterations
 };
 
 namespace pc {
 // ---- solve (pc_solve.hip) ---------------------------------------------------
 // Solves sigma * lap_h x = b - mean(b), mean(x) = 0 (sigma = 1: phi;
 // sigma = 3 dt / 2: the pressure itself).
+// skip (nullable): device flag; every launch returns at once when it is set
+// (used to enqueue IB iterations ahead of the convergence test).
 int solve_f64(const pc_plan* P, const double* b, double* phi, double* bmean_dev,
-              pc_workspace* ws, hipStream_t s, double sigma = 1.0);
+              pc_workspace* ws, hipStream_t s, double sigma = 1.0,
+              const int32_t* skip = nullptr);
 int solve_f32(const pc_plan* P, const float* b, float* phi, double* bmean_dev,
-              pc_workspace* ws, hipStream_t s, double sigma = 1.0);
+              pc_workspace* ws, hipStream_t s, double sigma = 1.0,
+              const int32_t* skip = nullptr);
 int solve_mixed(const pc_plan* P, const double* b, double* phi, int sweeps, double* bmean_dev,
-                pc_workspace* ws, hipStream_t s, double sigma = 1.0);
+                pc_workspace* ws, hipStream_t s, double sigma = 1.0,
+                const int32_t* skip = nullptr);
 int ensure_plan_ws(const pc_plan* P, pc_workspace** ws);
 // deterministic mean of a float64 grid field into out_dev[0]
 int mean_f64(const double* x, int64_t n, double* partial, int nblk, double* out_dev,
-             hipStream_t s);
+             hipStream_t s, const int32_t* skip = nullptr);
 int fill_zero(void* p, size_t bytes, hipStream_t s);
 }  // namespace pc

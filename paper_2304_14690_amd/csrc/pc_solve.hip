@@ -22,6 +22,10 @@ namespace pc {
 namespace {
 
 constexpr int XCDS = 8;
+// Radix-16 transform tiles: threads per workgroup for contiguous rows, and
+// the thread cap for the strided (column/pencil) passes.
+constexpr int ROW_THREADS = 256;
+constexpr int COL_MAX_THREADS = 512;
 
 // Workgroup -> tile map that gives each XCD (own L2) a contiguous range of
 // tiles, so tiles that share cache lines meet in the same L2.
@@ -59,6 +63,8 @@ struct LineArgs {
   const double* rb;     // residual loader: b
   const double* rphi;   // residual loader / accumulating store: phi
   const double* sub;    // nullable: float64 scalar subtracted on load
+  const int32_t* skip;  // nullable: the launch does nothing when *skip != 0
+  const int32_t* tiles; // nullable: workgroup b transforms tile tiles[b]
   int N, logH;
   int pad;              // LDS line padding in reals (0 or 2)
   int C;                // lines per tile
@@ -73,6 +79,7 @@ struct LineArgs {
   const TC* lam1;       // FDI in 3D: eigenvalues of axis 1 (indexed by j)
   TC outscale;          // store scale
   TC lscale;            // FDI: eigenvalues are multiplied by this (sigma)
+  TC lamc;              // FDI: -4 / h^2 of this axis
   double rscale;        // residual: r = b - rscale * lap_h phi
   double* bmean;        // FDI: receives X(0)/prod(2N_a) from the zero line
   double meannorm;
@@ -254,6 +261,7 @@ __device__ __forceinline__ void pre_pair(TC xk, TC xnk, TC xhk, TC xhpk, int k, 
 template <typename TC, typename TI, typename TO, int OP, int LD, int ST, int B>
 __global__ void __launch_bounds__(1024) dct_lines(LineArgs<TC> A) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
+  if (A.skip && *A.skip) return;
   TC* s = reinterpret_cast<TC*>(smem_raw);
   const int N = A.N, H = N >> 1, C = A.C;
   const int ls = N + A.pad;  // line stride in LDS (reals)
@@ -405,10 +413,522 @@ __global__ void __launch_bounds__(1024) dct_lines(LineArgs<TC> A) {
   }
 }
 
+// ---- register-resident radix-16 line transform ------------------------------
+// For H = N/2 >= 16, every line is handled by T = H/16 threads; thread t holds
+// the 16 complex values a[q] = z[t + T q] of the half-length FFT input.  The
+// Stockham stages are radix 16 followed by one stage of radix 2^(log2 H mod
+// 4): every stage reads only the thread's own values, scatters its outputs
+// through LDS (the last stage is in place), so an FFT of 1024 points costs
+// two LDS exchanges.  The cosine-transform split needs Z[H-k] next to Z[k]
+// (one exchange); the fused forward/divide/inverse then recomputes the
+// partner's outputs instead of exchanging them again.
+
+template <typename TC, bool INV>
+__device__ __forceinline__ void dft4(cplx<TC>& a0, cplx<TC>& a1, cplx<TC>& a2, cplx<TC>& a3) {
+  cplx<TC> t0 = cadd(a0, a2), t1 = csub(a0, a2), t2 = cadd(a1, a3), t3 = csub(a1, a3);
+  cplx<TC> it3 = INV ? cplx<TC>{-t3.im, t3.re} : cplx<TC>{t3.im, -t3.re};
+  a0 = cadd(t0, t2);
+  a2 = csub(t0, t2);
+  a1 = cadd(t1, it3);
+  a3 = csub(t1, it3);
+}
+
+// multiply by exp(-+ 2 pi i m / 16) for the constant m (sign by INV)
+template <typename TC, bool INV, int m>
+__device__ __forceinline__ cplx<TC> w16(cplx<TC> a) {
+  constexpr double C1 = 0.92387953251128675613;  // cos(pi/8)
+  constexpr double S1 = 0.38268343236508977173;  // sin(pi/8)
+  constexpr double R2 = 0.70710678118654752440;  // sqrt(1/2)
+  double c, s;  // w = c - i s (forward)
+  if (m == 0) return a;
+  if (m == 1) { c = C1; s = S1; }
+  if (m == 2) { c = R2; s = R2; }
+  if (m == 3) { c = S1; s = C1; }
+  if (m == 4) {  // -i (forward) / +i (inverse)
+    return INV ? cplx<TC>{-a.im, a.re} : cplx<TC>{a.im, -a.re};
+  }
+  if (m == 6) { c = -R2; s = R2; }
+  if (m == 9) { c = -C1; s = -S1; }
+  cplx<TC> w = {(TC)c, INV ? (TC)s : (TC)-s};
+  return cmul(a, w);
+}
+
+template <typename TC, bool INV>
+__device__ __forceinline__ void dft16(cplx<TC>* a) {
+  // n = 4 n1 + n2, k = k1 + 4 k2
+#pragma unroll
+  for (int n2 = 0; n2 < 4; ++n2) dft4<TC, INV>(a[n2], a[4 + n2], a[8 + n2], a[12 + n2]);
+  // a[4 k1 + n2] *= W16^(n2 k1)
+  a[5] = w16<TC, INV, 1>(a[5]);
+  a[6] = w16<TC, INV, 2>(a[6]);
+  a[7] = w16<TC, INV, 3>(a[7]);
+  a[9] = w16<TC, INV, 2>(a[9]);
+  a[10] = w16<TC, INV, 4>(a[10]);
+  a[11] = w16<TC, INV, 6>(a[11]);
+  a[13] = w16<TC, INV, 3>(a[13]);
+  a[14] = w16<TC, INV, 6>(a[14]);
+  a[15] = w16<TC, INV, 9>(a[15]);
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1) dft4<TC, INV>(a[4 * k1], a[4 * k1 + 1], a[4 * k1 + 2], a[4 * k1 + 3]);
+  // a[4 k1 + k2] = A[k1 + 4 k2]: transpose to natural order
+  cplx<TC> o[16];
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1)
+#pragma unroll
+    for (int k2 = 0; k2 < 4; ++k2) o[k1 + 4 * k2] = a[4 * k1 + k2];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) a[i] = o[i];
+}
+
+template <typename TC, bool INV>
+__device__ __forceinline__ void dft8(cplx<TC>* a) {  // a[0..7], natural order in and out
+  dft4<TC, INV>(a[0], a[2], a[4], a[6]);
+  dft4<TC, INV>(a[1], a[3], a[5], a[7]);
+  // B1[k1] at a[2 k1 + 1] times W8^k1
+  a[3] = w16<TC, INV, 2>(a[3]);
+  a[5] = w16<TC, INV, 4>(a[5]);
+  a[7] = w16<TC, INV, 6>(a[7]);
+  cplx<TC> o[8];
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1) {
+    o[k1] = cadd(a[2 * k1], a[2 * k1 + 1]);
+    o[k1 + 4] = csub(a[2 * k1], a[2 * k1 + 1]);
+  }
+#pragma unroll
+  for (int i = 0; i < 8; ++i) a[i] = o[i];
+}
+
+template <typename TC, bool INV, int R>
+__device__ __forceinline__ void dftR(cplx<TC>* a) {
+  if (R == 16) dft16<TC, INV>(a);
+  if (R == 8) dft8<TC, INV>(a);
+  if (R == 4) dft4<TC, INV>(a[0], a[1], a[2], a[3]);
+  if (R == 2) {
+    cplx<TC> x0 = a[0], x1 = a[1];
+    a[0] = cadd(x0, x1);
+    a[1] = csub(x0, x1);
+  }
+}
+
+// LDS index of complex element i of a line (one pad slot per 16).
+__device__ __forceinline__ int lpad(int i) { return i + (i >> 4); }
+
+// Synchronisation of the threads of one line.  A line of T <= 64 threads
+// lies inside one wavefront, whose LDS accesses execute in issue order, so
+// wavefront-scope fences (compiler ordering only) are enough; longer lines
+// span several wavefronts and need the workgroup barrier.
+template <int T>
+__device__ __forceinline__ void line_sync() {
+  if (T <= 64) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
+
+// Per-thread twiddle state of the radix-16 FFT, loaded once per launch so
+// that no table load sits on the critical path of a stage:
+//   the radix-16 stage with L = 16: butterfly j = t, k = t mod 16; the
+//   factors w^(r k) come from w^k and w^(4k) by at most two products;
+//   the final stage of radix R < 16: butterflies j = t + T b with k = j, and
+//   w^k = w^t w^(T b) where w^(T b) is the same for the whole wavefront.
+template <typename TC>
+struct R16Tw {
+  cplx<TC> w1, w4;  // radix-16 stage with L = 16
+  cplx<TC> fin;     // final stage: twH[t]
+};
+
+template <typename TC>
+__device__ __forceinline__ void twiddle_r16(cplx<TC>* v, cplx<TC> w1, cplx<TC> w4, bool inv) {
+  cplx<TC> p[4], q4[4];
+  p[0] = {TC(1), TC(0)};
+  p[1] = w1;
+  p[2] = cmul(w1, w1);
+  p[3] = cmul(p[2], w1);
+  q4[0] = {TC(1), TC(0)};
+  q4[1] = w4;
+  q4[2] = cmul(w4, w4);
+  q4[3] = cmul(q4[2], w4);
+#pragma unroll
+  for (int r = 1; r < 16; ++r) {
+    cplx<TC> w = (r >> 2) == 0 ? p[r & 3] : ((r & 3) == 0 ? q4[r >> 2] : cmul(q4[r >> 2], p[r & 3]));
+    v[r] = inv ? cmulc(v[r], w) : cmul(v[r], w);
+  }
+}
+
+// One radix-16 Stockham stage (L = 1 or 16) on the thread's 16 values.
+// LAST: outputs stay in the thread's own slots; otherwise they go through
+// the line's LDS region z and come back in the z[t + T q] layout.
+template <typename TC, bool INV, bool LAST, int T>
+__device__ __forceinline__ void r16_stage16(cplx<TC>* a, int t, int L, const R16Tw<TC>& tw,
+                                            cplx<TC>* z) {
+  cplx<TC> v[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) v[r] = a[r];
+  if (L > 1) twiddle_r16(v, tw.w1, tw.w4, INV);
+  dft16<TC, INV>(v);
+  if (LAST) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) a[r] = v[r];
+  } else {
+    const int k = t & (L - 1);
+    const int base = (t - k) * 16 + k;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) z[lpad(base + r * L)] = v[r];
+    line_sync<T>();
+#pragma unroll
+    for (int q = 0; q < 16; ++q) a[q] = z[lpad(t + T * q)];
+    line_sync<T>();
+  }
+}
+
+// The final stage of radix R < 16 (always in place: L = H / R > j).
+template <typename TC, bool INV, int R>
+__device__ __forceinline__ void r16_final(cplx<TC>* a, int T, const R16Tw<TC>& tw,
+                                          const cplx<TC>* __restrict__ twH) {
+  constexpr int NB = 16 / R;
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    cplx<TC> v[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[r] = a[b + NB * r];
+    const cplx<TC> w = b ? cmul(tw.fin, twH[T * b]) : tw.fin;  // twH[t + T b]
+    cplx<TC> wr = w;
+#pragma unroll
+    for (int r = 1; r < R; ++r) {
+      v[r] = INV ? cmulc(v[r], wr) : cmul(v[r], wr);
+      if (r + 1 < R) wr = cmul(wr, w);  // w^(r+1)
+    }
+    dftR<TC, INV, R>(v);
+#pragma unroll
+    for (int r = 0; r < R; ++r) a[b + NB * r] = v[r];
+  }
+}
+
+template <typename TC, bool INV, int LOGH>
+__device__ __forceinline__ void r16_fft(cplx<TC>* a, int t, const R16Tw<TC>& tw,
+                                        const cplx<TC>* __restrict__ twH, cplx<TC>* z) {
+  constexpr int H = 1 << LOGH;
+  constexpr int T = H / 16;
+  constexpr int S16 = LOGH / 4;        // radix-16 stages (1 or 2 for H <= 2048)
+  constexpr int RR = 1 << (LOGH % 4);  // final radix (1: none)
+  static_assert(S16 >= 1 && S16 <= 2, "radix-16 plan covers 16 <= H <= 2048");
+  r16_stage16<TC, INV, (S16 == 1 && RR == 1), T>(a, t, 1, tw, z);
+  if (S16 == 2) r16_stage16<TC, INV, (RR == 1), T>(a, t, 16, tw, z);
+  if (RR == 8) r16_final<TC, INV, 8>(a, T, tw, twH);
+  if (RR == 4) r16_final<TC, INV, 4>(a, T, tw, twH);
+  if (RR == 2) r16_final<TC, INV, 2>(a, T, tw, twH);
+}
+
+// exp(-i pi (H-k) / (2N)) = exp(-i pi / 4) conj(exp(-i pi k / (2N))), N = 2H
+template <typename TC>
+__device__ __forceinline__ cplx<TC> t4n_mirror(cplx<TC> w) {
+  const TC r = (TC)0.70710678118654752440;
+  return {r * (w.re - w.im), -r * (w.re + w.im)};
+}
+
+// Inverse pre-processing of the own index k (see pre_pair): from X[k],
+// X[N-k], X[H-k], X[H+k] and the shift twiddles of k, returns Z[k].
+template <typename TC>
+__device__ __forceinline__ cplx<TC> pre_own(TC xk, TC xnk, TC xhk, TC xhpk, cplx<TC> w4, cplx<TC> wN) {
+  cplx<TC> Yk = {xk * TC(0.5), -xnk * TC(0.5)};
+  cplx<TC> Yj = {xhk * TC(0.5), -xhpk * TC(0.5)};
+  cplx<TC> Vk = cmulc(Yk, w4);
+  cplx<TC> Vj = cmulc(Yj, t4n_mirror(w4));
+  cplx<TC> Vjc = conj_(Vj);
+  cplx<TC> E = {(Vk.re + Vjc.re) * TC(0.5), (Vk.im + Vjc.im) * TC(0.5)};
+  cplx<TC> D = {(Vk.re - Vjc.re) * TC(0.5), (Vk.im - Vjc.im) * TC(0.5)};
+  cplx<TC> O = cmulc(D, wN);
+  return {E.re - O.im, E.im + O.re};
+}
+
+// Position of real v[p] (Makhoul order) in the line: x[2p] or x[2(N-1-p)+1].
+__device__ __forceinline__ int mk_src(int p, int N) { return p < N / 2 ? 2 * p : 2 * (N - 1 - p) + 1; }
+// LDS real index of v[p] (complex slot lpad(p/2), component p&1).
+__device__ __forceinline__ int vpad(int p) { return 2 * lpad(p >> 1) + (p & 1); }
+// LDS real index of X[r] (two pad slots per 32 reals).
+__device__ __forceinline__ int xpad(int r) { return r + 2 * (r >> 5); }
+
+template <typename TC, typename TI, typename TO, int OP, int LD, int ST, int LOGH>
+__global__ void __launch_bounds__(512) dct_r16(LineArgs<TC> A) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  if (A.skip && *A.skip) return;
+  constexpr int H = 1 << LOGH;
+  constexpr int N = 2 * H;
+  constexpr int T = H / 16;
+  const int LS = H + H / 16 + 1;  // complex slots per line in LDS
+  const int C = A.C;
+  const bool rows = A.axis == 0;
+  const int tile = A.tiles ? A.tiles[blockIdx.x] : (rows ? blockIdx.x : xcd_tile(blockIdx.x, gridDim.x));
+  // the T threads of a line are consecutive (one wavefront for T <= 64)
+  const int c = threadIdx.x / T;
+  const int t = threadIdx.x - c * T;
+  cplx<TC>* z = reinterpret_cast<cplx<TC>*>(smem_raw) + c * LS;
+  TC* const zr0 = reinterpret_cast<TC*>(smem_raw);  // line cc at zr0 + 2 * cc * LS
+  // Strided passes move the C-line tile cooperatively: element e of the
+  // tile is line e % C, position e / C, so each access covers C adjacent
+  // lines (C * sizeof element contiguous bytes).
+  const int nthr = blockDim.x;
+  int64_t lbase[1];
+  {
+    int li0, lo0;
+    lbase[0] = line_base(A, tile, 0, &li0, &lo0);  // line cc is at lbase + cc (x-adjacent)
+  }
+  TC* zr = reinterpret_cast<TC*>(z);
+  int li, lo;
+  const int64_t lb = line_base(A, tile, c, &li, &lo);
+  const int64_t st = A.stride;
+  const TI* __restrict__ in = reinterpret_cast<const TI*>(A.in);
+  TO* __restrict__ out = reinterpret_cast<TO*>(A.out);
+  const AxisTables<TC>& Tb = A.tab;
+
+  // twiddle state (issued first; in flight with the data loads)
+  R16Tw<TC> tw;
+  if (LOGH >= 8) {
+    const int step = (H / 256) * (t & 15);
+    tw.w1 = Tb.twH[step];
+    tw.w4 = Tb.twH[4 * step];
+  }
+  if (LOGH % 4) tw.fin = Tb.twH[t];
+  const cplx<TC> tNb = Tb.tN[t];
+  const cplx<TC> t4b = Tb.t4N[t];
+
+  auto load = [&](int n) -> TC {
+    int64_t p = lb + (int64_t)n * st;
+    if (LD == LD_RESID) {
+      double r = resid_at(A.rb, A.rphi, p, A.d, A.n0, A.n1, A.n2, A.ih2, A.rscale);
+      if (A.sub) r -= *A.sub;
+      return (TC)r;
+    } else if (A.sub) {
+      return (TC)((double)in[p] - *A.sub);
+    }
+    return (TC)in[p];
+  };
+
+  // cooperative tile load (strided passes): value of position n of line cc
+  // goes to real index pos(n) of line cc's LDS region
+  auto tile_load = [&](auto pos) {
+    const int64_t base = lbase[0];
+#pragma unroll 4
+    for (int e = threadIdx.x; e < C * N; e += nthr) {
+      const int cc = e % C, n = e / C;
+      int64_t p = base + cc + (int64_t)n * st;
+      TC v;
+      if (LD == LD_RESID) {
+        double r = resid_at(A.rb, A.rphi, p, A.d, A.n0, A.n1, A.n2, A.ih2, A.rscale);
+        if (A.sub) r -= *A.sub;
+        v = (TC)r;
+      } else if (A.sub) {
+        v = (TC)((double)in[p] - *A.sub);
+      } else {
+        v = (TC)in[p];
+      }
+      zr0[2 * cc * LS + pos(n)] = v;
+    }
+    __syncthreads();
+  };
+
+  cplx<TC> a[16];
+  if (OP != OP_INV) {
+    if (rows) {
+      // coalesced loads, reordered into Makhoul order through LDS
+      TC xv[32];
+#pragma unroll
+      for (int i = 0; i < 32; ++i) xv[i] = load(t + T * i);
+#pragma unroll
+      for (int i = 0; i < 32; ++i) zr[vpad(mk_pos(t + T * i, N))] = xv[i];
+      line_sync<T>();
+    } else {
+      tile_load([&](int n) { return vpad(mk_pos(n, N)); });
+    }
+#pragma unroll
+    for (int q = 0; q < 16; ++q) a[q] = z[lpad(t + T * q)];
+    line_sync<T>();
+    r16_fft<TC, false, LOGH>(a, t, tw, Tb.twH, z);
+    // partner exchange: Z[H-k] next to Z[k]
+#pragma unroll
+    for (int q = 0; q < 16; ++q) z[lpad(t + T * q)] = a[q];
+    line_sync<T>();
+    TC rest = TC(0), x0 = TC(0);
+    if (OP == OP_FDI) {
+      rest = A.lam0[li];
+      if (A.lam1) rest += A.lam1[lo];
+    }
+    const TC lc = A.lamc, ls_ = A.lscale;
+    TC ya[16], yb[16];  // own X[k] and X[N-k] (X[H] for k = 0), divided in FDI
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int k = t + T * q;
+      cplx<TC> Zk = a[q];
+      cplx<TC> Zc = conj_(z[lpad((H - k) & (H - 1))]);
+      cplx<TC> E = {(Zk.re + Zc.re) * TC(0.5), (Zk.im + Zc.im) * TC(0.5)};
+      cplx<TC> D = {(Zk.re - Zc.re) * TC(0.5), (Zk.im - Zc.im) * TC(0.5)};
+      cplx<TC> O = {D.im, -D.re};
+      const cplx<TC> wN = q ? cmul(tNb, Tb.tN[T * q]) : tNb;   // tN[k]
+      const cplx<TC> w4 = q ? cmul(t4b, Tb.t4N[T * q]) : t4b;  // t4N[k]
+      cplx<TC> WO = cmul(wN, O);
+      cplx<TC> Y = cmul(w4, cadd(E, WO));
+      TC xa = TC(2) * Y.re;   // X[k]
+      TC xb = TC(-2) * Y.im;  // X[N-k]; for k = 0 replaced by X[H]
+      if (k == 0) {
+        cplx<TC> Yh = cmul(t4n_mirror(w4), conj_(csub(E, WO)));
+        xb = TC(2) * Yh.re;
+      }
+      if (OP == OP_FWD) {
+        ya[q] = xa;
+        yb[q] = xb;
+      } else {
+        // divide by the summed eigenvalues; the 1D eigenvalue of index j is
+        // -(4/h^2) sin^2(pi j / (2N)): sin(pi k/2N) = -Im w4, cos = Re w4,
+        // and index H (k = 0) has sin^2 = 1/2
+        TC s_a = w4.im * w4.im;
+        TC s_b = k ? w4.re * w4.re : TC(0.5);
+        TC l_a = (rest + lc * s_a) * ls_;
+        TC l_b = (rest + lc * s_b) * ls_;
+        if (k == 0) x0 = xa;
+        ya[q] = l_a != TC(0) ? xa / l_a : TC(0);
+        yb[q] = xb / l_b;
+      }
+    }
+    if (OP == OP_FWD) {
+      if (rows) {
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+          const int k = t + T * q;
+          out[lb + (int64_t)k * st] = (TO)ya[q];
+          out[lb + (int64_t)(k ? N - k : H) * st] = (TO)yb[q];
+        }
+      } else {
+        line_sync<T>();
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+          const int k = t + T * q;
+          zr[xpad(k)] = ya[q];
+          zr[xpad(k ? N - k : H)] = yb[q];
+        }
+        __syncthreads();
+        const int64_t base = lbase[0];
+#pragma unroll 4
+        for (int e = threadIdx.x; e < C * N; e += nthr) {
+          const int cc = e % C, n = e / C;
+          out[base + cc + (int64_t)n * st] = (TO)zr0[2 * cc * LS + xpad(n)];
+        }
+      }
+      return;
+    }
+    // the zero line's mode 0 is sum(b) * prod(2 N_a): the compatibility defect
+    if (t == 0 && rest == TC(0) && A.bmean) *A.bmean = (double)x0 * A.meannorm;
+    line_sync<T>();
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int k = t + T * q;
+      zr[xpad(k)] = ya[q];
+      zr[xpad(k ? N - k : H)] = yb[q];
+    }
+    line_sync<T>();
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int k = t + T * q;
+      const cplx<TC> wN = q ? cmul(tNb, Tb.tN[T * q]) : tNb;
+      const cplx<TC> w4 = q ? cmul(t4b, Tb.t4N[T * q]) : t4b;
+      TC xhk = zr[xpad(H - k)];
+      TC xhpk = zr[xpad(H + k)];
+      a[q] = pre_own(ya[q], k ? yb[q] : TC(0), xhk, xhpk, w4, wN);
+    }
+    line_sync<T>();
+  } else {
+    // X in natural order: own X[k], X[N-k] and the partners' via LDS
+    TC xk[16], xn[16];
+    if (rows) {
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        int k = t + T * q;
+        xk[q] = load(k);
+        xn[q] = load(k ? N - k : H);
+      }
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        int k = t + T * q;
+        zr[xpad(k)] = xk[q];
+        zr[xpad(k ? N - k : H)] = xn[q];
+      }
+      line_sync<T>();
+    } else {
+      tile_load([&](int n) { return xpad(n); });
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        int k = t + T * q;
+        xk[q] = zr[xpad(k)];
+        xn[q] = zr[xpad(k ? N - k : H)];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int k = t + T * q;
+      const cplx<TC> wN = q ? cmul(tNb, Tb.tN[T * q]) : tNb;
+      const cplx<TC> w4 = q ? cmul(t4b, Tb.t4N[T * q]) : t4b;
+      TC xhk = zr[xpad(H - k)];
+      TC xhpk = zr[xpad(H + k)];
+      a[q] = pre_own(xk[q], k ? xn[q] : TC(0), xhk, xhpk, w4, wN);
+    }
+    line_sync<T>();
+  }
+
+  // inverse half-length FFT, then unpack v -> x.  Opaque copies of the
+  // thread index and LDS base keep the compiler from carrying the forward
+  // FFT's address arithmetic live into this second FFT.
+  int ti = t;
+  cplx<TC>* zi = z;
+  asm volatile("" : "+v"(ti));
+  asm volatile("" : "+v"(zi));
+  r16_fft<TC, true, LOGH>(a, ti, tw, Tb.twH, zi);
+  const TC sc = A.outscale;
+  // The stores hit the same addresses as the loads; opaque copies of the
+  // line base and stride make the compiler recompute them here instead of
+  // keeping them live through the whole kernel.
+  int64_t lb2 = lb, st2 = st;
+  int t2 = t;
+  asm volatile("" : "+v"(lb2));
+  asm volatile("" : "+s"(st2));
+  asm volatile("" : "+v"(t2));
+  auto put = [&](int64_t p, TC v) {
+    if (ST == ST_ACCUM) {
+      double* o = reinterpret_cast<double*>(A.out);
+      o[p] = A.rphi[p] + (double)v;
+    } else {
+      out[p] = (TO)v;
+    }
+  };
+#pragma unroll
+  for (int q = 0; q < 16; ++q) zi[lpad(ti + T * q)] = {a[q].re * sc, a[q].im * sc};
+  if (rows) {
+    // back to natural order through LDS, then coalesced stores
+    line_sync<T>();
+    TC* zri = reinterpret_cast<TC*>(zi);
+#pragma unroll
+    for (int i = 0; i < 32; ++i) {
+      const int n = t2 + T * i;
+      put(lb2 + (int64_t)n * st2, zri[vpad(mk_pos(n, N))]);
+    }
+  } else {
+    __syncthreads();
+    const int64_t base = lbase[0];
+#pragma unroll 4
+    for (int e = threadIdx.x; e < C * N; e += nthr) {
+      const int cc = e % C, n = e / C;
+      put(base + cc + (int64_t)n * st2, zr0[2 * cc * LS + vpad(mk_pos(n, N))]);
+    }
+  }
+}
+
 // ---- deterministic mean ----------------------------------------------------
 __global__ void __launch_bounds__(256) partial_sum_f64(const double* __restrict__ x, int64_t n,
-                                                       double* __restrict__ part) {
+                                                       double* __restrict__ part,
+                                                       const int32_t* __restrict__ skip) {
   __shared__ double red[256];
+  if (skip && *skip) return;
   double acc = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
     acc += x[i];
@@ -422,8 +942,10 @@ __global__ void __launch_bounds__(256) partial_sum_f64(const double* __restrict_
 }
 
 __global__ void __launch_bounds__(256) finish_mean(const double* __restrict__ part, int nblk,
-                                                   double scale, double* __restrict__ out) {
+                                                   double scale, double* __restrict__ out,
+                                                   const int32_t* __restrict__ skip) {
   __shared__ double red[256];
+  if (skip && *skip) return;
   double acc = 0.0;
   for (int i = threadIdx.x; i < nblk; i += 256) acc += part[i];
   red[threadIdx.x] = acc;
@@ -436,7 +958,9 @@ __global__ void __launch_bounds__(256) finish_mean(const double* __restrict__ pa
 }
 
 __global__ void __launch_bounds__(256) sub_scalar_f64(double* __restrict__ x, int64_t n,
-                                                      const double* __restrict__ m) {
+                                                      const double* __restrict__ m,
+                                                      const int32_t* __restrict__ skip) {
+  if (skip && *skip) return;
   double mv = m[0];
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
     x[i] -= mv;
@@ -489,14 +1013,41 @@ void tile_shape(int axis, int N, int lines_x, int* C, int* nthr, int* B) {
   *B = b;
 }
 
+}  // namespace
+
+// Lines per workgroup tile of the radix-16 transform along `axis` (0 when
+// the axis uses the generic kernel, N < 32).
+int r16_tile_lines(const pc_plan* P, int axis, size_t elem) {
+  const int N = P->n[axis];
+  if (N < 32) return 0;
+  const int H = N / 2, T = H / 16, LS = H + H / 16 + 1;
+  const int64_t lines = P->G / N;
+  int C;
+  if (axis == 0) {
+    C = std::max(1, ROW_THREADS / T);
+    while (C > 1 && (int64_t)C > lines) C >>= 1;
+  } else {
+    C = (int)(128 / elem);
+    while (C > 1 && (C * T > COL_MAX_THREADS || C > P->n[0])) C >>= 1;
+  }
+  while (C > 1 && (size_t)C * LS * 2 * elem > (size_t)lds_limit()) C >>= 1;
+  return C;
+}
+
+namespace {
+
 template <typename TC, typename TI, typename TO, int OP, int LD, int ST>
 int launch_pass(const pc_plan* P, int axis, const TI* in, TO* out, const AxisTables<TC>* tabs,
                 const double* rb, const double* rphi, double* bmean, hipStream_t s,
-                const double* sub = nullptr, double sigma = 1.0) {
+                const double* sub = nullptr, double sigma = 1.0, const int32_t* skip = nullptr,
+                const int32_t* tiles = nullptr, int ntiles = -1) {
   LineArgs<TC> A{};
   A.sub = sub;
+  A.skip = skip;
+  A.tiles = tiles;
   A.lscale = (TC)sigma;
   A.rscale = sigma;
+  A.lamc = (TC)(-4.0 / (P->h[axis] * P->h[axis]));
   A.in = in;
   A.out = out;
   A.rb = rb;
@@ -521,8 +1072,52 @@ int launch_pass(const pc_plan* P, int axis, const TI* in, TO* out, const AxisTab
   double norm = 1.0;
   for (int a = 0; a < P->d; ++a) norm *= 2.0 * P->n[a];
   A.meannorm = 1.0 / norm;
-  int C, nthr, B;
   int64_t lines = P->G / A.N;
+  if (A.N >= 32) {
+    // radix-16 register kernel: T = H/16 threads per line, C lines per group
+    const int T = H / 16;
+    const int LS = H + H / 16 + 1;
+    const int C = r16_tile_lines(P, axis, sizeof(TC));
+    if ((size_t)C * LS * 2 * sizeof(TC) > (size_t)lds_limit())
+      return fail(PC_ERR_UNSUPPORTED_SIZE, "transform line does not fit in LDS");
+    A.C = C;
+    int ntile;
+    if (axis == 0) {
+      if (lines % C) return fail(PC_ERR_UNSUPPORTED_SIZE, "row count not a multiple of the tile");
+      ntile = (int)(lines / C);
+    } else {
+      A.tx = P->n[0] / C;
+      ntile = (int)(lines / C);
+    }
+    if (tiles) {
+      if (ntiles <= 0) return PC_OK;
+      ntile = ntiles;
+    }
+    size_t lds = (size_t)C * LS * 2 * sizeof(TC);
+    dim3 grid(ntile), block(C * T);
+    const void* fn = nullptr;
+    switch (logH) {
+#define PC_R16_CASE(LH) \
+      case LH: fn = (const void*)dct_r16<TC, TI, TO, OP, LD, ST, LH>; break;
+      PC_R16_CASE(4) PC_R16_CASE(5) PC_R16_CASE(6) PC_R16_CASE(7)
+      PC_R16_CASE(8) PC_R16_CASE(9) PC_R16_CASE(10) PC_R16_CASE(11)
+#undef PC_R16_CASE
+      default: return fail(PC_ERR_UNSUPPORTED_SIZE, "transform length");
+    }
+    if (lds > 65536)
+      PC_HIP_CHECK(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    switch (logH) {
+#define PC_R16_LAUNCH(LH) \
+      case LH: hipLaunchKernelGGL((dct_r16<TC, TI, TO, OP, LD, ST, LH>), grid, block, lds, s, A); break;
+      PC_R16_LAUNCH(4) PC_R16_LAUNCH(5) PC_R16_LAUNCH(6) PC_R16_LAUNCH(7)
+      PC_R16_LAUNCH(8) PC_R16_LAUNCH(9) PC_R16_LAUNCH(10) PC_R16_LAUNCH(11)
+#undef PC_R16_LAUNCH
+    }
+    PC_HIP_CHECK(hipGetLastError());
+    return PC_OK;
+  }
+  int C, nthr, B;
+
   tile_shape<TC>(axis, A.N, axis == 0 ? (int)std::min<int64_t>(lines, 1 << 20) : P->n[0], &C,
                  &nthr, &B);
   A.C = C;
@@ -570,27 +1165,30 @@ int launch_pass(const pc_plan* P, int axis, const TI* in, TO* out, const AxisTab
 template <typename TC, typename TI, typename TO, int LD, int ST>
 int solve_passes(const pc_plan* P, const AxisTables<TC>* tabs, const TI* in, TO* out,
                  TC* work, const double* rb, const double* rphi, double* bmean, hipStream_t s,
-                 const double* sub = nullptr, double sigma = 1.0) {
+                 const double* sub = nullptr, double sigma = 1.0,
+                 const int32_t* skip = nullptr) {
   if (P->d == 2) {
     PC_TRY((launch_pass<TC, TI, TC, OP_FWD, LD, ST_PLAIN>(P, 0, in, work, tabs, rb, rphi, nullptr, s,
-                                                          sub, sigma)));
+                                                          sub, sigma, skip)));
     PC_TRY((launch_pass<TC, TC, TC, OP_FDI, LD_PLAIN, ST_PLAIN>(P, 1, work, work, tabs, nullptr,
                                                                 nullptr, bmean, s, nullptr,
-                                                                sigma)));
+                                                                sigma, skip)));
     PC_TRY((launch_pass<TC, TC, TO, OP_INV, LD_PLAIN, ST>(P, 0, work, out, tabs, nullptr, rphi,
-                                                          nullptr, s)));
+                                                          nullptr, s, nullptr, 1.0, skip)));
   } else {
     PC_TRY((launch_pass<TC, TI, TC, OP_FWD, LD, ST_PLAIN>(P, 0, in, work, tabs, rb, rphi, nullptr, s,
-                                                          sub, sigma)));
+                                                          sub, sigma, skip)));
     PC_TRY((launch_pass<TC, TC, TC, OP_FWD, LD_PLAIN, ST_PLAIN>(P, 1, work, work, tabs, nullptr,
-                                                                nullptr, nullptr, s)));
+                                                                nullptr, nullptr, s, nullptr, 1.0,
+                                                                skip)));
     PC_TRY((launch_pass<TC, TC, TC, OP_FDI, LD_PLAIN, ST_PLAIN>(P, 2, work, work, tabs, nullptr,
                                                                 nullptr, bmean, s, nullptr,
-                                                                sigma)));
+                                                                sigma, skip)));
     PC_TRY((launch_pass<TC, TC, TC, OP_INV, LD_PLAIN, ST_PLAIN>(P, 1, work, work, tabs, nullptr,
-                                                                nullptr, nullptr, s)));
+                                                                nullptr, nullptr, s, nullptr, 1.0,
+                                                                skip)));
     PC_TRY((launch_pass<TC, TC, TO, OP_INV, LD_PLAIN, ST>(P, 0, work, out, tabs, nullptr, rphi,
-                                                          nullptr, s)));
+                                                          nullptr, s, nullptr, 1.0, skip)));
   }
   return PC_OK;
 }
@@ -608,24 +1206,24 @@ int fill_zero(void* p, size_t bytes, hipStream_t s) {
 }
 
 int mean_f64(const double* x, int64_t n, double* partial, int nblk, double* out_dev,
-             hipStream_t s) {
-  hipLaunchKernelGGL(partial_sum_f64, dim3(nblk), dim3(256), 0, s, x, n, partial);
+             hipStream_t s, const int32_t* skip) {
+  hipLaunchKernelGGL(partial_sum_f64, dim3(nblk), dim3(256), 0, s, x, n, partial, skip);
   hipLaunchKernelGGL(finish_mean, dim3(1), dim3(256), 0, s, partial, nblk, 1.0 / (double)n,
-                     out_dev);
+                     out_dev, skip);
   PC_HIP_CHECK(hipGetLastError());
   return PC_OK;
 }
 
 int solve_f64(const pc_plan* P, const double* b, double* phi, double* bmean_dev, pc_workspace*,
-              hipStream_t s, double sigma) {
+              hipStream_t s, double sigma, const int32_t* skip) {
   return solve_passes<double, double, double, LD_PLAIN, ST_PLAIN>(
-      P, P->ax64, b, phi, phi, nullptr, nullptr, bmean_dev, s, nullptr, sigma);
+      P, P->ax64, b, phi, phi, nullptr, nullptr, bmean_dev, s, nullptr, sigma, skip);
 }
 
 int solve_f32(const pc_plan* P, const float* b, float* phi, double* bmean_dev, pc_workspace*,
-              hipStream_t s, double sigma) {
+              hipStream_t s, double sigma, const int32_t* skip) {
   return solve_passes<float, float, float, LD_PLAIN, ST_PLAIN>(
-      P, P->ax32, b, phi, phi, nullptr, nullptr, bmean_dev, s, nullptr, sigma);
+      P, P->ax32, b, phi, phi, nullptr, nullptr, bmean_dev, s, nullptr, sigma, skip);
 }
 
 // Defect correction: bbar = mean(b) in float64; phi0 = S32(b - bbar); then
@@ -635,21 +1233,21 @@ int solve_f32(const pc_plan* P, const float* b, float* phi, double* bmean_dev, p
 // each conversion to float32: left in, the compatibility defect would
 // dominate the float32 rounding of the much smaller residual.
 int solve_mixed(const pc_plan* P, const double* b, double* phi, int sweeps, double* bmean_dev,
-                pc_workspace* ws, hipStream_t s, double sigma) {
+                pc_workspace* ws, hipStream_t s, double sigma, const int32_t* skip) {
   if (!ws || !ws->w32) return fail(PC_ERR_INVALID_ARG, "mixed solve needs a MIXED workspace");
   float* w = ws->w32;
   double* bm = bmean_dev ? bmean_dev : ws->scal;
-  PC_TRY(mean_f64(b, P->G, ws->partial, ws->nblk, bm, s));
-  PC_TRY((solve_passes<float, double, double, LD_PLAIN, ST_PLAIN>(P, P->ax32, b, phi, w, nullptr,
-                                                                  nullptr, nullptr, s, bm, sigma)));
+  PC_TRY(mean_f64(b, P->G, ws->partial, ws->nblk, bm, s, skip));
+  PC_TRY((solve_passes<float, double, double, LD_PLAIN, ST_PLAIN>(
+      P, P->ax32, b, phi, w, nullptr, nullptr, nullptr, s, bm, sigma, skip)));
   for (int it = 0; it < sweeps; ++it) {
-    PC_TRY((solve_passes<float, double, double, LD_RESID, ST_ACCUM>(P, P->ax32, b, phi, w, b, phi,
-                                                                    nullptr, s, bm, sigma)));
+    PC_TRY((solve_passes<float, double, double, LD_RESID, ST_ACCUM>(
+        P, P->ax32, b, phi, w, b, phi, nullptr, s, bm, sigma, skip)));
   }
-  PC_TRY(mean_f64(phi, P->G, ws->partial, ws->nblk, ws->scal + 3, s));
+  PC_TRY(mean_f64(phi, P->G, ws->partial, ws->nblk, ws->scal + 3, s, skip));
   int nb = (int)std::min<int64_t>(8192, (P->G + 255) / 256);
   hipLaunchKernelGGL(sub_scalar_f64, dim3(nb), dim3(256), 0, s, phi, P->G,
-                     (const double*)(ws->scal + 3));
+                     (const double*)(ws->scal + 3), skip);
   PC_HIP_CHECK(hipGetLastError());
   return PC_OK;
 }

@@ -66,20 +66,29 @@ __global__ void __launch_bounds__(TPB) k_div_all(const int32_t* __restrict__ gid
 }
 
 // ---- div_to_grid near the IB: b[near[q]] = base[q] (or b) + D(g) -----------
+// g lives on the B+V nodes only, so each near point sums over its B+V
+// entries (ELL layout, coalesced over q).
 template <typename T, int D, bool ADD>
 __global__ void __launch_bounds__(TPB) k_div_near(const int32_t* __restrict__ near, int64_t nnear,
-                                                  const int32_t* __restrict__ nptr,
-                                                  const int32_t* __restrict__ nslot,
-                                                  const T* __restrict__ ncoef, int64_t nent,
+                                                  int W, const int32_t* __restrict__ nslot,
+                                                  const T* __restrict__ ncoef,
                                                   const T* __restrict__ gib, int64_t nib,
-                                                  const T* __restrict__ base, T* __restrict__ b) {
+                                                  const T* __restrict__ base, T* __restrict__ b,
+                                                  const int32_t* __restrict__ skip) {
+  if (skip && *skip) return;
   int64_t q = (int64_t)blockIdx.x * TPB + threadIdx.x;
   if (q >= nnear) return;
   T acc = T(0);
-  for (int e = nptr[q]; e < nptr[q + 1]; ++e) {
-    int s = nslot[e];
+  // fully unrolled over the widest possible stencil so that the loads of all
+  // entries are in flight together
 #pragma unroll
-    for (int a = 0; a < D; ++a) acc += ncoef[a * nent + e] * gib[a * nib + s];
+  for (int e = 0; e < PC_MAX_K_GRID; ++e) {
+    if (e < W) {
+      // padding entries have slot -1 and coefficient exactly 0
+      const int s = max(nslot[(int64_t)e * nnear + q], 0);
+#pragma unroll
+      for (int a = 0; a < D; ++a) acc += ncoef[((int64_t)a * W + e) * nnear + q] * gib[a * nib + s];
+    }
   }
   int64_t p = near[q];
   if (ADD)
@@ -129,7 +138,9 @@ template <typename T, int D, bool LOCALREF>
 __global__ void __launch_bounds__(TPB) k_grad_ib(const int32_t* __restrict__ ibbase,
                                                  const T* __restrict__ ibcoef, int64_t nib, int bn,
                                                  BlockOffsets bo, const T* __restrict__ phi,
-                                                 T scale, T* __restrict__ out) {
+                                                 T scale, T* __restrict__ out,
+                                                 const int32_t* __restrict__ skip) {
+  if (skip && *skip) return;
   const int64_t s = (int64_t)blockIdx.x * TPB + threadIdx.x;
   if (s >= nib) return;
   const int64_t base = ibbase[s];
@@ -181,8 +192,10 @@ constexpr int IB_BLOCKS = 256;
 template <typename T, int D>
 __global__ void __launch_bounds__(TPB) k_ib_update(const T* __restrict__ uib,
                                                    const T* __restrict__ grad, T* __restrict__ g,
-                                                   int64_t nib, double* __restrict__ part) {
+                                                   int64_t nib, double* __restrict__ part,
+                                                   const int32_t* __restrict__ skip) {
   __shared__ double rn[TPB], rd[TPB];
+  if (skip && *skip) return;
   double num = 0.0, den = 0.0;
   for (int64_t s = (int64_t)blockIdx.x * TPB + threadIdx.x; s < nib;
        s += (int64_t)gridDim.x * TPB) {
@@ -215,10 +228,13 @@ __global__ void __launch_bounds__(TPB) k_ib_update(const T* __restrict__ uib,
   }
 }
 
+// conv[0]: converged flag (also the skip flag of later iterations);
+// conv[1]: number of iterations run.
 __global__ void __launch_bounds__(TPB) k_ib_finish(const double* __restrict__ part, int nblk,
                                                    double tol, double* __restrict__ sums,
-                                                   int32_t* __restrict__ conv) {
+                                                   int32_t* __restrict__ conv, int count) {
   __shared__ double rn[TPB], rd[TPB];
+  if (count && conv[0]) return;
   double num = 0.0, den = 0.0;
   for (int i = threadIdx.x; i < nblk; i += TPB) {
     num += part[2 * i];
@@ -238,7 +254,137 @@ __global__ void __launch_bounds__(TPB) k_ib_finish(const double* __restrict__ pa
     sums[0] = rn[0];
     sums[1] = rd[0];
     conv[0] = (rn[0] < tol * rd[0] || rn[0] == 0.0) ? 1 : 0;
+    if (count) conv[1] += 1;
   }
+}
+
+// ---- fused IB step: gradient at the B+V nodes, force update, criterion ----------
+// One launch per IB iteration: every thread takes one B+V node, computes
+// grad phi there (sigma * grad p), g_new = -u* + grad, the two criterion
+// terms, and overwrites g.  Block partial sums go to part[]; the last block
+// to finish (ticket counter) adds them in block order, so the sums do not
+// depend on scheduling, sets the converged flag and counts the iteration.
+template <typename T, int D, int BN>
+__global__ void __launch_bounds__(TPB) k_ib_step(const int32_t* __restrict__ ibbase,
+                                                 const T* __restrict__ ibcoef, int64_t nib, int bnrt,
+                                                 BlockOffsets bo, const T* __restrict__ phi,
+                                                 T scale, const T* __restrict__ uib,
+                                                 T* __restrict__ g, double* __restrict__ part,
+                                                 int32_t* __restrict__ ticket, double tol,
+                                                 double* __restrict__ sums,
+                                                 int32_t* __restrict__ conv,
+                                                 const int32_t* __restrict__ skip,
+                                                 int32_t* host_flag) {
+  __shared__ double rn[TPB], rd[TPB];
+  __shared__ int is_last;
+  if (skip && *skip) return;
+  const int bn = BN > 0 ? BN : bnrt;
+  const int64_t s = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  double num = 0.0, den = 0.0;
+  if (s < nib) {
+    const int64_t base = ibbase[s];
+    T acc[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) acc[a] = T(0);
+    const bool lr = sizeof(T) == 4;
+    T ref = lr ? phi[base + bo.off[0]] : T(0);
+#pragma unroll
+    for (int o = 0; o < (BN > 0 ? BN : PC_MAX_K_NODE); ++o) {
+      if (o < bn) {
+        T f = phi[base + bo.off[o]];
+        if (lr) f -= ref;
+#pragma unroll
+        for (int a = 0; a < D; ++a) acc[a] += ibcoef[((int64_t)a * bn + o) * nib + s] * f;
+      }
+    }
+    double mn = 0.0, mo = 0.0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      T gn = -uib[a * nib + s] + scale * acc[a];
+      T go = g[a * nib + s];
+      mn += (double)gn * (double)gn;
+      mo += (double)go * (double)go;
+      g[a * nib + s] = gn;
+    }
+    double dm = sqrt(mn) - sqrt(mo);
+    num = dm * dm;
+    den = mo;
+  }
+  rn[threadIdx.x] = num;
+  rd[threadIdx.x] = den;
+  __syncthreads();
+  for (int w = TPB / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      rn[threadIdx.x] += rn[threadIdx.x + w];
+      rd[threadIdx.x] += rd[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = rn[0];
+    part[2 * blockIdx.x + 1] = rd[0];
+    __threadfence();
+    is_last = atomicAdd(ticket, 1) == (int)gridDim.x - 1;
+  }
+  __syncthreads();
+  if (!is_last) return;
+  __threadfence();
+  num = 0.0;
+  den = 0.0;
+  for (int i = threadIdx.x; i < (int)gridDim.x; i += TPB) {
+    num += __builtin_nontemporal_load(part + 2 * i);
+    den += __builtin_nontemporal_load(part + 2 * i + 1);
+  }
+  rn[threadIdx.x] = num;
+  rd[threadIdx.x] = den;
+  __syncthreads();
+  for (int w = TPB / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      rn[threadIdx.x] += rn[threadIdx.x + w];
+      rd[threadIdx.x] += rd[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    sums[0] = rn[0];
+    sums[1] = rd[0];
+    const int32_t cv = (rn[0] < tol * rd[0] || rn[0] == 0.0) ? 1 : 0;
+    conv[0] = cv;
+    conv[1] += 1;
+    *ticket = 0;
+    if (host_flag) {
+      // pinned host memory, read by the host once this launch has completed
+      *host_flag = cv;
+      __threadfence_system();
+    }
+  }
+}
+
+// Prologue of a sub-step: u* at the B+V nodes, the initial IB force (zero or
+// the caller's warm start) and the device flags, in one launch.
+template <typename T>
+__global__ void __launch_bounds__(TPB) k_prologue(const int32_t* __restrict__ ib, int64_t nib,
+                                                  int d, const T* __restrict__ u, int64_t M,
+                                                  T* __restrict__ uib, T* __restrict__ gib,
+                                                  const T* __restrict__ g_in,
+                                                  int32_t* __restrict__ flag) {
+  int64_t s = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  if (blockIdx.x == 0 && threadIdx.x < 16) flag[threadIdx.x] = 0;
+  if (s >= nib) return;
+  int64_t n = ib[s];
+  for (int a = 0; a < d; ++a) {
+    uib[a * nib + s] = u[a * M + n];
+    gib[a * nib + s] = g_in ? g_in[a * nib + s] : T(0);
+  }
+}
+
+// Statistics into pinned host memory: bmean, criterion sums, flags.
+__global__ void __launch_bounds__(64) k_stats_out(const double* __restrict__ scal,
+                                                  const int32_t* __restrict__ flag,
+                                                  double* hs, int32_t* hf) {
+  if (threadIdx.x < 3) hs[threadIdx.x] = scal[threadIdx.x];
+  if (threadIdx.x < 2) hf[threadIdx.x + 2] = flag[threadIdx.x];
+  __threadfence_system();
 }
 
 template <typename T>
@@ -312,12 +458,12 @@ int launch_div_all(const pc_geom* g, const T* gcoef, const T* v, T* b, hipStream
 
 template <typename T>
 int launch_div_near(const pc_geom* g, const T* ncoefib, const T* gib, const T* base, T* b,
-                    bool add, hipStream_t s) {
+                    bool add, hipStream_t s, const int32_t* skip = nullptr) {
   if (g->n_near == 0) return PC_OK;
   dim3 grid(nblk(g->n_near)), block(TPB);
 #define DNL(D, ADD)                                                                          \
-  hipLaunchKernelGGL((k_div_near<T, D, ADD>), grid, block, 0, s, g->near, g->n_near, g->nptr, \
-                     g->nslot, ncoefib, g->n_near_entries, gib, g->n_ib, base, b)
+  hipLaunchKernelGGL((k_div_near<T, D, ADD>), grid, block, 0, s, g->near, g->n_near, g->near_w, \
+                     g->nslot, ncoefib, gib, g->n_ib, base, b, skip)
   if (g->d == 2) {
     if (add) DNL(2, true); else DNL(2, false);
   } else {
@@ -357,7 +503,7 @@ int launch_grad_all(const pc_geom* g, const T* ncoef, const T* phi, T scale, con
 
 template <typename T>
 int launch_grad_ib(const pc_geom* g, const T* ibcoef, const T* phi, T scale, T* out,
-                   hipStream_t s) {
+                   hipStream_t s, const int32_t* skip = nullptr) {
   if (g->n_ib == 0) return PC_OK;
   const bool lr = sizeof(T) == 4;
   BlockOffsets bo = block_offsets(g);
@@ -365,17 +511,17 @@ int launch_grad_ib(const pc_geom* g, const T* ibcoef, const T* phi, T scale, T* 
   if (g->d == 2) {
     if (lr)
       hipLaunchKernelGGL((k_grad_ib<T, 2, true>), grid, block, 0, s, g->ibbase, ibcoef, g->n_ib,
-                         g->bn, bo, phi, scale, out);
+                         g->bn, bo, phi, scale, out, skip);
     else
       hipLaunchKernelGGL((k_grad_ib<T, 2, false>), grid, block, 0, s, g->ibbase, ibcoef, g->n_ib,
-                         g->bn, bo, phi, scale, out);
+                         g->bn, bo, phi, scale, out, skip);
   } else {
     if (lr)
       hipLaunchKernelGGL((k_grad_ib<T, 3, true>), grid, block, 0, s, g->ibbase, ibcoef, g->n_ib,
-                         g->bn, bo, phi, scale, out);
+                         g->bn, bo, phi, scale, out, skip);
     else
       hipLaunchKernelGGL((k_grad_ib<T, 3, false>), grid, block, 0, s, g->ibbase, ibcoef, g->n_ib,
-                         g->bn, bo, phi, scale, out);
+                         g->bn, bo, phi, scale, out, skip);
   }
   PC_HIP_CHECK(hipGetLastError());
   return PC_OK;
@@ -383,14 +529,38 @@ int launch_grad_ib(const pc_geom* g, const T* ibcoef, const T* phi, T scale, T* 
 
 template <typename T>
 int launch_ib_update(const pc_geom* g, const T* uib, const T* grad, T* gib, double tol,
-                     double* part, double* sums, int32_t* conv, hipStream_t s) {
+                     double* part, double* sums, int32_t* conv, hipStream_t s,
+                     const int32_t* skip = nullptr, int count = 0) {
   int nb = (int)std::min<int64_t>(IB_BLOCKS, std::max<int64_t>(1, nblk(g->n_ib)));
   if (g->d == 2)
-    hipLaunchKernelGGL((k_ib_update<T, 2>), dim3(nb), dim3(TPB), 0, s, uib, grad, gib, g->n_ib, part);
+    hipLaunchKernelGGL((k_ib_update<T, 2>), dim3(nb), dim3(TPB), 0, s, uib, grad, gib, g->n_ib, part,
+                       skip);
   else
-    hipLaunchKernelGGL((k_ib_update<T, 3>), dim3(nb), dim3(TPB), 0, s, uib, grad, gib, g->n_ib, part);
+    hipLaunchKernelGGL((k_ib_update<T, 3>), dim3(nb), dim3(TPB), 0, s, uib, grad, gib, g->n_ib, part,
+                       skip);
   hipLaunchKernelGGL(k_ib_finish, dim3(1), dim3(TPB), 0, s, (const double*)part, nb, tol, sums,
-                     conv);
+                     conv, count);
+  PC_HIP_CHECK(hipGetLastError());
+  return PC_OK;
+}
+
+template <typename T>
+int launch_ib_step(const pc_geom* g, const T* ibcoef, const T* phi, T scale, const T* uib, T* gib,
+                   double tol, double* part, int32_t* flag, double* sums, hipStream_t s,
+                   const int32_t* skip, int32_t* host_flag) {
+  if (g->n_ib == 0) return PC_OK;
+  BlockOffsets bo = block_offsets(g);
+  dim3 grid(nblk(g->n_ib)), block(TPB);
+  // flag[0]: converged, flag[1]: iterations, flag[2]: ticket counter
+#define IBS(D, BN)                                                                              \
+  hipLaunchKernelGGL((k_ib_step<T, D, BN>), grid, block, 0, s, g->ibbase, ibcoef, g->n_ib, g->bn, \
+                     bo, phi, scale, uib, gib, part, flag + 2, tol, sums, flag, skip, host_flag)
+  if (g->d == 2) {
+    if (g->bn == 16) IBS(2, 16); else IBS(2, 0);
+  } else {
+    if (g->bn == 27) IBS(3, 27); else IBS(3, 0);
+  }
+#undef IBS
   PC_HIP_CHECK(hipGetLastError());
   return PC_OK;
 }
@@ -442,46 +612,62 @@ int pressure_correct_t(const pc_geom* g, const pc_plan* P, int mode, const T* u,
   T* gradib = reinterpret_cast<T*>(W->gradib);
   const int64_t nib = g->n_ib;
 
-  if (nib) {
-    hipLaunchKernelGGL(k_gather_ib<T>, dim3(nblk(nib)), dim3(TPB), 0, s, g->ib, nib, g->d, u, g->M,
-                       uib);
-    if (g_io)
-      PC_HIP_CHECK(hipMemcpyAsync(gib, g_io, (size_t)g->d * nib * sizeof(T),
-                                  hipMemcpyDeviceToDevice, s));
-    else
-      PC_TRY(fill_zero(gib, (size_t)g->d * nib * sizeof(T), s));
-  }
+  hipLaunchKernelGGL(k_prologue<T>, dim3(std::max<unsigned>(1, nblk(nib))), dim3(TPB), 0, s, g->ib,
+                     nib, g->d, u, g->M, uib, gib, (const T*)g_io, W->flag);
+  PC_HIP_CHECK(hipGetLastError());
   PC_TRY(launch_div_all<T>(g, gc<T>(g), u, b, s));
   if (g->n_near)
     hipLaunchKernelGGL(k_gather_near<T>, dim3(nblk(g->n_near)), dim3(TPB), 0, s, g->near, g->n_near,
                        (const T*)b, bnear);
-  PC_TRY(fill_zero(W->flag, 16 * 4, s));
+
+  // One IB iteration (Sec. 2.3): RHS update near the IB, Poisson solve,
+  // gradient at the B+V nodes, force update and criterion.  With `skip` set,
+  // every launch of the iteration returns at once once the device flag says
+  // an earlier iteration has converged.
+  auto iteration = [&](int it, const int32_t* skip, int32_t* host_flag) -> int {
+    if (it > 1 || g_io) PC_TRY(launch_div_near<T>(g, nci<T>(g), gib, bnear, b, false, s, skip));
+    if (mode == PC_F64)
+      PC_TRY(solve_f64(P, (const double*)b, (double*)p, W->scal, W, s, sigma, skip));
+    else if (mode == PC_F32)
+      PC_TRY(solve_f32(P, (const float*)b, (float*)p, W->scal, W, s, sigma, skip));
+    else
+      PC_TRY(solve_mixed(P, (const double*)b, (double*)p, sweeps, W->scal, W, s, sigma, skip));
+    if (nib)
+      PC_TRY(launch_ib_step<T>(g, ibc<T>(g), p, (T)sigma, uib, gib, tol, W->partial, W->flag,
+                               W->scal + 1, s, skip, host_flag));
+    return PC_OK;
+  };
 
   int it = 0;
   bool converged = nib == 0;
-  while (true) {
-    ++it;
-    if (it > 1 || g_io) PC_TRY(launch_div_near<T>(g, nci<T>(g), gib, bnear, b, false, s));
-    if (mode == PC_F64)
-      PC_TRY(solve_f64(P, (const double*)b, (double*)p, W->scal, W, s, sigma));
-    else if (mode == PC_F32)
-      PC_TRY(solve_f32(P, (const float*)b, (float*)p, W->scal, W, s, sigma));
-    else
-      PC_TRY(solve_mixed(P, (const double*)b, (double*)p, sweeps, W->scal, W, s, sigma));
-    if (nib == 0) break;
-    PC_TRY(launch_grad_ib<T>(g, ibc<T>(g), p, (T)sigma, gradib, s));
-    PC_TRY(launch_ib_update<T>(g, uib, gradib, gib, tol, W->partial, W->scal + 1, W->flag, s));
-    if (fixed_it > 0) {
-      if (it >= fixed_it) break;
-      continue;
+  if (nib == 0) {
+    PC_TRY(iteration(1, nullptr, nullptr));
+    it = 1;
+  } else if (fixed_it > 0) {
+    for (it = 1; it <= fixed_it; ++it) PC_TRY(iteration(it, nullptr, nullptr));
+    it = fixed_it;
+  } else {
+    // Enqueue one iteration ahead of the convergence test: while the host
+    // waits for iteration i, the device already runs i+1 (which does nothing
+    // if i converged), so the device does not idle on the host.  The IB
+    // kernel of iteration i writes its flag straight into pinned host slot
+    // i % 2; an event marks the iteration's completion.
+    volatile int32_t* hf = W->hflag;
+    hf[0] = hf[1] = -1;
+    PC_TRY(iteration(1, W->flag, W->hflag + 1));
+    PC_HIP_CHECK(hipEventRecord(W->ev[1], s));
+    for (it = 1;; ++it) {
+      if (it < max_it) {
+        PC_TRY(iteration(it + 1, W->flag, W->hflag + ((it + 1) & 1)));
+        PC_HIP_CHECK(hipEventRecord(W->ev[(it + 1) & 1], s));
+      }
+      PC_HIP_CHECK(hipEventSynchronize(W->ev[it & 1]));
+      if (hf[it & 1] == 1) {
+        converged = true;
+        break;
+      }
+      if (it >= max_it) break;
     }
-    PC_HIP_CHECK(hipMemcpyAsync(W->hflag, W->flag, 4, hipMemcpyDeviceToHost, s));
-    PC_HIP_CHECK(hipStreamSynchronize(s));
-    if (W->hflag[0]) {
-      converged = true;
-      break;
-    }
-    if (it >= max_it) break;
   }
   PC_TRY((launch_grad_all<T, true>(g, nc<T>(g), p, (T)sigma, u, u_out, s)));
   PC_TRY(launch_zero_ib<T>(g, u_out, s));
@@ -493,14 +679,19 @@ int pressure_correct_t(const pc_geom* g, const pc_plan* P, int mode, const T* u,
     PC_HIP_CHECK(hipGetLastError());
   }
   if (st) {
-    PC_HIP_CHECK(hipMemcpyAsync(W->hscal, W->scal, 16 * 8, hipMemcpyDeviceToHost, s));
-    PC_HIP_CHECK(hipMemcpyAsync(W->hflag, W->flag, 4, hipMemcpyDeviceToHost, s));
-    PC_HIP_CHECK(hipStreamSynchronize(s));
+    hipLaunchKernelGGL(k_stats_out, dim3(1), dim3(64), 0, s, (const double*)W->scal,
+                       (const int32_t*)W->flag, W->hscal, W->hflag);
+    PC_HIP_CHECK(hipGetLastError());
+    PC_HIP_CHECK(hipEventRecord(W->ev[0], s));
+    PC_HIP_CHECK(hipEventSynchronize(W->ev[0]));
+    volatile double* hs = W->hscal;
+    volatile int32_t* hf = W->hflag;
     st->n_it = it;
-    st->converged = (nib == 0 || W->hflag[0]) ? 1 : 0;
-    st->bmean = W->hscal[0];
-    st->ib_num = W->hscal[1];
-    st->ib_den = W->hscal[2];
+    st->converged = (nib == 0 || hf[2]) ? 1 : 0;
+    if (nib && fixed_it <= 0) st->converged = converged ? 1 : 0;
+    st->bmean = hs[0];
+    st->ib_num = hs[1];
+    st->ib_den = hs[2];
     converged = st->converged;
   }
   if (fixed_it > 0) return PC_OK;

@@ -520,24 +520,28 @@ __global__ void __launch_bounds__(256) k_slot_map(const int32_t* __restrict__ ib
 
 template <typename T>
 __global__ void __launch_bounds__(256) k_near_fill(const int32_t* __restrict__ near, int64_t nnear,
-                                                   const int32_t* __restrict__ nptr,
-                                                   const int32_t* __restrict__ gidx,
+                                                   int W, const int32_t* __restrict__ gidx,
                                                    const T* __restrict__ gcoef, int64_t G, int k,
                                                    int d, const int32_t* __restrict__ slot,
-                                                   int64_t nent, int32_t* __restrict__ nslot,
+                                                   int32_t* __restrict__ nslot,
                                                    T* __restrict__ ncoefib) {
   int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (q >= nnear) return;
   int64_t p = near[q];
-  int e = nptr[q];
+  int e = 0;
   for (int i = 0; i < k; ++i) {
     int nid = gidx[(int64_t)i * G + p];
     int s = slot[nid];
-    if (s >= 0) {
-      nslot[e] = s;
-      for (int a = 0; a < d; ++a) ncoefib[(int64_t)a * nent + e] = gcoef[((int64_t)a * k + i) * G + p];
+    if (s >= 0 && e < W) {
+      nslot[(int64_t)e * nnear + q] = s;
+      for (int a = 0; a < d; ++a)
+        ncoefib[((int64_t)a * W + e) * nnear + q] = gcoef[((int64_t)a * k + i) * G + p];
       ++e;
     }
+  }
+  for (; e < W; ++e) {
+    nslot[(int64_t)e * nnear + q] = -1;
+    for (int a = 0; a < d; ++a) ncoefib[((int64_t)a * W + e) * nnear + q] = T(0);
   }
 }
 
@@ -572,7 +576,7 @@ unsigned nblocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 void geom_free(pc_geom* g) {
   if (!g) return;
   void* ptrs[] = {g->gidx, g->gcoef, g->gcoef32, g->nbase, g->ncoef, g->ncoef32, g->ib,
-                  g->near, g->nptr, g->nslot, g->ncoefib, g->ncoefib32, g->ibbase, g->ibcoef,
+                  g->near, g->nslot, g->ncoefib, g->ncoefib32, g->ibbase, g->ibcoef,
                   g->ibcoef32};
   for (void* p : ptrs) dev_free(p);
 }
@@ -720,40 +724,42 @@ int build(const pc_plan* P, const double* xyz, const uint8_t* kind, int64_t M,
   std::vector<uint8_t> hflag((size_t)G);
   PC_HIP_CHECK(hipMemcpyAsync(hflag.data(), nflag, (size_t)G, hipMemcpyDeviceToHost, s));
   PC_HIP_CHECK(hipStreamSynchronize(s));
-  std::vector<int32_t> hnear, hptr(1, 0);
+  std::vector<int32_t> hnear;
+  int near_w = 0;
+  int64_t near_entries = 0;
   for (int64_t p = 0; p < G; ++p) {
     if (hflag[p]) {
       hnear.push_back((int32_t)p);
-      hptr.push_back(hptr.back() + hflag[p]);
+      near_w = std::max(near_w, (int)hflag[p]);
+      near_entries += hflag[p];
     }
   }
   g->n_near = (int64_t)hnear.size();
-  g->n_near_entries = hptr.back();
+  g->n_near_entries = near_entries;
+  g->near_w = near_w;
   if (g->n_ib) {
     PC_TRY(dev_alloc((void**)&g->ib, (size_t)g->n_ib * 4, "IB list"));
     PC_HIP_CHECK(hipMemcpy(g->ib, hib.data(), (size_t)g->n_ib * 4, hipMemcpyHostToDevice));
   }
   if (g->n_near) {
+    const int64_t ell = (int64_t)near_w * g->n_near;
     PC_TRY(dev_alloc((void**)&g->near, (size_t)g->n_near * 4, "near list"));
-    PC_TRY(dev_alloc((void**)&g->nptr, (size_t)(g->n_near + 1) * 4, "near offsets"));
-    PC_TRY(dev_alloc((void**)&g->nslot, (size_t)g->n_near_entries * 4, "near slots"));
-    PC_TRY(dev_alloc((void**)&g->ncoefib, (size_t)d * g->n_near_entries * 8, "near coefs"));
-    if (want32)
-      PC_TRY(dev_alloc((void**)&g->ncoefib32, (size_t)d * g->n_near_entries * 4, "near coefs"));
+    PC_TRY(dev_alloc((void**)&g->nslot, (size_t)ell * 4, "near slots"));
+    PC_TRY(dev_alloc((void**)&g->ncoefib, (size_t)d * ell * 8, "near coefs"));
+    if (want32) PC_TRY(dev_alloc((void**)&g->ncoefib32, (size_t)d * ell * 4, "near coefs"));
     PC_HIP_CHECK(hipMemcpy(g->near, hnear.data(), (size_t)g->n_near * 4, hipMemcpyHostToDevice));
-    PC_HIP_CHECK(hipMemcpy(g->nptr, hptr.data(), (size_t)(g->n_near + 1) * 4, hipMemcpyHostToDevice));
     int32_t* slot;
     PC_TRY(tmp.alloc((void**)&slot, (size_t)M * 4, "slot map"));
     PC_HIP_CHECK(hipMemsetAsync(slot, 0xff, (size_t)M * 4, s));
     hipLaunchKernelGGL(k_slot_map, dim3(nblocks(g->n_ib, 256)), dim3(256), 0, s, g->ib, g->n_ib,
                        slot);
     hipLaunchKernelGGL(k_near_fill<double>, dim3(nblocks(g->n_near, 256)), dim3(256), 0, s,
-                       g->near, g->n_near, g->nptr, g->gidx, g->gcoef, G, k_grid, d, slot,
-                       g->n_near_entries, g->nslot, g->ncoefib);
+                       g->near, g->n_near, near_w, g->gidx, g->gcoef, G, k_grid, d, slot,
+                       g->nslot, g->ncoefib);
     if (want32)
       hipLaunchKernelGGL(k_near_fill<float>, dim3(nblocks(g->n_near, 256)), dim3(256), 0, s,
-                         g->near, g->n_near, g->nptr, g->gidx, g->gcoef32, G, k_grid, d, slot,
-                         g->n_near_entries, g->nslot, g->ncoefib32);
+                         g->near, g->n_near, near_w, g->gidx, g->gcoef32, G, k_grid, d, slot,
+                         g->nslot, g->ncoefib32);
     PC_HIP_CHECK(hipGetLastError());
   }
   if (g->n_ib) {
@@ -769,12 +775,13 @@ int build(const pc_plan* P, const double* xyz, const uint8_t* kind, int64_t M,
     PC_HIP_CHECK(hipGetLastError());
   }
   PC_HIP_CHECK(hipStreamSynchronize(s));
+  const int64_t ell = (int64_t)g->near_w * g->n_near;
   int64_t bytes = (int64_t)k_grid * G * 4 + (int64_t)d * k_grid * G * 8 + M * 4 +
-                  (int64_t)d * bn * M * 8 + g->n_ib * 4 + g->n_near * 8 + 4 +
-                  g->n_near_entries * (4 + 8 * d) + g->n_ib * (4 + 8 * (int64_t)d * bn);
+                  (int64_t)d * bn * M * 8 + g->n_ib * 4 + g->n_near * 4 + ell * (4 + 8 * d) +
+                  g->n_ib * (4 + 8 * (int64_t)d * bn);
   if (want32)
-    bytes += (int64_t)d * k_grid * G * 4 + (int64_t)d * bn * M * 4 +
-             g->n_near_entries * 4 * d + g->n_ib * 4 * (int64_t)d * bn;
+    bytes += (int64_t)d * k_grid * G * 4 + (int64_t)d * bn * M * 4 + ell * 4 * d +
+             g->n_ib * 4 * (int64_t)d * bn;
   g->bytes = bytes;
   return PC_OK;
 }
