@@ -62,6 +62,11 @@ def bytes_solve(G, d, s):
     return (2 * d - 1) * bytes_solve_pass(G, s, s)
 
 
+def bytes_grad(G, M, bn, d, s):
+    """coefficients + block corner per node, phi read once, gradient written."""
+    return M * (bn * d * s + 4 + d * s) + G * s
+
+
 def bytes_grad_project(G, M, bn, d, s):
     """coefficients + block corner per node, u* read, u^{n+1} written, phi read once."""
     return M * (bn * d * s + 4 + 2 * d * s) + G * s
@@ -153,21 +158,31 @@ def main():
     t_solve = time_launches(lambda: pc.poisson_fft_solve(plan, b64, phi64, pc.PC_F64), reps)
     t_grad = time_launches(lambda: pc.grad_to_nodes(geom, phi64, gr64), reps)
     k, bn = geom.k_grid, geom.bn
+    n_it = results.get("f64", {}).get("n_it", 1)
+    # kernel: (device kernel, bytes per launch, seconds per launch, launches per step);
+    # the solve call is three kernels (rows forward, fused column pass, rows inverse)
     kern = {
-        "div_to_grid": {"bytes": bytes_div_all(G, M, k, d, 8), "s": t_div, "launches_per_step": 1},
-        "poisson_fft_solve": {"bytes": bytes_solve(G, d, 8), "s": t_solve,
-                              "launches_per_step": results.get("f64", {}).get("n_it", 1)},
-        "grad_to_nodes": {"bytes": bytes_grad_project(G, M, bn, d, 8) - M * d * 8, "s": t_grad,
-                          "launches_per_step": 1},
+        "div_to_grid": {"kernel": f"k_div_all<double,{d},{k}>",
+                        "bytes": bytes_div_all(G, M, k, d, 8), "s": t_div,
+                        "launches_per_step": 1, "kernels_per_call": 1},
+        "poisson_fft_solve": {"kernel": "dct_r16 x3", "bytes": bytes_solve(G, d, 8),
+                              "s": t_solve, "launches_per_step": n_it,
+                              "kernels_per_call": 2 * d - 1},
+        "grad_to_nodes": {"kernel": f"k_grad_all<double,{d},{bn}>",
+                          "bytes": bytes_grad(G, M, bn, d, 8),
+                          "s": t_grad, "launches_per_step": 1, "kernels_per_call": 1},
     }
     for v in kern.values():
         v["GBs"] = v["bytes"] / v["s"] / 1e9
         v["frac"] = v["GBs"] / HBM_PEAK_GBS
         v["us"] = v["s"] * 1e6
-    dom = max(kern, key=lambda n: kern[n]["s"] * kern[n]["launches_per_step"])
+    # the dominant single kernel: largest time per step among one-kernel calls
+    single = [n for n in kern if kern[n]["kernels_per_call"] == 1]
+    dom = max(single, key=lambda n: kern[n]["s"] * kern[n]["launches_per_step"])
     roof = {"bound": "hbm", "achieved": round(kern[dom]["GBs"], 1), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(kern[dom]["frac"], 4), "traffic": None,
-            "kernel": dom, "bytes_per_launch": kern[dom]["bytes"],
+            "unit": "GB/s", "frac": round(kern[dom]["frac"], 4),
+            "traffic": measured_traffic(kern[dom]["kernel"], G),
+            "kernel": kern[dom]["kernel"], "call": dom, "bytes_per_launch": kern[dom]["bytes"],
             "avg_launch_us": round(kern[dom]["us"], 2)}
 
     if args.copy_probe:
@@ -211,6 +226,39 @@ def main():
         "device": torch.cuda.get_device_name(dev),
     }
     print(json.dumps(out))
+
+
+def kernel_source_digest(name):
+    """sha256 (16 hex digits) of a kernel's source text and of its launch
+    helper in csrc/pc_step.hip: a changed kernel invalidates old counters."""
+    import hashlib
+    import re
+    root = os.path.dirname(os.path.abspath(__file__))
+    text = open(os.path.join(root, "paper_2304_14690_amd", "csrc", "pc_step.hip")).read()
+    parts = re.findall(r"template <[^\n]*>\n__global__[^\n]*\b" + name + r"\(.*?\n}\n", text, re.S)
+    parts += re.findall(r"\nint launch_" + name[2:] + r"\(.*?\n}\n", text, re.S)
+    return hashlib.sha256("".join(parts).encode()).hexdigest()[:16]
+
+
+def measured_traffic(kernel, G):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy of known size),
+    or None when the summary is absent, was taken on another workload, or
+    the kernel source has changed since it was taken."""
+    root = os.path.dirname(os.path.abspath(__file__))
+    path = os.path.join(root, "profiles", "k_div_all_2048.traffic.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            key, val = line.split(":", 1)
+            vals[key.strip()] = val.strip()
+    digest = kernel_source_digest(kernel.split("<")[0])
+    if vals.get("kernel") != kernel.split("<")[0] or vals.get("source_sha256_16") != digest \
+            or int(vals.get("G", -1)) != G:
+        return None
+    return float(vals["hbm_bytes_per_launch"])
 
 
 def cpu_baseline(N):

@@ -112,7 +112,17 @@ typedef struct pc_ib_opts {
   int32_t fixed_it;  /* > 0: run exactly this many iterations               */
   int32_t sweeps;    /* PC_MIXED defect-correction sweeps (default 2)       */
   int32_t gauge;     /* 0: zero-mean pressure; 1: zero at the first cell    */
+  int32_t flags;     /* PC_IB_* bits below                                  */
 } pc_ib_opts;
+
+/* pc_ib_opts.flags: transform every grid line in every IB iteration.  By
+ * default (PC_F64, PC_F32, every n[a] >= 32) iterations after the first
+ * redo the forward transforms only on the grid lines that hold near-IB
+ * points (the only ones whose right-hand side changes, Sec. 2.3) and run
+ * the inverse transforms only on the lines the B+V gradient reads; the
+ * remaining lines are completed after the last iteration.  The results are
+ * identical bit for bit; this flag exists to show that. */
+#define PC_IB_FULL_TRANSFORMS 1
 
 typedef struct pc_stats {
   int32_t n_it;      /* IB iterations run                                   */
@@ -145,7 +155,7 @@ int pc_last_error(char* buf, size_t n);
 int pc_plan_create(int d, const int32_t* n, const double* h, void* stream, pc_plan** out);
 int pc_plan_destroy(pc_plan* plan);
 
-/* ---- a3 + a4 (+ a8): the Poisson solve ---------------------------------- */
+/* ---- the Poisson solve ---------------------------------------------------- */
 
 /* Solves lap_h phi = b - mean(b) with mean(phi) = 0 on the plan's grid
  * (Sec. 2.3: forward transforms along each axis, division by the sum of the
@@ -162,7 +172,7 @@ int pc_plan_destroy(pc_plan* plan);
 int pc_poisson_fft_solve(const pc_plan* plan, int mode, const void* b_dev, void* phi_dev,
                          int sweeps, double* bmean_dev, pc_workspace* ws, void* stream);
 
-/* ---- a1: stencils -------------------------------------------------------- */
+/* ---- WLS stencils --------------------------------------------------------- */
 
 /* Builds the WLS stencils of one node cloud (Sec. 2.2; computed once per
  * geometry, last paragraph of Sec. 2.2):
@@ -204,7 +214,7 @@ int pc_geom_export(const pc_geom* geom, int32_t* grid_idx_dev, double* grid_coef
                    int32_t* node_base_dev, double* node_coef_dev, int32_t* ib_dev,
                    int32_t* near_dev, void* stream);
 
-/* ---- a2: right-hand side -------------------------------------------------- */
+/* ---- right-hand side ------------------------------------------------------ */
 
 /* b = WLS divergence of v at the grid points (Sec. 2.3, Eq. 20 right-hand
  * side, with v = u* + g):  b_p = sum_a sum_i c^a_{p,i} v_a[idx_{p,i}].
@@ -217,7 +227,7 @@ int pc_geom_export(const pc_geom* geom, int32_t* grid_idx_dev, double* grid_coef
 int pc_div_to_grid(const pc_geom* geom, int dtype, const void* v_dev, void* b_dev, int subset,
                    void* stream);
 
-/* ---- a5: gradient transfer ----------------------------------------------- */
+/* ---- gradient transfer ---------------------------------------------------- */
 
 /* grad = WLS gradient of phi at the nodes (Sec. 2.3):
  * grad_a(n) = sum_j c^a_{n,j} phi[src_{n,j}].
@@ -226,7 +236,7 @@ int pc_div_to_grid(const pc_geom* geom, int dtype, const void* v_dev, void* b_de
 int pc_grad_to_nodes(const pc_geom* geom, int dtype, const void* phi_dev, void* grad_dev,
                      int subset, void* stream);
 
-/* ---- a6: one IB-force update ----------------------------------------------- */
+/* ---- one IB-force update -------------------------------------------------- */
 
 /* g_new = -u* + grad at the B+V nodes (Eq. 19 times dt); sums the criterion
  * of Sec. 2.3, num = sum (|g_new| - |g_old|)^2 and den = sum |g_old|^2, into
@@ -236,7 +246,7 @@ int pc_grad_to_nodes(const pc_geom* geom, int dtype, const void* phi_dev, void* 
 int pc_ib_update(const pc_geom* geom, int dtype, const void* u_dev, const void* grad_ib_dev,
                  void* g_dev, double tol, double* sums_dev, int32_t* conv_dev, void* stream);
 
-/* ---- a7: projection ---------------------------------------------------------- */
+/* ---- projection ----------------------------------------------------------- */
 
 /* u_out = u* - grad + g (Eq. 18 with phi, g): u* - grad on velocity points
  * and exactly 0 on boundary and virtual points, where Eq. 19 cancels it.
@@ -263,9 +273,11 @@ int64_t pc_workspace_bytes(const pc_plan* plan, const pc_geom* geom, int mode);
  *   the IB force times dt (Sec. 2.3: taken from the previous time step) and
  *   its final value.  NULL starts from zero.
  *   stats (nullable) is filled after the call synchronises `stream`.
- * Synchronises `stream` once per IB iteration to read the 4-byte
- * convergence flag (not when fixed_it > 0).  Returns PC_WARN_IB_NOT_CONVERGED
- * when max_it is reached first. */
+ * The host waits once per IB iteration for that iteration's 4-byte
+ * convergence flag (written by the device into pinned host memory) while
+ * the next iteration is already queued; a queued iteration after
+ * convergence exits at once on a device-side flag.  Not when fixed_it > 0.
+ * Returns PC_WARN_IB_NOT_CONVERGED when max_it is reached first. */
 int pc_pressure_correct(const pc_geom* geom, const pc_plan* plan, int mode, const void* u_dev,
                         double dt, void* u_out_dev, void* p_dev, void* g_inout_dev,
                         const pc_ib_opts* opts, pc_stats* stats, pc_workspace* ws,

@@ -208,11 +208,46 @@ int64_t pc_workspace_bytes(const pc_plan* P, const pc_geom* g, int mode) {
     add(3 * (int64_t)g->d * g->n_ib * (int64_t)s);  // uib, gib, gradib
   }
   if (mode == PC_MIXED) add(P->G * 4);   // w32
+  if (pc::resident_ok(P, g, mode)) {
+    if (P->d == 3) add(P->G * (int64_t)s);             // w1b
+    add(4 * pc::resident_tiles_max(P, s));            // tile lists
+  }
   add(8 * partial_doubles(g));           // partials
   add(16 * 8);                           // scalars
   add(16 * 4);                           // flags
   return bytes;
 }
+
+}  // extern "C"
+
+namespace {
+
+// Builds the tile lists of the resident transforms from the geometry's
+// near-IB points and B+V stencil blocks and uploads them.
+int resident_setup(const pc_plan* P, const pc_geom* g, size_t elem, pc_workspace* W) {
+  std::vector<int32_t> near_pts(g->n_near), ib_base(g->n_ib);
+  if (g->n_near)
+    PC_HIP_CHECK(hipMemcpy(near_pts.data(), g->near, 4 * g->n_near, hipMemcpyDeviceToHost));
+  if (g->n_ib)
+    PC_HIP_CHECK(hipMemcpy(ib_base.data(), g->ibbase, 4 * g->n_ib, hipMemcpyDeviceToHost));
+  std::vector<int32_t> lists[6];
+  pc::resident_tiles(P, elem, near_pts, ib_base, g->m_node, lists);
+  std::vector<int32_t> all;
+  for (int l = 0; l < 6; ++l) {
+    W->tl[l] = W->tiles + all.size();
+    W->ntl[l] = (int)lists[l].size();
+    all.insert(all.end(), lists[l].begin(), lists[l].end());
+  }
+  if ((int64_t)all.size() > pc::resident_tiles_max(P, elem))
+    return fail(PC_ERR_INVALID_ARG, "resident tile lists exceed their bound");
+  if (!all.empty())
+    PC_HIP_CHECK(hipMemcpy(W->tiles, all.data(), 4 * all.size(), hipMemcpyHostToDevice));
+  return PC_OK;
+}
+
+}  // namespace
+
+extern "C" {
 
 int pc_workspace_create(const pc_plan* P, const pc_geom* g, int mode, pc_workspace** out) {
   if (!P || !out) return fail(PC_ERR_INVALID_ARG, "pc_workspace_create: null argument");
@@ -249,16 +284,30 @@ int pc_workspace_create(const pc_plan* P, const pc_geom* g, int mode, pc_workspa
     W->gradib = take((int64_t)g->d * g->n_ib * (int64_t)s);
   }
   if (mode == PC_MIXED) W->w32 = reinterpret_cast<float*>(take(P->G * 4));
+  if (pc::resident_ok(P, g, mode)) {
+    if (P->d == 3) W->w1b = take(P->G * (int64_t)s);
+    W->tiles = reinterpret_cast<int32_t*>(take(4 * pc::resident_tiles_max(P, s)));
+    W->resident = 1;
+  }
   W->partial = reinterpret_cast<double*>(take(8 * partial_doubles(g)));
   W->scal = reinterpret_cast<double*>(take(16 * 8));
   W->flag = reinterpret_cast<int32_t*>(take(16 * 4));
-  if (hipHostMalloc((void**)&W->hscal, 16 * 8 + 16 * 4, hipHostMallocDefault) != hipSuccess) {
+  // coherent: the IB kernel's flag store (system-scope fence) is read by the
+  // host while later kernels of the stream are still running
+  if (hipHostMalloc((void**)&W->hscal, 16 * 8 + 16 * 4, hipHostMallocCoherent) != hipSuccess) {
     (void)hipGetLastError();
     dev_free(W->block);
     delete W;
     return fail(PC_ERR_OOM, "pinned host scalars");
   }
   W->hflag = reinterpret_cast<int32_t*>(W->hscal + 16);
+  if (W->resident) {
+    int rc2 = resident_setup(P, g, s, W);
+    if (rc2 != PC_OK) {
+      pc_workspace_destroy(W);
+      return rc2;
+    }
+  }
   for (int i = 0; i < 2; ++i) {
     if (hipEventCreateWithFlags(&W->ev[i], hipEventDisableTiming) != hipSuccess) {
       (void)hipGetLastError();

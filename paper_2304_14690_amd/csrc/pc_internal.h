@@ -133,7 +133,22 @@ struct pc_workspace {
   double* hscal;     // pinned host mirror of scal
   int nblk;          // partial-sum blocks
   hipEvent_t ev[2];  // convergence-flag copies of alternate iterations
+  // Resident transforms of the IB iteration (F64/F32 with a geometry): the
+  // forward transforms of the right-hand side stay in `phi` (first axis) and
+  // `w1b` (3D: second axis) between iterations, so later iterations redo
+  // only the lines that hold near-IB points, and the inverse transforms run
+  // only on the lines the B+V gradient reads until the loop has ended.
+  int resident;
+  void* w1b;         // [G] field dtype (3D only)
+  int32_t* tiles;    // device tile lists, list l at tl[l]
+  int32_t* tl[6];
+  int ntl[6];
 };
+
+namespace pc {
+// tile lists of the resident transforms
+enum { TL_FWD0 = 0, TL_FWD1, TL_INV1_IB, TL_INV1_REST, TL_INV0_IB, TL_INV0_REST };
+}
 
 namespace pc {
 // ---- solve (pc_solve.hip) ---------------------------------------------------
@@ -151,6 +166,28 @@ int solve_mixed(const pc_plan* P, const double* b, double* phi, int sweeps, doub
                 pc_workspace* ws, hipStream_t s, double sigma = 1.0,
                 const int32_t* skip = nullptr);
 int ensure_plan_ws(const pc_plan* P, pc_workspace** ws);
+// Lines per workgroup tile of the radix-16 transform along `axis` for
+// elements of `elem` bytes (0 when the axis is shorter than 32).
+int r16_tile_lines(const pc_plan* P, int axis, size_t elem);
+// Whether the resident IB-iteration transforms apply to this plan/geometry/mode.
+bool resident_ok(const pc_plan* P, const pc_geom* g, int mode);
+// Upper bound of the total length of the six tile lists.
+int64_t resident_tiles_max(const pc_plan* P, size_t elem);
+// Tile lists (host) of the resident transforms: near_pts are the near-IB
+// grid points, ib_base the block corners of the B+V node stencils (block
+// of m grid lines per axis).
+void resident_tiles(const pc_plan* P, size_t elem, const std::vector<int32_t>& near_pts,
+                    const std::vector<int32_t>& ib_base, int m, std::vector<int32_t> out[6]);
+// One resident solve.  phase 0: first iteration (every line); phase 1: a
+// later iteration (forward passes on the near-IB lines only); both leave
+// the inverse transforms done only on the lines read by the B+V gradient.
+// phase 2: completes the inverse transforms on the remaining lines.
+int solve_resident_f64(const pc_plan* P, const double* b, double* p, double* bmean_dev,
+                       pc_workspace* ws, hipStream_t s, double sigma, const int32_t* skip,
+                       int phase);
+int solve_resident_f32(const pc_plan* P, const float* b, float* p, double* bmean_dev,
+                       pc_workspace* ws, hipStream_t s, double sigma, const int32_t* skip,
+                       int phase);
 // deterministic mean of a float64 grid field into out_dev[0]
 int mean_f64(const double* x, int64_t n, double* partial, int nblk, double* out_dev,
              hipStream_t s, const int32_t* skip = nullptr);

@@ -670,7 +670,6 @@ __global__ void __launch_bounds__(512) dct_r16(LineArgs<TC> A) {
   // Strided passes move the C-line tile cooperatively: element e of the
   // tile is line e % C, position e / C, so each access covers C adjacent
   // lines (C * sizeof element contiguous bytes).
-  const int nthr = blockDim.x;
   int64_t lbase[1];
   {
     int li0, lo0;
@@ -707,25 +706,45 @@ __global__ void __launch_bounds__(512) dct_r16(LineArgs<TC> A) {
     return (TC)in[p];
   };
 
-  // cooperative tile load (strided passes): value of position n of line cc
-  // goes to real index pos(n) of line cc's LDS region
+  // Strided passes move the tile cooperatively.  Thread x takes line
+  // cc = x % C at positions n = x / C + r T, r = 0..31 (C T threads, N = 32 T
+  // positions per line), so each access covers C adjacent lines; all 32
+  // loads are issued before the first is used.
+  const int tcc = threadIdx.x & (C - 1);
+  const int tn0 = threadIdx.x >> __builtin_ctz(C);
+  // value of position n of line tcc goes to real index pos(n) of its LDS region
   auto tile_load = [&](auto pos) {
-    const int64_t base = lbase[0];
-#pragma unroll 4
-    for (int e = threadIdx.x; e < C * N; e += nthr) {
-      const int cc = e % C, n = e / C;
-      int64_t p = base + cc + (int64_t)n * st;
-      TC v;
-      if (LD == LD_RESID) {
-        double r = resid_at(A.rb, A.rphi, p, A.d, A.n0, A.n1, A.n2, A.ih2, A.rscale);
-        if (A.sub) r -= *A.sub;
-        v = (TC)r;
-      } else if (A.sub) {
-        v = (TC)((double)in[p] - *A.sub);
-      } else {
-        v = (TC)in[p];
+    const int64_t p0 = lbase[0] + tcc + (int64_t)tn0 * st;
+    const int64_t dp = (int64_t)T * st;
+    TC* zl = zr0 + 2 * tcc * LS;
+    if (LD == LD_RESID) {
+      // the residual reads 5-7 values per point: batches of 8 points
+#pragma unroll
+      for (int r0 = 0; r0 < 32; r0 += 8) {
+        TC v[8];
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+          double x = resid_at(A.rb, A.rphi, p0 + (r0 + r) * dp, A.d, A.n0, A.n1, A.n2, A.ih2,
+                              A.rscale);
+          if (A.sub) x -= *A.sub;
+          v[r] = (TC)x;
+        }
+#pragma unroll
+        for (int r = 0; r < 8; ++r) zl[pos(tn0 + (r0 + r) * T)] = v[r];
       }
-      zr0[2 * cc * LS + pos(n)] = v;
+    } else {
+      TC v[32];
+      const TI* src = in + p0;
+      if (A.sub) {
+        const double sb = *A.sub;
+#pragma unroll
+        for (int r = 0; r < 32; ++r) v[r] = (TC)((double)src[r * dp] - sb);
+      } else {
+#pragma unroll
+        for (int r = 0; r < 32; ++r) v[r] = (TC)src[r * dp];
+      }
+#pragma unroll
+      for (int r = 0; r < 32; ++r) zl[pos(tn0 + r * T)] = v[r];
     }
     __syncthreads();
   };
@@ -809,12 +828,10 @@ __global__ void __launch_bounds__(512) dct_r16(LineArgs<TC> A) {
           zr[xpad(k ? N - k : H)] = yb[q];
         }
         __syncthreads();
-        const int64_t base = lbase[0];
-#pragma unroll 4
-        for (int e = threadIdx.x; e < C * N; e += nthr) {
-          const int cc = e % C, n = e / C;
-          out[base + cc + (int64_t)n * st] = (TO)zr0[2 * cc * LS + xpad(n)];
-        }
+        TO* dst = out + lbase[0] + tcc + (int64_t)tn0 * st;
+        const TC* zl = zr0 + 2 * tcc * LS;
+#pragma unroll
+        for (int r = 0; r < 32; ++r) dst[(int64_t)r * T * st] = (TO)zl[xpad(tn0 + r * T)];
       }
       return;
     }
@@ -914,12 +931,11 @@ __global__ void __launch_bounds__(512) dct_r16(LineArgs<TC> A) {
     }
   } else {
     __syncthreads();
-    const int64_t base = lbase[0];
-#pragma unroll 4
-    for (int e = threadIdx.x; e < C * N; e += nthr) {
-      const int cc = e % C, n = e / C;
-      put(base + cc + (int64_t)n * st2, zr0[2 * cc * LS + vpad(mk_pos(n, N))]);
-    }
+    const int64_t p0 = lbase[0] + tcc + (int64_t)tn0 * st2;
+    const TC* zl = zr0 + 2 * tcc * LS;
+#pragma unroll
+    for (int r = 0; r < 32; ++r)
+      put(p0 + (int64_t)r * T * st2, zl[vpad(mk_pos(tn0 + r * T, N))]);
   }
 }
 
@@ -1250,6 +1266,134 @@ int solve_mixed(const pc_plan* P, const double* b, double* phi, int sweeps, doub
                      (const double*)(ws->scal + 3), skip);
   PC_HIP_CHECK(hipGetLastError());
   return PC_OK;
+}
+
+
+// ---- resident transforms of the IB iteration -----------------------------------
+// After the first IB iteration the right-hand side changes only at the
+// near-IB grid points (Sec. 2.3), and each 1D transform acts on its own line,
+// so the forward transforms of the lines without near-IB points carry over
+// unchanged from iteration to iteration.  The iteration itself reads the
+// solution only through the gradient at the B+V nodes, so the inverse
+// transforms can stop at the lines that gradient reads; the other lines are
+// completed once, after the last iteration.  Every line that is transformed
+// is transformed exactly as in the full solve, so the result is the same
+// bit for bit.
+
+bool resident_ok(const pc_plan* P, const pc_geom* g, int mode) {
+  if (!g || g->n_ib == 0 || (mode != PC_F64 && mode != PC_F32)) return false;
+  for (int a = 0; a < P->d; ++a)
+    if (P->n[a] < 32) return false;
+  return true;
+}
+
+int64_t resident_tiles_max(const pc_plan* P, size_t elem) {
+  const int C0 = r16_tile_lines(P, 0, elem);
+  int64_t t0 = C0 > 0 ? P->G / P->n[0] / C0 : 0;
+  int64_t t1 = 0;
+  if (P->d == 3) {
+    const int C1 = r16_tile_lines(P, 1, elem);
+    t1 = C1 > 0 ? P->G / P->n[1] / C1 : 0;
+  }
+  return 3 * (t0 + t1);
+}
+
+void resident_tiles(const pc_plan* P, size_t elem, const std::vector<int32_t>& near_pts,
+                    const std::vector<int32_t>& ib_base, int m, std::vector<int32_t> out[6]) {
+  for (int l = 0; l < 6; ++l) out[l].clear();
+  const int64_t n0 = P->n[0], n1 = P->n[1], n2 = P->d == 3 ? P->n[2] : 1;
+  const int C0 = r16_tile_lines(P, 0, elem);
+  const int64_t t0 = n1 * n2 / C0;  // x-line tiles: line j + n1 k, tile line / C0
+  std::vector<char> f0(t0, 0), i0(t0, 0);
+  for (int32_t q : near_pts) f0[(q / n0) / C0] = 1;
+  // lines read by the B+V gradient: the m x m (x m) block at each corner
+  std::vector<char> ibplane(n2, 0);
+  for (int32_t q : ib_base) {
+    const int64_t j0 = (q / n0) % n1, k0 = q / (n0 * n1);
+    const int kn = P->d == 3 ? m : 1;
+    for (int kk = 0; kk < kn; ++kk) {
+      ibplane[k0 + kk] = 1;
+      for (int jj = 0; jj < m; ++jj) i0[((j0 + jj) + n1 * (k0 + kk)) / C0] = 1;
+    }
+  }
+  for (int64_t t = 0; t < t0; ++t) {
+    if (f0[t]) out[TL_FWD0].push_back((int32_t)t);
+    out[i0[t] ? TL_INV0_IB : TL_INV0_REST].push_back((int32_t)t);
+    // the x-inverse runs in place on whole tiles, whose lines may reach into
+    // further planes (C0 > n1): those planes need their y-inverse first
+    if (i0[t])
+      for (int64_t l = t * C0; l < (t + 1) * C0; ++l) ibplane[l / n1] = 1;
+  }
+  if (P->d == 3) {
+    // y-line tiles: C1 adjacent x positions of one plane k, tile = k * tx + i / C1
+    const int C1 = r16_tile_lines(P, 1, elem);
+    const int64_t tx = n0 / C1;
+    std::vector<char> nearplane(n2, 0);
+    for (int32_t q : near_pts) nearplane[q / (n0 * n1)] = 1;
+    for (int64_t k = 0; k < n2; ++k)
+      for (int64_t t = k * tx; t < (k + 1) * tx; ++t) {
+        if (nearplane[k]) out[TL_FWD1].push_back((int32_t)t);
+        out[ibplane[k] ? TL_INV1_IB : TL_INV1_REST].push_back((int32_t)t);
+      }
+  }
+}
+
+namespace {
+
+template <typename TC>
+int solve_resident(const pc_plan* P, const AxisTables<TC>* tabs, const TC* b, TC* p,
+                   double* bmean, pc_workspace* W, hipStream_t s, double sigma,
+                   const int32_t* skip, int phase) {
+  if (!W || !W->resident) return fail(PC_ERR_INVALID_ARG, "resident solve without its workspace");
+  TC* w1 = reinterpret_cast<TC*>(W->phi);
+  TC* w1b = reinterpret_cast<TC*>(W->w1b);
+  auto tl = [&](int l) { return W->tl[l]; };
+  auto nt = [&](int l) { return W->ntl[l]; };
+  if (phase < 2) {
+    const bool later = phase == 1;
+    PC_TRY((launch_pass<TC, TC, TC, OP_FWD, LD_PLAIN, ST_PLAIN>(
+        P, 0, b, w1, tabs, nullptr, nullptr, nullptr, s, nullptr, sigma, skip,
+        later ? tl(TL_FWD0) : nullptr, later ? nt(TL_FWD0) : -1)));
+    const TC* last_in = w1;
+    if (P->d == 3) {
+      PC_TRY((launch_pass<TC, TC, TC, OP_FWD, LD_PLAIN, ST_PLAIN>(
+          P, 1, w1, w1b, tabs, nullptr, nullptr, nullptr, s, nullptr, 1.0, skip,
+          later ? tl(TL_FWD1) : nullptr, later ? nt(TL_FWD1) : -1)));
+      last_in = w1b;
+    }
+    PC_TRY((launch_pass<TC, TC, TC, OP_FDI, LD_PLAIN, ST_PLAIN>(
+        P, P->d - 1, last_in, p, tabs, nullptr, nullptr, bmean, s, nullptr, sigma, skip)));
+    if (P->d == 3)
+      PC_TRY((launch_pass<TC, TC, TC, OP_INV, LD_PLAIN, ST_PLAIN>(
+          P, 1, p, p, tabs, nullptr, nullptr, nullptr, s, nullptr, 1.0, skip, tl(TL_INV1_IB),
+          nt(TL_INV1_IB))));
+    PC_TRY((launch_pass<TC, TC, TC, OP_INV, LD_PLAIN, ST_PLAIN>(
+        P, 0, p, p, tabs, nullptr, nullptr, nullptr, s, nullptr, 1.0, skip, tl(TL_INV0_IB),
+        nt(TL_INV0_IB))));
+  } else {
+    if (P->d == 3)
+      PC_TRY((launch_pass<TC, TC, TC, OP_INV, LD_PLAIN, ST_PLAIN>(
+          P, 1, p, p, tabs, nullptr, nullptr, nullptr, s, nullptr, 1.0, skip, tl(TL_INV1_REST),
+          nt(TL_INV1_REST))));
+    PC_TRY((launch_pass<TC, TC, TC, OP_INV, LD_PLAIN, ST_PLAIN>(
+        P, 0, p, p, tabs, nullptr, nullptr, nullptr, s, nullptr, 1.0, skip, tl(TL_INV0_REST),
+        nt(TL_INV0_REST))));
+  }
+  return PC_OK;
+}
+
+}  // namespace
+
+int solve_resident_f64(const pc_plan* P, const double* b, double* p, double* bmean_dev,
+                       pc_workspace* ws, hipStream_t s, double sigma, const int32_t* skip,
+                       int phase) {
+  return solve_resident<double>(P, P->ax64, b, p, bmean_dev, ws, s, sigma, skip, phase);
+}
+
+int solve_resident_f32(const pc_plan* P, const float* b, float* p, double* bmean_dev,
+                       pc_workspace* ws, hipStream_t s, double sigma, const int32_t* skip,
+                       int phase) {
+  return solve_resident<float>(P, P->ax32, b, p, bmean_dev, ws, s, sigma, skip, phase);
 }
 
 }  // namespace pc

@@ -16,6 +16,8 @@
 #include <cmath>
 #include <cstring>
 
+#include <chrono>
+
 #include "pc_internal.h"
 
 namespace pc {
@@ -353,7 +355,8 @@ __global__ void __launch_bounds__(TPB) k_ib_step(const int32_t* __restrict__ ibb
     conv[1] += 1;
     *ticket = 0;
     if (host_flag) {
-      // pinned host memory, read by the host once this launch has completed
+      // coherent pinned host memory, polled by the host
+      __threadfence_system();
       *host_flag = cv;
       __threadfence_system();
     }
@@ -591,6 +594,27 @@ const T* ibc(const pc_geom* g) {
   if constexpr (sizeof(T) == 8) return g->ibcoef; else return g->ibcoef32;
 }
 
+// Waits until the device has stored a value other than -1 into the coherent
+// host flag *f.  The stream is not queried while the wait is short (a query
+// places a marker in the stream, which stalls the device); after two
+// seconds it is, so that a stream that drained without the store ends the
+// wait with an error instead of spinning forever.
+int wait_host_flag(volatile int32_t* f, hipStream_t s) {
+  auto t0 = std::chrono::steady_clock::now();
+  for (int64_t spin = 0;; ++spin) {
+    if (*f != -1) return PC_OK;
+    if ((spin & 4095) == 4095 &&
+        std::chrono::steady_clock::now() - t0 > std::chrono::seconds(2)) {
+      hipError_t e = hipStreamQuery(s);
+      if (e == hipSuccess) {
+        if (*f != -1) return PC_OK;
+        return fail(PC_ERR_HIP, "IB convergence flag not written by the device");
+      }
+      if (e != hipErrorNotReady) return fail(PC_ERR_HIP, hipGetErrorString(e));
+    }
+  }
+}
+
 // ---- the sub-step ---------------------------------------------------------------------
 template <typename T>
 int pressure_correct_t(const pc_geom* g, const pc_plan* P, int mode, const T* u, double dt,
@@ -601,6 +625,8 @@ int pressure_correct_t(const pc_geom* g, const pc_plan* P, int mode, const T* u,
   const int fixed_it = o ? o->fixed_it : 0;
   const int sweeps = o && o->sweeps > 0 ? o->sweeps : 2;
   const int gauge = o ? o->gauge : 0;
+  const bool resident = W->resident && !(o && (o->flags & PC_IB_FULL_TRANSFORMS)) &&
+                        mode != PC_MIXED;
   // the solve returns p = phi / sigma directly; the gradient of phi is
   // sigma * grad p
   const double sigma = 1.5 * dt;
@@ -612,10 +638,11 @@ int pressure_correct_t(const pc_geom* g, const pc_plan* P, int mode, const T* u,
   T* gradib = reinterpret_cast<T*>(W->gradib);
   const int64_t nib = g->n_ib;
 
+  // the long gather goes first so that the host queues the rest behind it
+  PC_TRY(launch_div_all<T>(g, gc<T>(g), u, b, s));
   hipLaunchKernelGGL(k_prologue<T>, dim3(std::max<unsigned>(1, nblk(nib))), dim3(TPB), 0, s, g->ib,
                      nib, g->d, u, g->M, uib, gib, (const T*)g_io, W->flag);
   PC_HIP_CHECK(hipGetLastError());
-  PC_TRY(launch_div_all<T>(g, gc<T>(g), u, b, s));
   if (g->n_near)
     hipLaunchKernelGGL(k_gather_near<T>, dim3(nblk(g->n_near)), dim3(TPB), 0, s, g->near, g->n_near,
                        (const T*)b, bnear);
@@ -626,7 +653,13 @@ int pressure_correct_t(const pc_geom* g, const pc_plan* P, int mode, const T* u,
   // an earlier iteration has converged.
   auto iteration = [&](int it, const int32_t* skip, int32_t* host_flag) -> int {
     if (it > 1 || g_io) PC_TRY(launch_div_near<T>(g, nci<T>(g), gib, bnear, b, false, s, skip));
-    if (mode == PC_F64)
+    if (resident && mode == PC_F64)
+      PC_TRY(solve_resident_f64(P, (const double*)b, (double*)p, W->scal, W, s, sigma, skip,
+                                it > 1 ? 1 : 0));
+    else if (resident)
+      PC_TRY(solve_resident_f32(P, (const float*)b, (float*)p, W->scal, W, s, sigma, skip,
+                                it > 1 ? 1 : 0));
+    else if (mode == PC_F64)
       PC_TRY(solve_f64(P, (const double*)b, (double*)p, W->scal, W, s, sigma, skip));
     else if (mode == PC_F32)
       PC_TRY(solve_f32(P, (const float*)b, (float*)p, W->scal, W, s, sigma, skip));
@@ -650,18 +683,18 @@ int pressure_correct_t(const pc_geom* g, const pc_plan* P, int mode, const T* u,
     // Enqueue one iteration ahead of the convergence test: while the host
     // waits for iteration i, the device already runs i+1 (which does nothing
     // if i converged), so the device does not idle on the host.  The IB
-    // kernel of iteration i writes its flag straight into pinned host slot
-    // i % 2; an event marks the iteration's completion.
+    // kernel of iteration i stores its flag (0/1) straight into coherent
+    // pinned host slot i % 2, which the host resets to -1 before queueing
+    // the iteration that reuses it.
     volatile int32_t* hf = W->hflag;
-    hf[0] = hf[1] = -1;
+    hf[1] = -1;
     PC_TRY(iteration(1, W->flag, W->hflag + 1));
-    PC_HIP_CHECK(hipEventRecord(W->ev[1], s));
     for (it = 1;; ++it) {
       if (it < max_it) {
+        hf[(it + 1) & 1] = -1;
         PC_TRY(iteration(it + 1, W->flag, W->hflag + ((it + 1) & 1)));
-        PC_HIP_CHECK(hipEventRecord(W->ev[(it + 1) & 1], s));
       }
-      PC_HIP_CHECK(hipEventSynchronize(W->ev[it & 1]));
+      PC_TRY(wait_host_flag(hf + (it & 1), s));
       if (hf[it & 1] == 1) {
         converged = true;
         break;
@@ -669,6 +702,12 @@ int pressure_correct_t(const pc_geom* g, const pc_plan* P, int mode, const T* u,
       if (it >= max_it) break;
     }
   }
+  // complete the inverse transforms of the last iteration on the lines the
+  // B+V gradient did not need
+  if (resident && mode == PC_F64)
+    PC_TRY(solve_resident_f64(P, (const double*)b, (double*)p, W->scal, W, s, sigma, nullptr, 2));
+  else if (resident)
+    PC_TRY(solve_resident_f32(P, (const float*)b, (float*)p, W->scal, W, s, sigma, nullptr, 2));
   PC_TRY((launch_grad_all<T, true>(g, nc<T>(g), p, (T)sigma, u, u_out, s)));
   PC_TRY(launch_zero_ib<T>(g, u_out, s));
   if (g_io && nib)

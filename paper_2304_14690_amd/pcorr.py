@@ -56,10 +56,13 @@ class WlsOpts(ctypes.Structure):
                 ("reserved", ctypes.c_int32)]
 
 
+PC_IB_FULL_TRANSFORMS = 1
+
+
 class IbOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_it", ctypes.c_int32),
                 ("fixed_it", ctypes.c_int32), ("sweeps", ctypes.c_int32),
-                ("gauge", ctypes.c_int32)]
+                ("gauge", ctypes.c_int32), ("flags", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -275,8 +278,9 @@ def pressure_correct(geom: Geometry, plan: Plan, mode: int, u: torch.Tensor, dt:
                      u_out: torch.Tensor, p: torch.Tensor, g: Optional[torch.Tensor] = None,
                      tol: float = 1e-3, max_it: int = 50, fixed_it: int = 0, sweeps: int = 2,
                      gauge: int = 0, ws: Optional[Workspace] = None, stream=None,
-                     want_stats: bool = True):
-    opts = IbOpts(tol, max_it, fixed_it, sweeps, gauge)
+                     want_stats: bool = True, full_transforms: bool = False):
+    opts = IbOpts(tol, max_it, fixed_it, sweeps, gauge,
+                  PC_IB_FULL_TRANSFORMS if full_transforms else 0)
     st = Stats()
     rc = _check(_lib.pc_pressure_correct(geom.h_, plan.h_, mode, _ptr(u), dt, _ptr(u_out),
                                          _ptr(p), _ptr(g), ctypes.byref(opts),
