@@ -45,6 +45,12 @@ def parse():
     ap.add_argument("--cpu-size", type=int, default=1024)
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain device copy of known size (counter scaling)")
+    ap.add_argument("--serve-seconds", type=float, default=3.0,
+                    help="length of the serving trace (0: no serving run)")
+    ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--serve-geoms", type=int, default=2,
+                    help="geometries per grid size in the serving pool")
+    ap.add_argument("--serve-only", action="store_true")
     return ap.parse_args()
 
 
@@ -83,6 +89,9 @@ def main():
     from paper_2304_14690_amd import inputs, pcorr as pc
 
     torch.cuda.init()
+    if args.serve_only:
+        print(json.dumps({"serving": serving(args)}))
+        return
     dev = torch.cuda.current_device()
     stream = torch.cuda.current_stream()
     N = args.size
@@ -191,6 +200,12 @@ def main():
         for _ in range(3):
             dst.copy_(src)
         torch.cuda.synchronize()
+        del src, dst
+
+    del geom, u64, b64, phi64, gr64
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    serving_out = serving(args) if args.serve_seconds > 0 else None
 
     # ---- CPU oracle on a bounded sample ----------------------------------------------
     cpu = None
@@ -223,6 +238,7 @@ def main():
                         for kk, vv in v.items()} for n, v in kern.items()},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "serving": serving_out,
         "device": torch.cuda.get_device_name(dev),
     }
     print(json.dumps(out))
@@ -238,6 +254,67 @@ def kernel_source_digest(name):
     parts = re.findall(r"template <[^\n]*>\n__global__[^\n]*\b" + name + r"\(.*?\n}\n", text, re.S)
     parts += re.findall(r"\nint launch_" + name[2:] + r"\(.*?\n}\n", text, re.S)
     return hashlib.sha256("".join(parts).encode()).hexdigest()[:16]
+
+
+def serving(args):
+    """The continuous-batching loop on a Poisson stream of mixed 2D/3D
+    requests (float64 and float32+float64-correction), against the float64
+    one-at-a-time path on the same arrivals and the same resident stencils."""
+    import torch
+    from paper_2304_14690_amd import pcorr as pc, serve
+    sizes = [(2, 128), (2, 512), (2, 2048), (3, 64), (3, 128), (3, 256)]
+    n_geom = {k: args.serve_geoms for k in sizes}
+    n_geom[(3, 256)] = min(args.serve_geoms, 4)
+    t0 = time.perf_counter()
+    ds = serve.Dataset(sizes, n_geom, 2, seed=9)
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
+    free, total = torch.cuda.mem_get_info()
+    budget = int(free - (16 << 30))
+    slots = 4
+    ex = serve.GpuExecutor(ds, slots=slots)
+    sch = serve.Scheduler(ex, budget=budget, slots=slots)
+    # warm-up (untimed): build every geometry's stencils and a workspace per mode
+    warm = [serve.Request(i, 0.0, d, N, g, 0, m)
+            for i, ((d, N, g), m) in enumerate((k, m) for k in ds.items
+                                               for m in (pc.PC_F64, pc.PC_MIXED))]
+    t0 = time.perf_counter()
+    sch.run(warm)
+    t_warm = time.perf_counter() - t0
+    n_req = int(round(args.serve_rate * args.serve_seconds))
+    trace = serve.poisson_trace(n_req, args.serve_rate, 9, sizes, n_geom, 2,
+                                [pc.PC_F64, pc.PC_MIXED])
+    mix = sch.run(trace)
+    s_mix = serve.summarize(mix)
+    s_mix["evictions"] = sch.evictions
+    s_mix["peak_gb"] = round(sch.peak_bytes / 2**30, 2)
+    s_mix["not_converged"] = sum(1 for r in mix if r.rc != 0)
+    base = [serve.Request(r.rid, r.arrival, r.d, r.N, r.geom, r.vel, pc.PC_F64) for r in trace]
+    out_f64 = sch.run(base)
+    s_f64 = serve.summarize(out_f64)
+    base = [serve.Request(r.rid, r.arrival, r.d, r.N, r.geom, r.vel, pc.PC_F64) for r in trace]
+    sch.slots = 1
+    out_base = sch.run(base)
+    s_base = serve.summarize(out_base)
+    sch.release()
+    del ex, sch, ds
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    per_size = {}
+    for (d, N) in sizes:
+        lat = [1e3 * r.latency for r in mix if (r.d, r.N) == (d, N)]
+        if lat:
+            per_size[f"{N}^{d}"] = {"n": len(lat), "p50_ms": float(np.percentile(lat, 50)),
+                                    "p99_ms": float(np.percentile(lat, 99))}
+    return {"workload": f"Poisson arrivals {args.serve_rate:g}/s for {args.serve_seconds:g} s, "
+                        "sizes uniform over 128^2, 512^2, 2048^2, 64^3, 128^3, 256^3, "
+                        "precision uniform over f64 and f32+f64 correction (2 sweeps), "
+                        f"{slots} slots, stencils resident per geometry (LRU under the HBM "
+                        "budget)",
+            "geometries": sum(n_geom.values()), "budget_gb": round(budget / 2**30, 1),
+            "setup_s": {"data": round(t_data, 2), "warm_build": round(t_warm, 2)},
+            "mix": s_mix, "fp64_batched": s_f64, "fp64_one_at_a_time": s_base,
+            "mix_per_size": per_size}
 
 
 def measured_traffic(kernel, G):

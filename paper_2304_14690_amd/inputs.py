@@ -146,18 +146,27 @@ def jittered_lattice(n: Sequence[int], h: Sequence[float], seed: int,
     return x
 
 
-def fourier_velocity(x: np.ndarray, n_modes: int, seed: int, kmax: int = 4,
-                     chunk: int = 1 << 20) -> np.ndarray:
-    """u*(x) = sum_m a_m cos(2 pi k_m . x + theta_m), k_m in {+-1..+-kmax}^d,
-    theta_m ~ U[0, 2pi), a_m ~ N(0, I_d).  x: [d, M].  Returns [d, M].
-    a_m is not orthogonal to k_m, so the field is divergent."""
-    d, M = x.shape
+def fourier_modes(d: int, n_modes: int, seed: int, kmax: int = 4):
+    """The random modes of the provisional velocity: wavenumbers k_m in
+    {+-1..+-kmax}^d (magnitudes, then signs), phases theta_m ~ U[0, 2pi),
+    amplitudes a_m ~ N(0, I_d), drawn in that order.  Returns (k [K, d],
+    theta [K], a [K, d])."""
     rng = np.random.Generator(np.random.PCG64(seed))
     kmag = rng.integers(1, kmax + 1, size=(n_modes, d))
     sgn = rng.choice(np.array([-1, 1]), size=(n_modes, d))
     kvec = (kmag * sgn).astype(np.float64)
     theta = rng.uniform(0.0, 2.0 * math.pi, size=n_modes)
     amp = rng.standard_normal(size=(n_modes, d))
+    return kvec, theta, amp
+
+
+def fourier_velocity(x: np.ndarray, n_modes: int, seed: int, kmax: int = 4,
+                     chunk: int = 1 << 20) -> np.ndarray:
+    """u*(x) = sum_m a_m cos(2 pi k_m . x + theta_m), k_m in {+-1..+-kmax}^d,
+    theta_m ~ U[0, 2pi), a_m ~ N(0, I_d).  x: [d, M].  Returns [d, M].
+    a_m is not orthogonal to k_m, so the field is divergent."""
+    d, M = x.shape
+    kvec, theta, amp = fourier_modes(d, n_modes, seed, kmax)
     u = np.zeros((d, M), dtype=np.float64)
     for s in range(0, M, chunk):
         e = min(M, s + chunk)
@@ -166,10 +175,29 @@ def fourier_velocity(x: np.ndarray, n_modes: int, seed: int, kmax: int = 4,
     return u
 
 
-def make_case(name: str, d: int, N: int, obstacles: Sequence[Obstacle], k_grid: int,
-              k_node: int, n_modes: int, seed_nodes: int, seed_vel: int,
-              jitter: float = 0.3, kmax: int = 4, dt: float = 1.0,
-              L: float = 1.0) -> Case:
+def fourier_velocity_torch(x, n_modes: int, seed: int, kmax: int = 4):
+    """The same field as fourier_velocity, evaluated with torch on x's device
+    (x: [d, M] float64 tensor): the same modes, summed mode by mode (the
+    rounding differs from fourier_velocity's matrix products)."""
+    import torch
+    d = x.shape[0]
+    kvec, theta, amp = fourier_modes(d, n_modes, seed, kmax)
+    u = torch.zeros_like(x)
+    for m in range(n_modes):
+        ph = x[0] * float(kvec[m, 0])
+        for a in range(1, d):
+            ph = ph + x[a] * float(kvec[m, a])
+        c = torch.cos(ph * (2.0 * math.pi) + float(theta[m]))
+        for a in range(d):
+            u[a].add_(c, alpha=float(amp[m, a]))
+    return u
+
+
+def make_geometry(d: int, N: int, obstacles: Sequence[Obstacle], seed_nodes: int,
+                  jitter: float = 0.3, L: float = 1.0):
+    """Node positions [d, M] and kinds [M] of a jittered lattice with the
+    obstacles' interior nodes turned virtual and their surface points
+    appended as boundary points."""
     n = tuple([N] * d)
     h = tuple([L / N] * d)
     lat = jittered_lattice(n, h, seed_nodes, jitter)
@@ -185,7 +213,14 @@ def make_case(name: str, d: int, N: int, obstacles: Sequence[Obstacle], k_grid: 
         kind = np.concatenate([kind, np.full(bpts.shape[0], KIND_B, np.uint8)])
     else:
         x = lat
-    x = np.ascontiguousarray(x)
+    return n, h, np.ascontiguousarray(x), kind
+
+
+def make_case(name: str, d: int, N: int, obstacles: Sequence[Obstacle], k_grid: int,
+              k_node: int, n_modes: int, seed_nodes: int, seed_vel: int,
+              jitter: float = 0.3, kmax: int = 4, dt: float = 1.0,
+              L: float = 1.0) -> Case:
+    n, h, x, kind = make_geometry(d, N, obstacles, seed_nodes, jitter, L)
     u = fourier_velocity(x, n_modes, seed_vel, kmax)
     u[:, kind == KIND_V] = 0.0
     return Case(name, d, n, h, x, kind, np.ascontiguousarray(u), dt, k_grid, k_node,
@@ -223,14 +258,22 @@ def config4(N: int = 512) -> Case:
                       Obstacle("box", (0.6, 0.4, 0.4), (0.8, 0.6, 0.6))], 27, 27, 64, 7, 8)
 
 
-def serving_case(d: int, N: int, seed: int, k: Optional[int] = None) -> Case:
-    """One request of the serving stream: its own node cloud, circle/sphere of
-    radius U(0.05, 0.15) centred in U(0.3, 0.7)^d, and a random-mode field."""
+def serving_geometry(d: int, N: int, seed: int):
+    """Geometry of one serving request family: a circle/sphere of radius
+    U(0.05, 0.15) centred in U(0.3, 0.7)^d over its own jittered cloud.
+    Returns (obstacles, node seed, velocity seed, k, modes)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     R = float(rng.uniform(0.05, 0.15))
     c = tuple(float(v) for v in rng.uniform(0.3, 0.7, size=d))
     s_nodes, s_vel = (int(v) for v in rng.integers(0, 2**31 - 1, size=2))
-    k = k if k is not None else (16 if d == 2 else 27)
+    k = 16 if d == 2 else 27
     shape = "circle" if d == 2 else "sphere"
-    return make_case(f"serve_{d}d_{N}_{seed}", d, N, [Obstacle(shape, c, (R,))], k, k,
-                     32 if d == 2 else 64, s_nodes, s_vel)
+    return [Obstacle(shape, c, (R,))], s_nodes, s_vel, k, (32 if d == 2 else 64)
+
+
+def serving_case(d: int, N: int, seed: int, k: Optional[int] = None) -> Case:
+    """One request of the serving stream: its own node cloud, circle/sphere of
+    radius U(0.05, 0.15) centred in U(0.3, 0.7)^d, and a random-mode field."""
+    obs, s_nodes, s_vel, k0, modes = serving_geometry(d, N, seed)
+    k = k if k is not None else k0
+    return make_case(f"serve_{d}d_{N}_{seed}", d, N, obs, k, k, modes, s_nodes, s_vel)
