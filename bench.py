@@ -1,28 +1,36 @@
 #!/usr/bin/env python3
 """Benchmark of the hybrid pressure-correction sub-step on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--size 2048]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload 2d2048]
 
-Workload (the 2D workload the throughput metric is quoted on): a 2048^2
-cell-centred pressure grid on the unit square, 4.2M jittered-lattice nodes
-(seeded jitter +-0.3h), a cylinder of radius 0.05 at (0.3, 0.5) whose
-interior lattice nodes are virtual points and whose surface carries the
-boundary points, 16-neighbour second-order WLS stencils with Gaussian
-weights, a random 32-mode velocity field, Neumann box.  The stencils are
-built once (timed separately, not part of a step); a step is one complete
-pressure-correction sub-step (RHS transfer, IB-force iterations of Poisson
-solve + gradient at the IB + force update, final gradient and projection)
-from a zero IB force, with all inputs resident in HBM.
+Workloads (all inputs seeded and synthetic, resident in HBM before timing):
+  2d2048  2048^2 cell-centred grid on the unit square, 4.2M jittered-lattice
+          nodes (jitter +-0.3h), a cylinder of radius 0.05 at (0.3, 0.5)
+          whose interior nodes are virtual points and whose surface carries
+          the boundary points, 16-neighbour WLS stencils, 32 random Fourier
+          modes, Neumann box.  The throughput metric is quoted on this one.
+  3d256   256^3 grid, 16.8M nodes, sphere of radius 0.1 at the centre,
+          27-neighbour stencils, 64 modes.
+  3d512   512^3 grid, 134M nodes, sphere of radius 0.1 at (0.3, 0.5, 0.5) plus
+          the box [0.6, 0.8] x [0.4, 0.6]^2, 27-neighbour stencils, 64 modes;
+          float32 transforms with 2 and 3 float64 defect-correction sweeps
+          against all-float64.
+The stencils are built once (timed separately, not part of a step).  A step
+is one complete pressure-correction sub-step (RHS transfer, IB-force
+iterations of Poisson solve + gradient at the IB + force update, final
+gradient and projection) from a zero IB force.
 
-One JSON line is printed: grid-points/s of the float64 sub-step, p50/p99
-step latency, the float32 and float32+float64-defect-correction variants,
-per-kernel HIP-event timings with the roofline of the dominant kernel, and
-the CPU oracle timed on this host on a bounded sample.
+One JSON line is printed: grid-points/s of the float64 sub-step, p50/p99 step
+latency, the other precisions with their error against float64, per-kernel
+HIP-event timings with the roofline of the dominant kernel, the serving loop
+(2d2048 only, unless --serve-seconds 0), and the CPU oracle timed on this
+host on a bounded sample.
 """
 from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import statistics
 import sys
@@ -32,17 +40,31 @@ import numpy as np
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 
+WORKLOADS = {
+    "2d2048": {"d": 2, "N": 2048, "modes": "f64,f32,mixed", "cpu_N": 1024,
+               "desc": "2D 2048^2 grid, {M} jittered nodes, cylinder r=0.05 at (0.3,0.5), "
+                       "16-NN WLS, 32-mode velocity, Neumann box, cold IB start"},
+    "3d256": {"d": 3, "N": 256, "modes": "f64,f32,mixed", "cpu_N": 64,
+              "desc": "3D 256^3 grid, {M} jittered nodes, sphere r=0.1 at the centre, 27-NN "
+                      "WLS, 64-mode velocity, Neumann box, cold IB start"},
+    "3d512": {"d": 3, "N": 512, "modes": "f64,mixed,mixed3", "cpu_N": 64,
+              "desc": "3D 512^3 grid, {M} jittered nodes, sphere r=0.1 at (0.3,0.5,0.5) plus "
+                      "box [0.6,0.8]x[0.4,0.6]^2, 27-NN WLS, 64-mode velocity, Neumann box, "
+                      "cold IB start"},
+}
+
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--size", type=int, default=2048)
-    ap.add_argument("--modes", default="f64,f32,mixed")
+    ap.add_argument("--workload", default="2d2048", choices=list(WORKLOADS))
+    ap.add_argument("--size", type=int, default=0, help="override N of the workload")
+    ap.add_argument("--modes", default="", help="comma list of f64, f32, mixed, mixed3")
     ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-size", type=int, default=1024)
+    ap.add_argument("--cpu-size", type=int, default=0)
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain device copy of known size (counter scaling)")
     ap.add_argument("--serve-seconds", type=float, default=3.0,
@@ -78,6 +100,36 @@ def bytes_grad_project(G, M, bn, d, s):
     return M * (bn * d * s + 4 + 2 * d * s) + G * s
 
 
+def make_workload(name, N):
+    """Seeded inputs of a workload: (Case-like dict) with x, kind on the host
+    and u on the device (2D: numpy velocity; 3D: the same modes evaluated
+    with torch on the device, much faster at 16.8M-134M nodes)."""
+    import torch
+    from paper_2304_14690_amd import inputs
+    if name == "2d2048":
+        c = inputs.config2(N)
+        return {"d": 2, "n": c.n, "h": c.h, "x": c.x, "kind": c.kind, "k": c.k_grid,
+                "u": torch.from_numpy(c.u).cuda()}
+    if name == "3d256":
+        obs, sn, sv = [inputs.Obstacle("sphere", (0.5, 0.5, 0.5), (0.1,))], 5, 6
+    else:
+        obs, sn, sv = [inputs.Obstacle("sphere", (0.3, 0.5, 0.5), (0.1,)),
+                       inputs.Obstacle("box", (0.6, 0.4, 0.4), (0.8, 0.6, 0.6))], 7, 8
+    n, h, x, kind = inputs.make_geometry(3, N, obs, sn)
+    xt = torch.from_numpy(x).cuda()
+    u = inputs.fourier_velocity_torch(xt, 64, sv)
+    u[:, torch.from_numpy(kind).cuda() == inputs.KIND_V] = 0.0
+    del xt
+    return {"d": 3, "n": n, "h": h, "x": x, "kind": kind, "k": 27, "u": u}
+
+
+def rel_l2(a, b):
+    import torch
+    a = a.double()
+    b = b.double()
+    return float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -86,62 +138,79 @@ def main():
                                    "design notes)", "n_gpus": args.gpus}))
         sys.exit(2)
     import torch
-    from paper_2304_14690_amd import inputs, pcorr as pc
+    from paper_2304_14690_amd import pcorr as pc
 
     torch.cuda.init()
     if args.serve_only:
         print(json.dumps({"serving": serving(args)}))
         return
+    wl = WORKLOADS[args.workload]
     dev = torch.cuda.current_device()
     stream = torch.cuda.current_stream()
-    N = args.size
+    N = args.size or wl["N"]
     t0 = time.perf_counter()
-    case = inputs.config2(N)
+    case = make_workload(args.workload, N)
+    torch.cuda.synchronize()
     t_gen = time.perf_counter() - t0
-    G, M, d = case.G, case.M, case.d
-    plan = pc.Plan(d, case.n, case.h)
-    x = torch.from_numpy(case.x).cuda()
-    kind = torch.from_numpy(case.kind).cuda()
+    d = case["d"]
+    G = int(np.prod(case["n"]))
+    M = int(case["kind"].size)
+    plan = pc.Plan(d, case["n"], case["h"])
+    x = torch.from_numpy(case["x"]).cuda()
+    kind = torch.from_numpy(case["kind"]).cuda()
+    case["x"] = None
+    modes = [m for m in (args.modes or wl["modes"]).split(",") if m]
+    want_f32 = "f32" in modes
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    geom = pc.wls_build(plan, x, kind, case.k_grid, case.k_node, want_f32=True)
+    geom = pc.wls_build(plan, x, kind, case["k"], case["k"], want_f32=want_f32)
     torch.cuda.synchronize()
     t_build = time.perf_counter() - t0
+    del x, kind
 
-    modes = [m for m in args.modes.split(",") if m]
     results = {}
+    ref = None
     for mname in modes:
-        mode = pc.MODES[mname]
+        mode = pc.MODES["mixed" if mname == "mixed3" else mname]
+        sweeps = 3 if mname == "mixed3" else 2
         dtype = torch.float32 if mode == pc.PC_F32 else torch.float64
-        u = torch.from_numpy(case.u).to(dtype).cuda()
+        u = case["u"].to(dtype)
         uo = torch.empty_like(u)
         p = torch.empty(G, dtype=dtype, device="cuda")
         ws = pc.Workspace(plan, geom, mode)
         stats = None
         for _ in range(args.warmup):
-            _, stats = pc.pressure_correct(geom, plan, mode, u, 1.0, uo, p, ws=ws)
+            _, stats = pc.pressure_correct(geom, plan, mode, u, 1.0, uo, p, ws=ws, sweeps=sweeps)
         torch.cuda.synchronize()
         lat = []
-        torch.cuda.synchronize()
         t_start = time.perf_counter()
         for _ in range(args.steps):
             ts = time.perf_counter()
-            _, stats = pc.pressure_correct(geom, plan, mode, u, 1.0, uo, p, ws=ws)
+            _, stats = pc.pressure_correct(geom, plan, mode, u, 1.0, uo, p, ws=ws, sweeps=sweeps)
             torch.cuda.synchronize()
             lat.append(time.perf_counter() - ts)
         torch.cuda.synchronize()
         total = time.perf_counter() - t_start
-        ms = 1e3 * total / args.steps
         lat_ms = sorted(1e3 * v for v in lat)
         results[mname] = {
             "value": G / (total / args.steps),
-            "ms_per_step": ms,
+            "ms_per_step": 1e3 * total / args.steps,
             "p50_ms": float(np.percentile(lat_ms, 50)),
             "p99_ms": float(np.percentile(lat_ms, 99)),
             "n_it": stats["n_it"],
             "converged": stats["converged"],
         }
-        del ws
+        if mname == "f64":
+            ref = (uo.clone(), p.clone(), stats["n_it"])
+        elif ref is not None:
+            # error against the float64 sub-step at the same iteration count
+            _, st2 = pc.pressure_correct(geom, plan, mode, u, 1.0, uo, p, ws=ws, sweeps=sweeps,
+                                         fixed_it=ref[2])
+            results[mname]["vs_f64"] = {"u": rel_l2(uo, ref[0]), "p": rel_l2(p, ref[1]),
+                                        "fixed_it": ref[2]}
+        del ws, u, uo, p
+    del ref
+
 
     # ---- per-kernel HIP-event timings (same kernels, same launch shapes) ----------
     def time_launches(fn, reps):
@@ -156,7 +225,7 @@ def main():
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / reps * 1e-3  # seconds per launch
 
-    u64 = torch.from_numpy(case.u).cuda()
+    u64 = case["u"]
     b64 = torch.empty(G, dtype=torch.float64, device="cuda")
     phi64 = torch.empty(G, dtype=torch.float64, device="cuda")
     gr64 = torch.empty((d, M), dtype=torch.float64, device="cuda")
@@ -169,12 +238,12 @@ def main():
     k, bn = geom.k_grid, geom.bn
     n_it = results.get("f64", {}).get("n_it", 1)
     # kernel: (device kernel, bytes per launch, seconds per launch, launches per step);
-    # the solve call is three kernels (rows forward, fused column pass, rows inverse)
+    # the solve call is 2d-1 kernels (forward passes, fused last-axis pass, inverse passes)
     kern = {
         "div_to_grid": {"kernel": f"k_div_all<double,{d},{k}>",
                         "bytes": bytes_div_all(G, M, k, d, 8), "s": t_div,
                         "launches_per_step": 1, "kernels_per_call": 1},
-        "poisson_fft_solve": {"kernel": "dct_r16 x3", "bytes": bytes_solve(G, d, 8),
+        "poisson_fft_solve": {"kernel": f"dct_r16 x{2 * d - 1}", "bytes": bytes_solve(G, d, 8),
                               "s": t_solve, "launches_per_step": n_it,
                               "kernels_per_call": 2 * d - 1},
         "grad_to_nodes": {"kernel": f"k_grad_all<double,{d},{bn}>",
@@ -190,7 +259,7 @@ def main():
     dom = max(single, key=lambda n: kern[n]["s"] * kern[n]["launches_per_step"])
     roof = {"bound": "hbm", "achieved": round(kern[dom]["GBs"], 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(kern[dom]["frac"], 4),
-            "traffic": measured_traffic(kern[dom]["kernel"], G),
+            "traffic": measured_traffic(kern[dom]["kernel"], args.workload, G),
             "kernel": kern[dom]["kernel"], "call": dom, "bytes_per_launch": kern[dom]["bytes"],
             "avg_launch_us": round(kern[dom]["us"], 2)}
 
@@ -202,19 +271,21 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    del geom, u64, b64, phi64, gr64
+    del geom, u64, b64, phi64, gr64, case
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
-    serving_out = serving(args) if args.serve_seconds > 0 else None
+    serving_out = None
+    if args.workload == "2d2048" and args.serve_seconds > 0:
+        serving_out = serving(args)
 
     # ---- CPU oracle on a bounded sample ----------------------------------------------
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(args.cpu_size)
+        cpu = cpu_baseline(args.workload, args.cpu_size or wl["cpu_N"])
 
     f64 = results.get("f64") or next(iter(results.values()))
     out = {
-        "metric": "pressure-correction grid-pts/s (float64 sub-step, 2048^2)",
+        "metric": f"pressure-correction grid-pts/s (float64 sub-step, {N}^{d})",
         "value": f64["value"],
         "unit": "grid-pts/s",
         "n_gpus": 1,
@@ -228,9 +299,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"2D {N}^2 grid, {M} jittered nodes, cylinder r=0.05 at "
-                               f"(0.3,0.5), 16-NN WLS, 32-mode velocity, Neumann box, "
-                               f"cold IB start", "G": G, "M": M, "k": k,
+        "config": {"workload": wl["desc"].format(M=M), "G": G, "M": M, "k": k,
                    "n_it": f64["n_it"], "build_s": round(t_build, 3),
                    "gen_s": round(t_gen, 3)},
         "modes": results,
@@ -245,14 +314,19 @@ def main():
 
 
 def kernel_source_digest(name):
-    """sha256 (16 hex digits) of a kernel's source text and of its launch
-    helper in csrc/pc_step.hip: a changed kernel invalidates old counters."""
+    """sha256 (16 hex digits) of a kernel's source text, its launch helper,
+    and the stencil builder whose layout decides its gather pattern: a
+    change to any of them invalidates old counters."""
     import hashlib
     import re
     root = os.path.dirname(os.path.abspath(__file__))
-    text = open(os.path.join(root, "paper_2304_14690_amd", "csrc", "pc_step.hip")).read()
-    parts = re.findall(r"template <[^\n]*>\n__global__[^\n]*\b" + name + r"\(.*?\n}\n", text, re.S)
-    parts += re.findall(r"\nint launch_" + name[2:] + r"\(.*?\n}\n", text, re.S)
+    csrc = os.path.join(root, "paper_2304_14690_amd", "csrc")
+    step = open(os.path.join(csrc, "pc_step.hip")).read()
+    wls = open(os.path.join(csrc, "pc_wls.hip")).read()
+    parts = re.findall(r"template <[^\n]*>\n__global__[^\n]*\b" + name + r"\(.*?\n}\n", step, re.S)
+    parts += re.findall(r"\nint launch_" + name[2:] + r"\(.*?\n}\n", step, re.S)
+    parts += re.findall(r"template <[^\n]*>\n__global__[^\n]*\bk_grid_stencils\(.*?\n}\n",
+                        wls, re.S)
     return hashlib.sha256("".join(parts).encode()).hexdigest()[:16]
 
 
@@ -317,13 +391,14 @@ def serving(args):
             "mix_per_size": per_size}
 
 
-def measured_traffic(kernel, G):
+def measured_traffic(kernel, workload, G):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy of known size),
-    or None when the summary is absent, was taken on another workload, or
-    the kernel source has changed since it was taken."""
+    summary of this workload (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy
+    of known size), or None when the summary is absent, was taken at another
+    size, or the kernel source has changed since it was taken."""
     root = os.path.dirname(os.path.abspath(__file__))
-    path = os.path.join(root, "profiles", "k_div_all_2048.traffic.txt")
+    name = kernel.split("<")[0]
+    path = os.path.join(root, "profiles", f"{name}_{workload}.traffic.txt")
     if not os.path.exists(path):
         return None
     vals = {}
@@ -331,22 +406,26 @@ def measured_traffic(kernel, G):
         if ":" in line and not line.startswith("#"):
             key, val = line.split(":", 1)
             vals[key.strip()] = val.strip()
-    digest = kernel_source_digest(kernel.split("<")[0])
-    if vals.get("kernel") != kernel.split("<")[0] or vals.get("source_sha256_16") != digest \
+    if vals.get("kernel") != name or vals.get("source_sha256_16") != kernel_source_digest(name) \
             or int(vals.get("G", -1)) != G:
         return None
     return float(vals["hbm_bytes_per_launch"])
 
 
-def cpu_baseline(N):
-    """The float64 oracle's sub-step on this host: the same workload at N^2
-    (same obstacle, stencil size and modes), stencils built first and not
+def cpu_baseline(workload, N):
+    """The float64 oracle's sub-step on this host: the same workload at N^d
+    (same obstacles, stencil size and modes), stencils built first and not
     timed, median of three timed sub-steps."""
     import oracle
     from oracle import projection as P
     from paper_2304_14690_amd import inputs
     cores = len(os.sched_getaffinity(0))
-    c = inputs.config2(N)
+    if workload == "2d2048":
+        c = inputs.config2(N)
+    elif workload == "3d256":
+        c = inputs.config3(N)
+    else:
+        c = inputs.config4(N)
     grid = oracle.Grid(c.d, c.n, c.h)
     t0 = time.perf_counter()
     st = P.build_stencils(grid, c.x.T.copy(), c.kind, c.k_grid, c.k_node, workers=cores)
@@ -361,7 +440,7 @@ def cpu_baseline(N):
         n_it = r["n_it"]
     t = statistics.median(times)
     return {"value": c.G / t, "unit": "grid-pts/s", "cores": cores, "kind": "oracle",
-            "sample": f"config-2 workload at {N}^2 ({c.M} nodes), float64 oracle sub-step, "
+            "sample": f"the same workload at {N}^{c.d} ({c.M} nodes), float64 oracle sub-step, "
                       f"median of 3, n_it={n_it}; stencil build {t_build:.1f}s not timed",
             "s_per_step": t}
 

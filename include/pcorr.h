@@ -200,7 +200,8 @@ int pc_geom_destroy(pc_geom* geom);
 int pc_geom_info(const pc_geom* geom, int64_t* counts6);
 
 /* Copies the stencils out (for inspection and tests).
- *   grid_idx_dev  int32   [k_grid][G]      node index, ascending (d^2, idx)
+ *   grid_idx_dev  int32   [k_grid][G]      node index, in ascending order
+ *                                          (the selection is by (d^2, idx))
  *   grid_coef_dev float64 [d][k_grid][G]   derivative coefficients
  *   node_base_dev int32   [M]              flat grid index of the block's
  *                                          low corner

@@ -346,8 +346,14 @@ __global__ void __launch_bounds__(64) k_grid_stencils(GridStencilArgs A) {
 #pragma unroll
   for (int j = 0; j < KMAX; ++j) {
     if (j < k) {
-      int pos = k - 1 - j;  // ascending key order
+      // stored in ascending node index: entry i then sits at nearly the same
+      // offset from the target in every lane, so the gathers of the
+      // transfer kernels stay close to contiguous
       int nid = li[j];
+      int pos = 0;
+#pragma unroll
+      for (int jj = 0; jj < KMAX; ++jj)
+        if (jj < k && li[jj] < nid) ++pos;
       double xi[3];
 #pragma unroll
       for (int a = 0; a < D; ++a) xi[a] = (A.xyz[a * A.M + nid] - xt[a]) / ht;
