@@ -74,6 +74,26 @@ def build_stencils(grid: Grid, x: np.ndarray, kind: np.ndarray, k_grid: int, k_n
     return Stencils(grid, gi, gcoef, ni, nbase, ncoef, ib, near, gs, ns)
 
 
+def sample_stencils(grid: Grid, x: np.ndarray, k_grid: int, k_node: int,
+                    grid_pts: np.ndarray, nodes: np.ndarray,
+                    eps: float = _wls.EPS_DEFAULT, support: float = _wls.SUPPORT_DEFAULT,
+                    delta: Optional[float] = None, workers: int = -1):
+    """The stencils of build_stencils for a subset of targets only: the
+    grid points `grid_pts` (flat indices) over all nodes x [M, d], and the
+    nodes `nodes` over the grid.  For checks at sizes where building every
+    stencil on the CPU is too slow.  Returns (grid_idx [S, k_g],
+    grid_coef [S, d, k_g], node_idx [T, k_n], node_coef [T, d, k_n])."""
+    delta = _wls.default_delta(grid.h) if delta is None else float(delta)
+    centres = grid.centres()
+    gc = centres[grid_pts]
+    gi, gd2 = _knn.knn(gc, x, k_grid, workers=workers)
+    gcoef, _, _ = _wls.derivative_coefficients(gc, x, gi, gd2, delta, eps, support)
+    xn = x[nodes]
+    ni, nd2, _ = _knn.knn_grid_window(xn, grid, k_node)
+    ncoef, _, _ = _wls.derivative_coefficients(xn, centres, ni, nd2, delta, eps, support)
+    return gi, gcoef, ni, ncoef
+
+
 def div_to_grid(st: Stencils, v: np.ndarray, rows: Optional[np.ndarray] = None,
                 chunk: int = 1 << 18) -> np.ndarray:
     """b_p = sum_a sum_i coef[p, a, i] v[idx[p, i], a] for the grid points

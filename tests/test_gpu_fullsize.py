@@ -1,0 +1,183 @@
+"""Parity at the full sizes the benchmark times: the 2048^2 workload (k = 16)
+and the 256^3 workload (k = 27), through pc_pressure_correct with its own
+workspace, as bench.py runs it.
+
+The oracle cannot build every stencil of these sizes within a test, so it is
+compared on outputs it computes one by one at sampled targets (random, next
+to the obstacle, on the box faces), and on properties that hold at any size:
+
+  * stencils: index sets and coefficients at sampled grid points and nodes;
+  * div_to_grid at sampled grid points = the oracle's rows applied to u*;
+  * the sub-step: u^{n+1} at sampled nodes = u* - grad phi with the oracle's
+    rows applied to the GPU's pressure; exactly 0 at every B/V node; the
+    final IB force at sampled B/V nodes = -u* + grad phi (Eq. 19);
+  * the Poisson equation of the final pressure over the whole grid, with the
+    right-hand side D(u* + g^{n-1}) of the last iteration, within a bound
+    from the operator's norm;
+  * the loop stops at the first iteration that meets the criterion;
+  * float32+float64 correction within 1e-10 and float32 within 5e-5 of the
+    float64 sub-step (which the oracle pins here and at smaller sizes).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import poisson, projection as P
+from paper_2304_14690_amd import inputs
+from tests.helpers import rel_l2
+
+pytestmark = pytest.mark.gpu
+
+SIGMA = 1.5  # phi = (3 dt / 2) p with dt = 1
+
+
+def _workload(name):
+    import torch
+    if name == "2d2048":
+        c = inputs.config2(2048)
+        return c.d, c.n, c.h, c.x, c.kind, c.k_grid, torch.from_numpy(c.u).cuda()
+    obs = [inputs.Obstacle("sphere", (0.5, 0.5, 0.5), (0.1,))]
+    n, h, x, kind = inputs.make_geometry(3, 256, obs, 5)
+    xt = torch.from_numpy(x).cuda()
+    u = inputs.fourier_velocity_torch(xt, 64, 6)
+    u[:, torch.from_numpy(kind).cuda() == inputs.KIND_V] = 0.0
+    return 3, n, h, x, kind, 27, u
+
+
+def _samples(rng, grid, x, ib, near, nsamp=500):
+    G, M, d = grid.G, x.shape[0], grid.d
+    gp = [rng.choice(G, nsamp, replace=False), rng.choice(near, min(nsamp, near.size),
+                                                           replace=False)]
+    # grid points on the box faces and corners
+    face = []
+    for a in range(d):
+        for side in (0, grid.n[a] - 1):
+            ci = rng.integers(0, np.array(grid.n), size=(40, d))
+            ci[:, a] = side
+            face.append(ci)
+    ci = np.concatenate(face + [np.zeros((1, d), np.int64),
+                                np.array([[v - 1 for v in grid.n]])])
+    stride = np.cumprod([1] + list(grid.n[:-1]))
+    gp.append(ci @ stride)
+    gp = np.unique(np.concatenate(gp)).astype(np.int64)
+    nd = [rng.choice(M, nsamp, replace=False), rng.choice(ib, min(nsamp, ib.size),
+                                                          replace=False)]
+    edge = np.flatnonzero((x < 1.5 * grid.h[0]).any(axis=1) |
+                          (x > 1.0 - 1.5 * grid.h[0]).any(axis=1))
+    nd.append(rng.choice(edge, min(300, edge.size), replace=False))
+    nd = np.unique(np.concatenate(nd)).astype(np.int64)
+    return gp, nd
+
+
+@pytest.mark.parametrize("name", ["2d2048", "3d256"])
+def test_full_size_sampled_parity(name):
+    import torch
+    from paper_2304_14690_amd import pcorr as pc
+    d, n, h, x, kind, k, u = _workload(name)
+    grid = oracle.Grid(d, n, h)
+    G, M = grid.G, kind.size
+    plan = pc.Plan(d, n, h)
+    geom = pc.wls_build(plan, torch.from_numpy(x).cuda(), torch.from_numpy(kind).cuda(), k, k,
+                        want_f32=True)
+    nib, nnear, bn = geom.n_ib, geom.n_near, geom.bn
+    gi = torch.empty((k, G), dtype=torch.int32, device="cuda")
+    gcf = torch.empty((d, k, G), dtype=torch.float64, device="cuda")
+    nb = torch.empty(M, dtype=torch.int32, device="cuda")
+    ncf = torch.empty((d, bn, M), dtype=torch.float64, device="cuda")
+    ibt = torch.empty(nib, dtype=torch.int32, device="cuda")
+    neart = torch.empty(nnear, dtype=torch.int32, device="cuda")
+    pc.geom_export(geom, gi, gcf, nb, ncf, ibt, neart)
+    torch.cuda.synchronize()
+    ib, near = ibt.cpu().numpy().astype(np.int64), neart.cpu().numpy().astype(np.int64)
+    assert np.array_equal(ib, np.flatnonzero(kind != inputs.KIND_F))
+
+    rng = np.random.Generator(np.random.PCG64(17))
+    xs = x.T.copy()
+    gp, nd = _samples(rng, grid, xs, ib, near)
+    ogi, ogc, oni, onc = P.sample_stencils(grid, xs, k, k, gp, nd)
+
+    # stencils at the sampled targets
+    gps = torch.from_numpy(gp).cuda()
+    g_idx = gi[:, gps].T.cpu().numpy()
+    g_cf = gcf[:, :, gps].permute(2, 0, 1).cpu().numpy()
+    order = np.argsort(ogi, axis=1, kind="stable")
+    np.testing.assert_array_equal(g_idx, np.take_along_axis(ogi, order, 1))
+    assert rel_l2(g_cf, np.take_along_axis(ogc, order[:, None, :], 2)) <= 1e-12
+    nds = torch.from_numpy(nd).cuda()
+    n_base = nb[nds].cpu().numpy().astype(np.int64)
+    n_cf = ncf[:, :, nds].cpu().numpy()                        # [d, bn, T]
+    m = round(bn ** (1.0 / d))
+    stride = np.array([1, n[0], n[0] * (n[1] if d == 3 else 1)])[:d]
+    rel = np.stack([(oni // stride[a]) % n[a] - ((n_base // stride[a]) % n[a])[:, None]
+                    for a in range(d)], -1)
+    assert rel.min() >= 0 and rel.max() < m
+    o = rel[..., 0] + m * rel[..., 1] + (m * m * rel[..., 2] if d == 3 else 0)
+    dense = np.zeros_like(n_cf)
+    cols = np.arange(nd.size)[:, None].repeat(o.shape[1], 1)
+    for a in range(d):
+        dense[a, o, cols] = onc[:, a, :]
+    assert rel_l2(n_cf, dense) <= 1e-12
+    del gi, gcf, ncf
+
+    # right-hand side at the sampled grid points
+    uh = u.cpu().numpy()
+    b = torch.empty(G, dtype=torch.float64, device="cuda")
+    pc.div_to_grid(geom, u, b)
+    b_s = np.einsum("tak,tka->t", ogc, uh.T[ogi])
+    assert rel_l2(b[gps].cpu().numpy(), b_s) <= 1e-11
+
+    # the sub-step as the benchmark runs it
+    ws = pc.Workspace(plan, geom, pc.PC_F64)
+    uo = torch.empty_like(u)
+    p = torch.empty(G, dtype=torch.float64, device="cuda")
+    g = torch.zeros((d, nib), dtype=torch.float64, device="cuda")
+    rc, st = pc.pressure_correct(geom, plan, pc.PC_F64, u, 1.0, uo, p, g=g, ws=ws)
+    torch.cuda.synchronize()
+    n_it = st["n_it"]
+    print(f"{name}: n_it {n_it}, num/den {st['ib_num'] / st['ib_den']:.3e}")
+    assert rc == 0 and st["converged"] == 1 and n_it >= 2
+    assert st["ib_num"] < 1e-3 * st["ib_den"]
+    ph = SIGMA * p.cpu().numpy()
+    uoh = uo.cpu().numpy()
+    gh = g.cpu().numpy()
+    assert np.all(uoh[:, ib] == 0.0)
+    grad_s = np.einsum("tak,tk->ta", onc, ph[oni])             # [T, d]
+    fl = kind[nd] == inputs.KIND_F
+    assert rel_l2(uoh[:, nd[fl]].T, uh[:, nd[fl]].T - grad_s[fl]) <= 1e-11
+    pos = np.searchsorted(ib, nd[~fl])
+    assert rel_l2(gh[:, pos].T, -uh[:, nd[~fl]].T + grad_s[~fl]) <= 1e-11
+
+    # one iteration fewer: not yet converged, and its force is the last RHS's
+    g1 = torch.zeros_like(g)
+    uo1 = torch.empty_like(u)
+    p1 = torch.empty_like(p)
+    _, st1 = pc.pressure_correct(geom, plan, pc.PC_F64, u, 1.0, uo1, p1, g=g1, ws=ws,
+                                 fixed_it=n_it - 1)
+    assert not (st1["ib_num"] < 1e-3 * st1["ib_den"])
+    v = u.clone()
+    v[:, ibt.long()] += g1
+    pc.div_to_grid(geom, v, b)
+    bh = b.cpu().numpy()
+    bc = bh - bh.mean()
+    r = SIGMA * poisson.laplacian(grid, p.cpu().numpy()) - bc
+    lnorm = sum(4.0 / (hh * hh) for hh in h)
+    bound = 16 * math.log2(G) * 2.2e-16 * lnorm * np.linalg.norm(ph) / np.linalg.norm(bc)
+    res = np.linalg.norm(r) / np.linalg.norm(bc)
+    print(f"{name}: Poisson residual {res:.2e} (bound {bound:.2e})")
+    assert res <= bound
+
+    # the other precisions against float64 at the same iteration count
+    for mode, dtype, tol in ((pc.PC_MIXED, torch.float64, 1e-10),
+                             (pc.PC_F32, torch.float32, 5e-5)):
+        wsm = pc.Workspace(plan, geom, mode)
+        um = u.to(dtype)
+        uom = torch.empty_like(um)
+        pm = torch.empty(G, dtype=dtype, device="cuda")
+        pc.pressure_correct(geom, plan, mode, um, 1.0, uom, pm, ws=wsm, fixed_it=n_it)
+        torch.cuda.synchronize()
+        eu, ep = rel_l2(uom.cpu().numpy(), uoh), rel_l2(pm.cpu().numpy(), ph / SIGMA)
+        print(f"{name}: mode {mode} vs f64: u {eu:.2e} p {ep:.2e}")
+        assert eu <= tol and ep <= tol
+        del wsm

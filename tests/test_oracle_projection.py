@@ -160,3 +160,20 @@ def test_near_list_and_split_rhs():
     np.testing.assert_allclose(r["b_last"], full, atol=1e-12 * np.abs(full).max())
     far = np.setdiff1d(np.arange(st.grid.G), st.near)
     assert np.all(P.div_to_grid(st, g)[far] == 0.0)
+
+
+def test_sample_stencils_equal_full_build():
+    """The subset builder gives exactly the rows of the full build."""
+    from paper_2304_14690_amd import inputs
+    c = inputs.config1()
+    grid = Grid(c.d, c.n, c.h)
+    x = c.x.T.copy()
+    st = P.build_stencils(grid, x, c.kind, c.k_grid, c.k_node)
+    rng = np.random.Generator(np.random.PCG64(3))
+    gp = rng.choice(grid.G, 50, replace=False)
+    nd = np.concatenate([rng.choice(c.M, 40, replace=False), st.ib[:10]])
+    gi, gcf, ni, ncf = P.sample_stencils(grid, x, c.k_grid, c.k_node, gp, nd)
+    np.testing.assert_array_equal(gi, st.grid_idx[gp])
+    np.testing.assert_array_equal(gcf, st.grid_coef[gp])
+    np.testing.assert_array_equal(ni, st.node_idx[nd])
+    np.testing.assert_array_equal(ncf, st.node_coef[nd])
