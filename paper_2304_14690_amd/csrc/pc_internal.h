@@ -92,8 +92,10 @@ struct pc_geom {
   float* gcoef32;  // [d][k_grid][G] or null
   // node stencils (block order)
   int32_t* nbase;   // [M]
-  double* ncoef;    // [d][bn][M]
-  float* ncoef32;   // [d][bn][M] or null
+  int64_t ms;       // stride of the node coefficient streams: M rounded up
+                    // to 64, so that every stream starts on a 512-byte line
+  double* ncoef;    // [d][bn][ms]
+  float* ncoef32;   // [d][bn][ms] or null
   // IB lists
   int32_t* ib;          // [n_ib] node index
   int32_t* near;        // [n_near] grid index

@@ -107,7 +107,7 @@ struct BlockOffsets {
 template <typename T, int D, int BN, bool LOCALREF, bool PROJECT>
 __global__ void __launch_bounds__(TPB) k_grad_all(const int32_t* __restrict__ nbase,
                                                   const T* __restrict__ ncoef, int64_t M,
-                                                  int bnrt, BlockOffsets bo,
+                                                  int64_t ms, int bnrt, BlockOffsets bo,
                                                   const T* __restrict__ phi, T scale,
                                                   const T* __restrict__ u,
                                                   T* __restrict__ out) {
@@ -124,7 +124,7 @@ __global__ void __launch_bounds__(TPB) k_grad_all(const int32_t* __restrict__ nb
     T f = phi[base + bo.off[o]];
     if (LOCALREF) f -= ref;
 #pragma unroll
-    for (int a = 0; a < D; ++a) acc[a] += ldnt(ncoef + ((int64_t)a * bn + o) * M + n) * f;
+    for (int a = 0; a < D; ++a) acc[a] += ldnt(ncoef + ((int64_t)a * bn + o) * ms + n) * f;
   }
 #pragma unroll
   for (int a = 0; a < D; ++a) {
@@ -487,10 +487,10 @@ int launch_grad_all(const pc_geom* g, const T* ncoef, const T* phi, T scale, con
   do {                                                                                       \
     if (lr)                                                                                  \
       hipLaunchKernelGGL((k_grad_all<T, D, BN, true, PROJECT>), grid, block, 0, s, g->nbase,  \
-                         ncoef, g->M, g->bn, bo, phi, scale, u, out);                        \
+                         ncoef, g->M, g->ms, g->bn, bo, phi, scale, u, out);                 \
     else                                                                                     \
       hipLaunchKernelGGL((k_grad_all<T, D, BN, false, PROJECT>), grid, block, 0, s, g->nbase, \
-                         ncoef, g->M, g->bn, bo, phi, scale, u, out);                        \
+                         ncoef, g->M, g->ms, g->bn, bo, phi, scale, u, out);                 \
   } while (0)
   if (g->d == 2) {
     if (g->bn == 16) GRL(2, 16);

@@ -382,7 +382,8 @@ struct NodeStencilArgs {
   int m, bn, k;
   double eps, hsup;
   int32_t* nbase;   // [M]
-  double* ncoef;    // [d][bn][M]
+  int64_t ms;       // coefficient stream stride (>= M)
+  double* ncoef;    // [d][bn][ms]
   float* ncoef32;
   int32_t* bad;
 };
@@ -476,7 +477,7 @@ __global__ void __launch_bounds__(64) k_node_stencils(NodeStencilArgs A) {
 #pragma unroll
   for (int a = 0; a < D; ++a) chol_unit_solve<MU>(Cm, 1 + a, y[a]);
   A.nbase[n] = (int32_t)flat0;
-  const int64_t M = A.M;
+  const int64_t ms = A.ms;
 #pragma unroll
   for (int o = 0; o < BNMAX; ++o) {
     if (o < bn) {
@@ -500,8 +501,8 @@ __global__ void __launch_bounds__(64) k_node_stencils(NodeStencilArgs A) {
       }
 #pragma unroll
       for (int a = 0; a < D; ++a) {
-        A.ncoef[((int64_t)a * bn + o) * M + n] = cv[a];
-        if (A.ncoef32) A.ncoef32[((int64_t)a * bn + o) * M + n] = (float)cv[a];
+        A.ncoef[((int64_t)a * bn + o) * ms + n] = cv[a];
+        if (A.ncoef32) A.ncoef32[((int64_t)a * bn + o) * ms + n] = (float)cv[a];
       }
     }
   }
@@ -554,14 +555,14 @@ __global__ void __launch_bounds__(256) k_near_fill(const int32_t* __restrict__ n
 template <typename T>
 __global__ void __launch_bounds__(256) k_ib_gather(const int32_t* __restrict__ ib, int64_t nib,
                                                    const int32_t* __restrict__ nbase,
-                                                   const T* __restrict__ ncoef, int64_t M,
+                                                   const T* __restrict__ ncoef, int64_t ms,
                                                    int rows, int32_t* __restrict__ ibbase,
                                                    T* __restrict__ ibcoef) {
   int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (s >= nib) return;
   int64_t nid = ib[s];
   if (ibbase) ibbase[s] = nbase[nid];
-  for (int r = 0; r < rows; ++r) ibcoef[(int64_t)r * nib + s] = ncoef[(int64_t)r * M + nid];
+  for (int r = 0; r < rows; ++r) ibcoef[(int64_t)r * nib + s] = ncoef[(int64_t)r * ms + nid];
 }
 
 int scan_exclusive(const int32_t* in, int64_t n, int32_t* out, hipStream_t s) {
@@ -694,9 +695,11 @@ int build(const pc_plan* P, const double* xyz, const uint8_t* kind, int64_t M,
 
   // node-target stencils
   PC_TRY(dev_alloc((void**)&g->nbase, (size_t)M * 4, "node stencil bases"));
-  PC_TRY(dev_alloc((void**)&g->ncoef, (size_t)d * bn * M * 8, "node stencil coefficients"));
-  if (want32) PC_TRY(dev_alloc((void**)&g->ncoef32, (size_t)d * bn * M * 4, "node stencil f32"));
-  NodeStencilArgs na{xyz, M, gd, m, bn, k_node, eps, support * delta, g->nbase, g->ncoef,
+  g->ms = (M + 63) / 64 * 64;
+  PC_TRY(dev_alloc((void**)&g->ncoef, (size_t)d * bn * g->ms * 8, "node stencil coefficients"));
+  if (want32)
+    PC_TRY(dev_alloc((void**)&g->ncoef32, (size_t)d * bn * g->ms * 4, "node stencil f32"));
+  NodeStencilArgs na{xyz, M, gd, m, bn, k_node, eps, support * delta, g->nbase, g->ms, g->ncoef,
                      g->ncoef32, bad};
   if (d == 2)
     hipLaunchKernelGGL(k_node_stencils<2>, dim3(nblocks(M, 64)), dim3(64), 0, s, na);
@@ -772,21 +775,22 @@ int build(const pc_plan* P, const double* xyz, const uint8_t* kind, int64_t M,
     PC_TRY(dev_alloc((void**)&g->ibbase, (size_t)g->n_ib * 4, "IB bases"));
     PC_TRY(dev_alloc((void**)&g->ibcoef, (size_t)d * bn * g->n_ib * 8, "IB coefs"));
     hipLaunchKernelGGL(k_ib_gather<double>, dim3(nblocks(g->n_ib, 256)), dim3(256), 0, s, g->ib,
-                       g->n_ib, g->nbase, g->ncoef, M, d * bn, g->ibbase, g->ibcoef);
+                       g->n_ib, g->nbase, g->ncoef, g->ms, d * bn, g->ibbase, g->ibcoef);
     if (want32) {
       PC_TRY(dev_alloc((void**)&g->ibcoef32, (size_t)d * bn * g->n_ib * 4, "IB coefs"));
       hipLaunchKernelGGL(k_ib_gather<float>, dim3(nblocks(g->n_ib, 256)), dim3(256), 0, s, g->ib,
-                         g->n_ib, g->nbase, g->ncoef32, M, d * bn, (int32_t*)nullptr, g->ibcoef32);
+                         g->n_ib, g->nbase, g->ncoef32, g->ms, d * bn, (int32_t*)nullptr,
+                         g->ibcoef32);
     }
     PC_HIP_CHECK(hipGetLastError());
   }
   PC_HIP_CHECK(hipStreamSynchronize(s));
   const int64_t ell = (int64_t)g->near_w * g->n_near;
   int64_t bytes = (int64_t)k_grid * G * 4 + (int64_t)d * k_grid * G * 8 + M * 4 +
-                  (int64_t)d * bn * M * 8 + g->n_ib * 4 + g->n_near * 4 + ell * (4 + 8 * d) +
+                  (int64_t)d * bn * g->ms * 8 + g->n_ib * 4 + g->n_near * 4 + ell * (4 + 8 * d) +
                   g->n_ib * (4 + 8 * (int64_t)d * bn);
   if (want32)
-    bytes += (int64_t)d * k_grid * G * 4 + (int64_t)d * bn * M * 4 + ell * 4 * d +
+    bytes += (int64_t)d * k_grid * G * 4 + (int64_t)d * bn * g->ms * 4 + ell * 4 * d +
              g->n_ib * 4 * (int64_t)d * bn;
   g->bytes = bytes;
   return PC_OK;
@@ -857,7 +861,10 @@ int pc_geom_export(const pc_geom* g, int32_t* gidx, double* gcoef, int32_t* nbas
   PC_TRY(cp(gidx, g->gidx, (size_t)g->k_grid * g->G * 4));
   PC_TRY(cp(gcoef, g->gcoef, (size_t)g->d * g->k_grid * g->G * 8));
   PC_TRY(cp(nbase, g->nbase, (size_t)g->M * 4));
-  PC_TRY(cp(ncoef, g->ncoef, (size_t)g->d * g->bn * g->M * 8));
+  if (ncoef && g->M)
+    PC_HIP_CHECK(hipMemcpy2DAsync(ncoef, (size_t)g->M * 8, g->ncoef, (size_t)g->ms * 8,
+                                  (size_t)g->M * 8, (size_t)g->d * g->bn,
+                                  hipMemcpyDeviceToDevice, s));
   PC_TRY(cp(ib, g->ib, (size_t)g->n_ib * 4));
   PC_TRY(cp(near, g->near, (size_t)g->n_near * 4));
   return PC_OK;
