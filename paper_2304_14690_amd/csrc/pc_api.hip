@@ -87,7 +87,8 @@ void set_axis_ptrs(AxisTables<T>& A, T* base, int N) {
 // the IB update.
 int64_t partial_doubles(const pc_geom* g) {
   int64_t n = 1024;
-  if (g) n = std::max<int64_t>(n, 2 * ((g->n_ib + 255) / 256));
+  // two partial sums per block of the IB iteration kernel (64 threads)
+  if (g) n = std::max<int64_t>(n, 2 * ((g->n_ib + 63) / 64));
   return n;
 }
 

@@ -100,15 +100,18 @@ struct pc_geom {
   int32_t* ib;          // [n_ib] node index
   int32_t* near;        // [n_near] grid index
   // near-IB stencils restricted to their B+V entries, ELL layout of width
-  // near_w: entry e of near point q at e*n_near + q (slot -1 / coefficient 0
-  // past the point's last entry)
+  // near_w (8, 16 or 32, at least the most B+V entries of any near point):
+  // entry e of near point q at e*nns + q, slot -1 / coefficient 0 past the
+  // point's last entry; nns = n_near rounded up to 64
   int near_w;
-  int32_t* nslot;       // [near_w][n_near] ib slot
-  double* ncoefib;      // [d][near_w][n_near]
+  int64_t nns;
+  int32_t* nslot;       // [near_w][nns] ib slot
+  double* ncoefib;      // [d][near_w][nns]
   float* ncoefib32;
-  // compact node stencils of the B+V nodes
+  // compact node stencils of the B+V nodes; ibs = n_ib rounded up to 64
+  int64_t ibs;
   int32_t* ibbase;      // [n_ib]
-  double* ibcoef;       // [d][bn][n_ib]
+  double* ibcoef;       // [d][bn][ibs]
   float* ibcoef32;
   int64_t bytes;
   pc_workspace* own_ws;

@@ -36,6 +36,7 @@ __device__ __forceinline__ T ldnt(const T* p) {
 }
 
 constexpr int TPB = 256;
+constexpr int IBT = 64;  // threads per block of the IB iteration kernel (one wavefront)
 
 // ---- div_to_grid (all grid points) -------------------------------------------
 template <typename T, int D, int K, bool LOCALREF>
@@ -70,9 +71,9 @@ __global__ void __launch_bounds__(TPB) k_div_all(const int32_t* __restrict__ gid
 // ---- div_to_grid near the IB: b[near[q]] = base[q] (or b) + D(g) -----------
 // g lives on the B+V nodes only, so each near point sums over its B+V
 // entries (ELL layout, coalesced over q).
-template <typename T, int D, bool ADD>
+template <typename T, int D, bool ADD, int WT>
 __global__ void __launch_bounds__(TPB) k_div_near(const int32_t* __restrict__ near, int64_t nnear,
-                                                  int W, const int32_t* __restrict__ nslot,
+                                                  int64_t nns, const int32_t* __restrict__ nslot,
                                                   const T* __restrict__ ncoef,
                                                   const T* __restrict__ gib, int64_t nib,
                                                   const T* __restrict__ base, T* __restrict__ b,
@@ -80,17 +81,17 @@ __global__ void __launch_bounds__(TPB) k_div_near(const int32_t* __restrict__ ne
   if (skip && *skip) return;
   int64_t q = (int64_t)blockIdx.x * TPB + threadIdx.x;
   if (q >= nnear) return;
+  // WT is the table width itself (padding entries have slot -1 and
+  // coefficient exactly 0), so every load is unconditional and all of them
+  // are in flight together
+  int s[WT];
+#pragma unroll
+  for (int e = 0; e < WT; ++e) s[e] = max(nslot[(int64_t)e * nns + q], 0);
   T acc = T(0);
-  // fully unrolled over the widest possible stencil so that the loads of all
-  // entries are in flight together
 #pragma unroll
-  for (int e = 0; e < PC_MAX_K_GRID; ++e) {
-    if (e < W) {
-      // padding entries have slot -1 and coefficient exactly 0
-      const int s = max(nslot[(int64_t)e * nnear + q], 0);
+  for (int e = 0; e < WT; ++e) {
 #pragma unroll
-      for (int a = 0; a < D; ++a) acc += ncoef[((int64_t)a * W + e) * nnear + q] * gib[a * nib + s];
-    }
+    for (int a = 0; a < D; ++a) acc += ncoef[((int64_t)a * WT + e) * nns + q] * gib[a * nib + s[e]];
   }
   int64_t p = near[q];
   if (ADD)
@@ -138,7 +139,8 @@ __global__ void __launch_bounds__(TPB) k_grad_all(const int32_t* __restrict__ nb
 // ---- grad at the B+V nodes (compact stencils) ---------------------------------
 template <typename T, int D, bool LOCALREF>
 __global__ void __launch_bounds__(TPB) k_grad_ib(const int32_t* __restrict__ ibbase,
-                                                 const T* __restrict__ ibcoef, int64_t nib, int bn,
+                                                 const T* __restrict__ ibcoef, int64_t nib,
+                                                 int64_t ibs, int bn,
                                                  BlockOffsets bo, const T* __restrict__ phi,
                                                  T scale, T* __restrict__ out,
                                                  const int32_t* __restrict__ skip) {
@@ -154,7 +156,7 @@ __global__ void __launch_bounds__(TPB) k_grad_ib(const int32_t* __restrict__ ibb
     T f = phi[base + bo.off[o]];
     if (LOCALREF) f -= ref;
 #pragma unroll
-    for (int a = 0; a < D; ++a) acc[a] += ibcoef[((int64_t)a * bn + o) * nib + s] * f;
+    for (int a = 0; a < D; ++a) acc[a] += ibcoef[((int64_t)a * bn + o) * ibs + s] * f;
   }
 #pragma unroll
   for (int a = 0; a < D; ++a) out[a * nib + s] = scale * acc[a];
@@ -261,27 +263,22 @@ __global__ void __launch_bounds__(TPB) k_ib_finish(const double* __restrict__ pa
 }
 
 // ---- fused IB step: gradient at the B+V nodes, force update, criterion ----------
-// One launch per IB iteration: every thread takes one B+V node, computes
-// grad phi there (sigma * grad p), g_new = -u* + grad, the two criterion
-// terms, and overwrites g.  Block partial sums go to part[]; the last block
-// to finish (ticket counter) adds them in block order, so the sums do not
-// depend on scheduling, sets the converged flag and counts the iteration.
+// Every thread takes one B+V node, computes grad phi there (sigma * grad p),
+// g_new = -u* + grad and the two criterion terms, and overwrites g.  Each
+// block (one wavefront) writes its partial sums to part[]; k_ib_close adds
+// them.  (A last-block-finishes scheme needs a device-scope fence and an
+// atomic per block, which cost more than a second launch here.)
 template <typename T, int D, int BN>
-__global__ void __launch_bounds__(TPB) k_ib_step(const int32_t* __restrict__ ibbase,
-                                                 const T* __restrict__ ibcoef, int64_t nib, int bnrt,
+__global__ void __launch_bounds__(IBT) k_ib_step(const int32_t* __restrict__ ibbase,
+                                                 const T* __restrict__ ibcoef, int64_t nib,
+                                                 int64_t ibs, int bnrt,
                                                  BlockOffsets bo, const T* __restrict__ phi,
                                                  T scale, const T* __restrict__ uib,
                                                  T* __restrict__ g, double* __restrict__ part,
-                                                 int32_t* __restrict__ ticket, double tol,
-                                                 double* __restrict__ sums,
-                                                 int32_t* __restrict__ conv,
-                                                 const int32_t* __restrict__ skip,
-                                                 int32_t* host_flag) {
-  __shared__ double rn[TPB], rd[TPB];
-  __shared__ int is_last;
+                                                 const int32_t* __restrict__ skip) {
   if (skip && *skip) return;
   const int bn = BN > 0 ? BN : bnrt;
-  const int64_t s = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  const int64_t s = (int64_t)blockIdx.x * IBT + threadIdx.x;
   double num = 0.0, den = 0.0;
   if (s < nib) {
     const int64_t base = ibbase[s];
@@ -296,7 +293,7 @@ __global__ void __launch_bounds__(TPB) k_ib_step(const int32_t* __restrict__ ibb
         T f = phi[base + bo.off[o]];
         if (lr) f -= ref;
 #pragma unroll
-        for (int a = 0; a < D; ++a) acc[a] += ibcoef[((int64_t)a * bn + o) * nib + s] * f;
+        for (int a = 0; a < D; ++a) acc[a] += ibcoef[((int64_t)a * bn + o) * ibs + s] * f;
       }
     }
     double mn = 0.0, mo = 0.0;
@@ -312,48 +309,58 @@ __global__ void __launch_bounds__(TPB) k_ib_step(const int32_t* __restrict__ ibb
     num = dm * dm;
     den = mo;
   }
-  rn[threadIdx.x] = num;
-  rd[threadIdx.x] = den;
-  __syncthreads();
-  for (int w = TPB / 2; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) {
-      rn[threadIdx.x] += rn[threadIdx.x + w];
-      rd[threadIdx.x] += rd[threadIdx.x + w];
-    }
-    __syncthreads();
+  // one wavefront per block: reduce in a fixed order (the result does not
+  // depend on scheduling)
+#pragma unroll
+  for (int off = IBT / 2; off > 0; off >>= 1) {
+    num += __shfl_down(num, off, IBT);
+    den += __shfl_down(den, off, IBT);
   }
   if (threadIdx.x == 0) {
-    part[2 * blockIdx.x] = rn[0];
-    part[2 * blockIdx.x + 1] = rd[0];
-    __threadfence();
-    is_last = atomicAdd(ticket, 1) == (int)gridDim.x - 1;
+    part[2 * blockIdx.x] = num;
+    part[2 * blockIdx.x + 1] = den;
+  }
+}
+
+// Criterion of the IB iteration (Sec. 2.3) from k_ib_step's block partial
+// sums, added in block order: sums[0..1], the converged flag conv[0], the
+// iteration count conv[1], and (if given) the flag in coherent pinned host
+// memory that the host polls.
+__global__ void __launch_bounds__(TPB) k_ib_close(const double* __restrict__ part, int nblk,
+                                                  double tol, double* __restrict__ sums,
+                                                  int32_t* __restrict__ conv,
+                                                  const int32_t* __restrict__ skip,
+                                                  int32_t* host_flag) {
+  __shared__ double rn[TPB / 64], rd[TPB / 64];
+  if (skip && *skip) return;
+  double num = 0.0, den = 0.0;
+  for (int i = threadIdx.x; i < nblk; i += TPB) {
+    num += part[2 * i];
+    den += part[2 * i + 1];
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    num += __shfl_down(num, off, 64);
+    den += __shfl_down(den, off, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    rn[threadIdx.x >> 6] = num;
+    rd[threadIdx.x >> 6] = den;
   }
   __syncthreads();
-  if (!is_last) return;
-  __threadfence();
-  num = 0.0;
-  den = 0.0;
-  for (int i = threadIdx.x; i < (int)gridDim.x; i += TPB) {
-    num += __builtin_nontemporal_load(part + 2 * i);
-    den += __builtin_nontemporal_load(part + 2 * i + 1);
-  }
-  rn[threadIdx.x] = num;
-  rd[threadIdx.x] = den;
-  __syncthreads();
-  for (int w = TPB / 2; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) {
-      rn[threadIdx.x] += rn[threadIdx.x + w];
-      rd[threadIdx.x] += rd[threadIdx.x + w];
-    }
-    __syncthreads();
-  }
   if (threadIdx.x == 0) {
-    sums[0] = rn[0];
-    sums[1] = rd[0];
-    const int32_t cv = (rn[0] < tol * rd[0] || rn[0] == 0.0) ? 1 : 0;
+    num = rn[0];
+    den = rd[0];
+#pragma unroll
+    for (int w = 1; w < TPB / 64; ++w) {
+      num += rn[w];
+      den += rd[w];
+    }
+    sums[0] = num;
+    sums[1] = den;
+    const int32_t cv = (num < tol * den || num == 0.0) ? 1 : 0;
     conv[0] = cv;
     conv[1] += 1;
-    *ticket = 0;
     if (host_flag) {
       // coherent pinned host memory, polled by the host
       __threadfence_system();
@@ -464,14 +471,23 @@ int launch_div_near(const pc_geom* g, const T* ncoefib, const T* gib, const T* b
                     bool add, hipStream_t s, const int32_t* skip = nullptr) {
   if (g->n_near == 0) return PC_OK;
   dim3 grid(nblk(g->n_near)), block(TPB);
-#define DNL(D, ADD)                                                                          \
-  hipLaunchKernelGGL((k_div_near<T, D, ADD>), grid, block, 0, s, g->near, g->n_near, g->near_w, \
+#define DNL(D, ADD, WT)                                                                        \
+  hipLaunchKernelGGL((k_div_near<T, D, ADD, WT>), grid, block, 0, s, g->near, g->n_near, g->nns, \
                      g->nslot, ncoefib, gib, g->n_ib, base, b, skip)
+#define DNW(D, ADD)                                 \
+  do {                                              \
+    if (g->near_w == 8) DNL(D, ADD, 8);             \
+    else if (g->near_w == 16) DNL(D, ADD, 16);      \
+    else DNL(D, ADD, 32);                           \
+  } while (0)
+  if (g->near_w != 8 && g->near_w != 16 && g->near_w != 32)
+    return fail(PC_ERR_INVALID_ARG, "near-IB table width");
   if (g->d == 2) {
-    if (add) DNL(2, true); else DNL(2, false);
+    if (add) DNW(2, true); else DNW(2, false);
   } else {
-    if (add) DNL(3, true); else DNL(3, false);
+    if (add) DNW(3, true); else DNW(3, false);
   }
+#undef DNW
 #undef DNL
   PC_HIP_CHECK(hipGetLastError());
   return PC_OK;
@@ -514,17 +530,17 @@ int launch_grad_ib(const pc_geom* g, const T* ibcoef, const T* phi, T scale, T* 
   if (g->d == 2) {
     if (lr)
       hipLaunchKernelGGL((k_grad_ib<T, 2, true>), grid, block, 0, s, g->ibbase, ibcoef, g->n_ib,
-                         g->bn, bo, phi, scale, out, skip);
+                         g->ibs, g->bn, bo, phi, scale, out, skip);
     else
       hipLaunchKernelGGL((k_grad_ib<T, 2, false>), grid, block, 0, s, g->ibbase, ibcoef, g->n_ib,
-                         g->bn, bo, phi, scale, out, skip);
+                         g->ibs, g->bn, bo, phi, scale, out, skip);
   } else {
     if (lr)
       hipLaunchKernelGGL((k_grad_ib<T, 3, true>), grid, block, 0, s, g->ibbase, ibcoef, g->n_ib,
-                         g->bn, bo, phi, scale, out, skip);
+                         g->ibs, g->bn, bo, phi, scale, out, skip);
     else
       hipLaunchKernelGGL((k_grad_ib<T, 3, false>), grid, block, 0, s, g->ibbase, ibcoef, g->n_ib,
-                         g->bn, bo, phi, scale, out, skip);
+                         g->ibs, g->bn, bo, phi, scale, out, skip);
   }
   PC_HIP_CHECK(hipGetLastError());
   return PC_OK;
@@ -553,17 +569,19 @@ int launch_ib_step(const pc_geom* g, const T* ibcoef, const T* phi, T scale, con
                    const int32_t* skip, int32_t* host_flag) {
   if (g->n_ib == 0) return PC_OK;
   BlockOffsets bo = block_offsets(g);
-  dim3 grid(nblk(g->n_ib)), block(TPB);
-  // flag[0]: converged, flag[1]: iterations, flag[2]: ticket counter
+  dim3 grid((unsigned)((g->n_ib + IBT - 1) / IBT)), block(IBT);
+  // flag[0]: converged, flag[1]: iterations
 #define IBS(D, BN)                                                                              \
-  hipLaunchKernelGGL((k_ib_step<T, D, BN>), grid, block, 0, s, g->ibbase, ibcoef, g->n_ib, g->bn, \
-                     bo, phi, scale, uib, gib, part, flag + 2, tol, sums, flag, skip, host_flag)
+  hipLaunchKernelGGL((k_ib_step<T, D, BN>), grid, block, 0, s, g->ibbase, ibcoef, g->n_ib, g->ibs, \
+                     g->bn, bo, phi, scale, uib, gib, part, skip)
   if (g->d == 2) {
     if (g->bn == 16) IBS(2, 16); else IBS(2, 0);
   } else {
     if (g->bn == 27) IBS(3, 27); else IBS(3, 0);
   }
 #undef IBS
+  hipLaunchKernelGGL(k_ib_close, dim3(1), dim3(TPB), 0, s, (const double*)part, (int)grid.x, tol,
+                     sums, flag, skip, host_flag);
   PC_HIP_CHECK(hipGetLastError());
   return PC_OK;
 }

@@ -527,7 +527,8 @@ __global__ void __launch_bounds__(256) k_slot_map(const int32_t* __restrict__ ib
 
 template <typename T>
 __global__ void __launch_bounds__(256) k_near_fill(const int32_t* __restrict__ near, int64_t nnear,
-                                                   int W, const int32_t* __restrict__ gidx,
+                                                   int64_t nns, int W,
+                                                   const int32_t* __restrict__ gidx,
                                                    const T* __restrict__ gcoef, int64_t G, int k,
                                                    int d, const int32_t* __restrict__ slot,
                                                    int32_t* __restrict__ nslot,
@@ -540,15 +541,15 @@ __global__ void __launch_bounds__(256) k_near_fill(const int32_t* __restrict__ n
     int nid = gidx[(int64_t)i * G + p];
     int s = slot[nid];
     if (s >= 0 && e < W) {
-      nslot[(int64_t)e * nnear + q] = s;
+      nslot[(int64_t)e * nns + q] = s;
       for (int a = 0; a < d; ++a)
-        ncoefib[((int64_t)a * W + e) * nnear + q] = gcoef[((int64_t)a * k + i) * G + p];
+        ncoefib[((int64_t)a * W + e) * nns + q] = gcoef[((int64_t)a * k + i) * G + p];
       ++e;
     }
   }
   for (; e < W; ++e) {
-    nslot[(int64_t)e * nnear + q] = -1;
-    for (int a = 0; a < d; ++a) ncoefib[((int64_t)a * W + e) * nnear + q] = T(0);
+    nslot[(int64_t)e * nns + q] = -1;
+    for (int a = 0; a < d; ++a) ncoefib[((int64_t)a * W + e) * nns + q] = T(0);
   }
 }
 
@@ -556,13 +557,14 @@ template <typename T>
 __global__ void __launch_bounds__(256) k_ib_gather(const int32_t* __restrict__ ib, int64_t nib,
                                                    const int32_t* __restrict__ nbase,
                                                    const T* __restrict__ ncoef, int64_t ms,
-                                                   int rows, int32_t* __restrict__ ibbase,
+                                                   int rows, int64_t ibs,
+                                                   int32_t* __restrict__ ibbase,
                                                    T* __restrict__ ibcoef) {
   int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (s >= nib) return;
   int64_t nid = ib[s];
   if (ibbase) ibbase[s] = nbase[nid];
-  for (int r = 0; r < rows; ++r) ibcoef[(int64_t)r * nib + s] = ncoef[(int64_t)r * ms + nid];
+  for (int r = 0; r < rows; ++r) ibcoef[(int64_t)r * ibs + s] = ncoef[(int64_t)r * ms + nid];
 }
 
 int scan_exclusive(const int32_t* in, int64_t n, int32_t* out, hipStream_t s) {
@@ -745,13 +747,17 @@ int build(const pc_plan* P, const double* xyz, const uint8_t* kind, int64_t M,
   }
   g->n_near = (int64_t)hnear.size();
   g->n_near_entries = near_entries;
+  // the ELL width is one of three compile-time bounds of the update kernel
+  near_w = near_w <= 8 ? 8 : (near_w <= 16 ? 16 : 32);
   g->near_w = near_w;
+  g->nns = (g->n_near + 63) / 64 * 64;
+  g->ibs = (g->n_ib + 63) / 64 * 64;
   if (g->n_ib) {
     PC_TRY(dev_alloc((void**)&g->ib, (size_t)g->n_ib * 4, "IB list"));
     PC_HIP_CHECK(hipMemcpy(g->ib, hib.data(), (size_t)g->n_ib * 4, hipMemcpyHostToDevice));
   }
   if (g->n_near) {
-    const int64_t ell = (int64_t)near_w * g->n_near;
+    const int64_t ell = (int64_t)near_w * g->nns;
     PC_TRY(dev_alloc((void**)&g->near, (size_t)g->n_near * 4, "near list"));
     PC_TRY(dev_alloc((void**)&g->nslot, (size_t)ell * 4, "near slots"));
     PC_TRY(dev_alloc((void**)&g->ncoefib, (size_t)d * ell * 8, "near coefs"));
@@ -763,35 +769,35 @@ int build(const pc_plan* P, const double* xyz, const uint8_t* kind, int64_t M,
     hipLaunchKernelGGL(k_slot_map, dim3(nblocks(g->n_ib, 256)), dim3(256), 0, s, g->ib, g->n_ib,
                        slot);
     hipLaunchKernelGGL(k_near_fill<double>, dim3(nblocks(g->n_near, 256)), dim3(256), 0, s,
-                       g->near, g->n_near, near_w, g->gidx, g->gcoef, G, k_grid, d, slot,
-                       g->nslot, g->ncoefib);
+                       g->near, g->n_near, g->nns, near_w, g->gidx, g->gcoef, G, k_grid, d,
+                       slot, g->nslot, g->ncoefib);
     if (want32)
       hipLaunchKernelGGL(k_near_fill<float>, dim3(nblocks(g->n_near, 256)), dim3(256), 0, s,
-                         g->near, g->n_near, near_w, g->gidx, g->gcoef32, G, k_grid, d, slot,
-                         g->nslot, g->ncoefib32);
+                         g->near, g->n_near, g->nns, near_w, g->gidx, g->gcoef32, G, k_grid,
+                         d, slot, g->nslot, g->ncoefib32);
     PC_HIP_CHECK(hipGetLastError());
   }
   if (g->n_ib) {
     PC_TRY(dev_alloc((void**)&g->ibbase, (size_t)g->n_ib * 4, "IB bases"));
-    PC_TRY(dev_alloc((void**)&g->ibcoef, (size_t)d * bn * g->n_ib * 8, "IB coefs"));
+    PC_TRY(dev_alloc((void**)&g->ibcoef, (size_t)d * bn * g->ibs * 8, "IB coefs"));
     hipLaunchKernelGGL(k_ib_gather<double>, dim3(nblocks(g->n_ib, 256)), dim3(256), 0, s, g->ib,
-                       g->n_ib, g->nbase, g->ncoef, g->ms, d * bn, g->ibbase, g->ibcoef);
+                       g->n_ib, g->nbase, g->ncoef, g->ms, d * bn, g->ibs, g->ibbase, g->ibcoef);
     if (want32) {
-      PC_TRY(dev_alloc((void**)&g->ibcoef32, (size_t)d * bn * g->n_ib * 4, "IB coefs"));
+      PC_TRY(dev_alloc((void**)&g->ibcoef32, (size_t)d * bn * g->ibs * 4, "IB coefs"));
       hipLaunchKernelGGL(k_ib_gather<float>, dim3(nblocks(g->n_ib, 256)), dim3(256), 0, s, g->ib,
-                         g->n_ib, g->nbase, g->ncoef32, g->ms, d * bn, (int32_t*)nullptr,
+                         g->n_ib, g->nbase, g->ncoef32, g->ms, d * bn, g->ibs, (int32_t*)nullptr,
                          g->ibcoef32);
     }
     PC_HIP_CHECK(hipGetLastError());
   }
   PC_HIP_CHECK(hipStreamSynchronize(s));
-  const int64_t ell = (int64_t)g->near_w * g->n_near;
+  const int64_t ell = g->n_near ? (int64_t)g->near_w * g->nns : 0;
   int64_t bytes = (int64_t)k_grid * G * 4 + (int64_t)d * k_grid * G * 8 + M * 4 +
                   (int64_t)d * bn * g->ms * 8 + g->n_ib * 4 + g->n_near * 4 + ell * (4 + 8 * d) +
-                  g->n_ib * (4 + 8 * (int64_t)d * bn);
+                  g->n_ib * 4 + g->ibs * 8 * (int64_t)d * bn;
   if (want32)
     bytes += (int64_t)d * k_grid * G * 4 + (int64_t)d * bn * g->ms * 4 + ell * 4 * d +
-             g->n_ib * 4 * (int64_t)d * bn;
+             g->ibs * 4 * (int64_t)d * bn;
   g->bytes = bytes;
   return PC_OK;
 }
