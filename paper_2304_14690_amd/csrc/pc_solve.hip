@@ -622,6 +622,111 @@ __device__ __forceinline__ void r16_fft(cplx<TC>* a, int t, const R16Tw<TC>& tw,
   if (RR == 2) r16_final<TC, INV, 2>(a, T, tw, twH);
 }
 
+// ---- radix-8 plan (8 values per thread, T = H/8 threads per line) -------------
+// Used where a pass has few lines (a 2D grid): twice the threads per line of
+// the radix-16 plan, so twice the wavefronts to hide latency with.
+
+// Twiddle state of the radix-8 plan: the stage bases w = exp(-+2 pi i k/(8L))
+// for the stages with L = 8 and L = 64 (k = t mod L), and twH[t] for the
+// final stage; loaded once per launch.
+template <typename TC>
+struct R8Tw {
+  cplx<TC> s1, s2, fin;
+};
+
+// v[r] *= w^r, r = 1..7, with the powers built by squaring (each power is at
+// most three products away from w).
+template <typename TC, bool INV>
+__device__ __forceinline__ void twiddle_r8(cplx<TC>* v, cplx<TC> w) {
+  const cplx<TC> w2 = cmul(w, w);
+  const cplx<TC> w4 = cmul(w2, w2);
+  const cplx<TC> w3 = cmul(w2, w);
+  cplx<TC> p[8];
+  p[1] = w;
+  p[2] = w2;
+  p[3] = w3;
+  p[4] = w4;
+  p[5] = cmul(w4, w);
+  p[6] = cmul(w4, w2);
+  p[7] = cmul(w4, w3);
+#pragma unroll
+  for (int r = 1; r < 8; ++r) v[r] = INV ? cmulc(v[r], p[r]) : cmul(v[r], p[r]);
+}
+
+// One radix-8 Stockham stage with sub-transform length L on the thread's 8
+// values (butterfly j = t, k = t mod L, inputs at j + T r, outputs at
+// (j - k) 8 + k + r L); see r16_stage16.
+template <typename TC, bool INV, bool LAST, int T>
+__device__ __forceinline__ void r8_stage(cplx<TC>* a, int t, int L, cplx<TC> w, cplx<TC>* z) {
+  cplx<TC> v[8];
+#pragma unroll
+  for (int r = 0; r < 8; ++r) v[r] = a[r];
+  if (L > 1) twiddle_r8<TC, INV>(v, w);
+  dft8<TC, INV>(v);
+  if (LAST) {
+#pragma unroll
+    for (int r = 0; r < 8; ++r) a[r] = v[r];
+  } else {
+    const int k = t & (L - 1);
+    const int base = (t - k) * 8 + k;
+#pragma unroll
+    for (int r = 0; r < 8; ++r) z[lpad(base + r * L)] = v[r];
+    line_sync<T>();
+#pragma unroll
+    for (int q = 0; q < 8; ++q) a[q] = z[lpad(t + T * q)];
+    line_sync<T>();
+  }
+}
+
+// The final stage of radix R < RT on a thread holding RT values (always in
+// place: butterflies j = t + T b, b < RT/R, with k = j).
+template <typename TC, bool INV, int RT, int R>
+__device__ __forceinline__ void rad_final(cplx<TC>* a, int T, cplx<TC> fin,
+                                          const cplx<TC>* __restrict__ twH) {
+  constexpr int NB = RT / R;
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    cplx<TC> v[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[r] = a[b + NB * r];
+    const cplx<TC> w = b ? cmul(fin, twH[T * b]) : fin;  // twH[t + T b]
+    cplx<TC> wr = w;
+#pragma unroll
+    for (int r = 1; r < R; ++r) {
+      v[r] = INV ? cmulc(v[r], wr) : cmul(v[r], wr);
+      if (r + 1 < R) wr = cmul(wr, w);
+    }
+    dftR<TC, INV, R>(v);
+#pragma unroll
+    for (int r = 0; r < R; ++r) a[b + NB * r] = v[r];
+  }
+}
+
+template <typename TC, bool INV, int LOGH>
+__device__ __forceinline__ void r8_fft(cplx<TC>* a, int t, const R8Tw<TC>& tw,
+                                       const cplx<TC>* __restrict__ twH, cplx<TC>* z) {
+  constexpr int H = 1 << LOGH;
+  constexpr int T = H / 8;
+  constexpr int S8 = LOGH / 3;         // radix-8 stages (1 to 3 for 16 <= H <= 2048)
+  constexpr int RR = 1 << (LOGH % 3);  // final radix (1: none)
+  static_assert(S8 >= 1 && S8 <= 3, "radix-8 plan covers 16 <= H <= 2048");
+  r8_stage<TC, INV, (S8 == 1 && RR == 1), T>(a, t, 1, tw.s1, z);
+  if (S8 >= 2) r8_stage<TC, INV, (S8 == 2 && RR == 1), T>(a, t, 8, tw.s1, z);
+  if (S8 >= 3) r8_stage<TC, INV, (RR == 1), T>(a, t, 64, tw.s2, z);
+  if (RR == 4) rad_final<TC, INV, 8, 4>(a, T, tw.fin, twH);
+  if (RR == 2) rad_final<TC, INV, 8, 2>(a, T, tw.fin, twH);
+}
+
+template <typename TC, bool INV, int LOGH, int RT>
+__device__ __forceinline__ void rad_fft(cplx<TC>* a, int t, const R16Tw<TC>& tw,
+                                        const R8Tw<TC>& tw8, const cplx<TC>* __restrict__ twH,
+                                        cplx<TC>* z) {
+  if constexpr (RT == 16)
+    r16_fft<TC, INV, LOGH>(a, t, tw, twH, z);
+  else
+    r8_fft<TC, INV, LOGH>(a, t, tw8, twH, z);
+}
+
 // exp(-i pi (H-k) / (2N)) = exp(-i pi / 4) conj(exp(-i pi k / (2N))), N = 2H
 template <typename TC>
 __device__ __forceinline__ cplx<TC> t4n_mirror(cplx<TC> w) {
@@ -651,13 +756,18 @@ __device__ __forceinline__ int vpad(int p) { return 2 * lpad(p >> 1) + (p & 1); 
 // LDS real index of X[r] (two pad slots per 32 reals).
 __device__ __forceinline__ int xpad(int r) { return r + 2 * (r >> 5); }
 
-template <typename TC, typename TI, typename TO, int OP, int LD, int ST, int LOGH>
-__global__ void __launch_bounds__(512) dct_r16(LineArgs<TC> A) {
+// One pass of the cosine transforms over a tile of C lines: forward DCT-II
+// (OP_FWD), inverse DCT-III (OP_INV), or forward, division by the
+// eigenvalues and inverse along the last axis (OP_FDI).  RT complex values
+// per thread (16 or 8), T = H / RT threads per line.
+template <typename TC, typename TI, typename TO, int OP, int LD, int ST, int LOGH, int RT>
+__global__ void __launch_bounds__(512) dct_rad(LineArgs<TC> A) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   if (A.skip && *A.skip) return;
   constexpr int H = 1 << LOGH;
   constexpr int N = 2 * H;
-  constexpr int T = H / 16;
+  constexpr int T = H / RT;
+  constexpr int NV = 2 * RT;  // reals per thread
   const int LS = H + H / 16 + 1;  // complex slots per line in LDS
   const int C = A.C;
   const bool rows = A.axis == 0;
@@ -685,12 +795,19 @@ __global__ void __launch_bounds__(512) dct_r16(LineArgs<TC> A) {
 
   // twiddle state (issued first; in flight with the data loads)
   R16Tw<TC> tw;
-  if (LOGH >= 8) {
-    const int step = (H / 256) * (t & 15);
-    tw.w1 = Tb.twH[step];
-    tw.w4 = Tb.twH[4 * step];
+  R8Tw<TC> tw8;
+  if constexpr (RT == 16) {
+    if (LOGH >= 8) {
+      const int step = (H / 256) * (t & 15);
+      tw.w1 = Tb.twH[step];
+      tw.w4 = Tb.twH[4 * step];
+    }
+    if (LOGH % 4) tw.fin = Tb.twH[t];
+  } else {
+    if (LOGH >= 6) tw8.s1 = Tb.twH[(H / 64) * (t & 7)];
+    if (LOGH >= 9) tw8.s2 = Tb.twH[(H / 512) * (t & 63)];
+    if (LOGH % 3) tw8.fin = Tb.twH[t];
   }
-  if (LOGH % 4) tw.fin = Tb.twH[t];
   const cplx<TC> tNb = Tb.tN[t];
   const cplx<TC> t4b = Tb.t4N[t];
 
@@ -707,8 +824,8 @@ __global__ void __launch_bounds__(512) dct_r16(LineArgs<TC> A) {
   };
 
   // Strided passes move the tile cooperatively.  Thread x takes line
-  // cc = x % C at positions n = x / C + r T, r = 0..31 (C T threads, N = 32 T
-  // positions per line), so each access covers C adjacent lines; all 32
+  // cc = x % C at positions n = x / C + r T, r < NV (C T threads, N = NV T
+  // positions per line), so each access covers C adjacent lines; all NV
   // loads are issued before the first is used.
   const int tcc = threadIdx.x & (C - 1);
   const int tn0 = threadIdx.x >> __builtin_ctz(C);
@@ -720,7 +837,7 @@ __global__ void __launch_bounds__(512) dct_r16(LineArgs<TC> A) {
     if (LD == LD_RESID) {
       // the residual reads 5-7 values per point: batches of 8 points
 #pragma unroll
-      for (int r0 = 0; r0 < 32; r0 += 8) {
+      for (int r0 = 0; r0 < NV; r0 += 8) {
         TC v[8];
 #pragma unroll
         for (int r = 0; r < 8; ++r) {
@@ -733,42 +850,42 @@ __global__ void __launch_bounds__(512) dct_r16(LineArgs<TC> A) {
         for (int r = 0; r < 8; ++r) zl[pos(tn0 + (r0 + r) * T)] = v[r];
       }
     } else {
-      TC v[32];
+      TC v[NV];
       const TI* src = in + p0;
       if (A.sub) {
         const double sb = *A.sub;
 #pragma unroll
-        for (int r = 0; r < 32; ++r) v[r] = (TC)((double)src[r * dp] - sb);
+        for (int r = 0; r < NV; ++r) v[r] = (TC)((double)src[r * dp] - sb);
       } else {
 #pragma unroll
-        for (int r = 0; r < 32; ++r) v[r] = (TC)src[r * dp];
+        for (int r = 0; r < NV; ++r) v[r] = (TC)src[r * dp];
       }
 #pragma unroll
-      for (int r = 0; r < 32; ++r) zl[pos(tn0 + r * T)] = v[r];
+      for (int r = 0; r < NV; ++r) zl[pos(tn0 + r * T)] = v[r];
     }
     __syncthreads();
   };
 
-  cplx<TC> a[16];
+  cplx<TC> a[RT];
   if (OP != OP_INV) {
     if (rows) {
       // coalesced loads, reordered into Makhoul order through LDS
-      TC xv[32];
+      TC xv[NV];
 #pragma unroll
-      for (int i = 0; i < 32; ++i) xv[i] = load(t + T * i);
+      for (int i = 0; i < NV; ++i) xv[i] = load(t + T * i);
 #pragma unroll
-      for (int i = 0; i < 32; ++i) zr[vpad(mk_pos(t + T * i, N))] = xv[i];
+      for (int i = 0; i < NV; ++i) zr[vpad(mk_pos(t + T * i, N))] = xv[i];
       line_sync<T>();
     } else {
       tile_load([&](int n) { return vpad(mk_pos(n, N)); });
     }
 #pragma unroll
-    for (int q = 0; q < 16; ++q) a[q] = z[lpad(t + T * q)];
+    for (int q = 0; q < RT; ++q) a[q] = z[lpad(t + T * q)];
     line_sync<T>();
-    r16_fft<TC, false, LOGH>(a, t, tw, Tb.twH, z);
+    rad_fft<TC, false, LOGH, RT>(a, t, tw, tw8, Tb.twH, z);
     // partner exchange: Z[H-k] next to Z[k]
 #pragma unroll
-    for (int q = 0; q < 16; ++q) z[lpad(t + T * q)] = a[q];
+    for (int q = 0; q < RT; ++q) z[lpad(t + T * q)] = a[q];
     line_sync<T>();
     TC rest = TC(0), x0 = TC(0);
     if (OP == OP_FDI) {
@@ -776,9 +893,9 @@ __global__ void __launch_bounds__(512) dct_r16(LineArgs<TC> A) {
       if (A.lam1) rest += A.lam1[lo];
     }
     const TC lc = A.lamc, ls_ = A.lscale;
-    TC ya[16], yb[16];  // own X[k] and X[N-k] (X[H] for k = 0), divided in FDI
+    TC ya[RT], yb[RT];  // own X[k] and X[N-k] (X[H] for k = 0), divided in FDI
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
+    for (int q = 0; q < RT; ++q) {
       const int k = t + T * q;
       cplx<TC> Zk = a[q];
       cplx<TC> Zc = conj_(z[lpad((H - k) & (H - 1))]);
@@ -814,7 +931,7 @@ __global__ void __launch_bounds__(512) dct_r16(LineArgs<TC> A) {
     if (OP == OP_FWD) {
       if (rows) {
 #pragma unroll
-        for (int q = 0; q < 16; ++q) {
+        for (int q = 0; q < RT; ++q) {
           const int k = t + T * q;
           out[lb + (int64_t)k * st] = (TO)ya[q];
           out[lb + (int64_t)(k ? N - k : H) * st] = (TO)yb[q];
@@ -822,7 +939,7 @@ __global__ void __launch_bounds__(512) dct_r16(LineArgs<TC> A) {
       } else {
         line_sync<T>();
 #pragma unroll
-        for (int q = 0; q < 16; ++q) {
+        for (int q = 0; q < RT; ++q) {
           const int k = t + T * q;
           zr[xpad(k)] = ya[q];
           zr[xpad(k ? N - k : H)] = yb[q];
@@ -831,7 +948,7 @@ __global__ void __launch_bounds__(512) dct_r16(LineArgs<TC> A) {
         TO* dst = out + lbase[0] + tcc + (int64_t)tn0 * st;
         const TC* zl = zr0 + 2 * tcc * LS;
 #pragma unroll
-        for (int r = 0; r < 32; ++r) dst[(int64_t)r * T * st] = (TO)zl[xpad(tn0 + r * T)];
+        for (int r = 0; r < NV; ++r) dst[(int64_t)r * T * st] = (TO)zl[xpad(tn0 + r * T)];
       }
       return;
     }
@@ -839,14 +956,14 @@ __global__ void __launch_bounds__(512) dct_r16(LineArgs<TC> A) {
     if (t == 0 && rest == TC(0) && A.bmean) *A.bmean = (double)x0 * A.meannorm;
     line_sync<T>();
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
+    for (int q = 0; q < RT; ++q) {
       const int k = t + T * q;
       zr[xpad(k)] = ya[q];
       zr[xpad(k ? N - k : H)] = yb[q];
     }
     line_sync<T>();
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
+    for (int q = 0; q < RT; ++q) {
       const int k = t + T * q;
       const cplx<TC> wN = q ? cmul(tNb, Tb.tN[T * q]) : tNb;
       const cplx<TC> w4 = q ? cmul(t4b, Tb.t4N[T * q]) : t4b;
@@ -857,16 +974,16 @@ __global__ void __launch_bounds__(512) dct_r16(LineArgs<TC> A) {
     line_sync<T>();
   } else {
     // X in natural order: own X[k], X[N-k] and the partners' via LDS
-    TC xk[16], xn[16];
+    TC xk[RT], xn[RT];
     if (rows) {
 #pragma unroll
-      for (int q = 0; q < 16; ++q) {
+      for (int q = 0; q < RT; ++q) {
         int k = t + T * q;
         xk[q] = load(k);
         xn[q] = load(k ? N - k : H);
       }
 #pragma unroll
-      for (int q = 0; q < 16; ++q) {
+      for (int q = 0; q < RT; ++q) {
         int k = t + T * q;
         zr[xpad(k)] = xk[q];
         zr[xpad(k ? N - k : H)] = xn[q];
@@ -875,14 +992,14 @@ __global__ void __launch_bounds__(512) dct_r16(LineArgs<TC> A) {
     } else {
       tile_load([&](int n) { return xpad(n); });
 #pragma unroll
-      for (int q = 0; q < 16; ++q) {
+      for (int q = 0; q < RT; ++q) {
         int k = t + T * q;
         xk[q] = zr[xpad(k)];
         xn[q] = zr[xpad(k ? N - k : H)];
       }
     }
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
+    for (int q = 0; q < RT; ++q) {
       const int k = t + T * q;
       const cplx<TC> wN = q ? cmul(tNb, Tb.tN[T * q]) : tNb;
       const cplx<TC> w4 = q ? cmul(t4b, Tb.t4N[T * q]) : t4b;
@@ -900,7 +1017,7 @@ __global__ void __launch_bounds__(512) dct_r16(LineArgs<TC> A) {
   cplx<TC>* zi = z;
   asm volatile("" : "+v"(ti));
   asm volatile("" : "+v"(zi));
-  r16_fft<TC, true, LOGH>(a, ti, tw, Tb.twH, zi);
+  rad_fft<TC, true, LOGH, RT>(a, ti, tw, tw8, Tb.twH, zi);
   const TC sc = A.outscale;
   // The stores hit the same addresses as the loads; opaque copies of the
   // line base and stride make the compiler recompute them here instead of
@@ -919,13 +1036,13 @@ __global__ void __launch_bounds__(512) dct_r16(LineArgs<TC> A) {
     }
   };
 #pragma unroll
-  for (int q = 0; q < 16; ++q) zi[lpad(ti + T * q)] = {a[q].re * sc, a[q].im * sc};
+  for (int q = 0; q < RT; ++q) zi[lpad(ti + T * q)] = {a[q].re * sc, a[q].im * sc};
   if (rows) {
     // back to natural order through LDS, then coalesced stores
     line_sync<T>();
     TC* zri = reinterpret_cast<TC*>(zi);
 #pragma unroll
-    for (int i = 0; i < 32; ++i) {
+    for (int i = 0; i < NV; ++i) {
       const int n = t2 + T * i;
       put(lb2 + (int64_t)n * st2, zri[vpad(mk_pos(n, N))]);
     }
@@ -934,7 +1051,7 @@ __global__ void __launch_bounds__(512) dct_r16(LineArgs<TC> A) {
     const int64_t p0 = lbase[0] + tcc + (int64_t)tn0 * st2;
     const TC* zl = zr0 + 2 * tcc * LS;
 #pragma unroll
-    for (int r = 0; r < 32; ++r)
+    for (int r = 0; r < NV; ++r)
       put(p0 + (int64_t)r * T * st2, zl[vpad(mk_pos(tn0 + r * T, N))]);
   }
 }
@@ -1031,12 +1148,23 @@ void tile_shape(int axis, int N, int lines_x, int* C, int* nthr, int* B) {
 
 }  // namespace
 
-// Lines per workgroup tile of the radix-16 transform along `axis` (0 when
+// Complex values per thread of the transforms along `axis`: 16, or 8 when
+// the pass has too few lines to give the device four wavefronts per SIMD
+// with 16 (a 2D grid; small 3D grids), which doubles the wavefronts.
+int pass_radix(const pc_plan* P, int axis) {
+  const int64_t N = P->n[axis];
+  const int64_t lines = P->G / N;
+  const int64_t t16 = N / 32;  // threads per line with 16 values each
+  const int64_t waves16 = (lines * t16 + 63) / 64;
+  return waves16 < 4 * 1024 ? 8 : 16;
+}
+
+// Lines per workgroup tile of the radix-16/8 transform along `axis` (0 when
 // the axis uses the generic kernel, N < 32).
 int r16_tile_lines(const pc_plan* P, int axis, size_t elem) {
   const int N = P->n[axis];
   if (N < 32) return 0;
-  const int H = N / 2, T = H / 16, LS = H + H / 16 + 1;
+  const int H = N / 2, T = H / pass_radix(P, axis), LS = H + H / 16 + 1;
   const int64_t lines = P->G / N;
   int C;
   if (axis == 0) {
@@ -1090,8 +1218,9 @@ int launch_pass(const pc_plan* P, int axis, const TI* in, TO* out, const AxisTab
   A.meannorm = 1.0 / norm;
   int64_t lines = P->G / A.N;
   if (A.N >= 32) {
-    // radix-16 register kernel: T = H/16 threads per line, C lines per group
-    const int T = H / 16;
+    // register kernel: T = H/RT threads per line, C lines per group
+    const int RT = pass_radix(P, axis);
+    const int T = H / RT;
     const int LS = H + H / 16 + 1;
     const int C = r16_tile_lines(P, axis, sizeof(TC));
     if ((size_t)C * LS * 2 * sizeof(TC) > (size_t)lds_limit())
@@ -1112,22 +1241,28 @@ int launch_pass(const pc_plan* P, int axis, const TI* in, TO* out, const AxisTab
     size_t lds = (size_t)C * LS * 2 * sizeof(TC);
     dim3 grid(ntile), block(C * T);
     const void* fn = nullptr;
-    switch (logH) {
-#define PC_R16_CASE(LH) \
-      case LH: fn = (const void*)dct_r16<TC, TI, TO, OP, LD, ST, LH>; break;
-      PC_R16_CASE(4) PC_R16_CASE(5) PC_R16_CASE(6) PC_R16_CASE(7)
-      PC_R16_CASE(8) PC_R16_CASE(9) PC_R16_CASE(10) PC_R16_CASE(11)
-#undef PC_R16_CASE
+    const int key = logH * 32 + RT;
+    switch (key) {
+#define PC_RAD_CASE(LH, R) \
+      case LH * 32 + R: fn = (const void*)dct_rad<TC, TI, TO, OP, LD, ST, LH, R>; break;
+      PC_RAD_CASE(4, 16) PC_RAD_CASE(5, 16) PC_RAD_CASE(6, 16) PC_RAD_CASE(7, 16)
+      PC_RAD_CASE(8, 16) PC_RAD_CASE(9, 16) PC_RAD_CASE(10, 16) PC_RAD_CASE(11, 16)
+      PC_RAD_CASE(4, 8) PC_RAD_CASE(5, 8) PC_RAD_CASE(6, 8) PC_RAD_CASE(7, 8)
+      PC_RAD_CASE(8, 8) PC_RAD_CASE(9, 8) PC_RAD_CASE(10, 8) PC_RAD_CASE(11, 8)
+#undef PC_RAD_CASE
       default: return fail(PC_ERR_UNSUPPORTED_SIZE, "transform length");
     }
     if (lds > 65536)
       PC_HIP_CHECK(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    switch (logH) {
-#define PC_R16_LAUNCH(LH) \
-      case LH: hipLaunchKernelGGL((dct_r16<TC, TI, TO, OP, LD, ST, LH>), grid, block, lds, s, A); break;
-      PC_R16_LAUNCH(4) PC_R16_LAUNCH(5) PC_R16_LAUNCH(6) PC_R16_LAUNCH(7)
-      PC_R16_LAUNCH(8) PC_R16_LAUNCH(9) PC_R16_LAUNCH(10) PC_R16_LAUNCH(11)
-#undef PC_R16_LAUNCH
+    switch (key) {
+#define PC_RAD_LAUNCH(LH, R) \
+      case LH * 32 + R: \
+        hipLaunchKernelGGL((dct_rad<TC, TI, TO, OP, LD, ST, LH, R>), grid, block, lds, s, A); break;
+      PC_RAD_LAUNCH(4, 16) PC_RAD_LAUNCH(5, 16) PC_RAD_LAUNCH(6, 16) PC_RAD_LAUNCH(7, 16)
+      PC_RAD_LAUNCH(8, 16) PC_RAD_LAUNCH(9, 16) PC_RAD_LAUNCH(10, 16) PC_RAD_LAUNCH(11, 16)
+      PC_RAD_LAUNCH(4, 8) PC_RAD_LAUNCH(5, 8) PC_RAD_LAUNCH(6, 8) PC_RAD_LAUNCH(7, 8)
+      PC_RAD_LAUNCH(8, 8) PC_RAD_LAUNCH(9, 8) PC_RAD_LAUNCH(10, 8) PC_RAD_LAUNCH(11, 8)
+#undef PC_RAD_LAUNCH
     }
     PC_HIP_CHECK(hipGetLastError());
     return PC_OK;
