@@ -111,7 +111,9 @@ __global__ void __launch_bounds__(TPB) k_grad_all(const int32_t* __restrict__ nb
                                                   int64_t ms, int bnrt, BlockOffsets bo,
                                                   const T* __restrict__ phi, T scale,
                                                   const T* __restrict__ u,
-                                                  T* __restrict__ out) {
+                                                  T* __restrict__ out,
+                                                  const int32_t* __restrict__ skip) {
+  if (skip && *skip) return;
   const int bn = BN > 0 ? BN : bnrt;
   const int64_t n = xcd_block(blockIdx.x, gridDim.x) * TPB + threadIdx.x;
   if (n >= M) return;
@@ -175,7 +177,9 @@ __global__ void __launch_bounds__(TPB) k_gather_ib(const int32_t* __restrict__ i
 
 template <typename T>
 __global__ void __launch_bounds__(TPB) k_zero_ib(const int32_t* __restrict__ ib, int64_t nib,
-                                                 int d, int64_t M, T* __restrict__ out) {
+                                                 int d, int64_t M, T* __restrict__ out,
+                                                 const int32_t* __restrict__ skip) {
+  if (skip && *skip) return;
   int64_t s = (int64_t)blockIdx.x * TPB + threadIdx.x;
   if (s >= nib) return;
   int64_t n = ib[s];
@@ -330,7 +334,7 @@ __global__ void __launch_bounds__(TPB) k_ib_close(const double* __restrict__ par
                                                   double tol, double* __restrict__ sums,
                                                   int32_t* __restrict__ conv,
                                                   const int32_t* __restrict__ skip,
-                                                  int32_t* host_flag) {
+                                                  int32_t* host_flag, double* host_sums) {
   __shared__ double rn[TPB / 64], rd[TPB / 64];
   if (skip && *skip) return;
   double num = 0.0, den = 0.0;
@@ -361,8 +365,12 @@ __global__ void __launch_bounds__(TPB) k_ib_close(const double* __restrict__ par
     const int32_t cv = (num < tol * den || num == 0.0) ? 1 : 0;
     conv[0] = cv;
     conv[1] += 1;
+    conv[4] = 1 - cv;  // guard of work queued for the converged case only
     if (host_flag) {
-      // coherent pinned host memory, polled by the host
+      // coherent pinned host memory, polled by the host: the sums first,
+      // then the flag that says they are there
+      host_sums[0] = num;
+      host_sums[1] = den;
       __threadfence_system();
       *host_flag = cv;
       __threadfence_system();
@@ -391,7 +399,9 @@ __global__ void __launch_bounds__(TPB) k_prologue(const int32_t* __restrict__ ib
 // Statistics into pinned host memory: bmean, criterion sums, flags.
 __global__ void __launch_bounds__(64) k_stats_out(const double* __restrict__ scal,
                                                   const int32_t* __restrict__ flag,
-                                                  double* hs, int32_t* hf) {
+                                                  double* hs, int32_t* hf,
+                                                  const int32_t* __restrict__ skip) {
+  if (skip && *skip) return;
   if (threadIdx.x < 3) hs[threadIdx.x] = scal[threadIdx.x];
   if (threadIdx.x < 2) hf[threadIdx.x + 2] = flag[threadIdx.x];
   __threadfence_system();
@@ -405,7 +415,9 @@ __global__ void __launch_bounds__(TPB) k_project(const T* __restrict__ u, const 
 }
 
 template <typename T>
-__global__ void __launch_bounds__(TPB) k_sub_first(T* __restrict__ x, int64_t n) {
+__global__ void __launch_bounds__(TPB) k_sub_first(T* __restrict__ x, int64_t n,
+                                                   const int32_t* __restrict__ skip) {
+  if (skip && *skip) return;
   // gauge: subtract the value at the first cell (read once per thread before
   // any write of this launch can reach it: element 0 is written last)
   T v0 = x[0];
@@ -414,8 +426,18 @@ __global__ void __launch_bounds__(TPB) k_sub_first(T* __restrict__ x, int64_t n)
 }
 
 template <typename T>
-__global__ void __launch_bounds__(1) k_zero_first(T* __restrict__ x) {
+__global__ void __launch_bounds__(1) k_zero_first(T* __restrict__ x,
+                                                 const int32_t* __restrict__ skip) {
+  if (skip && *skip) return;
   x[0] = T(0);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(TPB) k_copy(const T* __restrict__ src, T* __restrict__ dst,
+                                              int64_t n, const int32_t* __restrict__ skip) {
+  if (skip && *skip) return;
+  int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  if (i < n) dst[i] = src[i];
 }
 
 unsigned nblk(int64_t n) { return (unsigned)((n + TPB - 1) / TPB); }
@@ -495,7 +517,7 @@ int launch_div_near(const pc_geom* g, const T* ncoefib, const T* gib, const T* b
 
 template <typename T, bool PROJECT>
 int launch_grad_all(const pc_geom* g, const T* ncoef, const T* phi, T scale, const T* u, T* out,
-                    hipStream_t s) {
+                    hipStream_t s, const int32_t* skip = nullptr) {
   const bool lr = sizeof(T) == 4;
   BlockOffsets bo = block_offsets(g);
   dim3 grid(nblk(g->M)), block(TPB);
@@ -503,10 +525,10 @@ int launch_grad_all(const pc_geom* g, const T* ncoef, const T* phi, T scale, con
   do {                                                                                       \
     if (lr)                                                                                  \
       hipLaunchKernelGGL((k_grad_all<T, D, BN, true, PROJECT>), grid, block, 0, s, g->nbase,  \
-                         ncoef, g->M, g->ms, g->bn, bo, phi, scale, u, out);                 \
+                         ncoef, g->M, g->ms, g->bn, bo, phi, scale, u, out, skip);           \
     else                                                                                     \
       hipLaunchKernelGGL((k_grad_all<T, D, BN, false, PROJECT>), grid, block, 0, s, g->nbase, \
-                         ncoef, g->M, g->ms, g->bn, bo, phi, scale, u, out);                 \
+                         ncoef, g->M, g->ms, g->bn, bo, phi, scale, u, out, skip);           \
   } while (0)
   if (g->d == 2) {
     if (g->bn == 16) GRL(2, 16);
@@ -566,7 +588,7 @@ int launch_ib_update(const pc_geom* g, const T* uib, const T* grad, T* gib, doub
 template <typename T>
 int launch_ib_step(const pc_geom* g, const T* ibcoef, const T* phi, T scale, const T* uib, T* gib,
                    double tol, double* part, int32_t* flag, double* sums, hipStream_t s,
-                   const int32_t* skip, int32_t* host_flag) {
+                   const int32_t* skip, int32_t* host_flag, double* host_sums) {
   if (g->n_ib == 0) return PC_OK;
   BlockOffsets bo = block_offsets(g);
   dim3 grid((unsigned)((g->n_ib + IBT - 1) / IBT)), block(IBT);
@@ -581,16 +603,16 @@ int launch_ib_step(const pc_geom* g, const T* ibcoef, const T* phi, T scale, con
   }
 #undef IBS
   hipLaunchKernelGGL(k_ib_close, dim3(1), dim3(TPB), 0, s, (const double*)part, (int)grid.x, tol,
-                     sums, flag, skip, host_flag);
+                     sums, flag, skip, host_flag, host_sums);
   PC_HIP_CHECK(hipGetLastError());
   return PC_OK;
 }
 
 template <typename T>
-int launch_zero_ib(const pc_geom* g, T* out, hipStream_t s) {
+int launch_zero_ib(const pc_geom* g, T* out, hipStream_t s, const int32_t* skip = nullptr) {
   if (g->n_ib == 0) return PC_OK;
   hipLaunchKernelGGL(k_zero_ib<T>, dim3(nblk(g->n_ib)), dim3(TPB), 0, s, g->ib, g->n_ib, g->d,
-                     g->M, out);
+                     g->M, out, skip);
   PC_HIP_CHECK(hipGetLastError());
   return PC_OK;
 }
@@ -670,6 +692,7 @@ int pressure_correct_t(const pc_geom* g, const pc_plan* P, int mode, const T* u,
   // every launch of the iteration returns at once once the device flag says
   // an earlier iteration has converged.
   auto iteration = [&](int it, const int32_t* skip, int32_t* host_flag) -> int {
+    double* host_sums = host_flag ? W->hscal + 4 + 2 * (it & 1) : nullptr;
     if (it > 1 || g_io) PC_TRY(launch_div_near<T>(g, nci<T>(g), gib, bnear, b, false, s, skip));
     if (resident && mode == PC_F64)
       PC_TRY(solve_resident_f64(P, (const double*)b, (double*)p, W->scal, W, s, sigma, skip,
@@ -685,12 +708,39 @@ int pressure_correct_t(const pc_geom* g, const pc_plan* P, int mode, const T* u,
       PC_TRY(solve_mixed(P, (const double*)b, (double*)p, sweeps, W->scal, W, s, sigma, skip));
     if (nib)
       PC_TRY(launch_ib_step<T>(g, ibc<T>(g), p, (T)sigma, uib, gib, tol, W->partial, W->flag,
-                               W->scal + 1, s, skip, host_flag));
+                               W->scal + 1, s, skip, host_flag, host_sums));
+    return PC_OK;
+  };
+
+  // The work after the last iteration: complete the inverse transforms on
+  // the lines the B+V gradient did not need, the gradient at every node
+  // fused with the projection (Eq. 18), exactly 0 at B+V, the final force,
+  // the gauge and the statistics.  With a guard it does nothing unless the
+  // guarded iteration converged.
+  auto final_work = [&](const int32_t* guard) -> int {
+    if (resident && mode == PC_F64)
+      PC_TRY(solve_resident_f64(P, (const double*)b, (double*)p, W->scal, W, s, sigma, guard, 2));
+    else if (resident)
+      PC_TRY(solve_resident_f32(P, (const float*)b, (float*)p, W->scal, W, s, sigma, guard, 2));
+    PC_TRY((launch_grad_all<T, true>(g, nc<T>(g), p, (T)sigma, u, u_out, s, guard)));
+    PC_TRY(launch_zero_ib<T>(g, u_out, s, guard));
+    if (g_io && nib)
+      hipLaunchKernelGGL(k_copy<T>, dim3(nblk((int64_t)g->d * nib)), dim3(TPB), 0, s,
+                         (const T*)gib, g_io, (int64_t)g->d * nib, guard);
+    if (gauge == 1) {
+      hipLaunchKernelGGL(k_sub_first<T>, dim3(nblk(P->G)), dim3(TPB), 0, s, p, P->G, guard);
+      hipLaunchKernelGGL(k_zero_first<T>, dim3(1), dim3(1), 0, s, p, guard);
+    }
+    if (st)
+      hipLaunchKernelGGL(k_stats_out, dim3(1), dim3(64), 0, s, (const double*)W->scal,
+                         (const int32_t*)W->flag, W->hscal, W->hflag, guard);
+    PC_HIP_CHECK(hipGetLastError());
     return PC_OK;
   };
 
   int it = 0;
   bool converged = nib == 0;
+  bool final_queued = false;
   if (nib == 0) {
     PC_TRY(iteration(1, nullptr, nullptr));
     it = 1;
@@ -701,44 +751,48 @@ int pressure_correct_t(const pc_geom* g, const pc_plan* P, int mode, const T* u,
     // Enqueue one iteration ahead of the convergence test: while the host
     // waits for iteration i, the device already runs i+1 (which does nothing
     // if i converged), so the device does not idle on the host.  The IB
-    // kernel of iteration i stores its flag (0/1) straight into coherent
-    // pinned host slot i % 2, which the host resets to -1 before queueing
-    // the iteration that reuses it.
+    // kernels of iteration i store its flag (0/1) and criterion sums straight
+    // into coherent pinned host slot i % 2, which the host resets to -1
+    // before queueing the iteration that reuses it.
+    // Where iteration i is predicted to meet the criterion, the final work
+    // is queued behind it instead, guarded by the device's "not converged"
+    // word: the ratio q = num/den of the criterion falls about
+    // geometrically, q_i ~ q_{i-1}^2 / q_{i-2}, and the prediction must be
+    // below 2/3 of the tolerance.  A wrong prediction costs a few launches
+    // that return at once and a late enqueue; it never changes the result.
     volatile int32_t* hf = W->hflag;
+    volatile double* hs = W->hscal;
+    double q1 = 0.0, q2 = 0.0;  // q of the two previous iterations (0: unknown)
     hf[1] = -1;
     PC_TRY(iteration(1, W->flag, W->hflag + 1));
     for (it = 1;; ++it) {
-      if (it < max_it) {
+      bool ahead = false;
+      const bool likely = q1 > 0.0 && q2 > 0.0 && q1 * q1 < (2.0 / 3.0) * tol * q2;
+      if (likely) {
+        PC_TRY(final_work(W->flag + 4));
+      } else if (it < max_it) {
         hf[(it + 1) & 1] = -1;
         PC_TRY(iteration(it + 1, W->flag, W->hflag + ((it + 1) & 1)));
+        ahead = true;
       }
       PC_TRY(wait_host_flag(hf + (it & 1), s));
       if (hf[it & 1] == 1) {
         converged = true;
+        final_queued = likely;
         break;
       }
       if (it >= max_it) break;
+      const double num = hs[4 + 2 * (it & 1)], den = hs[5 + 2 * (it & 1)];
+      q2 = q1;
+      q1 = den > 0.0 ? num / den : 0.0;
+      if (!ahead) {
+        hf[(it + 1) & 1] = -1;
+        PC_TRY(iteration(it + 1, W->flag, W->hflag + ((it + 1) & 1)));
+      }
     }
   }
-  // complete the inverse transforms of the last iteration on the lines the
-  // B+V gradient did not need
-  if (resident && mode == PC_F64)
-    PC_TRY(solve_resident_f64(P, (const double*)b, (double*)p, W->scal, W, s, sigma, nullptr, 2));
-  else if (resident)
-    PC_TRY(solve_resident_f32(P, (const float*)b, (float*)p, W->scal, W, s, sigma, nullptr, 2));
-  PC_TRY((launch_grad_all<T, true>(g, nc<T>(g), p, (T)sigma, u, u_out, s)));
-  PC_TRY(launch_zero_ib<T>(g, u_out, s));
-  if (g_io && nib)
-    PC_HIP_CHECK(hipMemcpyAsync(g_io, gib, (size_t)g->d * nib * sizeof(T), hipMemcpyDeviceToDevice, s));
-  if (gauge == 1) {
-    hipLaunchKernelGGL(k_sub_first<T>, dim3(nblk(P->G)), dim3(TPB), 0, s, p, P->G);
-    hipLaunchKernelGGL(k_zero_first<T>, dim3(1), dim3(1), 0, s, p);
-    PC_HIP_CHECK(hipGetLastError());
-  }
+  if (!final_queued) PC_TRY(final_work(nullptr));
   if (st) {
-    hipLaunchKernelGGL(k_stats_out, dim3(1), dim3(64), 0, s, (const double*)W->scal,
-                       (const int32_t*)W->flag, W->hscal, W->hflag);
-    PC_HIP_CHECK(hipGetLastError());
     PC_HIP_CHECK(hipEventRecord(W->ev[0], s));
     PC_HIP_CHECK(hipEventSynchronize(W->ev[0]));
     volatile double* hs = W->hscal;
