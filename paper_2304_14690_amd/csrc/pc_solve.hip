@@ -126,6 +126,27 @@ __device__ __forceinline__ double resid_at(const double* __restrict__ b,
   return b[p] - rscale * lap;
 }
 
+// The same residual at cell (i, j, k) of flat index p, with the coordinates
+// known to the caller (no divisions).
+__device__ __forceinline__ double resid_ijk(const double* __restrict__ b,
+                                            const double* __restrict__ phi, int64_t p, int i,
+                                            int j, int k, int d, int32_t n0, int32_t n1,
+                                            int32_t n2, const double* ih2, double rscale) {
+  const int64_t s1 = n0, s2 = (int64_t)n0 * n1;
+  double c = phi[p];
+  double xm = i > 0 ? phi[p - 1] : c;
+  double xp = i < n0 - 1 ? phi[p + 1] : c;
+  double ym = j > 0 ? phi[p - s1] : c;
+  double yp = j < n1 - 1 ? phi[p + s1] : c;
+  double lap = ((xp - c) - (c - xm)) * ih2[0] + ((yp - c) - (c - ym)) * ih2[1];
+  if (d == 3) {
+    double zm = k > 0 ? phi[p - s2] : c;
+    double zp = k < n2 - 1 ? phi[p + s2] : c;
+    lap += ((zp - c) - (c - zm)) * ih2[2];
+  }
+  return b[p] - rscale * lap;
+}
+
 // Radix-4 / radix-2 Stockham FFT of the C lines held in LDS (complex view,
 // line c at zc + c*ls).  B butterflies per thread per radix-4 stage.
 template <typename TC, int B, bool INV>
@@ -811,10 +832,12 @@ __global__ void __launch_bounds__(512) dct_rad(LineArgs<TC> A) {
   const cplx<TC> tNb = Tb.tN[t];
   const cplx<TC> t4b = Tb.t4N[t];
 
+  // coordinates of this line's cells for the residual (rows: x varies)
+  const int lj = rows ? lo % A.n1 : 0, lk = rows ? lo / A.n1 : 0;
   auto load = [&](int n) -> TC {
     int64_t p = lb + (int64_t)n * st;
     if (LD == LD_RESID) {
-      double r = resid_at(A.rb, A.rphi, p, A.d, A.n0, A.n1, A.n2, A.ih2, A.rscale);
+      double r = resid_ijk(A.rb, A.rphi, p, n, lj, lk, A.d, A.n0, A.n1, A.n2, A.ih2, A.rscale);
       if (A.sub) r -= *A.sub;
       return (TC)r;
     } else if (A.sub) {
@@ -832,17 +855,24 @@ __global__ void __launch_bounds__(512) dct_rad(LineArgs<TC> A) {
   // value of position n of line tcc goes to real index pos(n) of its LDS region
   auto tile_load = [&](auto pos) {
     const int64_t p0 = lbase[0] + tcc + (int64_t)tn0 * st;
+    int ti_x = 0, to = 0;
+    if (LD == LD_RESID) line_base(A, tile, tcc, &ti_x, &to);
     const int64_t dp = (int64_t)T * st;
     TC* zl = zr0 + 2 * tcc * LS;
     if (LD == LD_RESID) {
-      // the residual reads 5-7 values per point: batches of 8 points
-#pragma unroll
+      // the residual reads 5-7 values per point: batches of 8 points, the
+      // batch loop kept rolled so that the kernel stays small
+#pragma unroll 1
       for (int r0 = 0; r0 < NV; r0 += 8) {
         TC v[8];
 #pragma unroll
         for (int r = 0; r < 8; ++r) {
-          double x = resid_at(A.rb, A.rphi, p0 + (r0 + r) * dp, A.d, A.n0, A.n1, A.n2, A.ih2,
-                              A.rscale);
+          // strided line along axis 1 (y) or 2 (z) at x position ti_x, the
+          // other coordinate to
+          const int pn = tn0 + (r0 + r) * T;
+          const int cj = A.axis == 1 ? pn : to, ck = A.axis == 1 ? to : pn;
+          double x = resid_ijk(A.rb, A.rphi, p0 + (r0 + r) * dp, ti_x, cj, ck, A.d, A.n0, A.n1,
+                               A.n2, A.ih2, A.rscale);
           if (A.sub) x -= *A.sub;
           v[r] = (TC)x;
         }
@@ -868,7 +898,19 @@ __global__ void __launch_bounds__(512) dct_rad(LineArgs<TC> A) {
 
   cplx<TC> a[RT];
   if (OP != OP_INV) {
-    if (rows) {
+    if (rows && LD == LD_RESID) {
+      // the residual reads 5-7 values per point: batches of 8 points, the
+      // batch loop kept rolled so that the kernel stays small
+#pragma unroll 1
+      for (int i0 = 0; i0 < NV; i0 += 8) {
+        TC xv[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) xv[i] = load(t + T * (i0 + i));
+#pragma unroll
+        for (int i = 0; i < 8; ++i) zr[vpad(mk_pos(t + T * (i0 + i), N))] = xv[i];
+      }
+      line_sync<T>();
+    } else if (rows) {
       // coalesced loads, reordered into Makhoul order through LDS
       TC xv[NV];
 #pragma unroll
