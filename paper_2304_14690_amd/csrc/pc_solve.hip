@@ -531,6 +531,15 @@ __device__ __forceinline__ void dftR(cplx<TC>* a) {
   }
 }
 
+// Load of a table entry whose address is the same in every lane, through
+// the scalar data cache (read only): the value lands in scalar registers
+// instead of occupying vector registers and a vector memory slot.
+template <typename TC>
+__device__ __forceinline__ cplx<TC> ldu(const cplx<TC>* p) {
+  const __attribute__((address_space(4))) TC* q = (const __attribute__((address_space(4))) TC*)(p);
+  return {q[0], q[1]};
+}
+
 // LDS index of complex element i of a line (one pad slot per 16).
 __device__ __forceinline__ int lpad(int i) { return i + (i >> 4); }
 
@@ -615,7 +624,7 @@ __device__ __forceinline__ void r16_final(cplx<TC>* a, int T, const R16Tw<TC>& t
     cplx<TC> v[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) v[r] = a[b + NB * r];
-    const cplx<TC> w = b ? cmul(tw.fin, twH[T * b]) : tw.fin;  // twH[t + T b]
+    const cplx<TC> w = b ? cmul(tw.fin, ldu(twH + T * b)) : tw.fin;  // twH[t + T b]
     cplx<TC> wr = w;
 #pragma unroll
     for (int r = 1; r < R; ++r) {
@@ -710,7 +719,7 @@ __device__ __forceinline__ void rad_final(cplx<TC>* a, int T, cplx<TC> fin,
     cplx<TC> v[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) v[r] = a[b + NB * r];
-    const cplx<TC> w = b ? cmul(fin, twH[T * b]) : fin;  // twH[t + T b]
+    const cplx<TC> w = b ? cmul(fin, ldu(twH + T * b)) : fin;  // twH[t + T b]
     cplx<TC> wr = w;
 #pragma unroll
     for (int r = 1; r < R; ++r) {
@@ -944,8 +953,8 @@ __global__ void __launch_bounds__(512) dct_rad(LineArgs<TC> A) {
       cplx<TC> E = {(Zk.re + Zc.re) * TC(0.5), (Zk.im + Zc.im) * TC(0.5)};
       cplx<TC> D = {(Zk.re - Zc.re) * TC(0.5), (Zk.im - Zc.im) * TC(0.5)};
       cplx<TC> O = {D.im, -D.re};
-      const cplx<TC> wN = q ? cmul(tNb, Tb.tN[T * q]) : tNb;   // tN[k]
-      const cplx<TC> w4 = q ? cmul(t4b, Tb.t4N[T * q]) : t4b;  // t4N[k]
+      const cplx<TC> wN = q ? cmul(tNb, ldu(Tb.tN + T * q)) : tNb;   // tN[k]
+      const cplx<TC> w4 = q ? cmul(t4b, ldu(Tb.t4N + T * q)) : t4b;  // t4N[k]
       cplx<TC> WO = cmul(wN, O);
       cplx<TC> Y = cmul(w4, cadd(E, WO));
       TC xa = TC(2) * Y.re;   // X[k]
@@ -1007,8 +1016,8 @@ __global__ void __launch_bounds__(512) dct_rad(LineArgs<TC> A) {
 #pragma unroll
     for (int q = 0; q < RT; ++q) {
       const int k = t + T * q;
-      const cplx<TC> wN = q ? cmul(tNb, Tb.tN[T * q]) : tNb;
-      const cplx<TC> w4 = q ? cmul(t4b, Tb.t4N[T * q]) : t4b;
+      const cplx<TC> wN = q ? cmul(tNb, ldu(Tb.tN + T * q)) : tNb;
+      const cplx<TC> w4 = q ? cmul(t4b, ldu(Tb.t4N + T * q)) : t4b;
       TC xhk = zr[xpad(H - k)];
       TC xhpk = zr[xpad(H + k)];
       a[q] = pre_own(ya[q], k ? yb[q] : TC(0), xhk, xhpk, w4, wN);
@@ -1043,8 +1052,8 @@ __global__ void __launch_bounds__(512) dct_rad(LineArgs<TC> A) {
 #pragma unroll
     for (int q = 0; q < RT; ++q) {
       const int k = t + T * q;
-      const cplx<TC> wN = q ? cmul(tNb, Tb.tN[T * q]) : tNb;
-      const cplx<TC> w4 = q ? cmul(t4b, Tb.t4N[T * q]) : t4b;
+      const cplx<TC> wN = q ? cmul(tNb, ldu(Tb.tN + T * q)) : tNb;
+      const cplx<TC> w4 = q ? cmul(t4b, ldu(Tb.t4N + T * q)) : t4b;
       TC xhk = zr[xpad(H - k)];
       TC xhpk = zr[xpad(H + k)];
       a[q] = pre_own(xk[q], k ? xn[q] : TC(0), xhk, xhpk, w4, wN);
