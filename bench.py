@@ -374,12 +374,16 @@ def serving(args):
     del ex, sch, ds
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
-    per_size = {}
-    for (d, N) in sizes:
-        lat = [1e3 * r.latency for r in mix if (r.d, r.N) == (d, N)]
-        if lat:
-            per_size[f"{N}^{d}"] = {"n": len(lat), "p50_ms": float(np.percentile(lat, 50)),
-                                    "p99_ms": float(np.percentile(lat, 99))}
+    def by_size(reqs):
+        out = {}
+        for (d, N) in sizes:
+            lat = [1e3 * r.latency for r in reqs if (r.d, r.N) == (d, N)]
+            if lat:
+                out[f"{N}^{d}"] = {"n": len(lat), "p50_ms": round(float(np.percentile(lat, 50)), 3),
+                                   "p99_ms": round(float(np.percentile(lat, 99)), 3)}
+        return out
+    per_size = {"mix": by_size(mix), "fp64_batched": by_size(out_f64),
+                "fp64_one_at_a_time": by_size(out_base)}
     return {"workload": f"Poisson arrivals {args.serve_rate:g}/s for {args.serve_seconds:g} s, "
                         "sizes uniform over 128^2, 512^2, 2048^2, 64^3, 128^3, 256^3, "
                         "precision uniform over f64 and f32+f64 correction (2 sweeps), "
@@ -388,7 +392,7 @@ def serving(args):
             "geometries": sum(n_geom.values()), "budget_gb": round(budget / 2**30, 1),
             "setup_s": {"data": round(t_data, 2), "warm_build": round(t_warm, 2)},
             "mix": s_mix, "fp64_batched": s_f64, "fp64_one_at_a_time": s_base,
-            "mix_per_size": per_size}
+            "per_size": per_size}
 
 
 def measured_traffic(kernel, workload, G):
