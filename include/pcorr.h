@@ -166,7 +166,8 @@ int pc_plan_destroy(pc_plan* plan);
  *   mode PC_MIXED: b_dev, phi_dev float64 [G]; transforms in float32 with
  *                  `sweeps` float64 defect-correction sweeps
  *                  r = b - mean(b) - lap_h phi, phi += solve32(r).
- * b_dev and phi_dev may alias (in-place).  bmean_dev (nullable) receives
+ * b_dev and phi_dev may alias (in place) in PC_F64 and PC_F32, not in
+ * PC_MIXED (the residual re-reads b).  bmean_dev (nullable) receives
  * mean(b) as one float64.  ws: a workspace of this plan (nullable: the
  * plan's own, which makes concurrent calls on the plan race). */
 int pc_poisson_fft_solve(const pc_plan* plan, int mode, const void* b_dev, void* phi_dev,
@@ -243,7 +244,9 @@ int pc_grad_to_nodes(const pc_geom* geom, int dtype, const void* phi_dev, void* 
  * of Sec. 2.3, num = sum (|g_new| - |g_old|)^2 and den = sum |g_old|^2, into
  * sums_dev[0..1] (float64, deterministic order), sets *conv_dev = 1 if
  * num < tol * den or num == 0 (else 0), and overwrites g_dev with g_new.
- * u_dev [d][M] (dtype); grad_ib_dev, g_dev [d][n_ib] (dtype). */
+ * u_dev [d][M] (dtype); grad_ib_dev, g_dev [d][n_ib] (dtype).  Allocates
+ * its own device scratch and synchronises `stream` before freeing it
+ * (pc_pressure_correct runs the same step without either). */
 int pc_ib_update(const pc_geom* geom, int dtype, const void* u_dev, const void* grad_ib_dev,
                  void* g_dev, double tol, double* sums_dev, int32_t* conv_dev, void* stream);
 
@@ -274,11 +277,16 @@ int64_t pc_workspace_bytes(const pc_plan* plan, const pc_geom* geom, int mode);
  *   the IB force times dt (Sec. 2.3: taken from the previous time step) and
  *   its final value.  NULL starts from zero.
  *   stats (nullable) is filled after the call synchronises `stream`.
- * The host waits once per IB iteration for that iteration's 4-byte
- * convergence flag (written by the device into pinned host memory) while
- * the next iteration is already queued; a queued iteration after
- * convergence exits at once on a device-side flag.  Not when fixed_it > 0.
- * Returns PC_WARN_IB_NOT_CONVERGED when max_it is reached first. */
+ *   ws: a workspace created for this plan, geometry and mode, or NULL for
+ *   the geometry's own (created on first use, replaced when the mode
+ *   changes); calls that share a workspace, including the geometry's own,
+ *   must not overlap.
+ * The host waits once per IB iteration for that iteration's convergence
+ * flag (written by the device into pinned host memory) while the next
+ * iteration is already queued; a queued iteration after convergence exits
+ * at once on a device-side flag.  Not when fixed_it > 0.  u_out_dev must
+ * not alias u_dev.  Returns PC_WARN_IB_NOT_CONVERGED when max_it is
+ * reached first. */
 int pc_pressure_correct(const pc_geom* geom, const pc_plan* plan, int mode, const void* u_dev,
                         double dt, void* u_out_dev, void* p_dev, void* g_inout_dev,
                         const pc_ib_opts* opts, pc_stats* stats, pc_workspace* ws,
