@@ -4,7 +4,7 @@ Neumann walls in Sec. 3.3).  Test infrastructure only."""
 from __future__ import annotations
 
 import dataclasses
-from typing import Tuple
+from typing import Optional, Tuple
 
 import numpy as np
 
@@ -14,6 +14,17 @@ class Grid:
     d: int
     n: Tuple[int, ...]      # cells per axis
     h: Tuple[float, ...]    # spacing per axis; box is [0, n_a h_a]
+    # boundary condition per axis: "neumann" (homogeneous, Eq. 7, mirror
+    # ghosts) or "periodic" (the lateral condition of the paper's cases in
+    # Sec. 3); None means Neumann everywhere
+    bc: Optional[Tuple[str, ...]] = None
+
+    def periodic(self, a: int) -> bool:
+        return self.bc is not None and self.bc[a] == "periodic"
+
+    @property
+    def length(self) -> Tuple[float, ...]:
+        return tuple(self.n[a] * self.h[a] for a in range(self.d))
 
     @property
     def G(self) -> int:

@@ -7,12 +7,14 @@ transform and eigenvalues to a table of Fuka 2015 that is not reproduced):
 
   * grid: staggered / cell-centred (the grid used with Neumann walls in
     Sec. 3.3);
-  * boundary condition: the homogeneous Neumann condition, Eq. (7), on every
-    box face, discretised with mirror ghosts phi_{-1} = phi_0,
-    phi_n = phi_{n-1};
+  * boundary condition per axis: the homogeneous Neumann condition, Eq. (7),
+    discretised with mirror ghosts phi_{-1} = phi_0, phi_n = phi_{n-1}; or
+    periodic (phi_{-1} = phi_{n-1}, phi_n = phi_0), the lateral condition of
+    the verification cases of Sec. 3;
   * method: central finite differences (the variant used for the reported
     timings of Sec. 3.2).  The mirror-ghost 3-point operator is diagonalised
-    by the DCT-II, with eigenvalues -(4/h^2) sin^2(pi k / (2n));
+    by the DCT-II, with eigenvalues -(4/h^2) sin^2(pi k / (2n)); the periodic
+    one by the DFT, with eigenvalues -(4/h^2) sin^2(pi k / n);
   * zero mode: with Neumann walls everywhere the operator is singular; the
     mean of the right-hand side (the compatibility defect) is removed and
     reported, and the solution is taken with zero mean (the mode-0
@@ -30,13 +32,19 @@ import scipy.fft as sfft
 from .grid import Grid
 
 
+def eigenvalues_1d(grid: Grid, a: int) -> np.ndarray:
+    """1D eigenvalues of axis a: -(4/h^2) sin^2(pi k / (2n)) (Neumann, DCT-II
+    index k) or -(4/h^2) sin^2(pi k / n) (periodic, DFT index k)."""
+    k = np.arange(grid.n[a], dtype=np.float64)
+    den = grid.n[a] if grid.periodic(a) else 2.0 * grid.n[a]
+    return -(4.0 / (grid.h[a] ** 2)) * np.sin(np.pi * k / den) ** 2
+
+
 def eigenvalues(grid: Grid) -> np.ndarray:
-    """Sum of the 1D eigenvalues -(4/h_a^2) sin^2(pi k_a / (2 n_a)), as an
-    array of the grid's (z, y, x) shape."""
+    """Sum of the 1D eigenvalues, as an array of the grid's (z, y, x) shape."""
     lam = np.zeros(grid.shape_zyx)
     for a in range(grid.d):
-        k = np.arange(grid.n[a], dtype=np.float64)
-        la = -(4.0 / (grid.h[a] ** 2)) * np.sin(np.pi * k / (2.0 * grid.n[a])) ** 2
+        la = eigenvalues_1d(grid, a)
         shape = [1] * grid.d
         shape[grid.d - 1 - a] = grid.n[a]
         lam = lam + la.reshape(shape)
@@ -48,33 +56,44 @@ def solve(grid: Grid, b: np.ndarray, workers: int = -1):
     Returns (phi flat [G], bmean)."""
     bm = float(np.mean(b))
     B = grid.to_array(b - bm)
-    Bh = sfft.dctn(B, type=2, workers=workers)
+    neu = tuple(grid.d - 1 - a for a in range(grid.d) if not grid.periodic(a))
+    per = tuple(grid.d - 1 - a for a in range(grid.d) if grid.periodic(a))
+    Bh = sfft.dctn(B, type=2, axes=neu, workers=workers) if neu else B
+    if per:
+        Bh = sfft.fftn(Bh, axes=per, workers=workers)
     lam = eigenvalues(grid)
     lam.flat[0] = 1.0
     Ph = Bh / lam
     Ph.flat[0] = 0.0
-    phi = sfft.idctn(Ph, type=2, workers=workers)
+    if per:
+        Ph = sfft.ifftn(Ph, axes=per, workers=workers).real
+    phi = sfft.idctn(Ph, type=2, axes=neu, workers=workers) if neu else Ph
     return np.ascontiguousarray(phi).reshape(-1), bm
 
 
 def laplacian(grid: Grid, phi: np.ndarray) -> np.ndarray:
-    """Mirror-ghost central-difference Laplacian (the operator solve()
-    inverts).  phi flat [G] -> flat [G]."""
+    """Central-difference Laplacian with mirror ghosts (Neumann axes) or
+    wrap-around (periodic axes): the operator solve() inverts.  phi flat
+    [G] -> flat [G]."""
     P = grid.to_array(phi)
     out = np.zeros_like(P)
     for a in range(grid.d):
         ax = grid.d - 1 - a
-        lo = np.concatenate([np.take(P, [0], axis=ax), P], axis=ax)
-        hi = np.concatenate([P, np.take(P, [grid.n[a] - 1], axis=ax)], axis=ax)
-        up = np.take(hi, np.arange(1, grid.n[a] + 1), axis=ax)
-        dn = np.take(lo, np.arange(0, grid.n[a]), axis=ax)
+        if grid.periodic(a):
+            up = np.roll(P, -1, axis=ax)
+            dn = np.roll(P, 1, axis=ax)
+        else:
+            lo = np.concatenate([np.take(P, [0], axis=ax), P], axis=ax)
+            hi = np.concatenate([P, np.take(P, [grid.n[a] - 1], axis=ax)], axis=ax)
+            up = np.take(hi, np.arange(1, grid.n[a] + 1), axis=ax)
+            dn = np.take(lo, np.arange(0, grid.n[a]), axis=ax)
         out = out + (up - 2.0 * P + dn) / (grid.h[a] ** 2)
     return out.reshape(-1)
 
 
 def laplacian_dense(grid: Grid) -> np.ndarray:
     """The same operator as a dense [G, G] matrix, assembled cell by cell
-    (for tiny grids only)."""
+    with its ghost rule per axis (for tiny grids only)."""
     G = grid.G
     L = np.zeros((G, G))
     strides = [int(np.prod(grid.n[:a])) for a in range(grid.d)]
@@ -88,7 +107,10 @@ def laplacian_dense(grid: Grid) -> np.ndarray:
             inv = 1.0 / grid.h[a] ** 2
             for step in (-1, 1):
                 c = coords[a] + step
-                q = p if (c < 0 or c >= grid.n[a]) else p + step * strides[a]
+                if grid.periodic(a):
+                    q = p + ((c % grid.n[a]) - coords[a]) * strides[a]
+                else:
+                    q = p if (c < 0 or c >= grid.n[a]) else p + step * strides[a]
                 L[p, q] += inv
                 L[p, p] -= inv
     return L

@@ -105,3 +105,88 @@ def test_exact_rational_tiny():
     phi, bm = poisson.solve(grid, np.array([float(v) for v in b]))
     assert bm == pytest.approx(float(sol[-1]), abs=1e-15)
     np.testing.assert_allclose(phi, [float(v) for v in sol[:-1]], atol=1e-14)
+
+
+# ---- periodic and mixed periodic x Neumann boxes (the lateral condition of
+# the verification cases of Sec. 3) ----------------------------------------------
+
+def _eigvec_mixed(grid, ks, phases):
+    """Products of cos(pi k (i + 1/2) / n) along Neumann axes and
+    cos(2 pi k i / n + theta) along periodic axes, with their eigenvalues
+    written out from the 3-point stencil (not from oracle.poisson)."""
+    idx = np.indices(grid.shape_zyx)
+    v = np.ones(grid.shape_zyx)
+    lam = 0.0
+    for a in range(grid.d):
+        i = idx[grid.d - 1 - a]
+        if grid.periodic(a):
+            v = v * np.cos(2 * np.pi * ks[a] * i / grid.n[a] + phases[a])
+            lam += (2 * np.cos(2 * np.pi * ks[a] / grid.n[a]) - 2) / grid.h[a] ** 2
+        else:
+            v = v * np.cos(np.pi * ks[a] * (i + 0.5) / grid.n[a])
+            lam += (2 * np.cos(np.pi * ks[a] / grid.n[a]) - 2) / grid.h[a] ** 2
+    return v.reshape(-1), lam
+
+
+@pytest.mark.parametrize("n,h,bc,ks,ph", [
+    ((64, 64), (1 / 64, 1 / 64), ("periodic", "periodic"), (3, 5), (0.3, 1.1)),
+    ((64, 32), (1 / 64, 1 / 32), ("periodic", "neumann"), (7, 4), (2.0, 0.0)),
+    ((16, 32), (0.1, 0.03), ("neumann", "periodic"), (15, 1), (0.0, 0.7)),
+    ((16, 8, 32), (1 / 16, 0.2, 0.01), ("periodic", "neumann", "periodic"), (2, 7, 9),
+     (0.5, 0.0, 2.5)),
+    ((32, 32), (1 / 32, 1 / 32), ("periodic", "periodic"), (16, 16), (0.4, 0.9)),
+])
+def test_eigenfunctions_mixed(n, h, bc, ks, ph):
+    grid = Grid(len(n), n, h, bc)
+    v, lam = _eigvec_mixed(grid, ks, ph)
+    np.testing.assert_allclose(poisson.laplacian(grid, v), lam * v,
+                               atol=1e-12 * abs(lam) * np.abs(v).max())
+    phi, bm = poisson.solve(grid, v)
+    assert abs(bm) < 1e-14
+    np.testing.assert_allclose(phi, v / lam, rtol=0, atol=1e-13 * np.abs(v / lam).max())
+
+
+@pytest.mark.parametrize("n,h,bc", [
+    ((3, 5), (0.3, 0.2), ("periodic", "neumann")),
+    ((4, 6), (0.25, 0.1), ("periodic", "periodic")),
+    ((5, 3), (0.2, 0.4), ("neumann", "periodic")),
+    ((4, 4, 4), (0.25, 0.25, 0.25), ("periodic", "neumann", "periodic")),
+    ((2, 3, 5), (0.5, 0.1, 0.7), ("neumann", "periodic", "neumann")),
+])
+def test_bordered_lu_mixed(rng, n, h, bc):
+    grid = Grid(len(n), n, h, bc)
+    b = rng.normal(size=grid.G)
+    phi, bm = poisson.solve(grid, b)
+    phi2, mu = poisson.solve_bordered(grid, b)
+    assert mu == pytest.approx(np.mean(b), abs=1e-13)
+    assert bm == pytest.approx(mu, abs=1e-13)
+    np.testing.assert_allclose(phi, phi2, atol=1e-12 * np.abs(phi2).max())
+
+
+def test_dense_periodic_operator_matches_stencil(rng):
+    grid = Grid(3, (3, 4, 5), (0.2, 0.3, 0.5), ("periodic", "neumann", "periodic"))
+    v = rng.normal(size=grid.G)
+    L = poisson.laplacian_dense(grid)
+    np.testing.assert_allclose(L @ v, poisson.laplacian(grid, v),
+                               atol=1e-12 * np.abs(v).max() / 0.04)
+    # the wrap-around couples the first and last cells of a periodic row
+    assert L[0, 2] == pytest.approx(1 / 0.04) and L[0, 1] == pytest.approx(1 / 0.04)
+
+
+@pytest.mark.parametrize("n,bc", [((64, 64), ("periodic", "neumann")),
+                                  ((16, 16, 16), ("periodic", "periodic", "periodic"))])
+def test_residual_vanishes_mixed(rng, n, bc):
+    grid = Grid(len(n), n, tuple(1.0 / v for v in n), bc)
+    b = rng.normal(size=grid.G) + 0.7
+    phi, bm = poisson.solve(grid, b)
+    r = (b - bm) - poisson.laplacian(grid, phi)
+    assert np.linalg.norm(r) / np.linalg.norm(b - bm) < 1e-13
+
+
+def test_exact_rational_periodic():
+    grid = Grid(2, (3, 2), (1.0, 0.5), ("periodic", "neumann"))
+    b = [Fraction(v) for v in (1, -2, 3, 5, 0, -4)]
+    sol = _exact_solve(grid, b)
+    phi, bm = poisson.solve(grid, np.array([float(v) for v in b]))
+    assert bm == pytest.approx(float(sol[-1]), abs=1e-15)
+    np.testing.assert_allclose(phi, [float(v) for v in sol[:-1]], atol=1e-14)
