@@ -80,6 +80,11 @@ extern "C" {
 #define PC_NEAR_IB 1 /* grid points whose stencil holds a B or V node        */
 #define PC_IB 2      /* boundary and virtual nodes, in ascending node order  */
 
+/* ---- boundary condition of a grid axis ------------------------------------ */
+#define PC_BC_NEUMANN 0  /* homogeneous Neumann on both faces (Eq. 7)        */
+#define PC_BC_PERIODIC 1 /* periodic (the lateral condition of the paper's   */
+                         /* verification cases, Sec. 3)                     */
+
 #define PC_KIND_F 0
 #define PC_KIND_B 1
 #define PC_KIND_V 2
@@ -153,6 +158,17 @@ int pc_last_error(char* buf, size_t n);
  * float32 copies).  n[a] must be a power of two in [8, 4096].  Synchronises
  * `stream`.  Release with pc_plan_destroy. */
 int pc_plan_create(int d, const int32_t* n, const double* h, void* stream, pc_plan** out);
+
+/* pc_plan_create with a boundary condition per axis, bc[a] = PC_BC_NEUMANN
+ * or PC_BC_PERIODIC (NULL: Neumann everywhere).  A periodic axis of n cells
+ * (n a power of two in [32, 4096]) joins cell n-1 to cell 0; its transform
+ * is the real DFT, packed into n reals, and its 1D eigenvalues are
+ * -(4/h_a^2) sin^2(pi k / n_a), those of the wrap-around central-difference
+ * Laplacian.  Every entry point that takes the plan follows its axes'
+ * conditions: the solve, and the WLS stencils of pc_wls_build (a periodic
+ * axis wraps node positions and neighbourhoods around the box). */
+int pc_plan_create_bc(int d, const int32_t* n, const double* h, const int32_t* bc,
+                      void* stream, pc_plan** out);
 int pc_plan_destroy(pc_plan* plan);
 
 /* ---- the Poisson solve ---------------------------------------------------- */

@@ -48,7 +48,7 @@ size_t axis_table_reals(int N) {
   return 2 * (size_t)H + 2 * (size_t)(H + 1) * 2 + (size_t)N;
 }
 
-void fill_axis_tables(int N, double h, std::vector<double>& out) {
+void fill_axis_tables(int N, double h, bool periodic, std::vector<double>& out) {
   const long double PI = 3.141592653589793238462643383279502884L;
   int H = N / 2;
   out.clear();
@@ -68,8 +68,11 @@ void fill_axis_tables(int N, double h, std::vector<double>& out) {
     out.push_back((double)cosl(a));
     out.push_back((double)-sinl(a));
   }
+  // eigenvalue of slot k: DCT-II index k (Neumann) or mode min(k, N-k)
+  // (periodic; sin^2 is the same for both)
+  const long double den = periodic ? (long double)N : 2.0L * (long double)N;
   for (int k = 0; k < N; ++k) {
-    long double sn = sinl(PI * (long double)k / (2.0L * (long double)N));
+    long double sn = sinl(PI * (long double)k / den);
     out.push_back((double)(-(4.0L / ((long double)h * (long double)h)) * sn * sn));
   }
 }
@@ -127,12 +130,22 @@ int pc_last_error(char* buf, size_t n) {
 }
 
 int pc_plan_create(int d, const int32_t* n, const double* h, void* stream, pc_plan** out) {
+  return pc_plan_create_bc(d, n, h, nullptr, stream, out);
+}
+
+int pc_plan_create_bc(int d, const int32_t* n, const double* h, const int32_t* bc,
+                      void* stream, pc_plan** out) {
   if (!out || !n || !h) return fail(PC_ERR_INVALID_ARG, "pc_plan_create: null argument");
   *out = nullptr;
   if (d != 2 && d != 3) return fail(PC_ERR_UNSUPPORTED_SIZE, "d must be 2 or 3");
   for (int a = 0; a < d; ++a) {
+    const int32_t b = bc ? bc[a] : PC_BC_NEUMANN;
+    if (b != PC_BC_NEUMANN && b != PC_BC_PERIODIC)
+      return fail(PC_ERR_INVALID_ARG, "bc[a] must be PC_BC_NEUMANN or PC_BC_PERIODIC");
     if (!is_pow2(n[a]) || n[a] < 8 || n[a] > 4096)
       return fail(PC_ERR_UNSUPPORTED_SIZE, "n[a] must be a power of two in [8, 4096]");
+    if (b == PC_BC_PERIODIC && n[a] < 32)
+      return fail(PC_ERR_UNSUPPORTED_SIZE, "a periodic axis needs a power of two in [32, 4096]");
     if (!(h[a] > 0.0) || !std::isfinite(h[a]))
       return fail(PC_ERR_INVALID_ARG, "h[a] must be positive and finite");
   }
@@ -148,6 +161,7 @@ int pc_plan_create(int d, const int32_t* n, const double* h, void* stream, pc_pl
   for (int a = 0; a < 3; ++a) {
     P->n[a] = a < d ? n[a] : 1;
     P->h[a] = a < d ? h[a] : 1.0;
+    P->bc[a] = (a < d && bc) ? bc[a] : PC_BC_NEUMANN;
     P->G *= P->n[a];
   }
   if (hipGetDevice(&P->device) != hipSuccess) {
@@ -158,7 +172,7 @@ int pc_plan_create(int d, const int32_t* n, const double* h, void* stream, pc_pl
   size_t offs[3];
   for (int a = 0; a < d; ++a) {
     offs[a] = all.size();
-    fill_axis_tables(P->n[a], P->h[a], one);
+    fill_axis_tables(P->n[a], P->h[a], P->bc[a] == PC_BC_PERIODIC, one);
     all.insert(all.end(), one.begin(), one.end());
   }
   std::vector<float> all32(all.size());

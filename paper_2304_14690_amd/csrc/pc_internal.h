@@ -48,7 +48,10 @@ struct cplx {
 //   twH[j]  = exp(-2 pi i j / H),      j = 0..H-1   (half-length FFT)
 //   tN[k]   = exp(-2 pi i k / N),      k = 0..H     (real-FFT split)
 //   t4N[k]  = exp(-i pi k / (2N)),     k = 0..H     (cosine-transform shift)
-//   lam[k]  = -(4 / h^2) sin^2(pi k / (2N)), k = 0..N-1
+//   lam[s]  = the 1D eigenvalue of slot s, s = 0..N-1:
+//             -(4 / h^2) sin^2(pi s / (2N))  (Neumann axis, DCT-II index s)
+//             -(4 / h^2) sin^2(pi s / N)     (periodic axis: slots s and N-s
+//                                             both hold mode s)
 template <typename T>
 struct AxisTables {
   const cplx<T>* twH;
@@ -64,6 +67,7 @@ struct pc_plan {
   int d;
   int32_t n[3];
   double h[3];
+  int32_t bc[3];  // PC_BC_NEUMANN or PC_BC_PERIODIC per axis
   int64_t G;
   int device;
   // one allocation per precision holding all axis tables

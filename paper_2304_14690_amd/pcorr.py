@@ -30,12 +30,14 @@ PC_ERR_NO_DEVICE = -7
 PC_F64, PC_F32, PC_MIXED = 1, 2, 3
 PC_ALL, PC_NEAR_IB, PC_IB = 0, 1, 2
 PC_KIND_F, PC_KIND_B, PC_KIND_V = 0, 1, 2
+PC_BC_NEUMANN, PC_BC_PERIODIC = 0, 1
+BCS = {"neumann": PC_BC_NEUMANN, "periodic": PC_BC_PERIODIC}
 
 MODES = {"f64": PC_F64, "f32": PC_F32, "mixed": PC_MIXED}
 
 # every symbol include/pcorr.h declares
 EXPORTS = [
-    "pc_version", "pc_last_error", "pc_plan_create", "pc_plan_destroy",
+    "pc_version", "pc_last_error", "pc_plan_create", "pc_plan_create_bc", "pc_plan_destroy",
     "pc_poisson_fft_solve", "pc_wls_build", "pc_geom_destroy", "pc_geom_info",
     "pc_geom_export", "pc_div_to_grid", "pc_grad_to_nodes", "pc_ib_update", "pc_project",
     "pc_workspace_create", "pc_workspace_destroy", "pc_workspace_bytes",
@@ -83,6 +85,7 @@ def _load():
         "pc_version": ([], ctypes.c_int),
         "pc_last_error": ([ctypes.c_char_p, ctypes.c_size_t], ctypes.c_int),
         "pc_plan_create": ([ctypes.c_int, vp, vp, vp, ctypes.POINTER(vp)], ctypes.c_int),
+        "pc_plan_create_bc": ([ctypes.c_int, vp, vp, vp, vp, ctypes.POINTER(vp)], ctypes.c_int),
         "pc_plan_destroy": ([vp], ctypes.c_int),
         "pc_poisson_fft_solve": ([vp, ctypes.c_int, vp, vp, ctypes.c_int, vp, vp, vp],
                                  ctypes.c_int),
@@ -158,14 +161,26 @@ def _dtype_code(t: torch.Tensor) -> int:
 
 
 class Plan:
-    """Grid and transform tables (pc_plan)."""
+    """Grid and transform tables (pc_plan).  bc: per-axis "neumann" or
+    "periodic" (or the PC_BC_* codes); None is Neumann everywhere."""
 
-    def __init__(self, d: int, n: Sequence[int], h: Sequence[float], stream=None):
+    def __init__(self, d: int, n: Sequence[int], h: Sequence[float], stream=None,
+                 bc: Optional[Sequence] = None):
         nn = (ctypes.c_int32 * 3)(*(list(n) + [1] * (3 - len(n))))
         hh = (ctypes.c_double * 3)(*(list(h) + [1.0] * (3 - len(h))))
         out = ctypes.c_void_p()
-        _check(_lib.pc_plan_create(d, ctypes.addressof(nn), ctypes.addressof(hh),
-                                   _stream(stream), ctypes.byref(out)))
+        if bc is None:
+            _check(_lib.pc_plan_create(d, ctypes.addressof(nn), ctypes.addressof(hh),
+                                       _stream(stream), ctypes.byref(out)))
+            self.bc = ("neumann",) * d
+        else:
+            codes = [BCS[b] if isinstance(b, str) else int(b) for b in bc]
+            bb = (ctypes.c_int32 * 3)(*(codes + [0] * (3 - len(codes))))
+            _check(_lib.pc_plan_create_bc(d, ctypes.addressof(nn), ctypes.addressof(hh),
+                                          ctypes.addressof(bb), _stream(stream),
+                                          ctypes.byref(out)))
+            names = {v: k for k, v in BCS.items()}
+            self.bc = tuple(names.get(c, str(c)) for c in codes)
         self.h_ = out
         self.d, self.n, self.h = d, tuple(n), tuple(h)
         self.G = 1

@@ -51,6 +51,14 @@ def test_host_side_validation():
     assert lib.pc_wls_build(None, None, None, 0, None, None, ctypes.byref(out)) == \
         pcorr.PC_ERR_INVALID_ARG
     assert lib.pc_plan_destroy(None) == pcorr.PC_OK
+    # per-axis conditions: unknown codes, and periodic axes below 32 cells
+    bc = (ctypes.c_int32 * 3)(pcorr.PC_BC_PERIODIC, 7, 0)
+    assert lib.pc_plan_create_bc(2, n, h, bc, None, ctypes.byref(out)) == pcorr.PC_ERR_INVALID_ARG
+    small = (ctypes.c_int32 * 3)(16, 64, 1)
+    bc = (ctypes.c_int32 * 3)(pcorr.PC_BC_PERIODIC, pcorr.PC_BC_NEUMANN, 0)
+    assert lib.pc_plan_create_bc(2, small, h, bc, None, ctypes.byref(out)) == \
+        pcorr.PC_ERR_UNSUPPORTED_SIZE
+    assert "periodic" in pcorr.last_error()
 
 
 def test_no_device_is_an_error_not_a_fallback():
