@@ -9,6 +9,10 @@ float64 with every product and sum rounded separately (no fused multiply-add).
 The index in the key makes the set unique when distances tie exactly, which
 happens for points placed on grid symmetry lines.
 
+Periodic axes (the lateral condition of the verification cases of Sec. 3)
+measure offsets by the minimal image: t = x_s - x_t, then t - L if t > L/2
+or t + L if t < -L/2 (one rounding each), L the box length of the axis.
+
 Test infrastructure only.
 """
 from __future__ import annotations
@@ -17,14 +21,33 @@ import numpy as np
 from scipy.spatial import cKDTree
 
 
-def exact_d2(targets: np.ndarray, sources: np.ndarray, idx: np.ndarray) -> np.ndarray:
+def wrap_offset(t: np.ndarray, L: float) -> np.ndarray:
+    """Minimal-image offset along a periodic axis of length L."""
+    return np.where(t > 0.5 * L, t - L, np.where(t < -0.5 * L, t + L, t))
+
+
+def offsets(targets: np.ndarray, sources: np.ndarray, idx: np.ndarray,
+            lengths=None) -> np.ndarray:
+    """Source-minus-target offsets [T, c, d]; lengths[a] (None for a
+    non-periodic axis) selects the minimal image along axis a."""
+    d = targets.shape[1]
+    out = np.empty(idx.shape + (d,))
+    for a in range(d):
+        t = sources[idx, a] - targets[:, a:a + 1]
+        if lengths is not None and lengths[a] is not None:
+            t = wrap_offset(t, lengths[a])
+        out[..., a] = t
+    return out
+
+
+def exact_d2(targets: np.ndarray, sources: np.ndarray, idx: np.ndarray,
+             lengths=None) -> np.ndarray:
     """Squared distances with the fixed operation order.  targets [T, d],
     sources [S, d], idx [T, c] -> [T, c]."""
-    d = targets.shape[1]
+    X = offsets(targets, sources, idx, lengths)
     acc = None
-    for a in range(d):
-        diff = sources[idx, a] - targets[:, a:a + 1]
-        sq = diff * diff
+    for a in range(targets.shape[1]):
+        sq = X[..., a] * X[..., a]
         acc = sq if acc is None else acc + sq
     return acc
 
@@ -35,48 +58,80 @@ def _sort_by_key(d2: np.ndarray, idx: np.ndarray):
             np.take_along_axis(idx, order, axis=-1))
 
 
-def knn_brute(targets: np.ndarray, sources: np.ndarray, k: int):
+def knn_brute(targets: np.ndarray, sources: np.ndarray, k: int, lengths=None):
     """Definition by exhaustion: every source is a candidate.  O(T*S); for
     tiny inputs and for pinning knn() below."""
     S = sources.shape[0]
     idx = np.broadcast_to(np.arange(S, dtype=np.int64), (targets.shape[0], S)).copy()
-    d2 = exact_d2(targets, sources, idx)
+    d2 = exact_d2(targets, sources, idx, lengths)
     d2s, idxs = _sort_by_key(d2, idx)
     return idxs[:, :k], d2s[:, :k]
 
 
+def _images(sources: np.ndarray, lengths):
+    """The sources and their copies shifted by -L and +L along every
+    periodic axis (3^p copies), as one array; copy c of source i is row
+    c * S + i."""
+    d = sources.shape[1]
+    per = [a for a in range(d) if lengths is not None and lengths[a] is not None]
+    shifts = [np.zeros(d)]
+    for a in per:
+        new = []
+        for sh in shifts:
+            for sgn in (-1.0, 1.0):
+                v = sh.copy()
+                v[a] = sgn * lengths[a]
+                new.append(v)
+        shifts = shifts + new
+    return np.concatenate([sources + sh for sh in shifts], axis=0)
+
+
 def knn(targets: np.ndarray, sources: np.ndarray, k: int, extra: int = 8,
-        workers: int = -1, chunk: int = 1 << 18, tree: cKDTree | None = None):
+        workers: int = -1, chunk: int = 1 << 18, tree: cKDTree | None = None,
+        lengths=None):
     """Same result as knn_brute, found through a k-d tree: the tree proposes
     k+extra candidates, the exact key re-ranks them, and a target whose k-th
     key is not safely inside the candidate radius is re-queried with more
-    candidates.  Returns (idx [T, k] int64, d2 [T, k] float64)."""
+    candidates.  With periodic axes the tree holds every periodic image of
+    the sources; candidates map back to their source and are ranked by the
+    minimal-image key.  Returns (idx [T, k] int64, d2 [T, k] float64)."""
     S = sources.shape[0]
     if k > S:
         raise ValueError("k larger than the number of sources")
     T = targets.shape[0]
-    tree = tree if tree is not None else cKDTree(sources)
+    periodic = lengths is not None and any(v is not None for v in lengths)
+    if tree is None:
+        tree = cKDTree(_images(sources, lengths) if periodic else sources)
+    SX = tree.n
     out_i = np.empty((T, k), dtype=np.int64)
     out_d = np.empty((T, k), dtype=np.float64)
     for s in range(0, T, chunk):
         e = min(T, s + chunk)
         todo = np.arange(s, e)
-        kk = min(S, k + extra)
+        kk = min(SX, k + extra)
         while todo.size:
             dist, cand = tree.query(targets[todo], k=kk, workers=workers)
-            cand = cand.astype(np.int64)
-            d2 = exact_d2(targets[todo], sources, cand)
+            cand = cand.astype(np.int64) % S
+            d2 = exact_d2(targets[todo], sources, cand, lengths)
+            if periodic:
+                # two images of one source: keep one
+                o = np.argsort(cand, axis=1, kind="stable")
+                cs_ = np.take_along_axis(cand, o, 1)
+                dup = np.zeros(cs_.shape, dtype=bool)
+                dup[:, 1:] = cs_[:, 1:] == cs_[:, :-1]
+                d2 = d2.copy()
+                np.put_along_axis(d2, o, np.where(dup, np.inf, np.take_along_axis(d2, o, 1)), 1)
             d2s, cs = _sort_by_key(d2, cand)
             out_i[todo] = cs[:, :k]
             out_d[todo] = d2s[:, :k]
-            if kk == S:
+            if kk == SX:
                 break
             # A source outside the candidate set lies at tree distance
             # >= dist[:, -1]; require a relative margin far above rounding.
             rlim = dist[:, -1]
             safe = d2s[:, k - 1] < (rlim * rlim) * (1.0 - 1e-9)
             todo = todo[~safe]
-            kk = min(S, 2 * kk)
+            kk = min(SX, 2 * kk)
     return out_i, out_d
 
 
@@ -89,15 +144,17 @@ def window_m(k: int, d: int) -> int:
     return m
 
 
-def node_window_base(x: np.ndarray, n, h, m: int) -> np.ndarray:
+def node_window_base(x: np.ndarray, n, h, m: int, periodic=None) -> np.ndarray:
     """Lowest grid line of the m lines nearest to each node along each axis,
-    clamped so the block lies inside the box.  Grid line i sits at
-    (i + 1/2) h, so the m nearest lines start at floor(x/h - m/2 + 1/2).
-    x [T, d] -> [T, d] int64."""
+    clamped so the block lies inside the box (not along a periodic axis,
+    where the block may run past a face and wraps around).  Grid line i sits
+    at (i + 1/2) h, so the m nearest lines start at floor(x/h - m/2 + 1/2).
+    x [T, d] -> [T, d] int64 (unwrapped: -1 or above n - m on a periodic
+    axis)."""
     out = np.empty(x.shape, dtype=np.int64)
     for a in range(x.shape[1]):
         lo = np.floor(x[:, a] / h[a] - (0.5 * m - 0.5)).astype(np.int64)
-        out[:, a] = np.clip(lo, 0, n[a] - m)
+        out[:, a] = lo if (periodic is not None and periodic[a]) else np.clip(lo, 0, n[a] - m)
     return out
 
 
@@ -109,23 +166,30 @@ def knn_grid_window(x: np.ndarray, grid, k: int):
     inside the box).  Unrestricted k-nearest selection can fall on only two
     grid planes next to a box face in 3D (k = 27), where the quadratic fit of
     Eq. (16) is singular; the block always spans at least three lines per
-    axis.  Returns (idx [T, k] flat grid index, d2 [T, k], base [T, d])."""
+    axis.  Along a periodic axis the block is not clamped: its lines past a
+    face are the periodic images of the lines at the other side (flat index
+    of the wrapped line, offset to the unwrapped centre).
+    Returns (idx [T, k] flat grid index, d2 [T, k], base [T, d] wrapped low
+    corner, X [T, k, d] offsets of the selected centres from the node)."""
     d = x.shape[1]
     m = window_m(k, d)
     if any(v < m for v in grid.n):
         raise ValueError("grid smaller than the stencil block")
-    base = node_window_base(x, grid.n, grid.h, m)
+    per = [grid.periodic(a) for a in range(d)]
+    base = node_window_base(x, grid.n, grid.h, m, per)
     offs = np.indices((m,) * d).reshape(d, -1)[::-1].T      # [m^d, d], x fastest
-    cell = base[:, None, :] + offs[None, :, :]              # [T, m^d, d]
+    cell = base[:, None, :] + offs[None, :, :]              # [T, m^d, d], unwrapped
+    wrapped = cell % np.array(grid.n)[None, None, :]
     stride = np.cumprod([1] + list(grid.n[:-1]))
-    flat = np.einsum("tcd,d->tc", cell, stride)
-    centres = np.empty(cell.shape, dtype=np.float64)
+    flat = np.einsum("tcd,d->tc", wrapped, stride)
+    diffs = np.empty(cell.shape, dtype=np.float64)
     for a in range(d):
-        centres[..., a] = (cell[..., a] + 0.5) * grid.h[a]
+        diffs[..., a] = (cell[..., a] + 0.5) * grid.h[a] - x[:, a:a + 1]
     acc = None
     for a in range(d):
-        diff = centres[..., a] - x[:, a:a + 1]
-        sq = diff * diff
+        sq = diffs[..., a] * diffs[..., a]
         acc = sq if acc is None else acc + sq
-    d2s, idxs = _sort_by_key(acc, flat)
-    return idxs[:, :k], d2s[:, :k], base
+    order = np.lexsort((flat, acc), axis=-1)[:, :k]
+    X = np.take_along_axis(diffs, order[:, :, None], axis=1)
+    return (np.take_along_axis(flat, order, 1), np.take_along_axis(acc, order, 1),
+            base % np.array(grid.n)[None, :], X)

@@ -61,17 +61,37 @@ class Stencils:
 def build_stencils(grid: Grid, x: np.ndarray, kind: np.ndarray, k_grid: int, k_node: int,
                    eps: float = _wls.EPS_DEFAULT, support: float = _wls.SUPPORT_DEFAULT,
                    delta: Optional[float] = None, workers: int = -1) -> Stencils:
-    """x: [M, d] node positions; kind: [M]."""
+    """x: [M, d] node positions; kind: [M].  Along a periodic axis of the
+    grid the positions must lie in [0, n h) and offsets are minimal images."""
     delta = _wls.default_delta(grid.h) if delta is None else float(delta)
+    lengths = _lengths(grid, x)
     gc = grid.centres()
-    gi, gd2 = _knn.knn(gc, x, k_grid, workers=workers)
-    gcoef, _, gs = _wls.derivative_coefficients(gc, x, gi, gd2, delta, eps, support)
-    ni, nd2, nbase = _knn.knn_grid_window(x, grid, k_node)
-    ncoef, _, ns = _wls.derivative_coefficients(x, gc, ni, nd2, delta, eps, support)
+    gi, gd2 = _knn.knn(gc, x, k_grid, workers=workers, lengths=lengths)
+    Xg = _knn.offsets(gc, x, gi, lengths) if lengths else None
+    gcoef, _, gs = _wls.derivative_coefficients(gc, x, gi, gd2, delta, eps, support, X=Xg)
+    ni, nd2, nbase, Xn = _knn.knn_grid_window(x, grid, k_node)
+    ncoef, _, ns = _wls.derivative_coefficients(x, gc, ni, nd2, delta, eps, support, X=Xn)
     ib = np.flatnonzero(kind != KIND_F).astype(np.int64)
     is_ib = kind != KIND_F
     near = np.flatnonzero(is_ib[gi].any(axis=1)).astype(np.int64)
     return Stencils(grid, gi, gcoef, ni, nbase, ncoef, ib, near, gs, ns)
+
+
+def _lengths(grid: Grid, x: np.ndarray):
+    """Box lengths of the periodic axes (None elsewhere), or None when no
+    axis is periodic; checks that the positions lie in the periodic box."""
+    if not any(grid.periodic(a) for a in range(grid.d)):
+        return None
+    out = []
+    for a in range(grid.d):
+        if grid.periodic(a):
+            L = grid.length[a]
+            if not (np.all(x[:, a] >= 0.0) and np.all(x[:, a] < L)):
+                raise ValueError("positions along a periodic axis must lie in [0, n h)")
+            out.append(L)
+        else:
+            out.append(None)
+    return tuple(out)
 
 
 def sample_stencils(grid: Grid, x: np.ndarray, k_grid: int, k_node: int,
@@ -84,13 +104,15 @@ def sample_stencils(grid: Grid, x: np.ndarray, k_grid: int, k_node: int,
     stencil on the CPU is too slow.  Returns (grid_idx [S, k_g],
     grid_coef [S, d, k_g], node_idx [T, k_n], node_coef [T, d, k_n])."""
     delta = _wls.default_delta(grid.h) if delta is None else float(delta)
+    lengths = _lengths(grid, x)
     centres = grid.centres()
     gc = centres[grid_pts]
-    gi, gd2 = _knn.knn(gc, x, k_grid, workers=workers)
-    gcoef, _, _ = _wls.derivative_coefficients(gc, x, gi, gd2, delta, eps, support)
+    gi, gd2 = _knn.knn(gc, x, k_grid, workers=workers, lengths=lengths)
+    Xg = _knn.offsets(gc, x, gi, lengths) if lengths else None
+    gcoef, _, _ = _wls.derivative_coefficients(gc, x, gi, gd2, delta, eps, support, X=Xg)
     xn = x[nodes]
-    ni, nd2, _ = _knn.knn_grid_window(xn, grid, k_node)
-    ncoef, _, _ = _wls.derivative_coefficients(xn, centres, ni, nd2, delta, eps, support)
+    ni, nd2, _, Xn = _knn.knn_grid_window(xn, grid, k_node)
+    ncoef, _, _ = _wls.derivative_coefficients(xn, centres, ni, nd2, delta, eps, support, X=Xn)
     return gi, gcoef, ni, ncoef
 
 

@@ -75,10 +75,12 @@ def default_delta(h) -> float:
 
 def wls_rows(targets: np.ndarray, sources: np.ndarray, idx: np.ndarray, d2: np.ndarray,
              delta: float, eps: float = EPS_DEFAULT, support: float = SUPPORT_DEFAULT,
-             chunk: int = 1 << 16):
+             chunk: int = 1 << 16, X: np.ndarray | None = None):
     """Full C^-1 A (Eq. 13) for every target, in unscaled coordinates.
 
-    targets [T, d], sources [S, d], idx/d2 [T, k] from knn.
+    targets [T, d], sources [S, d], idx/d2 [T, k] from knn.  X (optional)
+    [T, k, d]: the source-minus-target offsets, when they are not the plain
+    differences (periodic images).
     Returns (rows [T, m, k], h_t [T], singular [T] bool) where rows[t, j, i]
     is the weight of f(x_i) in the j-th unknown of target t."""
     T, k = idx.shape
@@ -93,14 +95,14 @@ def wls_rows(targets: np.ndarray, sources: np.ndarray, idx: np.ndarray, d2: np.n
     order = np.array([0] + [1] * d + [2] * (m - 1 - d), dtype=np.float64)
     for s in range(0, T, chunk):
         e = min(T, s + chunk)
-        X = sources[idx[s:e]] - targets[s:e, None, :]          # [t, k, d]
+        Xc = (sources[idx[s:e]] - targets[s:e, None, :]) if X is None else X[s:e]
         r2 = d2[s:e]
         ht = np.maximum(support * delta, np.sqrt(r2[:, -1]))
         # the selected neighbours lie inside the support by construction
         # (r <= r_k <= h_t); re-testing r <= h_t after the square root could
         # drop the k-th neighbour on a rounding of sqrt(r_k^2)^2
         w = np.exp(-eps * r2 / (ht[:, None] * ht[:, None]))
-        xi = X / ht[:, None, None]
+        xi = Xc / ht[:, None, None]
         Q = basis6(xi)                                          # [t, k, m]
         sw = np.sqrt(w)
         Qr, R = np.linalg.qr(sw[:, :, None] * Q)                # [t,k,m], [t,m,m]
@@ -118,11 +120,11 @@ def wls_rows(targets: np.ndarray, sources: np.ndarray, idx: np.ndarray, d2: np.n
 
 
 def derivative_coefficients(targets, sources, idx, d2, delta, eps=EPS_DEFAULT,
-                            support=SUPPORT_DEFAULT, chunk: int = 1 << 16):
+                            support=SUPPORT_DEFAULT, chunk: int = 1 << 16, X=None):
     """First-derivative rows of C^-1 A: coef [T, d, k] with
     df/dx_a (target t) ~= sum_i coef[t, a, i] f(x_idx[t, i])."""
     d = targets.shape[1]
-    rows, ht, sing = wls_rows(targets, sources, idx, d2, delta, eps, support, chunk)
+    rows, ht, sing = wls_rows(targets, sources, idx, d2, delta, eps, support, chunk, X)
     return np.ascontiguousarray(rows[:, 1:1 + d, :]), ht, sing
 
 

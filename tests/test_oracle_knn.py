@@ -71,7 +71,7 @@ def test_grid_window_is_knn_inside_block(rng, d, k, n):
     from oracle import Grid
     grid = Grid(d, (n,) * d, (1.0 / n,) * d)
     x = rng.uniform(-0.02, 1.02, size=(200, d))
-    idx, d2, base = knn.knn_grid_window(x, grid, k)
+    idx, d2, base, _ = knn.knn_grid_window(x, grid, k)
     m = knn.window_m(k, d)
     centres = grid.centres()
     for t in range(0, 200, 7):
@@ -96,7 +96,7 @@ def test_window_spans_three_lines_per_axis(rng):
     from oracle import Grid
     grid = Grid(3, (8, 8, 8), (0.125,) * 3)
     x = rng.uniform(0, 1, size=(500, 3))
-    idx, _, _ = knn.knn_grid_window(x, grid, 27)
+    idx, _, _, _ = knn.knn_grid_window(x, grid, 27)
     cells = np.stack([idx % 8, (idx // 8) % 8, idx // 64], -1)
     for a in range(3):
         assert all(len(np.unique(cells[t, :, a])) >= 3 for t in range(500))

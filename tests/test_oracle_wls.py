@@ -53,7 +53,7 @@ def test_reproduces_quadratics_node_targets_all_rows(rng, d, k):
     n = 16 if d == 2 else 8
     nodes, centres, h = _cloud(rng, d, n)
     grid = Grid(d, (n,) * d, (h,) * d)
-    idx, d2, _ = knn.knn_grid_window(nodes, grid, k)
+    idx, d2, _, _ = knn.knn_grid_window(nodes, grid, k)
     rows, ht, sing = wls.wls_rows(nodes, centres, idx, d2, h)
     assert not sing.any()
     f, grad, H = _quad(rng, d)
