@@ -268,8 +268,7 @@ int pc_workspace_create(const pc_plan* P, const pc_geom* g, int mode, pc_workspa
   if (!P || !out) return fail(PC_ERR_INVALID_ARG, "pc_workspace_create: null argument");
   *out = nullptr;
   PC_TRY(check_mode(mode));
-  if (g && (g->G != P->G || g->d != P->d))
-    return fail(PC_ERR_INVALID_ARG, "geometry and plan grids differ");
+  if (g && !same_grid(P, g)) return fail(PC_ERR_INVALID_ARG, "geometry and plan grids differ");
   pc_workspace* W = new pc_workspace();
   std::memset(W, 0, sizeof(*W));
   W->plan = P;

@@ -83,6 +83,7 @@ struct pc_geom {
   int64_t M, G;
   int32_t n[3];
   double h[3];
+  int per;      // bit a set: axis a of the plan was periodic
   int k_grid;   // stencil size of grid targets
   int k_node;   // selected entries of node stencils
   int m_node;   // block lines per axis; block size bn = m^d
@@ -95,7 +96,8 @@ struct pc_geom {
   double* gcoef;   // [d][k_grid][G]
   float* gcoef32;  // [d][k_grid][G] or null
   // node stencils (block order)
-  int32_t* nbase;   // [M]
+  int32_t* nbase;   // [M] flat index of the block's low corner; ~corner
+                    // (negative) for a block that wraps around a periodic axis
   int64_t ms;       // stride of the node coefficient streams: M rounded up
                     // to 64, so that every stream starts on a 512-byte line
   double* ncoef;    // [d][bn][ms]
@@ -120,6 +122,20 @@ struct pc_geom {
   int64_t bytes;
   pc_workspace* own_ws;
 };
+
+namespace pc {
+// Whether a geometry was built on a plan of this grid (shape, spacing and
+// boundary conditions).
+inline bool same_grid(const pc_plan* P, const pc_geom* g) {
+  if (P->d != g->d || P->G != g->G) return false;
+  int per = 0;
+  for (int a = 0; a < P->d; ++a) {
+    if (P->n[a] != g->n[a] || P->h[a] != g->h[a]) return false;
+    if (P->bc[a] == PC_BC_PERIODIC) per |= 1 << a;
+  }
+  return per == g->per;
+}
+}  // namespace pc
 
 struct pc_workspace {
   const pc_plan* plan;

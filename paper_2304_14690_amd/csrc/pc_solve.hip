@@ -691,12 +691,15 @@ void resident_tiles(const pc_plan* P, size_t elem, const std::vector<int32_t>& n
   for (int32_t q : near_pts) f0[(q / n0) / C0] = 1;
   // lines read by the B+V gradient: the m x m (x m) block at each corner
   std::vector<char> ibplane(n2, 0);
-  for (int32_t q : ib_base) {
+  for (int32_t qb : ib_base) {
+    // a negative base marks a block that wraps around a periodic axis
+    const int64_t q = qb >= 0 ? qb : ~qb;
     const int64_t j0 = (q / n0) % n1, k0 = q / (n0 * n1);
     const int kn = P->d == 3 ? m : 1;
     for (int kk = 0; kk < kn; ++kk) {
-      ibplane[k0 + kk] = 1;
-      for (int jj = 0; jj < m; ++jj) i0[((j0 + jj) + n1 * (k0 + kk)) / C0] = 1;
+      const int64_t kw = (k0 + kk) % n2;
+      ibplane[kw] = 1;
+      for (int jj = 0; jj < m; ++jj) i0[((j0 + jj) % n1 + n1 * kw) / C0] = 1;
     }
   }
   for (int64_t t = 0; t < t0; ++t) {

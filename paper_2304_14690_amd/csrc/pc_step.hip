@@ -102,8 +102,25 @@ __global__ void __launch_bounds__(TPB) k_div_near(const int32_t* __restrict__ ne
 
 // ---- grad_to_nodes (all nodes), optionally fused with the projection ---------
 struct BlockOffsets {
-  int32_t off[PC_MAX_K_NODE];
+  int32_t off[PC_MAX_K_NODE];  // flat offset of block entry o from the low corner
+  int32_t n0, n1, n2, m;       // grid and block shape, for blocks that wrap
 };
+
+// Source index of block entry o of a node whose block wraps around a
+// periodic axis (marked by a negative base); c0 is the block's low corner.
+// Only periodic axes can run past the last line (Neumann blocks are clamped
+// inside the box), so every axis may take the wrap test.
+__device__ __forceinline__ int64_t wrap_src(int64_t c0, int o, const BlockOffsets& bo) {
+  const int m = bo.m;
+  const int64_t r = c0 / bo.n0;
+  int i = (int)(c0 - r * bo.n0) + o % m;
+  int j = (int)(r % bo.n1) + (o / m) % m;
+  int k = (int)(r / bo.n1) + o / (m * m);
+  if (i >= bo.n0) i -= bo.n0;
+  if (j >= bo.n1) j -= bo.n1;
+  if (k >= bo.n2) k -= bo.n2;
+  return i + (int64_t)bo.n0 * (j + (int64_t)bo.n1 * k);
+}
 
 template <typename T, int D, int BN, bool LOCALREF, bool PROJECT>
 __global__ void __launch_bounds__(TPB) k_grad_all(const int32_t* __restrict__ nbase,
@@ -117,17 +134,30 @@ __global__ void __launch_bounds__(TPB) k_grad_all(const int32_t* __restrict__ nb
   const int bn = BN > 0 ? BN : bnrt;
   const int64_t n = xcd_block(blockIdx.x, gridDim.x) * TPB + threadIdx.x;
   if (n >= M) return;
-  const int64_t base = ldnt(nbase + n);
+  const int32_t b32 = ldnt(nbase + n);
   T acc[D];
 #pragma unroll
   for (int a = 0; a < D; ++a) acc[a] = T(0);
-  T ref = LOCALREF ? phi[base + bo.off[0]] : T(0);
+  if (b32 >= 0) {
+    const int64_t base = b32;
+    T ref = LOCALREF ? phi[base + bo.off[0]] : T(0);
 #pragma unroll 9
-  for (int o = 0; o < bn; ++o) {
-    T f = phi[base + bo.off[o]];
-    if (LOCALREF) f -= ref;
+    for (int o = 0; o < bn; ++o) {
+      T f = phi[base + bo.off[o]];
+      if (LOCALREF) f -= ref;
 #pragma unroll
-    for (int a = 0; a < D; ++a) acc[a] += ldnt(ncoef + ((int64_t)a * bn + o) * ms + n) * f;
+      for (int a = 0; a < D; ++a) acc[a] += ldnt(ncoef + ((int64_t)a * bn + o) * ms + n) * f;
+    }
+  } else {
+    // a block that wraps around a periodic axis (a node next to a periodic face)
+    const int64_t c0 = ~b32;
+    T ref = LOCALREF ? phi[c0] : T(0);
+    for (int o = 0; o < bn; ++o) {
+      T f = phi[wrap_src(c0, o, bo)];
+      if (LOCALREF) f -= ref;
+#pragma unroll
+      for (int a = 0; a < D; ++a) acc[a] += ldnt(ncoef + ((int64_t)a * bn + o) * ms + n) * f;
+    }
   }
 #pragma unroll
   for (int a = 0; a < D; ++a) {
@@ -149,13 +179,14 @@ __global__ void __launch_bounds__(TPB) k_grad_ib(const int32_t* __restrict__ ibb
   if (skip && *skip) return;
   const int64_t s = (int64_t)blockIdx.x * TPB + threadIdx.x;
   if (s >= nib) return;
-  const int64_t base = ibbase[s];
+  const int32_t b32 = ibbase[s];
+  const int64_t base = b32 >= 0 ? b32 : ~b32;
   T acc[D];
 #pragma unroll
   for (int a = 0; a < D; ++a) acc[a] = T(0);
-  T ref = LOCALREF ? phi[base + bo.off[0]] : T(0);
+  T ref = LOCALREF ? phi[base] : T(0);
   for (int o = 0; o < bn; ++o) {
-    T f = phi[base + bo.off[o]];
+    T f = phi[b32 >= 0 ? base + bo.off[o] : wrap_src(base, o, bo)];
     if (LOCALREF) f -= ref;
 #pragma unroll
     for (int a = 0; a < D; ++a) acc[a] += ibcoef[((int64_t)a * bn + o) * ibs + s] * f;
@@ -285,16 +316,29 @@ __global__ void __launch_bounds__(IBT) k_ib_step(const int32_t* __restrict__ ibb
   const int64_t s = (int64_t)blockIdx.x * IBT + threadIdx.x;
   double num = 0.0, den = 0.0;
   if (s < nib) {
-    const int64_t base = ibbase[s];
+    const int32_t b32 = ibbase[s];
     T acc[D];
 #pragma unroll
     for (int a = 0; a < D; ++a) acc[a] = T(0);
     const bool lr = sizeof(T) == 4;
-    T ref = lr ? phi[base + bo.off[0]] : T(0);
+    if (b32 >= 0) {
+      const int64_t base = b32;
+      T ref = lr ? phi[base + bo.off[0]] : T(0);
 #pragma unroll
-    for (int o = 0; o < (BN > 0 ? BN : PC_MAX_K_NODE); ++o) {
-      if (o < bn) {
-        T f = phi[base + bo.off[o]];
+      for (int o = 0; o < (BN > 0 ? BN : PC_MAX_K_NODE); ++o) {
+        if (o < bn) {
+          T f = phi[base + bo.off[o]];
+          if (lr) f -= ref;
+#pragma unroll
+          for (int a = 0; a < D; ++a) acc[a] += ibcoef[((int64_t)a * bn + o) * ibs + s] * f;
+        }
+      }
+    } else {
+      // a block that wraps around a periodic axis
+      const int64_t c0 = ~b32;
+      T ref = lr ? phi[c0] : T(0);
+      for (int o = 0; o < bn; ++o) {
+        T f = phi[wrap_src(c0, o, bo)];
         if (lr) f -= ref;
 #pragma unroll
         for (int a = 0; a < D; ++a) acc[a] += ibcoef[((int64_t)a * bn + o) * ibs + s] * f;
@@ -450,6 +494,10 @@ BlockOffsets block_offsets(const pc_geom* g) {
     int ox = o % m, oy = (o / m) % m, oz = o / (m * m);
     bo.off[o] = ox + g->n[0] * (oy + g->n[1] * (g->d == 3 ? oz : 0));
   }
+  bo.n0 = g->n[0];
+  bo.n1 = g->n[1];
+  bo.n2 = g->d == 3 ? g->n[2] : 1;
+  bo.m = m;
   return bo;
 }
 
@@ -920,7 +968,7 @@ int pc_pressure_correct(const pc_geom* g, const pc_plan* P, int mode, const void
     return fail(PC_ERR_INVALID_ARG, "pc_pressure_correct: null argument");
   if (mode != PC_F64 && mode != PC_F32 && mode != PC_MIXED)
     return fail(PC_ERR_INVALID_ARG, "mode must be PC_F64, PC_F32 or PC_MIXED");
-  if (g->G != P->G || g->d != P->d) return fail(PC_ERR_INVALID_ARG, "plan and geometry differ");
+  if (!same_grid(P, g)) return fail(PC_ERR_INVALID_ARG, "plan and geometry differ");
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(PC_ERR_INVALID_ARG, "dt must be positive");
   if (mode == PC_F32 && !g->has32)
     return fail(PC_ERR_INVALID_ARG, "geometry was built without float32 stencils");

@@ -9,7 +9,11 @@
 //     closer node;
 //   * for every node, the k_node nearest grid points by (d^2, flat index)
 //     within the block of the m grid lines nearest to it along each axis
-//     (block clamped inside the box);
+//     (block clamped inside the box, except along a periodic axis, where it
+//     wraps around);
+//   * along a periodic axis (the lateral condition of the verification
+//     cases of Sec. 3) offsets are minimal images: t = x_s - x_t, then
+//     t - L if t > L/2 or t + L if t < -L/2;
 //   * per target, the Eq. 16 polynomial vector (10 terms in 3D) in
 //     coordinates scaled by h_t = max(support*delta, r_k), the Gaussian
 //     weights of Eq. 17, C = sum w q q^T (Eq. 14), its Cholesky factor, and
@@ -114,8 +118,24 @@ __device__ __forceinline__ void chol_unit_solve(const double* L, int col, double
 struct GridDesc {
   int32_t n[3];
   double h[3];
+  double L[3];  // box length n h per axis
+  int per;      // bit a set: axis a is periodic
   int64_t G;
 };
+
+// Offset x_s - x_t along axis a, as the minimal image on a periodic axis.
+__device__ __forceinline__ double axis_diff(double xs, double xt, const GridDesc& g, int a) {
+#pragma clang fp contract(off)
+  double t = xs - xt;
+  if ((g.per >> a) & 1) {
+    const double hl = 0.5 * g.L[a];
+    if (t > hl)
+      t = t - g.L[a];
+    else if (t < -hl)
+      t = t + g.L[a];
+  }
+  return t;
+}
 
 // ---- cell list ------------------------------------------------------------
 template <int D>
@@ -134,9 +154,16 @@ __device__ __forceinline__ int64_t cell_of(const double* __restrict__ xyz, int64
 
 template <int D>
 __global__ void __launch_bounds__(256) k_cell_count(const double* __restrict__ xyz, int64_t M,
-                                                    GridDesc g, int32_t* __restrict__ count) {
+                                                    GridDesc g, int32_t* __restrict__ count,
+                                                    int32_t* __restrict__ bad) {
   int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (n >= M) return;
+  // positions along a periodic axis must lie in the box [0, L)
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    const double x = xyz[a * M + n];
+    if (((g.per >> a) & 1) && !(x >= 0.0 && x < g.L[a])) atomicOr(bad, 4);
+  }
   atomicAdd(&count[cell_of<D>(xyz, M, n, g)], 1);
 }
 
@@ -266,21 +293,40 @@ __global__ void __launch_bounds__(64) k_grid_stencils(GridStencilArgs A) {
       lo[a] = a < D ? ci[a] - R : 0;
       hi[a] = a < D ? ci[a] + R : 0;
     }
+    // A cell index c along axis a is scanned when it lies in the box (a
+    // Neumann axis) or in the window of n cells centred on the target's
+    // cell (a periodic axis; c then stands for its wrapped cell, each cell
+    // once).
+    auto cell_in = [&](int a, int c, int* w) -> bool {
+      const int na = A.g.n[a];
+      if ((A.g.per >> a) & 1) {
+        const int lo_w = ci[a] - na / 2;
+        if (c < lo_w || c >= lo_w + na) return false;
+        *w = c < 0 ? c + na : (c >= na ? c - na : c);
+        return true;
+      }
+      *w = c;
+      return c >= 0 && c < na;
+    };
     for (int cz = lo[2]; cz <= hi[2]; ++cz) {
-      if (D == 3 && (cz < 0 || cz >= A.g.n[2])) continue;
+      int wz = 0;
+      if (D == 3 && !cell_in(2, cz, &wz)) continue;
       for (int cy = lo[1]; cy <= hi[1]; ++cy) {
-        if (cy < 0 || cy >= A.g.n[1]) continue;
+        int wy;
+        if (!cell_in(1, cy, &wy)) continue;
         bool yz_edge = (cy == lo[1] || cy == hi[1]) || (D == 3 && (cz == lo[2] || cz == hi[2]));
         int step = (yz_edge || R == 0) ? 1 : 2 * R;
         for (int cx = lo[0]; cx <= hi[0]; cx += step) {
-          if (cx < 0 || cx >= A.g.n[0]) continue;
-          int64_t c = cx + (int64_t)A.g.n[0] * (cy + (int64_t)A.g.n[1] * cz);
+          int wx;
+          if (!cell_in(0, cx, &wx)) continue;
+          int64_t c = wx + (int64_t)A.g.n[0] * (wy + (int64_t)A.g.n[1] * wz);
           int s0 = A.start[c], s1 = A.start[c + 1];
           for (int s = s0; s < s1; ++s) {
             int nid = A.sorted[s];
-            double dx = A.xyz[nid] - xt[0];
-            double dy = A.xyz[A.M + nid] - xt[1];
-            double d2 = D == 2 ? sq_sum2(dx, dy) : sq_sum3(dx, dy, A.xyz[2 * A.M + nid] - xt[2]);
+            double dx = axis_diff(A.xyz[nid], xt[0], A.g, 0);
+            double dy = axis_diff(A.xyz[A.M + nid], xt[1], A.g, 1);
+            double d2 = D == 2 ? sq_sum2(dx, dy)
+                               : sq_sum3(dx, dy, axis_diff(A.xyz[2 * A.M + nid], xt[2], A.g, 2));
             ++found;
             if (key_lt(d2, nid, ld[0], li[0])) {
               ld[0] = d2;
@@ -322,7 +368,7 @@ __global__ void __launch_bounds__(64) k_grid_stencils(GridStencilArgs A) {
       int nid = li[j];
       double xi[3];
 #pragma unroll
-      for (int a = 0; a < D; ++a) xi[a] = (A.xyz[a * A.M + nid] - xt[a]) / ht;
+      for (int a = 0; a < D; ++a) xi[a] = axis_diff(A.xyz[a * A.M + nid], xt[a], A.g, a) / ht;
       double w = exp((-A.eps * ld[j]) / (ht * ht));
       double q[MU];
       basis<D>(xi, q);
@@ -356,7 +402,7 @@ __global__ void __launch_bounds__(64) k_grid_stencils(GridStencilArgs A) {
         if (jj < k && li[jj] < nid) ++pos;
       double xi[3];
 #pragma unroll
-      for (int a = 0; a < D; ++a) xi[a] = (A.xyz[a * A.M + nid] - xt[a]) / ht;
+      for (int a = 0; a < D; ++a) xi[a] = axis_diff(A.xyz[a * A.M + nid], xt[a], A.g, a) / ht;
       double w = exp((-A.eps * ld[j]) / (ht * ht));
       double q[MU];
       basis<D>(xi, q);
@@ -395,16 +441,23 @@ __global__ void __launch_bounds__(64) k_node_stencils(NodeStencilArgs A) {
   if (n >= A.M) return;
   const int m = A.m, bn = A.bn, k = A.k;
   double x[3];
+  // base: the block's low line along each axis, unwrapped (a periodic axis
+  // may start it at -1 or end it past n - 1: those lines are the periodic
+  // images of the lines at the other face)
   int base[3] = {0, 0, 0};
   int64_t flat0 = 0, stride = 1;
+  bool wraps = false;
 #pragma unroll
   for (int a = 0; a < D; ++a) {
     x[a] = A.xyz[a * A.M + n];
     double lo = floor(x[a] / A.g.h[a] - (0.5 * m - 0.5));
-    lo = fmin(fmax(lo, 0.0), (double)(A.g.n[a] - m));
+    if (!((A.g.per >> a) & 1)) lo = fmin(fmax(lo, 0.0), (double)(A.g.n[a] - m));
     base[a] = (int)lo;
-    flat0 += (int64_t)base[a] * stride;
-    stride *= A.g.n[a];
+    const int na = A.g.n[a];
+    const int bw = base[a] < 0 ? base[a] + na : base[a];
+    wraps = wraps || base[a] < 0 || base[a] + m > na;
+    flat0 += (int64_t)bw * stride;
+    stride *= na;
   }
   // squared distances of the block points
   double d2[BNMAX];
@@ -421,8 +474,9 @@ __global__ void __launch_bounds__(64) k_node_stencils(NodeStencilArgs A) {
       for (int a = 0; a < D; ++a) {
         int cc = base[a] + oc[a];
         dd[a] = ((double)cc + 0.5) * A.g.h[a] - x[a];
-        f += (int64_t)cc * st;
-        st *= A.g.n[a];
+        const int na = A.g.n[a];
+        f += (int64_t)(cc < 0 ? cc + na : (cc >= na ? cc - na : cc)) * st;
+        st *= na;
       }
       d2[o] = D == 2 ? sq_sum2(dd[0], dd[1]) : sq_sum3(dd[0], dd[1], dd[2]);
       fl[o] = f;
@@ -476,7 +530,9 @@ __global__ void __launch_bounds__(64) k_node_stencils(NodeStencilArgs A) {
   double y[D][MU];
 #pragma unroll
   for (int a = 0; a < D; ++a) chol_unit_solve<MU>(Cm, 1 + a, y[a]);
-  A.nbase[n] = (int32_t)flat0;
+  // a block that wraps around a periodic axis is marked by storing the
+  // one's complement of its low corner (the gathers then wrap its entries)
+  A.nbase[n] = wraps ? ~(int32_t)flat0 : (int32_t)flat0;
   const int64_t ms = A.ms;
 #pragma unroll
   for (int o = 0; o < BNMAX; ++o) {
@@ -567,6 +623,16 @@ __global__ void __launch_bounds__(256) k_ib_gather(const int32_t* __restrict__ i
   for (int r = 0; r < rows; ++r) ibcoef[(int64_t)r * ibs + s] = ncoef[(int64_t)r * ms + nid];
 }
 
+// Node block bases for export: the low corner, with the wrap mark removed.
+__global__ void __launch_bounds__(256) k_base_export(const int32_t* __restrict__ in, int64_t n,
+                                                     int32_t* __restrict__ out) {
+  int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) {
+    const int32_t v = in[i];
+    out[i] = v < 0 ? ~v : v;
+  }
+}
+
 int scan_exclusive(const int32_t* in, int64_t n, int32_t* out, hipStream_t s) {
   int64_t nb = (n + SCAN_B - 1) / SCAN_B;
   int64_t* bsum = nullptr;
@@ -652,11 +718,15 @@ int build(const pc_plan* P, const double* xyz, const uint8_t* kind, int64_t M,
   g->bn = bn;
   g->has32 = want32;
   GridDesc gd;
+  gd.per = 0;
   for (int a = 0; a < 3; ++a) {
     gd.n[a] = P->n[a];
     gd.h[a] = P->h[a];
+    gd.L[a] = (double)P->n[a] * P->h[a];
+    if (a < d && P->bc[a] == PC_BC_PERIODIC) gd.per |= 1 << a;
   }
   gd.G = G;
+  g->per = gd.per;
 
   Scratch tmp;
   int32_t *count, *start, *cursor, *sorted, *bad;
@@ -669,9 +739,11 @@ int build(const pc_plan* P, const double* xyz, const uint8_t* kind, int64_t M,
   PC_TRY(fill_zero(cursor, (size_t)G * 4, s));
   PC_TRY(fill_zero(bad, 256, s));
   if (d == 2)
-    hipLaunchKernelGGL(k_cell_count<2>, dim3(nblocks(M, 256)), dim3(256), 0, s, xyz, M, gd, count);
+    hipLaunchKernelGGL(k_cell_count<2>, dim3(nblocks(M, 256)), dim3(256), 0, s, xyz, M, gd, count,
+                       bad);
   else
-    hipLaunchKernelGGL(k_cell_count<3>, dim3(nblocks(M, 256)), dim3(256), 0, s, xyz, M, gd, count);
+    hipLaunchKernelGGL(k_cell_count<3>, dim3(nblocks(M, 256)), dim3(256), 0, s, xyz, M, gd, count,
+                       bad);
   PC_HIP_CHECK(hipGetLastError());
   PC_TRY(scan_exclusive(count, G, start, s));
   if (d == 2)
@@ -712,6 +784,8 @@ int build(const pc_plan* P, const double* xyz, const uint8_t* kind, int64_t M,
   int32_t hbad = 0;
   PC_HIP_CHECK(hipMemcpyAsync(&hbad, bad, 4, hipMemcpyDeviceToHost, s));
   PC_HIP_CHECK(hipStreamSynchronize(s));
+  if (hbad & 4)
+    return fail(PC_ERR_INVALID_ARG, "positions along a periodic axis must lie in [0, n h)");
   if (hbad & 2) return fail(PC_ERR_INVALID_ARG, "a grid point found fewer than k_grid nodes");
   if (hbad & 1)
     return fail(PC_ERR_SINGULAR_STENCIL, "a WLS normal matrix is singular (squared pivot ratio "
@@ -866,7 +940,11 @@ int pc_geom_export(const pc_geom* g, int32_t* gidx, double* gcoef, int32_t* nbas
   };
   PC_TRY(cp(gidx, g->gidx, (size_t)g->k_grid * g->G * 4));
   PC_TRY(cp(gcoef, g->gcoef, (size_t)g->d * g->k_grid * g->G * 8));
-  PC_TRY(cp(nbase, g->nbase, (size_t)g->M * 4));
+  if (nbase && g->M) {
+    hipLaunchKernelGGL(k_base_export, dim3(nblocks(g->M, 256)), dim3(256), 0, s, g->nbase, g->M,
+                       nbase);
+    PC_HIP_CHECK(hipGetLastError());
+  }
   if (ncoef && g->M)
     PC_HIP_CHECK(hipMemcpy2DAsync(ncoef, (size_t)g->M * 8, g->ncoef, (size_t)g->ms * 8,
                                   (size_t)g->M * 8, (size_t)g->d * g->bn,

@@ -15,7 +15,10 @@ inside an obstacle become virtual points (the frozen fluid of Sec. 2.3), and
 boundary points are laid on the obstacle surface at the lattice spacing.
 The provisional velocity is a sum of random Fourier modes evaluated at F and
 B points and set to zero at V points (Sec. 2.3: the virtual points carry a
-zero intermediate velocity).
+zero intermediate velocity).  On a box with periodic axes (the lateral
+condition of the verification cases of Sec. 3) obstacles wrap around the
+periodic faces, every position lies in [0, L) along those axes, and the
+modes (integer wavenumbers on the unit box) are periodic.
 
 Random streams: numpy.random.Generator(PCG64(seed)).  The node seed drives the
 jitter only; the velocity seed drives the mode draw in the order wavenumber
@@ -43,12 +46,18 @@ class Obstacle:
     a: Tuple[float, ...]
     b: Tuple[float, ...]
 
-    def inside(self, x: np.ndarray) -> np.ndarray:
-        """x: [T, d].  Strictly-inside test (points on the surface are fluid)."""
+    def inside(self, x: np.ndarray, lengths=None) -> np.ndarray:
+        """x: [T, d].  Strictly-inside test (points on the surface are fluid).
+        lengths[a] (not None): axis a is periodic with that box length, and a
+        circle/sphere wraps around it."""
         if self.shape in ("circle", "sphere"):
             c = np.asarray(self.a, dtype=np.float64)
             r = float(self.b[0])
             dx = x - c[None, :]
+            if lengths is not None:
+                for a, L in enumerate(lengths):
+                    if L is not None:
+                        dx[:, a] -= L * np.round(dx[:, a] / L)
             return np.einsum("td,td->t", dx, dx) < r * r
         if self.shape == "box":
             lo = np.asarray(self.a, dtype=np.float64)
@@ -193,20 +202,47 @@ def fourier_velocity_torch(x, n_modes: int, seed: int, kmax: int = 4):
     return u
 
 
+def wrap_into_box(p: np.ndarray, lengths) -> np.ndarray:
+    """Positions [T, d] moved into [0, L) along the periodic axes (lengths[a]
+    not None)."""
+    p = p.copy()
+    for a, L in enumerate(lengths):
+        if L is not None:
+            v = np.mod(p[:, a], L)
+            v[v >= L] = 0.0  # a tiny negative coordinate rounds up to L
+            p[:, a] = v
+    return p
+
+
 def make_geometry(d: int, N: int, obstacles: Sequence[Obstacle], seed_nodes: int,
-                  jitter: float = 0.3, L: float = 1.0):
+                  jitter: float = 0.3, L: float = 1.0, bc=None):
     """Node positions [d, M] and kinds [M] of a jittered lattice with the
     obstacles' interior nodes turned virtual and their surface points
-    appended as boundary points."""
+    appended as boundary points.  bc: per-axis "neumann"/"periodic" (None:
+    Neumann everywhere)."""
     n = tuple([N] * d)
     h = tuple([L / N] * d)
+    return make_geometry_n(n, h, obstacles, seed_nodes, jitter, bc)
+
+
+def make_geometry_n(n: Sequence[int], h: Sequence[float], obstacles: Sequence[Obstacle],
+                    seed_nodes: int, jitter: float = 0.3, bc=None):
+    """make_geometry for any grid shape n and spacing h."""
+    n, h = tuple(n), tuple(h)
+    d = len(n)
+    lengths = None
+    if bc is not None and any(b == "periodic" for b in bc):
+        lengths = tuple(n[a] * h[a] if bc[a] == "periodic" else None for a in range(d))
     lat = jittered_lattice(n, h, seed_nodes, jitter)
     pts = lat.T
     inside = np.zeros(pts.shape[0], dtype=bool)
     for ob in obstacles:
-        inside |= ob.inside(pts)
+        inside |= ob.inside(pts, lengths)
     kind = np.where(inside, KIND_V, KIND_F).astype(np.uint8)
-    surf = [ob.surface_points(L / N) for ob in obstacles]
+    delta = h[0] if all(v == h[0] for v in h) else math.exp(sum(math.log(v) for v in h) / d)
+    surf = [ob.surface_points(delta) for ob in obstacles]
+    if lengths is not None:
+        surf = [wrap_into_box(sp, lengths) for sp in surf]
     if surf:
         bpts = np.concatenate(surf, axis=0)
         x = np.concatenate([lat, bpts.T], axis=1)
@@ -219,8 +255,8 @@ def make_geometry(d: int, N: int, obstacles: Sequence[Obstacle], seed_nodes: int
 def make_case(name: str, d: int, N: int, obstacles: Sequence[Obstacle], k_grid: int,
               k_node: int, n_modes: int, seed_nodes: int, seed_vel: int,
               jitter: float = 0.3, kmax: int = 4, dt: float = 1.0,
-              L: float = 1.0) -> Case:
-    n, h, x, kind = make_geometry(d, N, obstacles, seed_nodes, jitter, L)
+              L: float = 1.0, bc=None) -> Case:
+    n, h, x, kind = make_geometry(d, N, obstacles, seed_nodes, jitter, L, bc)
     u = fourier_velocity(x, n_modes, seed_vel, kmax)
     u[:, kind == KIND_V] = 0.0
     return Case(name, d, n, h, x, kind, np.ascontiguousarray(u), dt, k_grid, k_node,

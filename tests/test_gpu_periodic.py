@@ -1,0 +1,204 @@
+"""GPU parity on boxes with periodic axes (the lateral condition of the
+paper's verification cases, Sec. 3): the WLS stencils (minimal-image
+neighbour search, node blocks that wrap around a periodic face), the
+transfers through wrapped blocks, and the whole sub-step in every precision,
+against the float64 oracle; obstacles that cross a periodic face put
+boundary/virtual nodes on wrapped blocks.  Bars as for the Neumann box:
+index sets bit-exact, coefficients 1e-12, float64 1e-11, float32 5e-5,
+float32 transforms + float64 correction 1e-10 (relative L2).  Also: the
+resident transforms equal the full ones bit for bit, and positions outside
+the periodic box or a plan with other conditions are rejected."""
+import numpy as np
+import pytest
+
+from oracle import Grid, projection as P
+from paper_2304_14690_amd import inputs
+from tests.helpers import rel_l2, to_np
+
+pytestmark = pytest.mark.gpu
+
+PE, NE = "periodic", "neumann"
+
+
+def _case(name, n, bc, obstacles, k_grid, k_node, modes, seeds):
+    h = tuple(1.0 / v for v in n)
+    n, h, x, kind = inputs.make_geometry_n(n, h, obstacles, seeds[0], bc=bc)
+    u = inputs.fourier_velocity(x, modes, seeds[1])
+    u[:, kind == inputs.KIND_V] = 0.0
+    c = inputs.Case(name, len(n), n, h, x, kind, np.ascontiguousarray(u), 1.0, k_grid, k_node,
+                    list(obstacles))
+    return c, bc
+
+
+CASES = {
+    "2d_px_64": lambda: _case("2d_px_64", (64, 64), (PE, NE),
+                              [inputs.Obstacle("circle", (0.03, 0.5), (0.15,))], 16, 16, 8,
+                              (31, 32)),
+    "2d_pxy_64x128": lambda: _case("2d_pxy_64x128", (64, 128), (PE, PE),
+                                   [inputs.Obstacle("circle", (0.5, 0.97), (0.12,))], 12, 16, 8,
+                                   (33, 34)),
+    "2d_py_128x64_open": lambda: _case("2d_py_128x64_open", (128, 64), (NE, PE), [], 12, 12, 8,
+                                       (35, 36)),
+    "3d_pxz_32": lambda: _case("3d_pxz_32", (32, 32, 32), (PE, NE, PE),
+                               [inputs.Obstacle("sphere", (0.97, 0.5, 0.04), (0.2,))], 27, 27,
+                               16, (37, 38)),
+    "3d_ppp_32x32x64": lambda: _case("3d_ppp_32x32x64", (32, 32, 64), (PE, PE, PE),
+                                     [inputs.Obstacle("sphere", (0.5, 0.03, 0.98), (0.18,))], 27,
+                                     27, 16, (39, 40)),
+}
+_CACHE = {}
+
+
+@pytest.fixture(scope="module")
+def pc():
+    from paper_2304_14690_amd import pcorr
+    return pcorr
+
+
+def case(name):
+    if name not in _CACHE:
+        c, bc = CASES[name]()
+        grid = Grid(c.d, c.n, c.h, bc)
+        st = P.build_stencils(grid, c.x.T.copy(), c.kind, c.k_grid, c.k_node)
+        _CACHE[name] = (c, bc, grid, st)
+    return _CACHE[name]
+
+
+def gpu_geom(pc, c, bc, want_f32=False):
+    import torch
+    plan = pc.Plan(c.d, c.n, c.h, bc=bc)
+    geom = pc.wls_build(plan, torch.from_numpy(c.x).cuda(), torch.from_numpy(c.kind).cuda(),
+                        c.k_grid, c.k_node, want_f32=want_f32)
+    return plan, geom
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_periodic_stencils_match_oracle(pc, name):
+    import torch
+    c, bc, grid, st = case(name)
+    plan, geom = gpu_geom(pc, c, bc)
+    G, M, d = grid.G, c.M, c.d
+    gi = torch.empty((geom.k_grid, G), dtype=torch.int32, device="cuda")
+    gcf = torch.empty((d, geom.k_grid, G), dtype=torch.float64, device="cuda")
+    nb = torch.empty(M, dtype=torch.int32, device="cuda")
+    ncf = torch.empty((d, geom.bn, M), dtype=torch.float64, device="cuda")
+    ib = torch.empty(max(1, geom.n_ib), dtype=torch.int32, device="cuda")
+    near = torch.empty(max(1, geom.n_near), dtype=torch.int32, device="cuda")
+    pc.geom_export(geom, gi, gcf, nb, ncf, ib, near)
+    torch.cuda.synchronize()
+    gi, gcf, nb, ncf = to_np(gi), to_np(gcf), to_np(nb), to_np(ncf)
+    order = np.argsort(st.grid_idx, axis=1, kind="stable")
+    np.testing.assert_array_equal(gi.T, np.take_along_axis(st.grid_idx, order, axis=1))
+    err_g = rel_l2(np.transpose(gcf, (2, 0, 1)),
+                   np.take_along_axis(st.grid_coef, order[:, None, :], axis=2))
+    # node blocks: the low corner (wrapped), entries at (cell - corner) mod n
+    stride = np.array([1, c.n[0], c.n[0] * c.n[1]])[:d]
+    obase = st.node_base @ stride
+    np.testing.assert_array_equal(nb, obase)
+    m = round(geom.bn ** (1.0 / d))
+    cell = np.stack([(st.node_idx // stride[a]) % c.n[a] for a in range(d)], -1)
+    rel = (cell - st.node_base[:, None, :]) % np.array(c.n)
+    assert rel.max() < m
+    o = rel[..., 0] + m * rel[..., 1] + (m * m * rel[..., 2] if d == 3 else 0)
+    dense = np.zeros_like(ncf)
+    rows = np.arange(M)[:, None].repeat(o.shape[1], 1)
+    for a in range(d):
+        dense[a, o, rows] = st.node_coef[:, a, :]
+    err_n = rel_l2(ncf, dense)
+    wrapped = int(np.count_nonzero(((st.node_base + m) > np.array(c.n)).any(axis=1)))
+    print(f"{name}: grid coef {err_g:.2e} node coef {err_n:.2e}, {wrapped} wrapped blocks")
+    assert err_g <= 1e-12 and err_n <= 1e-12 and wrapped > 0
+    np.testing.assert_array_equal(to_np(ib)[:geom.n_ib], st.ib)
+    np.testing.assert_array_equal(to_np(near)[:geom.n_near], st.near)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_periodic_transfers_match_oracle(pc, name):
+    import torch
+    c, bc, grid, st = case(name)
+    plan, geom = gpu_geom(pc, c, bc)
+    rng = np.random.Generator(np.random.PCG64(5))
+    v = rng.normal(size=(c.d, c.M))
+    phi = rng.normal(size=grid.G)
+    b = torch.empty(grid.G, dtype=torch.float64, device="cuda")
+    pc.div_to_grid(geom, torch.from_numpy(v).cuda(), b)
+    gr = torch.empty((c.d, c.M), dtype=torch.float64, device="cuda")
+    pc.grad_to_nodes(geom, torch.from_numpy(phi).cuda(), gr)
+    torch.cuda.synchronize()
+    assert rel_l2(to_np(b), P.div_to_grid(st, v.T.copy())) <= 1e-12
+    assert rel_l2(to_np(gr).T, P.grad_to_nodes(st, phi)) <= 1e-12
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_periodic_pressure_correct_all_modes(pc, name):
+    import torch
+    c, bc, grid, st = case(name)
+    ref = P.pressure_correct(st, c.u.T.copy(), solver=lambda b: _solve(grid, b))
+    plan, geom = gpu_geom(pc, c, bc, want_f32=True)
+    res = {}
+    for mode, dtype in ((pc.PC_F64, torch.float64), (pc.PC_MIXED, torch.float64),
+                        (pc.PC_F32, torch.float32)):
+        u_in = c.u if mode != pc.PC_F32 else c.u.astype(np.float32).astype(np.float64)
+        r = ref if mode != pc.PC_F32 else P.pressure_correct(
+            st, u_in.T.copy(), fixed_it=ref["n_it"], solver=lambda b: _solve(grid, b))
+        ut = torch.from_numpy(u_in).to(dtype).cuda()
+        uo = torch.empty_like(ut)
+        p = torch.empty(grid.G, dtype=dtype, device="cuda")
+        fixed = 0 if mode == pc.PC_F64 else ref["n_it"]
+        rc, stats = pc.pressure_correct(geom, plan, mode, ut, 1.0, uo, p, fixed_it=fixed)
+        torch.cuda.synchronize()
+        eu, ep = rel_l2(to_np(uo), r["u_new"].T), rel_l2(to_np(p), r["p"])
+        res[mode] = (stats["n_it"], eu, ep)
+        assert np.all(to_np(uo)[:, st.ib] == 0.0)
+    print(f"{name}: oracle n_it {ref['n_it']}, gpu {res}")
+    n_it, eu, ep = res[pc.PC_F64]
+    assert n_it == ref["n_it"] and eu <= 1e-11 and ep <= 1e-11
+    assert res[pc.PC_MIXED][1] <= 1e-10 and res[pc.PC_MIXED][2] <= 1e-10
+    assert res[pc.PC_F32][1] <= 5e-5 and res[pc.PC_F32][2] <= 5e-5
+
+
+def _solve(grid, b):
+    from oracle import poisson
+    return poisson.solve(grid, b)
+
+
+@pytest.mark.parametrize("name", ["2d_px_64", "3d_pxz_32", "3d_ppp_32x32x64"])
+def test_periodic_resident_transforms_bitwise(pc, name):
+    import torch
+    c, bc, grid, st = case(name)
+    plan, geom = gpu_geom(pc, c, bc, want_f32=True)
+    for mode, dtype in ((pc.PC_F64, torch.float64), (pc.PC_F32, torch.float32)):
+        ut = torch.from_numpy(c.u).to(dtype).cuda()
+        outs = []
+        for full in (False, True):
+            uo = torch.empty_like(ut)
+            p = torch.empty(grid.G, dtype=dtype, device="cuda")
+            g = torch.zeros((c.d, geom.n_ib), dtype=dtype, device="cuda")
+            rc, s = pc.pressure_correct(geom, plan, mode, ut, 1.0, uo, p, g=g,
+                                        full_transforms=full)
+            torch.cuda.synchronize()
+            outs.append((rc, s["n_it"], to_np(uo), to_np(p), to_np(g)))
+        a, b = outs
+        assert a[0] == b[0] and a[1] == b[1]
+        for xa, xb in zip(a[2:], b[2:]):
+            assert np.array_equal(xa, xb)
+
+
+def test_periodic_argument_errors(pc):
+    import torch
+    c, bc, grid, st = case("2d_px_64")
+    plan = pc.Plan(c.d, c.n, c.h, bc=bc)
+    x = c.x.copy()
+    x[0, 7] = 1.0  # on the far periodic face: outside [0, L)
+    with pytest.raises(pc.PcError) as e:
+        pc.wls_build(plan, torch.from_numpy(x).cuda(), torch.from_numpy(c.kind).cuda(),
+                     c.k_grid, c.k_node)
+    assert e.value.code == pc.PC_ERR_INVALID_ARG and "periodic" in str(e.value)
+    geom = pc.wls_build(plan, torch.from_numpy(c.x).cuda(), torch.from_numpy(c.kind).cuda(),
+                        c.k_grid, c.k_node)
+    neumann = pc.Plan(c.d, c.n, c.h)
+    u = torch.from_numpy(c.u).cuda()
+    with pytest.raises(pc.PcError) as e:
+        pc.pressure_correct(geom, neumann, pc.PC_F64, u, 1.0, torch.empty_like(u),
+                            torch.empty(grid.G, dtype=torch.float64, device="cuda"))
+    assert e.value.code == pc.PC_ERR_INVALID_ARG
