@@ -15,6 +15,9 @@ Workloads (all inputs seeded and synthetic, resident in HBM before timing):
           the box [0.6, 0.8] x [0.4, 0.6]^2, 27-neighbour stencils, 64 modes;
           float32 transforms with 2 and 3 float64 defect-correction sweeps
           against all-float64.
+  2d2048p 2d2048 with a periodic x axis (a channel: periodic lateral faces,
+          as in the paper's verification cases, Sec. 3) and Neumann walls in y.
+  3d256p  3d256 with periodic x and z axes and Neumann walls in y.
 The stencils are built once (timed separately, not part of a step).  A step
 is one complete pressure-correction sub-step (RHS transfer, IB-force
 iterations of Poisson solve + gradient at the IB + force update, final
@@ -47,6 +50,16 @@ WORKLOADS = {
     "3d256": {"d": 3, "N": 256, "modes": "f64,f32,mixed", "cpu_N": 64,
               "desc": "3D 256^3 grid, {M} jittered nodes, sphere r=0.1 at the centre, 27-NN "
                       "WLS, 64-mode velocity, Neumann box, cold IB start"},
+    "2d2048p": {"d": 2, "N": 2048, "modes": "f64,f32,mixed", "cpu_N": 1024,
+                "bc": ("periodic", "neumann"),
+                "desc": "2D 2048^2 grid, {M} jittered nodes, cylinder r=0.05 at (0.3,0.5), "
+                        "16-NN WLS, 32-mode velocity, periodic in x, Neumann walls in y, "
+                        "cold IB start"},
+    "3d256p": {"d": 3, "N": 256, "modes": "f64,f32,mixed", "cpu_N": 64,
+               "bc": ("periodic", "neumann", "periodic"),
+               "desc": "3D 256^3 grid, {M} jittered nodes, sphere r=0.1 at the centre, 27-NN "
+                       "WLS, 64-mode velocity, periodic in x and z, Neumann walls in y, "
+                       "cold IB start"},
     "3d512": {"d": 3, "N": 512, "modes": "f64,mixed,mixed3", "cpu_N": 64,
               "desc": "3D 512^3 grid, {M} jittered nodes, sphere r=0.1 at (0.3,0.5,0.5) plus "
                       "box [0.6,0.8]x[0.4,0.6]^2, 27-NN WLS, 64-mode velocity, Neumann box, "
@@ -106,21 +119,23 @@ def make_workload(name, N):
     with torch on the device, much faster at 16.8M-134M nodes)."""
     import torch
     from paper_2304_14690_amd import inputs
-    if name == "2d2048":
-        c = inputs.config2(N)
+    bc = WORKLOADS[name].get("bc")
+    if name in ("2d2048", "2d2048p"):
+        c = inputs.make_case(name, 2, N, [inputs.Obstacle("circle", (0.3, 0.5), (0.05,))],
+                             16, 16, 32, 3, 4, bc=bc)
         return {"d": 2, "n": c.n, "h": c.h, "x": c.x, "kind": c.kind, "k": c.k_grid,
-                "u": torch.from_numpy(c.u).cuda()}
-    if name == "3d256":
+                "u": torch.from_numpy(c.u).cuda(), "bc": bc}
+    if name in ("3d256", "3d256p"):
         obs, sn, sv = [inputs.Obstacle("sphere", (0.5, 0.5, 0.5), (0.1,))], 5, 6
     else:
         obs, sn, sv = [inputs.Obstacle("sphere", (0.3, 0.5, 0.5), (0.1,)),
                        inputs.Obstacle("box", (0.6, 0.4, 0.4), (0.8, 0.6, 0.6))], 7, 8
-    n, h, x, kind = inputs.make_geometry(3, N, obs, sn)
+    n, h, x, kind = inputs.make_geometry(3, N, obs, sn, bc=bc)
     xt = torch.from_numpy(x).cuda()
     u = inputs.fourier_velocity_torch(xt, 64, sv)
     u[:, torch.from_numpy(kind).cuda() == inputs.KIND_V] = 0.0
     del xt
-    return {"d": 3, "n": n, "h": h, "x": x, "kind": kind, "k": 27, "u": u}
+    return {"d": 3, "n": n, "h": h, "x": x, "kind": kind, "k": 27, "u": u, "bc": bc}
 
 
 def rel_l2(a, b):
@@ -155,7 +170,7 @@ def main():
     d = case["d"]
     G = int(np.prod(case["n"]))
     M = int(case["kind"].size)
-    plan = pc.Plan(d, case["n"], case["h"])
+    plan = pc.Plan(d, case["n"], case["h"], bc=case["bc"])
     x = torch.from_numpy(case["x"]).cuda()
     kind = torch.from_numpy(case["kind"]).cuda()
     case["x"] = None
@@ -243,7 +258,7 @@ def main():
         "div_to_grid": {"kernel": f"k_div_all<double,{d},{k}>",
                         "bytes": bytes_div_all(G, M, k, d, 8), "s": t_div,
                         "launches_per_step": 1, "kernels_per_call": 1},
-        "poisson_fft_solve": {"kernel": f"dct_r16 x{2 * d - 1}", "bytes": bytes_solve(G, d, 8),
+        "poisson_fft_solve": {"kernel": f"dct_rad x{2 * d - 1}", "bytes": bytes_solve(G, d, 8),
                               "s": t_solve, "launches_per_step": n_it,
                               "kernels_per_call": 2 * d - 1},
         "grad_to_nodes": {"kernel": f"k_grad_all<double,{d},{bn}>",
@@ -424,13 +439,16 @@ def cpu_baseline(workload, N):
     from oracle import projection as P
     from paper_2304_14690_amd import inputs
     cores = len(os.sched_getaffinity(0))
-    if workload == "2d2048":
-        c = inputs.config2(N)
-    elif workload == "3d256":
-        c = inputs.config3(N)
+    bc = WORKLOADS[workload].get("bc")
+    if workload in ("2d2048", "2d2048p"):
+        c = inputs.make_case(workload, 2, N, [inputs.Obstacle("circle", (0.3, 0.5), (0.05,))],
+                             16, 16, 32, 3, 4, bc=bc)
+    elif workload in ("3d256", "3d256p"):
+        c = inputs.make_case(workload, 3, N, [inputs.Obstacle("sphere", (0.5, 0.5, 0.5), (0.1,))],
+                             27, 27, 64, 5, 6, bc=bc)
     else:
         c = inputs.config4(N)
-    grid = oracle.Grid(c.d, c.n, c.h)
+    grid = oracle.Grid(c.d, c.n, c.h, bc)
     t0 = time.perf_counter()
     st = P.build_stencils(grid, c.x.T.copy(), c.kind, c.k_grid, c.k_node, workers=cores)
     t_build = time.perf_counter() - t0

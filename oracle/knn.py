@@ -68,40 +68,49 @@ def knn_brute(targets: np.ndarray, sources: np.ndarray, k: int, lengths=None):
     return idxs[:, :k], d2s[:, :k]
 
 
-def _images(sources: np.ndarray, lengths):
+def _images(sources: np.ndarray, lengths, margin=None):
     """The sources and their copies shifted by -L and +L along every
-    periodic axis (3^p copies), as one array; copy c of source i is row
-    c * S + i."""
+    periodic axis, as (points, source index of each point).  With a margin,
+    only the copies that land within `margin` of the box are kept."""
     d = sources.shape[1]
-    per = [a for a in range(d) if lengths is not None and lengths[a] is not None]
-    shifts = [np.zeros(d)]
-    for a in per:
-        new = []
-        for sh in shifts:
-            for sgn in (-1.0, 1.0):
-                v = sh.copy()
-                v[a] = sgn * lengths[a]
-                new.append(v)
-        shifts = shifts + new
-    return np.concatenate([sources + sh for sh in shifts], axis=0)
+    pts, src = sources, np.arange(sources.shape[0], dtype=np.int64)
+    for a in range(d):
+        if lengths is None or lengths[a] is None:
+            continue
+        L = lengths[a]
+        parts, ids = [pts], [src]
+        for sgn in (-1.0, 1.0):
+            q = pts.copy()
+            q[:, a] = pts[:, a] + sgn * L
+            keep = slice(None) if margin is None else (q[:, a] > -margin) & (q[:, a] < L + margin)
+            parts.append(q[keep])
+            ids.append(src[keep])
+        pts, src = np.concatenate(parts), np.concatenate(ids)
+    return pts, src
 
 
 def knn(targets: np.ndarray, sources: np.ndarray, k: int, extra: int = 8,
         workers: int = -1, chunk: int = 1 << 18, tree: cKDTree | None = None,
-        lengths=None):
+        lengths=None, margin=None):
     """Same result as knn_brute, found through a k-d tree: the tree proposes
     k+extra candidates, the exact key re-ranks them, and a target whose k-th
     key is not safely inside the candidate radius is re-queried with more
-    candidates.  With periodic axes the tree holds every periodic image of
-    the sources; candidates map back to their source and are ranked by the
-    minimal-image key.  Returns (idx [T, k] int64, d2 [T, k] float64)."""
+    candidates.  With periodic axes the tree holds the periodic images of
+    the sources (all of them, or those within `margin` of the box, for
+    targets inside the box; a k-th neighbour beyond the margin is an error);
+    candidates map back to their source and are ranked by the minimal-image
+    key.  Returns (idx [T, k] int64, d2 [T, k] float64)."""
     S = sources.shape[0]
     if k > S:
         raise ValueError("k larger than the number of sources")
     T = targets.shape[0]
     periodic = lengths is not None and any(v is not None for v in lengths)
-    if tree is None:
-        tree = cKDTree(_images(sources, lengths) if periodic else sources)
+    src_of = None
+    if periodic:
+        pts, src_of = _images(sources, lengths, margin)
+        tree = cKDTree(pts)
+    elif tree is None:
+        tree = cKDTree(sources)
     SX = tree.n
     out_i = np.empty((T, k), dtype=np.int64)
     out_d = np.empty((T, k), dtype=np.float64)
@@ -111,7 +120,9 @@ def knn(targets: np.ndarray, sources: np.ndarray, k: int, extra: int = 8,
         kk = min(SX, k + extra)
         while todo.size:
             dist, cand = tree.query(targets[todo], k=kk, workers=workers)
-            cand = cand.astype(np.int64) % S
+            cand = cand.astype(np.int64)
+            if periodic:
+                cand = src_of[cand]
             d2 = exact_d2(targets[todo], sources, cand, lengths)
             if periodic:
                 # two images of one source: keep one
@@ -132,6 +143,8 @@ def knn(targets: np.ndarray, sources: np.ndarray, k: int, extra: int = 8,
             safe = d2s[:, k - 1] < (rlim * rlim) * (1.0 - 1e-9)
             todo = todo[~safe]
             kk = min(SX, 2 * kk)
+    if periodic and margin is not None and not np.all(out_d[:, -1] < margin * margin):
+        raise ValueError("a k-th neighbour lies beyond the image margin")
     return out_i, out_d
 
 

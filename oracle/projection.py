@@ -97,17 +97,21 @@ def _lengths(grid: Grid, x: np.ndarray):
 def sample_stencils(grid: Grid, x: np.ndarray, k_grid: int, k_node: int,
                     grid_pts: np.ndarray, nodes: np.ndarray,
                     eps: float = _wls.EPS_DEFAULT, support: float = _wls.SUPPORT_DEFAULT,
-                    delta: Optional[float] = None, workers: int = -1):
+                    delta: Optional[float] = None, workers: int = -1,
+                    image_margin: Optional[float] = None):
     """The stencils of build_stencils for a subset of targets only: the
     grid points `grid_pts` (flat indices) over all nodes x [M, d], and the
     nodes `nodes` over the grid.  For checks at sizes where building every
-    stencil on the CPU is too slow.  Returns (grid_idx [S, k_g],
-    grid_coef [S, d, k_g], node_idx [T, k_n], node_coef [T, d, k_n])."""
+    stencil on the CPU is too slow.  image_margin: on a periodic box, keep
+    only the periodic images within this distance of the box (the neighbour
+    search raises if a stencil reaches further).  Returns (grid_idx
+    [S, k_g], grid_coef [S, d, k_g], node_idx [T, k_n], node_coef
+    [T, d, k_n])."""
     delta = _wls.default_delta(grid.h) if delta is None else float(delta)
     lengths = _lengths(grid, x)
     centres = grid.centres()
     gc = centres[grid_pts]
-    gi, gd2 = _knn.knn(gc, x, k_grid, workers=workers, lengths=lengths)
+    gi, gd2 = _knn.knn(gc, x, k_grid, workers=workers, lengths=lengths, margin=image_margin)
     Xg = _knn.offsets(gc, x, gi, lengths) if lengths else None
     gcoef, _, _ = _wls.derivative_coefficients(gc, x, gi, gd2, delta, eps, support, X=Xg)
     xn = x[nodes]

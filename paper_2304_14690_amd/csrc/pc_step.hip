@@ -104,25 +104,42 @@ __global__ void __launch_bounds__(TPB) k_div_near(const int32_t* __restrict__ ne
 struct BlockOffsets {
   int32_t off[PC_MAX_K_NODE];  // flat offset of block entry o from the low corner
   int32_t n0, n1, n2, m;       // grid and block shape, for blocks that wrap
+  int32_t l0, l1;              // log2 n0, log2 n1 (the plan's n are powers of two)
+  int32_t per;                 // bit a set: axis a is periodic
 };
 
-// Source index of block entry o of a node whose block wraps around a
-// periodic axis (marked by a negative base); c0 is the block's low corner.
-// Only periodic axes can run past the last line (Neumann blocks are clamped
-// inside the box), so every axis may take the wrap test.
-__device__ __forceinline__ int64_t wrap_src(int64_t c0, int o, const BlockOffsets& bo) {
-  const int m = bo.m;
-  const int64_t r = c0 / bo.n0;
-  int i = (int)(c0 - r * bo.n0) + o % m;
-  int j = (int)(r % bo.n1) + (o / m) % m;
-  int k = (int)(r / bo.n1) + o / (m * m);
-  if (i >= bo.n0) i -= bo.n0;
-  if (j >= bo.n1) j -= bo.n1;
-  if (k >= bo.n2) k -= bo.n2;
-  return i + (int64_t)bo.n0 * (j + (int64_t)bo.n1 * k);
+// Wrap thresholds of one node's block on a grid with periodic axes: block
+// entry o with offsets (ox, oy, oz) from the low corner c0 runs past the last
+// line along x when ox >= tx (and so on); its source is then one box length
+// back along that axis.  A Neumann axis never wraps (threshold m).
+struct BlockWrap {
+  int tx, ty, tz;
+};
+
+__device__ __forceinline__ BlockWrap block_wrap(int64_t c0, const BlockOffsets& bo) {
+  const int i0 = (int)(c0 & (bo.n0 - 1));
+  const int j0 = (int)((c0 >> bo.l0) & (bo.n1 - 1));
+  const int k0 = (int)(c0 >> (bo.l0 + bo.l1));
+  BlockWrap w;
+  w.tx = (bo.per & 1) ? bo.n0 - i0 : bo.m;
+  w.ty = (bo.per & 2) ? bo.n1 - j0 : bo.m;
+  w.tz = (bo.per & 4) ? bo.n2 - k0 : bo.m;
+  return w;
 }
 
-template <typename T, int D, int BN, bool LOCALREF, bool PROJECT>
+__device__ __forceinline__ int64_t wrap_adjust(int64_t src, int ox, int oy, int oz,
+                                               const BlockWrap& w, const BlockOffsets& bo) {
+  const int64_t plane = (int64_t)bo.n0 * bo.n1;
+  if (ox >= w.tx) src -= bo.n0;
+  if (oy >= w.ty) src -= plane;
+  if (oz >= w.tz) src -= plane * bo.n2;
+  return src;
+}
+
+// WRAP: the grid has periodic axes, and blocks next to a periodic face wrap
+// around it (their base is marked by a one's complement); every lane then
+// applies its own wrap thresholds, so such blocks cost no divergence.
+template <typename T, int D, int BN, bool LOCALREF, bool PROJECT, bool WRAP>
 __global__ void __launch_bounds__(TPB) k_grad_all(const int32_t* __restrict__ nbase,
                                                   const T* __restrict__ ncoef, int64_t M,
                                                   int64_t ms, int bnrt, BlockOffsets bo,
@@ -132,32 +149,27 @@ __global__ void __launch_bounds__(TPB) k_grad_all(const int32_t* __restrict__ nb
                                                   const int32_t* __restrict__ skip) {
   if (skip && *skip) return;
   const int bn = BN > 0 ? BN : bnrt;
+  // block lines per axis (16 = 4^2 in 2D, 27 = 3^3 in 3D)
+  constexpr int MB = BN == 16 && D == 2 ? 4 : (BN == 27 && D == 3 ? 3 : 0);
+  const int m = MB > 0 ? MB : bo.m;
   const int64_t n = xcd_block(blockIdx.x, gridDim.x) * TPB + threadIdx.x;
   if (n >= M) return;
   const int32_t b32 = ldnt(nbase + n);
+  const int64_t base = WRAP ? (b32 >= 0 ? b32 : ~b32) : b32;
+  BlockWrap w = {0, 0, 0};
+  if (WRAP) w = block_wrap(base, bo);
   T acc[D];
 #pragma unroll
   for (int a = 0; a < D; ++a) acc[a] = T(0);
-  if (b32 >= 0) {
-    const int64_t base = b32;
-    T ref = LOCALREF ? phi[base + bo.off[0]] : T(0);
+  T ref = LOCALREF ? phi[base + bo.off[0]] : T(0);
 #pragma unroll 9
-    for (int o = 0; o < bn; ++o) {
-      T f = phi[base + bo.off[o]];
-      if (LOCALREF) f -= ref;
+  for (int o = 0; o < bn; ++o) {
+    int64_t src = base + bo.off[o];
+    if (WRAP) src = wrap_adjust(src, o % m, (o / m) % m, o / (m * m), w, bo);
+    T f = phi[src];
+    if (LOCALREF) f -= ref;
 #pragma unroll
-      for (int a = 0; a < D; ++a) acc[a] += ldnt(ncoef + ((int64_t)a * bn + o) * ms + n) * f;
-    }
-  } else {
-    // a block that wraps around a periodic axis (a node next to a periodic face)
-    const int64_t c0 = ~b32;
-    T ref = LOCALREF ? phi[c0] : T(0);
-    for (int o = 0; o < bn; ++o) {
-      T f = phi[wrap_src(c0, o, bo)];
-      if (LOCALREF) f -= ref;
-#pragma unroll
-      for (int a = 0; a < D; ++a) acc[a] += ldnt(ncoef + ((int64_t)a * bn + o) * ms + n) * f;
-    }
+    for (int a = 0; a < D; ++a) acc[a] += ldnt(ncoef + ((int64_t)a * bn + o) * ms + n) * f;
   }
 #pragma unroll
   for (int a = 0; a < D; ++a) {
@@ -180,13 +192,15 @@ __global__ void __launch_bounds__(TPB) k_grad_ib(const int32_t* __restrict__ ibb
   const int64_t s = (int64_t)blockIdx.x * TPB + threadIdx.x;
   if (s >= nib) return;
   const int32_t b32 = ibbase[s];
-  const int64_t base = b32 >= 0 ? b32 : ~b32;
+  const int64_t base = b32 >= 0 ? b32 : ~b32;  // ~corner: the block wraps
+  const BlockWrap w = block_wrap(base, bo);
   T acc[D];
 #pragma unroll
   for (int a = 0; a < D; ++a) acc[a] = T(0);
   T ref = LOCALREF ? phi[base] : T(0);
+  const int m = bo.m;
   for (int o = 0; o < bn; ++o) {
-    T f = phi[b32 >= 0 ? base + bo.off[o] : wrap_src(base, o, bo)];
+    T f = phi[wrap_adjust(base + bo.off[o], o % m, (o / m) % m, o / (m * m), w, bo)];
     if (LOCALREF) f -= ref;
 #pragma unroll
     for (int a = 0; a < D; ++a) acc[a] += ibcoef[((int64_t)a * bn + o) * ibs + s] * f;
@@ -317,28 +331,19 @@ __global__ void __launch_bounds__(IBT) k_ib_step(const int32_t* __restrict__ ibb
   double num = 0.0, den = 0.0;
   if (s < nib) {
     const int32_t b32 = ibbase[s];
+    const int64_t base = b32 >= 0 ? b32 : ~b32;  // ~corner: the block wraps
+    const BlockWrap w = block_wrap(base, bo);
+    constexpr int MB = BN == 16 && D == 2 ? 4 : (BN == 27 && D == 3 ? 3 : 0);
+    const int m = MB > 0 ? MB : bo.m;
     T acc[D];
 #pragma unroll
     for (int a = 0; a < D; ++a) acc[a] = T(0);
     const bool lr = sizeof(T) == 4;
-    if (b32 >= 0) {
-      const int64_t base = b32;
-      T ref = lr ? phi[base + bo.off[0]] : T(0);
+    T ref = lr ? phi[base + bo.off[0]] : T(0);
 #pragma unroll
-      for (int o = 0; o < (BN > 0 ? BN : PC_MAX_K_NODE); ++o) {
-        if (o < bn) {
-          T f = phi[base + bo.off[o]];
-          if (lr) f -= ref;
-#pragma unroll
-          for (int a = 0; a < D; ++a) acc[a] += ibcoef[((int64_t)a * bn + o) * ibs + s] * f;
-        }
-      }
-    } else {
-      // a block that wraps around a periodic axis
-      const int64_t c0 = ~b32;
-      T ref = lr ? phi[c0] : T(0);
-      for (int o = 0; o < bn; ++o) {
-        T f = phi[wrap_src(c0, o, bo)];
+    for (int o = 0; o < (BN > 0 ? BN : PC_MAX_K_NODE); ++o) {
+      if (o < bn) {
+        T f = phi[wrap_adjust(base + bo.off[o], o % m, (o / m) % m, o / (m * m), w, bo)];
         if (lr) f -= ref;
 #pragma unroll
         for (int a = 0; a < D; ++a) acc[a] += ibcoef[((int64_t)a * bn + o) * ibs + s] * f;
@@ -498,6 +503,9 @@ BlockOffsets block_offsets(const pc_geom* g) {
   bo.n1 = g->n[1];
   bo.n2 = g->d == 3 ? g->n[2] : 1;
   bo.m = m;
+  bo.l0 = __builtin_ctz((unsigned)bo.n0);
+  bo.l1 = __builtin_ctz((unsigned)bo.n1);
+  bo.per = g->per;
   return bo;
 }
 
@@ -569,14 +577,19 @@ int launch_grad_all(const pc_geom* g, const T* ncoef, const T* phi, T scale, con
   const bool lr = sizeof(T) == 4;
   BlockOffsets bo = block_offsets(g);
   dim3 grid(nblk(g->M)), block(TPB);
-#define GRL(D, BN)                                                                            \
-  do {                                                                                       \
-    if (lr)                                                                                  \
-      hipLaunchKernelGGL((k_grad_all<T, D, BN, true, PROJECT>), grid, block, 0, s, g->nbase,  \
-                         ncoef, g->M, g->ms, g->bn, bo, phi, scale, u, out, skip);           \
-    else                                                                                     \
-      hipLaunchKernelGGL((k_grad_all<T, D, BN, false, PROJECT>), grid, block, 0, s, g->nbase, \
-                         ncoef, g->M, g->ms, g->bn, bo, phi, scale, u, out, skip);           \
+#define GRW(D, BN, W)                                                                           \
+  do {                                                                                          \
+    if (lr)                                                                                     \
+      hipLaunchKernelGGL((k_grad_all<T, D, BN, true, PROJECT, W>), grid, block, 0, s, g->nbase,  \
+                         ncoef, g->M, g->ms, g->bn, bo, phi, scale, u, out, skip);              \
+    else                                                                                        \
+      hipLaunchKernelGGL((k_grad_all<T, D, BN, false, PROJECT, W>), grid, block, 0, s, g->nbase, \
+                         ncoef, g->M, g->ms, g->bn, bo, phi, scale, u, out, skip);              \
+  } while (0)
+#define GRL(D, BN)                  \
+  do {                              \
+    if (g->per) GRW(D, BN, true);   \
+    else GRW(D, BN, false);         \
   } while (0)
   if (g->d == 2) {
     if (g->bn == 16) GRL(2, 16);
@@ -586,6 +599,7 @@ int launch_grad_all(const pc_geom* g, const T* ncoef, const T* phi, T scale, con
     else GRL(3, 0);
   }
 #undef GRL
+#undef GRW
   PC_HIP_CHECK(hipGetLastError());
   return PC_OK;
 }

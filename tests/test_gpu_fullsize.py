@@ -1,6 +1,7 @@
 """Parity at the full sizes the benchmark times: the 2048^2 workload (k = 16)
-and the 256^3 workload (k = 27), through pc_pressure_correct with its own
-workspace, as bench.py runs it.
+and the 256^3 workload (k = 27), and their variants with periodic axes
+(2048^2 periodic in x; 256^3 periodic in x and z), through
+pc_pressure_correct with its own workspace, as bench.py runs it.
 
 The oracle cannot build every stencil of these sizes within a test, so it is
 compared on outputs it computes one by one at sampled targets (random, next
@@ -33,13 +34,19 @@ pytestmark = pytest.mark.gpu
 SIGMA = 1.5  # phi = (3 dt / 2) p with dt = 1
 
 
+BCS = {"2d2048": None, "3d256": None, "2d2048p": ("periodic", "neumann"),
+       "3d256p": ("periodic", "neumann", "periodic")}
+
+
 def _workload(name):
     import torch
-    if name == "2d2048":
-        c = inputs.config2(2048)
+    bc = BCS[name]
+    if name.startswith("2d"):
+        c = inputs.make_case(name, 2, 2048, [inputs.Obstacle("circle", (0.3, 0.5), (0.05,))],
+                             16, 16, 32, 3, 4, bc=bc)
         return c.d, c.n, c.h, c.x, c.kind, c.k_grid, torch.from_numpy(c.u).cuda()
     obs = [inputs.Obstacle("sphere", (0.5, 0.5, 0.5), (0.1,))]
-    n, h, x, kind = inputs.make_geometry(3, 256, obs, 5)
+    n, h, x, kind = inputs.make_geometry(3, 256, obs, 5, bc=bc)
     xt = torch.from_numpy(x).cuda()
     u = inputs.fourier_velocity_torch(xt, 64, 6)
     u[:, torch.from_numpy(kind).cuda() == inputs.KIND_V] = 0.0
@@ -71,14 +78,15 @@ def _samples(rng, grid, x, ib, near, nsamp=500):
     return gp, nd
 
 
-@pytest.mark.parametrize("name", ["2d2048", "3d256"])
+@pytest.mark.parametrize("name", list(BCS))
 def test_full_size_sampled_parity(name):
     import torch
     from paper_2304_14690_amd import pcorr as pc
     d, n, h, x, kind, k, u = _workload(name)
-    grid = oracle.Grid(d, n, h)
+    bc = BCS[name]
+    grid = oracle.Grid(d, n, h, bc)
     G, M = grid.G, kind.size
-    plan = pc.Plan(d, n, h)
+    plan = pc.Plan(d, n, h, bc=bc)
     geom = pc.wls_build(plan, torch.from_numpy(x).cuda(), torch.from_numpy(kind).cuda(), k, k,
                         want_f32=True)
     nib, nnear, bn = geom.n_ib, geom.n_near, geom.bn
@@ -96,7 +104,7 @@ def test_full_size_sampled_parity(name):
     rng = np.random.Generator(np.random.PCG64(17))
     xs = x.T.copy()
     gp, nd = _samples(rng, grid, xs, ib, near)
-    ogi, ogc, oni, onc = P.sample_stencils(grid, xs, k, k, gp, nd)
+    ogi, ogc, oni, onc = P.sample_stencils(grid, xs, k, k, gp, nd, image_margin=8 * max(h))
 
     # stencils at the sampled targets
     gps = torch.from_numpy(gp).cuda()
@@ -110,7 +118,8 @@ def test_full_size_sampled_parity(name):
     n_cf = ncf[:, :, nds].cpu().numpy()                        # [d, bn, T]
     m = round(bn ** (1.0 / d))
     stride = np.array([1, n[0], n[0] * (n[1] if d == 3 else 1)])[:d]
-    rel = np.stack([(oni // stride[a]) % n[a] - ((n_base // stride[a]) % n[a])[:, None]
+    # (entry - corner) mod n: blocks wrap around periodic axes
+    rel = np.stack([((oni // stride[a]) % n[a] - ((n_base // stride[a]) % n[a])[:, None]) % n[a]
                     for a in range(d)], -1)
     assert rel.min() >= 0 and rel.max() < m
     o = rel[..., 0] + m * rel[..., 1] + (m * m * rel[..., 2] if d == 3 else 0)

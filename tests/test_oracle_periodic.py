@@ -129,3 +129,15 @@ def test_positions_outside_periodic_box_rejected(rng):
     x[5, 0] = 1.0
     with pytest.raises(ValueError):
         P.build_stencils(grid, x, np.zeros(1024, np.uint8), 16, 16)
+
+
+@pytest.mark.parametrize("d,L", [(2, (1.0, None)), (3, (1.0, None, 1.0))])
+def test_image_margin_same_selection(rng, d, L):
+    s = rng.uniform(size=(3000, d))
+    t = np.concatenate([rng.uniform(size=(300, d)), rng.uniform(size=(300, d)) * 0.05])
+    i1, d1 = knn.knn(t, s, 16, lengths=L)
+    i2, d2 = knn.knn(t, s, 16, lengths=L, margin=0.2)
+    np.testing.assert_array_equal(i1, i2)
+    np.testing.assert_array_equal(d1, d2)
+    with pytest.raises(ValueError):
+        knn.knn(t, s, 16, lengths=L, margin=0.01)
