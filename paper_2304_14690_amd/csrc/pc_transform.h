@@ -91,22 +91,26 @@ __device__ __forceinline__ int64_t line_base(const LineArgs<TC>& A, int t, int c
 
 // The float64 residual r = b - rscale * lap_h phi at cell (i, j, k) of flat
 // index p.  Neumann axes take the mirror ghost (phi_{-1} = phi_0), periodic
-// axes (bit a of perm) wrap around.
+// axes (bit a of perm) wrap around.  Each neighbour's address is selected
+// first (the ghost re-reads the cell itself), so all loads are
+// unconditional and in flight together.
 __device__ __forceinline__ double resid_ijk(const double* __restrict__ b,
                                             const double* __restrict__ phi, int64_t p, int i,
                                             int j, int k, int d, int32_t n0, int32_t n1,
                                             int32_t n2, int perm, const double* ih2,
                                             double rscale) {
   const int64_t s1 = n0, s2 = (int64_t)n0 * n1;
+  const int64_t pxm = i > 0 ? p - 1 : ((perm & 1) ? p + (n0 - 1) : p);
+  const int64_t pxp = i < n0 - 1 ? p + 1 : ((perm & 1) ? p - (n0 - 1) : p);
+  const int64_t pym = j > 0 ? p - s1 : ((perm & 2) ? p + (n1 - 1) * s1 : p);
+  const int64_t pyp = j < n1 - 1 ? p + s1 : ((perm & 2) ? p - (n1 - 1) * s1 : p);
   const double c = phi[p];
-  const double xm = i > 0 ? phi[p - 1] : ((perm & 1) ? phi[p + (n0 - 1)] : c);
-  const double xp = i < n0 - 1 ? phi[p + 1] : ((perm & 1) ? phi[p - (n0 - 1)] : c);
-  const double ym = j > 0 ? phi[p - s1] : ((perm & 2) ? phi[p + (n1 - 1) * s1] : c);
-  const double yp = j < n1 - 1 ? phi[p + s1] : ((perm & 2) ? phi[p - (n1 - 1) * s1] : c);
+  const double xm = phi[pxm], xp = phi[pxp], ym = phi[pym], yp = phi[pyp];
   double lap = ((xp - c) - (c - xm)) * ih2[0] + ((yp - c) - (c - ym)) * ih2[1];
   if (d == 3) {
-    const double zm = k > 0 ? phi[p - s2] : ((perm & 4) ? phi[p + (n2 - 1) * s2] : c);
-    const double zp = k < n2 - 1 ? phi[p + s2] : ((perm & 4) ? phi[p - (n2 - 1) * s2] : c);
+    const int64_t pzm = k > 0 ? p - s2 : ((perm & 4) ? p + (n2 - 1) * s2 : p);
+    const int64_t pzp = k < n2 - 1 ? p + s2 : ((perm & 4) ? p - (n2 - 1) * s2 : p);
+    const double zm = phi[pzm], zp = phi[pzp];
     lap += ((zp - c) - (c - zm)) * ih2[2];
   }
   return b[p] - rscale * lap;
