@@ -18,6 +18,10 @@ class Grid:
     # ghosts) or "periodic" (the lateral condition of the paper's cases in
     # Sec. 3); None means Neumann everywhere
     bc: Optional[Tuple[str, ...]] = None
+    # eigenvalues of the solve: "fd2" (central differences, the variant of
+    # the reported timings, Sec. 3.2) or "spectral" (pseudo-spectral, one of
+    # the variants Sec. 3 reports as giving no noticeable difference)
+    eig: str = "fd2"
 
     def periodic(self, a: int) -> bool:
         return self.bc is not None and self.bc[a] == "periodic"

@@ -12,7 +12,9 @@ transform and eigenvalues to a table of Fuka 2015 that is not reproduced):
     periodic (phi_{-1} = phi_{n-1}, phi_n = phi_0), the lateral condition of
     the verification cases of Sec. 3;
   * method: central finite differences (the variant used for the reported
-    timings of Sec. 3.2).  The mirror-ghost 3-point operator is diagonalised
+    timings of Sec. 3.2), or the pseudo-spectral eigenvalues (the squared
+    wavenumbers of the transform's modes), one of the variants Sec. 3
+    reports as interchangeable.  The mirror-ghost 3-point operator is diagonalised
     by the DCT-II, with eigenvalues -(4/h^2) sin^2(pi k / (2n)); the periodic
     one by the DFT, with eigenvalues -(4/h^2) sin^2(pi k / n);
   * zero mode: with Neumann walls everywhere the operator is singular; the
@@ -33,10 +35,21 @@ from .grid import Grid
 
 
 def eigenvalues_1d(grid: Grid, a: int) -> np.ndarray:
-    """1D eigenvalues of axis a: -(4/h^2) sin^2(pi k / (2n)) (Neumann, DCT-II
-    index k) or -(4/h^2) sin^2(pi k / n) (periodic, DFT index k)."""
-    k = np.arange(grid.n[a], dtype=np.float64)
-    den = grid.n[a] if grid.periodic(a) else 2.0 * grid.n[a]
+    """1D eigenvalues of axis a.  Central differences: -(4/h^2) sin^2(pi k /
+    (2n)) (Neumann, DCT-II index k) or -(4/h^2) sin^2(pi k / n) (periodic,
+    DFT index k).  Pseudo-spectral: minus the squared wavenumber of the
+    mode, -(pi k / L)^2 (Neumann: cos(pi k x / L)) or -(2 pi m / L)^2 with
+    m = min(k, n - k) (periodic), L = n h."""
+    n = grid.n[a]
+    k = np.arange(n, dtype=np.float64)
+    if grid.eig == "spectral":
+        L = n * grid.h[a]
+        if grid.periodic(a):
+            return -(2.0 * np.pi * np.minimum(k, n - k) / L) ** 2
+        return -(np.pi * k / L) ** 2
+    if grid.eig != "fd2":
+        raise ValueError(grid.eig)
+    den = n if grid.periodic(a) else 2.0 * n
     return -(4.0 / (grid.h[a] ** 2)) * np.sin(np.pi * k / den) ** 2
 
 

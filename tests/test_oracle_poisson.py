@@ -190,3 +190,46 @@ def test_exact_rational_periodic():
     phi, bm = poisson.solve(grid, np.array([float(v) for v in b]))
     assert bm == pytest.approx(float(sol[-1]), abs=1e-15)
     np.testing.assert_allclose(phi, [float(v) for v in sol[:-1]], atol=1e-14)
+
+
+# ---- pseudo-spectral eigenvalues (a solver variant Sec. 3 reports as giving
+# no noticeable difference) -------------------------------------------------------
+
+def _trig_field(grid, terms):
+    """f = sum_t c_t prod_a m_{t,a}(x_a) at the cell centres, with
+    m = cos(pi k x / L) on a Neumann axis or cos(2 pi k x / L + theta) on a
+    periodic one, and its Laplacian written out analytically."""
+    X = grid.centres()
+    f = np.zeros(grid.G)
+    lap = np.zeros(grid.G)
+    for c, modes in terms:
+        prod = np.full(grid.G, float(c))
+        w2 = 0.0
+        for a, (k, th) in enumerate(modes):
+            L = grid.length[a]
+            w = (2.0 * np.pi * k / L) if grid.periodic(a) else (np.pi * k / L)
+            prod = prod * np.cos(w * X[:, a] + th)
+            w2 += w * w
+        f += prod
+        lap -= w2 * prod
+    return f, lap
+
+
+@pytest.mark.parametrize("n,bc,terms", [
+    ((32, 64), ("neumann", "neumann"), [(1.0, ((3, 0.0), (5, 0.0))), (0.3, ((7, 0.0), (0, 0.0)))]),
+    ((64, 32), ("periodic", "neumann"), [(1.0, ((3, 0.4), (2, 0.0))), (-0.7, ((32, 0.3), (1, 0.0)))]),
+    ((16, 8, 32), ("periodic", "neumann", "periodic"),
+     [(1.0, ((2, 1.1), (3, 0.0), (5, 0.2))), (0.5, ((8, 0.0), (0, 0.0), (16, 0.9)))]),
+])
+def test_spectral_solve_exact_on_trig_polynomials(n, bc, terms):
+    """The pseudo-spectral solve inverts the Laplacian of a trigonometric
+    polynomial exactly (the central-difference one only to O(h^2))."""
+    d = len(n)
+    h = tuple(1.0 / v for v in n)
+    grid = Grid(d, n, h, bc, eig="spectral")
+    f, lap = _trig_field(grid, terms)
+    phi, bm = poisson.solve(grid, lap)
+    assert abs(bm) < 1e-9 * np.abs(lap).max()
+    np.testing.assert_allclose(phi, f - f.mean(), atol=1e-12 * np.abs(f).max())
+    fd, _ = poisson.solve(Grid(d, n, h, bc), lap)
+    assert np.abs(fd - (f - f.mean())).max() > 1e-4 * np.abs(f).max()
