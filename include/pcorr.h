@@ -85,6 +85,13 @@ extern "C" {
 #define PC_BC_PERIODIC 1 /* periodic (the lateral condition of the paper's   */
                          /* verification cases, Sec. 3)                     */
 
+/* ---- eigenvalues of the Poisson solve --------------------------------------- */
+#define PC_EIG_FD2 0      /* central differences (the variant of the paper's   */
+                          /* timings, Sec. 3.2)                                */
+#define PC_EIG_SPECTRAL 1 /* pseudo-spectral: minus the squared wavenumber of  */
+                          /* each mode (a variant Sec. 3 reports as giving no  */
+                          /* noticeable difference)                            */
+
 #define PC_KIND_F 0
 #define PC_KIND_B 1
 #define PC_KIND_V 2
@@ -159,15 +166,23 @@ int pc_last_error(char* buf, size_t n);
  * `stream`.  Release with pc_plan_destroy. */
 int pc_plan_create(int d, const int32_t* n, const double* h, void* stream, pc_plan** out);
 
-/* pc_plan_create with a boundary condition per axis, bc[a] = PC_BC_NEUMANN
- * or PC_BC_PERIODIC (NULL: Neumann everywhere).  A periodic axis of n cells
- * (n a power of two in [32, 4096]) joins cell n-1 to cell 0; its transform
- * is the real DFT, packed into n reals, and its 1D eigenvalues are
- * -(4/h_a^2) sin^2(pi k / n_a), those of the wrap-around central-difference
- * Laplacian.  Every entry point that takes the plan follows its axes'
- * conditions: the solve, and the WLS stencils of pc_wls_build (a periodic
- * axis wraps node positions and neighbourhoods around the box). */
-int pc_plan_create_bc(int d, const int32_t* n, const double* h, const int32_t* bc,
+/* pc_plan_create with a boundary condition per axis and a choice of
+ * eigenvalues.
+ *   bc[a] = PC_BC_NEUMANN or PC_BC_PERIODIC (bc NULL: Neumann everywhere).
+ *     A periodic axis of n cells (n a power of two in [32, 4096]) joins cell
+ *     n-1 to cell 0; its transform is the real DFT, packed into n reals, and
+ *     its central-difference eigenvalues are -(4/h_a^2) sin^2(pi k / n_a),
+ *     those of the wrap-around 3-point Laplacian.  Every entry point that
+ *     takes the plan follows its axes' conditions: the solve, and the WLS
+ *     stencils of pc_wls_build (a periodic axis wraps node positions and
+ *     neighbourhoods around the box).
+ *   eig = PC_EIG_FD2 (the eigenvalues above and in pc_plan_create) or
+ *     PC_EIG_SPECTRAL: -(pi k / L_a)^2 for cosine mode k of a Neumann axis,
+ *     -(2 pi m / L_a)^2 for Fourier mode m of a periodic axis (L_a = n_a h_a).
+ *     PC_MIXED needs PC_EIG_FD2 (its defect correction evaluates the
+ *     3-point Laplacian); with PC_EIG_SPECTRAL it returns
+ *     PC_ERR_INVALID_ARG. */
+int pc_plan_create_ex(int d, const int32_t* n, const double* h, const int32_t* bc, int32_t eig,
                       void* stream, pc_plan** out);
 int pc_plan_destroy(pc_plan* plan);
 

@@ -48,7 +48,7 @@ size_t axis_table_reals(int N) {
   return 2 * (size_t)H + 2 * (size_t)(H + 1) * 2 + (size_t)N;
 }
 
-void fill_axis_tables(int N, double h, bool periodic, std::vector<double>& out) {
+void fill_axis_tables(int N, double h, bool periodic, bool spectral, std::vector<double>& out) {
   const long double PI = 3.141592653589793238462643383279502884L;
   int H = N / 2;
   out.clear();
@@ -71,6 +71,15 @@ void fill_axis_tables(int N, double h, bool periodic, std::vector<double>& out) 
   // eigenvalue of slot k: DCT-II index k (Neumann) or mode min(k, N-k)
   // (periodic; sin^2 is the same for both)
   const long double den = periodic ? (long double)N : 2.0L * (long double)N;
+  if (spectral) {
+    const long double L = (long double)N * (long double)h;
+    for (int k = 0; k < N; ++k) {
+      const long double w = periodic ? 2.0L * PI * (long double)std::min(k, N - k) / L
+                                     : PI * (long double)k / L;
+      out.push_back((double)(-(w * w)));
+    }
+    return;
+  }
   for (int k = 0; k < N; ++k) {
     long double sn = sinl(PI * (long double)k / den);
     out.push_back((double)(-(4.0L / ((long double)h * (long double)h)) * sn * sn));
@@ -130,13 +139,15 @@ int pc_last_error(char* buf, size_t n) {
 }
 
 int pc_plan_create(int d, const int32_t* n, const double* h, void* stream, pc_plan** out) {
-  return pc_plan_create_bc(d, n, h, nullptr, stream, out);
+  return pc_plan_create_ex(d, n, h, nullptr, PC_EIG_FD2, stream, out);
 }
 
-int pc_plan_create_bc(int d, const int32_t* n, const double* h, const int32_t* bc,
+int pc_plan_create_ex(int d, const int32_t* n, const double* h, const int32_t* bc, int32_t eig,
                       void* stream, pc_plan** out) {
   if (!out || !n || !h) return fail(PC_ERR_INVALID_ARG, "pc_plan_create: null argument");
   *out = nullptr;
+  if (eig != PC_EIG_FD2 && eig != PC_EIG_SPECTRAL)
+    return fail(PC_ERR_INVALID_ARG, "eig must be PC_EIG_FD2 or PC_EIG_SPECTRAL");
   if (d != 2 && d != 3) return fail(PC_ERR_UNSUPPORTED_SIZE, "d must be 2 or 3");
   for (int a = 0; a < d; ++a) {
     const int32_t b = bc ? bc[a] : PC_BC_NEUMANN;
@@ -162,6 +173,7 @@ int pc_plan_create_bc(int d, const int32_t* n, const double* h, const int32_t* b
     P->n[a] = a < d ? n[a] : 1;
     P->h[a] = a < d ? h[a] : 1.0;
     P->bc[a] = (a < d && bc) ? bc[a] : PC_BC_NEUMANN;
+    P->eig = eig;
     P->G *= P->n[a];
   }
   if (hipGetDevice(&P->device) != hipSuccess) {
@@ -172,7 +184,7 @@ int pc_plan_create_bc(int d, const int32_t* n, const double* h, const int32_t* b
   size_t offs[3];
   for (int a = 0; a < d; ++a) {
     offs[a] = all.size();
-    fill_axis_tables(P->n[a], P->h[a], P->bc[a] == PC_BC_PERIODIC, one);
+    fill_axis_tables(P->n[a], P->h[a], P->bc[a] == PC_BC_PERIODIC, eig == PC_EIG_SPECTRAL, one);
     all.insert(all.end(), one.begin(), one.end());
   }
   std::vector<float> all32(all.size());
@@ -354,6 +366,8 @@ int pc_poisson_fft_solve(const pc_plan* P, int mode, const void* b, void* phi, i
     return solve_f64(P, (const double*)b, (double*)phi, bmean_dev, ws, s);
   if (mode == PC_F32) return solve_f32(P, (const float*)b, (float*)phi, bmean_dev, ws, s);
   if (b == phi) return fail(PC_ERR_INVALID_ARG, "PC_MIXED needs b and phi to be distinct");
+  if (P->eig != PC_EIG_FD2)
+    return fail(PC_ERR_INVALID_ARG, "PC_MIXED needs the central-difference eigenvalues");
   if (ws && ws->mode != PC_MIXED)
     return fail(PC_ERR_INVALID_ARG, "PC_MIXED needs a workspace created for PC_MIXED");
   PC_TRY(ensure_plan_ws(P, &ws));

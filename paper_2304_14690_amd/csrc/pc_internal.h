@@ -52,6 +52,8 @@ struct cplx {
 //             -(4 / h^2) sin^2(pi s / (2N))  (Neumann axis, DCT-II index s)
 //             -(4 / h^2) sin^2(pi s / N)     (periodic axis: slots s and N-s
 //                                             both hold mode s)
+//             or, with pseudo-spectral eigenvalues, -(pi s / L)^2 (Neumann)
+//             and -(2 pi min(s, N-s) / L)^2 (periodic), L = N h
 template <typename T>
 struct AxisTables {
   const cplx<T>* twH;
@@ -68,6 +70,7 @@ struct pc_plan {
   int32_t n[3];
   double h[3];
   int32_t bc[3];  // PC_BC_NEUMANN or PC_BC_PERIODIC per axis
+  int32_t eig;    // PC_EIG_FD2 or PC_EIG_SPECTRAL
   int64_t G;
   int device;
   // one allocation per precision holding all axis tables

@@ -482,6 +482,7 @@ int launch_pass(const pc_plan* P, int axis, const TI* in, TO* out, const AxisTab
   double norm = 1.0;
   for (int a = 0; a < P->d; ++a) norm *= (P->bc[a] == PC_BC_PERIODIC ? 1.0 : 2.0) * P->n[a];
   A.meannorm = 1.0 / norm;
+  A.own_table = P->eig == PC_EIG_SPECTRAL;
   A.perm = 0;
   for (int a = 0; a < P->d; ++a)
     if (P->bc[a] == PC_BC_PERIODIC) A.perm |= 1 << a;

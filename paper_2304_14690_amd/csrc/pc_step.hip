@@ -983,6 +983,8 @@ int pc_pressure_correct(const pc_geom* g, const pc_plan* P, int mode, const void
   if (mode != PC_F64 && mode != PC_F32 && mode != PC_MIXED)
     return fail(PC_ERR_INVALID_ARG, "mode must be PC_F64, PC_F32 or PC_MIXED");
   if (!same_grid(P, g)) return fail(PC_ERR_INVALID_ARG, "plan and geometry differ");
+  if (mode == PC_MIXED && P->eig != PC_EIG_FD2)
+    return fail(PC_ERR_INVALID_ARG, "PC_MIXED needs the central-difference eigenvalues");
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(PC_ERR_INVALID_ARG, "dt must be positive");
   if (mode == PC_F32 && !g->has32)
     return fail(PC_ERR_INVALID_ARG, "geometry was built without float32 stencils");

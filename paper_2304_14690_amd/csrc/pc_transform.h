@@ -57,6 +57,9 @@ struct LineArgs {
   int axis;             // 0, 1, 2
   int d;
   int perm;             // bit a set: axis a is periodic (residual wrap-around)
+  int own_table;        // FDI: take this axis's eigenvalues from tab.lam (by
+                        // slot) instead of computing them from the shift
+                        // twiddles (pseudo-spectral eigenvalues)
   int32_t n0, n1, n2;
   double ih2[3];        // 1/h^2 (residual)
   int64_t stride;       // element stride along the axis
@@ -702,18 +705,22 @@ __global__ void __launch_bounds__(512) dct_rad(LineArgs<TC> A) {
         // sin(pi k/2N) = -Im w4, cos = Re w4, and slot H (k = 0) has
         // sin^2 = 1/2.  Real DFT: slots k and N-k both hold mode k, of
         // eigenvalue -(4/h^2) sin^2(pi k / N) = -(4/h^2) 4 sin^2 cos^2 of
-        // pi k / (2N), and slot H (k = 0) has sin^2 = 1.
-        TC s_a, s_b;
-        if (PER) {
+        // pi k / (2N), and slot H (k = 0) has sin^2 = 1.  Pseudo-spectral
+        // eigenvalues come from the axis table by slot.
+        TC e_a, e_b;  // this axis's eigenvalues of the two slots
+        if (A.own_table) {
+          e_a = Tb.lam[k];
+          e_b = Tb.lam[k ? N - k : H];
+        } else if (PER) {
           const TC sc2 = TC(2) * w4.re * w4.im;
-          s_a = sc2 * sc2;
-          s_b = k ? s_a : TC(1);
+          e_a = lc * (sc2 * sc2);
+          e_b = k ? e_a : lc;
         } else {
-          s_a = w4.im * w4.im;
-          s_b = k ? w4.re * w4.re : TC(0.5);
+          e_a = lc * (w4.im * w4.im);
+          e_b = lc * (k ? w4.re * w4.re : TC(0.5));
         }
-        TC l_a = (rest + lc * s_a) * ls_;
-        TC l_b = (rest + lc * s_b) * ls_;
+        TC l_a = (rest + e_a) * ls_;
+        TC l_b = (rest + e_b) * ls_;
         if (k == 0) x0 = xa;
         ya[q] = l_a != TC(0) ? xa / l_a : TC(0);
         yb[q] = xb / l_b;

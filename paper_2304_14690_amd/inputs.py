@@ -294,6 +294,25 @@ def config4(N: int = 512) -> Case:
                       Obstacle("box", (0.6, 0.4, 0.4), (0.8, 0.6, 0.6))], 27, 27, 64, 7, 8)
 
 
+def coarse_grid_case(name: str, d: int, N_grid: int, N_nodes: int,
+                     obstacles: Sequence[Obstacle], k_grid: int, k_node: int, n_modes: int,
+                     seed_nodes: int, seed_vel: int) -> Case:
+    """A pressure grid coarser than the velocity cloud (the 256^2 grid under
+    a 400^2-density cloud of Sec. 3): an N_nodes^d jittered lattice of
+    spacing 1/N_nodes on the unit box, with the pressure grid of N_grid
+    cells per axis.  The case's n, h are the grid's; the node spacing is
+    1/N_nodes (pass it as the WLS mean spacing)."""
+    n_nodes = tuple([N_nodes] * d)
+    h_nodes = tuple([1.0 / N_nodes] * d)
+    _, _, x, kind = make_geometry_n(n_nodes, h_nodes, obstacles, seed_nodes)
+    u = fourier_velocity(x, n_modes, seed_vel)
+    u[:, kind == KIND_V] = 0.0
+    n = tuple([N_grid] * d)
+    h = tuple([1.0 / N_grid] * d)
+    return Case(name, d, n, h, x, kind, np.ascontiguousarray(u), 1.0, k_grid, k_node,
+                list(obstacles))
+
+
 def serving_geometry(d: int, N: int, seed: int):
     """Geometry of one serving request family: a circle/sphere of radius
     U(0.05, 0.15) centred in U(0.3, 0.7)^d over its own jittered cloud.

@@ -32,12 +32,14 @@ PC_ALL, PC_NEAR_IB, PC_IB = 0, 1, 2
 PC_KIND_F, PC_KIND_B, PC_KIND_V = 0, 1, 2
 PC_BC_NEUMANN, PC_BC_PERIODIC = 0, 1
 BCS = {"neumann": PC_BC_NEUMANN, "periodic": PC_BC_PERIODIC}
+PC_EIG_FD2, PC_EIG_SPECTRAL = 0, 1
+EIGS = {"fd2": PC_EIG_FD2, "spectral": PC_EIG_SPECTRAL}
 
 MODES = {"f64": PC_F64, "f32": PC_F32, "mixed": PC_MIXED}
 
 # every symbol include/pcorr.h declares
 EXPORTS = [
-    "pc_version", "pc_last_error", "pc_plan_create", "pc_plan_create_bc", "pc_plan_destroy",
+    "pc_version", "pc_last_error", "pc_plan_create", "pc_plan_create_ex", "pc_plan_destroy",
     "pc_poisson_fft_solve", "pc_wls_build", "pc_geom_destroy", "pc_geom_info",
     "pc_geom_export", "pc_div_to_grid", "pc_grad_to_nodes", "pc_ib_update", "pc_project",
     "pc_workspace_create", "pc_workspace_destroy", "pc_workspace_bytes",
@@ -85,7 +87,8 @@ def _load():
         "pc_version": ([], ctypes.c_int),
         "pc_last_error": ([ctypes.c_char_p, ctypes.c_size_t], ctypes.c_int),
         "pc_plan_create": ([ctypes.c_int, vp, vp, vp, ctypes.POINTER(vp)], ctypes.c_int),
-        "pc_plan_create_bc": ([ctypes.c_int, vp, vp, vp, vp, ctypes.POINTER(vp)], ctypes.c_int),
+        "pc_plan_create_ex": ([ctypes.c_int, vp, vp, vp, i32, vp, ctypes.POINTER(vp)],
+                              ctypes.c_int),
         "pc_plan_destroy": ([vp], ctypes.c_int),
         "pc_poisson_fft_solve": ([vp, ctypes.c_int, vp, vp, ctypes.c_int, vp, vp, vp],
                                  ctypes.c_int),
@@ -162,25 +165,28 @@ def _dtype_code(t: torch.Tensor) -> int:
 
 class Plan:
     """Grid and transform tables (pc_plan).  bc: per-axis "neumann" or
-    "periodic" (or the PC_BC_* codes); None is Neumann everywhere."""
+    "periodic" (or the PC_BC_* codes); None is Neumann everywhere.  eig:
+    "fd2" (central differences) or "spectral" (pseudo-spectral)."""
 
     def __init__(self, d: int, n: Sequence[int], h: Sequence[float], stream=None,
-                 bc: Optional[Sequence] = None):
+                 bc: Optional[Sequence] = None, eig: str = "fd2"):
         nn = (ctypes.c_int32 * 3)(*(list(n) + [1] * (3 - len(n))))
         hh = (ctypes.c_double * 3)(*(list(h) + [1.0] * (3 - len(h))))
         out = ctypes.c_void_p()
-        if bc is None:
+        if bc is None and eig == "fd2":
             _check(_lib.pc_plan_create(d, ctypes.addressof(nn), ctypes.addressof(hh),
                                        _stream(stream), ctypes.byref(out)))
             self.bc = ("neumann",) * d
         else:
-            codes = [BCS[b] if isinstance(b, str) else int(b) for b in bc]
+            codes = [BCS[b] if isinstance(b, str) else int(b) for b in (bc or ("neumann",) * d)]
             bb = (ctypes.c_int32 * 3)(*(codes + [0] * (3 - len(codes))))
-            _check(_lib.pc_plan_create_bc(d, ctypes.addressof(nn), ctypes.addressof(hh),
-                                          ctypes.addressof(bb), _stream(stream),
+            e = EIGS[eig] if isinstance(eig, str) else int(eig)
+            _check(_lib.pc_plan_create_ex(d, ctypes.addressof(nn), ctypes.addressof(hh),
+                                          ctypes.addressof(bb), e, _stream(stream),
                                           ctypes.byref(out)))
             names = {v: k for k, v in BCS.items()}
             self.bc = tuple(names.get(c, str(c)) for c in codes)
+        self.eig = eig
         self.h_ = out
         self.d, self.n, self.h = d, tuple(n), tuple(h)
         self.G = 1

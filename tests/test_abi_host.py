@@ -53,10 +53,14 @@ def test_host_side_validation():
     assert lib.pc_plan_destroy(None) == pcorr.PC_OK
     # per-axis conditions: unknown codes, and periodic axes below 32 cells
     bc = (ctypes.c_int32 * 3)(pcorr.PC_BC_PERIODIC, 7, 0)
-    assert lib.pc_plan_create_bc(2, n, h, bc, None, ctypes.byref(out)) == pcorr.PC_ERR_INVALID_ARG
+    assert lib.pc_plan_create_ex(2, n, h, bc, 0, None, ctypes.byref(out)) == \
+        pcorr.PC_ERR_INVALID_ARG
+    assert lib.pc_plan_create_ex(2, n, h, None, 5, None, ctypes.byref(out)) == \
+        pcorr.PC_ERR_INVALID_ARG
+    assert "eig" in pcorr.last_error()
     small = (ctypes.c_int32 * 3)(16, 64, 1)
     bc = (ctypes.c_int32 * 3)(pcorr.PC_BC_PERIODIC, pcorr.PC_BC_NEUMANN, 0)
-    assert lib.pc_plan_create_bc(2, small, h, bc, None, ctypes.byref(out)) == \
+    assert lib.pc_plan_create_ex(2, small, h, bc, 0, None, ctypes.byref(out)) == \
         pcorr.PC_ERR_UNSUPPORTED_SIZE
     assert "periodic" in pcorr.last_error()
 

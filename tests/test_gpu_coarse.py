@@ -1,0 +1,77 @@
+"""A pressure grid coarser than the velocity cloud (Sec. 3: the 256^2
+pressure grid under a 400^2-density cloud, the paper's largest saving):
+stencils and the whole sub-step against the float64 oracle, with the WLS
+mean spacing set to the node spacing.  Also on a periodic box.  Bars as for
+the other parity tests."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import projection as P
+from paper_2304_14690_amd import inputs
+from tests.helpers import rel_l2, to_np
+
+pytestmark = pytest.mark.gpu
+
+CASES = {
+    "2d_256_under_400": (lambda: inputs.coarse_grid_case(
+        "c2", 2, 256, 400, [inputs.Obstacle("circle", (0.4, 0.5), (0.1,))], 16, 16, 8, 41, 42),
+        1 / 400, None),
+    "3d_32_under_50": (lambda: inputs.coarse_grid_case(
+        "c3", 3, 32, 50, [inputs.Obstacle("sphere", (0.5, 0.5, 0.5), (0.2,))], 27, 27, 8, 43, 44),
+        1 / 50, None),
+    "2d_128_under_200_periodic_x": (lambda: inputs.coarse_grid_case(
+        "c2p", 2, 128, 200, [inputs.Obstacle("circle", (0.5, 0.5), (0.12,))], 16, 16, 8, 45, 46),
+        1 / 200, ("periodic", "neumann")),
+}
+_CACHE = {}
+
+
+def case(name):
+    if name not in _CACHE:
+        make, delta, bc = CASES[name]
+        c = make()
+        grid = oracle.Grid(c.d, c.n, c.h, bc)
+        st = P.build_stencils(grid, c.x.T.copy(), c.kind, c.k_grid, c.k_node, delta=delta)
+        _CACHE[name] = (c, delta, bc, grid, st)
+    return _CACHE[name]
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_coarse_grid_sub_step(name):
+    import torch
+    from paper_2304_14690_amd import pcorr as pc
+    c, delta, bc, grid, st = case(name)
+    assert c.M > grid.G
+    plan = pc.Plan(c.d, c.n, c.h, bc=bc)
+    geom = pc.wls_build(plan, torch.from_numpy(c.x).cuda(), torch.from_numpy(c.kind).cuda(),
+                        c.k_grid, c.k_node, delta=delta, want_f32=True)
+    # grid stencils: index sets and coefficients
+    gi = torch.empty((c.k_grid, grid.G), dtype=torch.int32, device="cuda")
+    gcf = torch.empty((c.d, c.k_grid, grid.G), dtype=torch.float64, device="cuda")
+    pc.geom_export(geom, gi, gcf)
+    torch.cuda.synchronize()
+    order = np.argsort(st.grid_idx, axis=1, kind="stable")
+    np.testing.assert_array_equal(to_np(gi).T, np.take_along_axis(st.grid_idx, order, axis=1))
+    assert rel_l2(np.transpose(to_np(gcf), (2, 0, 1)),
+                  np.take_along_axis(st.grid_coef, order[:, None, :], axis=2)) <= 1e-12
+    ref = P.pressure_correct(st, c.u.T.copy(), solver=lambda b: oracle.poisson.solve(grid, b))
+    res = {}
+    for mode, dtype in ((pc.PC_F64, torch.float64), (pc.PC_MIXED, torch.float64),
+                        (pc.PC_F32, torch.float32)):
+        u_in = c.u if mode != pc.PC_F32 else c.u.astype(np.float32).astype(np.float64)
+        r = ref if mode != pc.PC_F32 else P.pressure_correct(
+            st, u_in.T.copy(), fixed_it=ref["n_it"],
+            solver=lambda b: oracle.poisson.solve(grid, b))
+        ut = torch.from_numpy(u_in).to(dtype).cuda()
+        uo = torch.empty_like(ut)
+        p = torch.empty(grid.G, dtype=dtype, device="cuda")
+        rc, stats = pc.pressure_correct(geom, plan, mode, ut, 1.0, uo, p,
+                                        fixed_it=0 if mode == pc.PC_F64 else ref["n_it"])
+        torch.cuda.synchronize()
+        res[mode] = (stats["n_it"], rel_l2(to_np(uo), r["u_new"].T), rel_l2(to_np(p), r["p"]))
+    print(f"{name}: M {c.M} G {grid.G}, oracle n_it {ref['n_it']}, gpu {res}")
+    assert res[pc.PC_F64][0] == ref["n_it"]
+    assert res[pc.PC_F64][1] <= 1e-11 and res[pc.PC_F64][2] <= 1e-11
+    assert res[pc.PC_MIXED][1] <= 1e-10 and res[pc.PC_MIXED][2] <= 1e-10
+    assert res[pc.PC_F32][1] <= 5e-5 and res[pc.PC_F32][2] <= 5e-5
