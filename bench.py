@@ -18,6 +18,9 @@ Workloads (all inputs seeded and synthetic, resident in HBM before timing):
   2d2048p 2d2048 with a periodic x axis (a channel: periodic lateral faces,
           as in the paper's verification cases, Sec. 3) and Neumann walls in y.
   3d256p  3d256 with periodic x and z axes and Neumann walls in y.
+  2d1024c the 2d2048 node cloud (the same 4.2M nodes and cylinder) under a
+          1024^2 pressure grid: a pressure grid coarser than the velocity
+          cloud, the saving Sec. 3 reports (WLS mean spacing = node spacing).
 The stencils are built once (timed separately, not part of a step).  A step
 is one complete pressure-correction sub-step (RHS transfer, IB-force
 iterations of Poisson solve + gradient at the IB + force update, final
@@ -60,6 +63,10 @@ WORKLOADS = {
                "desc": "3D 256^3 grid, {M} jittered nodes, sphere r=0.1 at the centre, 27-NN "
                        "WLS, 64-mode velocity, periodic in x and z, Neumann walls in y, "
                        "cold IB start"},
+    "2d1024c": {"d": 2, "N": 1024, "modes": "f64,f32,mixed", "cpu_N": 512, "nodes_per_axis": 2,
+                "desc": "2D 1024^2 pressure grid under the 2048^2 workload's {M} jittered "
+                        "nodes (node spacing 1/2048), cylinder r=0.05 at (0.3,0.5), 16-NN WLS, "
+                        "32-mode velocity, Neumann box, cold IB start"},
     "3d512": {"d": 3, "N": 512, "modes": "f64,mixed,mixed3", "cpu_N": 64,
               "desc": "3D 512^3 grid, {M} jittered nodes, sphere r=0.1 at (0.3,0.5,0.5) plus "
                       "box [0.6,0.8]x[0.4,0.6]^2, 27-NN WLS, 64-mode velocity, Neumann box, "
@@ -120,6 +127,12 @@ def make_workload(name, N):
     import torch
     from paper_2304_14690_amd import inputs
     bc = WORKLOADS[name].get("bc")
+    if name == "2d1024c":
+        c = inputs.coarse_grid_case(name, 2, N, 2 * N,
+                                    [inputs.Obstacle("circle", (0.3, 0.5), (0.05,))],
+                                    16, 16, 32, 3, 4)
+        return {"d": 2, "n": c.n, "h": c.h, "x": c.x, "kind": c.kind, "k": c.k_grid,
+                "u": torch.from_numpy(c.u).cuda(), "bc": None, "delta": 1.0 / (2 * N)}
     if name in ("2d2048", "2d2048p"):
         c = inputs.make_case(name, 2, N, [inputs.Obstacle("circle", (0.3, 0.5), (0.05,))],
                              16, 16, 32, 3, 4, bc=bc)
@@ -178,7 +191,8 @@ def main():
     want_f32 = "f32" in modes
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    geom = pc.wls_build(plan, x, kind, case["k"], case["k"], want_f32=want_f32)
+    geom = pc.wls_build(plan, x, kind, case["k"], case["k"], want_f32=want_f32,
+                        delta=case.get("delta", 0.0))
     torch.cuda.synchronize()
     t_build = time.perf_counter() - t0
     del x, kind
@@ -440,7 +454,13 @@ def cpu_baseline(workload, N):
     from paper_2304_14690_amd import inputs
     cores = len(os.sched_getaffinity(0))
     bc = WORKLOADS[workload].get("bc")
-    if workload in ("2d2048", "2d2048p"):
+    delta = None
+    if workload == "2d1024c":
+        c = inputs.coarse_grid_case(workload, 2, N, 2 * N,
+                                    [inputs.Obstacle("circle", (0.3, 0.5), (0.05,))],
+                                    16, 16, 32, 3, 4)
+        delta = 1.0 / (2 * N)
+    elif workload in ("2d2048", "2d2048p"):
         c = inputs.make_case(workload, 2, N, [inputs.Obstacle("circle", (0.3, 0.5), (0.05,))],
                              16, 16, 32, 3, 4, bc=bc)
     elif workload in ("3d256", "3d256p"):
@@ -450,7 +470,8 @@ def cpu_baseline(workload, N):
         c = inputs.config4(N)
     grid = oracle.Grid(c.d, c.n, c.h, bc)
     t0 = time.perf_counter()
-    st = P.build_stencils(grid, c.x.T.copy(), c.kind, c.k_grid, c.k_node, workers=cores)
+    st = P.build_stencils(grid, c.x.T.copy(), c.kind, c.k_grid, c.k_node, workers=cores,
+                          delta=delta)
     t_build = time.perf_counter() - t0
     u = c.u.T.copy()
     times = []
