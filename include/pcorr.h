@@ -61,8 +61,8 @@ extern "C" {
 #define PC_OK 0
 #define PC_WARN_IB_NOT_CONVERGED 1   /* max_it reached before the criterion */
 #define PC_ERR_INVALID_ARG (-1)      /* null pointer, bad enum, k too small  */
-#define PC_ERR_UNSUPPORTED_SIZE (-2) /* n not a power of two in [8, 4096],   */
-                                     /* d not 2 or 3, k above the maximum    */
+#define PC_ERR_UNSUPPORTED_SIZE (-2) /* n odd or outside [8, 4096], d not 2  */
+                                     /* or 3, k above the maximum            */
 #define PC_ERR_ALIGN (-3)            /* device pointer not 16-byte aligned   */
 #define PC_ERR_OOM (-4)              /* device allocation failed             */
 #define PC_ERR_SINGULAR_STENCIL (-5) /* a WLS normal matrix is singular      */
@@ -162,13 +162,18 @@ int pc_last_error(char* buf, size_t n);
  * tables of the cosine transforms and the 1D eigenvalues
  * -(4/h_a^2) sin^2(pi k / (2 n_a)) of the mirror-ghost central-difference
  * Laplacian (homogeneous Neumann condition, Eq. 7), and uploads them (plus
- * float32 copies).  n[a] must be a power of two in [8, 4096].  Synchronises
- * `stream`.  Release with pc_plan_destroy. */
+ * float32 copies).  n[a] must be even and in [8, 4096].  Powers of two of
+ * at least 32 take the register-resident transform kernels; other lengths
+ * (such as the 400 x 402 and 280 x 480 grids of Sec. 3) take a mixed-radix
+ * kernel staged in LDS whose cost per line grows with the sum of the prime
+ * factors of n/2, and the IB iteration then transforms every line.
+ * Synchronises `stream`.  Release with pc_plan_destroy. */
 int pc_plan_create(int d, const int32_t* n, const double* h, void* stream, pc_plan** out);
 
 /* pc_plan_create with a boundary condition per axis and a choice of
  * eigenvalues.
  *   bc[a] = PC_BC_NEUMANN or PC_BC_PERIODIC (bc NULL: Neumann everywhere).
+ *     A plan with a periodic axis needs every n[a] to be a power of two.
  *     A periodic axis of n cells (n a power of two in [32, 4096]) joins cell
  *     n-1 to cell 0; its transform is the real DFT, packed into n reals, and
  *     its central-difference eigenvalues are -(4/h_a^2) sin^2(pi k / n_a),

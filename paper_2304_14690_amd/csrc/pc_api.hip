@@ -149,17 +149,23 @@ int pc_plan_create_ex(int d, const int32_t* n, const double* h, const int32_t* b
   if (eig != PC_EIG_FD2 && eig != PC_EIG_SPECTRAL)
     return fail(PC_ERR_INVALID_ARG, "eig must be PC_EIG_FD2 or PC_EIG_SPECTRAL");
   if (d != 2 && d != 3) return fail(PC_ERR_UNSUPPORTED_SIZE, "d must be 2 or 3");
+  bool any_periodic = false, all_pow2 = true;
   for (int a = 0; a < d; ++a) {
     const int32_t b = bc ? bc[a] : PC_BC_NEUMANN;
     if (b != PC_BC_NEUMANN && b != PC_BC_PERIODIC)
       return fail(PC_ERR_INVALID_ARG, "bc[a] must be PC_BC_NEUMANN or PC_BC_PERIODIC");
-    if (!is_pow2(n[a]) || n[a] < 8 || n[a] > 4096)
-      return fail(PC_ERR_UNSUPPORTED_SIZE, "n[a] must be a power of two in [8, 4096]");
-    if (b == PC_BC_PERIODIC && n[a] < 32)
+    if (n[a] < 8 || n[a] > 4096 || (n[a] & 1))
+      return fail(PC_ERR_UNSUPPORTED_SIZE, "n[a] must be even and in [8, 4096]");
+    if (b == PC_BC_PERIODIC && (!is_pow2(n[a]) || n[a] < 32))
       return fail(PC_ERR_UNSUPPORTED_SIZE, "a periodic axis needs a power of two in [32, 4096]");
+    any_periodic = any_periodic || b == PC_BC_PERIODIC;
+    all_pow2 = all_pow2 && is_pow2(n[a]);
     if (!(h[a] > 0.0) || !std::isfinite(h[a]))
       return fail(PC_ERR_INVALID_ARG, "h[a] must be positive and finite");
   }
+  if (any_periodic && !all_pow2)
+    return fail(PC_ERR_UNSUPPORTED_SIZE,
+                "a plan with a periodic axis needs every n[a] to be a power of two");
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
     (void)hipGetLastError();

@@ -34,97 +34,49 @@ namespace {
 constexpr int ROW_THREADS = 256;
 constexpr int COL_MAX_THREADS = 512;
 
-// Radix-4 / radix-2 Stockham FFT of the C lines held in LDS (complex view,
-// line c at zc + c*ls).  B butterflies per thread per radix-4 stage.
-template <typename TC, int B, bool INV>
-__device__ __forceinline__ void fft_lds(cplx<TC>* zc, int ls, int C, int H, int logH,
-                                        const cplx<TC>* __restrict__ twH, int tid, int nthr) {
+// Mixed-radix Stockham FFT of the C lines held in LDS, for any H whose
+// factors are listed in A.rad (complex view, line c at a + c*lsc; b is a
+// second buffer of the same shape).  The stage of radix r after the stages
+// of combined length L produces output p of a line as
+//   s' = (p / L) mod r,  k = p mod L,  j = (p / (L r)) L + k,
+//   out[p] = sum_{s<r} in[j + (H/r) s] w^(s (k + L s')),  w = exp(-+2 pi i / (L r)),
+// a direct sum over the radix (so a prime factor such as 67 costs r terms per
+// output), with w^e = twH[(H / (L r)) e].  Returns the buffer holding the
+// result (the stages alternate between a and b).
+template <typename TC, bool INV>
+__device__ cplx<TC>* fft_lds_mixed(cplx<TC>* a, cplx<TC>* b, int lsc, int C, int H,
+                                   const LineArgs<TC>& A, int tid, int nthr) {
+  const cplx<TC>* __restrict__ twH = A.tab.twH;
   int L = 1;
-  int rem = logH;
-  while (rem > 0) {
-    if (rem >= 2) {
-      const int nb = H >> 2;  // butterflies per line
-      cplx<TC> a[B][4];
-      int pos[B];
-      int lc[B];
-#pragma unroll
-      for (int b = 0; b < B; ++b) {
-        int bi = tid + b * nthr;
-        lc[b] = -1;
-        if (bi < C * nb) {
-          int c = bi / nb;
-          int j = bi - c * nb;
-          int k = j & (L - 1);
-          cplx<TC>* z = zc + c * ls;
-          int tstep = (H / (L * 4)) * k;
-#pragma unroll
-          for (int r = 0; r < 4; ++r) a[b][r] = z[j + r * nb];
-#pragma unroll
-          for (int r = 1; r < 4; ++r) {
-            cplx<TC> w = twH[tstep * r];
-            a[b][r] = INV ? cmulc(a[b][r], w) : cmul(a[b][r], w);
-          }
-          cplx<TC> t0 = cadd(a[b][0], a[b][2]), t1 = csub(a[b][0], a[b][2]);
-          cplx<TC> t2 = cadd(a[b][1], a[b][3]), t3 = csub(a[b][1], a[b][3]);
-          // -i*t3 (forward) or +i*t3 (inverse)
-          cplx<TC> it3 = INV ? cplx<TC>{-t3.im, t3.re} : cplx<TC>{t3.im, -t3.re};
-          a[b][0] = cadd(t0, t2);
-          a[b][2] = csub(t0, t2);
-          a[b][1] = cadd(t1, it3);
-          a[b][3] = csub(t1, it3);
-          lc[b] = c;
-          pos[b] = (j - k) * 4 + k;
-        }
+  for (int st = 0; st < A.nrad; ++st) {
+    const int r = A.rad[st];
+    const int nb = H / r;
+    const int Lr = L * r;
+    const int tstep = H / Lr;
+    for (int e = tid; e < C * H; e += nthr) {
+      const int c = e / H, p = e - c * H;
+      const int sp = (p / L) % r, k = p % L;
+      const int j = (p / Lr) * L + k;
+      const int q = k + L * sp;
+      const cplx<TC>* x = a + c * lsc;
+      cplx<TC> acc = x[j];
+      int ex = 0;
+      for (int sidx = 1; sidx < r; ++sidx) {
+        ex += q;
+        if (ex >= Lr) ex -= Lr;
+        const cplx<TC> w = twH[tstep * ex];
+        const cplx<TC> v = x[j + nb * sidx];
+        acc = cadd(acc, INV ? cmulc(v, w) : cmul(v, w));
       }
-      __syncthreads();
-#pragma unroll
-      for (int b = 0; b < B; ++b) {
-        if (lc[b] >= 0) {
-          cplx<TC>* z = zc + lc[b] * ls;
-#pragma unroll
-          for (int r = 0; r < 4; ++r) z[pos[b] + r * L] = a[b][r];
-        }
-      }
-      __syncthreads();
-      L <<= 2;
-      rem -= 2;
-    } else {
-      const int nb = H >> 1;
-      cplx<TC> a[2 * B][2];
-      int pos[2 * B];
-      int lc[2 * B];
-#pragma unroll
-      for (int b = 0; b < 2 * B; ++b) {
-        int bi = tid + b * nthr;
-        lc[b] = -1;
-        if (bi < C * nb) {
-          int c = bi / nb;
-          int j = bi - c * nb;
-          int k = j & (L - 1);
-          cplx<TC>* z = zc + c * ls;
-          cplx<TC> x0 = z[j], x1 = z[j + nb];
-          cplx<TC> w = twH[(H / (L * 2)) * k];
-          x1 = INV ? cmulc(x1, w) : cmul(x1, w);
-          a[b][0] = cadd(x0, x1);
-          a[b][1] = csub(x0, x1);
-          lc[b] = c;
-          pos[b] = (j - k) * 2 + k;
-        }
-      }
-      __syncthreads();
-#pragma unroll
-      for (int b = 0; b < 2 * B; ++b) {
-        if (lc[b] >= 0) {
-          cplx<TC>* z = zc + lc[b] * ls;
-          z[pos[b]] = a[b][0];
-          z[pos[b] + L] = a[b][1];
-        }
-      }
-      __syncthreads();
-      L <<= 1;
-      rem -= 1;
+      b[c * lsc + p] = acc;
     }
+    __syncthreads();
+    cplx<TC>* t = a;
+    a = b;
+    b = t;
+    L = Lr;
   }
+  return a;
 }
 
 // Forward post-processing of pair k (0 <= k <= H/2) of one line: from the
@@ -134,7 +86,7 @@ __device__ __forceinline__ void post_pair(const cplx<TC>* z, int k, int N, int H
                                           const AxisTables<TC>& T, TC* xk, TC* xnk, TC* xhk,
                                           TC* xhpk) {
   cplx<TC> Zk = z[k];
-  cplx<TC> Zc = conj_(z[(H - k) & (H - 1)]);
+  cplx<TC> Zc = conj_(z[k ? H - k : 0]);
   cplx<TC> E = {(Zk.re + Zc.re) * TC(0.5), (Zk.im + Zc.im) * TC(0.5)};
   cplx<TC> D = {(Zk.re - Zc.re) * TC(0.5), (Zk.im - Zc.im) * TC(0.5)};
   cplx<TC> O = {D.im, -D.re};  // -i * D
@@ -166,6 +118,11 @@ __device__ __forceinline__ void pre_pair(TC xk, TC xnk, TC xhk, TC xhpk, int k, 
   *Zhk = {E.re + O.im, -E.im + O.re};    // conj(E) + i conj(O)
 }
 
+// The generic line transform (cosine transforms of Neumann axes of any even
+// length N, short or not a power of two): C lines per workgroup staged in
+// LDS, the mixed-radix FFT above, pairs (k, H-k) of the real-FFT split per
+// thread.  Two LDS buffers of C lines each.  With H odd no pair is its own
+// partner; with H even the pair k = H/2 is.
 template <typename TC, typename TI, typename TO, int OP, int LD, int ST, int B>
 __global__ void __launch_bounds__(1024) dct_lines(LineArgs<TC> A) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -173,6 +130,7 @@ __global__ void __launch_bounds__(1024) dct_lines(LineArgs<TC> A) {
   TC* s = reinterpret_cast<TC*>(smem_raw);
   const int N = A.N, H = N >> 1, C = A.C;
   const int ls = N + A.pad;  // line stride in LDS (reals)
+  TC* s2 = s + (size_t)C * ls;  // second buffer
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int t = A.axis == 0 ? blockIdx.x : xcd_tile(blockIdx.x, gridDim.x);
   const TI* __restrict__ in = reinterpret_cast<const TI*>(A.in);
@@ -200,8 +158,10 @@ __global__ void __launch_bounds__(1024) dct_lines(LineArgs<TC> A) {
   __syncthreads();
 
   cplx<TC>* zc = reinterpret_cast<cplx<TC>*>(s);
+  cplx<TC>* zc2 = reinterpret_cast<cplx<TC>*>(s2);
   const int lsc = ls >> 1;
   const int npair = H / 2 + 1;
+  const TC* res = s;  // reals of the final result (natural or Makhoul order)
 
   if (OP == OP_INV) {
     // pre-process pairs into Z (in place through registers)
@@ -232,9 +192,9 @@ __global__ void __launch_bounds__(1024) dct_lines(LineArgs<TC> A) {
       }
     }
     __syncthreads();
-    fft_lds<TC, B, true>(zc, lsc, C, H, A.logH, A.tab.twH, tid, nthr);
+    res = reinterpret_cast<const TC*>(fft_lds_mixed<TC, true>(zc, zc2, lsc, C, H, A, tid, nthr));
   } else {
-    fft_lds<TC, B, false>(zc, lsc, C, H, A.logH, A.tab.twH, tid, nthr);
+    const cplx<TC>* zf = fft_lds_mixed<TC, false>(zc, zc2, lsc, C, H, A, tid, nthr);
     constexpr int PB = 2 * B + 1;
     TC xa[PB], xb[PB], xc[PB], xd[PB];
     int ck[PB], kk[PB];
@@ -244,7 +204,7 @@ __global__ void __launch_bounds__(1024) dct_lines(LineArgs<TC> A) {
       ck[b] = -1;
       if (w < C * npair) {
         int c = w / npair, k = w - c * npair;
-        post_pair(zc + c * lsc, k, N, H, A.tab, &xa[b], &xb[b], &xc[b], &xd[b]);
+        post_pair(zf + c * lsc, k, N, H, A.tab, &xa[b], &xb[b], &xc[b], &xd[b]);
         ck[b] = c;
         kk[b] = k;
       }
@@ -262,7 +222,7 @@ __global__ void __launch_bounds__(1024) dct_lines(LineArgs<TC> A) {
           if (A.lam1) rest += A.lam1[o];
           const TC* lam = A.tab.lam;
           const TC ls_ = A.lscale;
-          TC l0 = (rest + lam[k]) * ls_, l1 = (rest + lam[(N - k) & (N - 1)]) * ls_,
+          TC l0 = (rest + lam[k]) * ls_, l1 = (rest + lam[k ? N - k : 0]) * ls_,
              l2 = (rest + lam[H - k]) * ls_, l3 = (rest + lam[H + k]) * ls_;
           if (k == 0) {
             if (rest == TC(0) && A.bmean) *A.bmean = (double)xa[b] * A.meannorm;
@@ -287,7 +247,7 @@ __global__ void __launch_bounds__(1024) dct_lines(LineArgs<TC> A) {
         }
       }
       __syncthreads();
-      fft_lds<TC, B, true>(zc, lsc, C, H, A.logH, A.tab.twH, tid, nthr);
+      res = reinterpret_cast<const TC*>(fft_lds_mixed<TC, true>(zc, zc2, lsc, C, H, A, tid, nthr));
     } else {
       __syncthreads();
 #pragma unroll
@@ -295,13 +255,16 @@ __global__ void __launch_bounds__(1024) dct_lines(LineArgs<TC> A) {
         if (ck[b] >= 0) {
           TC* x = s + ck[b] * ls;
           int k = kk[b];
+          // the pair k = H/2 (H even) is its own partner: X[H-k] = X[k] and
+          // X[H+k] = X[N-k] are written once
           x[k] = xa[b];
           if (k != 0) x[N - k] = xb[b];
-          if (k != H / 2 || H == 1) x[H - k] = xc[b];
-          if (k != 0 && k != H / 2) x[H + k] = xd[b];
+          if (2 * k != H || H == 1) x[H - k] = xc[b];
+          if (k != 0 && 2 * k != H) x[H + k] = xd[b];
         }
       }
       __syncthreads();
+      res = s;
     }
   }
 
@@ -312,7 +275,7 @@ __global__ void __launch_bounds__(1024) dct_lines(LineArgs<TC> A) {
     int i, o;
     int64_t p = line_base(A, t, c, &i, &o) + (int64_t)n * A.stride;
     int q = (OP == OP_FWD) ? n : mk_pos(n, N);
-    TC v = s[c * ls + q] * A.outscale;
+    TC v = res[c * ls + q] * A.outscale;
     if (ST == ST_ACCUM) {
       reinterpret_cast<double*>(A.out)[p] = A.rphi[p] + (double)v;
     } else {
@@ -385,22 +348,23 @@ int lds_limit() {
   return g_lds_limit;
 }
 
-// Chooses lines per tile and threads for one pass.
+// Chooses lines per tile and threads for one pass of the generic kernel
+// (two LDS buffers of C lines; C a power of two that divides lines_x, the
+// row count or the x extent).
 template <typename TC>
 void tile_shape(int axis, int N, int lines_x, int* C, int* nthr, int* B) {
   const int H = N / 2;
   const int lim = lds_limit();
   int c;
   if (axis == 0) {
-    c = 1024 / H;  // aim for C*H/4 = 256 threads
-    if (c < 1) c = 1;
-    while (c > lines_x) c >>= 1;
+    c = 1;
+    while (2 * c <= 1024 / H) c <<= 1;  // aim for C*H/4 = 256 threads
   } else {
     c = (int)(128 / sizeof(TC));  // 128-byte row segments
-    while (c > 1 && (size_t)c * N * sizeof(TC) > (size_t)lim / 2) c >>= 1;
-    while (c > lines_x) c >>= 1;
+    while (c > 1 && (size_t)c * N * sizeof(TC) * 2 > (size_t)lim / 2) c >>= 1;
   }
-  while (c > 1 && (size_t)c * N * sizeof(TC) > (size_t)lim) c >>= 1;
+  while (c > 1 && (c > lines_x || lines_x % c)) c >>= 1;
+  while (c > 1 && (size_t)c * N * sizeof(TC) * 2 > (size_t)lim) c >>= 1;
   int want = c * H / 4;
   if (want < 64) want = 64;
   int t = want > 1024 ? 1024 : want;
@@ -416,6 +380,27 @@ void tile_shape(int axis, int N, int lines_x, int* C, int* nthr, int* B) {
 // Complex values per thread of the transforms along `axis`: 16, or 8 when
 // the pass has too few lines to give the device four wavefronts per SIMD
 // with 16 (a 2D grid; small 3D grids), which doubles the wavefronts.
+// Radices of the generic kernel's FFT of half length H: fours, a two,
+// then the odd primes.
+int generic_radices(int H, int* rad) {
+  int n = 0;
+  for (int r : {4, 2}) {
+    while (H % r == 0 && H > 1 && n < 24) {
+      rad[n++] = r;
+      H /= r;
+    }
+  }
+  for (int p = 3; H > 1 && n < 24; p += 2) {
+    while (H % p == 0 && n < 24) {
+      rad[n++] = p;
+      H /= p;
+    }
+  }
+  return H == 1 ? n : -1;
+}
+
+bool pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+
 int pass_radix(const pc_plan* P, int axis) {
   const int64_t N = P->n[axis];
   const int64_t lines = P->G / N;
@@ -428,16 +413,18 @@ int pass_radix(const pc_plan* P, int axis) {
 // the axis uses the generic kernel, N < 32).
 int r16_tile_lines(const pc_plan* P, int axis, size_t elem) {
   const int N = P->n[axis];
-  if (N < 32) return 0;
+  if (N < 32 || !pow2(N)) return 0;
   const int H = N / 2, T = H / pass_radix(P, axis), LS = H + H / 16 + 1;
   const int64_t lines = P->G / N;
   int C;
+  // C divides the row count (rows) or the x extent (strided lines), which
+  // need not be powers of two when another axis is not
   if (axis == 0) {
     C = std::max(1, ROW_THREADS / T);
-    while (C > 1 && (int64_t)C > lines) C >>= 1;
+    while (C > 1 && ((int64_t)C > lines || lines % C)) C >>= 1;
   } else {
     C = (int)(128 / elem);
-    while (C > 1 && (C * T > COL_MAX_THREADS || C > P->n[0])) C >>= 1;
+    while (C > 1 && (C * T > COL_MAX_THREADS || C > P->n[0] || P->n[0] % C)) C >>= 1;
   }
   while (C > 1 && (size_t)C * LS * 2 * elem > (size_t)lds_limit()) C >>= 1;
   return C;
@@ -487,7 +474,7 @@ int launch_pass(const pc_plan* P, int axis, const TI* in, TO* out, const AxisTab
   for (int a = 0; a < P->d; ++a)
     if (P->bc[a] == PC_BC_PERIODIC) A.perm |= 1 << a;
   int64_t lines = P->G / A.N;
-  if (A.N >= 32) {
+  if (A.N >= 32 && pow2(A.N)) {
     // register kernel: T = H/RT threads per line, C lines per group
     const int RT = pass_radix(P, axis);
     const int T = H / RT;
@@ -516,10 +503,11 @@ int launch_pass(const pc_plan* P, int axis, const TI* in, TO* out, const AxisTab
   }
   if (P->bc[axis] == PC_BC_PERIODIC)
     return fail(PC_ERR_UNSUPPORTED_SIZE, "a periodic axis needs at least 32 cells");
+  A.nrad = generic_radices(H, A.rad);
+  if (A.nrad < 0) return fail(PC_ERR_UNSUPPORTED_SIZE, "transform length has too many factors");
   int C, nthr, B;
 
-  tile_shape<TC>(axis, A.N, axis == 0 ? (int)std::min<int64_t>(lines, 1 << 20) : P->n[0], &C,
-                 &nthr, &B);
+  tile_shape<TC>(axis, A.N, axis == 0 ? (int)lines : P->n[0], &C, &nthr, &B);
   A.C = C;
   if (C > nthr) return fail(PC_ERR_UNSUPPORTED_SIZE, "transform tile has more lines than threads");
   int ntile;
@@ -531,8 +519,9 @@ int launch_pass(const pc_plan* P, int axis, const TI* in, TO* out, const AxisTab
     ntile = (int)(lines / C);
   }
   // pad each LDS line by one complex when it fits (fewer bank conflicts)
-  A.pad = ((size_t)C * (A.N + 2) * sizeof(TC) <= (size_t)lds_limit()) ? 2 : 0;
-  size_t lds = (size_t)C * (A.N + A.pad) * sizeof(TC);
+  A.pad = ((size_t)C * (A.N + 2) * sizeof(TC) * 2 <= (size_t)lds_limit()) ? 2 : 0;
+  size_t lds = (size_t)C * (A.N + A.pad) * sizeof(TC) * 2;
+  if (lds > (size_t)lds_limit()) return fail(PC_ERR_UNSUPPORTED_SIZE, "transform line too long");
   dim3 grid(ntile), block(nthr);
   const void* fn;
   switch (B) {
@@ -667,7 +656,7 @@ int solve_mixed(const pc_plan* P, const double* b, double* phi, int sweeps, doub
 bool resident_ok(const pc_plan* P, const pc_geom* g, int mode) {
   if (!g || g->n_ib == 0 || (mode != PC_F64 && mode != PC_F32)) return false;
   for (int a = 0; a < P->d; ++a)
-    if (P->n[a] < 32) return false;
+    if (P->n[a] < 32 || !pow2(P->n[a])) return false;
   return true;
 }
 

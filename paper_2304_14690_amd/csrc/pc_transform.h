@@ -51,6 +51,8 @@ struct LineArgs {
   const int32_t* skip;  // nullable: the launch does nothing when *skip != 0
   const int32_t* tiles; // nullable: workgroup b transforms tile tiles[b]
   int N, logH;
+  int nrad;             // generic kernel: the radices of the half length H
+  int rad[24];
   int pad;              // LDS line padding in reals (0 or 2)
   int C;                // lines per tile
   int tx;               // tiles along x (strided axes)

@@ -41,7 +41,7 @@ def test_host_side_validation():
     h = (ctypes.c_double * 3)(1 / 64, 1 / 64, 1.0)
     assert lib.pc_plan_create(4, n, h, None, ctypes.byref(out)) == pcorr.PC_ERR_UNSUPPORTED_SIZE
     assert "d must be" in pcorr.last_error()
-    bad = (ctypes.c_int32 * 3)(48, 64, 1)
+    bad = (ctypes.c_int32 * 3)(49, 64, 1)
     assert lib.pc_plan_create(2, bad, h, None, ctypes.byref(out)) == pcorr.PC_ERR_UNSUPPORTED_SIZE
     assert lib.pc_plan_create(2, None, h, None, ctypes.byref(out)) == pcorr.PC_ERR_INVALID_ARG
     negh = (ctypes.c_double * 3)(-1.0, 1.0, 1.0)

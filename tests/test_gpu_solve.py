@@ -129,7 +129,7 @@ def test_deterministic_and_inplace(pc):
 def test_argument_errors(pc):
     import torch
     with pytest.raises(pc.PcError) as e:
-        pc.Plan(2, (48, 64), (1.0, 1.0))
+        pc.Plan(2, (49, 64), (1.0, 1.0))
     assert e.value.code == pc.PC_ERR_UNSUPPORTED_SIZE
     plan = pc.Plan(2, (16, 16), (1.0, 1.0))
     b = torch.zeros(256, dtype=torch.float64, device="cuda")
