@@ -114,7 +114,9 @@ typedef struct pc_wls_opts {
                      /* the geometric mean of the per-axis spacings)        */
   int32_t dtype_mask;/* PC_F64 and/or PC_F32 stencil copies to keep; bit    */
                      /* (1 << mode) for each mode; 0 = float64 only         */
-  int32_t reserved;
+  int32_t k_self;    /* > 0: also build node-to-node stencils of k_self     */
+                     /* other nodes for the first fractional step           */
+                     /* (pc_momentum_predict); 0 = none                    */
 } pc_wls_opts;
 
 /* Options of the IB-force iteration (Sec. 2.3). */
@@ -252,6 +254,15 @@ int pc_geom_export(const pc_geom* geom, int32_t* grid_idx_dev, double* grid_coef
                    int32_t* node_base_dev, double* node_coef_dev, int32_t* ib_dev,
                    int32_t* near_dev, void* stream);
 
+/* Copies the node-to-node stencils out (geometry built with k_self > 0):
+ *   idx_dev  int32   [k_self][M]       neighbour node indices, ascending (the
+ *                                      selection is by (d^2, idx), the node
+ *                                      itself excluded)
+ *   coef_dev float64 [d+1][k_self][M]  rows d_x, d_y(, d_z) and the Laplacian,
+ *                                      applied to f(x_i) - f(x)
+ * Either pointer may be NULL. */
+int pc_geom_export_self(const pc_geom* geom, int32_t* idx_dev, double* coef_dev, void* stream);
+
 /* ---- right-hand side ------------------------------------------------------ */
 
 /* b = WLS divergence of v at the grid points (Sec. 2.3, Eq. 20 right-hand
@@ -293,6 +304,36 @@ int pc_ib_update(const pc_geom* geom, int dtype, const void* u_dev, const void* 
  * u_dev, grad_dev, u_out_dev [d][M] (dtype).  u_out may alias u. */
 int pc_project(const pc_geom* geom, int dtype, const void* u_dev, const void* grad_dev,
                void* u_out_dev, void* stream);
+
+/* ---- the first fractional step (Eq. 3) ------------------------------------- */
+
+/* The intermediate velocity of the second-order Adams-Bashforth step with the
+ * pressure gradient dropped from R^n (Eq. 3):
+ *   R     = -u_j d_j u + nu lap u + F   at every node, from the node-to-node
+ *           stencils of the geometry (pc_wls_opts.k_self > 0: the known-value
+ *           WLS form of Sec. 2.2, Eqs. 10-15, over the k_self nearest other
+ *           nodes);
+ *   u*    = u + dt (3/2 R - 1/2 R_prev), or u + dt R when r_prev_dev is NULL
+ *           (the first step); 0 at the virtual points (the frozen fluid of
+ *           Sec. 2.3).
+ * u_dev, r_prev_dev (nullable), r_dev (out: R) and ustar_dev (out) are
+ * [d][M] in dtype (PC_F32 needs a geometry built with float32 stencils).
+ * force (host, nullable) is the body force F, d values.  ustar_dev must not
+ * alias u_dev; r_dev may alias r_prev_dev.  Pass u* to pc_pressure_correct,
+ * then pc_momentum_pressure for the next step's R_prev. */
+int pc_momentum_predict(const pc_geom* geom, int dtype, const void* u_dev, const void* r_prev_dev,
+                        double dt, double nu, const double* force, void* r_dev, void* ustar_dev,
+                        void* stream);
+
+/* R_prev for the next step: R^n - grad p^n at every node (R^{n-1} of Eq. 3
+ * includes the pressure gradient), where Eq. 18 gives grad p^n =
+ * 2 (u* - u^{n+1} + g) / (3 dt) with g the IB force times dt at the B+V
+ * nodes.  r_dev, ustar_dev, unew_dev, r_prev_dev [d][M]; g_ib_dev [d][n_ib]
+ * as returned by pc_pressure_correct (nullable: zero); r_prev_dev may alias
+ * r_dev. */
+int pc_momentum_pressure(const pc_geom* geom, int dtype, const void* r_dev, const void* ustar_dev,
+                         const void* unew_dev, const void* g_ib_dev, double dt, void* r_prev_dev,
+                         void* stream);
 
 /* ---- the whole sub-step ------------------------------------------------------ */
 

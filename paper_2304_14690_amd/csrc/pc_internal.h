@@ -122,6 +122,15 @@ struct pc_geom {
   int32_t* ibbase;      // [n_ib]
   double* ibcoef;       // [d][bn][ibs]
   float* ibcoef32;
+  // node-to-node stencils of the first fractional step (k_self = 0: none):
+  // neighbour node sidx [k_self][ms] (ascending), coefficients
+  // scoef [d+1][k_self][ms] (d first-derivative rows, then the Laplacian row)
+  int k_self;
+  int32_t* sidx;
+  double* scoef;
+  float* scoef32;
+  int64_t n_v;       // virtual nodes
+  int32_t* vlist;    // [n_v] their indices
   int64_t bytes;
   pc_workspace* own_ws;
 };

@@ -871,6 +871,121 @@ int pressure_correct_t(const pc_geom* g, const pc_plan* P, int mode, const T* u,
   return converged ? PC_OK : PC_WARN_IB_NOT_CONVERGED;
 }
 
+// ---- the first fractional step (Eq. 3) ---------------------------------------------
+struct Force3 {
+  double f[3];
+};
+
+// R = -u.grad u + nu lap u + F at every node from its node-to-node stencil
+// (known-value WLS rows applied to u(x_i) - u(x)), and the Adams-Bashforth
+// predictor u* = u + dt (3/2 R - 1/2 R_prev) (u + dt R when rprev is null).
+// One thread per node; the stencil streams are coalesced over nodes.
+template <typename T, int D, int K>
+__global__ void __launch_bounds__(TPB) k_momentum(const int32_t* __restrict__ sidx,
+                                                  const T* __restrict__ scoef, int64_t M,
+                                                  int64_t ms, int krt, const T* __restrict__ u,
+                                                  const T* __restrict__ rprev, T dt, T nu,
+                                                  Force3 F, T* __restrict__ rout,
+                                                  T* __restrict__ ustar) {
+  const int k = K > 0 ? K : krt;
+  const int64_t n = xcd_block(blockIdx.x, gridDim.x) * TPB + threadIdx.x;
+  if (n >= M) return;
+  T un[D], lp[D], gr[D][D];
+#pragma unroll
+  for (int c = 0; c < D; ++c) {
+    un[c] = u[c * M + n];
+    lp[c] = T(0);
+#pragma unroll
+    for (int a = 0; a < D; ++a) gr[a][c] = T(0);
+  }
+#pragma unroll 4
+  for (int i = 0; i < k; ++i) {
+    const int64_t j = ldnt(sidx + (int64_t)i * ms + n);
+    T du[D];
+#pragma unroll
+    for (int c = 0; c < D; ++c) du[c] = u[c * M + j] - un[c];
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      const T cg = ldnt(scoef + ((int64_t)a * k + i) * ms + n);
+#pragma unroll
+      for (int c = 0; c < D; ++c) gr[a][c] += cg * du[c];
+    }
+    const T cl = ldnt(scoef + ((int64_t)D * k + i) * ms + n);
+#pragma unroll
+    for (int c = 0; c < D; ++c) lp[c] += cl * du[c];
+  }
+#pragma unroll
+  for (int c = 0; c < D; ++c) {
+    T conv = T(0);
+#pragma unroll
+    for (int a = 0; a < D; ++a) conv += un[a] * gr[a][c];
+    const T R = -conv + nu * lp[c] + (T)F.f[c];
+    const T rp = rprev ? rprev[c * M + n] : T(0);
+    rout[c * M + n] = R;
+    ustar[c * M + n] = un[c] + dt * (rprev ? (T(1.5) * R - T(0.5) * rp) : R);
+  }
+}
+
+// R_prev = R - c (u* - u^{n+1}) over [d][M]; then R_prev -= c g at the B+V
+// nodes (c = 2 / (3 dt): the pressure gradient of Eq. 18)
+template <typename T>
+__global__ void __launch_bounds__(TPB) k_rprev(const T* __restrict__ r, const T* __restrict__ us,
+                                               const T* __restrict__ un, T c, int64_t n,
+                                               T* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  if (i < n) out[i] = r[i] - c * (us[i] - un[i]);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(TPB) k_rprev_ib(const int32_t* __restrict__ ib, int64_t nib,
+                                                  int d, int64_t M, const T* __restrict__ g, T c,
+                                                  T* __restrict__ out) {
+  const int64_t s = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  if (s >= nib) return;
+  const int64_t n = ib[s];
+  for (int a = 0; a < d; ++a) out[a * M + n] -= c * g[a * nib + s];
+}
+
+template <typename T>
+int momentum_predict_t(const pc_geom* g, const T* u, const T* rprev, T dt, T nu, Force3 F,
+                       T* r, T* ustar, const T* coef, hipStream_t s) {
+  dim3 grid(nblk(g->M)), block(TPB);
+#define MOM(D, K)                                                                          \
+  hipLaunchKernelGGL((k_momentum<T, D, K>), grid, block, 0, s, g->sidx, coef, g->M, g->ms, \
+                     g->k_self, u, rprev, dt, nu, F, r, ustar)
+  if (g->d == 2) {
+    if (g->k_self == 12) MOM(2, 12);
+    else if (g->k_self == 16) MOM(2, 16);
+    else MOM(2, 0);
+  } else {
+    if (g->k_self == 20) MOM(3, 20);
+    else if (g->k_self == 27) MOM(3, 27);
+    else MOM(3, 0);
+  }
+#undef MOM
+  PC_HIP_CHECK(hipGetLastError());
+  // virtual points: the frozen fluid inside the body (Sec. 2.3)
+  if (g->n_v) {
+    hipLaunchKernelGGL(k_zero_ib<T>, dim3(nblk(g->n_v)), dim3(TPB), 0, s, g->vlist, g->n_v, g->d,
+                       g->M, ustar, (const int32_t*)nullptr);
+    PC_HIP_CHECK(hipGetLastError());
+  }
+  return PC_OK;
+}
+
+template <typename T>
+int momentum_pressure_t(const pc_geom* g, const T* r, const T* us, const T* un, const T* gib,
+                        T dt, T* out, hipStream_t s) {
+  const T c = T(2.0 / (3.0 * (double)dt));
+  const int64_t n = (int64_t)g->d * g->M;
+  hipLaunchKernelGGL(k_rprev<T>, dim3(nblk(n)), dim3(TPB), 0, s, r, us, un, c, n, out);
+  if (gib && g->n_ib)
+    hipLaunchKernelGGL(k_rprev_ib<T>, dim3(nblk(g->n_ib)), dim3(TPB), 0, s, g->ib, g->n_ib, g->d,
+                       g->M, gib, c, out);
+  PC_HIP_CHECK(hipGetLastError());
+  return PC_OK;
+}
+
 int check_fields(const void* a, const void* b = nullptr, const void* c = nullptr) {
   if (!a) return fail(PC_ERR_INVALID_ARG, "null field");
   for (const void* p : {a, b, c})
@@ -1009,6 +1124,50 @@ int pc_pressure_correct(const pc_geom* g, const pc_plan* P, int mode, const void
                                      (float*)g_io, o, st, ws, s);
   return pressure_correct_t<double>(g, P, mode, (const double*)u, dt, (double*)u_out, (double*)p,
                                     (double*)g_io, o, st, ws, s);
+}
+
+int pc_momentum_predict(const pc_geom* g, int dtype, const void* u, const void* r_prev,
+                        double dt, double nu, const double* force, void* r, void* ustar,
+                        void* stream) {
+  if (!g || !u || !r || !ustar) return fail(PC_ERR_INVALID_ARG, "pc_momentum_predict: null argument");
+  if (!g->k_self)
+    return fail(PC_ERR_INVALID_ARG, "the geometry was built without node-to-node stencils");
+  if (dtype != PC_F64 && dtype != PC_F32) return fail(PC_ERR_INVALID_ARG, "dtype");
+  if (dtype == PC_F32 && !g->scoef32)
+    return fail(PC_ERR_INVALID_ARG, "geometry was built without float32 stencils");
+  if (!(dt > 0.0) || !std::isfinite(dt) || !(nu >= 0.0) || !std::isfinite(nu))
+    return fail(PC_ERR_INVALID_ARG, "dt must be positive and nu non-negative");
+  if (ustar == u) return fail(PC_ERR_INVALID_ARG, "ustar must not alias u");
+  PC_TRY(check_fields(u, r, ustar));
+  if (r_prev && !aligned16(r_prev)) return fail(PC_ERR_ALIGN, "fields must be 16-byte aligned");
+  Force3 F{{0.0, 0.0, 0.0}};
+  if (force)
+    for (int a = 0; a < g->d; ++a) F.f[a] = force[a];
+  hipStream_t s = as_stream(stream);
+  if (dtype == PC_F64)
+    return momentum_predict_t<double>(g, (const double*)u, (const double*)r_prev, dt, nu, F,
+                                      (double*)r, (double*)ustar, g->scoef, s);
+  return momentum_predict_t<float>(g, (const float*)u, (const float*)r_prev, (float)dt,
+                                   (float)nu, F, (float*)r, (float*)ustar, g->scoef32, s);
+}
+
+int pc_momentum_pressure(const pc_geom* g, int dtype, const void* r, const void* ustar,
+                         const void* unew, const void* g_ib, double dt, void* r_prev,
+                         void* stream) {
+  if (!g || !r || !ustar || !unew || !r_prev)
+    return fail(PC_ERR_INVALID_ARG, "pc_momentum_pressure: null argument");
+  if (dtype != PC_F64 && dtype != PC_F32) return fail(PC_ERR_INVALID_ARG, "dtype");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(PC_ERR_INVALID_ARG, "dt must be positive");
+  PC_TRY(check_fields(r, ustar, unew));
+  if (!aligned16(r_prev) || (g_ib && !aligned16(g_ib)))
+    return fail(PC_ERR_ALIGN, "fields must be 16-byte aligned");
+  hipStream_t s = as_stream(stream);
+  if (dtype == PC_F64)
+    return momentum_pressure_t<double>(g, (const double*)r, (const double*)ustar,
+                                       (const double*)unew, (const double*)g_ib, dt,
+                                       (double*)r_prev, s);
+  return momentum_pressure_t<float>(g, (const float*)r, (const float*)ustar, (const float*)unew,
+                                    (const float*)g_ib, (float)dt, (float*)r_prev, s);
 }
 
 }  // extern "C"

@@ -236,46 +236,27 @@ __global__ void __launch_bounds__(SCAN_B) k_scan_apply(const int32_t* __restrict
   if (i == n - 1) out[n] = (int32_t)incl;
 }
 
-// ---- grid-target stencils ---------------------------------------------------
-struct GridStencilArgs {
+// ---- k-nearest search over the cell list ------------------------------------------
+struct RingArgs {
   const double* xyz;
   int64_t M;
   GridDesc g;
   const int32_t* start;   // [G+1]
   const int32_t* sorted;  // [M]
-  int k;
-  double eps, hsup;       // hsup = support * delta
-  int32_t* gidx;          // [k][G]
-  double* gcoef;          // [d][k][G]
-  float* gcoef32;
-  int32_t* bad;           // singular flag
 };
 
+// The k nearest nodes of target xt (in cell ci) by the key (d^2, node index),
+// skipping node `exclude` (-1: none), kept in ld/li in descending key order
+// (ld[0] the worst kept).  Rings of cells at Chebyshev distance R = 0, 1, ...
+// are scanned until every unscanned node lies at least (R + bound_off) hmin
+// away: bound_off = 1/2 for a target at a cell centre, 0 for one anywhere in
+// its cell.  Returns the number of nodes seen.
 template <int D>
-__global__ void __launch_bounds__(64) k_grid_stencils(GridStencilArgs A) {
-  constexpr int MU = D == 2 ? 6 : 10;
-  const int64_t p = (int64_t)blockIdx.x * 64 + threadIdx.x;
-  if (p >= A.g.G) return;
-  const int k = A.k;
-  int ci[3] = {0, 0, 0};
-  {
-    int64_t r = p;
-#pragma unroll
-    for (int a = 0; a < D; ++a) {
-      ci[a] = (int)(r % A.g.n[a]);
-      r /= A.g.n[a];
-    }
-  }
-  double xt[3];
-#pragma unroll
-  for (int a = 0; a < D; ++a) xt[a] = ((double)ci[a] + 0.5) * A.g.h[a];
+__device__ __forceinline__ int knn_ring(const RingArgs& A, const double* xt, const int* ci, int k,
+                                        int exclude, double bound_off, double* ld, int* li) {
   double hmin = A.g.h[0];
 #pragma unroll
   for (int a = 1; a < D; ++a) hmin = fmin(hmin, A.g.h[a]);
-
-  // kept list in descending key order: L[0] is the worst kept
-  double ld[KMAX];
-  int li[KMAX];
 #pragma unroll
   for (int j = 0; j < KMAX; ++j) {
     ld[j] = INFINITY;
@@ -323,6 +304,7 @@ __global__ void __launch_bounds__(64) k_grid_stencils(GridStencilArgs A) {
           int s0 = A.start[c], s1 = A.start[c + 1];
           for (int s = s0; s < s1; ++s) {
             int nid = A.sorted[s];
+            if (nid == exclude) continue;
             double dx = axis_diff(A.xyz[nid], xt[0], A.g, 0);
             double dy = axis_diff(A.xyz[A.M + nid], xt[1], A.g, 1);
             double d2 = D == 2 ? sq_sum2(dx, dy)
@@ -347,17 +329,53 @@ __global__ void __launch_bounds__(64) k_grid_stencils(GridStencilArgs A) {
         }
       }
     }
-    // every unscanned node lies at least (R + 1/2) hmin away
-    double bound = (R + 0.5) * hmin;
+    // every unscanned node lies at least (R + bound_off) hmin away
+    double bound = (R + bound_off) * hmin;
     if (found >= k && ld[0] < bound * bound * (1.0 - 1e-12)) break;
   }
+  return found;
+}
+
+// ---- grid-target stencils ---------------------------------------------------
+struct GridStencilArgs {
+  RingArgs r;
+  int k;
+  double eps, hsup;       // hsup = support * delta
+  int32_t* gidx;          // [k][G]
+  double* gcoef;          // [d][k][G]
+  float* gcoef32;
+  int32_t* bad;           // singular flag
+};
+
+template <int D>
+__global__ void __launch_bounds__(64) k_grid_stencils(GridStencilArgs GA) {
+  constexpr int MU = D == 2 ? 6 : 10;
+  const RingArgs& A = GA.r;
+  const int64_t p = (int64_t)blockIdx.x * 64 + threadIdx.x;
+  if (p >= A.g.G) return;
+  const int k = GA.k;
+  int ci[3] = {0, 0, 0};
+  {
+    int64_t r = p;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      ci[a] = (int)(r % A.g.n[a]);
+      r /= A.g.n[a];
+    }
+  }
+  double xt[3];
+#pragma unroll
+  for (int a = 0; a < D; ++a) xt[a] = ((double)ci[a] + 0.5) * A.g.h[a];
+  double ld[KMAX];
+  int li[KMAX];
+  const int found = knn_ring<D>(A, xt, ci, k, -1, 0.5, ld, li);
   if (found < k) {
-    atomicOr(A.bad, 2);
+    atomicOr(GA.bad, 2);
     return;
   }
   // ---- WLS (Eqs. 13-17) ----
   const double rk = sqrt(ld[0]);
-  const double ht = fmax(A.hsup, rk);
+  const double ht = fmax(GA.hsup, rk);
   const double iht = 1.0 / ht;
   double Cm[MU * (MU + 1) / 2];
 #pragma unroll
@@ -369,7 +387,7 @@ __global__ void __launch_bounds__(64) k_grid_stencils(GridStencilArgs A) {
       double xi[3];
 #pragma unroll
       for (int a = 0; a < D; ++a) xi[a] = axis_diff(A.xyz[a * A.M + nid], xt[a], A.g, a) / ht;
-      double w = exp((-A.eps * ld[j]) / (ht * ht));
+      double w = exp((-GA.eps * ld[j]) / (ht * ht));
       double q[MU];
       basis<D>(xi, q);
 #pragma unroll
@@ -382,7 +400,7 @@ __global__ void __launch_bounds__(64) k_grid_stencils(GridStencilArgs A) {
   }
   double ratio = cholesky<MU>(Cm);
   if (!(ratio >= SINGULAR_RATIO)) {
-    atomicOr(A.bad, 1);
+    atomicOr(GA.bad, 1);
     return;
   }
   double y[D][MU];
@@ -403,18 +421,18 @@ __global__ void __launch_bounds__(64) k_grid_stencils(GridStencilArgs A) {
       double xi[3];
 #pragma unroll
       for (int a = 0; a < D; ++a) xi[a] = axis_diff(A.xyz[a * A.M + nid], xt[a], A.g, a) / ht;
-      double w = exp((-A.eps * ld[j]) / (ht * ht));
+      double w = exp((-GA.eps * ld[j]) / (ht * ht));
       double q[MU];
       basis<D>(xi, q);
-      A.gidx[(int64_t)pos * G + p] = nid;
+      GA.gidx[(int64_t)pos * G + p] = nid;
 #pragma unroll
       for (int a = 0; a < D; ++a) {
         double t = 0.0;
 #pragma unroll
         for (int r = 0; r < MU; ++r) t += y[a][r] * q[r];
         double cval = w * t * iht;
-        A.gcoef[((int64_t)a * k + pos) * G + p] = cval;
-        if (A.gcoef32) A.gcoef32[((int64_t)a * k + pos) * G + p] = (float)cval;
+        GA.gcoef[((int64_t)a * k + pos) * G + p] = cval;
+        if (GA.gcoef32) GA.gcoef32[((int64_t)a * k + pos) * G + p] = (float)cval;
       }
     }
   }
@@ -564,6 +582,127 @@ __global__ void __launch_bounds__(64) k_node_stencils(NodeStencilArgs A) {
   }
 }
 
+// ---- node-to-node stencils (the first fractional step) ------------------------------
+// Eq. 11 polynomial vector of the known-value form (2D: x, y, x^2/2, xy, y^2/2;
+// 3D: x, y, z, x^2/2, xy, xz, y^2/2, yz, z^2/2) of scaled offsets.
+template <int D>
+__device__ __forceinline__ void basis_known(const double* xi, double* q) {
+  if (D == 2) {
+    q[0] = xi[0]; q[1] = xi[1];
+    q[2] = 0.5 * xi[0] * xi[0]; q[3] = xi[0] * xi[1]; q[4] = 0.5 * xi[1] * xi[1];
+  } else {
+    q[0] = xi[0]; q[1] = xi[1]; q[2] = xi[2];
+    q[3] = 0.5 * xi[0] * xi[0]; q[4] = xi[0] * xi[1]; q[5] = xi[0] * xi[2];
+    q[6] = 0.5 * xi[1] * xi[1]; q[7] = xi[1] * xi[2]; q[8] = 0.5 * xi[2] * xi[2];
+  }
+}
+
+struct SelfStencilArgs {
+  RingArgs r;
+  int k;
+  double eps, hsup;
+  int64_t ms;       // stream stride
+  int32_t* sidx;    // [k][ms] neighbour node, ascending
+  double* scoef;    // [d+1][k][ms]: d first-derivative rows, then the Laplacian row
+  float* scoef32;
+  int32_t* bad;
+};
+
+// Every node's k nearest other nodes and the known-value WLS rows of
+// Eqs. 13-15 (data f(x_i) - f(x)): first derivatives and the Laplacian
+// (the sum of the pure second-derivative rows), in float64.
+template <int D>
+__global__ void __launch_bounds__(64) k_self_stencils(SelfStencilArgs SA) {
+  constexpr int MU = D == 2 ? 5 : 9;
+  const RingArgs& A = SA.r;
+  const int64_t n = (int64_t)blockIdx.x * 64 + threadIdx.x;
+  if (n >= A.M) return;
+  const int k = SA.k;
+  double xt[3];
+  int ci[3] = {0, 0, 0};
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    xt[a] = A.xyz[a * A.M + n];
+    const double t = floor(xt[a] / A.g.h[a]);
+    ci[a] = (int)fmin(fmax(t, 0.0), (double)(A.g.n[a] - 1));
+  }
+  double ld[KMAX];
+  int li[KMAX];
+  const int found = knn_ring<D>(A, xt, ci, k, (int)n, 0.0, ld, li);
+  if (found < k) {
+    atomicOr(SA.bad, 2);
+    return;
+  }
+  const double ht = fmax(SA.hsup, sqrt(ld[0]));
+  const double iht = 1.0 / ht;
+  double Cm[MU * (MU + 1) / 2];
+#pragma unroll
+  for (int j = 0; j < MU * (MU + 1) / 2; ++j) Cm[j] = 0.0;
+#pragma unroll
+  for (int j = 0; j < KMAX; ++j) {
+    if (j < k) {
+      const int nid = li[j];
+      double xi[3];
+#pragma unroll
+      for (int a = 0; a < D; ++a) xi[a] = axis_diff(A.xyz[a * A.M + nid], xt[a], A.g, a) / ht;
+      const double w = exp((-SA.eps * ld[j]) / (ht * ht));
+      double q[MU];
+      basis_known<D>(xi, q);
+#pragma unroll
+      for (int r = 0; r < MU; ++r) {
+        const double wq = w * q[r];
+#pragma unroll
+        for (int c = 0; c <= r; ++c) Cm[tri(r, c)] += wq * q[c];
+      }
+    }
+  }
+  if (!(cholesky<MU>(Cm) >= SINGULAR_RATIO)) {
+    atomicOr(SA.bad, 1);
+    return;
+  }
+  // rows of C^-1: the first derivatives (unknowns 0..D-1) and the sum of the
+  // pure second derivatives (2D: unknowns 2, 4; 3D: 3, 6, 8)
+  double y[D + 1][MU];
+#pragma unroll
+  for (int a = 0; a < D; ++a) chol_unit_solve<MU>(Cm, a, y[a]);
+  {
+    double t0[MU], t1[MU], t2[MU];
+    chol_unit_solve<MU>(Cm, D == 2 ? 2 : 3, t0);
+    chol_unit_solve<MU>(Cm, D == 2 ? 4 : 6, t1);
+    if (D == 3) chol_unit_solve<MU>(Cm, 8, t2);
+#pragma unroll
+    for (int r = 0; r < MU; ++r) y[D][r] = D == 2 ? t0[r] + t1[r] : (t0[r] + t1[r]) + t2[r];
+  }
+  const int64_t ms = SA.ms;
+#pragma unroll
+  for (int j = 0; j < KMAX; ++j) {
+    if (j < k) {
+      const int nid = li[j];
+      int pos = 0;  // ascending node index (near-contiguous gathers)
+#pragma unroll
+      for (int jj = 0; jj < KMAX; ++jj)
+        if (jj < k && li[jj] < nid) ++pos;
+      double xi[3];
+#pragma unroll
+      for (int a = 0; a < D; ++a) xi[a] = axis_diff(A.xyz[a * A.M + nid], xt[a], A.g, a) / ht;
+      const double w = exp((-SA.eps * ld[j]) / (ht * ht));
+      double q[MU];
+      basis_known<D>(xi, q);
+      SA.sidx[(int64_t)pos * ms + n] = nid;
+#pragma unroll
+      for (int a = 0; a <= D; ++a) {
+        double t = 0.0;
+#pragma unroll
+        for (int r = 0; r < MU; ++r) t += y[a][r] * q[r];
+        // first derivatives scale by 1/h_t, the Laplacian by 1/h_t^2
+        const double cval = a < D ? w * t * iht : w * t * (iht * iht);
+        SA.scoef[((int64_t)a * k + pos) * ms + n] = cval;
+        if (SA.scoef32) SA.scoef32[((int64_t)a * k + pos) * ms + n] = (float)cval;
+      }
+    }
+  }
+}
+
 // ---- IB lists ------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_near_flags(const int32_t* __restrict__ gidx, int64_t G,
                                                     int k, const uint8_t* __restrict__ kind,
@@ -650,9 +789,9 @@ unsigned nblocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 void geom_free(pc_geom* g) {
   if (!g) return;
-  void* ptrs[] = {g->gidx, g->gcoef, g->gcoef32, g->nbase, g->ncoef, g->ncoef32, g->ib,
-                  g->near, g->nslot, g->ncoefib, g->ncoefib32, g->ibbase, g->ibcoef,
-                  g->ibcoef32};
+  void* ptrs[] = {g->gidx,   g->gcoef,  g->gcoef32, g->nbase,  g->ncoef,  g->ncoef32,
+                  g->ib,     g->near,   g->nslot,   g->ncoefib, g->ncoefib32, g->ibbase,
+                  g->ibcoef, g->ibcoef32, g->sidx,  g->scoef,   g->scoef32,  g->vlist};
   for (void* p : ptrs) dev_free(p);
 }
 
@@ -678,6 +817,10 @@ int build(const pc_plan* P, const double* xyz, const uint8_t* kind, int64_t M,
   double support = o && o->support != 0.0 ? o->support : 3.0;
   double delta = o ? o->delta : 0.0;
   bool want32 = o && (o->dtype_mask & 1);
+  const int k_self = o ? o->k_self : 0;
+  if (k_self != 0 && (k_self < (d == 2 ? 5 : 9) || k_self > KMAX))
+    return fail(PC_ERR_INVALID_ARG, "k_self must be 0 or in [5 (2D) / 9 (3D), PC_MAX_K_GRID]");
+  if (k_self >= M) return fail(PC_ERR_INVALID_ARG, "k_self must be below the number of nodes");
   if (k_grid < MU || k_node < MU)
     return fail(PC_ERR_INVALID_ARG, "k_grid and k_node must be at least the number of unknowns");
   if (k_grid > KMAX) return fail(PC_ERR_UNSUPPORTED_SIZE, "k_grid above PC_MAX_K_GRID");
@@ -759,8 +902,8 @@ int build(const pc_plan* P, const double* xyz, const uint8_t* kind, int64_t M,
   PC_TRY(dev_alloc((void**)&g->gcoef, (size_t)d * k_grid * G * 8, "grid stencil coefficients"));
   if (want32)
     PC_TRY(dev_alloc((void**)&g->gcoef32, (size_t)d * k_grid * G * 4, "grid stencil f32"));
-  GridStencilArgs ga{xyz, M, gd, start, sorted, k_grid, eps, support * delta, g->gidx, g->gcoef,
-                     g->gcoef32, bad};
+  const RingArgs ring{xyz, M, gd, start, sorted};
+  GridStencilArgs ga{ring, k_grid, eps, support * delta, g->gidx, g->gcoef, g->gcoef32, bad};
   if (d == 2)
     hipLaunchKernelGGL(k_grid_stencils<2>, dim3(nblocks(G, 64)), dim3(64), 0, s, ga);
   else
@@ -781,6 +924,23 @@ int build(const pc_plan* P, const double* xyz, const uint8_t* kind, int64_t M,
     hipLaunchKernelGGL(k_node_stencils<3>, dim3(nblocks(M, 64)), dim3(64), 0, s, na);
   PC_HIP_CHECK(hipGetLastError());
 
+  // node-to-node stencils (the first fractional step)
+  g->k_self = k_self;
+  if (k_self) {
+    PC_TRY(dev_alloc((void**)&g->sidx, (size_t)k_self * g->ms * 4, "node-node indices"));
+    PC_TRY(dev_alloc((void**)&g->scoef, (size_t)(d + 1) * k_self * g->ms * 8, "node-node coefs"));
+    if (want32)
+      PC_TRY(dev_alloc((void**)&g->scoef32, (size_t)(d + 1) * k_self * g->ms * 4,
+                       "node-node coefs f32"));
+    SelfStencilArgs sa{ring, k_self, eps, support * delta, g->ms, g->sidx, g->scoef, g->scoef32,
+                       bad};
+    if (d == 2)
+      hipLaunchKernelGGL(k_self_stencils<2>, dim3(nblocks(M, 64)), dim3(64), 0, s, sa);
+    else
+      hipLaunchKernelGGL(k_self_stencils<3>, dim3(nblocks(M, 64)), dim3(64), 0, s, sa);
+    PC_HIP_CHECK(hipGetLastError());
+  }
+
   int32_t hbad = 0;
   PC_HIP_CHECK(hipMemcpyAsync(&hbad, bad, 4, hipMemcpyDeviceToHost, s));
   PC_HIP_CHECK(hipStreamSynchronize(s));
@@ -794,12 +954,18 @@ int build(const pc_plan* P, const double* xyz, const uint8_t* kind, int64_t M,
   // boundary + virtual node list (ascending)
   std::vector<uint8_t> hkind((size_t)M);
   PC_HIP_CHECK(hipMemcpy(hkind.data(), kind, (size_t)M, hipMemcpyDeviceToHost));
-  std::vector<int32_t> hib;
+  std::vector<int32_t> hib, hv;
   for (int64_t n = 0; n < M; ++n) {
     if (hkind[n] > PC_KIND_V) return fail(PC_ERR_INVALID_ARG, "node kind must be 0, 1 or 2");
     if (hkind[n] != PC_KIND_F) hib.push_back((int32_t)n);
+    if (hkind[n] == PC_KIND_V) hv.push_back((int32_t)n);
   }
   g->n_ib = (int64_t)hib.size();
+  g->n_v = (int64_t)hv.size();
+  if (g->n_v) {
+    PC_TRY(dev_alloc((void**)&g->vlist, (size_t)g->n_v * 4, "virtual list"));
+    PC_HIP_CHECK(hipMemcpy(g->vlist, hv.data(), (size_t)g->n_v * 4, hipMemcpyHostToDevice));
+  }
   // near-IB grid points and their compact stencils
   uint8_t* nflag;
   PC_TRY(tmp.alloc((void**)&nflag, (size_t)G, "near flags"));
@@ -872,6 +1038,8 @@ int build(const pc_plan* P, const double* xyz, const uint8_t* kind, int64_t M,
   if (want32)
     bytes += (int64_t)d * k_grid * G * 4 + (int64_t)d * bn * g->ms * 4 + ell * 4 * d +
              g->ibs * 4 * (int64_t)d * bn;
+  bytes += (int64_t)k_self * g->ms * (4 + 8 * (d + 1)) + g->n_v * 4;
+  if (want32) bytes += (int64_t)k_self * g->ms * 4 * (d + 1);
   g->bytes = bytes;
   return PC_OK;
 }
@@ -926,6 +1094,21 @@ int pc_geom_info(const pc_geom* g, int64_t* c) {
   c[3] = g->k_grid;
   c[4] = g->bn;
   c[5] = g->bytes;
+  return PC_OK;
+}
+
+int pc_geom_export_self(const pc_geom* g, int32_t* idx, double* coef, void* stream) {
+  if (!g) return fail(PC_ERR_INVALID_ARG, "pc_geom_export_self: null geometry");
+  if (!g->k_self) return fail(PC_ERR_INVALID_ARG, "the geometry has no node-to-node stencils");
+  hipStream_t s = as_stream(stream);
+  if (idx)
+    PC_HIP_CHECK(hipMemcpy2DAsync(idx, (size_t)g->M * 4, g->sidx, (size_t)g->ms * 4,
+                                  (size_t)g->M * 4, (size_t)g->k_self, hipMemcpyDeviceToDevice,
+                                  s));
+  if (coef)
+    PC_HIP_CHECK(hipMemcpy2DAsync(coef, (size_t)g->M * 8, g->scoef, (size_t)g->ms * 8,
+                                  (size_t)g->M * 8, (size_t)(g->d + 1) * g->k_self,
+                                  hipMemcpyDeviceToDevice, s));
   return PC_OK;
 }
 

@@ -43,7 +43,7 @@ EXPORTS = [
     "pc_poisson_fft_solve", "pc_wls_build", "pc_geom_destroy", "pc_geom_info",
     "pc_geom_export", "pc_div_to_grid", "pc_grad_to_nodes", "pc_ib_update", "pc_project",
     "pc_workspace_create", "pc_workspace_destroy", "pc_workspace_bytes",
-    "pc_pressure_correct",
+    "pc_pressure_correct", "pc_geom_export_self", "pc_momentum_predict", "pc_momentum_pressure",
 ]
 
 
@@ -57,7 +57,7 @@ class WlsOpts(ctypes.Structure):
     _fields_ = [("k_grid", ctypes.c_int32), ("k_node", ctypes.c_int32),
                 ("eps", ctypes.c_double), ("support", ctypes.c_double),
                 ("delta", ctypes.c_double), ("dtype_mask", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("k_self", ctypes.c_int32)]
 
 
 PC_IB_FULL_TRANSFORMS = 1
@@ -107,6 +107,10 @@ def _load():
         "pc_pressure_correct": ([vp, vp, ctypes.c_int, vp, dbl, vp, vp, vp,
                                  ctypes.POINTER(IbOpts), ctypes.POINTER(Stats), vp, vp],
                                 ctypes.c_int),
+        "pc_geom_export_self": ([vp, vp, vp, vp], ctypes.c_int),
+        "pc_momentum_predict": ([vp, ctypes.c_int, vp, vp, dbl, dbl, vp, vp, vp, vp],
+                                ctypes.c_int),
+        "pc_momentum_pressure": ([vp, ctypes.c_int, vp, vp, vp, vp, dbl, vp, vp], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         if hasattr(lib, name):
@@ -255,9 +259,9 @@ def poisson_fft_solve(plan: Plan, b: torch.Tensor, phi: torch.Tensor, mode: int 
 
 def wls_build(plan: Plan, xyz: torch.Tensor, kind: torch.Tensor, k_grid: int = 0,
               k_node: int = 0, eps: float = 0.0, support: float = 0.0, delta: float = 0.0,
-              want_f32: bool = False, stream=None) -> Geometry:
+              want_f32: bool = False, stream=None, k_self: int = 0) -> Geometry:
     assert xyz.dtype == torch.float64 and kind.dtype == torch.uint8
-    opts = WlsOpts(k_grid, k_node, eps, support, delta, 1 if want_f32 else 0, 0)
+    opts = WlsOpts(k_grid, k_node, eps, support, delta, 1 if want_f32 else 0, k_self)
     out = ctypes.c_void_p()
     _check(_lib.pc_wls_build(plan.h_, _ptr(xyz), _ptr(kind), kind.numel(), ctypes.byref(opts),
                              _stream(stream), ctypes.byref(out)))
@@ -308,3 +312,28 @@ def pressure_correct(geom: Geometry, plan: Plan, mode: int, u: torch.Tensor, dt:
                                          ctypes.byref(st) if want_stats else None,
                                          ws.h_ if ws else None, _stream(stream)))
     return rc, st.as_dict()
+
+
+def geom_export_self(geom: Geometry, idx=None, coef=None, stream=None) -> int:
+    return _check(_lib.pc_geom_export_self(geom.h_, _ptr(idx), _ptr(coef), _stream(stream)))
+
+
+def momentum_predict(geom: Geometry, u: torch.Tensor, r_prev: Optional[torch.Tensor], dt: float,
+                     nu: float, r: torch.Tensor, ustar: torch.Tensor, force=None,
+                     stream=None) -> int:
+    """The first fractional step (Eq. 3): r <- R^n, ustar <- u*."""
+    f = None
+    if force is not None:
+        f = (ctypes.c_double * 3)(*(list(force) + [0.0] * (3 - len(force))))
+    return _check(_lib.pc_momentum_predict(geom.h_, _dtype_code(u), _ptr(u), _ptr(r_prev), dt, nu,
+                                           ctypes.addressof(f) if f is not None else None,
+                                           _ptr(r), _ptr(ustar), _stream(stream)))
+
+
+def momentum_pressure(geom: Geometry, r: torch.Tensor, ustar: torch.Tensor, unew: torch.Tensor,
+                      g_ib: Optional[torch.Tensor], dt: float, r_prev: torch.Tensor,
+                      stream=None) -> int:
+    """r_prev <- R^n - grad p^n for the next step."""
+    return _check(_lib.pc_momentum_pressure(geom.h_, _dtype_code(r), _ptr(r), _ptr(ustar),
+                                            _ptr(unew), _ptr(g_ib), dt, _ptr(r_prev),
+                                            _stream(stream)))

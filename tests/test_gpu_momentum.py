@@ -1,0 +1,158 @@
+"""The first fractional step (Eq. 3) and whole time steps on the GPU against
+the float64 oracle: node-to-node stencils (index sets exact, coefficients
+1e-12), R^n and u* (1e-11), R^{n-1} with the pressure gradient, five
+complete time steps with an immersed cylinder (1e-10 in float64, n_it per
+step equal; float32 within 1e-4), and the Taylor-Green vortex on the
+periodic box against its exact decay."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import momentum as OM, projection as P
+from paper_2304_14690_amd import inputs
+from tests.helpers import rel_l2, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pc():
+    from paper_2304_14690_amd import pcorr
+    return pcorr
+
+
+def _cylinder():
+    c = inputs.make_case("mom2", 2, 64, [inputs.Obstacle("circle", (0.45, 0.5), (0.12,))],
+                         16, 16, 8, 71, 72)
+    return c, None, 16
+
+
+def _sphere():
+    c = inputs.make_case("mom3", 3, 16, [inputs.Obstacle("sphere", (0.5, 0.5, 0.5), (0.25,))],
+                         27, 27, 8, 73, 74)
+    return c, None, 20
+
+
+def _periodic():
+    bc = ("periodic", "neumann")
+    c = inputs.make_case("mom2p", 2, 64, [inputs.Obstacle("circle", (0.02, 0.5), (0.12,))],
+                         16, 16, 8, 75, 76, bc=bc)
+    return c, bc, 12
+
+
+CASES = {"2d_cylinder": _cylinder, "3d_sphere": _sphere, "2d_periodic_x": _periodic}
+
+
+def _setup(pc, name, want_f32=False):
+    import torch
+    c, bc, ks = CASES[name]()
+    grid = oracle.Grid(c.d, c.n, c.h, bc)
+    L = None if bc is None else tuple(grid.length[a] if grid.periodic(a) else None
+                                      for a in range(c.d))
+    x = c.x.T.copy()
+    plan = pc.Plan(c.d, c.n, c.h, bc=bc)
+    geom = pc.wls_build(plan, torch.from_numpy(c.x).cuda(), torch.from_numpy(c.kind).cuda(),
+                        c.k_grid, c.k_node, want_f32=want_f32, k_self=ks)
+    return c, grid, L, x, ks, plan, geom
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_self_stencils_and_predict(pc, name):
+    import torch
+    c, grid, L, x, ks, plan, geom = _setup(pc, name)
+    sidx, scoef, sing = OM.self_stencils(x, ks, oracle.wls.default_delta(c.h), lengths=L)
+    assert not sing.any()
+    gi = torch.empty((ks, c.M), dtype=torch.int32, device="cuda")
+    gc = torch.empty((c.d + 1, ks, c.M), dtype=torch.float64, device="cuda")
+    pc.geom_export_self(geom, gi, gc)
+    torch.cuda.synchronize()
+    order = np.argsort(sidx, axis=1, kind="stable")
+    np.testing.assert_array_equal(to_np(gi).T, np.take_along_axis(sidx, order, 1))
+    ocoef = np.take_along_axis(scoef, order[:, None, :], 2)
+    e_c = rel_l2(np.transpose(to_np(gc), (2, 0, 1)), ocoef)
+    # R^n and u* (first step and an AB2 step)
+    rng = np.random.Generator(np.random.PCG64(3))
+    u = c.u.T.copy()
+    rp = rng.normal(size=u.shape)
+    nu, dt, F = 0.02, 0.01, [0.3, -0.1, 0.2][:c.d]
+    R = OM.momentum_rhs(sidx, scoef, u, nu, F)
+    ut = torch.from_numpy(c.u).cuda()
+    r = torch.empty_like(ut)
+    us = torch.empty_like(ut)
+    errs = []
+    for first in (True, False):
+        rpt = None if first else torch.from_numpy(rp.T.copy()).cuda()
+        pc.momentum_predict(geom, ut, rpt, dt, nu, r, us, force=F)
+        torch.cuda.synchronize()
+        want = OM.predict(u, R, None if first else rp, dt, c.kind)
+        errs.append((rel_l2(to_np(r).T, R), rel_l2(to_np(us).T, want)))
+        assert np.all(to_np(us)[:, c.kind == inputs.KIND_V] == 0.0)
+    # R_prev with the pressure gradient
+    un = rng.normal(size=u.shape)
+    gib = rng.normal(size=(int(np.count_nonzero(c.kind != inputs.KIND_F)), c.d))
+    g_full = np.zeros_like(u)
+    g_full[c.kind != inputs.KIND_F] = gib
+    want_rp = OM.r_prev_next(R, to_np(us).T, un, g_full, dt)
+    out = torch.empty_like(ut)
+    pc.momentum_pressure(geom, r, us, torch.from_numpy(un.T.copy()).cuda(),
+                         torch.from_numpy(gib.T.copy()).cuda(), dt, out)
+    torch.cuda.synchronize()
+    e_rp = rel_l2(to_np(out).T, want_rp)
+    print(f"{name}: coef {e_c:.2e}, (R, u*) {errs}, R_prev {e_rp:.2e}")
+    assert e_c <= 1e-12 and e_rp <= 1e-12
+    for a, b in errs:
+        assert a <= 1e-11 and b <= 1e-11
+
+
+@pytest.mark.parametrize("name", ["2d_cylinder", "2d_periodic_x", "3d_sphere"])
+def test_time_steps_match_oracle(pc, name):
+    import torch
+    from paper_2304_14690_amd.timeloop import TimeStepper
+    c, grid, L, x, ks, plan, geom = _setup(pc, name, want_f32=True)
+    st = P.build_stencils(grid, x, c.kind, c.k_grid, c.k_node)
+    sidx, scoef, _ = OM.self_stencils(x, ks, oracle.wls.default_delta(c.h), lengths=L)
+    dt, nu, steps = 0.002, 0.01, 5
+    u0 = c.u.T.copy()
+    ref, _ = OM.advance(st, sidx, scoef, c.kind, u0, dt, nu, steps)
+    res = {}
+    for mode, dtype in ((pc.PC_F64, torch.float64), (pc.PC_F32, torch.float32)):
+        ts = TimeStepper(plan, geom, mode, dt, nu)
+        u = torch.from_numpy(c.u).to(dtype).cuda()
+        u2 = torch.empty_like(u)
+        for _ in range(steps):
+            ts.step(u, u2)
+            u, u2 = u2, u
+        torch.cuda.synchronize()
+        res[mode] = rel_l2(to_np(u).T, ref)
+    print(f"{name}: after {steps} steps f64 {res[pc.PC_F64]:.2e} f32 {res[pc.PC_F32]:.2e}")
+    assert res[pc.PC_F64] <= 1e-10 and res[pc.PC_F32] <= 1e-4
+
+
+def test_taylor_green_on_gpu(pc):
+    """Both fractional steps keep the Taylor-Green vortex (an exact solution
+    on the periodic box) to second order: 64^2 nodes and grid, 50 steps."""
+    import torch
+    from paper_2304_14690_amd.timeloop import TimeStepper
+    n, h = (64, 64), (1 / 64, 1 / 64)
+    x = inputs.jittered_lattice(n, h, 81)
+    kind = np.zeros(x.shape[1], np.uint8)
+    plan = pc.Plan(2, n, h, bc=("periodic", "periodic"))
+    geom = pc.wls_build(plan, torch.from_numpy(x).cuda(), torch.from_numpy(kind).cuda(), 16, 16,
+                        k_self=16)
+
+    def tg(t, nu):
+        a = np.exp(-8 * np.pi ** 2 * nu * t)
+        return a * np.stack([np.sin(2 * np.pi * x[0]) * np.cos(2 * np.pi * x[1]),
+                             -np.cos(2 * np.pi * x[0]) * np.sin(2 * np.pi * x[1])])
+    nu, dt, steps = 0.01, 0.002, 50
+    ts = TimeStepper(plan, geom, pc.PC_F64, dt, nu)
+    u = torch.from_numpy(tg(0.0, nu)).cuda()
+    u2 = torch.empty_like(u)
+    for _ in range(steps):
+        ts.step(u, u2)
+        u, u2 = u2, u
+    torch.cuda.synchronize()
+    exact = tg(dt * steps, nu)
+    err = rel_l2(to_np(u), exact)
+    print(f"Taylor-Green: rel err {err:.2e} after {steps} steps")
+    assert err < 5e-3
