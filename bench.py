@@ -18,6 +18,10 @@ Workloads (all inputs seeded and synthetic, resident in HBM before timing):
   2d2048p 2d2048 with a periodic x axis (a channel: periodic lateral faces,
           as in the paper's verification cases, Sec. 3) and Neumann walls in y.
   3d256p  3d256 with periodic x and z axes and Neumann walls in y.
+  2d2048pp, 3d256pp  the same, periodic along every axis; these also time
+          whole time steps (the first fractional step of Eq. 3 + the sub-step):
+          the first step needs velocity conditions on non-periodic faces,
+          which are the caller's, so whole steps are timed without faces.
   2d1024c the 2d2048 node cloud (the same 4.2M nodes and cylinder) under a
           1024^2 pressure grid: a pressure grid coarser than the velocity
           cloud, the saving Sec. 3 reports (WLS mean spacing = node spacing).
@@ -63,6 +67,14 @@ WORKLOADS = {
                "desc": "3D 256^3 grid, {M} jittered nodes, sphere r=0.1 at the centre, 27-NN "
                        "WLS, 64-mode velocity, periodic in x and z, Neumann walls in y, "
                        "cold IB start"},
+    "2d2048pp": {"d": 2, "N": 2048, "modes": "f64,f32,mixed", "cpu_N": 1024,
+                 "bc": ("periodic", "periodic"),
+                 "desc": "2D 2048^2 grid, {M} jittered nodes, cylinder r=0.05 at (0.3,0.5), "
+                         "16-NN WLS, 32-mode velocity, periodic box, cold IB start"},
+    "3d256pp": {"d": 3, "N": 256, "modes": "f64,f32,mixed", "cpu_N": 64,
+                "bc": ("periodic", "periodic", "periodic"),
+                "desc": "3D 256^3 grid, {M} jittered nodes, sphere r=0.1 at the centre, 27-NN "
+                        "WLS, 64-mode velocity, periodic box, cold IB start"},
     "2d1024c": {"d": 2, "N": 1024, "modes": "f64,f32,mixed", "cpu_N": 512, "nodes_per_axis": 2,
                 "desc": "2D 1024^2 pressure grid under the 2048^2 workload's {M} jittered "
                         "nodes (node spacing 1/2048), cylinder r=0.05 at (0.3,0.5), 16-NN WLS, "
@@ -93,6 +105,9 @@ def parse():
     ap.add_argument("--serve-geoms", type=int, default=2,
                     help="geometries per grid size in the serving pool")
     ap.add_argument("--serve-only", action="store_true")
+    ap.add_argument("--time-steps", type=int, default=20,
+                    help="on a periodic-box workload, also time whole time steps (first "
+                         "fractional step + sub-step); 0: off")
     return ap.parse_args()
 
 
@@ -120,6 +135,12 @@ def bytes_grad_project(G, M, bn, d, s):
     return M * (bn * d * s + 4 + 2 * d * s) + G * s
 
 
+def bytes_momentum(M, k, d, s):
+    """node-to-node stencil streams (index + d derivative rows + Laplacian
+    row per entry), u read once, R_prev read, R and u* written."""
+    return M * (k * (4 + (d + 1) * s) + 4 * d * s)
+
+
 def make_workload(name, N):
     """Seeded inputs of a workload: (Case-like dict) with x, kind on the host
     and u on the device (2D: numpy velocity; 3D: the same modes evaluated
@@ -133,12 +154,12 @@ def make_workload(name, N):
                                     16, 16, 32, 3, 4)
         return {"d": 2, "n": c.n, "h": c.h, "x": c.x, "kind": c.kind, "k": c.k_grid,
                 "u": torch.from_numpy(c.u).cuda(), "bc": None, "delta": 1.0 / (2 * N)}
-    if name in ("2d2048", "2d2048p"):
+    if name in ("2d2048", "2d2048p", "2d2048pp"):
         c = inputs.make_case(name, 2, N, [inputs.Obstacle("circle", (0.3, 0.5), (0.05,))],
                              16, 16, 32, 3, 4, bc=bc)
         return {"d": 2, "n": c.n, "h": c.h, "x": c.x, "kind": c.kind, "k": c.k_grid,
                 "u": torch.from_numpy(c.u).cuda(), "bc": bc}
-    if name in ("3d256", "3d256p"):
+    if name in ("3d256", "3d256p", "3d256pp"):
         obs, sn, sv = [inputs.Obstacle("sphere", (0.5, 0.5, 0.5), (0.1,))], 5, 6
     else:
         obs, sn, sv = [inputs.Obstacle("sphere", (0.3, 0.5, 0.5), (0.1,)),
@@ -191,8 +212,13 @@ def main():
     want_f32 = "f32" in modes
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    # whole time steps only on a box without faces (the first fractional step
+    # has no velocity condition of its own on them)
+    if not (case["bc"] and all(b == "periodic" for b in case["bc"])):
+        args.time_steps = 0
+    k_self = (16 if d == 2 else 20) if args.time_steps > 0 else 0
     geom = pc.wls_build(plan, x, kind, case["k"], case["k"], want_f32=want_f32,
-                        delta=case.get("delta", 0.0))
+                        delta=case.get("delta", 0.0), k_self=k_self)
     torch.cuda.synchronize()
     t_build = time.perf_counter() - t0
     del x, kind
@@ -292,6 +318,44 @@ def main():
             "kernel": kern[dom]["kernel"], "call": dom, "bytes_per_launch": kern[dom]["bytes"],
             "avg_launch_us": round(kern[dom]["us"], 2)}
 
+    # ---- whole time steps: the first fractional step (Eq. 3) + the sub-step --------
+    timestep = None
+    if args.time_steps > 0:
+        from paper_2304_14690_amd.timeloop import TimeStepper
+        # dt at a convective CFL number of 0.1 for the largest speed of the
+        # random-mode field
+        dt_ts = 0.1 * min(case["h"]) / float(case["u"].abs().max())
+        nu_ts = 1e-3
+        u = case["u"].clone()
+        u2 = torch.empty_like(u)
+        ts = TimeStepper(plan, geom, pc.PC_F64, dt_ts, nu_ts)
+        for _ in range(3):
+            ts.step(u, u2)
+            u, u2 = u2, u
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        n_its = []
+        for _ in range(args.time_steps):
+            st = ts.step(u, u2)
+            n_its.append(st["n_it"])
+            u, u2 = u2, u
+        torch.cuda.synchronize()
+        t_step = (time.perf_counter() - t0) / args.time_steps
+        r = torch.empty_like(u)
+        us = torch.empty_like(u)
+        t_mom = time_launches(lambda: pc.momentum_predict(geom, u, ts.r_prev, dt_ts, nu_ts, r, us),
+                              reps)
+        bm = bytes_momentum(M, k_self, d, 8)
+        timestep = {"ms_per_time_step": round(1e3 * t_step, 4), "steps": args.time_steps,
+                    "dt": dt_ts, "nu": nu_ts, "k_self": k_self,
+                    "n_it_per_step": [min(n_its), max(n_its)],
+                    "momentum_predict": {"kernel": f"k_momentum<double,{d},{k_self}>",
+                                         "us": round(t_mom * 1e6, 2), "bytes": bm,
+                                         "GBs": round(bm / t_mom / 1e9, 1),
+                                         "frac": round(bm / t_mom / 1e9 / HBM_PEAK_GBS, 4)}}
+        del ts, u, u2, r, us
+        torch.cuda.synchronize()
+
     if args.copy_probe:
         src = torch.empty(1 << 27, dtype=torch.float64, device="cuda")  # 1 GiB
         dst = torch.empty_like(src)
@@ -336,6 +400,7 @@ def main():
                         for kk, vv in v.items()} for n, v in kern.items()},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "time_step": timestep,
         "serving": serving_out,
         "device": torch.cuda.get_device_name(dev),
     }
@@ -460,10 +525,10 @@ def cpu_baseline(workload, N):
                                     [inputs.Obstacle("circle", (0.3, 0.5), (0.05,))],
                                     16, 16, 32, 3, 4)
         delta = 1.0 / (2 * N)
-    elif workload in ("2d2048", "2d2048p"):
+    elif workload in ("2d2048", "2d2048p", "2d2048pp"):
         c = inputs.make_case(workload, 2, N, [inputs.Obstacle("circle", (0.3, 0.5), (0.05,))],
                              16, 16, 32, 3, 4, bc=bc)
-    elif workload in ("3d256", "3d256p"):
+    elif workload in ("3d256", "3d256p", "3d256pp"):
         c = inputs.make_case(workload, 3, N, [inputs.Obstacle("sphere", (0.5, 0.5, 0.5), (0.1,))],
                              27, 27, 64, 5, 6, bc=bc)
     else:
