@@ -22,13 +22,28 @@ class Grid:
     # the reported timings, Sec. 3.2) or "spectral" (pseudo-spectral, one of
     # the variants Sec. 3 reports as giving no noticeable difference)
     eig: str = "fd2"
+    # grid points at the cell centres (i + 1/2) h (the staggered grid of the
+    # paper's timings) or at the vertices i h of n - 1 intervals (the regular
+    # grid, a variant Sec. 3 reports as interchangeable; Neumann axes only)
+    vertex: bool = False
+
+    def __post_init__(self):
+        if self.vertex and any(self.periodic(a) for a in range(self.d)):
+            raise ValueError("a vertex grid has Neumann axes only")
 
     def periodic(self, a: int) -> bool:
         return self.bc is not None and self.bc[a] == "periodic"
 
     @property
+    def offset(self) -> float:
+        """Position of grid point 0 in units of h."""
+        return 0.0 if self.vertex else 0.5
+
+    @property
     def length(self) -> Tuple[float, ...]:
-        return tuple(self.n[a] * self.h[a] for a in range(self.d))
+        """Box length per axis: n h (cells), (n - 1) h (vertices)."""
+        m = 1 if self.vertex else 0
+        return tuple((self.n[a] - m) * self.h[a] for a in range(self.d))
 
     @property
     def G(self) -> int:
@@ -44,7 +59,7 @@ class Grid:
         idx = np.indices(self.shape_zyx)
         out = np.empty((self.G, self.d), dtype=np.float64)
         for a in range(self.d):
-            out[:, a] = (idx[self.d - 1 - a].reshape(-1) + 0.5) * self.h[a]
+            out[:, a] = (idx[self.d - 1 - a].reshape(-1) + self.offset) * self.h[a]
         return out
 
     def to_array(self, flat: np.ndarray) -> np.ndarray:

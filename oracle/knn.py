@@ -157,16 +157,18 @@ def window_m(k: int, d: int) -> int:
     return m
 
 
-def node_window_base(x: np.ndarray, n, h, m: int, periodic=None) -> np.ndarray:
+def node_window_base(x: np.ndarray, n, h, m: int, periodic=None,
+                     offset: float = 0.5) -> np.ndarray:
     """Lowest grid line of the m lines nearest to each node along each axis,
     clamped so the block lies inside the box (not along a periodic axis,
     where the block may run past a face and wraps around).  Grid line i sits
-    at (i + 1/2) h, so the m nearest lines start at floor(x/h - m/2 + 1/2).
+    at (i + offset) h (offset 1/2 on the cell-centred grid, 0 on the vertex
+    grid), so the m nearest lines start at floor(x/h - offset - m/2 + 1).
     x [T, d] -> [T, d] int64 (unwrapped: -1 or above n - m on a periodic
     axis)."""
     out = np.empty(x.shape, dtype=np.int64)
     for a in range(x.shape[1]):
-        lo = np.floor(x[:, a] / h[a] - (0.5 * m - 0.5)).astype(np.int64)
+        lo = np.floor(x[:, a] / h[a] - (0.5 * m - 1.0 + offset)).astype(np.int64)
         out[:, a] = lo if (periodic is not None and periodic[a]) else np.clip(lo, 0, n[a] - m)
     return out
 
@@ -189,7 +191,7 @@ def knn_grid_window(x: np.ndarray, grid, k: int):
     if any(v < m for v in grid.n):
         raise ValueError("grid smaller than the stencil block")
     per = [grid.periodic(a) for a in range(d)]
-    base = node_window_base(x, grid.n, grid.h, m, per)
+    base = node_window_base(x, grid.n, grid.h, m, per, grid.offset)
     offs = np.indices((m,) * d).reshape(d, -1)[::-1].T      # [m^d, d], x fastest
     cell = base[:, None, :] + offs[None, :, :]              # [T, m^d, d], unwrapped
     wrapped = cell % np.array(grid.n)[None, None, :]
@@ -197,7 +199,7 @@ def knn_grid_window(x: np.ndarray, grid, k: int):
     flat = np.einsum("tcd,d->tc", wrapped, stride)
     diffs = np.empty(cell.shape, dtype=np.float64)
     for a in range(d):
-        diffs[..., a] = (cell[..., a] + 0.5) * grid.h[a] - x[:, a:a + 1]
+        diffs[..., a] = (cell[..., a] + grid.offset) * grid.h[a] - x[:, a:a + 1]
     acc = None
     for a in range(d):
         sq = diffs[..., a] * diffs[..., a]

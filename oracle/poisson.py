@@ -43,14 +43,31 @@ def eigenvalues_1d(grid: Grid, a: int) -> np.ndarray:
     n = grid.n[a]
     k = np.arange(n, dtype=np.float64)
     if grid.eig == "spectral":
-        L = n * grid.h[a]
+        L = grid.length[a]
         if grid.periodic(a):
             return -(2.0 * np.pi * np.minimum(k, n - k) / L) ** 2
         return -(np.pi * k / L) ** 2
     if grid.eig != "fd2":
         raise ValueError(grid.eig)
+    if grid.vertex:  # DCT-I index k of the mirror-about-the-vertex operator
+        return -(4.0 / (grid.h[a] ** 2)) * np.sin(np.pi * k / (2.0 * (n - 1))) ** 2
     den = n if grid.periodic(a) else 2.0 * n
     return -(4.0 / (grid.h[a] ** 2)) * np.sin(np.pi * k / den) ** 2
+
+
+def weights(grid: Grid) -> np.ndarray:
+    """Quadrature weights of the grid points (flat [G]): 1, except 1/2 per
+    vertex-grid axis at its two end points (the trapezoid rule; the vertex
+    operator is symmetric in the inner product they define)."""
+    w = np.ones(grid.shape_zyx)
+    if grid.vertex:
+        for a in range(grid.d):
+            wa = np.ones(grid.n[a])
+            wa[0] = wa[-1] = 0.5
+            shape = [1] * grid.d
+            shape[grid.d - 1 - a] = grid.n[a]
+            w = w * wa.reshape(shape)
+    return w.reshape(-1)
 
 
 def eigenvalues(grid: Grid) -> np.ndarray:
@@ -66,12 +83,16 @@ def eigenvalues(grid: Grid) -> np.ndarray:
 
 def solve(grid: Grid, b: np.ndarray, workers: int = -1):
     """phi with L_h phi = b - mean(b) and mean(phi) = 0.  b: flat [G].
-    Returns (phi flat [G], bmean)."""
-    bm = float(np.mean(b))
+    Returns (phi flat [G], bmean).  On a vertex grid the transform is the
+    DCT-I, bmean the weighted mean (weights()) and phi has zero weighted
+    mean."""
+    w = weights(grid)
+    bm = float(np.sum(w * b) / np.sum(w)) if grid.vertex else float(np.mean(b))
     B = grid.to_array(b - bm)
     neu = tuple(grid.d - 1 - a for a in range(grid.d) if not grid.periodic(a))
     per = tuple(grid.d - 1 - a for a in range(grid.d) if grid.periodic(a))
-    Bh = sfft.dctn(B, type=2, axes=neu, workers=workers) if neu else B
+    ttype = 1 if grid.vertex else 2
+    Bh = sfft.dctn(B, type=ttype, axes=neu, workers=workers) if neu else B
     if per:
         Bh = sfft.fftn(Bh, axes=per, workers=workers)
     lam = eigenvalues(grid)
@@ -80,7 +101,7 @@ def solve(grid: Grid, b: np.ndarray, workers: int = -1):
     Ph.flat[0] = 0.0
     if per:
         Ph = sfft.ifftn(Ph, axes=per, workers=workers).real
-    phi = sfft.idctn(Ph, type=2, axes=neu, workers=workers) if neu else Ph
+    phi = sfft.idctn(Ph, type=ttype, axes=neu, workers=workers) if neu else Ph
     return np.ascontiguousarray(phi).reshape(-1), bm
 
 
@@ -95,6 +116,10 @@ def laplacian(grid: Grid, phi: np.ndarray) -> np.ndarray:
         if grid.periodic(a):
             up = np.roll(P, -1, axis=ax)
             dn = np.roll(P, 1, axis=ax)
+        elif grid.vertex:  # mirror about the end vertex: phi_{-1} = phi_1
+            n = grid.n[a]
+            up = np.take(P, list(range(1, n)) + [n - 2], axis=ax)
+            dn = np.take(P, [1] + list(range(0, n - 1)), axis=ax)
         else:
             lo = np.concatenate([np.take(P, [0], axis=ax), P], axis=ax)
             hi = np.concatenate([P, np.take(P, [grid.n[a] - 1], axis=ax)], axis=ax)
@@ -122,6 +147,8 @@ def laplacian_dense(grid: Grid) -> np.ndarray:
                 c = coords[a] + step
                 if grid.periodic(a):
                     q = p + ((c % grid.n[a]) - coords[a]) * strides[a]
+                elif grid.vertex and (c < 0 or c >= grid.n[a]):
+                    q = p - step * strides[a]  # the mirror image of the neighbour
                 else:
                     q = p if (c < 0 or c >= grid.n[a]) else p + step * strides[a]
                 L[p, q] += inv
@@ -130,13 +157,14 @@ def laplacian_dense(grid: Grid) -> np.ndarray:
 
 
 def solve_bordered(grid: Grid, b: np.ndarray):
-    """Dense LU of [[L, 1], [1^T, 0]] [phi; mu] = [b; 0].  mu equals mean(b)
-    and phi has zero mean.  Tiny grids only."""
+    """Dense LU of [[L, 1], [w^T, 0]] [phi; mu] = [b; 0] (w = weights()).
+    mu equals the (weighted) mean of b and phi has zero (weighted) mean.
+    Tiny grids only."""
     G = grid.G
     K = np.zeros((G + 1, G + 1))
     K[:G, :G] = laplacian_dense(grid)
     K[:G, G] = 1.0
-    K[G, :G] = 1.0
+    K[G, :G] = weights(grid)
     rhs = np.concatenate([b, [0.0]])
     sol = np.linalg.solve(K, rhs)
     return sol[:G], float(sol[G])

@@ -100,3 +100,32 @@ def test_window_spans_three_lines_per_axis(rng):
     cells = np.stack([idx % 8, (idx // 8) % 8, idx // 64], -1)
     for a in range(3):
         assert all(len(np.unique(cells[t, :, a])) >= 3 for t in range(500))
+
+
+@pytest.mark.parametrize("d,k", [(2, 16), (3, 27)])
+def test_vertex_node_window_by_exhaustion(rng, d, k):
+    """On the vertex grid (points at i h) the block holds the m grid lines
+    nearest to the node along each axis, clamped inside the box, and the
+    stencil is the k smallest keys of the block."""
+    from oracle import Grid
+    n = (9, 12, 7)[:d]
+    h = (0.1, 0.07, 0.13)[:d]
+    grid = Grid(d, n, h, vertex=True)
+    x = rng.uniform(size=(200, d)) * np.array([(v - 1) * hh for v, hh in zip(n, h)])
+    idx, d2, base, X = knn.knn_grid_window(x, grid, k)
+    m = knn.window_m(k, d)
+    for t in range(x.shape[0]):
+        for a in range(d):
+            lines = np.arange(n[a])
+            dist = np.abs(lines * h[a] - x[t, a])
+            near = np.sort(np.argsort(dist, kind="stable")[:m])
+            # the m nearest lines form a run; the block is that run
+            assert base[t, a] == near[0] or abs(dist[near[0]] - dist[base[t, a] + m - 1]) < 1e-12
+        cells = np.indices((m,) * d).reshape(d, -1)[::-1].T + base[t]
+        stride = np.cumprod([1] + list(n[:-1]))
+        flat = cells @ stride
+        pos = cells * np.array(h)
+        dd = ((pos - x[t]) ** 2).sum(1)
+        order = np.lexsort((flat, dd))[:k]
+        assert set(flat[order]) == set(idx[t])
+    np.testing.assert_allclose(X, grid.centres()[idx] - x[:, None, :], atol=1e-15)

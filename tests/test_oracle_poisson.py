@@ -233,3 +233,85 @@ def test_spectral_solve_exact_on_trig_polynomials(n, bc, terms):
     np.testing.assert_allclose(phi, f - f.mean(), atol=1e-12 * np.abs(f).max())
     fd, _ = poisson.solve(Grid(d, n, h, bc), lap)
     assert np.abs(fd - (f - f.mean())).max() > 1e-4 * np.abs(f).max()
+
+
+# ---- the regular (vertex) grid with the DCT-I (a solver variant Sec. 3 reports
+# as giving no noticeable difference) ---------------------------------------------
+
+def _vertex_eig(grid, ks):
+    """cos(pi k i / (n - 1)) per axis, eigenvalue of the 3-point stencil with
+    mirror ghosts about the end vertices written out."""
+    idx = np.indices(grid.shape_zyx)
+    v = np.ones(grid.shape_zyx)
+    lam = 0.0
+    for a in range(grid.d):
+        i = idx[grid.d - 1 - a]
+        n = grid.n[a]
+        v = v * np.cos(np.pi * ks[a] * i / (n - 1))
+        lam += (2 * np.cos(np.pi * ks[a] / (n - 1)) - 2) / grid.h[a] ** 2
+    return v.reshape(-1), lam
+
+
+@pytest.mark.parametrize("n,h,ks", [((33, 17), (1 / 32, 1 / 16), (5, 16)),
+                                    ((9, 12, 7), (0.1, 0.2, 0.05), (8, 3, 1))])
+def test_vertex_eigenfunctions(n, h, ks):
+    grid = Grid(len(n), n, h, vertex=True)
+    v, lam = _vertex_eig(grid, ks)
+    np.testing.assert_allclose(poisson.laplacian(grid, v), lam * v,
+                               atol=1e-12 * abs(lam) * np.abs(v).max())
+    phi, bm = poisson.solve(grid, v)
+    assert abs(bm) < 1e-13
+    np.testing.assert_allclose(phi, v / lam, atol=1e-13 * np.abs(v / lam).max())
+
+
+@pytest.mark.parametrize("n,h", [((3, 5), (0.3, 0.2)), ((4, 4, 4), (0.25,) * 3),
+                                 ((2, 3, 5), (0.5, 0.1, 0.7))])
+def test_vertex_bordered_lu(rng, n, h):
+    grid = Grid(len(n), n, h, vertex=True)
+    b = rng.normal(size=grid.G)
+    phi, bm = poisson.solve(grid, b)
+    phi2, mu = poisson.solve_bordered(grid, b)
+    w = poisson.weights(grid)
+    assert mu == pytest.approx(float(np.sum(w * b) / np.sum(w)), abs=1e-13)
+    assert bm == pytest.approx(mu, abs=1e-13)
+    np.testing.assert_allclose(phi, phi2, atol=1e-12 * np.abs(phi2).max())
+
+
+def test_vertex_dense_operator_and_exact_solve():
+    grid = Grid(2, (3, 4), (1.0, 0.5), vertex=True)
+    rng = np.random.Generator(np.random.PCG64(4))
+    v = rng.normal(size=grid.G)
+    np.testing.assert_allclose(poisson.laplacian_dense(grid) @ v, poisson.laplacian(grid, v),
+                               atol=1e-12)
+    # the end vertex's mirror neighbour counts twice: row 0 has 2/h^2 on its
+    # x neighbour
+    assert poisson.laplacian_dense(grid)[0, 1] == pytest.approx(2.0)
+    b = [Fraction(v) for v in (1, -2, 3, 5, 0, -4, 2, 2, -1, 0, 1, 3)]
+    # the bordered system with trapezoid weights, in rationals
+    L = poisson.laplacian_dense(grid)
+    w = poisson.weights(grid)
+    G = grid.G
+    K = [[Fraction(L[i, j]).limit_denominator(10 ** 6) for j in range(G)] + [Fraction(1), b[i]]
+         for i in range(G)]
+    K.append([Fraction(wj).limit_denominator(10) for wj in w] + [Fraction(0), Fraction(0)])
+    n_ = G + 1
+    for c in range(n_):
+        p = next(r for r in range(c, n_) if K[r][c] != 0)
+        K[c], K[p] = K[p], K[c]
+        for r in range(n_):
+            if r != c and K[r][c] != 0:
+                f = K[r][c] / K[c][c]
+                K[r] = [a - f * bb for a, bb in zip(K[r], K[c])]
+    sol = [K[i][G + 1] / K[i][i] for i in range(n_)]
+    phi, bm = poisson.solve(grid, np.array([float(v) for v in b]))
+    assert bm == pytest.approx(float(sol[-1]), abs=1e-14)
+    np.testing.assert_allclose(phi, [float(v) for v in sol[:-1]], atol=1e-13)
+
+
+def test_vertex_spectral_exact_on_trig():
+    n, h = (33, 17), (1 / 32, 1 / 16)
+    grid = Grid(2, n, h, eig="spectral", vertex=True)
+    f, lap = _trig_field(grid, [(1.0, ((3, 0.0), (5, 0.0))), (0.4, ((32, 0.0), (0, 0.0)))])
+    phi, _ = poisson.solve(grid, lap)
+    w = poisson.weights(grid)
+    np.testing.assert_allclose(phi, f - np.sum(w * f) / np.sum(w), atol=1e-12 * np.abs(f).max())
