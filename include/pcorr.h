@@ -92,6 +92,12 @@ extern "C" {
                           /* each mode (a variant Sec. 3 reports as giving no  */
                           /* noticeable difference)                            */
 
+/* ---- placement of the pressure grid points ---------------------------------- */
+#define PC_GRID_CELL 0   /* cell centres (i + 1/2) h: the staggered grid of the */
+                         /* paper's timings (Sec. 3.2)                         */
+#define PC_GRID_VERTEX 1 /* vertices i h of n - 1 intervals: the regular grid, */
+                         /* a variant Sec. 3 reports as interchangeable        */
+
 #define PC_KIND_F 0
 #define PC_KIND_B 1
 #define PC_KIND_V 2
@@ -172,8 +178,8 @@ int pc_last_error(char* buf, size_t n);
  * Synchronises `stream`.  Release with pc_plan_destroy. */
 int pc_plan_create(int d, const int32_t* n, const double* h, void* stream, pc_plan** out);
 
-/* pc_plan_create with a boundary condition per axis and a choice of
- * eigenvalues.
+/* pc_plan_create with a boundary condition per axis, a choice of eigenvalues
+ * and of grid-point placement.
  *   bc[a] = PC_BC_NEUMANN or PC_BC_PERIODIC (bc NULL: Neumann everywhere).
  *     A plan with a periodic axis needs every n[a] to be a power of two.
  *     A periodic axis of n cells (n a power of two in [32, 4096]) joins cell
@@ -188,9 +194,19 @@ int pc_plan_create(int d, const int32_t* n, const double* h, void* stream, pc_pl
  *     -(2 pi m / L_a)^2 for Fourier mode m of a periodic axis (L_a = n_a h_a).
  *     PC_MIXED needs PC_EIG_FD2 (its defect correction evaluates the
  *     3-point Laplacian); with PC_EIG_SPECTRAL it returns
- *     PC_ERR_INVALID_ARG. */
+ *     PC_ERR_INVALID_ARG.
+ *   grid = PC_GRID_CELL (points at (i + 1/2) h, box [0, n h]) or
+ *     PC_GRID_VERTEX (points at i h, box [0, (n - 1) h], n in [9, 2049],
+ *     Neumann axes only): the homogeneous Neumann condition mirrors about
+ *     the end vertex (phi_{-1} = phi_1), the transform is the DCT-I (the real
+ *     DFT of the even extension, on the mixed-radix kernel) and the
+ *     eigenvalues are -(4/h^2) sin^2(pi k / (2(n - 1))) (pseudo-spectral:
+ *     -(pi k / ((n - 1) h))^2).  The operator is symmetric in the trapezoid
+ *     weights (1/2 at the end points of each axis): bmean is the weighted
+ *     mean and phi has zero weighted mean.  PC_MIXED is refused.  The WLS
+ *     stencils of pc_wls_build use the same placement. */
 int pc_plan_create_ex(int d, const int32_t* n, const double* h, const int32_t* bc, int32_t eig,
-                      void* stream, pc_plan** out);
+                      int32_t grid, void* stream, pc_plan** out);
 int pc_plan_destroy(pc_plan* plan);
 
 /* ---- the Poisson solve ---------------------------------------------------- */

@@ -41,54 +41,61 @@ namespace {
 
 bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
 
-// Host float64 tables of one axis, written at `dst` (reals) in the order
-// twH[H] (complex), tN[H+1] (complex), t4N[H+1] (complex), lam[N].
-size_t axis_table_reals(int N) {
-  int H = N / 2;
-  return 2 * (size_t)H + 2 * (size_t)(H + 1) * 2 + (size_t)N;
+// Host float64 tables of one axis of n grid points, in the order twH[H]
+// (complex), tN[H+1] (complex), t4N[H+1] (complex), lam[n], where the real
+// sequence transformed has length NS = n (cell-centred axis) or 2(n-1) (the
+// even extension of a vertex axis, whose DCT-I is its real DFT) and H = NS/2.
+int axis_real_length(int n, bool vertex) { return vertex ? 2 * (n - 1) : n; }
+
+size_t axis_table_reals(int n, bool vertex) {
+  const int H = axis_real_length(n, vertex) / 2;
+  return 2 * (size_t)H + 2 * (size_t)(H + 1) * 2 + (size_t)n;
 }
 
-void fill_axis_tables(int N, double h, bool periodic, bool spectral, std::vector<double>& out) {
+void fill_axis_tables(int n, double h, bool periodic, bool vertex, bool spectral,
+                      std::vector<double>& out) {
   const long double PI = 3.141592653589793238462643383279502884L;
-  int H = N / 2;
+  const int NS = axis_real_length(n, vertex);
+  const int H = NS / 2;
   out.clear();
-  out.reserve(axis_table_reals(N));
+  out.reserve(axis_table_reals(n, vertex));
   for (int j = 0; j < H; ++j) {
     long double a = 2.0L * PI * (long double)j / (long double)H;
     out.push_back((double)cosl(a));
     out.push_back((double)-sinl(a));
   }
   for (int k = 0; k <= H; ++k) {
-    long double a = 2.0L * PI * (long double)k / (long double)N;
+    long double a = 2.0L * PI * (long double)k / (long double)NS;
     out.push_back((double)cosl(a));
     out.push_back((double)-sinl(a));
   }
   for (int k = 0; k <= H; ++k) {
-    long double a = PI * (long double)k / (2.0L * (long double)N);
+    long double a = PI * (long double)k / (2.0L * (long double)NS);
     out.push_back((double)cosl(a));
     out.push_back((double)-sinl(a));
   }
-  // eigenvalue of slot k: DCT-II index k (Neumann) or mode min(k, N-k)
-  // (periodic; sin^2 is the same for both)
-  const long double den = periodic ? (long double)N : 2.0L * (long double)N;
+  // eigenvalue of slot k: DCT-II index k (Neumann), mode min(k, n-k)
+  // (periodic; sin^2 is the same for both) or DCT-I index k (vertex axis)
+  const long double den = periodic ? (long double)n
+                                   : (vertex ? 2.0L * (long double)(n - 1) : 2.0L * (long double)n);
   if (spectral) {
-    const long double L = (long double)N * (long double)h;
-    for (int k = 0; k < N; ++k) {
-      const long double w = periodic ? 2.0L * PI * (long double)std::min(k, N - k) / L
+    const long double L = (long double)(vertex ? n - 1 : n) * (long double)h;
+    for (int k = 0; k < n; ++k) {
+      const long double w = periodic ? 2.0L * PI * (long double)std::min(k, n - k) / L
                                      : PI * (long double)k / L;
       out.push_back((double)(-(w * w)));
     }
     return;
   }
-  for (int k = 0; k < N; ++k) {
+  for (int k = 0; k < n; ++k) {
     long double sn = sinl(PI * (long double)k / den);
     out.push_back((double)(-(4.0L / ((long double)h * (long double)h)) * sn * sn));
   }
 }
 
 template <typename T>
-void set_axis_ptrs(AxisTables<T>& A, T* base, int N) {
-  int H = N / 2;
+void set_axis_ptrs(AxisTables<T>& A, T* base, int n, bool vertex) {
+  const int H = axis_real_length(n, vertex) / 2;
   A.twH = reinterpret_cast<const cplx<T>*>(base);
   A.tN = reinterpret_cast<const cplx<T>*>(base + 2 * (size_t)H);
   A.t4N = reinterpret_cast<const cplx<T>*>(base + 2 * (size_t)H + 2 * (size_t)(H + 1));
@@ -139,23 +146,32 @@ int pc_last_error(char* buf, size_t n) {
 }
 
 int pc_plan_create(int d, const int32_t* n, const double* h, void* stream, pc_plan** out) {
-  return pc_plan_create_ex(d, n, h, nullptr, PC_EIG_FD2, stream, out);
+  return pc_plan_create_ex(d, n, h, nullptr, PC_EIG_FD2, PC_GRID_CELL, stream, out);
 }
 
 int pc_plan_create_ex(int d, const int32_t* n, const double* h, const int32_t* bc, int32_t eig,
-                      void* stream, pc_plan** out) {
+                      int32_t grid, void* stream, pc_plan** out) {
   if (!out || !n || !h) return fail(PC_ERR_INVALID_ARG, "pc_plan_create: null argument");
   *out = nullptr;
   if (eig != PC_EIG_FD2 && eig != PC_EIG_SPECTRAL)
     return fail(PC_ERR_INVALID_ARG, "eig must be PC_EIG_FD2 or PC_EIG_SPECTRAL");
+  if (grid != PC_GRID_CELL && grid != PC_GRID_VERTEX)
+    return fail(PC_ERR_INVALID_ARG, "grid must be PC_GRID_CELL or PC_GRID_VERTEX");
+  const bool vertex = grid == PC_GRID_VERTEX;
   if (d != 2 && d != 3) return fail(PC_ERR_UNSUPPORTED_SIZE, "d must be 2 or 3");
   bool any_periodic = false, all_pow2 = true;
   for (int a = 0; a < d; ++a) {
     const int32_t b = bc ? bc[a] : PC_BC_NEUMANN;
     if (b != PC_BC_NEUMANN && b != PC_BC_PERIODIC)
       return fail(PC_ERR_INVALID_ARG, "bc[a] must be PC_BC_NEUMANN or PC_BC_PERIODIC");
-    if (n[a] < 8 || n[a] > 4096 || (n[a] & 1))
+    if (vertex) {
+      if (b != PC_BC_NEUMANN)
+        return fail(PC_ERR_INVALID_ARG, "a vertex grid has Neumann axes only");
+      if (n[a] < 9 || n[a] > 2049)
+        return fail(PC_ERR_UNSUPPORTED_SIZE, "a vertex axis needs n[a] in [9, 2049]");
+    } else if (n[a] < 8 || n[a] > 4096 || (n[a] & 1)) {
       return fail(PC_ERR_UNSUPPORTED_SIZE, "n[a] must be even and in [8, 4096]");
+    }
     if (b == PC_BC_PERIODIC && (!is_pow2(n[a]) || n[a] < 32))
       return fail(PC_ERR_UNSUPPORTED_SIZE, "a periodic axis needs a power of two in [32, 4096]");
     any_periodic = any_periodic || b == PC_BC_PERIODIC;
@@ -180,6 +196,7 @@ int pc_plan_create_ex(int d, const int32_t* n, const double* h, const int32_t* b
     P->h[a] = a < d ? h[a] : 1.0;
     P->bc[a] = (a < d && bc) ? bc[a] : PC_BC_NEUMANN;
     P->eig = eig;
+    P->vertex = vertex ? 1 : 0;
     P->G *= P->n[a];
   }
   if (hipGetDevice(&P->device) != hipSuccess) {
@@ -190,7 +207,8 @@ int pc_plan_create_ex(int d, const int32_t* n, const double* h, const int32_t* b
   size_t offs[3];
   for (int a = 0; a < d; ++a) {
     offs[a] = all.size();
-    fill_axis_tables(P->n[a], P->h[a], P->bc[a] == PC_BC_PERIODIC, eig == PC_EIG_SPECTRAL, one);
+    fill_axis_tables(P->n[a], P->h[a], P->bc[a] == PC_BC_PERIODIC, vertex, eig == PC_EIG_SPECTRAL,
+                     one);
     all.insert(all.end(), one.begin(), one.end());
   }
   std::vector<float> all32(all.size());
@@ -213,8 +231,8 @@ int pc_plan_create_ex(int d, const int32_t* n, const double* h, const int32_t* b
     return fail(PC_ERR_HIP, std::string("plan upload: ") + hipGetErrorString(e));
   }
   for (int a = 0; a < d; ++a) {
-    set_axis_ptrs(P->ax64[a], reinterpret_cast<double*>(P->tab64) + offs[a], P->n[a]);
-    set_axis_ptrs(P->ax32[a], reinterpret_cast<float*>(P->tab32) + offs[a], P->n[a]);
+    set_axis_ptrs(P->ax64[a], reinterpret_cast<double*>(P->tab64) + offs[a], P->n[a], vertex);
+    set_axis_ptrs(P->ax32[a], reinterpret_cast<float*>(P->tab32) + offs[a], P->n[a], vertex);
   }
   *out = P;
   return PC_OK;
@@ -374,6 +392,7 @@ int pc_poisson_fft_solve(const pc_plan* P, int mode, const void* b, void* phi, i
   if (b == phi) return fail(PC_ERR_INVALID_ARG, "PC_MIXED needs b and phi to be distinct");
   if (P->eig != PC_EIG_FD2)
     return fail(PC_ERR_INVALID_ARG, "PC_MIXED needs the central-difference eigenvalues");
+  if (P->vertex) return fail(PC_ERR_INVALID_ARG, "PC_MIXED needs the cell-centred grid");
   if (ws && ws->mode != PC_MIXED)
     return fail(PC_ERR_INVALID_ARG, "PC_MIXED needs a workspace created for PC_MIXED");
   PC_TRY(ensure_plan_ws(P, &ws));

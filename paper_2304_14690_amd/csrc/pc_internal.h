@@ -71,6 +71,7 @@ struct pc_plan {
   double h[3];
   int32_t bc[3];  // PC_BC_NEUMANN or PC_BC_PERIODIC per axis
   int32_t eig;    // PC_EIG_FD2 or PC_EIG_SPECTRAL
+  int32_t vertex; // 1: grid points at i h (regular grid, DCT-I); 0: cell centres
   int64_t G;
   int device;
   // one allocation per precision holding all axis tables
@@ -87,6 +88,7 @@ struct pc_geom {
   int32_t n[3];
   double h[3];
   int per;      // bit a set: axis a of the plan was periodic
+  int vertex;   // the plan's grid points sit at i h (1) or (i + 1/2) h (0)
   int k_grid;   // stencil size of grid targets
   int k_node;   // selected entries of node stencils
   int m_node;   // block lines per axis; block size bn = m^d
@@ -145,7 +147,7 @@ inline bool same_grid(const pc_plan* P, const pc_geom* g) {
     if (P->n[a] != g->n[a] || P->h[a] != g->h[a]) return false;
     if (P->bc[a] == PC_BC_PERIODIC) per |= 1 << a;
   }
-  return per == g->per;
+  return per == g->per && P->vertex == g->vertex;
 }
 }  // namespace pc
 

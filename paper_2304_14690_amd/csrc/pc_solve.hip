@@ -284,6 +284,144 @@ __global__ void __launch_bounds__(1024) dct_lines(LineArgs<TC> A) {
   }
 }
 
+// DCT-I of the lines of a vertex axis (n points, mirror about the end
+// vertices): the real DFT of the even extension e of length NS = 2(n-1)
+// (e[i] = x[i], e[NS-i] = x[i]) through the half-length complex FFT of
+// z[m] = e[2m] + i e[2m+1] (length H = n - 1) and the real-FFT split
+// X_k = Re(E_k + w^k O_k), w = exp(-2 pi i / NS), X_H = E_0 - O_0 (the
+// spectrum of an even sequence is real); the inverse builds Z from the real
+// spectrum with the same split, runs the inverse FFT and scales by 1/H.
+// C lines per workgroup in three LDS regions (two FFT buffers and the
+// spectra); lines past the end of a partial tile are masked.
+template <typename TC, typename TI, typename TO, int OP, int LD, int ST>
+__global__ void __launch_bounds__(1024) dct1_lines(LineArgs<TC> A) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  if (A.skip && *A.skip) return;
+  const int n = A.N, H = n - 1, NS = 2 * H, C = A.C;
+  const int ls = NS + A.pad;  // reals per line per region
+  const int lsc = ls >> 1;
+  TC* s0 = reinterpret_cast<TC*>(smem_raw);
+  TC* s1 = s0 + (size_t)C * ls;
+  TC* xs = s1 + (size_t)C * ls;
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int t = A.axis == 0 ? blockIdx.x : xcd_tile(blockIdx.x, gridDim.x);
+  const TI* __restrict__ in = reinterpret_cast<const TI*>(A.in);
+  TO* __restrict__ out = reinterpret_cast<TO*>(A.out);
+  const AxisTables<TC>& Tb = A.tab;
+  // global index of point i of line c (or -1 past the end of the tile)
+  auto gidx = [&](int c, int i) -> int64_t {
+    int li, lo;
+    const int64_t b = line_base(A, t, c, &li, &lo);
+    if (A.axis == 0 ? (int64_t)t * C + c >= A.lines : li >= A.n0) return -1;
+    return b + (int64_t)i * A.stride;
+  };
+  // element e of the tile's points: line c, point i (rows: points of a line
+  // adjacent; strided: lines adjacent)
+  auto split_e = [&](int e, int* c, int* i) {
+    if (A.axis == 0) { *c = e / n; *i = e - *c * n; } else { *i = e / C; *c = e - *i * C; }
+  };
+
+  if (OP != OP_INV) {
+    for (int e = tid; e < C * n; e += nthr) {
+      int c, i;
+      split_e(e, &c, &i);
+      const int64_t p = gidx(c, i);
+      TC v = TC(0);
+      if (p >= 0) {
+        if (LD == LD_RESID) {
+          double r = resid_at(A.rb, A.rphi, p, A.d, A.n0, A.n1, A.n2, A.perm, A.ih2, A.rscale);
+          if (A.sub) r -= *A.sub;
+          v = (TC)r;
+        } else if (A.sub) {
+          v = (TC)((double)in[p] - *A.sub);
+        } else {
+          v = (TC)in[p];
+        }
+      }
+      s0[c * ls + i] = v;
+      if (i > 0 && i < n - 1) s0[c * ls + NS - i] = v;
+    }
+    __syncthreads();
+    const cplx<TC>* zf = fft_lds_mixed<TC, false>(reinterpret_cast<cplx<TC>*>(s0),
+                                                  reinterpret_cast<cplx<TC>*>(s1), lsc, C, H, A,
+                                                  tid, nthr);
+    for (int e = tid; e < C * n; e += nthr) {
+      const int c = e / n, k = e - c * n;
+      const cplx<TC>* z = zf + c * lsc;
+      const int kk = k < H ? k : 0;
+      const cplx<TC> Zk = z[kk];
+      const cplx<TC> Zc = conj_(z[kk ? H - kk : 0]);
+      const cplx<TC> E = {(Zk.re + Zc.re) * TC(0.5), (Zk.im + Zc.im) * TC(0.5)};
+      const cplx<TC> D = {(Zk.re - Zc.re) * TC(0.5), (Zk.im - Zc.im) * TC(0.5)};
+      const cplx<TC> O = {D.im, -D.re};  // -i D
+      TC X;
+      if (k < H) {
+        const cplx<TC> WO = cmul(Tb.tN[k], O);
+        X = E.re + WO.re;
+      } else {
+        X = E.re - O.re;  // X_H = E_0 - O_0
+      }
+      xs[c * ls + k] = X;
+    }
+    __syncthreads();
+    if (OP == OP_FWD) {
+      for (int e = tid; e < C * n; e += nthr) {
+        int c, i;
+        split_e(e, &c, &i);
+        const int64_t p = gidx(c, i);
+        if (p >= 0) out[p] = (TO)(xs[c * ls + i] * A.outscale);
+      }
+      return;
+    }
+    // FDI: divide by the summed eigenvalues (slot k of this axis)
+    for (int e = tid; e < C * n; e += nthr) {
+      const int c = e / n, k = e - c * n;
+      int li, lo;
+      (void)line_base(A, t, c, &li, &lo);
+      const bool valid = A.axis == 0 ? (int64_t)t * C + c < A.lines : li < A.n0;
+      TC rest = TC(0);
+      if (valid) {
+        rest = A.lam0[li];
+        if (A.lam1) rest += A.lam1[lo];
+      }
+      const TC l = (rest + Tb.lam[k]) * A.lscale;
+      const TC X = xs[c * ls + k];
+      if (valid && k == 0 && rest == TC(0) && A.bmean) *A.bmean = (double)X * A.meannorm;
+      xs[c * ls + k] = l != TC(0) ? X / l : TC(0);
+    }
+    __syncthreads();
+  } else {
+    for (int e = tid; e < C * n; e += nthr) {
+      int c, i;
+      split_e(e, &c, &i);
+      const int64_t p = gidx(c, i);
+      xs[c * ls + i] = p >= 0 ? (TC)in[p] : TC(0);
+    }
+    __syncthreads();
+  }
+  // inverse: Z[k] from the real spectrum (imaginary parts zero)
+  cplx<TC>* za = reinterpret_cast<cplx<TC>*>(s0);
+  for (int e = tid; e < C * H; e += nthr) {
+    const int c = e / H, k = e - c * H;
+    const TC xk = xs[c * ls + k], xhk = xs[c * ls + H - k];
+    za[c * lsc + k] = pre_own_per(xk, TC(0), xhk, TC(0), Tb.tN[k]);
+  }
+  __syncthreads();
+  const TC* er = reinterpret_cast<const TC*>(
+      fft_lds_mixed<TC, true>(za, reinterpret_cast<cplx<TC>*>(s1), lsc, C, H, A, tid, nthr));
+  for (int e = tid; e < C * n; e += nthr) {
+    int c, i;
+    split_e(e, &c, &i);
+    const int64_t p = gidx(c, i);
+    if (p < 0) continue;
+    const TC v = er[c * ls + i] * A.outscale;
+    if (ST == ST_ACCUM)
+      reinterpret_cast<double*>(A.out)[p] = A.rphi[p] + (double)v;
+    else
+      out[p] = (TO)v;
+  }
+}
+
 // ---- deterministic mean ----------------------------------------------------
 __global__ void __launch_bounds__(256) partial_sum_f64(const double* __restrict__ x, int64_t n,
                                                        double* __restrict__ part,
@@ -465,15 +603,53 @@ int launch_pass(const pc_plan* P, int axis, const TI* in, TO* out, const AxisTab
   A.lam1 = (P->d == 3 && axis == 2) ? tabs[1].lam : nullptr;
   A.outscale = (OP == OP_FWD) ? TC(1) : TC(1.0 / (double)H);
   A.bmean = bmean;
-  // mode 0 of a line is 2 sum (cosine transform) or sum (real DFT)
+  // mode 0 of a line is 2 sum (cosine transform), sum (real DFT) or twice
+  // the trapezoid sum (DCT-I of a vertex axis)
   double norm = 1.0;
-  for (int a = 0; a < P->d; ++a) norm *= (P->bc[a] == PC_BC_PERIODIC ? 1.0 : 2.0) * P->n[a];
+  for (int a = 0; a < P->d; ++a)
+    norm *= P->vertex ? 2.0 * (P->n[a] - 1)
+                      : (P->bc[a] == PC_BC_PERIODIC ? 1.0 : 2.0) * P->n[a];
   A.meannorm = 1.0 / norm;
   A.own_table = P->eig == PC_EIG_SPECTRAL;
   A.perm = 0;
   for (int a = 0; a < P->d; ++a)
     if (P->bc[a] == PC_BC_PERIODIC) A.perm |= 1 << a;
   int64_t lines = P->G / A.N;
+  A.lines = lines;
+  if (P->vertex) {
+    // DCT-I kernel: C lines of the even extension (NS reals) in three LDS
+    // regions; partial tiles are masked, so C need not divide the counts
+    const int Hv = A.N - 1, NS = 2 * Hv;
+    A.nrad = generic_radices(Hv, A.rad);
+    if (A.nrad < 0) return fail(PC_ERR_UNSUPPORTED_SIZE, "transform length has too many factors");
+    A.outscale = (OP == OP_FWD) ? TC(1) : TC(1.0 / (double)Hv);
+    A.pad = 2;
+    const size_t per_line = (size_t)3 * (NS + A.pad) * sizeof(TC);
+    const int cmax = (int)std::max<size_t>(1, (size_t)lds_limit() / per_line);
+    int C = 1;
+    const int want = axis == 0 ? std::max(1, 2048 / NS) : (int)(128 / sizeof(TC));
+    while (2 * C <= std::min(want, cmax)) C <<= 1;
+    if ((size_t)C * per_line > (size_t)lds_limit())
+      return fail(PC_ERR_UNSUPPORTED_SIZE, "transform line does not fit in LDS");
+    A.C = C;
+    int64_t ntile;
+    if (axis == 0) {
+      ntile = (lines + C - 1) / C;
+    } else {
+      A.tx = (P->n[0] + C - 1) / C;
+      ntile = (int64_t)A.tx * (lines / P->n[0]);
+    }
+    int nthr = std::min(1024, std::max(64, C * Hv / 2));
+    nthr = (nthr + 63) / 64 * 64;
+    const size_t lds = (size_t)C * per_line;
+    const void* fn = (const void*)dct1_lines<TC, TI, TO, OP, LD, ST>;
+    if (lds > 65536)
+      PC_HIP_CHECK(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL((dct1_lines<TC, TI, TO, OP, LD, ST>), dim3((unsigned)ntile), dim3(nthr), lds,
+                       s, A);
+    PC_HIP_CHECK(hipGetLastError());
+    return PC_OK;
+  }
   if (A.N >= 32 && pow2(A.N)) {
     // register kernel: T = H/RT threads per line, C lines per group
     const int RT = pass_radix(P, axis);

@@ -63,6 +63,7 @@ struct LineArgs {
                         // slot) instead of computing them from the shift
                         // twiddles (pseudo-spectral eigenvalues)
   int32_t n0, n1, n2;
+  int64_t lines;        // lines along this axis (vertex-grid kernel: masking)
   double ih2[3];        // 1/h^2 (residual)
   int64_t stride;       // element stride along the axis
   AxisTables<TC> tab;   // tables of this axis

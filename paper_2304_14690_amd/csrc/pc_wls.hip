@@ -120,6 +120,7 @@ struct GridDesc {
   double h[3];
   double L[3];  // box length n h per axis
   int per;      // bit a set: axis a is periodic
+  double off;   // grid point i sits at (i + off) h: 1/2 (cell centres) or 0 (vertices)
   int64_t G;
 };
 
@@ -365,10 +366,11 @@ __global__ void __launch_bounds__(64) k_grid_stencils(GridStencilArgs GA) {
   }
   double xt[3];
 #pragma unroll
-  for (int a = 0; a < D; ++a) xt[a] = ((double)ci[a] + 0.5) * A.g.h[a];
+  for (int a = 0; a < D; ++a) xt[a] = ((double)ci[a] + A.g.off) * A.g.h[a];
   double ld[KMAX];
   int li[KMAX];
-  const int found = knn_ring<D>(A, xt, ci, k, -1, 0.5, ld, li);
+  // a cell centre is 1/2 h inside its cell, a vertex sits on its corner
+  const int found = knn_ring<D>(A, xt, ci, k, -1, A.g.off, ld, li);
   if (found < k) {
     atomicOr(GA.bad, 2);
     return;
@@ -468,7 +470,7 @@ __global__ void __launch_bounds__(64) k_node_stencils(NodeStencilArgs A) {
 #pragma unroll
   for (int a = 0; a < D; ++a) {
     x[a] = A.xyz[a * A.M + n];
-    double lo = floor(x[a] / A.g.h[a] - (0.5 * m - 0.5));
+    double lo = floor(x[a] / A.g.h[a] - (0.5 * m - 1.0 + A.g.off));
     if (!((A.g.per >> a) & 1)) lo = fmin(fmax(lo, 0.0), (double)(A.g.n[a] - m));
     base[a] = (int)lo;
     const int na = A.g.n[a];
@@ -491,7 +493,7 @@ __global__ void __launch_bounds__(64) k_node_stencils(NodeStencilArgs A) {
 #pragma unroll
       for (int a = 0; a < D; ++a) {
         int cc = base[a] + oc[a];
-        dd[a] = ((double)cc + 0.5) * A.g.h[a] - x[a];
+        dd[a] = ((double)cc + A.g.off) * A.g.h[a] - x[a];
         const int na = A.g.n[a];
         f += (int64_t)(cc < 0 ? cc + na : (cc >= na ? cc - na : cc)) * st;
         st *= na;
@@ -528,7 +530,8 @@ __global__ void __launch_bounds__(64) k_node_stencils(NodeStencilArgs A) {
       int oc[3] = {o % m, (o / m) % m, o / (m * m)};
       double xi[3];
 #pragma unroll
-      for (int a = 0; a < D; ++a) xi[a] = ((((double)(base[a] + oc[a]) + 0.5) * A.g.h[a]) - x[a]) / ht;
+      for (int a = 0; a < D; ++a)
+        xi[a] = ((((double)(base[a] + oc[a]) + A.g.off) * A.g.h[a]) - x[a]) / ht;
       double w = exp((-A.eps * d2[o]) / (ht * ht));
       double q[MU];
       basis<D>(xi, q);
@@ -561,7 +564,7 @@ __global__ void __launch_bounds__(64) k_node_stencils(NodeStencilArgs A) {
         double xi[3];
 #pragma unroll
         for (int a = 0; a < D; ++a)
-          xi[a] = ((((double)(base[a] + oc[a]) + 0.5) * A.g.h[a]) - x[a]) / ht;
+          xi[a] = ((((double)(base[a] + oc[a]) + A.g.off) * A.g.h[a]) - x[a]) / ht;
         double w = exp((-A.eps * d2[o]) / (ht * ht));
         double q[MU];
         basis<D>(xi, q);
@@ -869,7 +872,9 @@ int build(const pc_plan* P, const double* xyz, const uint8_t* kind, int64_t M,
     if (a < d && P->bc[a] == PC_BC_PERIODIC) gd.per |= 1 << a;
   }
   gd.G = G;
+  gd.off = P->vertex ? 0.0 : 0.5;
   g->per = gd.per;
+  g->vertex = P->vertex;
 
   Scratch tmp;
   int32_t *count, *start, *cursor, *sorted, *bad;

@@ -34,6 +34,8 @@ PC_BC_NEUMANN, PC_BC_PERIODIC = 0, 1
 BCS = {"neumann": PC_BC_NEUMANN, "periodic": PC_BC_PERIODIC}
 PC_EIG_FD2, PC_EIG_SPECTRAL = 0, 1
 EIGS = {"fd2": PC_EIG_FD2, "spectral": PC_EIG_SPECTRAL}
+PC_GRID_CELL, PC_GRID_VERTEX = 0, 1
+GRIDS = {"cell": PC_GRID_CELL, "vertex": PC_GRID_VERTEX}
 
 MODES = {"f64": PC_F64, "f32": PC_F32, "mixed": PC_MIXED}
 
@@ -87,7 +89,7 @@ def _load():
         "pc_version": ([], ctypes.c_int),
         "pc_last_error": ([ctypes.c_char_p, ctypes.c_size_t], ctypes.c_int),
         "pc_plan_create": ([ctypes.c_int, vp, vp, vp, ctypes.POINTER(vp)], ctypes.c_int),
-        "pc_plan_create_ex": ([ctypes.c_int, vp, vp, vp, i32, vp, ctypes.POINTER(vp)],
+        "pc_plan_create_ex": ([ctypes.c_int, vp, vp, vp, i32, i32, vp, ctypes.POINTER(vp)],
                               ctypes.c_int),
         "pc_plan_destroy": ([vp], ctypes.c_int),
         "pc_poisson_fft_solve": ([vp, ctypes.c_int, vp, vp, ctypes.c_int, vp, vp, vp],
@@ -170,14 +172,15 @@ def _dtype_code(t: torch.Tensor) -> int:
 class Plan:
     """Grid and transform tables (pc_plan).  bc: per-axis "neumann" or
     "periodic" (or the PC_BC_* codes); None is Neumann everywhere.  eig:
-    "fd2" (central differences) or "spectral" (pseudo-spectral)."""
+    "fd2" (central differences) or "spectral" (pseudo-spectral).  grid:
+    "cell" (points at (i + 1/2) h) or "vertex" (points at i h)."""
 
     def __init__(self, d: int, n: Sequence[int], h: Sequence[float], stream=None,
-                 bc: Optional[Sequence] = None, eig: str = "fd2"):
+                 bc: Optional[Sequence] = None, eig: str = "fd2", grid: str = "cell"):
         nn = (ctypes.c_int32 * 3)(*(list(n) + [1] * (3 - len(n))))
         hh = (ctypes.c_double * 3)(*(list(h) + [1.0] * (3 - len(h))))
         out = ctypes.c_void_p()
-        if bc is None and eig == "fd2":
+        if bc is None and eig == "fd2" and grid == "cell":
             _check(_lib.pc_plan_create(d, ctypes.addressof(nn), ctypes.addressof(hh),
                                        _stream(stream), ctypes.byref(out)))
             self.bc = ("neumann",) * d
@@ -185,12 +188,14 @@ class Plan:
             codes = [BCS[b] if isinstance(b, str) else int(b) for b in (bc or ("neumann",) * d)]
             bb = (ctypes.c_int32 * 3)(*(codes + [0] * (3 - len(codes))))
             e = EIGS[eig] if isinstance(eig, str) else int(eig)
+            gt = GRIDS[grid] if isinstance(grid, str) else int(grid)
             _check(_lib.pc_plan_create_ex(d, ctypes.addressof(nn), ctypes.addressof(hh),
-                                          ctypes.addressof(bb), e, _stream(stream),
+                                          ctypes.addressof(bb), e, gt, _stream(stream),
                                           ctypes.byref(out)))
             names = {v: k for k, v in BCS.items()}
             self.bc = tuple(names.get(c, str(c)) for c in codes)
         self.eig = eig
+        self.grid = grid
         self.h_ = out
         self.d, self.n, self.h = d, tuple(n), tuple(h)
         self.G = 1

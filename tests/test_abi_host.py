@@ -53,16 +53,26 @@ def test_host_side_validation():
     assert lib.pc_plan_destroy(None) == pcorr.PC_OK
     # per-axis conditions: unknown codes, and periodic axes below 32 cells
     bc = (ctypes.c_int32 * 3)(pcorr.PC_BC_PERIODIC, 7, 0)
-    assert lib.pc_plan_create_ex(2, n, h, bc, 0, None, ctypes.byref(out)) == \
+    assert lib.pc_plan_create_ex(2, n, h, bc, 0, 0, None, ctypes.byref(out)) == \
         pcorr.PC_ERR_INVALID_ARG
-    assert lib.pc_plan_create_ex(2, n, h, None, 5, None, ctypes.byref(out)) == \
+    assert lib.pc_plan_create_ex(2, n, h, None, 5, 0, None, ctypes.byref(out)) == \
         pcorr.PC_ERR_INVALID_ARG
     assert "eig" in pcorr.last_error()
     small = (ctypes.c_int32 * 3)(16, 64, 1)
     bc = (ctypes.c_int32 * 3)(pcorr.PC_BC_PERIODIC, pcorr.PC_BC_NEUMANN, 0)
-    assert lib.pc_plan_create_ex(2, small, h, bc, 0, None, ctypes.byref(out)) == \
+    assert lib.pc_plan_create_ex(2, small, h, bc, 0, 0, None, ctypes.byref(out)) == \
         pcorr.PC_ERR_UNSUPPORTED_SIZE
     assert "periodic" in pcorr.last_error()
+    # grid placement: unknown codes, vertex grids with a periodic axis or too short
+    assert lib.pc_plan_create_ex(2, n, h, None, 0, 7, None, ctypes.byref(out)) == \
+        pcorr.PC_ERR_INVALID_ARG
+    vb = (ctypes.c_int32 * 3)(pcorr.PC_BC_PERIODIC, pcorr.PC_BC_NEUMANN, 0)
+    vn = (ctypes.c_int32 * 3)(65, 65, 1)
+    assert lib.pc_plan_create_ex(2, vn, h, vb, 0, 1, None, ctypes.byref(out)) == \
+        pcorr.PC_ERR_INVALID_ARG
+    v8 = (ctypes.c_int32 * 3)(8, 65, 1)
+    assert lib.pc_plan_create_ex(2, v8, h, None, 0, 1, None, ctypes.byref(out)) == \
+        pcorr.PC_ERR_UNSUPPORTED_SIZE
 
 
 def test_no_device_is_an_error_not_a_fallback():
