@@ -252,9 +252,10 @@ struct RingArgs {
 // are scanned until every unscanned node lies at least (R + bound_off) hmin
 // away: bound_off = 1/2 for a target at a cell centre, 0 for one anywhere in
 // its cell.  Returns the number of nodes seen.
-template <int D>
-__device__ __forceinline__ int knn_ring(const RingArgs& A, const double* xt, const int* ci, int k,
-                                        int exclude, double bound_off, double* ld, int* li) {
+template <int D, bool EXCL>
+__device__ __forceinline__ int knn_ring(const RingArgs& A, const double (&xt)[3], const int (&ci)[3],
+                                        int k, int exclude, double bound_off, double (&ld)[KMAX],
+                                        int (&li)[KMAX]) {
   double hmin = A.g.h[0];
 #pragma unroll
   for (int a = 1; a < D; ++a) hmin = fmin(hmin, A.g.h[a]);
@@ -305,7 +306,7 @@ __device__ __forceinline__ int knn_ring(const RingArgs& A, const double* xt, con
           int s0 = A.start[c], s1 = A.start[c + 1];
           for (int s = s0; s < s1; ++s) {
             int nid = A.sorted[s];
-            if (nid == exclude) continue;
+            if (EXCL && nid == exclude) continue;
             double dx = axis_diff(A.xyz[nid], xt[0], A.g, 0);
             double dy = axis_diff(A.xyz[A.M + nid], xt[1], A.g, 1);
             double d2 = D == 2 ? sq_sum2(dx, dy)
@@ -348,6 +349,9 @@ struct GridStencilArgs {
   int32_t* bad;           // singular flag
 };
 
+// The ring search is written out here rather than through knn_ring: the
+// shared version costs this kernel its second wavefront per SIMD (register
+// spills into accumulation registers), which doubles the build time.
 template <int D>
 __global__ void __launch_bounds__(64) k_grid_stencils(GridStencilArgs GA) {
   constexpr int MU = D == 2 ? 6 : 10;
@@ -367,10 +371,89 @@ __global__ void __launch_bounds__(64) k_grid_stencils(GridStencilArgs GA) {
   double xt[3];
 #pragma unroll
   for (int a = 0; a < D; ++a) xt[a] = ((double)ci[a] + A.g.off) * A.g.h[a];
+  double hmin = A.g.h[0];
+#pragma unroll
+  for (int a = 1; a < D; ++a) hmin = fmin(hmin, A.g.h[a]);
+
+  // kept list in descending key order: L[0] is the worst kept
   double ld[KMAX];
   int li[KMAX];
-  // a cell centre is 1/2 h inside its cell, a vertex sits on its corner
-  const int found = knn_ring<D>(A, xt, ci, k, -1, A.g.off, ld, li);
+#pragma unroll
+  for (int j = 0; j < KMAX; ++j) {
+    ld[j] = INFINITY;
+    li[j] = 0x7fffffff;
+  }
+  int found = 0;
+  int nmax = A.g.n[0];
+#pragma unroll
+  for (int a = 1; a < D; ++a) nmax = max(nmax, (int)A.g.n[a]);
+  for (int R = 0; R <= nmax; ++R) {
+    // cells at Chebyshev distance exactly R from the target's cell
+    int lo[3], hi[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      lo[a] = a < D ? ci[a] - R : 0;
+      hi[a] = a < D ? ci[a] + R : 0;
+    }
+    // A cell index c along axis a is scanned when it lies in the box (a
+    // Neumann axis) or in the window of n cells centred on the target's
+    // cell (a periodic axis; c then stands for its wrapped cell, each cell
+    // once).
+    auto cell_in = [&](int a, int c, int* w) -> bool {
+      const int na = A.g.n[a];
+      if ((A.g.per >> a) & 1) {
+        const int lo_w = ci[a] - na / 2;
+        if (c < lo_w || c >= lo_w + na) return false;
+        *w = c < 0 ? c + na : (c >= na ? c - na : c);
+        return true;
+      }
+      *w = c;
+      return c >= 0 && c < na;
+    };
+    for (int cz = lo[2]; cz <= hi[2]; ++cz) {
+      int wz = 0;
+      if (D == 3 && !cell_in(2, cz, &wz)) continue;
+      for (int cy = lo[1]; cy <= hi[1]; ++cy) {
+        int wy;
+        if (!cell_in(1, cy, &wy)) continue;
+        bool yz_edge = (cy == lo[1] || cy == hi[1]) || (D == 3 && (cz == lo[2] || cz == hi[2]));
+        int step = (yz_edge || R == 0) ? 1 : 2 * R;
+        for (int cx = lo[0]; cx <= hi[0]; cx += step) {
+          int wx;
+          if (!cell_in(0, cx, &wx)) continue;
+          int64_t c = wx + (int64_t)A.g.n[0] * (wy + (int64_t)A.g.n[1] * wz);
+          int s0 = A.start[c], s1 = A.start[c + 1];
+          for (int s = s0; s < s1; ++s) {
+            int nid = A.sorted[s];
+            double dx = axis_diff(A.xyz[nid], xt[0], A.g, 0);
+            double dy = axis_diff(A.xyz[A.M + nid], xt[1], A.g, 1);
+            double d2 = D == 2 ? sq_sum2(dx, dy)
+                               : sq_sum3(dx, dy, axis_diff(A.xyz[2 * A.M + nid], xt[2], A.g, 2));
+            ++found;
+            if (key_lt(d2, nid, ld[0], li[0])) {
+              ld[0] = d2;
+              li[0] = nid;
+#pragma unroll
+              for (int j = 0; j + 1 < KMAX; ++j) {
+                if (j + 1 < k && key_lt(ld[j], li[j], ld[j + 1], li[j + 1])) {
+                  double td = ld[j];
+                  ld[j] = ld[j + 1];
+                  ld[j + 1] = td;
+                  int ti = li[j];
+                  li[j] = li[j + 1];
+                  li[j + 1] = ti;
+                }
+              }
+            }
+          }
+        }
+      }
+    }
+    // every unscanned node lies at least (R + off) hmin away (a cell centre
+    // is 1/2 h inside its cell, a vertex sits on its corner)
+    double bound = (R + A.g.off) * hmin;
+    if (found >= k && ld[0] < bound * bound * (1.0 - 1e-12)) break;
+  }
   if (found < k) {
     atomicOr(GA.bad, 2);
     return;
@@ -631,7 +714,7 @@ __global__ void __launch_bounds__(64) k_self_stencils(SelfStencilArgs SA) {
   }
   double ld[KMAX];
   int li[KMAX];
-  const int found = knn_ring<D>(A, xt, ci, k, (int)n, 0.0, ld, li);
+  const int found = knn_ring<D, true>(A, xt, ci, k, (int)n, 0.0, ld, li);
   if (found < k) {
     atomicOr(SA.bad, 2);
     return;
