@@ -15,9 +15,13 @@
  * with the divergence and the gradient carried between the scattered
  * velocity points ("nodes") and the grid by second-order weighted least
  * squares (Sec. 2.2, Eqs. 9-17), the Poisson equation solved directly by
- * cosine transforms (Sec. 2.3, the three-step transform algorithm, with the
- * homogeneous Neumann condition of Eq. 7 on every box face), and the
- * immersed-boundary force found by the fixed-point iteration of Sec. 2.3.
+ * transforms (Sec. 2.3, the three-step transform algorithm: cosine
+ * transforms for the homogeneous Neumann condition of Eq. 7, real Fourier
+ * transforms along periodic axes), and the immersed-boundary force found by
+ * the fixed-point iteration of Sec. 2.3.  Options cover the solver
+ * variants Sec. 3 reports as interchangeable (pseudo-spectral eigenvalues,
+ * the regular vertex grid with the DCT-I), grid sizes that are not powers
+ * of two, and the first fractional step (Eq. 3) for whole time steps.
  *
  * Internally the library works with phi = (3 dt / 2) p and g = dt f~, for
  * which Eqs. 18-20 read u^{n+1} = u* - grad phi + g, lap phi = div(u* + g),
@@ -155,7 +159,7 @@ typedef struct pc_stats {
 
 /* ---- library ------------------------------------------------------------ */
 
-/* ABI version (major*100 + minor). */
+/* ABI version (major*100 + minor): 110. */
 int pc_version(void);
 
 /* Copies the calling thread's last error message into buf (NUL-terminated,
@@ -214,7 +218,8 @@ int pc_plan_destroy(pc_plan* plan);
 /* Solves lap_h phi = b - mean(b) with mean(phi) = 0 on the plan's grid
  * (Sec. 2.3: forward transforms along each axis, division by the sum of the
  * 1D eigenvalues, backward transforms; the zero mode is dropped and the
- * compatibility defect mean(b) removed).
+ * compatibility defect mean(b) removed; on a vertex grid both means are
+ * weighted by the trapezoid rule).
  *   mode PC_F64:   b_dev, phi_dev float64 [G].
  *   mode PC_F32:   b_dev, phi_dev float32 [G].
  *   mode PC_MIXED: b_dev, phi_dev float64 [G]; transforms in float32 with
@@ -235,7 +240,9 @@ int pc_poisson_fft_solve(const pc_plan* plan, int mode, const void* b_dev, void*
  *     index), d^2 = ((dx*dx) + dy*dy) + dz*dz rounded term by term);
  *   - every node takes the k_node nearest grid points (same key, flat grid
  *     index) inside the block of the m = ceil(k_node^(1/d)) grid lines
- *     nearest to it along each axis, clamped inside the box;
+ *     nearest to it along each axis, clamped inside the box (along a
+ *     periodic axis the block wraps around; grid lines sit at the cell
+ *     centres or, on a vertex grid, at i h);
  *   - for each target, the Eq. 16 polynomial vector (10 terms in 3D) in
  *     coordinates scaled by the support radius h_t = max(support*delta,
  *     r_k), the Eq. 17 weights exp(-eps r^2/h_t^2), C = sum w q q^T
@@ -259,7 +266,8 @@ int pc_geom_info(const pc_geom* geom, int64_t* counts6);
  *                                          (the selection is by (d^2, idx))
  *   grid_coef_dev float64 [d][k_grid][G]   derivative coefficients
  *   node_base_dev int32   [M]              flat grid index of the block's
- *                                          low corner
+ *                                          low corner (entries past a
+ *                                          periodic face wrap around)
  *   node_coef_dev float64 [d][m^d][M]      coefficients in block order
  *                                          (x fastest); 0 for block points
  *                                          outside the k_node selection

@@ -133,7 +133,7 @@ using namespace pc;
 
 extern "C" {
 
-int pc_version(void) { return 100; }
+int pc_version(void) { return 110; }
 
 int pc_last_error(char* buf, size_t n) {
   const std::string& m = g_last_error;
