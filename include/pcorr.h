@@ -159,7 +159,7 @@ typedef struct pc_stats {
 
 /* ---- library ------------------------------------------------------------ */
 
-/* ABI version (major*100 + minor): 110. */
+/* ABI version (major*100 + minor): 111. */
 int pc_version(void);
 
 /* Copies the calling thread's last error message into buf (NUL-terminated,
@@ -185,9 +185,10 @@ int pc_plan_create(int d, const int32_t* n, const double* h, void* stream, pc_pl
 /* pc_plan_create with a boundary condition per axis, a choice of eigenvalues
  * and of grid-point placement.
  *   bc[a] = PC_BC_NEUMANN or PC_BC_PERIODIC (bc NULL: Neumann everywhere).
- *     A plan with a periodic axis needs every n[a] to be a power of two.
- *     A periodic axis of n cells (n a power of two in [32, 4096]) joins cell
- *     n-1 to cell 0; its transform is the real DFT, packed into n reals, and
+ *     A periodic axis of n cells (n even, in [8, 4096]) joins cell n-1 to
+ *     cell 0 (the 400 x 400 doubly periodic grid of Sec. 3, or a periodic
+ *     axis beside a Neumann one); its transform is the real DFT, packed into
+ *     n reals (slot k: Re X_k, slot n-k: Im X_k, slot n/2: X_{n/2}), and
  *     its central-difference eigenvalues are -(4/h_a^2) sin^2(pi k / n_a),
  *     those of the wrap-around 3-point Laplacian.  Every entry point that
  *     takes the plan follows its axes' conditions: the solve, and the WLS

@@ -39,8 +39,6 @@ void dev_free(void* p) {
 
 namespace {
 
-bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
-
 // Host float64 tables of one axis of n grid points, in the order twH[H]
 // (complex), tN[H+1] (complex), t4N[H+1] (complex), lam[n], where the real
 // sequence transformed has length NS = n (cell-centred axis) or 2(n-1) (the
@@ -133,7 +131,7 @@ using namespace pc;
 
 extern "C" {
 
-int pc_version(void) { return 110; }
+int pc_version(void) { return 111; }
 
 int pc_last_error(char* buf, size_t n) {
   const std::string& m = g_last_error;
@@ -159,7 +157,6 @@ int pc_plan_create_ex(int d, const int32_t* n, const double* h, const int32_t* b
     return fail(PC_ERR_INVALID_ARG, "grid must be PC_GRID_CELL or PC_GRID_VERTEX");
   const bool vertex = grid == PC_GRID_VERTEX;
   if (d != 2 && d != 3) return fail(PC_ERR_UNSUPPORTED_SIZE, "d must be 2 or 3");
-  bool any_periodic = false, all_pow2 = true;
   for (int a = 0; a < d; ++a) {
     const int32_t b = bc ? bc[a] : PC_BC_NEUMANN;
     if (b != PC_BC_NEUMANN && b != PC_BC_PERIODIC)
@@ -172,16 +169,9 @@ int pc_plan_create_ex(int d, const int32_t* n, const double* h, const int32_t* b
     } else if (n[a] < 8 || n[a] > 4096 || (n[a] & 1)) {
       return fail(PC_ERR_UNSUPPORTED_SIZE, "n[a] must be even and in [8, 4096]");
     }
-    if (b == PC_BC_PERIODIC && (!is_pow2(n[a]) || n[a] < 32))
-      return fail(PC_ERR_UNSUPPORTED_SIZE, "a periodic axis needs a power of two in [32, 4096]");
-    any_periodic = any_periodic || b == PC_BC_PERIODIC;
-    all_pow2 = all_pow2 && is_pow2(n[a]);
     if (!(h[a] > 0.0) || !std::isfinite(h[a]))
       return fail(PC_ERR_INVALID_ARG, "h[a] must be positive and finite");
   }
-  if (any_periodic && !all_pow2)
-    return fail(PC_ERR_UNSUPPORTED_SIZE,
-                "a plan with a periodic axis needs every n[a] to be a power of two");
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
     (void)hipGetLastError();

@@ -422,6 +422,136 @@ __global__ void __launch_bounds__(1024) dct1_lines(LineArgs<TC> A) {
   }
 }
 
+// The packed real DFT of the lines of a periodic axis of any even length N
+// (the generic counterpart of the periodic register kernel, same slots:
+// slot k = Re X_k, slot N-k = Im X_k, slot H = X_H): the half-length complex
+// FFT of z[m] = x[2m] + i x[2m+1] (mixed radix, H = N/2) and the real-FFT
+// split X_k = E_k + w^k O_k, w = exp(-2 pi i / N); the inverse runs the same
+// steps backwards and scales by 1/H.  C lines per workgroup in three LDS
+// regions; lines past the end of a partial tile are masked.
+template <typename TC, typename TI, typename TO, int OP, int LD, int ST>
+__global__ void __launch_bounds__(1024) rdft_lines(LineArgs<TC> A) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  if (A.skip && *A.skip) return;
+  const int N = A.N, H = N / 2, C = A.C;
+  const int ls = N + A.pad;
+  const int lsc = ls >> 1;
+  TC* s0 = reinterpret_cast<TC*>(smem_raw);
+  TC* s1 = s0 + (size_t)C * ls;
+  TC* xs = s1 + (size_t)C * ls;
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int t = A.axis == 0 ? blockIdx.x : xcd_tile(blockIdx.x, gridDim.x);
+  const TI* __restrict__ in = reinterpret_cast<const TI*>(A.in);
+  TO* __restrict__ out = reinterpret_cast<TO*>(A.out);
+  const AxisTables<TC>& Tb = A.tab;
+  auto gidx = [&](int c, int i) -> int64_t {
+    int li, lo;
+    const int64_t b = line_base(A, t, c, &li, &lo);
+    if (A.axis == 0 ? (int64_t)t * C + c >= A.lines : li >= A.n0) return -1;
+    return b + (int64_t)i * A.stride;
+  };
+  auto split_e = [&](int e, int* c, int* i) {
+    if (A.axis == 0) { *c = e / N; *i = e - *c * N; } else { *i = e / C; *c = e - *i * C; }
+  };
+
+  if (OP != OP_INV) {
+    for (int e = tid; e < C * N; e += nthr) {
+      int c, i;
+      split_e(e, &c, &i);
+      const int64_t p = gidx(c, i);
+      TC v = TC(0);
+      if (p >= 0) {
+        if (LD == LD_RESID) {
+          double r = resid_at(A.rb, A.rphi, p, A.d, A.n0, A.n1, A.n2, A.perm, A.ih2, A.rscale);
+          if (A.sub) r -= *A.sub;
+          v = (TC)r;
+        } else if (A.sub) {
+          v = (TC)((double)in[p] - *A.sub);
+        } else {
+          v = (TC)in[p];
+        }
+      }
+      s0[c * ls + i] = v;
+    }
+    __syncthreads();
+    const cplx<TC>* zf = fft_lds_mixed<TC, false>(reinterpret_cast<cplx<TC>*>(s0),
+                                                  reinterpret_cast<cplx<TC>*>(s1), lsc, C, H, A,
+                                                  tid, nthr);
+    // split: slots k and N-k from the own index k (k < H), slot H from k = 0
+    for (int e = tid; e < C * H; e += nthr) {
+      const int c = e / H, k = e - c * H;
+      const cplx<TC>* z = zf + c * lsc;
+      const cplx<TC> Zk = z[k];
+      const cplx<TC> Zc = conj_(z[k ? H - k : 0]);
+      const cplx<TC> E = {(Zk.re + Zc.re) * TC(0.5), (Zk.im + Zc.im) * TC(0.5)};
+      const cplx<TC> D = {(Zk.re - Zc.re) * TC(0.5), (Zk.im - Zc.im) * TC(0.5)};
+      const cplx<TC> O = {D.im, -D.re};  // -i D
+      const cplx<TC> WO = cmul(Tb.tN[k], O);
+      xs[c * ls + k] = E.re + WO.re;
+      if (k)
+        xs[c * ls + N - k] = E.im + WO.im;
+      else
+        xs[c * ls + H] = E.re - WO.re;  // X_H = E_0 - O_0 (w^0 = 1)
+    }
+    __syncthreads();
+    if (OP == OP_FWD) {
+      for (int e = tid; e < C * N; e += nthr) {
+        int c, i;
+        split_e(e, &c, &i);
+        const int64_t p = gidx(c, i);
+        if (p >= 0) out[p] = (TO)(xs[c * ls + i] * A.outscale);
+      }
+      return;
+    }
+    for (int e = tid; e < C * N; e += nthr) {
+      const int c = e / N, k = e - c * N;
+      int li, lo;
+      (void)line_base(A, t, c, &li, &lo);
+      const bool valid = A.axis == 0 ? (int64_t)t * C + c < A.lines : li < A.n0;
+      TC rest = TC(0);
+      if (valid) {
+        rest = A.lam0[li];
+        if (A.lam1) rest += A.lam1[lo];
+      }
+      const TC l = (rest + Tb.lam[k]) * A.lscale;  // the table is by slot
+      const TC X = xs[c * ls + k];
+      if (valid && k == 0 && rest == TC(0) && A.bmean) *A.bmean = (double)X * A.meannorm;
+      xs[c * ls + k] = l != TC(0) ? X / l : TC(0);
+    }
+    __syncthreads();
+  } else {
+    for (int e = tid; e < C * N; e += nthr) {
+      int c, i;
+      split_e(e, &c, &i);
+      const int64_t p = gidx(c, i);
+      xs[c * ls + i] = p >= 0 ? (TC)in[p] : TC(0);
+    }
+    __syncthreads();
+  }
+  cplx<TC>* za = reinterpret_cast<cplx<TC>*>(s0);
+  for (int e = tid; e < C * H; e += nthr) {
+    const int c = e / H, k = e - c * H;
+    const TC* x = xs + c * ls;
+    // X_k = (slot k, slot N-k); X_{H-k} = (slot H-k, slot H+k); k = 0: X_0, X_H real
+    za[c * lsc + k] = pre_own_per(x[k], k ? x[N - k] : TC(0), x[H - k], k ? x[H + k] : TC(0),
+                                  Tb.tN[k]);
+  }
+  __syncthreads();
+  const TC* er = reinterpret_cast<const TC*>(
+      fft_lds_mixed<TC, true>(za, reinterpret_cast<cplx<TC>*>(s1), lsc, C, H, A, tid, nthr));
+  for (int e = tid; e < C * N; e += nthr) {
+    int c, i;
+    split_e(e, &c, &i);
+    const int64_t p = gidx(c, i);
+    if (p < 0) continue;
+    const TC v = er[c * ls + i] * A.outscale;
+    if (ST == ST_ACCUM)
+      reinterpret_cast<double*>(A.out)[p] = A.rphi[p] + (double)v;
+    else
+      out[p] = (TO)v;
+  }
+}
+
 // ---- deterministic mean ----------------------------------------------------
 __global__ void __launch_bounds__(256) partial_sum_f64(const double* __restrict__ x, int64_t n,
                                                        double* __restrict__ part,
@@ -677,8 +807,37 @@ int launch_pass(const pc_plan* P, int axis, const TI* in, TO* out, const AxisTab
       return rad_launch<TC, TI, TO, OP, LD, ST, true>(A, key, dim3(ntile), dim3(C * T), lds, s);
     return rad_launch<TC, TI, TO, OP, LD, ST, false>(A, key, dim3(ntile), dim3(C * T), lds, s);
   }
-  if (P->bc[axis] == PC_BC_PERIODIC)
-    return fail(PC_ERR_UNSUPPORTED_SIZE, "a periodic axis needs at least 32 cells");
+  if (P->bc[axis] == PC_BC_PERIODIC) {
+    // packed real DFT on the mixed-radix kernel (short or not a power of two)
+    A.nrad = generic_radices(H, A.rad);
+    if (A.nrad < 0) return fail(PC_ERR_UNSUPPORTED_SIZE, "transform length has too many factors");
+    A.pad = 2;
+    const size_t per_line = (size_t)3 * (A.N + A.pad) * sizeof(TC);
+    const int cmax = (int)std::max<size_t>(1, (size_t)lds_limit() / per_line);
+    int C = 1;
+    const int want = axis == 0 ? std::max(1, 2048 / A.N) : (int)(128 / sizeof(TC));
+    while (2 * C <= std::min(want, cmax)) C <<= 1;
+    if ((size_t)C * per_line > (size_t)lds_limit())
+      return fail(PC_ERR_UNSUPPORTED_SIZE, "transform line does not fit in LDS");
+    A.C = C;
+    int64_t ntile;
+    if (axis == 0) {
+      ntile = (lines + C - 1) / C;
+    } else {
+      A.tx = (P->n[0] + C - 1) / C;
+      ntile = (int64_t)A.tx * (lines / P->n[0]);
+    }
+    int nthr = std::min(1024, std::max(64, C * H / 2));
+    nthr = (nthr + 63) / 64 * 64;
+    const size_t lds = (size_t)C * per_line;
+    const void* fn = (const void*)rdft_lines<TC, TI, TO, OP, LD, ST>;
+    if (lds > 65536)
+      PC_HIP_CHECK(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL((rdft_lines<TC, TI, TO, OP, LD, ST>), dim3((unsigned)ntile), dim3(nthr), lds,
+                       s, A);
+    PC_HIP_CHECK(hipGetLastError());
+    return PC_OK;
+  }
   A.nrad = generic_radices(H, A.rad);
   if (A.nrad < 0) return fail(PC_ERR_UNSUPPORTED_SIZE, "transform length has too many factors");
   int C, nthr, B;

@@ -104,7 +104,7 @@ __global__ void __launch_bounds__(TPB) k_div_near(const int32_t* __restrict__ ne
 struct BlockOffsets {
   int32_t off[PC_MAX_K_NODE];  // flat offset of block entry o from the low corner
   int32_t n0, n1, n2, m;       // grid and block shape, for blocks that wrap
-  int32_t l0, l1;              // log2 n0, log2 n1 (the plan's n are powers of two)
+  int32_t l0, l1;              // log2 n0, log2 n1, or -1 when n0 or n1 is not a power of two
   int32_t per;                 // bit a set: axis a is periodic
 };
 
@@ -117,9 +117,17 @@ struct BlockWrap {
 };
 
 __device__ __forceinline__ BlockWrap block_wrap(int64_t c0, const BlockOffsets& bo) {
-  const int i0 = (int)(c0 & (bo.n0 - 1));
-  const int j0 = (int)((c0 >> bo.l0) & (bo.n1 - 1));
-  const int k0 = (int)(c0 >> (bo.l0 + bo.l1));
+  int i0, j0, k0;
+  if (bo.l0 >= 0) {
+    i0 = (int)(c0 & (bo.n0 - 1));
+    j0 = (int)((c0 >> bo.l0) & (bo.n1 - 1));
+    k0 = (int)(c0 >> (bo.l0 + bo.l1));
+  } else {
+    const int64_t r = c0 / bo.n0;
+    i0 = (int)(c0 - r * bo.n0);
+    k0 = (int)(r / bo.n1);
+    j0 = (int)(r - (int64_t)k0 * bo.n1);
+  }
   BlockWrap w;
   w.tx = (bo.per & 1) ? bo.n0 - i0 : bo.m;
   w.ty = (bo.per & 2) ? bo.n1 - j0 : bo.m;
@@ -503,8 +511,9 @@ BlockOffsets block_offsets(const pc_geom* g) {
   bo.n1 = g->n[1];
   bo.n2 = g->d == 3 ? g->n[2] : 1;
   bo.m = m;
-  bo.l0 = __builtin_ctz((unsigned)bo.n0);
-  bo.l1 = __builtin_ctz((unsigned)bo.n1);
+  const bool p2 = (bo.n0 & (bo.n0 - 1)) == 0 && (bo.n1 & (bo.n1 - 1)) == 0;
+  bo.l0 = p2 ? __builtin_ctz((unsigned)bo.n0) : -1;
+  bo.l1 = p2 ? __builtin_ctz((unsigned)bo.n1) : -1;
   bo.per = g->per;
   return bo;
 }

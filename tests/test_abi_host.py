@@ -35,7 +35,7 @@ def test_library_exports_every_declared_symbol():
 def test_host_side_validation():
     from paper_2304_14690_amd import pcorr
     lib = pcorr.lib()
-    assert lib.pc_version() == 110
+    assert lib.pc_version() == 111
     out = ctypes.c_void_p()
     n = (ctypes.c_int32 * 3)(64, 64, 1)
     h = (ctypes.c_double * 3)(1 / 64, 1 / 64, 1.0)
@@ -51,18 +51,18 @@ def test_host_side_validation():
     assert lib.pc_wls_build(None, None, None, 0, None, None, ctypes.byref(out)) == \
         pcorr.PC_ERR_INVALID_ARG
     assert lib.pc_plan_destroy(None) == pcorr.PC_OK
-    # per-axis conditions: unknown codes, and periodic axes below 32 cells
+    # per-axis conditions: unknown codes, and an odd periodic axis
     bc = (ctypes.c_int32 * 3)(pcorr.PC_BC_PERIODIC, 7, 0)
     assert lib.pc_plan_create_ex(2, n, h, bc, 0, 0, None, ctypes.byref(out)) == \
         pcorr.PC_ERR_INVALID_ARG
     assert lib.pc_plan_create_ex(2, n, h, None, 5, 0, None, ctypes.byref(out)) == \
         pcorr.PC_ERR_INVALID_ARG
     assert "eig" in pcorr.last_error()
-    small = (ctypes.c_int32 * 3)(16, 64, 1)
+    odd = (ctypes.c_int32 * 3)(401, 64, 1)
     bc = (ctypes.c_int32 * 3)(pcorr.PC_BC_PERIODIC, pcorr.PC_BC_NEUMANN, 0)
-    assert lib.pc_plan_create_ex(2, small, h, bc, 0, 0, None, ctypes.byref(out)) == \
+    assert lib.pc_plan_create_ex(2, odd, h, bc, 0, 0, None, ctypes.byref(out)) == \
         pcorr.PC_ERR_UNSUPPORTED_SIZE
-    assert "periodic" in pcorr.last_error()
+    assert "even" in pcorr.last_error()
     # grid placement: unknown codes, vertex grids with a periodic axis or too short
     assert lib.pc_plan_create_ex(2, n, h, None, 0, 7, None, ctypes.byref(out)) == \
         pcorr.PC_ERR_INVALID_ARG

@@ -98,5 +98,7 @@ def test_mixed_radix_plan_rules(pc):
         pc.Plan(2, (401, 402), (1.0, 1.0))
     assert e.value.code == pc.PC_ERR_UNSUPPORTED_SIZE
     with pytest.raises(pc.PcError) as e:
-        pc.Plan(2, (400, 64), (1.0, 1.0), bc=("neumann", "periodic"))
-    assert e.value.code == pc.PC_ERR_UNSUPPORTED_SIZE
+        pc.Plan(2, (400, 66), (1.0, 1.0), bc=("neumann", "periodic"), grid="vertex")
+    assert e.value.code == pc.PC_ERR_INVALID_ARG
+    # a periodic axis of any even length beside a mixed-radix one
+    pc.Plan(2, (400, 64), (1.0, 1.0), bc=("neumann", "periodic"))

@@ -74,8 +74,14 @@ def gpu_geom(pc, c, bc, want_f32=False):
 
 @pytest.mark.parametrize("name", list(CASES))
 def test_periodic_stencils_match_oracle(pc, name):
+    check_stencils(pc, *case(name), name)
+
+
+def check_stencils(pc, c, bc, grid, st, name):
+    """Exported GPU stencils against the oracle's: grid index sets bit-exact
+    (the export sorts by index), node blocks and wrap marks exact,
+    coefficients to 1e-12; at least one block must wrap."""
     import torch
-    c, bc, grid, st = case(name)
     plan, geom = gpu_geom(pc, c, bc)
     G, M, d = grid.G, c.M, c.d
     gi = torch.empty((geom.k_grid, G), dtype=torch.int32, device="cuda")
@@ -114,8 +120,12 @@ def test_periodic_stencils_match_oracle(pc, name):
 
 @pytest.mark.parametrize("name", list(CASES))
 def test_periodic_transfers_match_oracle(pc, name):
+    check_transfers(pc, *case(name))
+
+
+def check_transfers(pc, c, bc, grid, st):
+    """The divergence and gradient transfers against the oracle's, 1e-12."""
     import torch
-    c, bc, grid, st = case(name)
     plan, geom = gpu_geom(pc, c, bc)
     rng = np.random.Generator(np.random.PCG64(5))
     v = rng.normal(size=(c.d, c.M))
