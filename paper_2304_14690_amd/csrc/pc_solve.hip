@@ -674,6 +674,9 @@ int pass_radix(const pc_plan* P, int axis) {
   const int64_t lines = P->G / N;
   const int64_t t16 = N / 32;  // threads per line with 16 values each
   const int64_t waves16 = (lines * t16 + 63) / 64;
+  // the fused pass of the last axis holds twice the data of the others:
+  // radix 8 keeps it within 128 registers
+  if (axis == P->d - 1) return 8;
   return waves16 < 4 * 1024 ? 8 : 16;
 }
 
@@ -712,6 +715,11 @@ int launch_pass(const pc_plan* P, int axis, const TI* in, TO* out, const AxisTab
   A.lscale = (TC)sigma;
   A.rscale = sigma;
   A.lamc = (TC)(-4.0 / (P->h[axis] * P->h[axis]));
+  {
+    const double L = (double)P->n[axis] * P->h[axis];
+    const double w = (P->bc[axis] == PC_BC_PERIODIC ? 2.0 : 1.0) * 3.14159265358979323846 / L;
+    A.lams = (TC)(-(w * w));
+  }
   A.in = in;
   A.out = out;
   A.rb = rb;

@@ -59,9 +59,9 @@ struct LineArgs {
   int axis;             // 0, 1, 2
   int d;
   int perm;             // bit a set: axis a is periodic (residual wrap-around)
-  int own_table;        // FDI: take this axis's eigenvalues from tab.lam (by
-                        // slot) instead of computing them from the shift
-                        // twiddles (pseudo-spectral eigenvalues)
+  int own_table;        // pseudo-spectral eigenvalues: the generic kernels read
+                        // them from tab.lam by slot, the register kernel's FDI
+                        // computes lams * m^2 for the slot's mode m
   int32_t n0, n1, n2;
   int64_t lines;        // lines along this axis (vertex-grid kernel: masking)
   double ih2[3];        // 1/h^2 (residual)
@@ -72,6 +72,8 @@ struct LineArgs {
   TC outscale;          // store scale
   TC lscale;            // FDI: eigenvalues are multiplied by this (sigma)
   TC lamc;              // FDI: -4 / h^2 of this axis
+  TC lams;              // FDI, pseudo-spectral: -(pi / L)^2 (cosine axis) or
+                        // -(2 pi / L)^2 (periodic axis), L = n h
   double rscale;        // residual: r = b - rscale * lap_h phi
   double* bmean;        // FDI: receives X(0)/prod(2N_a) from the zero line
   double meannorm;
@@ -517,9 +519,12 @@ __device__ __forceinline__ int xpad(int r) { return r + 2 * (r >> 5); }
 // Both leave the line's modes in slots whose 1D eigenvalue is a function of
 // the slot index (see the FDI step), so the passes of different axes
 // combine freely.
+// Radix 8 asks for four wavefronts per SIMD (at most 128 VGPRs), which the
+// float64 fused pass would otherwise exceed by a few registers.
 template <typename TC, typename TI, typename TO, int OP, int LD, int ST, int LOGH, int RT,
           bool PER>
-__global__ void __launch_bounds__(512) dct_rad(LineArgs<TC> A) {
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(RT == 8 ? 4 : 1)))
+dct_rad(LineArgs<TC> A) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   if (A.skip && *A.skip) return;
   constexpr int H = 1 << LOGH;
@@ -708,20 +713,28 @@ __global__ void __launch_bounds__(512) dct_rad(LineArgs<TC> A) {
         // sin(pi k/2N) = -Im w4, cos = Re w4, and slot H (k = 0) has
         // sin^2 = 1/2.  Real DFT: slots k and N-k both hold mode k, of
         // eigenvalue -(4/h^2) sin^2(pi k / N) = -(4/h^2) 4 sin^2 cos^2 of
-        // pi k / (2N), and slot H (k = 0) has sin^2 = 1.  Pseudo-spectral
-        // eigenvalues come from the axis table by slot.
-        TC e_a, e_b;  // this axis's eigenvalues of the two slots
-        if (A.own_table) {
-          e_a = Tb.lam[k];
-          e_b = Tb.lam[k ? N - k : H];
-        } else if (PER) {
-          const TC sc2 = TC(2) * w4.re * w4.im;
-          e_a = lc * (sc2 * sc2);
-          e_b = k ? e_a : lc;
+        // pi k / (2N), and slot H (k = 0) has sin^2 = 1.  Pseudo-spectral:
+        // lams m^2 for the slot's mode m (slot k: mode k; slot N-k: mode N-k
+        // on a cosine axis, k on a periodic one; slot H: mode H).  Both are
+        // scale * s^2 with per-slot s, picked by selects: a branch per slot
+        // (or per-slot table loads) costs the kernel half its occupancy.
+        const bool own = A.own_table;
+        TC sa, sb;
+        if (PER) {
+          sa = TC(2) * w4.re * w4.im;
+          sb = sa;
         } else {
-          e_a = lc * (w4.im * w4.im);
-          e_b = lc * (k ? w4.re * w4.re : TC(0.5));
+          sa = w4.im;
+          sb = w4.re;
         }
+        if (own) {
+          sa = (TC)k;
+          sb = (TC)(PER ? k : N - k);
+        }
+        const TC scale = own ? A.lams : lc;
+        const TC e_a = scale * (sa * sa);
+        TC e_b = scale * (sb * sb);
+        if (k == 0) e_b = own ? A.lams * (TC(H) * TC(H)) : (PER ? lc : lc * TC(0.5));
         TC l_a = (rest + e_a) * ls_;
         TC l_b = (rest + e_b) * ls_;
         if (k == 0) x0 = xa;
@@ -764,11 +777,16 @@ __global__ void __launch_bounds__(512) dct_rad(LineArgs<TC> A) {
       zr[xpad(k ? N - k : H)] = yb[q];
     }
     line_sync<T>();
+    // opaque copies of the base twiddles: the compiler would otherwise keep
+    // the forward split's 2 RT twiddle products live through the division
+    // and exchange (twice the registers of the data) instead of redoing them
+    cplx<TC> tNi = tNb, t4i = t4b;
+    asm volatile("" : "+v"(tNi.re), "+v"(tNi.im), "+v"(t4i.re), "+v"(t4i.im));
 #pragma unroll
     for (int q = 0; q < RT; ++q) {
       const int k = t + T * q;
-      const cplx<TC> wN = q ? cmul(tNb, ldu(Tb.tN + T * q)) : tNb;
-      const cplx<TC> w4 = q ? cmul(t4b, ldu(Tb.t4N + T * q)) : t4b;
+      const cplx<TC> wN = q ? cmul(tNi, ldu(Tb.tN + T * q)) : tNi;
+      const cplx<TC> w4 = q ? cmul(t4i, ldu(Tb.t4N + T * q)) : t4i;
       TC xhk = zr[xpad(H - k)];
       TC xhpk = zr[xpad(H + k)];
       if (PER)
@@ -821,10 +839,20 @@ __global__ void __launch_bounds__(512) dct_rad(LineArgs<TC> A) {
   // inverse half-length FFT, then unpack v -> x.  Opaque copies of the
   // thread index and LDS base keep the compiler from carrying the forward
   // FFT's address arithmetic live into this second FFT.
-  int ti = t;
-  cplx<TC>* zi = z;
+  if constexpr (OP == OP_FDI) {
+    // opaque twiddle state: otherwise the forward FFT's twiddle powers stay
+    // live through the division for reuse (as conjugates) in the inverse,
+    // which halves the occupancy
+    asm volatile("" : "+v"(tw.w1.re), "+v"(tw.w1.im), "+v"(tw.w4.re), "+v"(tw.w4.im));
+    asm volatile("" : "+v"(tw.fin.re), "+v"(tw.fin.im));
+    asm volatile("" : "+v"(tw8.s1.re), "+v"(tw8.s1.im), "+v"(tw8.s2.re), "+v"(tw8.s2.im));
+    asm volatile("" : "+v"(tw8.fin.re), "+v"(tw8.fin.im));
+  }
+  int ti = t, zoff = c * LS;
   asm volatile("" : "+v"(ti));
-  asm volatile("" : "+v"(zi));
+  asm volatile("" : "+v"(zoff));
+  // from the LDS base itself, so that the accesses stay LDS instructions
+  cplx<TC>* zi = reinterpret_cast<cplx<TC>*>(smem_raw) + zoff;
   rad_fft<TC, true, LOGH, RT>(a, ti, tw, tw8, Tb.twH, zi);
   const TC sc = A.outscale;
   // The stores hit the same addresses as the loads; opaque copies of the
