@@ -208,7 +208,8 @@ int pc_plan_create(int d, const int32_t* n, const double* h, void* stream, pc_pl
  *     eigenvalues are -(4/h^2) sin^2(pi k / (2(n - 1))) (pseudo-spectral:
  *     -(pi k / ((n - 1) h))^2).  The operator is symmetric in the trapezoid
  *     weights (1/2 at the end points of each axis): bmean is the weighted
- *     mean and phi has zero weighted mean.  PC_MIXED is refused.  The WLS
+ *     mean and phi has zero weighted mean; PC_MIXED evaluates its float64
+ *     residual with the same mirror and removes weighted means.  The WLS
  *     stencils of pc_wls_build use the same placement. */
 int pc_plan_create_ex(int d, const int32_t* n, const double* h, const int32_t* bc, int32_t eig,
                       int32_t grid, void* stream, pc_plan** out);

@@ -382,7 +382,6 @@ int pc_poisson_fft_solve(const pc_plan* P, int mode, const void* b, void* phi, i
   if (b == phi) return fail(PC_ERR_INVALID_ARG, "PC_MIXED needs b and phi to be distinct");
   if (P->eig != PC_EIG_FD2)
     return fail(PC_ERR_INVALID_ARG, "PC_MIXED needs the central-difference eigenvalues");
-  if (P->vertex) return fail(PC_ERR_INVALID_ARG, "PC_MIXED needs the cell-centred grid");
   if (ws && ws->mode != PC_MIXED)
     return fail(PC_ERR_INVALID_ARG, "PC_MIXED needs a workspace created for PC_MIXED");
   PC_TRY(ensure_plan_ws(P, &ws));

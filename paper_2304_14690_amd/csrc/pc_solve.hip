@@ -570,6 +570,33 @@ __global__ void __launch_bounds__(256) partial_sum_f64(const double* __restrict_
   if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
 
+// The same partial sums with the trapezoid weights of a vertex grid: each
+// axis weighs its two end points by 1/2 (the zero mode of the DCT-I).
+__global__ void __launch_bounds__(256) partial_wsum_f64(const double* __restrict__ x, int64_t n,
+                                                        int32_t n0, int32_t n1, int32_t n2,
+                                                        double* __restrict__ part,
+                                                        const int32_t* __restrict__ skip) {
+  __shared__ double red[256];
+  if (skip && *skip) return;
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    const int64_t r = i / n0;
+    const int a = (int)(i - r * n0), b = (int)(r % n1), c = (int)(r / n1);
+    double w = 1.0;
+    if (a == 0 || a == n0 - 1) w *= 0.5;
+    if (b == 0 || b == n1 - 1) w *= 0.5;
+    if (n2 > 1 && (c == 0 || c == n2 - 1)) w *= 0.5;
+    acc += w * x[i];
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
 __global__ void __launch_bounds__(256) finish_mean(const double* __restrict__ part, int nblk,
                                                    double scale, double* __restrict__ out,
                                                    const int32_t* __restrict__ skip) {
@@ -749,7 +776,7 @@ int launch_pass(const pc_plan* P, int axis, const TI* in, TO* out, const AxisTab
                       : (P->bc[a] == PC_BC_PERIODIC ? 1.0 : 2.0) * P->n[a];
   A.meannorm = 1.0 / norm;
   A.own_table = P->eig == PC_EIG_SPECTRAL;
-  A.perm = 0;
+  A.perm = P->vertex ? PERM_VERTEX : 0;
   for (int a = 0; a < P->d; ++a)
     if (P->bc[a] == PC_BC_PERIODIC) A.perm |= 1 << a;
   int64_t lines = P->G / A.N;
@@ -946,6 +973,21 @@ int mean_f64(const double* x, int64_t n, double* partial, int nblk, double* out_
   return PC_OK;
 }
 
+// Mean of a grid field: plain on a cell-centred grid, trapezoid-weighted
+// (the DCT-I zero mode) on a vertex grid.
+int grid_mean_f64(const pc_plan* P, const double* x, double* partial, int nblk, double* out_dev,
+                  hipStream_t s, const int32_t* skip) {
+  if (!P->vertex) return mean_f64(x, P->G, partial, nblk, out_dev, s, skip);
+  double wsum = 1.0;
+  for (int a = 0; a < P->d; ++a) wsum *= (double)(P->n[a] - 1);
+  hipLaunchKernelGGL(partial_wsum_f64, dim3(nblk), dim3(256), 0, s, x, P->G, P->n[0], P->n[1],
+                     P->d == 3 ? P->n[2] : 1, partial, skip);
+  hipLaunchKernelGGL(finish_mean, dim3(1), dim3(256), 0, s, partial, nblk, 1.0 / wsum, out_dev,
+                     skip);
+  PC_HIP_CHECK(hipGetLastError());
+  return PC_OK;
+}
+
 int solve_f64(const pc_plan* P, const double* b, double* phi, double* bmean_dev, pc_workspace*,
               hipStream_t s, double sigma, const int32_t* skip) {
   return solve_passes<double, double, double, LD_PLAIN, ST_PLAIN>(
@@ -958,7 +1000,8 @@ int solve_f32(const pc_plan* P, const float* b, float* phi, double* bmean_dev, p
       P, P->ax32, b, phi, phi, nullptr, nullptr, bmean_dev, s, nullptr, sigma, skip);
 }
 
-// Defect correction: bbar = mean(b) in float64; phi0 = S32(b - bbar); then
+// Defect correction (means trapezoid-weighted on a vertex grid): bbar =
+// mean(b) in float64; phi0 = S32(b - bbar); then
 // `sweeps` times r = (b - bbar) - lap_h phi (float64, fused into the first
 // pass), phi += S32(r) (accumulated in float64 in the last pass); finally
 // mean(phi) is removed in float64.  The mean is taken out in float64 before
@@ -969,14 +1012,14 @@ int solve_mixed(const pc_plan* P, const double* b, double* phi, int sweeps, doub
   if (!ws || !ws->w32) return fail(PC_ERR_INVALID_ARG, "mixed solve needs a MIXED workspace");
   float* w = ws->w32;
   double* bm = bmean_dev ? bmean_dev : ws->scal;
-  PC_TRY(mean_f64(b, P->G, ws->partial, ws->nblk, bm, s, skip));
+  PC_TRY(grid_mean_f64(P, b, ws->partial, ws->nblk, bm, s, skip));
   PC_TRY((solve_passes<float, double, double, LD_PLAIN, ST_PLAIN>(
       P, P->ax32, b, phi, w, nullptr, nullptr, nullptr, s, bm, sigma, skip)));
   for (int it = 0; it < sweeps; ++it) {
     PC_TRY((solve_passes<float, double, double, LD_RESID, ST_ACCUM>(
         P, P->ax32, b, phi, w, b, phi, nullptr, s, bm, sigma, skip)));
   }
-  PC_TRY(mean_f64(phi, P->G, ws->partial, ws->nblk, ws->scal + 3, s, skip));
+  PC_TRY(grid_mean_f64(P, phi, ws->partial, ws->nblk, ws->scal + 3, s, skip));
   int nb = (int)std::min<int64_t>(8192, (P->G + 255) / 256);
   hipLaunchKernelGGL(sub_scalar_f64, dim3(nb), dim3(256), 0, s, phi, P->G,
                      (const double*)(ws->scal + 3), skip);

@@ -38,6 +38,7 @@ __device__ __forceinline__ cplx<T> conj_(cplx<T> a) { return {a.re, -a.im}; }
 __device__ __forceinline__ int mk_pos(int n, int N) { return (n & 1) ? (N - 1 - (n >> 1)) : (n >> 1); }
 
 enum { OP_FWD = 0, OP_INV = 1, OP_FDI = 2 };
+constexpr int PERM_VERTEX = 8;  // LineArgs::perm flag of a vertex grid
 enum { LD_PLAIN = 0, LD_RESID = 1 };
 enum { ST_PLAIN = 0, ST_ACCUM = 1 };
 
@@ -58,7 +59,8 @@ struct LineArgs {
   int tx;               // tiles along x (strided axes)
   int axis;             // 0, 1, 2
   int d;
-  int perm;             // bit a set: axis a is periodic (residual wrap-around)
+  int perm;             // bit a set: axis a is periodic (residual wrap-around);
+                        // PERM_VERTEX: vertex grid (mirror about the end vertex)
   int own_table;        // pseudo-spectral eigenvalues: the generic kernels read
                         // them from tab.lam by slot, the register kernel's FDI
                         // computes lams * m^2 for the slot's mode m
@@ -98,8 +100,9 @@ __device__ __forceinline__ int64_t line_base(const LineArgs<TC>& A, int t, int c
 }
 
 // The float64 residual r = b - rscale * lap_h phi at cell (i, j, k) of flat
-// index p.  Neumann axes take the mirror ghost (phi_{-1} = phi_0), periodic
-// axes (bit a of perm) wrap around.  Each neighbour's address is selected
+// index p.  Neumann axes take the mirror ghost (phi_{-1} = phi_0, or
+// phi_{-1} = phi_1 on a vertex grid), periodic axes (bit a of perm) wrap
+// around.  Each neighbour's address is selected
 // first (the ghost re-reads the cell itself), so all loads are
 // unconditional and in flight together.
 __device__ __forceinline__ double resid_ijk(const double* __restrict__ b,
@@ -108,16 +111,20 @@ __device__ __forceinline__ double resid_ijk(const double* __restrict__ b,
                                             int32_t n2, int perm, const double* ih2,
                                             double rscale) {
   const int64_t s1 = n0, s2 = (int64_t)n0 * n1;
-  const int64_t pxm = i > 0 ? p - 1 : ((perm & 1) ? p + (n0 - 1) : p);
-  const int64_t pxp = i < n0 - 1 ? p + 1 : ((perm & 1) ? p - (n0 - 1) : p);
-  const int64_t pym = j > 0 ? p - s1 : ((perm & 2) ? p + (n1 - 1) * s1 : p);
-  const int64_t pyp = j < n1 - 1 ? p + s1 : ((perm & 2) ? p - (n1 - 1) * s1 : p);
+  // past a face: the wrapped point (periodic axis), the point itself
+  // (cell-centred mirror ghost) or the first interior point (mirror about
+  // the end vertex of a vertex grid, PERM_VERTEX)
+  const int64_t vx = (perm & PERM_VERTEX) ? 1 : 0;
+  const int64_t pxm = i > 0 ? p - 1 : ((perm & 1) ? p + (n0 - 1) : p + vx);
+  const int64_t pxp = i < n0 - 1 ? p + 1 : ((perm & 1) ? p - (n0 - 1) : p - vx);
+  const int64_t pym = j > 0 ? p - s1 : ((perm & 2) ? p + (n1 - 1) * s1 : p + vx * s1);
+  const int64_t pyp = j < n1 - 1 ? p + s1 : ((perm & 2) ? p - (n1 - 1) * s1 : p - vx * s1);
   const double c = phi[p];
   const double xm = phi[pxm], xp = phi[pxp], ym = phi[pym], yp = phi[pyp];
   double lap = ((xp - c) - (c - xm)) * ih2[0] + ((yp - c) - (c - ym)) * ih2[1];
   if (d == 3) {
-    const int64_t pzm = k > 0 ? p - s2 : ((perm & 4) ? p + (n2 - 1) * s2 : p);
-    const int64_t pzp = k < n2 - 1 ? p + s2 : ((perm & 4) ? p - (n2 - 1) * s2 : p);
+    const int64_t pzm = k > 0 ? p - s2 : ((perm & 4) ? p + (n2 - 1) * s2 : p + vx * s2);
+    const int64_t pzp = k < n2 - 1 ? p + s2 : ((perm & 4) ? p - (n2 - 1) * s2 : p - vx * s2);
     const double zm = phi[pzm], zp = phi[pzp];
     lap += ((zp - c) - (c - zm)) * ih2[2];
   }
