@@ -22,6 +22,9 @@ Workloads (all inputs seeded and synthetic, resident in HBM before timing):
           whole time steps (the first fractional step of Eq. 3 + the sub-step):
           the first step needs velocity conditions on non-periodic faces,
           which are the caller's, so whole steps are timed without faces.
+  2d400sq the grid of the flow over a square (Sec. 3): 400^2, periodic in x
+          and y, the square [0.45, 0.55]^2, 16-neighbour stencils, 32 modes;
+          also times whole time steps.
   2d1024c the 2d2048 node cloud (the same 4.2M nodes and cylinder) under a
           1024^2 pressure grid: a pressure grid coarser than the velocity
           cloud, the saving Sec. 3 reports (WLS mean spacing = node spacing).
@@ -75,6 +78,11 @@ WORKLOADS = {
                 "bc": ("periodic", "periodic", "periodic"),
                 "desc": "3D 256^3 grid, {M} jittered nodes, sphere r=0.1 at the centre, 27-NN "
                         "WLS, 64-mode velocity, periodic box, cold IB start"},
+    "2d400sq": {"d": 2, "N": 400, "modes": "f64,f32,mixed", "cpu_N": 400,
+                "bc": ("periodic", "periodic"),
+                "desc": "2D 400^2 grid, {M} jittered nodes, square [0.45,0.55]^2 (the "
+                        "flow-over-a-square grid), 16-NN WLS, 32-mode velocity, periodic box, "
+                        "cold IB start"},
     "2d1024c": {"d": 2, "N": 1024, "modes": "f64,f32,mixed", "cpu_N": 512, "nodes_per_axis": 2,
                 "desc": "2D 1024^2 pressure grid under the 2048^2 workload's {M} jittered "
                         "nodes (node spacing 1/2048), cylinder r=0.05 at (0.3,0.5), 16-NN WLS, "
@@ -154,6 +162,11 @@ def make_workload(name, N):
                                     16, 16, 32, 3, 4)
         return {"d": 2, "n": c.n, "h": c.h, "x": c.x, "kind": c.kind, "k": c.k_grid,
                 "u": torch.from_numpy(c.u).cuda(), "bc": None, "delta": 1.0 / (2 * N)}
+    if name == "2d400sq":
+        c = inputs.make_case(name, 2, N, [inputs.Obstacle("box", (0.45, 0.45), (0.55, 0.55))],
+                             16, 16, 32, 3, 4, bc=bc)
+        return {"d": 2, "n": c.n, "h": c.h, "x": c.x, "kind": c.kind, "k": c.k_grid,
+                "u": torch.from_numpy(c.u).cuda(), "bc": bc}
     if name in ("2d2048", "2d2048p", "2d2048pp"):
         c = inputs.make_case(name, 2, N, [inputs.Obstacle("circle", (0.3, 0.5), (0.05,))],
                              16, 16, 32, 3, 4, bc=bc)
@@ -525,6 +538,9 @@ def cpu_baseline(workload, N):
                                     [inputs.Obstacle("circle", (0.3, 0.5), (0.05,))],
                                     16, 16, 32, 3, 4)
         delta = 1.0 / (2 * N)
+    elif workload == "2d400sq":
+        c = inputs.make_case(workload, 2, N, [inputs.Obstacle("box", (0.45, 0.45), (0.55, 0.55))],
+                             16, 16, 32, 3, 4, bc=bc)
     elif workload in ("2d2048", "2d2048p", "2d2048pp"):
         c = inputs.make_case(workload, 2, N, [inputs.Obstacle("circle", (0.3, 0.5), (0.05,))],
                              16, 16, 32, 3, 4, bc=bc)

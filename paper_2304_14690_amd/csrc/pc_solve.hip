@@ -34,15 +34,87 @@ namespace {
 constexpr int ROW_THREADS = 256;
 constexpr int COL_MAX_THREADS = 512;
 
+// n / d for 0 <= n < 2^17 and 0 < d <= 2^16, with rinv = 1.0f / d: the
+// float32 product is within one of the quotient, and one correction step
+// makes it exact (integer division by a runtime divisor costs far more).
+__device__ __forceinline__ int div_small(int n, int d, float rinv) {
+  int q = (int)((float)n * rinv);
+  const int r = n - q * d;
+  if (r < 0) --q;
+  else if (r >= d) ++q;
+  return q;
+}
+
+// DFT of length 3 and 5 (forward exp(-2 pi i / r), inverse the conjugate).
+template <typename TC, bool INV>
+__device__ __forceinline__ void dft3(cplx<TC>* v) {
+  constexpr double S3 = 0.86602540378443864676;  // sin(2 pi / 3)
+  const cplx<TC> t = cadd(v[1], v[2]);
+  const cplx<TC> m = {v[0].re - TC(0.5) * t.re, v[0].im - TC(0.5) * t.im};
+  const cplx<TC> d = {TC(S3) * (v[1].re - v[2].re), TC(S3) * (v[1].im - v[2].im)};
+  const cplx<TC> id = INV ? cplx<TC>{-d.im, d.re} : cplx<TC>{d.im, -d.re};  // -+ i d
+  v[0] = cadd(v[0], t);
+  v[1] = cadd(m, id);
+  v[2] = csub(m, id);
+}
+
+template <typename TC, bool INV>
+__device__ __forceinline__ void dft5(cplx<TC>* v) {
+  constexpr double C1 = 0.30901699437494742410;   // cos(2 pi / 5)
+  constexpr double C2 = -0.80901699437494742410;  // cos(4 pi / 5)
+  constexpr double S1 = 0.95105651629515357212;   // sin(2 pi / 5)
+  constexpr double S2 = 0.58778525229247312917;   // sin(4 pi / 5)
+  const cplx<TC> t1 = cadd(v[1], v[4]), t2 = cadd(v[2], v[3]);
+  const cplx<TC> t3 = csub(v[1], v[4]), t4 = csub(v[2], v[3]);
+  const cplx<TC> a1 = {v[0].re + TC(C1) * t1.re + TC(C2) * t2.re,
+                       v[0].im + TC(C1) * t1.im + TC(C2) * t2.im};
+  const cplx<TC> a2 = {v[0].re + TC(C2) * t1.re + TC(C1) * t2.re,
+                       v[0].im + TC(C2) * t1.im + TC(C1) * t2.im};
+  const cplx<TC> b1 = {TC(S1) * t3.re + TC(S2) * t4.re, TC(S1) * t3.im + TC(S2) * t4.im};
+  const cplx<TC> b2 = {TC(S2) * t3.re - TC(S1) * t4.re, TC(S2) * t3.im - TC(S1) * t4.im};
+  // -+ i b
+  const cplx<TC> ib1 = INV ? cplx<TC>{-b1.im, b1.re} : cplx<TC>{b1.im, -b1.re};
+  const cplx<TC> ib2 = INV ? cplx<TC>{-b2.im, b2.re} : cplx<TC>{b2.im, -b2.re};
+  v[0] = cadd(v[0], cadd(t1, t2));
+  v[1] = cadd(a1, ib1);
+  v[4] = csub(a1, ib1);
+  v[2] = cadd(a2, ib2);
+  v[3] = csub(a2, ib2);
+}
+
+// One Stockham butterfly of compile-time radix R: inputs x[g + nb s],
+// twiddles w^(k s) = twH[tstep k s] (w = exp(-+2 pi i / (L R))), a length-R
+// DFT, outputs y[s' L] (y already offset by (g - k) R + k).
+template <typename TC, bool INV, int R>
+__device__ __forceinline__ void mixed_bfly(const cplx<TC>* x, cplx<TC>* y, int g, int nb, int k,
+                                           int L, int tstep, const cplx<TC>* __restrict__ twH) {
+  cplx<TC> v[R], w[R];
+#pragma unroll
+  for (int s = 0; s < R; ++s) v[s] = x[g + nb * s];
+#pragma unroll
+  for (int s = 1; s < R; ++s) w[s] = twH[tstep * k * s];
+#pragma unroll
+  for (int s = 1; s < R; ++s) v[s] = INV ? cmulc(v[s], w[s]) : cmul(v[s], w[s]);
+  if constexpr (R == 3)
+    dft3<TC, INV>(v);
+  else if constexpr (R == 5)
+    dft5<TC, INV>(v);
+  else
+    dftR<TC, INV, R>(v);
+#pragma unroll
+  for (int s = 0; s < R; ++s) y[s * L] = v[s];
+}
+
 // Mixed-radix Stockham FFT of the C lines held in LDS, for any H whose
 // factors are listed in A.rad (complex view, line c at a + c*lsc; b is a
 // second buffer of the same shape).  The stage of radix r after the stages
-// of combined length L produces output p of a line as
-//   s' = (p / L) mod r,  k = p mod L,  j = (p / (L r)) L + k,
-//   out[p] = sum_{s<r} in[j + (H/r) s] w^(s (k + L s')),  w = exp(-+2 pi i / (L r)),
-// a direct sum over the radix (so a prime factor such as 67 costs r terms per
-// output), with w^e = twH[(H / (L r)) e].  Returns the buffer holding the
-// result (the stages alternate between a and b).
+// of combined length L takes butterfly g (k = g mod L) of each line:
+//   v_s = in[g + (H/r) s] w^(k s),  w = exp(-+2 pi i / (L r)),
+//   out[(g - k) r + k + s' L] = sum_{s<r} v_s exp(-+2 pi i s s' / r),
+// with w^e = twH[(H / (L r)) e]; radices 2, 3, 4, 5 and 8 have their own
+// butterflies, any other prime factor (7, 67, ...) a direct sum of r terms
+// per output.  Returns the buffer holding the result (the stages alternate
+// between a and b).
 template <typename TC, bool INV>
 __device__ cplx<TC>* fft_lds_mixed(cplx<TC>* a, cplx<TC>* b, int lsc, int C, int H,
                                    const LineArgs<TC>& A, int tid, int nthr) {
@@ -53,22 +125,36 @@ __device__ cplx<TC>* fft_lds_mixed(cplx<TC>* a, cplx<TC>* b, int lsc, int C, int
     const int nb = H / r;
     const int Lr = L * r;
     const int tstep = H / Lr;
-    for (int e = tid; e < C * H; e += nthr) {
-      const int c = e / H, p = e - c * H;
-      const int sp = (p / L) % r, k = p % L;
-      const int j = (p / Lr) * L + k;
-      const int q = k + L * sp;
+    const float rnb = 1.0f / (float)nb, rL = 1.0f / (float)L;
+    for (int e = tid; e < C * nb; e += nthr) {
+      const int c = div_small(e, nb, rnb);
+      const int g = e - c * nb;
+      const int k = g - L * div_small(g, L, rL);
       const cplx<TC>* x = a + c * lsc;
-      cplx<TC> acc = x[j];
-      int ex = 0;
-      for (int sidx = 1; sidx < r; ++sidx) {
-        ex += q;
-        if (ex >= Lr) ex -= Lr;
-        const cplx<TC> w = twH[tstep * ex];
-        const cplx<TC> v = x[j + nb * sidx];
-        acc = cadd(acc, INV ? cmulc(v, w) : cmul(v, w));
+      cplx<TC>* y = b + c * lsc + (g - k) * r + k;
+      switch (r) {
+        case 2: mixed_bfly<TC, INV, 2>(x, y, g, nb, k, L, tstep, twH); break;
+        case 3: mixed_bfly<TC, INV, 3>(x, y, g, nb, k, L, tstep, twH); break;
+        case 4: mixed_bfly<TC, INV, 4>(x, y, g, nb, k, L, tstep, twH); break;
+        case 5: mixed_bfly<TC, INV, 5>(x, y, g, nb, k, L, tstep, twH); break;
+        case 8: mixed_bfly<TC, INV, 8>(x, y, g, nb, k, L, tstep, twH); break;
+        default: {
+          // direct sum: output s' takes v_s W_r^(s s'), W_r^m = twH[nb (m mod r)]
+          for (int sp = 0; sp < r; ++sp) {
+            cplx<TC> acc = x[g];
+            int ex = 0;            // (k + L s') s mod Lr, as in the twiddled DFT
+            const int q = k + L * sp;
+            for (int sidx = 1; sidx < r; ++sidx) {
+              ex += q;
+              if (ex >= Lr) ex -= Lr;
+              const cplx<TC> w = twH[tstep * ex];
+              const cplx<TC> v = x[g + nb * sidx];
+              acc = cadd(acc, INV ? cmulc(v, w) : cmul(v, w));
+            }
+            y[sp * L] = acc;
+          }
+        }
       }
-      b[c * lsc + p] = acc;
     }
     __syncthreads();
     cplx<TC>* t = a;
@@ -643,11 +729,39 @@ int lds_limit() {
   return g_lds_limit;
 }
 
+int g_cu_count = 0;
+
+int cu_count() {
+  if (g_cu_count == 0) {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        v <= 0)
+      v = 256;
+    g_cu_count = v;
+  }
+  return g_cu_count;
+}
+
+// Halves the lines per tile of a generic-kernel pass while the pass would
+// give the device fewer than two workgroups per compute unit: on small grids
+// (the 400 x 400 grids of Sec. 3) one or two lines per group fill the device
+// better than 128-byte row segments, and their data sits in the caches.
+// `tiles` is the tile count at C; halving C keeps C a divisor of the counts.
+int fill_device(int C, int64_t tiles) {
+  const int64_t want = 2 * (int64_t)cu_count();
+  while (C > 1 && tiles < want) {
+    C >>= 1;
+    tiles *= 2;
+  }
+  return C;
+}
+
 // Chooses lines per tile and threads for one pass of the generic kernel
 // (two LDS buffers of C lines; C a power of two that divides lines_x, the
 // row count or the x extent).
 template <typename TC>
-void tile_shape(int axis, int N, int lines_x, int* C, int* nthr, int* B) {
+void tile_shape(int axis, int N, int lines_x, int64_t groups, int* C, int* nthr, int* B) {
   const int H = N / 2;
   const int lim = lds_limit();
   int c;
@@ -660,6 +774,7 @@ void tile_shape(int axis, int N, int lines_x, int* C, int* nthr, int* B) {
   }
   while (c > 1 && (c > lines_x || lines_x % c)) c >>= 1;
   while (c > 1 && (size_t)c * N * sizeof(TC) * 2 > (size_t)lim) c >>= 1;
+  c = fill_device(c, (int64_t)(lines_x / c) * groups);
   int want = c * H / 4;
   if (want < 64) want = 64;
   int t = want > 1024 ? 1024 : want;
@@ -675,11 +790,11 @@ void tile_shape(int axis, int N, int lines_x, int* C, int* nthr, int* B) {
 // Complex values per thread of the transforms along `axis`: 16, or 8 when
 // the pass has too few lines to give the device four wavefronts per SIMD
 // with 16 (a 2D grid; small 3D grids), which doubles the wavefronts.
-// Radices of the generic kernel's FFT of half length H: fours, a two,
-// then the odd primes.
+// Radices of the generic kernel's FFT of half length H: eights, then a four
+// or a two, then the odd primes.
 int generic_radices(int H, int* rad) {
   int n = 0;
-  for (int r : {4, 2}) {
+  for (int r : {8, 4, 2}) {
     while (H % r == 0 && H > 1 && n < 24) {
       rad[n++] = r;
       H /= r;
@@ -794,6 +909,8 @@ int launch_pass(const pc_plan* P, int axis, const TI* in, TO* out, const AxisTab
     int C = 1;
     const int want = axis == 0 ? std::max(1, 2048 / NS) : (int)(128 / sizeof(TC));
     while (2 * C <= std::min(want, cmax)) C <<= 1;
+    C = fill_device(C, axis == 0 ? (lines + C - 1) / C
+                                 : (int64_t)((P->n[0] + C - 1) / C) * (lines / P->n[0]));
     if ((size_t)C * per_line > (size_t)lds_limit())
       return fail(PC_ERR_UNSUPPORTED_SIZE, "transform line does not fit in LDS");
     A.C = C;
@@ -852,6 +969,8 @@ int launch_pass(const pc_plan* P, int axis, const TI* in, TO* out, const AxisTab
     int C = 1;
     const int want = axis == 0 ? std::max(1, 2048 / A.N) : (int)(128 / sizeof(TC));
     while (2 * C <= std::min(want, cmax)) C <<= 1;
+    C = fill_device(C, axis == 0 ? (lines + C - 1) / C
+                                 : (int64_t)((P->n[0] + C - 1) / C) * (lines / P->n[0]));
     if ((size_t)C * per_line > (size_t)lds_limit())
       return fail(PC_ERR_UNSUPPORTED_SIZE, "transform line does not fit in LDS");
     A.C = C;
@@ -877,7 +996,8 @@ int launch_pass(const pc_plan* P, int axis, const TI* in, TO* out, const AxisTab
   if (A.nrad < 0) return fail(PC_ERR_UNSUPPORTED_SIZE, "transform length has too many factors");
   int C, nthr, B;
 
-  tile_shape<TC>(axis, A.N, axis == 0 ? (int)lines : P->n[0], &C, &nthr, &B);
+  tile_shape<TC>(axis, A.N, axis == 0 ? (int)lines : P->n[0], axis == 0 ? 1 : lines / P->n[0],
+                 &C, &nthr, &B);
   A.C = C;
   if (C > nthr) return fail(PC_ERR_UNSUPPORTED_SIZE, "transform tile has more lines than threads");
   int ntile;
