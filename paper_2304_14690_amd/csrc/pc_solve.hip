@@ -913,6 +913,8 @@ int launch_pass(const pc_plan* P, int axis, const TI* in, TO* out, const AxisTab
                                  : (int64_t)((P->n[0] + C - 1) / C) * (lines / P->n[0]));
     if ((size_t)C * per_line > (size_t)lds_limit())
       return fail(PC_ERR_UNSUPPORTED_SIZE, "transform line does not fit in LDS");
+    if ((int64_t)C * NS >= (1 << 17))  // div_small's range (butterfly indices)
+      return fail(PC_ERR_UNSUPPORTED_SIZE, "transform tile too large");
     A.C = C;
     int64_t ntile;
     if (axis == 0) {
@@ -973,6 +975,8 @@ int launch_pass(const pc_plan* P, int axis, const TI* in, TO* out, const AxisTab
                                  : (int64_t)((P->n[0] + C - 1) / C) * (lines / P->n[0]));
     if ((size_t)C * per_line > (size_t)lds_limit())
       return fail(PC_ERR_UNSUPPORTED_SIZE, "transform line does not fit in LDS");
+    if ((int64_t)C * A.N >= (1 << 17))  // div_small's range (butterfly indices)
+      return fail(PC_ERR_UNSUPPORTED_SIZE, "transform tile too large");
     A.C = C;
     int64_t ntile;
     if (axis == 0) {
@@ -1000,6 +1004,8 @@ int launch_pass(const pc_plan* P, int axis, const TI* in, TO* out, const AxisTab
                  &C, &nthr, &B);
   A.C = C;
   if (C > nthr) return fail(PC_ERR_UNSUPPORTED_SIZE, "transform tile has more lines than threads");
+  if ((int64_t)C * A.N >= (1 << 17))  // div_small's range (butterfly indices)
+    return fail(PC_ERR_UNSUPPORTED_SIZE, "transform tile too large");
   int ntile;
   if (axis == 0) {
     ntile = (int)((lines + C - 1) / C);
