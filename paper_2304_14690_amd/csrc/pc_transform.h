@@ -502,6 +502,32 @@ __device__ __forceinline__ cplx<TC> pre_own_per(TC xk, TC xnk, TC xhk, TC xhpk, 
   return {E.re - O.im, E.im + O.re};
 }
 
+// pre_own and pre_own_per without their halvings: 4 Z[k] (cosine) and
+// 2 Z[k] (real DFT); the register kernel folds the factor into its output
+// scale (a power of two, so exact), with eight (four) multiplies fewer per
+// value.
+template <typename TC>
+__device__ __forceinline__ cplx<TC> pre_own_x4(TC xk, TC xnk, TC xhk, TC xhpk, cplx<TC> w4,
+                                               cplx<TC> wN) {
+  cplx<TC> Yk = {xk, -xnk};
+  cplx<TC> Yj = {xhk, -xhpk};
+  cplx<TC> Vk = cmulc(Yk, w4);
+  cplx<TC> Vj = cmulc(Yj, t4n_mirror(w4));
+  cplx<TC> Vjc = conj_(Vj);
+  cplx<TC> E = {Vk.re + Vjc.re, Vk.im + Vjc.im};
+  cplx<TC> D = {Vk.re - Vjc.re, Vk.im - Vjc.im};
+  cplx<TC> O = cmulc(D, wN);
+  return {E.re - O.im, E.im + O.re};
+}
+
+template <typename TC>
+__device__ __forceinline__ cplx<TC> pre_own_per_x2(TC xk, TC xnk, TC xhk, TC xhpk, cplx<TC> wN) {
+  cplx<TC> E = {xk + xhk, xnk - xhpk};
+  cplx<TC> D = {xk - xhk, xnk + xhpk};
+  cplx<TC> O = cmulc(D, wN);
+  return {E.re - O.im, E.im + O.re};
+}
+
 // Position of the line's element n in the half-length FFT input (reals):
 // Makhoul's order for the cosine transform, the natural order for the real
 // DFT (z[m] = x[2m] + i x[2m+1]).
@@ -690,25 +716,30 @@ dct_rad(LineArgs<TC> A) {
       const int k = t + T * q;
       cplx<TC> Zk = a[q];
       cplx<TC> Zc = conj_(z[lpad((H - k) & (H - 1))]);
-      cplx<TC> E = {(Zk.re + Zc.re) * TC(0.5), (Zk.im + Zc.im) * TC(0.5)};
-      cplx<TC> D = {(Zk.re - Zc.re) * TC(0.5), (Zk.im - Zc.im) * TC(0.5)};
-      cplx<TC> O = {D.im, -D.re};
+      // twice the even/odd split E, D (and O = -i D): the cosine transform's
+      // factor 2 absorbs the halving (scaling by powers of two is exact; the
+      // results differ from halving first only where the compiler fuses
+      // multiply-adds differently), with multiplies fewer
+      cplx<TC> E2 = {Zk.re + Zc.re, Zk.im + Zc.im};
+      cplx<TC> D2 = {Zk.re - Zc.re, Zk.im - Zc.im};
+      cplx<TC> O2 = {D2.im, -D2.re};
       const cplx<TC> wN = q ? cmul(tNb, ldu(Tb.tN + T * q)) : tNb;   // tN[k]
       const cplx<TC> w4 = q ? cmul(t4b, ldu(Tb.t4N + T * q)) : t4b;  // t4N[k]
-      cplx<TC> WO = cmul(wN, O);
+      cplx<TC> WO2 = cmul(wN, O2);
       TC xa, xb;  // slots k and N-k; for k = 0 slots 0 and H
       if (PER) {
         // X_k = E + w_N^k O; X_H = E_0 - O_0
-        cplx<TC> V = cadd(E, WO);
-        xa = V.re;
-        xb = k ? V.im : csub(E, WO).re;
+        cplx<TC> V2 = cadd(E2, WO2);
+        xa = TC(0.5) * V2.re;
+        xb = TC(0.5) * (k ? V2.im : csub(E2, WO2).re);
       } else {
-        cplx<TC> Y = cmul(w4, cadd(E, WO));
-        xa = TC(2) * Y.re;   // X[k]
-        xb = TC(-2) * Y.im;  // X[N-k]; for k = 0 replaced by X[H]
+        // X[k] = 2 Re Y, X[N-k] = -2 Im Y with Y = t4N[k] (E + w_N^k O)
+        cplx<TC> Y2 = cmul(w4, cadd(E2, WO2));
+        xa = Y2.re;
+        xb = -Y2.im;  // X[N-k]; for k = 0 replaced by X[H]
         if (k == 0) {
-          cplx<TC> Yh = cmul(t4n_mirror(w4), conj_(csub(E, WO)));
-          xb = TC(2) * Yh.re;
+          cplx<TC> Yh2 = cmul(t4n_mirror(w4), conj_(csub(E2, WO2)));
+          xb = Yh2.re;
         }
       }
       if (OP == OP_FWD) {
@@ -797,9 +828,9 @@ dct_rad(LineArgs<TC> A) {
       TC xhk = zr[xpad(H - k)];
       TC xhpk = zr[xpad(H + k)];
       if (PER)
-        a[q] = pre_own_per(ya[q], k ? yb[q] : TC(0), xhk, k ? xhpk : TC(0), wN);
+        a[q] = pre_own_per_x2(ya[q], k ? yb[q] : TC(0), xhk, k ? xhpk : TC(0), wN);
       else
-        a[q] = pre_own(ya[q], k ? yb[q] : TC(0), xhk, xhpk, w4, wN);
+        a[q] = pre_own_x4(ya[q], k ? yb[q] : TC(0), xhk, xhpk, w4, wN);
     }
     line_sync<T>();
   } else {
@@ -836,9 +867,9 @@ dct_rad(LineArgs<TC> A) {
       TC xhk = zr[xpad(H - k)];
       TC xhpk = zr[xpad(H + k)];
       if (PER)
-        a[q] = pre_own_per(xk[q], k ? xn[q] : TC(0), xhk, k ? xhpk : TC(0), wN);
+        a[q] = pre_own_per_x2(xk[q], k ? xn[q] : TC(0), xhk, k ? xhpk : TC(0), wN);
       else
-        a[q] = pre_own(xk[q], k ? xn[q] : TC(0), xhk, xhpk, w4, wN);
+        a[q] = pre_own_x4(xk[q], k ? xn[q] : TC(0), xhk, xhpk, w4, wN);
     }
     line_sync<T>();
   }
@@ -861,7 +892,7 @@ dct_rad(LineArgs<TC> A) {
   // from the LDS base itself, so that the accesses stay LDS instructions
   cplx<TC>* zi = reinterpret_cast<cplx<TC>*>(smem_raw) + zoff;
   rad_fft<TC, true, LOGH, RT>(a, ti, tw, tw8, Tb.twH, zi);
-  const TC sc = A.outscale;
+  const TC sc = A.outscale * (PER ? TC(0.5) : TC(0.25));  // undoes pre_own*_x2/_x4
   // The stores hit the same addresses as the loads; opaque copies of the
   // line base and stride make the compiler recompute them here instead of
   // keeping them live through the whole kernel.
