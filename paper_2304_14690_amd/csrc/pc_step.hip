@@ -68,17 +68,96 @@ __global__ void __launch_bounds__(TPB) k_div_all(const int32_t* __restrict__ gid
   b[p] = acc;
 }
 
+// ---- criterion of the IB iteration (Sec. 2.3) ------------------------------------
+// The partial sums of k_ib_step's blocks, added in block order by one
+// workgroup of TPB threads, give sums[0..1], the converged flag conv[0], the
+// iteration count conv[1], conv[4] = 1 - converged (the guard of work queued
+// for the converged case) and, if given, the flag and sums in coherent
+// pinned host memory that the host polls.  Every thread of the block gets
+// the converged flag; only a block with `write` set stores anything, so
+// several blocks can evaluate the same criterion and agree on it.
+struct IbClose {
+  const double* part;  // [2 nblk] partial sums (numerator, denominator)
+  int nblk;
+  double tol;
+  double* sums;
+  int32_t* conv;
+  int32_t* host_flag;  // nullable
+  double* host_sums;
+};
+
+__device__ int ib_close_block(const IbClose& C, bool write) {
+  __shared__ double rn[TPB / 64], rd[TPB / 64];
+  __shared__ int cvs;
+  double num = 0.0, den = 0.0;
+  for (int i = threadIdx.x; i < C.nblk; i += TPB) {
+    num += C.part[2 * i];
+    den += C.part[2 * i + 1];
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    num += __shfl_down(num, off, 64);
+    den += __shfl_down(den, off, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    rn[threadIdx.x >> 6] = num;
+    rd[threadIdx.x >> 6] = den;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    num = rn[0];
+    den = rd[0];
+#pragma unroll
+    for (int w = 1; w < TPB / 64; ++w) {
+      num += rn[w];
+      den += rd[w];
+    }
+    const int32_t cv = (num < C.tol * den || num == 0.0) ? 1 : 0;
+    cvs = cv;
+    if (write) {
+      C.sums[0] = num;
+      C.sums[1] = den;
+      C.conv[0] = cv;
+      C.conv[1] += 1;
+      C.conv[4] = 1 - cv;
+      if (C.host_flag) {
+        // the sums first, then the flag that says they are there
+        C.host_sums[0] = num;
+        C.host_sums[1] = den;
+        __threadfence_system();
+        *C.host_flag = cv;
+        __threadfence_system();
+      }
+    }
+  }
+  __syncthreads();
+  return cvs;
+}
+
 // ---- div_to_grid near the IB: b[near[q]] = base[q] (or b) + D(g) -----------
 // g lives on the B+V nodes only, so each near point sums over its B+V
 // entries (ELL layout, coalesced over q).
-template <typename T, int D, bool ADD, int WT>
+// With CLOSE the launch first evaluates the criterion of the iteration that
+// produced g (every block, identically; block 0 stores it), which saves the
+// criterion its own launch, and updates b only if that iteration has not
+// converged.
+template <typename T, int D, bool ADD, int WT, bool CLOSE>
 __global__ void __launch_bounds__(TPB) k_div_near(const int32_t* __restrict__ near, int64_t nnear,
                                                   int64_t nns, const int32_t* __restrict__ nslot,
                                                   const T* __restrict__ ncoef,
                                                   const T* __restrict__ gib, int64_t nib,
                                                   const T* __restrict__ base, T* __restrict__ b,
-                                                  const int32_t* __restrict__ skip) {
-  if (skip && *skip) return;
+                                                  const int32_t* __restrict__ skip, IbClose close) {
+  if (CLOSE) {
+    // block 0 may set the flag while other blocks start: read it once per
+    // block, so that no thread leaves before the criterion's barriers
+    __shared__ int sk;
+    if (threadIdx.x == 0) sk = skip ? *skip : 0;
+    __syncthreads();
+    if (sk || ib_close_block(close, blockIdx.x == 0)) return;
+  } else if (skip && *skip) {
+    return;
+  }
   int64_t q = (int64_t)blockIdx.x * TPB + threadIdx.x;
   if (q >= nnear) return;
   // WT is the table width itself (padding entries have slot -1 and
@@ -322,9 +401,11 @@ __global__ void __launch_bounds__(TPB) k_ib_finish(const double* __restrict__ pa
 // ---- fused IB step: gradient at the B+V nodes, force update, criterion ----------
 // Every thread takes one B+V node, computes grad phi there (sigma * grad p),
 // g_new = -u* + grad and the two criterion terms, and overwrites g.  Each
-// block (one wavefront) writes its partial sums to part[]; k_ib_close adds
-// them.  (A last-block-finishes scheme needs a device-scope fence and an
-// atomic per block, which cost more than a second launch here.)
+// block (one wavefront) writes its partial sums to part[]; the criterion
+// (ib_close_block) adds them in the next launch: k_ib_close, or the next
+// iteration's RHS update near the IB.  (A last-block-finishes scheme needs a
+// device-scope fence and an atomic per block, which cost more than a second
+// launch here.)
 template <typename T, int D, int BN>
 __global__ void __launch_bounds__(IBT) k_ib_step(const int32_t* __restrict__ ibbase,
                                                  const T* __restrict__ ibcoef, int64_t nib,
@@ -383,56 +464,11 @@ __global__ void __launch_bounds__(IBT) k_ib_step(const int32_t* __restrict__ ibb
   }
 }
 
-// Criterion of the IB iteration (Sec. 2.3) from k_ib_step's block partial
-// sums, added in block order: sums[0..1], the converged flag conv[0], the
-// iteration count conv[1], and (if given) the flag in coherent pinned host
-// memory that the host polls.
-__global__ void __launch_bounds__(TPB) k_ib_close(const double* __restrict__ part, int nblk,
-                                                  double tol, double* __restrict__ sums,
-                                                  int32_t* __restrict__ conv,
-                                                  const int32_t* __restrict__ skip,
-                                                  int32_t* host_flag, double* host_sums) {
-  __shared__ double rn[TPB / 64], rd[TPB / 64];
+// Criterion of the IB iteration from k_ib_step's block partial sums, in a
+// launch of its own (see ib_close_block).
+__global__ void __launch_bounds__(TPB) k_ib_close(IbClose close, const int32_t* __restrict__ skip) {
   if (skip && *skip) return;
-  double num = 0.0, den = 0.0;
-  for (int i = threadIdx.x; i < nblk; i += TPB) {
-    num += part[2 * i];
-    den += part[2 * i + 1];
-  }
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    num += __shfl_down(num, off, 64);
-    den += __shfl_down(den, off, 64);
-  }
-  if ((threadIdx.x & 63) == 0) {
-    rn[threadIdx.x >> 6] = num;
-    rd[threadIdx.x >> 6] = den;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    num = rn[0];
-    den = rd[0];
-#pragma unroll
-    for (int w = 1; w < TPB / 64; ++w) {
-      num += rn[w];
-      den += rd[w];
-    }
-    sums[0] = num;
-    sums[1] = den;
-    const int32_t cv = (num < tol * den || num == 0.0) ? 1 : 0;
-    conv[0] = cv;
-    conv[1] += 1;
-    conv[4] = 1 - cv;  // guard of work queued for the converged case only
-    if (host_flag) {
-      // coherent pinned host memory, polled by the host: the sums first,
-      // then the flag that says they are there
-      host_sums[0] = num;
-      host_sums[1] = den;
-      __threadfence_system();
-      *host_flag = cv;
-      __threadfence_system();
-    }
-  }
+  (void)ib_close_block(close, true);
 }
 
 // Prologue of a sub-step: u* at the B+V nodes, the initial IB force (zero or
@@ -553,14 +589,25 @@ int launch_div_all(const pc_geom* g, const T* gcoef, const T* v, T* b, hipStream
   return PC_OK;
 }
 
+// close (nullable): the criterion of the iteration that produced gib,
+// evaluated in the same launch (needs n_near > 0).
 template <typename T>
 int launch_div_near(const pc_geom* g, const T* ncoefib, const T* gib, const T* base, T* b,
-                    bool add, hipStream_t s, const int32_t* skip = nullptr) {
-  if (g->n_near == 0) return PC_OK;
+                    bool add, hipStream_t s, const int32_t* skip = nullptr,
+                    const IbClose* close = nullptr) {
+  if (g->n_near == 0) return close ? fail(PC_ERR_INVALID_ARG, "criterion without near points")
+                                   : PC_OK;
   dim3 grid(nblk(g->n_near)), block(TPB);
-#define DNL(D, ADD, WT)                                                                        \
-  hipLaunchKernelGGL((k_div_near<T, D, ADD, WT>), grid, block, 0, s, g->near, g->n_near, g->nns, \
-                     g->nslot, ncoefib, gib, g->n_ib, base, b, skip)
+  const IbClose cl = close ? *close : IbClose{};
+#define DNL(D, ADD, WT)                                                                          \
+  do {                                                                                           \
+    if (close)                                                                                   \
+      hipLaunchKernelGGL((k_div_near<T, D, ADD, WT, true>), grid, block, 0, s, g->near,        \
+                         g->n_near, g->nns, g->nslot, ncoefib, gib, g->n_ib, base, b, skip, cl); \
+    else                                                                                         \
+      hipLaunchKernelGGL((k_div_near<T, D, ADD, WT, false>), grid, block, 0, s, g->near,       \
+                         g->n_near, g->nns, g->nslot, ncoefib, gib, g->n_ib, base, b, skip, cl); \
+  } while (0)
 #define DNW(D, ADD)                                 \
   do {                                              \
     if (g->near_w == 8) DNL(D, ADD, 8);             \
@@ -656,10 +703,18 @@ int launch_ib_update(const pc_geom* g, const T* uib, const T* grad, T* gib, doub
   return PC_OK;
 }
 
+// The criterion arguments of the IB step launched with these arguments.
+inline IbClose ib_close_args(const pc_geom* g, double tol, double* part, int32_t* flag,
+                             double* sums, int32_t* host_flag, double* host_sums) {
+  return IbClose{part, (int)((g->n_ib + IBT - 1) / IBT), tol, sums, flag, host_flag, host_sums};
+}
+
+// The IB step; with `close` also its criterion in a launch of its own
+// (otherwise the caller evaluates it, merged into the next RHS update).
 template <typename T>
 int launch_ib_step(const pc_geom* g, const T* ibcoef, const T* phi, T scale, const T* uib, T* gib,
                    double tol, double* part, int32_t* flag, double* sums, hipStream_t s,
-                   const int32_t* skip, int32_t* host_flag, double* host_sums) {
+                   const int32_t* skip, int32_t* host_flag, double* host_sums, bool close = true) {
   if (g->n_ib == 0) return PC_OK;
   BlockOffsets bo = block_offsets(g);
   dim3 grid((unsigned)((g->n_ib + IBT - 1) / IBT)), block(IBT);
@@ -673,8 +728,9 @@ int launch_ib_step(const pc_geom* g, const T* ibcoef, const T* phi, T scale, con
     if (g->bn == 27) IBS(3, 27); else IBS(3, 0);
   }
 #undef IBS
-  hipLaunchKernelGGL(k_ib_close, dim3(1), dim3(TPB), 0, s, (const double*)part, (int)grid.x, tol,
-                     sums, flag, skip, host_flag, host_sums);
+  if (close)
+    hipLaunchKernelGGL(k_ib_close, dim3(1), dim3(TPB), 0, s,
+                       ib_close_args(g, tol, part, flag, sums, host_flag, host_sums), skip);
   PC_HIP_CHECK(hipGetLastError());
   return PC_OK;
 }
@@ -762,9 +818,15 @@ int pressure_correct_t(const pc_geom* g, const pc_plan* P, int mode, const T* u,
   // gradient at the B+V nodes, force update and criterion.  With `skip` set,
   // every launch of the iteration returns at once once the device flag says
   // an earlier iteration has converged.
-  auto iteration = [&](int it, const int32_t* skip, int32_t* host_flag) -> int {
+  // With `defer` the iteration leaves its criterion to the caller (merged
+  // into the next iteration's RHS update, or queued alone); `prev` is the
+  // deferred criterion of iteration it - 1, evaluated in this iteration's
+  // RHS update.
+  auto iteration = [&](int it, const int32_t* skip, int32_t* host_flag, bool defer = false,
+                       const IbClose* prev = nullptr) -> int {
     double* host_sums = host_flag ? W->hscal + 4 + 2 * (it & 1) : nullptr;
-    if (it > 1 || g_io) PC_TRY(launch_div_near<T>(g, nci<T>(g), gib, bnear, b, false, s, skip));
+    if (it > 1 || g_io)
+      PC_TRY(launch_div_near<T>(g, nci<T>(g), gib, bnear, b, false, s, skip, prev));
     if (resident && mode == PC_F64)
       PC_TRY(solve_resident_f64(P, (const double*)b, (double*)p, W->scal, W, s, sigma, skip,
                                 it > 1 ? 1 : 0));
@@ -779,7 +841,18 @@ int pressure_correct_t(const pc_geom* g, const pc_plan* P, int mode, const T* u,
       PC_TRY(solve_mixed(P, (const double*)b, (double*)p, sweeps, W->scal, W, s, sigma, skip));
     if (nib)
       PC_TRY(launch_ib_step<T>(g, ibc<T>(g), p, (T)sigma, uib, gib, tol, W->partial, W->flag,
-                               W->scal + 1, s, skip, host_flag, host_sums));
+                               W->scal + 1, s, skip, host_flag, host_sums, !defer));
+    return PC_OK;
+  };
+  // the criterion of iteration it (host slot it % 2), deferred or alone
+  auto close_args = [&](int it) {
+    return ib_close_args(g, tol, W->partial, W->flag, W->scal + 1, W->hflag + (it & 1),
+                         W->hscal + 4 + 2 * (it & 1));
+  };
+  auto close_alone = [&](int it) -> int {
+    hipLaunchKernelGGL(k_ib_close, dim3(1), dim3(TPB), 0, s, close_args(it),
+                       (const int32_t*)W->flag);
+    PC_HIP_CHECK(hipGetLastError());
     return PC_OK;
   };
 
@@ -831,20 +904,33 @@ int pressure_correct_t(const pc_geom* g, const pc_plan* P, int mode, const T* u,
     // geometrically, q_i ~ q_{i-1}^2 / q_{i-2}, and the prediction must be
     // below 2/3 of the tolerance.  A wrong prediction costs a few launches
     // that return at once and a late enqueue; it never changes the result.
+    // The criterion of iteration i runs in the first launch of iteration
+    // i+1 (its RHS update near the IB) when that iteration is queued next,
+    // and in a launch of its own otherwise.
     volatile int32_t* hf = W->hflag;
     volatile double* hs = W->hscal;
     double q1 = 0.0, q2 = 0.0;  // q of the two previous iterations (0: unknown)
+    const bool merge = g->n_near > 0;
     hf[1] = -1;
-    PC_TRY(iteration(1, W->flag, W->hflag + 1));
+    PC_TRY(iteration(1, W->flag, W->hflag + 1, merge));
+    bool pending = merge;  // the criterion of iteration `it` is not queued yet
     for (it = 1;; ++it) {
       bool ahead = false;
       const bool likely = q1 > 0.0 && q2 > 0.0 && q1 * q1 < (2.0 / 3.0) * tol * q2;
       if (likely) {
+        if (pending) PC_TRY(close_alone(it));
+        pending = false;
         PC_TRY(final_work(W->flag + 4));
       } else if (it < max_it) {
         hf[(it + 1) & 1] = -1;
-        PC_TRY(iteration(it + 1, W->flag, W->hflag + ((it + 1) & 1)));
+        const IbClose prev = close_args(it);
+        PC_TRY(iteration(it + 1, W->flag, W->hflag + ((it + 1) & 1), merge,
+                         pending ? &prev : nullptr));
+        pending = merge;  // now the criterion of iteration it + 1
         ahead = true;
+      } else if (pending) {
+        PC_TRY(close_alone(it));
+        pending = false;
       }
       PC_TRY(wait_host_flag(hf + (it & 1), s));
       if (hf[it & 1] == 1) {
@@ -858,7 +944,8 @@ int pressure_correct_t(const pc_geom* g, const pc_plan* P, int mode, const T* u,
       q1 = den > 0.0 ? num / den : 0.0;
       if (!ahead) {
         hf[(it + 1) & 1] = -1;
-        PC_TRY(iteration(it + 1, W->flag, W->hflag + ((it + 1) & 1)));
+        PC_TRY(iteration(it + 1, W->flag, W->hflag + ((it + 1) & 1), merge));
+        pending = merge;
       }
     }
   }
