@@ -318,12 +318,30 @@ __global__ void __launch_bounds__(TPB) k_zero_ib(const int32_t* __restrict__ ib,
   for (int a = 0; a < d; ++a) out[a * M + n] = T(0);
 }
 
+// The work after the last iteration at the B+V nodes, in one launch:
+// u^{n+1} = 0 there (Eqs. 18 and 19 cancel), the final force to the caller
+// (g_out, nullable) and, with hs, the statistics into pinned host memory
+// (bmean, criterion sums, flags).
 template <typename T>
-__global__ void __launch_bounds__(TPB) k_gather_near(const int32_t* __restrict__ near,
-                                                     int64_t nnear, const T* __restrict__ b,
-                                                     T* __restrict__ bnear) {
-  int64_t q = (int64_t)blockIdx.x * TPB + threadIdx.x;
-  if (q < nnear) bnear[q] = b[near[q]];
+__global__ void __launch_bounds__(TPB) k_finish_ib(const int32_t* __restrict__ ib, int64_t nib,
+                                                   int d, int64_t M, T* __restrict__ out,
+                                                   const T* __restrict__ gib, T* __restrict__ g_out,
+                                                   const double* __restrict__ scal,
+                                                   const int32_t* __restrict__ flag, double* hs,
+                                                   int32_t* hf, const int32_t* __restrict__ skip) {
+  if (skip && *skip) return;
+  if (hs && blockIdx.x == 0 && threadIdx.x < 64) {
+    if (threadIdx.x < 3) hs[threadIdx.x] = scal[threadIdx.x];
+    if (threadIdx.x < 2) hf[threadIdx.x + 2] = flag[threadIdx.x];
+    __threadfence_system();
+  }
+  int64_t s = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  if (s >= nib) return;
+  int64_t n = ib[s];
+  for (int a = 0; a < d; ++a) {
+    out[a * M + n] = T(0);
+    if (g_out) g_out[a * nib + s] = gib[a * nib + s];
+  }
 }
 
 // ---- IB-force update with deterministic criterion sums ----------------------------
@@ -472,13 +490,21 @@ __global__ void __launch_bounds__(TPB) k_ib_close(IbClose close, const int32_t* 
 }
 
 // Prologue of a sub-step: u* at the B+V nodes, the initial IB force (zero or
-// the caller's warm start) and the device flags, in one launch.
+// the caller's warm start) and the device flags, in one launch; the blocks
+// past the first nbib copy b_u at the near-IB points (bnear[q] = b[near[q]]).
 template <typename T>
 __global__ void __launch_bounds__(TPB) k_prologue(const int32_t* __restrict__ ib, int64_t nib,
                                                   int d, const T* __restrict__ u, int64_t M,
                                                   T* __restrict__ uib, T* __restrict__ gib,
                                                   const T* __restrict__ g_in,
-                                                  int32_t* __restrict__ flag) {
+                                                  int32_t* __restrict__ flag, int nbib,
+                                                  const int32_t* __restrict__ near, int64_t nnear,
+                                                  const T* __restrict__ b, T* __restrict__ bnear) {
+  if ((int)blockIdx.x >= nbib) {
+    const int64_t q = (int64_t)(blockIdx.x - nbib) * TPB + threadIdx.x;
+    if (q < nnear) bnear[q] = b[near[q]];
+    return;
+  }
   int64_t s = (int64_t)blockIdx.x * TPB + threadIdx.x;
   if (blockIdx.x == 0 && threadIdx.x < 16) flag[threadIdx.x] = 0;
   if (s >= nib) return;
@@ -523,14 +549,6 @@ __global__ void __launch_bounds__(1) k_zero_first(T* __restrict__ x,
                                                  const int32_t* __restrict__ skip) {
   if (skip && *skip) return;
   x[0] = T(0);
-}
-
-template <typename T>
-__global__ void __launch_bounds__(TPB) k_copy(const T* __restrict__ src, T* __restrict__ dst,
-                                              int64_t n, const int32_t* __restrict__ skip) {
-  if (skip && *skip) return;
-  int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
-  if (i < n) dst[i] = src[i];
 }
 
 unsigned nblk(int64_t n) { return (unsigned)((n + TPB - 1) / TPB); }
@@ -807,12 +825,13 @@ int pressure_correct_t(const pc_geom* g, const pc_plan* P, int mode, const T* u,
 
   // the long gather goes first so that the host queues the rest behind it
   PC_TRY(launch_div_all<T>(g, gc<T>(g), u, b, s));
-  hipLaunchKernelGGL(k_prologue<T>, dim3(std::max<unsigned>(1, nblk(nib))), dim3(TPB), 0, s, g->ib,
-                     nib, g->d, u, g->M, uib, gib, (const T*)g_io, W->flag);
-  PC_HIP_CHECK(hipGetLastError());
-  if (g->n_near)
-    hipLaunchKernelGGL(k_gather_near<T>, dim3(nblk(g->n_near)), dim3(TPB), 0, s, g->near, g->n_near,
-                       (const T*)b, bnear);
+  {
+    const unsigned nbib = std::max<unsigned>(1, nblk(nib));
+    hipLaunchKernelGGL(k_prologue<T>, dim3(nbib + nblk(g->n_near)), dim3(TPB), 0, s, g->ib, nib,
+                       g->d, u, g->M, uib, gib, (const T*)g_io, W->flag, (int)nbib, g->near,
+                       g->n_near, (const T*)b, bnear);
+    PC_HIP_CHECK(hipGetLastError());
+  }
 
   // One IB iteration (Sec. 2.3): RHS update near the IB, Poisson solve,
   // gradient at the B+V nodes, force update and criterion.  With `skip` set,
@@ -867,17 +886,17 @@ int pressure_correct_t(const pc_geom* g, const pc_plan* P, int mode, const T* u,
     else if (resident)
       PC_TRY(solve_resident_f32(P, (const float*)b, (float*)p, W->scal, W, s, sigma, guard, 2));
     PC_TRY((launch_grad_all<T, true>(g, nc<T>(g), p, (T)sigma, u, u_out, s, guard)));
-    PC_TRY(launch_zero_ib<T>(g, u_out, s, guard));
-    if (g_io && nib)
-      hipLaunchKernelGGL(k_copy<T>, dim3(nblk((int64_t)g->d * nib)), dim3(TPB), 0, s,
-                         (const T*)gib, g_io, (int64_t)g->d * nib, guard);
+    if (nib)
+      hipLaunchKernelGGL(k_finish_ib<T>, dim3(nblk(nib)), dim3(TPB), 0, s, g->ib, nib, g->d, g->M,
+                         u_out, (const T*)gib, g_io, (const double*)W->scal,
+                         (const int32_t*)W->flag, st ? W->hscal : nullptr, W->hflag, guard);
+    else if (st)
+      hipLaunchKernelGGL(k_stats_out, dim3(1), dim3(64), 0, s, (const double*)W->scal,
+                         (const int32_t*)W->flag, W->hscal, W->hflag, guard);
     if (gauge == 1) {
       hipLaunchKernelGGL(k_sub_first<T>, dim3(nblk(P->G)), dim3(TPB), 0, s, p, P->G, guard);
       hipLaunchKernelGGL(k_zero_first<T>, dim3(1), dim3(1), 0, s, p, guard);
     }
-    if (st)
-      hipLaunchKernelGGL(k_stats_out, dim3(1), dim3(64), 0, s, (const double*)W->scal,
-                         (const int32_t*)W->flag, W->hscal, W->hflag, guard);
     PC_HIP_CHECK(hipGetLastError());
     return PC_OK;
   };
