@@ -2,7 +2,8 @@
 solver variants Sec. 3 reports as giving no noticeable difference): the
 eigenvalue of each transform mode is minus its squared wavenumber.  Solves
 against the oracle (float64 1e-11, float32 5e-5) on Neumann, periodic and
-mixed boxes, both register plans and the generic kernel; exact inversion of
+mixed boxes, both register plans and the generic kernels (periodic and
+Neumann axes that are short or not powers of two); exact inversion of
 a trigonometric polynomial's analytic Laplacian at full size; the sub-step
 with a pseudo-spectral plan against the oracle; PC_MIXED is refused (its
 defect correction evaluates the 3-point Laplacian)."""
@@ -20,6 +21,9 @@ PE, NE = "periodic", "neumann"
 CASES = [
     ((64, 64), (NE, NE)), ((2048, 2048), (NE, NE)), ((64, 32), (PE, NE)), ((16, 64), (NE, PE)),
     ((32, 16, 64), (PE, NE, PE)), ((256, 256, 256), (NE, NE, NE)), ((64, 64, 64), (PE, PE, PE)),
+    # generic kernels: periodic and Neumann axes that are short or not powers of two
+    ((400, 400), (PE, PE)), ((400, 402), (PE, NE)), ((280, 480), (NE, NE)), ((16, 64), (PE, NE)),
+    ((48, 40, 36), (PE, PE, NE)),
 ]
 
 
