@@ -415,7 +415,7 @@ __global__ void __launch_bounds__(1024) dct1_lines(LineArgs<TC> A) {
       TC v = TC(0);
       if (p >= 0) {
         if (LD == LD_RESID) {
-          double r = resid_at(A.rb, A.rphi, p, A.d, A.n0, A.n1, A.n2, A.perm, A.ih2, A.rscale);
+          double r = resid_at<true>(A.rb, A.rphi, p, A.d, A.n0, A.n1, A.n2, A.perm, A.ih2, A.rscale);
           if (A.sub) r -= *A.sub;
           v = (TC)r;
         } else if (A.sub) {
@@ -891,7 +891,7 @@ int launch_pass(const pc_plan* P, int axis, const TI* in, TO* out, const AxisTab
                       : (P->bc[a] == PC_BC_PERIODIC ? 1.0 : 2.0) * P->n[a];
   A.meannorm = 1.0 / norm;
   A.own_table = P->eig == PC_EIG_SPECTRAL;
-  A.perm = P->vertex ? PERM_VERTEX : 0;
+  A.perm = 0;
   for (int a = 0; a < P->d; ++a)
     if (P->bc[a] == PC_BC_PERIODIC) A.perm |= 1 << a;
   int64_t lines = P->G / A.N;

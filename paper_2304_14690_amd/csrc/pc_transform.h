@@ -38,7 +38,6 @@ __device__ __forceinline__ cplx<T> conj_(cplx<T> a) { return {a.re, -a.im}; }
 __device__ __forceinline__ int mk_pos(int n, int N) { return (n & 1) ? (N - 1 - (n >> 1)) : (n >> 1); }
 
 enum { OP_FWD = 0, OP_INV = 1, OP_FDI = 2 };
-constexpr int PERM_VERTEX = 8;  // LineArgs::perm flag of a vertex grid
 enum { LD_PLAIN = 0, LD_RESID = 1 };
 enum { ST_PLAIN = 0, ST_ACCUM = 1 };
 
@@ -59,8 +58,7 @@ struct LineArgs {
   int tx;               // tiles along x (strided axes)
   int axis;             // 0, 1, 2
   int d;
-  int perm;             // bit a set: axis a is periodic (residual wrap-around);
-                        // PERM_VERTEX: vertex grid (mirror about the end vertex)
+  int perm;             // bit a set: axis a is periodic (residual wrap-around)
   int own_table;        // pseudo-spectral eigenvalues: the generic kernels read
                         // them from tab.lam by slot, the register kernel's FDI
                         // computes lams * m^2 for the slot's mode m
@@ -100,21 +98,19 @@ __device__ __forceinline__ int64_t line_base(const LineArgs<TC>& A, int t, int c
 }
 
 // The float64 residual r = b - rscale * lap_h phi at cell (i, j, k) of flat
-// index p.  Neumann axes take the mirror ghost (phi_{-1} = phi_0, or
-// phi_{-1} = phi_1 on a vertex grid), periodic axes (bit a of perm) wrap
-// around.  Each neighbour's address is selected
-// first (the ghost re-reads the cell itself), so all loads are
+// index p.  Neumann axes take the mirror ghost (phi_{-1} = phi_0; on a vertex
+// grid, VERTEX, the mirror about the end vertex phi_{-1} = phi_1), periodic
+// axes (bit a of perm) wrap around.  Each neighbour's address is selected
+// first (the ghost re-reads a point of the line), so all loads are
 // unconditional and in flight together.
+template <bool VERTEX = false>
 __device__ __forceinline__ double resid_ijk(const double* __restrict__ b,
                                             const double* __restrict__ phi, int64_t p, int i,
                                             int j, int k, int d, int32_t n0, int32_t n1,
                                             int32_t n2, int perm, const double* ih2,
                                             double rscale) {
   const int64_t s1 = n0, s2 = (int64_t)n0 * n1;
-  // past a face: the wrapped point (periodic axis), the point itself
-  // (cell-centred mirror ghost) or the first interior point (mirror about
-  // the end vertex of a vertex grid, PERM_VERTEX)
-  const int64_t vx = (perm & PERM_VERTEX) ? 1 : 0;
+  constexpr int64_t vx = VERTEX ? 1 : 0;
   const int64_t pxm = i > 0 ? p - 1 : ((perm & 1) ? p + (n0 - 1) : p + vx);
   const int64_t pxp = i < n0 - 1 ? p + 1 : ((perm & 1) ? p - (n0 - 1) : p - vx);
   const int64_t pym = j > 0 ? p - s1 : ((perm & 2) ? p + (n1 - 1) * s1 : p + vx * s1);
@@ -132,6 +128,7 @@ __device__ __forceinline__ double resid_ijk(const double* __restrict__ b,
 }
 
 // The same residual at flat index p (coordinates by division).
+template <bool VERTEX = false>
 __device__ __forceinline__ double resid_at(const double* __restrict__ b,
                                            const double* __restrict__ phi, int64_t p, int d,
                                            int32_t n0, int32_t n1, int32_t n2, int perm,
@@ -139,7 +136,7 @@ __device__ __forceinline__ double resid_at(const double* __restrict__ b,
   const int i = (int)(p % n0);
   const int j = (int)((p / n0) % n1);
   const int k = d == 3 ? (int)(p / ((int64_t)n0 * n1)) : 0;
-  return resid_ijk(b, phi, p, i, j, k, d, n0, n1, n2, perm, ih2, rscale);
+  return resid_ijk<VERTEX>(b, phi, p, i, j, k, d, n0, n1, n2, perm, ih2, rscale);
 }
 
 // ---- register-resident radix-16 line transform ------------------------------
