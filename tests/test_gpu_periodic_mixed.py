@@ -30,6 +30,9 @@ SOLVES = [
     ((48, 40, 36), (PE, PE, NE)),
     ((26, 18, 14), (PE, NE, PE)),
     ((64, 134, 32), (NE, PE, PE)),
+    ((8, 8, 8), (PE, PE, PE)),
+    ((10, 8, 12), (PE, NE, PE)),
+    ((4094, 8), (PE, NE)),
 ]
 SIDS = ["x".join(map(str, n)) + "-" + "".join(b[0] for b in bc) for n, bc in SOLVES]
 
