@@ -85,6 +85,8 @@ def _tiled(grid, x):
     ((32, 64), ("periodic", "periodic"), 12, 16),
     ((32, 16), ("neumann", "periodic"), 16, 9),
     ((16, 16, 16), ("periodic", "neumann", "periodic"), 27, 27),
+    ((40, 24), ("periodic", "periodic"), 16, 16),
+    ((12, 10, 14), ("periodic", "neumann", "periodic"), 27, 27),
 ])
 def test_periodic_stencils_equal_tiled_cloud(rng, n, bc, k_grid, k_node):
     d = len(n)
