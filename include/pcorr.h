@@ -159,12 +159,29 @@ typedef struct pc_stats {
 
 /* ---- library ------------------------------------------------------------ */
 
-/* ABI version (major*100 + minor): 111. */
+/* ABI version (major*100 + minor): 112. */
 int pc_version(void);
 
 /* Copies the calling thread's last error message into buf (NUL-terminated,
  * truncated to n bytes).  Returns the message length. */
 int pc_last_error(char* buf, size_t n);
+
+/* Device memory of the library.  By default plans, geometries, workspaces
+ * and the scratch of a call take their device memory from hipMalloc and
+ * return it with hipFree.  A caller that accounts device memory itself (a
+ * serving loop's admission, a framework's caching allocator) installs its
+ * own pair: alloc(user, bytes, &ptr) returns 0 and a device pointer aligned
+ * to at least 256 bytes, or nonzero when it cannot (the library call then
+ * fails with PC_ERR_OOM); free(user, ptr) takes back a pointer that alloc
+ * returned.  Both are called on the calling thread, from inside library
+ * calls, with the current device unchanged.  (NULL, NULL) restores
+ * hipMalloc/hipFree.  The pair can be replaced only while no allocation made
+ * through the installed one is outstanding (every object created with it
+ * destroyed): otherwise PC_ERR_INVALID_ARG.  Pinned host memory (the
+ * convergence flags of a workspace) still comes from hipHostMalloc. */
+typedef int (*pc_alloc_fn)(void* user, size_t bytes, void** ptr);
+typedef void (*pc_free_fn)(void* user, void* ptr);
+int pc_set_allocator(pc_alloc_fn alloc, pc_free_fn free_fn, void* user);
 
 /* ---- plan: grid and transform tables ------------------------------------ */
 

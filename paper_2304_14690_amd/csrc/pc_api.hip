@@ -2,8 +2,10 @@
 // solve.  Geometry entry points live in pc_wls.hip, the transfers and the
 // whole sub-step in pc_step.hip.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 
 #include "pc_internal.h"
 
@@ -20,9 +22,36 @@ int fail(int code, const std::string& msg) {
   return code;
 }
 
+namespace {
+// the caller's allocator (pc_set_allocator), and the number of its
+// allocations not yet returned
+std::mutex g_alloc_mu;
+pc_alloc_fn g_alloc = nullptr;
+pc_free_fn g_free = nullptr;
+void* g_alloc_user = nullptr;
+std::atomic<int64_t> g_alloc_live{0};
+}  // namespace
+
 int dev_alloc(void** p, size_t bytes, const char* what) {
   *p = nullptr;
   if (bytes == 0) return PC_OK;
+  pc_alloc_fn fa;
+  void* user;
+  {
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    fa = g_alloc;
+    user = g_alloc_user;
+    if (fa) ++g_alloc_live;
+  }
+  if (fa) {
+    if (fa(user, bytes, p) != 0 || !*p) {
+      --g_alloc_live;
+      *p = nullptr;
+      return fail(PC_ERR_OOM, std::string("the installed allocator failed for ") + what + " (" +
+                                  std::to_string(bytes) + " bytes)");
+    }
+    return PC_OK;
+  }
   hipError_t e = hipMalloc(p, bytes);
   if (e != hipSuccess) {
     (void)hipGetLastError();
@@ -34,7 +63,20 @@ int dev_alloc(void** p, size_t bytes, const char* what) {
 }
 
 void dev_free(void* p) {
-  if (p) (void)hipFree(p);
+  if (!p) return;
+  pc_free_fn ff;
+  void* user;
+  {
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    ff = g_free;
+    user = g_alloc_user;
+  }
+  if (ff) {
+    ff(user, p);
+    --g_alloc_live;
+  } else {
+    (void)hipFree(p);
+  }
 }
 
 namespace {
@@ -131,7 +173,20 @@ using namespace pc;
 
 extern "C" {
 
-int pc_version(void) { return 111; }
+int pc_version(void) { return 112; }
+
+int pc_set_allocator(pc_alloc_fn alloc, pc_free_fn free_fn, void* user) {
+  if ((alloc == nullptr) != (free_fn == nullptr))
+    return fail(PC_ERR_INVALID_ARG, "pc_set_allocator: give both functions or neither");
+  std::lock_guard<std::mutex> lk(g_alloc_mu);
+  if (g_alloc_live.load() != 0)
+    return fail(PC_ERR_INVALID_ARG,
+                "pc_set_allocator: allocations of the installed allocator are outstanding");
+  g_alloc = alloc;
+  g_free = free_fn;
+  g_alloc_user = alloc ? user : nullptr;
+  return PC_OK;
+}
 
 int pc_last_error(char* buf, size_t n) {
   const std::string& m = g_last_error;
@@ -246,7 +301,7 @@ int64_t pc_workspace_bytes(const pc_plan* P, const pc_geom* g, int mode) {
     add(P->G * (int64_t)s);              // b
     add(P->G * (int64_t)s);              // phi
     add(g->n_near * (int64_t)s);         // bnear
-    add(3 * (int64_t)g->d * g->n_ib * (int64_t)s);  // uib, gib, gradib
+    for (int i = 0; i < 3; ++i) add((int64_t)g->d * g->n_ib * (int64_t)s);  // uib, gib, gradib
   }
   if (mode == PC_MIXED) add(P->G * 4);   // w32
   if (pc::resident_ok(P, g, mode)) {
@@ -332,6 +387,12 @@ int pc_workspace_create(const pc_plan* P, const pc_geom* g, int mode, pc_workspa
   W->partial = reinterpret_cast<double*>(take(8 * partial_doubles(g)));
   W->scal = reinterpret_cast<double*>(take(16 * 8));
   W->flag = reinterpret_cast<int32_t*>(take(16 * 4));
+  if (cur - reinterpret_cast<char*>(W->block) > W->bytes) {
+    // the layout above and pc_workspace_bytes must agree region by region
+    dev_free(W->block);
+    delete W;
+    return fail(PC_ERR_HIP, "workspace layout exceeds its allocation");
+  }
   // coherent: the IB kernel's flag store (system-scope fence) is read by the
   // host while later kernels of the stream are still running
   if (hipHostMalloc((void**)&W->hscal, 16 * 8 + 16 * 4, hipHostMallocCoherent) != hipSuccess) {

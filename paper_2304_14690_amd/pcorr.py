@@ -46,7 +46,13 @@ EXPORTS = [
     "pc_geom_export", "pc_div_to_grid", "pc_grad_to_nodes", "pc_ib_update", "pc_project",
     "pc_workspace_create", "pc_workspace_destroy", "pc_workspace_bytes",
     "pc_pressure_correct", "pc_geom_export_self", "pc_momentum_predict", "pc_momentum_pressure",
+    "pc_set_allocator",
 ]
+
+# pc_alloc_fn / pc_free_fn
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_size_t,
+                            ctypes.POINTER(ctypes.c_void_p))
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
 
 
 class PcError(RuntimeError):
@@ -113,6 +119,7 @@ def _load():
         "pc_momentum_predict": ([vp, ctypes.c_int, vp, vp, dbl, dbl, vp, vp, vp, vp],
                                 ctypes.c_int),
         "pc_momentum_pressure": ([vp, ctypes.c_int, vp, vp, vp, vp, dbl, vp, vp], ctypes.c_int),
+        "pc_set_allocator": ([ALLOC_FN, FREE_FN, vp], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         if hasattr(lib, name):
@@ -317,6 +324,49 @@ def pressure_correct(geom: Geometry, plan: Plan, mode: int, u: torch.Tensor, dt:
                                          ctypes.byref(st) if want_stats else None,
                                          ws.h_ if ws else None, _stream(stream)))
     return rc, st.as_dict()
+
+
+_allocator = None  # the installed callbacks, kept alive while installed
+
+
+def set_allocator(alloc=None, free=None) -> int:
+    """Routes the library's device allocations through alloc(nbytes) -> int
+    device pointer and free(ptr) (both None: hipMalloc/hipFree again); see
+    pc_set_allocator.  An exception in alloc reports PC_ERR_OOM."""
+    global _allocator
+    if alloc is None and free is None:
+        _check(_lib.pc_set_allocator(ALLOC_FN(), FREE_FN(), None))
+        _allocator = None
+        return PC_OK
+
+    def _a(user, nbytes, out):
+        try:
+            ptr = int(alloc(int(nbytes)))
+        except Exception:
+            return 1
+        out[0] = ptr
+        return 0 if ptr else 1
+
+    def _f(user, ptr):
+        free(int(ptr))
+
+    cbs = (ALLOC_FN(_a), FREE_FN(_f))
+    _check(_lib.pc_set_allocator(cbs[0], cbs[1], None))
+    _allocator = cbs
+    return PC_OK
+
+
+def torch_allocator():
+    """(alloc, free) through torch's caching allocator on the current device,
+    so that torch's memory statistics and limits cover the library."""
+    import torch
+
+    def alloc(nbytes: int) -> int:
+        return torch.cuda.caching_allocator_alloc(nbytes)
+
+    def free(ptr: int) -> None:
+        torch.cuda.caching_allocator_delete(ptr)
+    return alloc, free
 
 
 def geom_export_self(geom: Geometry, idx=None, coef=None, stream=None) -> int:

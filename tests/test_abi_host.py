@@ -35,7 +35,7 @@ def test_library_exports_every_declared_symbol():
 def test_host_side_validation():
     from paper_2304_14690_amd import pcorr
     lib = pcorr.lib()
-    assert lib.pc_version() == 111
+    assert lib.pc_version() == 112
     out = ctypes.c_void_p()
     n = (ctypes.c_int32 * 3)(64, 64, 1)
     h = (ctypes.c_double * 3)(1 / 64, 1 / 64, 1.0)
@@ -51,6 +51,10 @@ def test_host_side_validation():
     assert lib.pc_wls_build(None, None, None, 0, None, None, ctypes.byref(out)) == \
         pcorr.PC_ERR_INVALID_ARG
     assert lib.pc_plan_destroy(None) == pcorr.PC_OK
+    # the caller's allocator: both functions or neither
+    assert lib.pc_set_allocator(pcorr.ALLOC_FN(lambda u, n, p: 1), pcorr.FREE_FN(), None) == \
+        pcorr.PC_ERR_INVALID_ARG
+    assert lib.pc_set_allocator(pcorr.ALLOC_FN(), pcorr.FREE_FN(), None) == pcorr.PC_OK
     # per-axis conditions: unknown codes, and an odd periodic axis
     bc = (ctypes.c_int32 * 3)(pcorr.PC_BC_PERIODIC, 7, 0)
     assert lib.pc_plan_create_ex(2, n, h, bc, 0, 0, None, ctypes.byref(out)) == \
