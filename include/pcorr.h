@@ -174,7 +174,10 @@ int pc_last_error(char* buf, size_t n);
  * to at least 256 bytes, or nonzero when it cannot (the library call then
  * fails with PC_ERR_OOM); free(user, ptr) takes back a pointer that alloc
  * returned.  Both are called on the calling thread, from inside library
- * calls, with the current device unchanged.  (NULL, NULL) restores
+ * calls, with the current device unchanged.  A call may free its scratch
+ * while work it queued on its stream still uses it: the pair must order
+ * reuse after that stream's work (as a caching allocator bound to the same
+ * stream does) or wait for it.  (NULL, NULL) restores
  * hipMalloc/hipFree.  The pair can be replaced only while no allocation made
  * through the installed one is outstanding (every object created with it
  * destroyed): otherwise PC_ERR_INVALID_ARG.  Pinned host memory (the
