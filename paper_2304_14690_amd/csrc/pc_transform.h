@@ -247,6 +247,20 @@ __device__ __forceinline__ cplx<TC> ldu(const cplx<TC>* p) {
 
 // LDS index of complex element i of a line (one pad slot per 16).
 __device__ __forceinline__ int lpad(int i) { return i + (i >> 4); }
+// lpad(t + T q) from lt = lpad(t): linear in q when T is a multiple of 16
+template <int T>
+__device__ __forceinline__ int lpad_tq(int t, int lt, int q) {
+  if constexpr (T % 16 == 0)
+    return lt + q * (T + T / 16);
+  else
+    return lpad(t + T * q);
+}
+// lpad(base + r L) from lb = lpad(base), for the Stockham scatter of the
+// register kernels: base mod 16 plus r L mod 16 stays below 16 there
+// (L = 1 with base a multiple of the radix, or k < 8 with L = 8, or L a
+// multiple of 16), so the pad of base + r L is the pad of base plus that
+// of r L.
+__device__ __forceinline__ int lpad_scatter(int lb, int rl) { return lb + rl + (rl >> 4); }
 
 // Synchronisation of the threads of one line.  A line of T <= 64 threads
 // lies inside one wavefront, whose LDS accesses execute in issue order, so
@@ -309,12 +323,13 @@ __device__ __forceinline__ void r16_stage16(cplx<TC>* a, int t, int L, const R16
     for (int r = 0; r < 16; ++r) a[r] = v[r];
   } else {
     const int k = t & (L - 1);
-    const int base = (t - k) * 16 + k;
+    const int lb = lpad((t - k) * 16 + k);
 #pragma unroll
-    for (int r = 0; r < 16; ++r) z[lpad(base + r * L)] = v[r];
+    for (int r = 0; r < 16; ++r) z[lpad_scatter(lb, r * L)] = v[r];
     line_sync<T>();
+    const int lt = lpad(t);
 #pragma unroll
-    for (int q = 0; q < 16; ++q) a[q] = z[lpad(t + T * q)];
+    for (int q = 0; q < 16; ++q) a[q] = z[lpad_tq<T>(t, lt, q)];
     line_sync<T>();
   }
 }
@@ -403,12 +418,13 @@ __device__ __forceinline__ void r8_stage(cplx<TC>* a, int t, int L, cplx<TC> w, 
     for (int r = 0; r < 8; ++r) a[r] = v[r];
   } else {
     const int k = t & (L - 1);
-    const int base = (t - k) * 8 + k;
+    const int lb = lpad((t - k) * 8 + k);
 #pragma unroll
-    for (int r = 0; r < 8; ++r) z[lpad(base + r * L)] = v[r];
+    for (int r = 0; r < 8; ++r) z[lpad_scatter(lb, r * L)] = v[r];
     line_sync<T>();
+    const int lt = lpad(t);
 #pragma unroll
-    for (int q = 0; q < 8; ++q) a[q] = z[lpad(t + T * q)];
+    for (int q = 0; q < 8; ++q) a[q] = z[lpad_tq<T>(t, lt, q)];
     line_sync<T>();
   }
 }
@@ -694,12 +710,12 @@ dct_rad(LineArgs<TC> A) {
       tile_load([&](int n) { return vpad(line_pos<PER>(n, N)); });
     }
 #pragma unroll
-    for (int q = 0; q < RT; ++q) a[q] = z[lpad(t + T * q)];
+    for (int q = 0; q < RT; ++q) a[q] = z[lpad_tq<T>(t, lpad(t), q)];
     line_sync<T>();
     rad_fft<TC, false, LOGH, RT>(a, t, tw, tw8, Tb.twH, z);
     // partner exchange: Z[H-k] next to Z[k]
 #pragma unroll
-    for (int q = 0; q < RT; ++q) z[lpad(t + T * q)] = a[q];
+    for (int q = 0; q < RT; ++q) z[lpad_tq<T>(t, lpad(t), q)] = a[q];
     line_sync<T>();
     TC rest = TC(0), x0 = TC(0);
     if (OP == OP_FDI) {
@@ -907,7 +923,7 @@ dct_rad(LineArgs<TC> A) {
     }
   };
 #pragma unroll
-  for (int q = 0; q < RT; ++q) zi[lpad(ti + T * q)] = {a[q].re * sc, a[q].im * sc};
+  for (int q = 0; q < RT; ++q) zi[lpad_tq<T>(ti, lpad(ti), q)] = {a[q].re * sc, a[q].im * sc};
   if (rows) {
     // back to natural order through LDS, then coalesced stores
     line_sync<T>();
