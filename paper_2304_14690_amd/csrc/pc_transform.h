@@ -140,14 +140,15 @@ __device__ __forceinline__ double resid_at(const double* __restrict__ b,
 }
 
 // ---- register-resident radix-16 line transform ------------------------------
-// For H = N/2 >= 16, every line is handled by T = H/16 threads; thread t holds
-// the 16 complex values a[q] = z[t + T q] of the half-length FFT input.  The
-// Stockham stages are radix 16 followed by one stage of radix 2^(log2 H mod
-// 4): every stage reads only the thread's own values, scatters its outputs
-// through LDS (the last stage is in place), so an FFT of 1024 points costs
-// two LDS exchanges.  The cosine-transform split needs Z[H-k] next to Z[k]
-// (one exchange); the fused forward/divide/inverse then recomputes the
-// partner's outputs instead of exchanging them again.
+// For H = N/2 >= 16, every line is handled by T = H/RT threads (RT = 16 or
+// 8 values per thread); thread t holds the RT complex values a[q] =
+// z[t + T q] of the half-length FFT input.  The Stockham stages are radix RT
+// followed by one stage of the remaining radix: every stage reads only the
+// thread's own values and scatters its outputs through LDS (the last stage
+// is in place), so a radix-16 FFT of 1024 points costs two LDS exchanges.
+// The real-FFT split needs Z[H-k] next to Z[k] (one exchange); the fused
+// forward/divide/inverse exchanges the divided spectrum once more for the
+// inverse split, which needs slots H-k and H+k next to k and N-k.
 
 template <typename TC, bool INV>
 __device__ __forceinline__ void dft4(cplx<TC>& a0, cplx<TC>& a1, cplx<TC>& a2, cplx<TC>& a3) {
