@@ -29,7 +29,7 @@ namespace pc {
 
 namespace {
 
-// Radix-16 transform tiles: threads per workgroup for contiguous rows, and
+// Register-transform tiles: threads per workgroup for contiguous rows, and
 // the thread cap for the strided (column/pencil) passes.
 constexpr int ROW_THREADS = 256;
 constexpr int COL_MAX_THREADS = 512;

@@ -139,7 +139,7 @@ __device__ __forceinline__ double resid_at(const double* __restrict__ b,
   return resid_ijk<VERTEX>(b, phi, p, i, j, k, d, n0, n1, n2, perm, ih2, rscale);
 }
 
-// ---- register-resident radix-16 line transform ------------------------------
+// ---- register-resident radix-16/8 line transform ----------------------------
 // For H = N/2 >= 16, every line is handled by T = H/RT threads (RT = 16 or
 // 8 values per thread); thread t holds the RT complex values a[q] =
 // z[t + T q] of the half-length FFT input.  The Stockham stages are radix RT
