@@ -205,9 +205,11 @@ int solve_mixed(const pc_plan* P, const double* b, double* phi, int sweeps, doub
                 pc_workspace* ws, hipStream_t s, double sigma = 1.0,
                 const int32_t* skip = nullptr);
 int ensure_plan_ws(const pc_plan* P, pc_workspace** ws);
-// Lines per workgroup tile of the radix-16/8 transform along `axis` for
-// elements of `elem` bytes (0 when the axis is shorter than 32).
-int r16_tile_lines(const pc_plan* P, int axis, size_t elem);
+// Complex values per thread of the register transform (radix-8 plan).
+constexpr int RAD_VALUES = 8;
+// Lines per workgroup tile of the register transform along `axis` for
+// elements of `elem` bytes (0 when the axis uses the generic kernel).
+int rad_tile_lines(const pc_plan* P, int axis, size_t elem);
 // Whether the resident IB-iteration transforms apply to this plan/geometry/mode.
 bool resident_ok(const pc_plan* P, const pc_geom* g, int mode);
 // Upper bound of the total length of the six tile lists.

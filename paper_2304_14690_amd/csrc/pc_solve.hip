@@ -787,9 +787,6 @@ void tile_shape(int axis, int N, int lines_x, int64_t groups, int* C, int* nthr,
 
 }  // namespace
 
-// Complex values per thread of the transforms along `axis`: 16, or 8 when
-// the pass has too few lines to give the device four wavefronts per SIMD
-// with 16 (a 2D grid; small 3D grids), which doubles the wavefronts.
 // Radices of the generic kernel's FFT of half length H: eights, then a four
 // or a two, then the odd primes.
 int generic_radices(int H, int* rad) {
@@ -811,23 +808,12 @@ int generic_radices(int H, int* rad) {
 
 bool pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
 
-int pass_radix(const pc_plan* P, int axis) {
-  const int64_t N = P->n[axis];
-  const int64_t lines = P->G / N;
-  const int64_t t16 = N / 32;  // threads per line with 16 values each
-  const int64_t waves16 = (lines * t16 + 63) / 64;
-  // the fused pass of the last axis holds twice the data of the others:
-  // radix 8 keeps it within 128 registers
-  if (axis == P->d - 1) return 8;
-  return waves16 < 4 * 1024 ? 8 : 16;
-}
-
-// Lines per workgroup tile of the radix-16/8 transform along `axis` (0 when
-// the axis uses the generic kernel, N < 32).
-int r16_tile_lines(const pc_plan* P, int axis, size_t elem) {
+// Lines per workgroup tile of the register transform along `axis` (0 when
+// the axis uses the generic kernel: N < 32 or not a power of two).
+int rad_tile_lines(const pc_plan* P, int axis, size_t elem) {
   const int N = P->n[axis];
   if (N < 32 || !pow2(N)) return 0;
-  const int H = N / 2, T = H / pass_radix(P, axis), LS = H + H / 16 + 1;
+  const int H = N / 2, T = H / RAD_VALUES, LS = H + H / 16 + 1;
   const int64_t lines = P->G / N;
   int C;
   // C divides the row count (rows) or the x extent (strided lines), which
@@ -936,10 +922,10 @@ int launch_pass(const pc_plan* P, int axis, const TI* in, TO* out, const AxisTab
   }
   if (A.N >= 32 && pow2(A.N)) {
     // register kernel: T = H/RT threads per line, C lines per group
-    const int RT = pass_radix(P, axis);
+    constexpr int RT = RAD_VALUES;
     const int T = H / RT;
     const int LS = H + H / 16 + 1;
-    const int C = r16_tile_lines(P, axis, sizeof(TC));
+    const int C = rad_tile_lines(P, axis, sizeof(TC));
     if ((size_t)C * LS * 2 * sizeof(TC) > (size_t)lds_limit())
       return fail(PC_ERR_UNSUPPORTED_SIZE, "transform line does not fit in LDS");
     A.C = C;
@@ -1173,11 +1159,11 @@ bool resident_ok(const pc_plan* P, const pc_geom* g, int mode) {
 }
 
 int64_t resident_tiles_max(const pc_plan* P, size_t elem) {
-  const int C0 = r16_tile_lines(P, 0, elem);
+  const int C0 = rad_tile_lines(P, 0, elem);
   int64_t t0 = C0 > 0 ? P->G / P->n[0] / C0 : 0;
   int64_t t1 = 0;
   if (P->d == 3) {
-    const int C1 = r16_tile_lines(P, 1, elem);
+    const int C1 = rad_tile_lines(P, 1, elem);
     t1 = C1 > 0 ? P->G / P->n[1] / C1 : 0;
   }
   return 3 * (t0 + t1);
@@ -1187,7 +1173,7 @@ void resident_tiles(const pc_plan* P, size_t elem, const std::vector<int32_t>& n
                     const std::vector<int32_t>& ib_base, int m, std::vector<int32_t> out[6]) {
   for (int l = 0; l < 6; ++l) out[l].clear();
   const int64_t n0 = P->n[0], n1 = P->n[1], n2 = P->d == 3 ? P->n[2] : 1;
-  const int C0 = r16_tile_lines(P, 0, elem);
+  const int C0 = rad_tile_lines(P, 0, elem);
   const int64_t t0 = n1 * n2 / C0;  // x-line tiles: line j + n1 k, tile line / C0
   std::vector<char> f0(t0, 0), i0(t0, 0);
   for (int32_t q : near_pts) f0[(q / n0) / C0] = 1;
@@ -1214,7 +1200,7 @@ void resident_tiles(const pc_plan* P, size_t elem, const std::vector<int32_t>& n
   }
   if (P->d == 3) {
     // y-line tiles: C1 adjacent x positions of one plane k, tile = k * tx + i / C1
-    const int C1 = r16_tile_lines(P, 1, elem);
+    const int C1 = rad_tile_lines(P, 1, elem);
     const int64_t tx = n0 / C1;
     std::vector<char> nearplane(n2, 0);
     for (int32_t q : near_pts) nearplane[q / (n0 * n1)] = 1;

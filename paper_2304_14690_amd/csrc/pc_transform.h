@@ -1,5 +1,5 @@
 // Line-transform kernels shared by the translation units that instantiate
-// them: the register-resident radix-16/8 transforms of one grid axis, as a
+// them: the register-resident radix-8 transforms of one grid axis, as a
 // cosine transform (homogeneous Neumann condition, Eq. 7) or as a packed
 // real Fourier transform (periodic axis), and the argument block of every
 // transform launch.  Included by pc_solve.hip (Neumann axes) and
@@ -139,13 +139,13 @@ __device__ __forceinline__ double resid_at(const double* __restrict__ b,
   return resid_ijk<VERTEX>(b, phi, p, i, j, k, d, n0, n1, n2, perm, ih2, rscale);
 }
 
-// ---- register-resident radix-16/8 line transform ----------------------------
-// For H = N/2 >= 16, every line is handled by T = H/RT threads (RT = 16 or
-// 8 values per thread); thread t holds the RT complex values a[q] =
-// z[t + T q] of the half-length FFT input.  The Stockham stages are radix RT
+// ---- register-resident radix-8 line transform --------------------------------
+// For H = N/2 >= 16, every line is handled by T = H/RT threads (RT = 8
+// values per thread); thread t holds the RT complex values a[q] =
+// z[t + T q] of the half-length FFT input.  The Stockham stages are radix 8
 // followed by one stage of the remaining radix: every stage reads only the
 // thread's own values and scatters its outputs through LDS (the last stage
-// is in place), so a radix-16 FFT of 1024 points costs two LDS exchanges.
+// is in place), so a radix-8 FFT of 1024 points costs three LDS exchanges.
 // The real-FFT split needs Z[H-k] next to Z[k] (one exchange); the fused
 // forward/divide/inverse exchanges the divided spectrum once more for the
 // inverse split, which needs slots H-k and H+k next to k and N-k.
@@ -181,33 +181,6 @@ __device__ __forceinline__ cplx<TC> w16(cplx<TC> a) {
 }
 
 template <typename TC, bool INV>
-__device__ __forceinline__ void dft16(cplx<TC>* a) {
-  // n = 4 n1 + n2, k = k1 + 4 k2
-#pragma unroll
-  for (int n2 = 0; n2 < 4; ++n2) dft4<TC, INV>(a[n2], a[4 + n2], a[8 + n2], a[12 + n2]);
-  // a[4 k1 + n2] *= W16^(n2 k1)
-  a[5] = w16<TC, INV, 1>(a[5]);
-  a[6] = w16<TC, INV, 2>(a[6]);
-  a[7] = w16<TC, INV, 3>(a[7]);
-  a[9] = w16<TC, INV, 2>(a[9]);
-  a[10] = w16<TC, INV, 4>(a[10]);
-  a[11] = w16<TC, INV, 6>(a[11]);
-  a[13] = w16<TC, INV, 3>(a[13]);
-  a[14] = w16<TC, INV, 6>(a[14]);
-  a[15] = w16<TC, INV, 9>(a[15]);
-#pragma unroll
-  for (int k1 = 0; k1 < 4; ++k1) dft4<TC, INV>(a[4 * k1], a[4 * k1 + 1], a[4 * k1 + 2], a[4 * k1 + 3]);
-  // a[4 k1 + k2] = A[k1 + 4 k2]: transpose to natural order
-  cplx<TC> o[16];
-#pragma unroll
-  for (int k1 = 0; k1 < 4; ++k1)
-#pragma unroll
-    for (int k2 = 0; k2 < 4; ++k2) o[k1 + 4 * k2] = a[4 * k1 + k2];
-#pragma unroll
-  for (int i = 0; i < 16; ++i) a[i] = o[i];
-}
-
-template <typename TC, bool INV>
 __device__ __forceinline__ void dft8(cplx<TC>* a) {  // a[0..7], natural order in and out
   dft4<TC, INV>(a[0], a[2], a[4], a[6]);
   dft4<TC, INV>(a[1], a[3], a[5], a[7]);
@@ -227,7 +200,6 @@ __device__ __forceinline__ void dft8(cplx<TC>* a) {  // a[0..7], natural order i
 
 template <typename TC, bool INV, int R>
 __device__ __forceinline__ void dftR(cplx<TC>* a) {
-  if (R == 16) dft16<TC, INV>(a);
   if (R == 8) dft8<TC, INV>(a);
   if (R == 4) dft4<TC, INV>(a[0], a[1], a[2], a[3]);
   if (R == 2) {
@@ -278,104 +250,12 @@ __device__ __forceinline__ void line_sync() {
   }
 }
 
-// Per-thread twiddle state of the radix-16 FFT, loaded once per launch so
-// that no table load sits on the critical path of a stage:
-//   the radix-16 stage with L = 16: butterfly j = t, k = t mod 16; the
-//   factors w^(r k) come from w^k and w^(4k) by at most two products;
-//   the final stage of radix R < 16: butterflies j = t + T b with k = j, and
-//   w^k = w^t w^(T b) where w^(T b) is the same for the whole wavefront.
-template <typename TC>
-struct R16Tw {
-  cplx<TC> w1, w4;  // radix-16 stage with L = 16
-  cplx<TC> fin;     // final stage: twH[t]
-};
-
-template <typename TC>
-__device__ __forceinline__ void twiddle_r16(cplx<TC>* v, cplx<TC> w1, cplx<TC> w4, bool inv) {
-  cplx<TC> p[4], q4[4];
-  p[0] = {TC(1), TC(0)};
-  p[1] = w1;
-  p[2] = cmul(w1, w1);
-  p[3] = cmul(p[2], w1);
-  q4[0] = {TC(1), TC(0)};
-  q4[1] = w4;
-  q4[2] = cmul(w4, w4);
-  q4[3] = cmul(q4[2], w4);
-#pragma unroll
-  for (int r = 1; r < 16; ++r) {
-    cplx<TC> w = (r >> 2) == 0 ? p[r & 3] : ((r & 3) == 0 ? q4[r >> 2] : cmul(q4[r >> 2], p[r & 3]));
-    v[r] = inv ? cmulc(v[r], w) : cmul(v[r], w);
-  }
-}
-
-// One radix-16 Stockham stage (L = 1 or 16) on the thread's 16 values.
-// LAST: outputs stay in the thread's own slots; otherwise they go through
-// the line's LDS region z and come back in the z[t + T q] layout.
-template <typename TC, bool INV, bool LAST, int T>
-__device__ __forceinline__ void r16_stage16(cplx<TC>* a, int t, int L, const R16Tw<TC>& tw,
-                                            cplx<TC>* z) {
-  cplx<TC> v[16];
-#pragma unroll
-  for (int r = 0; r < 16; ++r) v[r] = a[r];
-  if (L > 1) twiddle_r16(v, tw.w1, tw.w4, INV);
-  dft16<TC, INV>(v);
-  if (LAST) {
-#pragma unroll
-    for (int r = 0; r < 16; ++r) a[r] = v[r];
-  } else {
-    const int k = t & (L - 1);
-    const int lb = lpad((t - k) * 16 + k);
-#pragma unroll
-    for (int r = 0; r < 16; ++r) z[lpad_scatter(lb, r * L)] = v[r];
-    line_sync<T>();
-    const int lt = lpad(t);
-#pragma unroll
-    for (int q = 0; q < 16; ++q) a[q] = z[lpad_tq<T>(t, lt, q)];
-    line_sync<T>();
-  }
-}
-
-// The final stage of radix R < 16 (always in place: L = H / R > j).
-template <typename TC, bool INV, int R>
-__device__ __forceinline__ void r16_final(cplx<TC>* a, int T, const R16Tw<TC>& tw,
-                                          const cplx<TC>* __restrict__ twH) {
-  constexpr int NB = 16 / R;
-#pragma unroll
-  for (int b = 0; b < NB; ++b) {
-    cplx<TC> v[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) v[r] = a[b + NB * r];
-    const cplx<TC> w = b ? cmul(tw.fin, ldu(twH + T * b)) : tw.fin;  // twH[t + T b]
-    cplx<TC> wr = w;
-#pragma unroll
-    for (int r = 1; r < R; ++r) {
-      v[r] = INV ? cmulc(v[r], wr) : cmul(v[r], wr);
-      if (r + 1 < R) wr = cmul(wr, w);  // w^(r+1)
-    }
-    dftR<TC, INV, R>(v);
-#pragma unroll
-    for (int r = 0; r < R; ++r) a[b + NB * r] = v[r];
-  }
-}
-
-template <typename TC, bool INV, int LOGH>
-__device__ __forceinline__ void r16_fft(cplx<TC>* a, int t, const R16Tw<TC>& tw,
-                                        const cplx<TC>* __restrict__ twH, cplx<TC>* z) {
-  constexpr int H = 1 << LOGH;
-  constexpr int T = H / 16;
-  constexpr int S16 = LOGH / 4;        // radix-16 stages (1 or 2 for H <= 2048)
-  constexpr int RR = 1 << (LOGH % 4);  // final radix (1: none)
-  static_assert(S16 >= 1 && S16 <= 2, "radix-16 plan covers 16 <= H <= 2048");
-  r16_stage16<TC, INV, (S16 == 1 && RR == 1), T>(a, t, 1, tw, z);
-  if (S16 == 2) r16_stage16<TC, INV, (RR == 1), T>(a, t, 16, tw, z);
-  if (RR == 8) r16_final<TC, INV, 8>(a, T, tw, twH);
-  if (RR == 4) r16_final<TC, INV, 4>(a, T, tw, twH);
-  if (RR == 2) r16_final<TC, INV, 2>(a, T, tw, twH);
-}
-
 // ---- radix-8 plan (8 values per thread, T = H/8 threads per line) -------------
-// Used where a pass has few lines (a 2D grid): twice the threads per line of
-// the radix-16 plan, so twice the wavefronts to hide latency with.
+// Radix-8 Stockham stages (the values of a stage are the thread's own; the
+// outputs scatter through LDS) and one final stage of radix 2 or 4.  A
+// radix-16 plan (half the threads per line, fewer stages) was measured no
+// faster in float64 and slower in the mixed mode, where its residual pass
+// held twice the registers.
 
 // Twiddle state of the radix-8 plan: the stage bases w = exp(-+2 pi i k/(8L))
 // for the stages with L = 8 and L = 64 (k = t mod L), and twH[t] for the
@@ -405,8 +285,9 @@ __device__ __forceinline__ void twiddle_r8(cplx<TC>* v, cplx<TC> w) {
 }
 
 // One radix-8 Stockham stage with sub-transform length L on the thread's 8
-// values (butterfly j = t, k = t mod L, inputs at j + T r, outputs at
-// (j - k) 8 + k + r L); see r16_stage16.
+// values: butterfly j = t, k = t mod L, inputs at j + T r (the thread's own
+// values), twiddles w^(k r), an 8-point DFT, outputs to (j - k) 8 + k + r L
+// through LDS and back as the next stage's inputs (in place for the last).
 template <typename TC, bool INV, bool LAST, int T>
 __device__ __forceinline__ void r8_stage(cplx<TC>* a, int t, int L, cplx<TC> w, cplx<TC>* z) {
   cplx<TC> v[8];
@@ -470,13 +351,10 @@ __device__ __forceinline__ void r8_fft(cplx<TC>* a, int t, const R8Tw<TC>& tw,
 }
 
 template <typename TC, bool INV, int LOGH, int RT>
-__device__ __forceinline__ void rad_fft(cplx<TC>* a, int t, const R16Tw<TC>& tw,
-                                        const R8Tw<TC>& tw8, const cplx<TC>* __restrict__ twH,
-                                        cplx<TC>* z) {
-  if constexpr (RT == 16)
-    r16_fft<TC, INV, LOGH>(a, t, tw, twH, z);
-  else
-    r8_fft<TC, INV, LOGH>(a, t, tw8, twH, z);
+__device__ __forceinline__ void rad_fft(cplx<TC>* a, int t, const R8Tw<TC>& tw8,
+                                        const cplx<TC>* __restrict__ twH, cplx<TC>* z) {
+  static_assert(RT == 8, "the register kernel runs the radix-8 plan");
+  r8_fft<TC, INV, LOGH>(a, t, tw8, twH, z);
 }
 
 // exp(-i pi (H-k) / (2N)) = exp(-i pi / 4) conj(exp(-i pi k / (2N))), N = 2H
@@ -557,7 +435,7 @@ __device__ __forceinline__ int xpad(int r) { return r + 2 * (r >> 5); }
 
 // One pass of the line transforms over a tile of C lines: forward (OP_FWD),
 // inverse (OP_INV), or forward, division by the eigenvalues and inverse
-// along the last axis (OP_FDI).  RT complex values per thread (16 or 8),
+// along the last axis (OP_FDI).  RT = 8 complex values per thread,
 // T = H / RT threads per line.
 //   PER = false: DCT-II forward, DCT-III / (2N) inverse (Neumann axis).
 //   PER = true:  packed real DFT of a periodic axis, in the same slots:
@@ -566,11 +444,11 @@ __device__ __forceinline__ int xpad(int r) { return r + 2 * (r >> 5); }
 // Both leave the line's modes in slots whose 1D eigenvalue is a function of
 // the slot index (see the FDI step), so the passes of different axes
 // combine freely.
-// Radix 8 asks for four wavefronts per SIMD (at most 128 VGPRs), which the
-// float64 fused pass would otherwise exceed by a few registers.
+// The kernel asks for four wavefronts per SIMD (at most 128 VGPRs), which
+// the float64 fused pass would otherwise exceed by a few registers.
 template <typename TC, typename TI, typename TO, int OP, int LD, int ST, int LOGH, int RT,
           bool PER>
-__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(RT == 8 ? 4 : 1)))
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4)))
 dct_rad(LineArgs<TC> A) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   if (A.skip && *A.skip) return;
@@ -604,20 +482,10 @@ dct_rad(LineArgs<TC> A) {
   const AxisTables<TC>& Tb = A.tab;
 
   // twiddle state (issued first; in flight with the data loads)
-  R16Tw<TC> tw;
   R8Tw<TC> tw8;
-  if constexpr (RT == 16) {
-    if (LOGH >= 8) {
-      const int step = (H / 256) * (t & 15);
-      tw.w1 = Tb.twH[step];
-      tw.w4 = Tb.twH[4 * step];
-    }
-    if (LOGH % 4) tw.fin = Tb.twH[t];
-  } else {
-    if (LOGH >= 6) tw8.s1 = Tb.twH[(H / 64) * (t & 7)];
-    if (LOGH >= 9) tw8.s2 = Tb.twH[(H / 512) * (t & 63)];
-    if (LOGH % 3) tw8.fin = Tb.twH[t];
-  }
+  if (LOGH >= 6) tw8.s1 = Tb.twH[(H / 64) * (t & 7)];
+  if (LOGH >= 9) tw8.s2 = Tb.twH[(H / 512) * (t & 63)];
+  if (LOGH % 3) tw8.fin = Tb.twH[t];
   const cplx<TC> tNb = Tb.tN[t];
   const cplx<TC> t4b = Tb.t4N[t];
 
@@ -713,7 +581,7 @@ dct_rad(LineArgs<TC> A) {
 #pragma unroll
     for (int q = 0; q < RT; ++q) a[q] = z[lpad_tq<T>(t, lpad(t), q)];
     line_sync<T>();
-    rad_fft<TC, false, LOGH, RT>(a, t, tw, tw8, Tb.twH, z);
+    rad_fft<TC, false, LOGH, RT>(a, t, tw8, Tb.twH, z);
     // partner exchange: Z[H-k] next to Z[k]
 #pragma unroll
     for (int q = 0; q < RT; ++q) z[lpad_tq<T>(t, lpad(t), q)] = a[q];
@@ -895,8 +763,6 @@ dct_rad(LineArgs<TC> A) {
     // opaque twiddle state: otherwise the forward FFT's twiddle powers stay
     // live through the division for reuse (as conjugates) in the inverse,
     // which halves the occupancy
-    asm volatile("" : "+v"(tw.w1.re), "+v"(tw.w1.im), "+v"(tw.w4.re), "+v"(tw.w4.im));
-    asm volatile("" : "+v"(tw.fin.re), "+v"(tw.fin.im));
     asm volatile("" : "+v"(tw8.s1.re), "+v"(tw8.s1.im), "+v"(tw8.s2.re), "+v"(tw8.s2.im));
     asm volatile("" : "+v"(tw8.fin.re), "+v"(tw8.fin.im));
   }
@@ -905,7 +771,7 @@ dct_rad(LineArgs<TC> A) {
   asm volatile("" : "+v"(zoff));
   // from the LDS base itself, so that the accesses stay LDS instructions
   cplx<TC>* zi = reinterpret_cast<cplx<TC>*>(smem_raw) + zoff;
-  rad_fft<TC, true, LOGH, RT>(a, ti, tw, tw8, Tb.twH, zi);
+  rad_fft<TC, true, LOGH, RT>(a, ti, tw8, Tb.twH, zi);
   const TC sc = A.outscale * (PER ? TC(0.5) : TC(0.25));  // undoes pre_own*_x2/_x4
   // The stores hit the same addresses as the loads; opaque copies of the
   // line base and stride make the compiler recompute them here instead of
@@ -953,8 +819,6 @@ int rad_launch(const LineArgs<TC>& A, int key, dim3 grid, dim3 block, size_t lds
   switch (key) {
 #define PC_RAD_CASE(LH, R) \
     case LH * 32 + R: fn = (const void*)dct_rad<TC, TI, TO, OP, LD, ST, LH, R, PER>; break;
-    PC_RAD_CASE(4, 16) PC_RAD_CASE(5, 16) PC_RAD_CASE(6, 16) PC_RAD_CASE(7, 16)
-    PC_RAD_CASE(8, 16) PC_RAD_CASE(9, 16) PC_RAD_CASE(10, 16) PC_RAD_CASE(11, 16)
     PC_RAD_CASE(4, 8) PC_RAD_CASE(5, 8) PC_RAD_CASE(6, 8) PC_RAD_CASE(7, 8)
     PC_RAD_CASE(8, 8) PC_RAD_CASE(9, 8) PC_RAD_CASE(10, 8) PC_RAD_CASE(11, 8)
 #undef PC_RAD_CASE
@@ -967,8 +831,6 @@ int rad_launch(const LineArgs<TC>& A, int key, dim3 grid, dim3 block, size_t lds
     case LH * 32 + R: \
       hipLaunchKernelGGL((dct_rad<TC, TI, TO, OP, LD, ST, LH, R, PER>), grid, block, lds, s, A); \
       break;
-    PC_RAD_LAUNCH(4, 16) PC_RAD_LAUNCH(5, 16) PC_RAD_LAUNCH(6, 16) PC_RAD_LAUNCH(7, 16)
-    PC_RAD_LAUNCH(8, 16) PC_RAD_LAUNCH(9, 16) PC_RAD_LAUNCH(10, 16) PC_RAD_LAUNCH(11, 16)
     PC_RAD_LAUNCH(4, 8) PC_RAD_LAUNCH(5, 8) PC_RAD_LAUNCH(6, 8) PC_RAD_LAUNCH(7, 8)
     PC_RAD_LAUNCH(8, 8) PC_RAD_LAUNCH(9, 8) PC_RAD_LAUNCH(10, 8) PC_RAD_LAUNCH(11, 8)
 #undef PC_RAD_LAUNCH

@@ -1,6 +1,6 @@
 """Edge cases of the sub-step against the float64 oracle: no obstacle (no IB
 iteration), anisotropic and non-square grids, axes shorter than the
-radix-16 transform (generic path), the largest grid stencil, a warm start
+register transform (generic path), the largest grid stencil, a warm start
 of the IB force, the corner gauge, and the iteration cap."""
 import math
 
