@@ -2,8 +2,8 @@
 condition of the paper's verification cases, Sec. 3) and mixed periodic x
 Neumann boxes, against the oracle's DFT/DCT solve: float64 to 1e-11,
 float32 to 5e-5, float32 transforms with float64 defect correction to 1e-10
-(relative L2).  Shapes cover both register plans (8 and 16 values per
-thread), the generic kernel on a short Neumann axis next to a periodic one,
+(relative L2).  Shapes cover the register kernel on both axes, the
+generic kernel on a short Neumann axis next to a periodic one,
 the longest axis (4096), the full 2048^2 and 256^3 sizes, and a discrete
 eigenfunction with a sine phase at full size."""
 import numpy as np
