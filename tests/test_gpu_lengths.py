@@ -4,9 +4,10 @@ lengths 16 ... 2048: one to three radix-8 stages and a final stage of radix
 Neumann axis, Eq. 7) and as a packed real DFT (periodic axis), in float64,
 float32 and float32 transforms with float64 defect correction, against the
 oracle's solve (float64 to 1e-11, float32 to 5e-5, the correction to 1e-10,
-relative L2).  The other axis is 16 points long (the generic kernel, whose
-pass the register kernel's output feeds or reads) or 32 (register kernel on
-both axes)."""
+relative L2).  In 2D the other axis is 16 points long (the generic kernel,
+whose pass the register kernel's output feeds or reads) or 32 (register
+kernel on both axes); in 3D the long axis is the middle one (the strided
+pass between two generic axes) or the last one (the fused pass)."""
 import numpy as np
 import pytest
 
@@ -22,6 +23,10 @@ for N in LENGTHS:
     for bc in (NE, P):
         CASES.append(((N, 16), (bc, NE)))   # long x rows, generic last axis
         CASES.append(((32, N), (NE, bc)))   # long last axis (fused pass)
+for N in LENGTHS:
+    for bc in (NE, P):
+        CASES.append(((16, N, 8), (NE, bc, NE)))   # 3D middle axis (strided pass)
+        CASES.append(((8, 16, N), (P, NE, bc)))    # 3D last axis (fused pass)
 IDS = ["x".join(map(str, n)) + "-" + "".join(b[0] for b in bc) for n, bc in CASES]
 
 
@@ -35,10 +40,11 @@ def pc():
 @pytest.mark.parametrize("n,bc", CASES, ids=IDS)
 def test_register_lengths_all_modes(pc, n, bc):
     import torch
+    d = len(n)
     h = tuple(1.0 / v for v in n)
-    grid = Grid(2, n, h, bc)
-    plan = pc.Plan(2, n, h, bc=bc)
-    rng = np.random.Generator(np.random.PCG64(4000 + n[0] + 7 * n[1]))
+    grid = Grid(d, n, h, bc)
+    plan = pc.Plan(d, n, h, bc=bc)
+    rng = np.random.Generator(np.random.PCG64(4000 + n[0] + 7 * n[1] + 13 * n[-1]))
     b = rng.normal(size=grid.G) + 0.3
     phi_ref, bm_ref = poisson.solve(grid, b)
     bt = torch.from_numpy(b).cuda()
