@@ -177,3 +177,73 @@ def test_sample_stencils_equal_full_build():
     np.testing.assert_array_equal(gcf, st.grid_coef[gp])
     np.testing.assert_array_equal(ni, st.node_idx[nd])
     np.testing.assert_array_equal(ncf, st.node_coef[nd])
+
+
+def _dense_history(st, u, K):
+    """The IB iteration of Sec. 2.3 written out with dense matrices (the
+    transfers assembled entry by entry, the Poisson solve as the
+    pseudo-inverse of the dense Laplacian), and the criterion sums of every
+    iteration added up point by point: [(num_1, den_1), ..., (num_K, den_K)]."""
+    M, d = u.shape
+    D, Gn = _dense(st, M, d)
+    Lp = np.linalg.pinv(poisson.laplacian_dense(st.grid), rcond=1e-12)
+    uf = u.T.reshape(-1)
+    g = np.zeros(d * M)
+    out = []
+    for _ in range(K):
+        grad = Gn @ (Lp @ (D @ (uf + g)))
+        num = den = 0.0
+        for n in st.ib:
+            new = [-uf[a * M + n] + grad[a * M + n] for a in range(d)]
+            old = [g[a * M + n] for a in range(d)]
+            mag_new = np.sqrt(sum(v * v for v in new))
+            mag_old = np.sqrt(sum(v * v for v in old))
+            num += (mag_new - mag_old) ** 2
+            den += mag_old ** 2
+            for a in range(d):
+                g[a * M + n] = new[a]
+        out.append((num, den))
+    return out
+
+
+def test_ib_stops_at_first_qualifying_iteration():
+    """The loop of Sec. 2.3 stops at the FIRST iteration whose criterion
+    holds (iteration 1 from a zero force has a zero denominator and never
+    does), reports convergence only then, and stops unconverged at the cap."""
+    c = _tiny_case(seed=13)
+    st = _stencils(c)
+    u = c.u.T.copy()
+    K = 12
+    hist = _dense_history(st, u, K)
+    assert hist[0][1] == 0.0
+    ratios = [num / den if den > 0 else np.inf for num, den in hist]
+
+    def first_stop(tol):
+        for it, (num, den) in enumerate(hist, start=1):
+            if num < tol * den or num == 0.0:
+                return it
+        return None
+
+    # the default tolerance, and tolerances placed between consecutive
+    # ratios so that a stop one iteration early or late changes n_it
+    tols = [1e-3]
+    for j in range(1, K - 1):
+        lo, hi = sorted((ratios[j], ratios[j + 1]))
+        if lo > 0 and hi / lo > 1.01:
+            tols.append(float(np.sqrt(lo * hi)))
+    assert len(tols) >= 4
+    for tol in tols:
+        want = first_stop(tol)
+        assert want is not None and want >= 2
+        r = P.pressure_correct(st, u, tol=tol)
+        assert r["n_it"] == want, (tol, r["n_it"], want)
+        assert r["converged"]
+        num, den = r["history"][-1]
+        np.testing.assert_allclose([num, den], hist[want - 1], rtol=1e-9)
+        if want > 2:
+            # capped one short of the stop: unconverged, at the cap
+            rc = P.pressure_correct(st, u, tol=tol, max_it=want - 1)
+            assert rc["n_it"] == want - 1 and not rc["converged"]
+        # capped exactly at the stop: converged
+        rc = P.pressure_correct(st, u, tol=tol, max_it=want)
+        assert rc["n_it"] == want and rc["converged"]
