@@ -178,10 +178,13 @@ int pc_last_error(char* buf, size_t n);
  * while work it queued on its stream still uses it: the pair must order
  * reuse after that stream's work (as a caching allocator bound to the same
  * stream does) or wait for it.  (NULL, NULL) restores
- * hipMalloc/hipFree.  The pair can be replaced only while no allocation made
- * through the installed one is outstanding (every object created with it
- * destroyed): otherwise PC_ERR_INVALID_ARG.  Pinned host memory (the
- * convergence flags of a workspace) still comes from hipHostMalloc. */
+ * hipMalloc/hipFree.  Every allocation is returned to whoever gave it out:
+ * objects created before a pair was installed go back to hipFree, objects
+ * created through a pair go back to that pair's free.  The pair can be
+ * replaced only while no allocation made through it is outstanding (every
+ * object created with it destroyed): otherwise PC_ERR_INVALID_ARG.  Pinned
+ * host memory (the convergence flags of a workspace) still comes from
+ * hipHostMalloc. */
 typedef int (*pc_alloc_fn)(void* user, size_t bytes, void** ptr);
 typedef void (*pc_free_fn)(void* user, void* ptr);
 int pc_set_allocator(pc_alloc_fn alloc, pc_free_fn free_fn, void* user);
@@ -194,7 +197,9 @@ int pc_set_allocator(pc_alloc_fn alloc, pc_free_fn free_fn, void* user);
  * tables of the cosine transforms and the 1D eigenvalues
  * -(4/h_a^2) sin^2(pi k / (2 n_a)) of the mirror-ghost central-difference
  * Laplacian (homogeneous Neumann condition, Eq. 7), and uploads them (plus
- * float32 copies).  n[a] must be even and in [8, 4096].  Powers of two of
+ * float32 copies).  n[a] must be even and in [8, 4096], and the grid may
+ * hold at most 2^31 - 2 points (flat grid indices are int32; larger grids
+ * give PC_ERR_UNSUPPORTED_SIZE).  Powers of two of
  * at least 32 take the register-resident transform kernels; other lengths
  * (such as the 400 x 402 and 280 x 480 grids of Sec. 3) take a mixed-radix
  * kernel staged in LDS whose cost per line grows with the sum of the prime

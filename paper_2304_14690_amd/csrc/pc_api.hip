@@ -2,10 +2,10 @@
 // solve.  Geometry entry points live in pc_wls.hip, the transfers and the
 // whole sub-step in pc_step.hip.
 #include <algorithm>
-#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <mutex>
+#include <unordered_map>
 
 #include "pc_internal.h"
 
@@ -23,33 +23,42 @@ int fail(int code, const std::string& msg) {
 }
 
 namespace {
-// the caller's allocator (pc_set_allocator), and the number of its
-// allocations not yet returned
+// The caller's allocator (pc_set_allocator), and the owner of every live
+// allocation made through an installed pair: each pointer is returned to the
+// pair that gave it out, whatever is installed when it is freed, and a
+// pointer with no record came from hipMalloc.  A pair cannot be replaced
+// while allocations of it are live (its `user` may not outlive the swap).
+struct Owner {
+  pc_free_fn free_fn;
+  void* user;
+};
 std::mutex g_alloc_mu;
 pc_alloc_fn g_alloc = nullptr;
 pc_free_fn g_free = nullptr;
 void* g_alloc_user = nullptr;
-std::atomic<int64_t> g_alloc_live{0};
+std::unordered_map<void*, Owner> g_owner;
 }  // namespace
 
 int dev_alloc(void** p, size_t bytes, const char* what) {
   *p = nullptr;
   if (bytes == 0) return PC_OK;
   pc_alloc_fn fa;
+  pc_free_fn ff;
   void* user;
   {
     std::lock_guard<std::mutex> lk(g_alloc_mu);
     fa = g_alloc;
+    ff = g_free;
     user = g_alloc_user;
-    if (fa) ++g_alloc_live;
   }
   if (fa) {
     if (fa(user, bytes, p) != 0 || !*p) {
-      --g_alloc_live;
       *p = nullptr;
       return fail(PC_ERR_OOM, std::string("the installed allocator failed for ") + what + " (" +
                                   std::to_string(bytes) + " bytes)");
     }
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    g_owner[*p] = Owner{ff, user};
     return PC_OK;
   }
   hipError_t e = hipMalloc(p, bytes);
@@ -64,19 +73,19 @@ int dev_alloc(void** p, size_t bytes, const char* what) {
 
 void dev_free(void* p) {
   if (!p) return;
-  pc_free_fn ff;
-  void* user;
+  Owner o{nullptr, nullptr};
   {
     std::lock_guard<std::mutex> lk(g_alloc_mu);
-    ff = g_free;
-    user = g_alloc_user;
+    auto it = g_owner.find(p);
+    if (it != g_owner.end()) {
+      o = it->second;
+      g_owner.erase(it);
+    }
   }
-  if (ff) {
-    ff(user, p);
-    --g_alloc_live;
-  } else {
+  if (o.free_fn)
+    o.free_fn(o.user, p);
+  else
     (void)hipFree(p);
-  }
 }
 
 namespace {
@@ -179,7 +188,7 @@ int pc_set_allocator(pc_alloc_fn alloc, pc_free_fn free_fn, void* user) {
   if ((alloc == nullptr) != (free_fn == nullptr))
     return fail(PC_ERR_INVALID_ARG, "pc_set_allocator: give both functions or neither");
   std::lock_guard<std::mutex> lk(g_alloc_mu);
-  if (g_alloc_live.load() != 0)
+  if (!g_owner.empty())
     return fail(PC_ERR_INVALID_ARG,
                 "pc_set_allocator: allocations of the installed allocator are outstanding");
   g_alloc = alloc;
@@ -226,6 +235,14 @@ int pc_plan_create_ex(int d, const int32_t* n, const double* h, const int32_t* b
     }
     if (!(h[a] > 0.0) || !std::isfinite(h[a]))
       return fail(PC_ERR_INVALID_ARG, "h[a] must be positive and finite");
+  }
+  {
+    // flat grid indices are stored as int32 (stencil sources, block corners
+    // and their one's-complement wrap mark)
+    int64_t G = 1;
+    for (int a = 0; a < d; ++a) G *= n[a];
+    if (G > (int64_t)INT32_MAX - 1)
+      return fail(PC_ERR_UNSUPPORTED_SIZE, "the grid has more than 2^31 - 2 points");
   }
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {

@@ -137,9 +137,11 @@ class Scheduler:
             need += self.ex.workspace_bytes(r.key, r.mode)
         return need
 
-    def _evict_for(self, need: int, keep: GeomKey) -> bool:
+    def _evict_for(self, need: int, keep: GeomKey, keep_mode: int) -> bool:
         """Frees idle residents, least recently used first, until `need`
-        bytes fit.  Returns whether they fit."""
+        bytes fit.  The geometry `keep` and its pooled workspaces of
+        `keep_mode` stay: `need` was computed counting on them.  Returns
+        whether they fit."""
         while self._held() + need > self.budget:
             victim = None
             for k, g in self.geoms.items():  # oldest first
@@ -150,7 +152,7 @@ class Scheduler:
                 # pooled workspaces of idle geometries go with them; a pooled
                 # workspace of `keep` in another mode can go alone
                 for (k, m), ws in self.ws_pool.items():
-                    if ws:  # pooled workspaces are idle by definition
+                    if ws and (k, m) != (keep, keep_mode):  # pooled ones are idle
                         w = ws.pop()
                         self.ex.free_workspace(w.handle)
                         self.evictions += 1
@@ -236,7 +238,7 @@ class Scheduler:
                         if need > self.budget:
                             raise MemoryError(f"request {r.rid} needs {need} bytes, "
                                               f"more than the budget {self.budget}")
-                        if not self._evict_for(need, r.key):
+                        if not self._evict_for(need, r.key, r.mode):
                             i += 1
                             continue
                         # admit r

@@ -75,3 +75,42 @@ def test_caller_allocator(pc):
     finally:
         gc.collect()
         pc.set_allocator(None, None)
+
+
+def test_objects_return_to_their_own_allocator(pc):
+    """A plan and geometry made on hipMalloc memory and destroyed while a
+    caller's pair is installed go back to hipFree: the pair's free is never
+    called for them, and the pair can be removed afterwards."""
+    import torch
+    c = inputs.make_case("alloc2", 2, 64, [inputs.Obstacle("circle", (0.5, 0.5), (0.1,))],
+                         12, 12, 8, 63, 64)
+    plan = pc.Plan(c.d, c.n, c.h)
+    geom = pc.wls_build(plan, torch.from_numpy(c.x).cuda(), torch.from_numpy(c.kind).cuda(),
+                        c.k_grid, c.k_node)
+    torch.cuda.synchronize()
+    alloc, free = pc.torch_allocator()
+    seen = {"alloc": set(), "freed": []}
+
+    def a(nbytes):
+        ptr = alloc(nbytes)
+        seen["alloc"].add(ptr)
+        return ptr
+
+    def f(ptr):
+        seen["freed"].append(ptr)
+        free(ptr)
+
+    pc.set_allocator(a, f)
+    try:
+        del geom, plan
+        gc.collect()
+        assert seen["freed"] == []
+        # objects made through the pair go back to it, hipMalloc ones do not
+        plan2 = pc.Plan(c.d, c.n, c.h)
+        del plan2
+        gc.collect()
+        assert seen["freed"] and set(seen["freed"]) <= seen["alloc"]
+        assert len(seen["freed"]) == len(seen["alloc"])
+    finally:
+        gc.collect()
+        pc.set_allocator(None, None)

@@ -169,3 +169,22 @@ def test_same_geometry_built_once_under_concurrency():
     out = sch.run(reqs)
     assert ex.built == [(3, 32, 0)]
     assert sum(r.built for r in out) == 1
+
+
+def test_pooled_workspace_counted_on_is_not_evicted():
+    """Admission that counts on a pooled workspace (and so leaves its bytes
+    out of the need) must not free that workspace to make room: the request
+    would then allocate a new one beyond the budget."""
+    sizes = {(2, 64): (100, 50, 20), (2, 8): (10, 10, 10)}
+    service = {(2, 64): 0.002, (2, 8): 0.08}
+    ex = FakeExecutor(sizes, service)
+    reqs = [serve.Request(0, 0.0, 2, 64, 0, 0, F64),
+            serve.Request(1, 0.001, 2, 8, 0, 0, F64),   # long-running
+            serve.Request(2, 0.03, 2, 64, 0, 0, F64)]   # A again, while B runs
+    sch = serve.Scheduler(ex, budget=195, slots=2)
+    out = {r.rid: r for r in sch.run(reqs)}
+    assert ex.peak <= 195 and sch.peak_bytes <= 195
+    # A waited for B: the only room was A's own pooled workspace
+    assert out[2].admitted >= out[1].done - 1e-3
+    sch.release()
+    assert ex.held == 0
