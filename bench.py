@@ -1,20 +1,22 @@
 #!/usr/bin/env python3
 """Benchmark of the hybrid pressure-correction sub-step on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload 2d2048]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload 3d512]
+                    [--extra 2d2048]
 
 Workloads (all inputs seeded and synthetic, resident in HBM before timing):
-  2d2048  2048^2 cell-centred grid on the unit square, 4.2M jittered-lattice
-          nodes (jitter +-0.3h), a cylinder of radius 0.05 at (0.3, 0.5)
-          whose interior nodes are virtual points and whose surface carries
-          the boundary points, 16-neighbour WLS stencils, 32 random Fourier
-          modes, Neumann box.  The throughput metric is quoted on this one.
+  3d512   512^3 grid, 134M jittered-lattice nodes (jitter +-0.3h), a sphere of
+          radius 0.1 at (0.3, 0.5, 0.5) plus the box [0.6, 0.8] x [0.4, 0.6]^2
+          whose interior nodes are virtual points and whose surfaces carry the
+          boundary points, 27-neighbour WLS stencils, 64 random Fourier modes,
+          Neumann box; float64, and float32 transforms with 2 and 3 float64
+          defect-correction sweeps against all-float64.  The largest
+          single-GPU workload: the headline is quoted on it.
+  2d2048  2048^2 grid, 4.2M nodes, a cylinder of radius 0.05 at (0.3, 0.5),
+          16-neighbour stencils, 32 modes; float64, float32 and float32 +
+          float64 correction.  Run after the headline (--extra).
   3d256   256^3 grid, 16.8M nodes, sphere of radius 0.1 at the centre,
           27-neighbour stencils, 64 modes.
-  3d512   512^3 grid, 134M nodes, sphere of radius 0.1 at (0.3, 0.5, 0.5) plus
-          the box [0.6, 0.8] x [0.4, 0.6]^2, 27-neighbour stencils, 64 modes;
-          float32 transforms with 2 and 3 float64 defect-correction sweeps
-          against all-float64.
   2d2048p 2d2048 with a periodic x axis (a channel: periodic lateral faces,
           as in the paper's verification cases, Sec. 3) and Neumann walls in y.
   3d256p  3d256 with periodic x and z axes and Neumann walls in y.
@@ -35,9 +37,9 @@ gradient and projection) from a zero IB force.
 
 One JSON line is printed: grid-points/s of the float64 sub-step, p50/p99 step
 latency, the other precisions with their error against float64, per-kernel
-HIP-event timings with the roofline of the dominant kernel, the serving loop
-(2d2048 only, unless --serve-seconds 0), and the CPU oracle timed on this
-host on a bounded sample.
+HIP-event timings with the roofline of the dominant kernel and of the whole
+sub-step, the extra workloads, the serving loop (unless --serve-seconds 0),
+and the CPU oracle timed on this host on a bounded sample.
 """
 from __future__ import annotations
 
@@ -88,6 +90,9 @@ WORKLOADS = {
                         "nodes (node spacing 1/2048), cylinder r=0.05 at (0.3,0.5), 16-NN WLS, "
                         "32-mode velocity, Neumann box, cold IB start"},
     "3d512": {"d": 3, "N": 512, "modes": "f64,mixed,mixed3", "cpu_N": 64,
+              "cpu_note": "the oracle's stencils of the 512^3 workload need ~230 GB of host "
+                          "memory and hours of build; 64^3 (same obstacles, k, modes) runs "
+                          "in seconds",
               "desc": "3D 512^3 grid, {M} jittered nodes, sphere r=0.1 at (0.3,0.5,0.5) plus "
                       "box [0.6,0.8]x[0.4,0.6]^2, 27-NN WLS, 64-mode velocity, Neumann box, "
                       "cold IB start"},
@@ -99,8 +104,11 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="2d2048", choices=list(WORKLOADS))
-    ap.add_argument("--size", type=int, default=0, help="override N of the workload")
+    ap.add_argument("--workload", default="3d512", choices=list(WORKLOADS))
+    ap.add_argument("--extra", default="2d2048",
+                    help="comma list of workloads run after the headline one (reported "
+                         "under 'extra'); empty: none")
+    ap.add_argument("--size", type=int, default=0, help="override N of the headline workload")
     ap.add_argument("--modes", default="", help="comma list of f64, f32, mixed, mixed3")
     ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -109,7 +117,8 @@ def parse():
                     help="also run a plain device copy of known size (counter scaling)")
     ap.add_argument("--serve-seconds", type=float, default=3.0,
                     help="length of the serving trace (0: no serving run)")
-    ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--serve-rate", type=str, default="200,800",
+                    help="comma list of arrival rates (requests/s) of the serving runs")
     ap.add_argument("--serve-geoms", type=int, default=2,
                     help="geometries per grid size in the serving pool")
     ap.add_argument("--serve-only", action="store_true")
@@ -192,26 +201,43 @@ def rel_l2(a, b):
     return float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(json.dumps({"error": "this library runs the sub-step on one GPU; "
-                                   "--gpus above 1 is not supported (see the sharding "
-                                   "design notes)", "n_gpus": args.gpus}))
-        sys.exit(2)
+def bytes_solve_mode(G, d, mode, sweeps):
+    """Algorithmic bytes of one Poisson solve: 2d - 1 passes, each reading and
+    writing the grid once.  In the correction mode the first pass reads the
+    float64 right-hand side and writes float32, the last reads float32 and
+    writes float64; each sweep's first pass reads b and phi (float64) and
+    writes float32, its last pass reads float32 and phi and writes phi."""
+    if mode == "f64":
+        return bytes_solve(G, d, 8)
+    if mode == "f32":
+        return bytes_solve(G, d, 4)
+    mid = 8 * (2 * d - 3)
+    return G * ((12 + mid + 12) + sweeps * (20 + mid + 20))
+
+
+def bytes_step(G, M, k, bn, d, mode, sweeps, n_it, n_near, near_entries, n_ib):
+    """Algorithmic bytes of one sub-step: the RHS transfer at every grid
+    point, n_it solves, the near-IB RHS update in every iteration after the
+    first (the B+V entries of the near stencils, b_u read and b written at
+    each near point), the IB step (gradient at the B+V nodes, force update)
+    in every iteration, and the final gradient fused with the projection."""
+    s = 4 if mode == "f32" else 8
+    near = near_entries * (4 + d * s) + n_near * 2 * s
+    ibstep = n_ib * (bn * d * s + 4 + 3 * d * s)
+    return (bytes_div_all(G, M, k, d, s) + bytes_grad_project(G, M, bn, d, s)
+            + n_it * (bytes_solve_mode(G, d, mode, sweeps) + ibstep) + (n_it - 1) * near)
+
+
+def run_workload(args, name, N, modes_arg):
+    """Times the sub-step of one workload in each mode and its kernels;
+    returns a dict (the device memory is released on return)."""
     import torch
     from paper_2304_14690_amd import pcorr as pc
-
-    torch.cuda.init()
-    if args.serve_only:
-        print(json.dumps({"serving": serving(args)}))
-        return
-    wl = WORKLOADS[args.workload]
-    dev = torch.cuda.current_device()
+    wl = WORKLOADS[name]
     stream = torch.cuda.current_stream()
-    N = args.size or wl["N"]
+    print(f"bench: workload {name} N={N}", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
-    case = make_workload(args.workload, N)
+    case = make_workload(name, N)
     torch.cuda.synchronize()
     t_gen = time.perf_counter() - t0
     d = case["d"]
@@ -221,20 +247,23 @@ def main():
     x = torch.from_numpy(case["x"]).cuda()
     kind = torch.from_numpy(case["kind"]).cuda()
     case["x"] = None
-    modes = [m for m in (args.modes or wl["modes"]).split(",") if m]
+    modes = [m for m in (modes_arg or wl["modes"]).split(",") if m]
     want_f32 = "f32" in modes
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     # whole time steps only on a box without faces (the first fractional step
     # has no velocity condition of its own on them)
+    time_steps = args.time_steps
     if not (case["bc"] and all(b == "periodic" for b in case["bc"])):
-        args.time_steps = 0
-    k_self = (16 if d == 2 else 20) if args.time_steps > 0 else 0
+        time_steps = 0
+    k_self = (16 if d == 2 else 20) if time_steps > 0 else 0
     geom = pc.wls_build(plan, x, kind, case["k"], case["k"], want_f32=want_f32,
                         delta=case.get("delta", 0.0), k_self=k_self)
     torch.cuda.synchronize()
     t_build = time.perf_counter() - t0
     del x, kind
+    print(f"bench: {name} generated in {t_gen:.1f} s, stencils built in {t_build:.2f} s",
+          file=sys.stderr, flush=True)
 
     results = {}
     ref = None
@@ -260,14 +289,23 @@ def main():
         torch.cuda.synchronize()
         total = time.perf_counter() - t_start
         lat_ms = sorted(1e3 * v for v in lat)
+        sec = total / args.steps
+        nb = bytes_step(G, M, geom.k_grid, geom.bn, d, "mixed" if mname == "mixed3" else mname,
+                        sweeps, stats["n_it"], geom.n_near, geom.near_entries, geom.n_ib)
         results[mname] = {
-            "value": G / (total / args.steps),
-            "ms_per_step": 1e3 * total / args.steps,
+            "value": G / sec,
+            "ms_per_step": 1e3 * sec,
             "p50_ms": float(np.percentile(lat_ms, 50)),
             "p99_ms": float(np.percentile(lat_ms, 99)),
             "n_it": stats["n_it"],
             "converged": stats["converged"],
+            "sweeps": sweeps if mode == pc.PC_MIXED else None,
+            "step_bytes": nb,
+            "step_GBs": round(nb / sec / 1e9, 1),
+            "step_frac": round(nb / sec / 1e9 / HBM_PEAK_GBS, 4),
         }
+        print(f"bench: {name} {mname}: {1e3 * sec:.3f} ms/step, n_it {stats['n_it']}",
+              file=sys.stderr, flush=True)
         if mname == "f64":
             ref = (uo.clone(), p.clone(), stats["n_it"])
         elif ref is not None:
@@ -278,7 +316,6 @@ def main():
                                         "fixed_it": ref[2]}
         del ws, u, uo, p
     del ref
-
 
     # ---- per-kernel HIP-event timings (same kernels, same launch shapes) ----------
     def time_launches(fn, reps):
@@ -327,13 +364,13 @@ def main():
     dom = max(single, key=lambda n: kern[n]["s"] * kern[n]["launches_per_step"])
     roof = {"bound": "hbm", "achieved": round(kern[dom]["GBs"], 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(kern[dom]["frac"], 4),
-            "traffic": measured_traffic(kern[dom]["kernel"], args.workload, G),
+            "traffic": measured_traffic(kern[dom]["kernel"], name, G),
             "kernel": kern[dom]["kernel"], "call": dom, "bytes_per_launch": kern[dom]["bytes"],
             "avg_launch_us": round(kern[dom]["us"], 2)}
 
     # ---- whole time steps: the first fractional step (Eq. 3) + the sub-step --------
     timestep = None
-    if args.time_steps > 0:
+    if time_steps > 0:
         from paper_2304_14690_amd.timeloop import TimeStepper
         # dt at a convective CFL number of 0.1 for the largest speed of the
         # random-mode field
@@ -348,18 +385,18 @@ def main():
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         n_its = []
-        for _ in range(args.time_steps):
+        for _ in range(time_steps):
             st = ts.step(u, u2)
             n_its.append(st["n_it"])
             u, u2 = u2, u
         torch.cuda.synchronize()
-        t_step = (time.perf_counter() - t0) / args.time_steps
+        t_step = (time.perf_counter() - t0) / time_steps
         r = torch.empty_like(u)
         us = torch.empty_like(u)
         t_mom = time_launches(lambda: pc.momentum_predict(geom, u, ts.r_prev, dt_ts, nu_ts, r, us),
                               reps)
         bm = bytes_momentum(M, k_self, d, 8)
-        timestep = {"ms_per_time_step": round(1e3 * t_step, 4), "steps": args.time_steps,
+        timestep = {"ms_per_time_step": round(1e3 * t_step, 4), "steps": time_steps,
                     "dt": dt_ts, "nu": nu_ts, "k_self": k_self,
                     "n_it_per_step": [min(n_its), max(n_its)],
                     "momentum_predict": {"kernel": f"k_momentum<double,{d},{k_self}>",
@@ -377,21 +414,61 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    del geom, u64, b64, phi64, gr64, case
+    info = {"G": G, "M": M, "k": k, "n_ib": geom.n_ib, "n_near": geom.n_near,
+            "build_s": round(t_build, 3), "gen_s": round(t_gen, 3)}
+    del geom, plan, u64, b64, phi64, gr64, case
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
+    f64 = results.get("f64") or next(iter(results.values()))
+    step_roof = {"bound": "hbm", "achieved": f64["step_GBs"], "peak": HBM_PEAK_GBS,
+                 "unit": "GB/s", "frac": f64["step_frac"], "bytes_per_step": f64["step_bytes"],
+                 "what": "whole float64 sub-step: algorithmic bytes (RHS transfer, n_it "
+                         "solves of 2d-1 passes, near-IB updates, IB steps, gradient + "
+                         "projection) over the measured time per step"}
+    return {"name": name, "N": N, "d": d, "desc": wl["desc"].format(M=M), "info": info,
+            "modes": results, "kernels": {n: {kk: (round(vv, 4) if isinstance(vv, float) else vv)
+                                              for kk, vv in v.items()} for n, v in kern.items()},
+            "roofline": roof, "roofline_step": step_roof, "time_step": timestep}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this library runs the sub-step on one GPU; "
+                                   "--gpus above 1 is not supported (see the sharding "
+                                   "design notes)", "n_gpus": args.gpus}))
+        sys.exit(2)
+    import torch
+
+    torch.cuda.init()
+    dev = torch.cuda.current_device()
+    rates = [float(v) for v in args.serve_rate.split(",") if v]
+    if args.serve_only:
+        print(json.dumps({"serving": serving(args, rates)}))
+        return
+    wl = WORKLOADS[args.workload]
+    N = args.size or wl["N"]
+    head = run_workload(args, args.workload, N, args.modes)
+    extras = {}
+    for name in [w for w in args.extra.split(",") if w and w != args.workload]:
+        extras[name] = run_workload(args, name, WORKLOADS[name]["N"], "")
     serving_out = None
-    if args.workload == "2d2048" and args.serve_seconds > 0:
-        serving_out = serving(args)
+    if args.serve_seconds > 0:
+        serving_out = serving(args, rates)
 
     # ---- CPU oracle on a bounded sample ----------------------------------------------
     cpu = None
     if not args.no_cpu_baseline:
+        print("bench: cpu baseline", file=sys.stderr, flush=True)
         cpu = cpu_baseline(args.workload, args.cpu_size or wl["cpu_N"])
+        for name, e in extras.items():
+            # 2D workloads at full size: the oracle's stencils fit in host memory
+            if WORKLOADS[name]["d"] == 2:
+                e["cpu_baseline"] = cpu_baseline(name, e["N"])
 
-    f64 = results.get("f64") or next(iter(results.values()))
+    f64 = head["modes"].get("f64") or next(iter(head["modes"].values()))
     out = {
-        "metric": f"pressure-correction grid-pts/s (float64 sub-step, {N}^{d})",
+        "metric": f"pressure-correction grid-pts/s (float64 sub-step, {N}^{head['d']})",
         "value": f64["value"],
         "unit": "grid-pts/s",
         "n_gpus": 1,
@@ -405,15 +482,14 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": wl["desc"].format(M=M), "G": G, "M": M, "k": k,
-                   "n_it": f64["n_it"], "build_s": round(t_build, 3),
-                   "gen_s": round(t_gen, 3)},
-        "modes": results,
-        "kernels": {n: {kk: (round(vv, 4) if isinstance(vv, float) else vv)
-                        for kk, vv in v.items()} for n, v in kern.items()},
-        "roofline": roof,
+        "config": dict({"workload": head["desc"], "n_it": f64["n_it"]}, **head["info"]),
+        "modes": head["modes"],
+        "kernels": head["kernels"],
+        "roofline": head["roofline"],
+        "roofline_step": head["roofline_step"],
         "cpu_baseline": cpu,
-        "time_step": timestep,
+        "time_step": head["time_step"],
+        "extra": extras,
         "serving": serving_out,
         "device": torch.cuda.get_device_name(dev),
     }
@@ -437,15 +513,17 @@ def kernel_source_digest(name):
     return hashlib.sha256("".join(parts).encode()).hexdigest()[:16]
 
 
-def serving(args):
-    """The continuous-batching loop on a Poisson stream of mixed 2D/3D
-    requests (float64 and float32+float64-correction), against the float64
-    one-at-a-time path on the same arrivals and the same resident stencils."""
+def serving(args, rates):
+    """The continuous-batching loop on Poisson streams of mixed 2D/3D
+    requests (float64 and float32+float64-correction) at each arrival rate,
+    against float64 alone on the same slots and float64 one at a time, on the
+    same arrivals and the same resident stencils."""
     import torch
     from paper_2304_14690_amd import pcorr as pc, serve
     sizes = [(2, 128), (2, 512), (2, 2048), (3, 64), (3, 128), (3, 256)]
     n_geom = {k: args.serve_geoms for k in sizes}
     n_geom[(3, 256)] = min(args.serve_geoms, 4)
+    print("bench: serving", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
     ds = serve.Dataset(sizes, n_geom, 2, seed=9)
     torch.cuda.synchronize()
@@ -462,25 +540,7 @@ def serving(args):
     t0 = time.perf_counter()
     sch.run(warm)
     t_warm = time.perf_counter() - t0
-    n_req = int(round(args.serve_rate * args.serve_seconds))
-    trace = serve.poisson_trace(n_req, args.serve_rate, 9, sizes, n_geom, 2,
-                                [pc.PC_F64, pc.PC_MIXED])
-    mix = sch.run(trace)
-    s_mix = serve.summarize(mix)
-    s_mix["evictions"] = sch.evictions
-    s_mix["peak_gb"] = round(sch.peak_bytes / 2**30, 2)
-    s_mix["not_converged"] = sum(1 for r in mix if r.rc != 0)
-    base = [serve.Request(r.rid, r.arrival, r.d, r.N, r.geom, r.vel, pc.PC_F64) for r in trace]
-    out_f64 = sch.run(base)
-    s_f64 = serve.summarize(out_f64)
-    base = [serve.Request(r.rid, r.arrival, r.d, r.N, r.geom, r.vel, pc.PC_F64) for r in trace]
-    sch.slots = 1
-    out_base = sch.run(base)
-    s_base = serve.summarize(out_base)
-    sch.release()
-    del ex, sch, ds
-    torch.cuda.synchronize()
-    torch.cuda.empty_cache()
+
     def by_size(reqs):
         out = {}
         for (d, N) in sizes:
@@ -489,17 +549,44 @@ def serving(args):
                 out[f"{N}^{d}"] = {"n": len(lat), "p50_ms": round(float(np.percentile(lat, 50)), 3),
                                    "p99_ms": round(float(np.percentile(lat, 99)), 3)}
         return out
-    per_size = {"mix": by_size(mix), "fp64_batched": by_size(out_f64),
-                "fp64_one_at_a_time": by_size(out_base)}
-    return {"workload": f"Poisson arrivals {args.serve_rate:g}/s for {args.serve_seconds:g} s, "
-                        "sizes uniform over 128^2, 512^2, 2048^2, 64^3, 128^3, 256^3, "
-                        "precision uniform over f64 and f32+f64 correction (2 sweeps), "
+
+    runs = []
+    for rate in rates:
+        n_req = int(round(rate * args.serve_seconds))
+        trace = serve.poisson_trace(n_req, rate, 9, sizes, n_geom, 2, [pc.PC_F64, pc.PC_MIXED])
+        sch.slots = slots
+        mix = sch.run(trace)
+        s_mix = serve.summarize(mix)
+        s_mix["evictions"] = sch.evictions
+        s_mix["peak_gb"] = round(sch.peak_bytes / 2**30, 2)
+        s_mix["not_converged"] = sum(1 for r in mix if r.rc != 0)
+        base = [serve.Request(r.rid, r.arrival, r.d, r.N, r.geom, r.vel, pc.PC_F64)
+                for r in trace]
+        out_f64 = sch.run(base)
+        s_f64 = serve.summarize(out_f64)
+        base = [serve.Request(r.rid, r.arrival, r.d, r.N, r.geom, r.vel, pc.PC_F64)
+                for r in trace]
+        sch.slots = 1
+        out_base = sch.run(base)
+        s_base = serve.summarize(out_base)
+        print(f"bench: serving at {rate:g}/s done", file=sys.stderr, flush=True)
+        runs.append({
+            "workload": f"Poisson arrivals {rate:g}/s for {args.serve_seconds:g} s, sizes uniform "
+                        "over 128^2, 512^2, 2048^2, 64^3, 128^3, 256^3, precision uniform over "
+                        "f64 and f32+f64 correction (2 sweeps), "
                         f"{slots} slots, stencils resident per geometry (LRU under the HBM "
                         "budget)",
-            "geometries": sum(n_geom.values()), "budget_gb": round(budget / 2**30, 1),
+            "rate": rate, "geometries": sum(n_geom.values()),
+            "budget_gb": round(budget / 2**30, 1),
             "setup_s": {"data": round(t_data, 2), "warm_build": round(t_warm, 2)},
             "mix": s_mix, "fp64_batched": s_f64, "fp64_one_at_a_time": s_base,
-            "per_size": per_size}
+            "per_size": {"mix": by_size(mix), "fp64_batched": by_size(out_f64),
+                         "fp64_one_at_a_time": by_size(out_base)}})
+    sch.release()
+    del ex, sch, ds
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    return runs
 
 
 def measured_traffic(kernel, workload, G):
@@ -563,9 +650,11 @@ def cpu_baseline(workload, N):
         times.append(time.perf_counter() - t0)
         n_it = r["n_it"]
     t = statistics.median(times)
+    note = WORKLOADS[workload].get("cpu_note") if N != WORKLOADS[workload]["N"] else None
     return {"value": c.G / t, "unit": "grid-pts/s", "cores": cores, "kind": "oracle",
             "sample": f"the same workload at {N}^{c.d} ({c.M} nodes), float64 oracle sub-step, "
-                      f"median of 3, n_it={n_it}; stencil build {t_build:.1f}s not timed",
+                      f"median of 3, n_it={n_it}; stencil build {t_build:.1f}s not timed"
+                      + (f" ({note})" if note else ""),
             "s_per_step": t}
 
 

@@ -159,7 +159,7 @@ typedef struct pc_stats {
 
 /* ---- library ------------------------------------------------------------ */
 
-/* ABI version (major*100 + minor): 112. */
+/* ABI version (major*100 + minor): 113. */
 int pc_version(void);
 
 /* Copies the calling thread's last error message into buf (NUL-terminated,
@@ -285,8 +285,10 @@ int pc_geom_destroy(pc_geom* geom);
 
 /* Sizes of a geometry: counts[0] = M, [1] = number of B+V nodes, [2] =
  * number of near-IB grid points, [3] = k_grid, [4] = k_node block size
- * m^d, [5] = device bytes held by the geometry. */
-int pc_geom_info(const pc_geom* geom, int64_t* counts6);
+ * m^d, [5] = device bytes held by the geometry, [6] = number of B+V entries
+ * over all near-IB stencils, [7] = width of the near-IB table (8, 16 or
+ * 32).  counts8 holds 8 values. */
+int pc_geom_info(const pc_geom* geom, int64_t* counts8);
 
 /* Copies the stencils out (for inspection and tests).
  *   grid_idx_dev  int32   [k_grid][G]      node index, in ascending order
@@ -304,6 +306,21 @@ int pc_geom_info(const pc_geom* geom, int64_t* counts6);
 int pc_geom_export(const pc_geom* geom, int32_t* grid_idx_dev, double* grid_coef_dev,
                    int32_t* node_base_dev, double* node_coef_dev, int32_t* ib_dev,
                    int32_t* near_dev, void* stream);
+
+/* The stencils of selected targets (for inspection and tests where a whole
+ * export does not fit in device memory, such as 512^3 grids):
+ *   grid_pts_dev  int64   [n_grid]            flat grid indices
+ *   grid_idx_dev  int32   [k_grid][n_grid]    as in pc_geom_export, per target
+ *   grid_coef_dev float64 [d][k_grid][n_grid]
+ *   nodes_dev     int64   [n_nodes]           node indices
+ *   node_base_dev int32   [n_nodes]
+ *   node_coef_dev float64 [d][m^d][n_nodes]
+ * Output pointers may be NULL.  Synchronises `stream`; an index out of range
+ * gives PC_ERR_INVALID_ARG (the other targets are still copied). */
+int pc_geom_export_at(const pc_geom* geom, const int64_t* grid_pts_dev, int64_t n_grid,
+                      int32_t* grid_idx_dev, double* grid_coef_dev, const int64_t* nodes_dev,
+                      int64_t n_nodes, int32_t* node_base_dev, double* node_coef_dev,
+                      void* stream);
 
 /* Copies the node-to-node stencils out (geometry built with k_self > 0):
  *   idx_dev  int32   [k_self][M]       neighbour node indices, ascending (the

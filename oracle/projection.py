@@ -94,24 +94,67 @@ def _lengths(grid: Grid, x: np.ndarray):
     return tuple(out)
 
 
+def window_candidates(targets: np.ndarray, x: np.ndarray, w: float,
+                      chunk: int = 1 << 24) -> np.ndarray:
+    """Ascending indices of the nodes x [M, d] that lie in the cubes of side
+    w adjacent to (or holding) a target's cube, cubes taken at multiples of
+    w.  Every node closer than w to a target is among them (its cube index
+    differs by at most one per axis)."""
+    d = x.shape[1]
+    ct = np.floor(targets / w).astype(np.int64)
+    lo = min(int(ct.min()), int(np.floor(x.min() / w))) - 1
+    hi = max(int(ct.max()), int(np.floor(x.max() / w))) + 1
+    nc = hi - lo + 1
+    if nc ** d > 1 << 28:
+        raise ValueError("candidate window too fine for the extent of the cloud")
+    mark = np.zeros(nc ** d, dtype=bool)
+    shifts = np.stack(np.meshgrid(*[np.arange(-1, 2)] * d, indexing="ij"), -1).reshape(-1, d)
+    for sh in shifts:
+        c = ct + sh - lo
+        key = np.zeros(c.shape[0], dtype=np.int64)
+        for a in reversed(range(d)):
+            key = key * nc + c[:, a]
+        mark[key] = True
+    out = []
+    for s in range(0, x.shape[0], chunk):
+        c = np.floor(x[s:s + chunk] / w).astype(np.int64) - lo
+        key = np.zeros(c.shape[0], dtype=np.int64)
+        for a in reversed(range(d)):
+            key = key * nc + c[:, a]
+        out.append(s + np.flatnonzero(mark[key]))
+    return np.concatenate(out)
+
+
 def sample_stencils(grid: Grid, x: np.ndarray, k_grid: int, k_node: int,
                     grid_pts: np.ndarray, nodes: np.ndarray,
                     eps: float = _wls.EPS_DEFAULT, support: float = _wls.SUPPORT_DEFAULT,
                     delta: Optional[float] = None, workers: int = -1,
-                    image_margin: Optional[float] = None):
+                    image_margin: Optional[float] = None, window: Optional[float] = None):
     """The stencils of build_stencils for a subset of targets only: the
     grid points `grid_pts` (flat indices) over all nodes x [M, d], and the
     nodes `nodes` over the grid.  For checks at sizes where building every
     stencil on the CPU is too slow.  image_margin: on a periodic box, keep
     only the periodic images within this distance of the box (the neighbour
-    search raises if a stencil reaches further).  Returns (grid_idx
-    [S, k_g], grid_coef [S, d, k_g], node_idx [T, k_n], node_coef
-    [T, d, k_n])."""
+    search raises if a stencil reaches further).  window (non-periodic
+    grids): search the grid points' neighbours only among the nodes of
+    window_candidates(..., window), and raise if a k-th neighbour is not
+    closer than the window (then a nearer node could have been missed).
+    Returns (grid_idx [S, k_g], grid_coef [S, d, k_g], node_idx [T, k_n],
+    node_coef [T, d, k_n])."""
     delta = _wls.default_delta(grid.h) if delta is None else float(delta)
     lengths = _lengths(grid, x)
     centres = grid.centres()
     gc = centres[grid_pts]
-    gi, gd2 = _knn.knn(gc, x, k_grid, workers=workers, lengths=lengths, margin=image_margin)
+    if window is not None:
+        if lengths is not None:
+            raise ValueError("the candidate window is for grids without periodic axes")
+        cand = window_candidates(gc, x, window)
+        li, gd2 = _knn.knn(gc, x[cand], k_grid, workers=workers)
+        if not np.all(gd2[:, -1] < window * window * (1.0 - 1e-9)):
+            raise ValueError("a k-th neighbour reaches the edge of the candidate window")
+        gi = cand[li]
+    else:
+        gi, gd2 = _knn.knn(gc, x, k_grid, workers=workers, lengths=lengths, margin=image_margin)
     Xg = _knn.offsets(gc, x, gi, lengths) if lengths else None
     gcoef, _, _ = _wls.derivative_coefficients(gc, x, gi, gd2, delta, eps, support, X=Xg)
     xn = x[nodes]

@@ -858,6 +858,50 @@ __global__ void __launch_bounds__(256) k_base_export(const int32_t* __restrict__
   }
 }
 
+// Stencils of selected targets, for inspection: grid stencils of the grid
+// points pts[t] and node stencils of the nodes nds[t] (one thread per target
+// and array); an index out of range sets *bad and is skipped.
+__global__ void __launch_bounds__(256) k_export_at(const int32_t* __restrict__ gidx,
+                                                   const double* __restrict__ gcoef, int64_t G,
+                                                   int kg, int d, const int64_t* __restrict__ pts,
+                                                   int64_t np_, int32_t* __restrict__ oidx,
+                                                   double* __restrict__ ocoef,
+                                                   const int32_t* __restrict__ nbase,
+                                                   const double* __restrict__ ncoef, int64_t M,
+                                                   int64_t ms, int bn,
+                                                   const int64_t* __restrict__ nds, int64_t nn,
+                                                   int32_t* __restrict__ obase,
+                                                   double* __restrict__ oncoef,
+                                                   int32_t* __restrict__ bad) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t < np_) {
+    const int64_t p = pts[t];
+    if (p < 0 || p >= G) {
+      *bad = 1;
+    } else {
+      for (int i = 0; i < kg; ++i) {
+        if (oidx) oidx[(int64_t)i * np_ + t] = gidx[(int64_t)i * G + p];
+        if (ocoef)
+          for (int a = 0; a < d; ++a)
+            ocoef[((int64_t)a * kg + i) * np_ + t] = gcoef[((int64_t)a * kg + i) * G + p];
+      }
+    }
+  }
+  if (t < nn) {
+    const int64_t n = nds[t];
+    if (n < 0 || n >= M) {
+      *bad = 1;
+    } else {
+      if (obase) {
+        const int32_t v = nbase[n];
+        obase[t] = v < 0 ? ~v : v;
+      }
+      if (oncoef)
+        for (int r = 0; r < d * bn; ++r) oncoef[(int64_t)r * nn + t] = ncoef[(int64_t)r * ms + n];
+    }
+  }
+}
+
 int scan_exclusive(const int32_t* in, int64_t n, int32_t* out, hipStream_t s) {
   int64_t nb = (n + SCAN_B - 1) / SCAN_B;
   int64_t* bsum = nullptr;
@@ -1182,6 +1226,8 @@ int pc_geom_info(const pc_geom* g, int64_t* c) {
   c[3] = g->k_grid;
   c[4] = g->bn;
   c[5] = g->bytes;
+  c[6] = g->n_near_entries;
+  c[7] = g->near_w;
   return PC_OK;
 }
 
@@ -1222,6 +1268,30 @@ int pc_geom_export(const pc_geom* g, int32_t* gidx, double* gcoef, int32_t* nbas
                                   hipMemcpyDeviceToDevice, s));
   PC_TRY(cp(ib, g->ib, (size_t)g->n_ib * 4));
   PC_TRY(cp(near, g->near, (size_t)g->n_near * 4));
+  return PC_OK;
+}
+
+int pc_geom_export_at(const pc_geom* g, const int64_t* grid_pts, int64_t n_grid,
+                      int32_t* grid_idx, double* grid_coef, const int64_t* nodes, int64_t n_nodes,
+                      int32_t* node_base, double* node_coef, void* stream) {
+  if (!g) return fail(PC_ERR_INVALID_ARG, "pc_geom_export_at: null geometry");
+  if (n_grid < 0 || n_nodes < 0 || (n_grid && !grid_pts) || (n_nodes && !nodes))
+    return fail(PC_ERR_INVALID_ARG, "pc_geom_export_at: bad target list");
+  const int64_t n = std::max(n_grid, n_nodes);
+  if (n == 0) return PC_OK;
+  hipStream_t s = as_stream(stream);
+  Scratch tmp;
+  int32_t* bad;
+  PC_TRY(tmp.alloc((void**)&bad, 256, "flags"));
+  PC_TRY(fill_zero(bad, 256, s));
+  hipLaunchKernelGGL(k_export_at, dim3(nblocks(n, 256)), dim3(256), 0, s, g->gidx, g->gcoef, g->G,
+                     g->k_grid, g->d, grid_pts, n_grid, grid_idx, grid_coef, g->nbase, g->ncoef,
+                     g->M, g->ms, g->bn, nodes, n_nodes, node_base, node_coef, bad);
+  PC_HIP_CHECK(hipGetLastError());
+  int32_t hbad = 0;
+  PC_HIP_CHECK(hipMemcpyAsync(&hbad, bad, 4, hipMemcpyDeviceToHost, s));
+  PC_HIP_CHECK(hipStreamSynchronize(s));
+  if (hbad) return fail(PC_ERR_INVALID_ARG, "pc_geom_export_at: target index out of range");
   return PC_OK;
 }
 

@@ -46,7 +46,7 @@ EXPORTS = [
     "pc_geom_export", "pc_div_to_grid", "pc_grad_to_nodes", "pc_ib_update", "pc_project",
     "pc_workspace_create", "pc_workspace_destroy", "pc_workspace_bytes",
     "pc_pressure_correct", "pc_geom_export_self", "pc_momentum_predict", "pc_momentum_pressure",
-    "pc_set_allocator",
+    "pc_set_allocator", "pc_geom_export_at",
 ]
 
 # pc_alloc_fn / pc_free_fn
@@ -116,6 +116,7 @@ def _load():
                                  ctypes.POINTER(IbOpts), ctypes.POINTER(Stats), vp, vp],
                                 ctypes.c_int),
         "pc_geom_export_self": ([vp, vp, vp, vp], ctypes.c_int),
+        "pc_geom_export_at": ([vp, vp, i64, vp, vp, vp, i64, vp, vp, vp], ctypes.c_int),
         "pc_momentum_predict": ([vp, ctypes.c_int, vp, vp, dbl, dbl, vp, vp, vp, vp],
                                 ctypes.c_int),
         "pc_momentum_pressure": ([vp, ctypes.c_int, vp, vp, vp, vp, dbl, vp, vp], ctypes.c_int),
@@ -221,9 +222,10 @@ class Geometry:
     def __init__(self, handle, plan: Plan):
         self.h_ = handle
         self.plan = plan
-        info = (ctypes.c_int64 * 6)()
+        info = (ctypes.c_int64 * 8)()
         _check(_lib.pc_geom_info(self.h_, info))
-        self.M, self.n_ib, self.n_near, self.k_grid, self.bn, self.bytes = (int(v) for v in info)
+        (self.M, self.n_ib, self.n_near, self.k_grid, self.bn, self.bytes, self.near_entries,
+         self.near_w) = (int(v) for v in info)
 
     def __del__(self):
         if getattr(self, "h_", None) and _lib is not None:
@@ -285,6 +287,20 @@ def geom_export(geom: Geometry, grid_idx=None, grid_coef=None, node_base=None,
     return _check(_lib.pc_geom_export(geom.h_, _ptr(grid_idx), _ptr(grid_coef),
                                       _ptr(node_base), _ptr(node_coef), _ptr(ib), _ptr(near),
                                       _stream(stream)))
+
+
+def geom_export_at(geom: Geometry, grid_pts: Optional[torch.Tensor] = None, grid_idx=None,
+                   grid_coef=None, nodes: Optional[torch.Tensor] = None, node_base=None,
+                   node_coef=None, stream=None) -> int:
+    """Stencils of the grid points grid_pts and the nodes `nodes` (int64
+    device tensors) into [k][S], [d][k][S], [T] and [d][bn][T] tensors."""
+    ng = 0 if grid_pts is None else grid_pts.numel()
+    nn = 0 if nodes is None else nodes.numel()
+    for t in (grid_pts, nodes):
+        assert t is None or t.dtype == torch.int64
+    return _check(_lib.pc_geom_export_at(geom.h_, _ptr(grid_pts), ng, _ptr(grid_idx),
+                                         _ptr(grid_coef), _ptr(nodes), nn, _ptr(node_base),
+                                         _ptr(node_coef), _stream(stream)))
 
 
 def div_to_grid(geom: Geometry, v: torch.Tensor, b: torch.Tensor, subset: int = PC_ALL,

@@ -1,7 +1,9 @@
-"""Parity at the full sizes the benchmark times: the 2048^2 workload (k = 16)
-and the 256^3 workload (k = 27), and their variants with periodic axes
-(2048^2 periodic in x; 256^3 periodic in x and z), through
-pc_pressure_correct with its own workspace, as bench.py runs it.
+"""Parity at the full sizes the benchmark times: the 2048^2 workload (k = 16),
+the 256^3 workload (k = 27), the 512^3 workload (134M nodes, a sphere plus a
+box, k = 27; float32 transforms with 2 and 3 float64 correction sweeps
+against float64), and the variants with periodic axes (2048^2 periodic in x;
+256^3 periodic in x and z), through pc_pressure_correct with its own
+workspace, as bench.py runs it.
 
 The oracle cannot build every stencil of these sizes within a test, so it is
 compared on outputs it computes one by one at sampled targets (random, next
@@ -16,8 +18,15 @@ to the obstacle, on the box faces), and on properties that hold at any size:
     right-hand side D(u* + g^{n-1}) of the last iteration, within a bound
     from the operator's norm;
   * the loop stops at the first iteration that meets the criterion;
-  * float32+float64 correction within 1e-10 and float32 within 5e-5 of the
-    float64 sub-step (which the oracle pins here and at smaller sizes).
+  * float32+float64 correction within 1e-10 (2 sweeps; at 512^3 also 3) and
+    float32 within 5e-5 of the float64 sub-step (which the oracle pins here
+    and at smaller sizes); the correction mode stops after as many IB
+    iterations as float64.  At 512^3 float64 stencils alone take 189 GB, so
+    no float32 copy is built there and the all-float32 mode is checked at
+    the smaller sizes only.
+
+Stencils are read back only at the sampled targets (pc_geom_export_at): a
+whole export would not fit next to the 512^3 geometry.
 """
 import math
 
@@ -35,7 +44,7 @@ SIGMA = 1.5  # phi = (3 dt / 2) p with dt = 1
 
 
 BCS = {"2d2048": None, "3d256": None, "2d2048p": ("periodic", "neumann"),
-       "3d256p": ("periodic", "neumann", "periodic")}
+       "3d256p": ("periodic", "neumann", "periodic"), "3d512": None}
 
 
 def _workload(name):
@@ -45,10 +54,15 @@ def _workload(name):
         c = inputs.make_case(name, 2, 2048, [inputs.Obstacle("circle", (0.3, 0.5), (0.05,))],
                              16, 16, 32, 3, 4, bc=bc)
         return c.d, c.n, c.h, c.x, c.kind, c.k_grid, torch.from_numpy(c.u).cuda()
-    obs = [inputs.Obstacle("sphere", (0.5, 0.5, 0.5), (0.1,))]
-    n, h, x, kind = inputs.make_geometry(3, 256, obs, 5, bc=bc)
+    if name == "3d512":
+        obs = [inputs.Obstacle("sphere", (0.3, 0.5, 0.5), (0.1,)),
+               inputs.Obstacle("box", (0.6, 0.4, 0.4), (0.8, 0.6, 0.6))]
+        N, sn, sv = 512, 7, 8
+    else:
+        obs, N, sn, sv = [inputs.Obstacle("sphere", (0.5, 0.5, 0.5), (0.1,))], 256, 5, 6
+    n, h, x, kind = inputs.make_geometry(3, N, obs, sn, bc=bc)
     xt = torch.from_numpy(x).cuda()
-    u = inputs.fourier_velocity_torch(xt, 64, 6)
+    u = inputs.fourier_velocity_torch(xt, 64, sv)
     u[:, torch.from_numpy(kind).cuda() == inputs.KIND_V] = 0.0
     return 3, n, h, x, kind, 27, u
 
@@ -82,40 +96,49 @@ def _samples(rng, grid, x, ib, near, nsamp=500):
 def test_full_size_sampled_parity(name):
     import torch
     from paper_2304_14690_amd import pcorr as pc
+    print(f"full size: {name}", flush=True)
     d, n, h, x, kind, k, u = _workload(name)
     bc = BCS[name]
+    big = name == "3d512"
     grid = oracle.Grid(d, n, h, bc)
     G, M = grid.G, kind.size
     plan = pc.Plan(d, n, h, bc=bc)
     geom = pc.wls_build(plan, torch.from_numpy(x).cuda(), torch.from_numpy(kind).cuda(), k, k,
-                        want_f32=True)
+                        want_f32=not big)
     nib, nnear, bn = geom.n_ib, geom.n_near, geom.bn
-    gi = torch.empty((k, G), dtype=torch.int32, device="cuda")
-    gcf = torch.empty((d, k, G), dtype=torch.float64, device="cuda")
-    nb = torch.empty(M, dtype=torch.int32, device="cuda")
-    ncf = torch.empty((d, bn, M), dtype=torch.float64, device="cuda")
     ibt = torch.empty(nib, dtype=torch.int32, device="cuda")
     neart = torch.empty(nnear, dtype=torch.int32, device="cuda")
-    pc.geom_export(geom, gi, gcf, nb, ncf, ibt, neart)
+    pc.geom_export(geom, ib=ibt, near=neart)
     torch.cuda.synchronize()
     ib, near = ibt.cpu().numpy().astype(np.int64), neart.cpu().numpy().astype(np.int64)
     assert np.array_equal(ib, np.flatnonzero(kind != inputs.KIND_F))
 
     rng = np.random.Generator(np.random.PCG64(17))
     xs = x.T.copy()
+    del x
     gp, nd = _samples(rng, grid, xs, ib, near)
-    ogi, ogc, oni, onc = P.sample_stencils(grid, xs, k, k, gp, nd, image_margin=8 * max(h))
+    if bc is None:
+        # candidates near the sampled grid points only (no search over the
+        # whole cloud); raises if a stencil reaches the window's edge
+        ogi, ogc, oni, onc = P.sample_stencils(grid, xs, k, k, gp, nd, window=4 * max(h))
+    else:
+        ogi, ogc, oni, onc = P.sample_stencils(grid, xs, k, k, gp, nd, image_margin=8 * max(h))
 
     # stencils at the sampled targets
     gps = torch.from_numpy(gp).cuda()
-    g_idx = gi[:, gps].T.cpu().numpy()
-    g_cf = gcf[:, :, gps].permute(2, 0, 1).cpu().numpy()
+    nds = torch.from_numpy(nd).cuda()
+    gi = torch.empty((k, gp.size), dtype=torch.int32, device="cuda")
+    gcf = torch.empty((d, k, gp.size), dtype=torch.float64, device="cuda")
+    nb = torch.empty(nd.size, dtype=torch.int32, device="cuda")
+    ncf = torch.empty((d, bn, nd.size), dtype=torch.float64, device="cuda")
+    pc.geom_export_at(geom, gps, gi, gcf, nds, nb, ncf)
+    g_idx = gi.T.cpu().numpy()
+    g_cf = gcf.permute(2, 0, 1).cpu().numpy()
     order = np.argsort(ogi, axis=1, kind="stable")
     np.testing.assert_array_equal(g_idx, np.take_along_axis(ogi, order, 1))
     assert rel_l2(g_cf, np.take_along_axis(ogc, order[:, None, :], 2)) <= 1e-12
-    nds = torch.from_numpy(nd).cuda()
-    n_base = nb[nds].cpu().numpy().astype(np.int64)
-    n_cf = ncf[:, :, nds].cpu().numpy()                        # [d, bn, T]
+    n_base = nb.cpu().numpy().astype(np.int64)
+    n_cf = ncf.cpu().numpy()                                   # [d, bn, T]
     m = round(bn ** (1.0 / d))
     stride = np.array([1, n[0], n[0] * (n[1] if d == 3 else 1)])[:d]
     # (entry - corner) mod n: blocks wrap around periodic axes
@@ -177,16 +200,26 @@ def test_full_size_sampled_parity(name):
     print(f"{name}: Poisson residual {res:.2e} (bound {bound:.2e})")
     assert res <= bound
 
-    # the other precisions against float64 at the same iteration count
-    for mode, dtype, tol in ((pc.PC_MIXED, torch.float64, 1e-10),
-                             (pc.PC_F32, torch.float32, 5e-5)):
+    del v, b, g1, uo1, p1, r, bh, bc
+
+    # the other precisions against float64 at the same iteration count, and
+    # the correction mode's own stopping iteration
+    others = [(pc.PC_MIXED, 2, torch.float64, 1e-10)]
+    others += [(pc.PC_MIXED, 3, torch.float64, 1e-10)] if big else \
+        [(pc.PC_F32, 0, torch.float32, 5e-5)]
+    for mode, sweeps, dtype, tol in others:
         wsm = pc.Workspace(plan, geom, mode)
         um = u.to(dtype)
         uom = torch.empty_like(um)
         pm = torch.empty(G, dtype=dtype, device="cuda")
-        pc.pressure_correct(geom, plan, mode, um, 1.0, uom, pm, ws=wsm, fixed_it=n_it)
+        pc.pressure_correct(geom, plan, mode, um, 1.0, uom, pm, ws=wsm, fixed_it=n_it,
+                            sweeps=sweeps or 2)
         torch.cuda.synchronize()
         eu, ep = rel_l2(uom.cpu().numpy(), uoh), rel_l2(pm.cpu().numpy(), ph / SIGMA)
-        print(f"{name}: mode {mode} vs f64: u {eu:.2e} p {ep:.2e}")
+        print(f"{name}: mode {mode} sweeps {sweeps} vs f64: u {eu:.2e} p {ep:.2e}")
         assert eu <= tol and ep <= tol
-        del wsm
+        if mode == pc.PC_MIXED:
+            _, stm = pc.pressure_correct(geom, plan, mode, um, 1.0, uom, pm, ws=wsm,
+                                         sweeps=sweeps)
+            assert stm["n_it"] == n_it and stm["converged"] == 1
+        del wsm, um, uom, pm

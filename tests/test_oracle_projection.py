@@ -247,3 +247,31 @@ def test_ib_stops_at_first_qualifying_iteration():
         # capped exactly at the stop: converged
         rc = P.pressure_correct(st, u, tol=tol, max_it=want)
         assert rc["n_it"] == want and rc["converged"]
+
+
+def test_sample_stencils_window_equals_full_search():
+    """The windowed candidate search gives the rows of the unrestricted one,
+    and refuses a window the k-th neighbour reaches."""
+    from paper_2304_14690_amd import inputs
+    for c in (inputs.config1(),
+              inputs.make_case("w3", 3, 12, [inputs.Obstacle("sphere", (0.4, 0.5, 0.5), (0.2,))],
+                               27, 27, 4, 21, 22)):
+        grid = Grid(c.d, c.n, c.h)
+        x = c.x.T.copy()
+        rng = np.random.Generator(np.random.PCG64(5))
+        gp = rng.choice(grid.G, 60, replace=False)
+        corners = np.array([0, grid.G - 1])
+        gp = np.unique(np.concatenate([gp, corners]))
+        nd = rng.choice(c.M, 30, replace=False)
+        full = P.sample_stencils(grid, x, c.k_grid, c.k_node, gp, nd)
+        win = P.sample_stencils(grid, x, c.k_grid, c.k_node, gp, nd, window=4 * c.h[0])
+        for a, b in zip(full, win):
+            np.testing.assert_array_equal(a, b)
+        cand = P.window_candidates(grid.centres()[gp[:3]], x, 4 * c.h[0])
+        assert cand.size < c.M and np.all(np.diff(cand) > 0)
+        # every node closer than the window to a target is a candidate
+        t = grid.centres()[gp[:3]]
+        dist = np.sqrt(((x[None, :, :] - t[:, None, :]) ** 2).sum(-1)).min(0)
+        assert np.all(np.isin(np.flatnonzero(dist < 4 * c.h[0]), cand))
+        with pytest.raises(ValueError):
+            P.sample_stencils(grid, x, c.k_grid, c.k_node, gp, nd, window=1.0 * c.h[0])
