@@ -365,6 +365,23 @@ int pc_grad_to_nodes(const pc_geom* geom, int dtype, const void* phi_dev, void* 
 int pc_ib_update(const pc_geom* geom, int dtype, const void* u_dev, const void* grad_ib_dev,
                  void* g_dev, double tol, double* sums_dev, int32_t* conv_dev, void* stream);
 
+/* pc_ib_update without device allocation, for callers that cannot allocate
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same update with its scratch (the partial sums and u* at
+ * the B+V nodes) in a static device array of PC_NOALLOC_SCRATCH_BYTES that
+ * each device holds until the process ends, and without synchronising
+ * `stream`.  Geometries with more than PC_NOALLOC_MAX_IB boundary/virtual
+ * nodes in float64 (twice as many in float32, in 2D 3/2 times as many) give
+ * PC_ERR_UNSUPPORTED_SIZE.  Every call on a device shares that device's
+ * array: calls that overlap on one device (other streams, other threads)
+ * race and must be ordered by the caller.  Results equal pc_ib_update's bit
+ * for bit. */
+#define PC_NOALLOC_SCRATCH_BYTES (64ll << 20)
+#define PC_NOALLOC_MAX_IB 2796000 /* 3D float64: (64 MiB - 4352 B) / 24 B */
+int pc_ib_update_noalloc(const pc_geom* geom, int dtype, const void* u_dev,
+                         const void* grad_ib_dev, void* g_dev, double tol, double* sums_dev,
+                         int32_t* conv_dev, void* stream);
+
 /* ---- projection ----------------------------------------------------------- */
 
 /* u_out = u* - grad + g (Eq. 18 with phi, g): u* - grad on velocity points

@@ -17,6 +17,7 @@
 #include <cstring>
 
 #include <chrono>
+#include <mutex>
 
 #include "pc_internal.h"
 
@@ -1108,6 +1109,73 @@ int check_fields(const void* a, const void* b = nullptr, const void* c = nullptr
   return PC_OK;
 }
 
+// ---- one IB-force update (pc_ib_update and its allocation-free variant) ---------
+int ib_update_check(const pc_geom* g, int dtype, const void* u, const void* grad_ib,
+                    const void* gib, const double* sums, const int32_t* conv) {
+  if (!g || !u || !grad_ib || !gib || !sums || !conv)
+    return fail(PC_ERR_INVALID_ARG, "pc_ib_update: null argument");
+  PC_TRY(check_dtype(g, dtype));
+  PC_TRY(check_fields(u, grad_ib, gib));
+  return PC_OK;
+}
+
+// Scratch of one update: the block partial sums, then u* gathered at the
+// B+V nodes.
+constexpr size_t IB_PART_BYTES = 2 * IB_BLOCKS * 8 + 256;
+
+size_t ib_scratch_bytes(const pc_geom* g, int dtype) {
+  const size_t es = dtype == PC_F64 ? 8 : 4;
+  return IB_PART_BYTES + (size_t)g->d * g->n_ib * es;
+}
+
+int ib_update_with(const pc_geom* g, int dtype, const void* u, const void* grad_ib, void* gib,
+                   double tol, double* sums, int32_t* conv, void* scratch, hipStream_t s) {
+  double* part = reinterpret_cast<double*>(scratch);
+  void* uib = reinterpret_cast<char*>(scratch) + IB_PART_BYTES;
+  if (dtype == PC_F64) {
+    hipLaunchKernelGGL(k_gather_ib<double>, dim3(nblk(g->n_ib)), dim3(TPB), 0, s, g->ib, g->n_ib,
+                       g->d, (const double*)u, g->M, (double*)uib);
+    return launch_ib_update<double>(g, (const double*)uib, (const double*)grad_ib, (double*)gib,
+                                    tol, part, sums, conv, s);
+  }
+  hipLaunchKernelGGL(k_gather_ib<float>, dim3(nblk(g->n_ib)), dim3(TPB), 0, s, g->ib, g->n_ib,
+                     g->d, (const float*)u, g->M, (float*)uib);
+  return launch_ib_update<float>(g, (const float*)uib, (const float*)grad_ib, (float*)gib, tol,
+                                 part, sums, conv, s);
+}
+
+// The static scratch of pc_ib_update_noalloc: one copy per device, held
+// until the process ends.  Host code never uses the array's name as an
+// address (on the host it is only a stand-in for the symbol): the device
+// address comes from hipGetSymbolAddress, once per device, with that device
+// current.  The kernels write every partial sum and every gathered value
+// they read afterwards, so nothing needs clearing between calls.
+__device__ __align__(256) unsigned char scratch[PC_NOALLOC_SCRATCH_BYTES];
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+
+int noalloc_scratch(void** out) {
+  int dev = 0;
+  PC_HIP_CHECK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= NOALLOC_MAX_DEVICES)
+    return fail(PC_ERR_UNSUPPORTED_SIZE, "device ordinal above the static scratch table");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      (void)hipGetLastError();
+      return fail(PC_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") +
+                                  hipGetErrorString(e));
+    }
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return PC_OK;
+}
+
 }  // namespace
 }  // namespace pc
 
@@ -1156,33 +1224,32 @@ int pc_grad_to_nodes(const pc_geom* g, int dtype, const void* phi, void* grad, i
 
 int pc_ib_update(const pc_geom* g, int dtype, const void* u, const void* grad_ib, void* gib,
                  double tol, double* sums, int32_t* conv, void* stream) {
-  if (!g || !u || !grad_ib || !gib || !sums || !conv)
-    return fail(PC_ERR_INVALID_ARG, "pc_ib_update: null argument");
-  PC_TRY(check_dtype(g, dtype));
-  PC_TRY(check_fields(u, grad_ib, gib));
+  PC_TRY(ib_update_check(g, dtype, u, grad_ib, gib, sums, conv));
   if (g->n_ib == 0) return PC_OK;
   hipStream_t s = as_stream(stream);
-  size_t es = dtype == PC_F64 ? 8 : 4;
-  // scratch: compact u* and the partial sums
   void* tmp = nullptr;
-  PC_TRY(dev_alloc(&tmp, (size_t)g->d * g->n_ib * es + 2 * IB_BLOCKS * 8 + 256, "ib scratch"));
-  double* part = reinterpret_cast<double*>(tmp);
-  void* uib = reinterpret_cast<char*>(tmp) + 2 * IB_BLOCKS * 8 + 256;
-  int rc;
-  if (dtype == PC_F64) {
-    hipLaunchKernelGGL(k_gather_ib<double>, dim3(nblk(g->n_ib)), dim3(TPB), 0, s, g->ib, g->n_ib,
-                       g->d, (const double*)u, g->M, (double*)uib);
-    rc = launch_ib_update<double>(g, (const double*)uib, (const double*)grad_ib, (double*)gib, tol,
-                                  part, sums, conv, s);
-  } else {
-    hipLaunchKernelGGL(k_gather_ib<float>, dim3(nblk(g->n_ib)), dim3(TPB), 0, s, g->ib, g->n_ib,
-                       g->d, (const float*)u, g->M, (float*)uib);
-    rc = launch_ib_update<float>(g, (const float*)uib, (const float*)grad_ib, (float*)gib, tol,
-                                 part, sums, conv, s);
-  }
+  PC_TRY(dev_alloc(&tmp, ib_scratch_bytes(g, dtype), "ib scratch"));
+  const int rc = ib_update_with(g, dtype, u, grad_ib, gib, tol, sums, conv, tmp, s);
   (void)hipStreamSynchronize(s);
   dev_free(tmp);
   return rc;
+}
+
+int pc_ib_update_noalloc(const pc_geom* g, int dtype, const void* u, const void* grad_ib,
+                         void* gib, double tol, double* sums, int32_t* conv, void* stream) {
+  PC_TRY(ib_update_check(g, dtype, u, grad_ib, gib, sums, conv));
+  if (g->n_ib == 0) return PC_OK;
+  const size_t need = ib_scratch_bytes(g, dtype);
+  if (need > (size_t)PC_NOALLOC_SCRATCH_BYTES)
+    return fail(PC_ERR_UNSUPPORTED_SIZE,
+                "pc_ib_update_noalloc: " + std::to_string(g->n_ib) +
+                    " boundary/virtual nodes need " + std::to_string(need) +
+                    " bytes of scratch, above the static " +
+                    std::to_string((long long)PC_NOALLOC_SCRATCH_BYTES) +
+                    " (PC_NOALLOC_MAX_IB; use pc_ib_update)");
+  void* scr = nullptr;
+  PC_TRY(noalloc_scratch(&scr));
+  return ib_update_with(g, dtype, u, grad_ib, gib, tol, sums, conv, scr, as_stream(stream));
 }
 
 int pc_project(const pc_geom* g, int dtype, const void* u, const void* grad, void* u_out,

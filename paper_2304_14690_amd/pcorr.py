@@ -46,7 +46,7 @@ EXPORTS = [
     "pc_geom_export", "pc_div_to_grid", "pc_grad_to_nodes", "pc_ib_update", "pc_project",
     "pc_workspace_create", "pc_workspace_destroy", "pc_workspace_bytes",
     "pc_pressure_correct", "pc_geom_export_self", "pc_momentum_predict", "pc_momentum_pressure",
-    "pc_set_allocator", "pc_geom_export_at",
+    "pc_set_allocator", "pc_geom_export_at", "pc_ib_update_noalloc",
 ]
 
 # pc_alloc_fn / pc_free_fn
@@ -108,6 +108,7 @@ def _load():
         "pc_div_to_grid": ([vp, ctypes.c_int, vp, vp, ctypes.c_int, vp], ctypes.c_int),
         "pc_grad_to_nodes": ([vp, ctypes.c_int, vp, vp, ctypes.c_int, vp], ctypes.c_int),
         "pc_ib_update": ([vp, ctypes.c_int, vp, vp, vp, dbl, vp, vp, vp], ctypes.c_int),
+        "pc_ib_update_noalloc": ([vp, ctypes.c_int, vp, vp, vp, dbl, vp, vp, vp], ctypes.c_int),
         "pc_project": ([vp, ctypes.c_int, vp, vp, vp, vp], ctypes.c_int),
         "pc_workspace_create": ([vp, vp, ctypes.c_int, ctypes.POINTER(vp)], ctypes.c_int),
         "pc_workspace_destroy": ([vp], ctypes.c_int),
@@ -319,6 +320,13 @@ def ib_update(geom: Geometry, u: torch.Tensor, grad_ib: torch.Tensor, g: torch.T
               tol: float, sums: torch.Tensor, conv: torch.Tensor, stream=None) -> int:
     return _check(_lib.pc_ib_update(geom.h_, _dtype_code(u), _ptr(u), _ptr(grad_ib), _ptr(g),
                                     tol, _ptr(sums), _ptr(conv), _stream(stream)))
+
+
+def ib_update_noalloc(geom: Geometry, u: torch.Tensor, grad_ib: torch.Tensor, g: torch.Tensor,
+                      tol: float, sums: torch.Tensor, conv: torch.Tensor, stream=None) -> int:
+    return _check(_lib.pc_ib_update_noalloc(geom.h_, _dtype_code(u), _ptr(u), _ptr(grad_ib),
+                                            _ptr(g), tol, _ptr(sums), _ptr(conv),
+                                            _stream(stream)))
 
 
 def project(geom: Geometry, u: torch.Tensor, grad: torch.Tensor, u_out: torch.Tensor,

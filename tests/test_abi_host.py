@@ -51,6 +51,15 @@ def test_host_side_validation():
     assert lib.pc_wls_build(None, None, None, 0, None, None, ctypes.byref(out)) == \
         pcorr.PC_ERR_INVALID_ARG
     assert lib.pc_plan_destroy(None) == pcorr.PC_OK
+    # flat grid indices are int32: more than 2^31 - 2 points is refused
+    huge = (ctypes.c_int32 * 3)(2048, 2048, 1024)
+    hh = (ctypes.c_double * 3)(1.0, 1.0, 1.0)
+    assert lib.pc_plan_create(3, huge, hh, None, ctypes.byref(out)) == \
+        pcorr.PC_ERR_UNSUPPORTED_SIZE
+    assert "2^31" in pcorr.last_error()
+    # the allocation-free IB update validates before touching a device
+    assert lib.pc_ib_update_noalloc(None, 1, None, None, None, 1e-3, None, None, None) == \
+        pcorr.PC_ERR_INVALID_ARG
     # the caller's allocator: both functions or neither
     assert lib.pc_set_allocator(pcorr.ALLOC_FN(lambda u, n, p: 1), pcorr.FREE_FN(), None) == \
         pcorr.PC_ERR_INVALID_ARG
