@@ -134,7 +134,11 @@ typedef struct pc_ib_opts {
   double tol;        /* criterion tolerance (default 1e-3)                  */
   int32_t max_it;    /* iteration cap (default 50)                          */
   int32_t fixed_it;  /* > 0: run exactly this many iterations               */
-  int32_t sweeps;    /* PC_MIXED defect-correction sweeps (default 2)       */
+  int32_t sweeps;    /* PC_MIXED defect-correction sweeps per IB iteration  */
+                     /* (default 2): the first iteration corrects a        */
+                     /* float32 solve, later ones start from the previous  */
+                     /* iteration's pressure (its right-hand side differs  */
+                     /* only near the IB); mean(p) is removed at the end   */
   int32_t gauge;     /* 0: zero-mean pressure; 1: zero at the first cell    */
   int32_t flags;     /* PC_IB_* bits below                                  */
 } pc_ib_opts;
@@ -291,8 +295,14 @@ int pc_geom_destroy(pc_geom* geom);
 int pc_geom_info(const pc_geom* geom, int64_t* counts8);
 
 /* Copies the stencils out (for inspection and tests).
- *   grid_idx_dev  int32   [k_grid][G]      node index, in ascending order
- *                                          (the selection is by (d^2, idx))
+ *   grid_idx_dev  int32   [k_grid][G]      node index (the selection is by
+ *                                          (d^2, idx)); entries ordered by
+ *                                          the node's offset from the grid
+ *                                          point in whole grid spacings
+ *                                          (rounded per axis, clamped to
+ *                                          [-4, 4]): shortest first, then by
+ *                                          its (z, y, x) components, then by
+ *                                          node index
  *   grid_coef_dev float64 [d][k_grid][G]   derivative coefficients
  *   node_base_dev int32   [M]              flat grid index of the block's
  *                                          low corner (entries past a

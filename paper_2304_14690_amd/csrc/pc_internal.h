@@ -201,9 +201,14 @@ int solve_f64(const pc_plan* P, const double* b, double* phi, double* bmean_dev,
 int solve_f32(const pc_plan* P, const float* b, float* phi, double* bmean_dev,
               pc_workspace* ws, hipStream_t s, double sigma = 1.0,
               const int32_t* skip = nullptr);
+// warm: start the sweeps from the phi passed in instead of S32(b);
+// remove_mean = false leaves mean(phi) (of the order of the float32 rounding
+// of the corrections) for the caller to remove.
 int solve_mixed(const pc_plan* P, const double* b, double* phi, int sweeps, double* bmean_dev,
                 pc_workspace* ws, hipStream_t s, double sigma = 1.0,
-                const int32_t* skip = nullptr);
+                const int32_t* skip = nullptr, bool warm = false, bool remove_mean = true);
+int remove_mean_f64(const pc_plan* P, double* phi, pc_workspace* ws, hipStream_t s,
+                    const int32_t* skip = nullptr);
 int ensure_plan_ws(const pc_plan* P, pc_workspace** ws);
 // Complex values per thread of the register transform (radix-8 plan).
 constexpr int RAD_VALUES = 8;

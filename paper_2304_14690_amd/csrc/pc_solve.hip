@@ -1113,24 +1113,33 @@ int solve_f32(const pc_plan* P, const float* b, float* phi, double* bmean_dev, p
 }
 
 // Defect correction (means trapezoid-weighted on a vertex grid): bbar =
-// mean(b) in float64; phi0 = S32(b - bbar); then
+// mean(b) in float64; phi0 = S32(b - bbar) (warm: phi0 = the phi passed in,
+// the solution of a nearby right-hand side); then
 // `sweeps` times r = (b - bbar) - lap_h phi (float64, fused into the first
 // pass), phi += S32(r) (accumulated in float64 in the last pass); finally
-// mean(phi) is removed in float64.  The mean is taken out in float64 before
+// (remove_mean) mean(phi) is removed in float64.  The mean is taken out in float64 before
 // each conversion to float32: left in, the compatibility defect would
 // dominate the float32 rounding of the much smaller residual.
 int solve_mixed(const pc_plan* P, const double* b, double* phi, int sweeps, double* bmean_dev,
-                pc_workspace* ws, hipStream_t s, double sigma, const int32_t* skip) {
+                pc_workspace* ws, hipStream_t s, double sigma, const int32_t* skip, bool warm,
+                bool remove_mean) {
   if (!ws || !ws->w32) return fail(PC_ERR_INVALID_ARG, "mixed solve needs a MIXED workspace");
   float* w = ws->w32;
   double* bm = bmean_dev ? bmean_dev : ws->scal;
   PC_TRY(grid_mean_f64(P, b, ws->partial, ws->nblk, bm, s, skip));
-  PC_TRY((solve_passes<float, double, double, LD_PLAIN, ST_PLAIN>(
-      P, P->ax32, b, phi, w, nullptr, nullptr, nullptr, s, bm, sigma, skip)));
+  if (!warm)
+    PC_TRY((solve_passes<float, double, double, LD_PLAIN, ST_PLAIN>(
+        P, P->ax32, b, phi, w, nullptr, nullptr, nullptr, s, bm, sigma, skip)));
   for (int it = 0; it < sweeps; ++it) {
     PC_TRY((solve_passes<float, double, double, LD_RESID, ST_ACCUM>(
         P, P->ax32, b, phi, w, b, phi, nullptr, s, bm, sigma, skip)));
   }
+  if (remove_mean) PC_TRY(remove_mean_f64(P, phi, ws, s, skip));
+  return PC_OK;
+}
+
+int remove_mean_f64(const pc_plan* P, double* phi, pc_workspace* ws, hipStream_t s,
+                    const int32_t* skip) {
   PC_TRY(grid_mean_f64(P, phi, ws->partial, ws->nblk, ws->scal + 3, s, skip));
   int nb = (int)std::min<int64_t>(8192, (P->G + 255) / 256);
   hipLaunchKernelGGL(sub_scalar_f64, dim3(nb), dim3(256), 0, s, phi, P->G,

@@ -40,13 +40,41 @@ constexpr int TPB = 256;
 constexpr int IBT = 64;  // threads per block of the IB iteration kernel (one wavefront)
 
 // ---- div_to_grid (all grid points) -------------------------------------------
+// Order of the grid points over the workgroups of a 3D launch.  A workgroup
+// takes TPB consecutive points of one x row (coalesced stencil streams);
+// with `on`, the workgroups that one XCD runs in a row cover blocks of
+// SY rows x SZ planes (all of each row), swept along y within slabs of SZ
+// planes, so that the node values gathered for a block (the stencils reach
+// one or two lines beyond it in every direction) are fetched into that
+// XCD's L2 about once instead of once per plane that needs them.
+struct DivMap {
+  int on;
+  int segs;       // TPB-point segments per row (n0 / TPB)
+  int tiles_y;    // n1 / SY
+  int64_t n0, n1;
+};
+constexpr int DIV_SY = 8, DIV_SZ = 16;
+
+__device__ __forceinline__ int64_t div_point(int64_t blk, const DivMap& m) {
+  if (!m.on) return blk * TPB + threadIdx.x;
+  const int64_t per = (int64_t)m.segs * DIV_SY * DIV_SZ;
+  const int64_t st = blk / per;
+  const int64_t r = blk - st * per;
+  const int64_t seg = r % m.segs;
+  const int64_t zz = (r / m.segs) % DIV_SZ;
+  const int64_t yy = r / ((int64_t)m.segs * DIV_SZ);
+  const int64_t ty = st % m.tiles_y, tz = st / m.tiles_y;
+  const int64_t y = ty * DIV_SY + yy, z = tz * DIV_SZ + zz;
+  return (z * m.n1 + y) * m.n0 + seg * TPB + threadIdx.x;
+}
+
 template <typename T, int D, int K, bool LOCALREF>
 __global__ void __launch_bounds__(TPB) k_div_all(const int32_t* __restrict__ gidx,
                                                  const T* __restrict__ gcoef, int64_t G, int krt,
                                                  const T* __restrict__ v, int64_t M,
-                                                 T* __restrict__ b) {
+                                                 T* __restrict__ b, DivMap dm) {
   const int k = K > 0 ? K : krt;
-  const int64_t p = xcd_block(blockIdx.x, gridDim.x) * TPB + threadIdx.x;
+  const int64_t p = div_point(xcd_block(blockIdx.x, gridDim.x), dm);
   if (p >= G) return;
   T acc = T(0);
   T ref[D];
@@ -582,18 +610,33 @@ int check_dtype(const pc_geom* g, int dtype) {
 }
 
 // ---- launch helpers ---------------------------------------------------------------
+// The block order of k_div_all (see DivMap): on 3D grids whose rows split
+// into whole workgroups and whose y and z extents hold whole blocks.
+DivMap div_map(const pc_geom* g) {
+  DivMap m{};
+  if (g->d == 3 && g->n[0] % TPB == 0 && g->n[1] % DIV_SY == 0 && g->n[2] % DIV_SZ == 0) {
+    m.on = 1;
+    m.segs = g->n[0] / TPB;
+    m.tiles_y = g->n[1] / DIV_SY;
+    m.n0 = g->n[0];
+    m.n1 = g->n[1];
+  }
+  return m;
+}
+
 template <typename T>
 int launch_div_all(const pc_geom* g, const T* gcoef, const T* v, T* b, hipStream_t s) {
   const bool lr = sizeof(T) == 4;
   dim3 grid(nblk(g->G)), block(TPB);
+  const DivMap dm = div_map(g);
 #define DIVL(D, K)                                                                           \
   do {                                                                                      \
     if (lr)                                                                                 \
       hipLaunchKernelGGL((k_div_all<T, D, K, true>), grid, block, 0, s, g->gidx, gcoef, g->G, \
-                         g->k_grid, v, g->M, b);                                           \
+                         g->k_grid, v, g->M, b, dm);                                       \
     else                                                                                    \
       hipLaunchKernelGGL((k_div_all<T, D, K, false>), grid, block, 0, s, g->gidx, gcoef, g->G, \
-                         g->k_grid, v, g->M, b);                                           \
+                         g->k_grid, v, g->M, b, dm);                                       \
   } while (0)
   if (g->d == 2) {
     if (g->k_grid == 16) DIVL(2, 16);
@@ -858,7 +901,11 @@ int pressure_correct_t(const pc_geom* g, const pc_plan* P, int mode, const T* u,
     else if (mode == PC_F32)
       PC_TRY(solve_f32(P, (const float*)b, (float*)p, W->scal, W, s, sigma, skip));
     else
-      PC_TRY(solve_mixed(P, (const double*)b, (double*)p, sweeps, W->scal, W, s, sigma, skip));
+      // the corrections of later iterations start from the previous
+      // iteration's pressure, whose right-hand side differs only near the
+      // IB; the mean is removed once, after the last iteration
+      PC_TRY(solve_mixed(P, (const double*)b, (double*)p, sweeps, W->scal, W, s, sigma, skip,
+                         it > 1, false));
     if (nib)
       PC_TRY(launch_ib_step<T>(g, ibc<T>(g), p, (T)sigma, uib, gib, tol, W->partial, W->flag,
                                W->scal + 1, s, skip, host_flag, host_sums, !defer));
@@ -882,6 +929,7 @@ int pressure_correct_t(const pc_geom* g, const pc_plan* P, int mode, const T* u,
   // the gauge and the statistics.  With a guard it does nothing unless the
   // guarded iteration converged.
   auto final_work = [&](const int32_t* guard) -> int {
+    if (mode == PC_MIXED) PC_TRY(remove_mean_f64(P, (double*)p, W, s, guard));
     if (resident && mode == PC_F64)
       PC_TRY(solve_resident_f64(P, (const double*)b, (double*)p, W->scal, W, s, sigma, guard, 2));
     else if (resident)

@@ -492,17 +492,38 @@ __global__ void __launch_bounds__(64) k_grid_stencils(GridStencilArgs GA) {
 #pragma unroll
   for (int a = 0; a < D; ++a) chol_unit_solve<MU>(Cm, 1 + a, y[a]);
   const int64_t G = A.g.G;
+  // Storage order: by the node's offset from the target in whole grid
+  // spacings (rounded per axis, each clamped to [-4, 4]), shortest offsets
+  // first, ties by the offset's coordinates (z, y, x), then by node index.
+  // The stencils of neighbouring grid points hold the same nearby offsets
+  // (the 3^d nodes around a cell centre nearly always, farther ones by
+  // turns), so entry i lies at the same offset from its target in most lanes
+  // of a wavefront and the gathers of the transfer kernels are close to
+  // contiguous.
+  int okey[KMAX];
+#pragma unroll
+  for (int j = 0; j < KMAX; ++j) {
+    okey[j] = 0x7fffffff;
+    if (j < k) {
+      int o2 = 0, lex = 0;
+#pragma unroll
+      for (int a = D - 1; a >= 0; --a) {
+        const double t = axis_diff(A.xyz[a * A.M + li[j]], xt[a], A.g, a) / A.g.h[a];
+        const int o = (int)fmin(fmax(rint(t), -4.0), 4.0);
+        o2 += o * o;
+        lex = lex * 9 + (o + 4);
+      }
+      okey[j] = o2 * 729 + lex;
+    }
+  }
 #pragma unroll
   for (int j = 0; j < KMAX; ++j) {
     if (j < k) {
-      // stored in ascending node index: entry i then sits at nearly the same
-      // offset from the target in every lane, so the gathers of the
-      // transfer kernels stay close to contiguous
       int nid = li[j];
       int pos = 0;
 #pragma unroll
       for (int jj = 0; jj < KMAX; ++jj)
-        if (jj < k && li[jj] < nid) ++pos;
+        if (jj < k && (okey[jj] < okey[j] || (okey[jj] == okey[j] && li[jj] < nid))) ++pos;
       double xi[3];
 #pragma unroll
       for (int a = 0; a < D; ++a) xi[a] = axis_diff(A.xyz[a * A.M + nid], xt[a], A.g, a) / ht;

@@ -9,7 +9,7 @@ import pytest
 import oracle
 from oracle import projection as P
 from paper_2304_14690_amd import inputs
-from tests.helpers import rel_l2, to_np
+from tests.helpers import rel_l2, to_np, stored_order
 
 pytestmark = pytest.mark.gpu
 
@@ -51,7 +51,7 @@ def test_coarse_grid_sub_step(name):
     gcf = torch.empty((c.d, c.k_grid, grid.G), dtype=torch.float64, device="cuda")
     pc.geom_export(geom, gi, gcf)
     torch.cuda.synchronize()
-    order = np.argsort(st.grid_idx, axis=1, kind="stable")
+    order = stored_order(grid, c.x.T, st.grid_idx)
     np.testing.assert_array_equal(to_np(gi).T, np.take_along_axis(st.grid_idx, order, axis=1))
     assert rel_l2(np.transpose(to_np(gcf), (2, 0, 1)),
                   np.take_along_axis(st.grid_coef, order[:, None, :], axis=2)) <= 1e-12

@@ -36,7 +36,7 @@ import pytest
 import oracle
 from oracle import poisson, projection as P
 from paper_2304_14690_amd import inputs
-from tests.helpers import rel_l2
+from tests.helpers import rel_l2, stored_order
 
 pytestmark = pytest.mark.gpu
 
@@ -134,7 +134,7 @@ def test_full_size_sampled_parity(name):
     pc.geom_export_at(geom, gps, gi, gcf, nds, nb, ncf)
     g_idx = gi.T.cpu().numpy()
     g_cf = gcf.permute(2, 0, 1).cpu().numpy()
-    order = np.argsort(ogi, axis=1, kind="stable")
+    order = stored_order(grid, xs, ogi, gp)
     np.testing.assert_array_equal(g_idx, np.take_along_axis(ogi, order, 1))
     assert rel_l2(g_cf, np.take_along_axis(ogc, order[:, None, :], 2)) <= 1e-12
     n_base = nb.cpu().numpy().astype(np.int64)

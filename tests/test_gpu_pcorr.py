@@ -10,7 +10,7 @@ import pytest
 
 from oracle import Grid, knn as oknn, poisson, projection as P
 from paper_2304_14690_amd import inputs
-from tests.helpers import rel_l2, to_np
+from tests.helpers import rel_l2, to_np, stored_order
 
 pytestmark = pytest.mark.gpu
 
@@ -101,8 +101,8 @@ def test_stencils_match_oracle(pc, name):
     plan, geom = gpu_geom(pc, c)
     gi, gcf, nb, ncf, ib, near = export(pc, geom, c)
     # grid-point stencils: identical index sets (selected by the (d^2, idx)
-    # key; the library stores each set in ascending node index)
-    order = np.argsort(st.grid_idx, axis=1, kind="stable")
+    # key; the library stores each set in its offset order)
+    order = stored_order(grid, c.x.T, st.grid_idx)
     oidx = np.take_along_axis(st.grid_idx, order, axis=1)
     np.testing.assert_array_equal(gi.T, oidx)
     ocoef = np.take_along_axis(st.grid_coef, order[:, None, :], axis=2)

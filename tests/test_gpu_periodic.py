@@ -13,7 +13,7 @@ import pytest
 
 from oracle import Grid, projection as P
 from paper_2304_14690_amd import inputs
-from tests.helpers import rel_l2, to_np
+from tests.helpers import rel_l2, to_np, stored_order
 
 pytestmark = pytest.mark.gpu
 
@@ -79,7 +79,7 @@ def test_periodic_stencils_match_oracle(pc, name):
 
 def check_stencils(pc, c, bc, grid, st, name):
     """Exported GPU stencils against the oracle's: grid index sets bit-exact
-    (the export sorts by index), node blocks and wrap marks exact,
+    (in the storage order), node blocks and wrap marks exact,
     coefficients to 1e-12; at least one block must wrap."""
     import torch
     plan, geom = gpu_geom(pc, c, bc)
@@ -93,7 +93,7 @@ def check_stencils(pc, c, bc, grid, st, name):
     pc.geom_export(geom, gi, gcf, nb, ncf, ib, near)
     torch.cuda.synchronize()
     gi, gcf, nb, ncf = to_np(gi), to_np(gcf), to_np(nb), to_np(ncf)
-    order = np.argsort(st.grid_idx, axis=1, kind="stable")
+    order = stored_order(grid, c.x.T, st.grid_idx)
     np.testing.assert_array_equal(gi.T, np.take_along_axis(st.grid_idx, order, axis=1))
     err_g = rel_l2(np.transpose(gcf, (2, 0, 1)),
                    np.take_along_axis(st.grid_coef, order[:, None, :], axis=2))

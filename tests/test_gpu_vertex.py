@@ -13,7 +13,7 @@ import pytest
 import oracle
 from oracle import Grid, poisson, projection as P
 from paper_2304_14690_amd import inputs
-from tests.helpers import rel_l2, to_np
+from tests.helpers import rel_l2, to_np, stored_order
 
 pytestmark = pytest.mark.gpu
 
@@ -96,7 +96,7 @@ def test_vertex_sub_step(pc, name):
     nb = torch.empty(x.shape[1], dtype=torch.int32, device="cuda")
     pc.geom_export(geom, gi, gcf, nb)
     torch.cuda.synchronize()
-    order = np.argsort(st.grid_idx, axis=1, kind="stable")
+    order = stored_order(grid, x.T, st.grid_idx)
     np.testing.assert_array_equal(to_np(gi).T, np.take_along_axis(st.grid_idx, order, 1))
     assert rel_l2(np.transpose(to_np(gcf), (2, 0, 1)),
                   np.take_along_axis(st.grid_coef, order[:, None, :], 2)) <= 1e-12
