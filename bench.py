@@ -122,6 +122,8 @@ def parse():
     ap.add_argument("--serve-geoms", type=int, default=2,
                     help="geometries per grid size in the serving pool")
     ap.add_argument("--serve-only", action="store_true")
+    ap.add_argument("--no-shuffle", action="store_true",
+                    help="skip the shuffled-node-order runs of the 2D extra workloads")
     ap.add_argument("--time-steps", type=int, default=20,
                     help="on a periodic-box workload, also time whole time steps (first "
                          "fractional step + sub-step); 0: off")
@@ -226,6 +228,64 @@ def bytes_step(G, M, k, bn, d, mode, sweeps, n_it, n_near, near_entries, n_ib):
     ibstep = n_ib * (bn * d * s + 4 + 3 * d * s)
     return (bytes_div_all(G, M, k, d, s) + bytes_grad_project(G, M, bn, d, s)
             + n_it * (bytes_solve_mode(G, d, mode, sweeps) + ibstep) + (n_it - 1) * near)
+
+
+def run_shuffled(args, name, N):
+    """The float64 sub-step with the nodes handed over in a seeded random
+    order: the library sorting them into cells (pc_wls_opts.order =
+    PC_ORDER_CELL; fields permuted once, untimed) and, for contrast, kept in
+    the shuffled order (PC_ORDER_CALLER)."""
+    import torch
+    from paper_2304_14690_amd import pcorr as pc
+    case = make_workload(name, N)
+    d = case["d"]
+    G = int(np.prod(case["n"]))
+    M = int(case["kind"].size)
+    rng = np.random.Generator(np.random.PCG64(11))
+    sh = rng.permutation(M)
+    x = torch.from_numpy(np.ascontiguousarray(case["x"][:, sh])).cuda()
+    kind = torch.from_numpy(np.ascontiguousarray(case["kind"][sh])).cuda()
+    shd = torch.from_numpy(sh).cuda()
+    u_sh = case["u"][:, shd].contiguous()
+    plan = pc.Plan(d, case["n"], case["h"], bc=case["bc"])
+    out = {}
+    ref_u = None
+    for order in ("cell", "caller"):
+        geom = pc.wls_build(plan, x, kind, case["k"], case["k"], order=order)
+        u = torch.empty_like(u_sh)
+        pc.geom_permute(geom, u_sh, u, to_internal=True)
+        uo = torch.empty_like(u)
+        p = torch.empty(G, dtype=torch.float64, device="cuda")
+        ws = pc.Workspace(plan, geom, pc.PC_F64)
+        for _ in range(args.warmup):
+            _, st = pc.pressure_correct(geom, plan, pc.PC_F64, u, 1.0, uo, p, ws=ws)
+        torch.cuda.synchronize()
+        lat = []
+        t_start = time.perf_counter()
+        for _ in range(args.steps):
+            ts = time.perf_counter()
+            _, st = pc.pressure_correct(geom, plan, pc.PC_F64, u, 1.0, uo, p, ws=ws)
+            torch.cuda.synchronize()
+            lat.append(1e3 * (time.perf_counter() - ts))
+        sec = (time.perf_counter() - t_start) / args.steps
+        # back to the lattice order of the unshuffled workload
+        uc = torch.empty_like(uo)
+        pc.geom_permute(geom, uo, uc, to_internal=False)
+        ul = torch.empty_like(uc)
+        ul[:, shd] = uc
+        if ref_u is None:
+            ref_u = ul
+        out[order] = {"ms_per_step": 1e3 * sec, "p50_ms": float(np.percentile(lat, 50)),
+                      "p99_ms": float(np.percentile(lat, 99)), "n_it": st["n_it"],
+                      "value": G / sec, "u_vs_cell_order": rel_l2(ul, ref_u)}
+        print(f"bench: {name} shuffled, order {order}: {1e3 * sec:.3f} ms/step",
+              file=sys.stderr, flush=True)
+        del geom, ws, u, uo, p, uc
+    del x, kind, u_sh, plan, case
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    return {"nodes": "the workload's nodes in a seeded random order (PCG64 seed 11)",
+            "cell_order": out["cell"], "caller_order": out["caller"]}
 
 
 def run_workload(args, name, N, modes_arg):
@@ -452,6 +512,8 @@ def main():
     extras = {}
     for name in [w for w in args.extra.split(",") if w and w != args.workload]:
         extras[name] = run_workload(args, name, WORKLOADS[name]["N"], "")
+        if WORKLOADS[name]["d"] == 2 and not args.no_shuffle:
+            extras[name]["shuffled"] = run_shuffled(args, name, WORKLOADS[name]["N"])
     serving_out = None
     if args.serve_seconds > 0:
         serving_out = serving(args, rates)

@@ -127,7 +127,27 @@ typedef struct pc_wls_opts {
   int32_t k_self;    /* > 0: also build node-to-node stencils of k_self     */
                      /* other nodes for the first fractional step           */
                      /* (pc_momentum_predict); 0 = none                    */
+  int32_t order;     /* PC_ORDER_CALLER (default) or PC_ORDER_CELL: the     */
+                     /* order of the node fields of this geometry           */
 } pc_wls_opts;
+
+/* pc_wls_opts.order.  The nodes may be given in any order (Sec. 2.2: the
+ * points can be distributed arbitrarily), but the transfers gather node
+ * values per grid point and grid values per node, and they stay near
+ * contiguous only if nodes close in space are close in index.
+ *   PC_ORDER_CALLER  node fields are in the caller's order (right when the
+ *                    caller's order is already spatially coherent, such as a
+ *                    lattice order);
+ *   PC_ORDER_CELL    the library sorts the nodes by pressure-grid cell (cells
+ *                    x fastest; within a cell by x, then y, then z, then the
+ *                    caller's index, so the order depends only on the point
+ *                    set) and every node field of the geometry -- u, u_out,
+ *                    the IB force and lists, the momentum fields, exported
+ *                    node stencils -- is in that internal order.
+ *                    pc_geom_permutation gives the order, pc_geom_permute
+ *                    moves fields between the two orders. */
+#define PC_ORDER_CALLER 0
+#define PC_ORDER_CELL 1
 
 /* Options of the IB-force iteration (Sec. 2.3). */
 typedef struct pc_ib_opts {
@@ -163,7 +183,7 @@ typedef struct pc_stats {
 
 /* ---- library ------------------------------------------------------------ */
 
-/* ABI version (major*100 + minor): 113. */
+/* ABI version (major*100 + minor): 114. */
 int pc_version(void);
 
 /* Copies the calling thread's last error message into buf (NUL-terminated,
@@ -316,6 +336,17 @@ int pc_geom_info(const pc_geom* geom, int64_t* counts8);
 int pc_geom_export(const pc_geom* geom, int32_t* grid_idx_dev, double* grid_coef_dev,
                    int32_t* node_base_dev, double* node_coef_dev, int32_t* ib_dev,
                    int32_t* near_dev, void* stream);
+
+/* The internal node order: perm_dev int32 [M], internal node i is the
+ * caller's node perm_dev[i] (the identity for PC_ORDER_CALLER). */
+int pc_geom_permutation(const pc_geom* geom, int32_t* perm_dev, void* stream);
+
+/* Moves ncomp node fields [ncomp][M] (dtype PC_F64 or PC_F32) between the
+ * caller's order and the geometry's internal order: to_internal != 0 gives
+ * dst[c][i] = src[c][perm[i]], to_internal == 0 the inverse.  src and dst
+ * must not alias (a plain copy for PC_ORDER_CALLER). */
+int pc_geom_permute(const pc_geom* geom, int dtype, int ncomp, int to_internal,
+                    const void* src_dev, void* dst_dev, void* stream);
 
 /* The stencils of selected targets (for inspection and tests where a whole
  * export does not fit in device memory, such as 512^3 grids):

@@ -135,6 +135,11 @@ struct pc_geom {
   int32_t* vlist;    // [n_v] their indices
   int64_t bytes;
   pc_workspace* own_ws;
+  // node order (PC_ORDER_CALLER, PC_ORDER_CELL): with PC_ORDER_CELL every
+  // node index above is internal and internal node i is the caller's node
+  // perm[i]; null for PC_ORDER_CALLER
+  int order;
+  int32_t* perm;
 };
 
 namespace pc {

@@ -180,6 +180,72 @@ __global__ void __launch_bounds__(256) k_cell_fill(const double* __restrict__ xy
   sorted[start[c] + slot] = (int32_t)n;
 }
 
+// Orders the nodes of every cell by position (x, then y, then z) and then
+// by caller index (insertion sort of the cell's slice; cells hold a few
+// nodes), so that the cell order of a node cloud does not depend on the
+// order the caller lists it in.
+template <int D>
+__global__ void __launch_bounds__(256) k_cell_order(const double* __restrict__ xyz, int64_t M,
+                                                    int64_t G, const int32_t* __restrict__ start,
+                                                    int32_t* __restrict__ sorted) {
+  const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (c >= G) return;
+  const int s0 = start[c], s1 = start[c + 1];
+  auto less = [&](int a, int b) {
+#pragma unroll
+    for (int ax = 0; ax < D; ++ax) {
+      const double xa = xyz[ax * M + a], xb = xyz[ax * M + b];
+      if (xa < xb) return true;
+      if (xb < xa) return false;
+    }
+    return a < b;
+  };
+  for (int i = s0 + 1; i < s1; ++i) {
+    const int v = sorted[i];
+    int j = i - 1;
+    while (j >= s0 && less(v, sorted[j])) {
+      sorted[j + 1] = sorted[j];
+      --j;
+    }
+    sorted[j + 1] = v;
+  }
+}
+
+// Node positions and kinds in the internal order: node i is caller node
+// perm[i].
+__global__ void __launch_bounds__(256) k_gather_nodes(const int32_t* __restrict__ perm, int64_t M,
+                                                      int d, const double* __restrict__ xyz,
+                                                      const uint8_t* __restrict__ kind,
+                                                      double* __restrict__ xo,
+                                                      uint8_t* __restrict__ ko) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= M) return;
+  const int64_t n = perm[i];
+  for (int a = 0; a < d; ++a) xo[a * M + i] = xyz[a * M + n];
+  ko[i] = kind[n];
+}
+
+// [ncomp][M] node fields between the caller's order and the internal one.
+template <typename T>
+__global__ void __launch_bounds__(256) k_permute(const int32_t* __restrict__ perm, int64_t M,
+                                                 int ncomp, int to_internal,
+                                                 const T* __restrict__ src, T* __restrict__ dst) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= M) return;
+  const int64_t n = perm[i];
+  for (int c = 0; c < ncomp; ++c) {
+    if (to_internal)
+      dst[c * M + i] = src[c * M + n];
+    else
+      dst[c * M + n] = src[c * M + i];
+  }
+}
+
+__global__ void __launch_bounds__(256) k_iota(int32_t* __restrict__ out, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) out[i] = (int32_t)i;
+}
+
 // Exclusive scan of int32 counts (n elements) into out (n+1 elements), in
 // three launches: block sums, a one-block scan of the sums, block rescans.
 constexpr int SCAN_B = 1024;
@@ -942,7 +1008,8 @@ void geom_free(pc_geom* g) {
   if (!g) return;
   void* ptrs[] = {g->gidx,   g->gcoef,  g->gcoef32, g->nbase,  g->ncoef,  g->ncoef32,
                   g->ib,     g->near,   g->nslot,   g->ncoefib, g->ncoefib32, g->ibbase,
-                  g->ibcoef, g->ibcoef32, g->sidx,  g->scoef,   g->scoef32,  g->vlist};
+                  g->ibcoef, g->ibcoef32, g->sidx,  g->scoef,   g->scoef32,  g->vlist,
+                  g->perm};
   for (void* p : ptrs) dev_free(p);
 }
 
@@ -957,6 +1024,73 @@ struct Scratch {
     return rc;
   }
 };
+
+GridDesc grid_desc(const pc_plan* P) {
+  GridDesc gd;
+  gd.per = 0;
+  for (int a = 0; a < 3; ++a) {
+    gd.n[a] = P->n[a];
+    gd.h[a] = P->h[a];
+    gd.L[a] = (double)P->n[a] * P->h[a];
+    if (a < P->d && P->bc[a] == PC_BC_PERIODIC) gd.per |= 1 << a;
+  }
+  gd.G = P->G;
+  gd.off = P->vertex ? 0.0 : 0.5;
+  return gd;
+}
+
+int build(const pc_plan* P, const double* xyz, const uint8_t* kind, int64_t M,
+          const pc_wls_opts* o, hipStream_t s, pc_geom* g);
+
+// PC_ORDER_CELL: the nodes sorted by grid cell (cells x fastest; within a
+// cell by position, then caller index) into g->perm, and the stencils built
+// on the cloud in that order.
+int build_cell_order(const pc_plan* P, const double* xyz, const uint8_t* kind, int64_t M,
+                     const pc_wls_opts* o, hipStream_t s, pc_geom* g) {
+  const int d = P->d;
+  const int64_t G = P->G;
+  const GridDesc gd = grid_desc(P);
+  Scratch tmp;
+  int32_t *count, *start, *cursor, *bad;
+  PC_TRY(tmp.alloc((void**)&count, (size_t)G * 4, "cell counts"));
+  PC_TRY(tmp.alloc((void**)&start, (size_t)(G + 1) * 4, "cell starts"));
+  PC_TRY(tmp.alloc((void**)&cursor, (size_t)G * 4, "cell cursors"));
+  PC_TRY(tmp.alloc((void**)&bad, 256, "flags"));
+  PC_TRY(dev_alloc((void**)&g->perm, (size_t)M * 4, "node permutation"));
+  PC_TRY(fill_zero(count, (size_t)G * 4, s));
+  PC_TRY(fill_zero(cursor, (size_t)G * 4, s));
+  PC_TRY(fill_zero(bad, 256, s));
+  if (d == 2)
+    hipLaunchKernelGGL(k_cell_count<2>, dim3(nblocks(M, 256)), dim3(256), 0, s, xyz, M, gd, count,
+                       bad);
+  else
+    hipLaunchKernelGGL(k_cell_count<3>, dim3(nblocks(M, 256)), dim3(256), 0, s, xyz, M, gd, count,
+                       bad);
+  PC_HIP_CHECK(hipGetLastError());
+  PC_TRY(scan_exclusive(count, G, start, s));
+  if (d == 2) {
+    hipLaunchKernelGGL(k_cell_fill<2>, dim3(nblocks(M, 256)), dim3(256), 0, s, xyz, M, gd, start,
+                       cursor, g->perm);
+    hipLaunchKernelGGL(k_cell_order<2>, dim3(nblocks(G, 256)), dim3(256), 0, s, xyz, M, G, start,
+                       g->perm);
+  } else {
+    hipLaunchKernelGGL(k_cell_fill<3>, dim3(nblocks(M, 256)), dim3(256), 0, s, xyz, M, gd, start,
+                       cursor, g->perm);
+    hipLaunchKernelGGL(k_cell_order<3>, dim3(nblocks(G, 256)), dim3(256), 0, s, xyz, M, G, start,
+                       g->perm);
+  }
+  PC_HIP_CHECK(hipGetLastError());
+  double* xi;
+  uint8_t* ki;
+  PC_TRY(tmp.alloc((void**)&xi, (size_t)d * M * 8, "node positions in cell order"));
+  PC_TRY(tmp.alloc((void**)&ki, (size_t)M, "node kinds in cell order"));
+  hipLaunchKernelGGL(k_gather_nodes, dim3(nblocks(M, 256)), dim3(256), 0, s, g->perm, M, d, xyz,
+                     kind, xi, ki);
+  PC_HIP_CHECK(hipGetLastError());
+  PC_TRY(build(P, xi, ki, M, o, s, g));
+  g->bytes += M * 4;
+  return PC_OK;
+}
 
 int build(const pc_plan* P, const double* xyz, const uint8_t* kind, int64_t M,
           const pc_wls_opts* o, hipStream_t s, pc_geom* g) {
@@ -1011,16 +1145,7 @@ int build(const pc_plan* P, const double* xyz, const uint8_t* kind, int64_t M,
   g->m_node = m;
   g->bn = bn;
   g->has32 = want32;
-  GridDesc gd;
-  gd.per = 0;
-  for (int a = 0; a < 3; ++a) {
-    gd.n[a] = P->n[a];
-    gd.h[a] = P->h[a];
-    gd.L[a] = (double)P->n[a] * P->h[a];
-    if (a < d && P->bc[a] == PC_BC_PERIODIC) gd.per |= 1 << a;
-  }
-  gd.G = G;
-  gd.off = P->vertex ? 0.0 : 0.5;
+  const GridDesc gd = grid_desc(P);
   g->per = gd.per;
   g->vertex = P->vertex;
 
@@ -1210,10 +1335,16 @@ int pc_wls_build(const pc_plan* P, const double* xyz, const uint8_t* kind, int64
   *out = nullptr;
   if (M <= 0) return fail(PC_ERR_INVALID_ARG, "M must be positive");
   if (!aligned16(xyz)) return fail(PC_ERR_ALIGN, "positions must be 16-byte aligned");
+  const int order = opts ? opts->order : PC_ORDER_CALLER;
+  if (order != PC_ORDER_CALLER && order != PC_ORDER_CELL)
+    return fail(PC_ERR_INVALID_ARG, "order must be PC_ORDER_CALLER or PC_ORDER_CELL");
+  if (M > INT32_MAX - 1) return fail(PC_ERR_UNSUPPORTED_SIZE, "more than 2^31-2 nodes");
   pc_geom* g = new pc_geom();
   std::memset(g, 0, sizeof(*g));
   (void)hipGetDevice(&g->device);
-  int rc = build(P, xyz, kind, M, opts, as_stream(stream), g);
+  g->order = order;
+  int rc = order == PC_ORDER_CELL ? build_cell_order(P, xyz, kind, M, opts, as_stream(stream), g)
+                                  : build(P, xyz, kind, M, opts, as_stream(stream), g);
   if (rc != PC_OK) {
     std::string keep;
     {
@@ -1289,6 +1420,40 @@ int pc_geom_export(const pc_geom* g, int32_t* gidx, double* gcoef, int32_t* nbas
                                   hipMemcpyDeviceToDevice, s));
   PC_TRY(cp(ib, g->ib, (size_t)g->n_ib * 4));
   PC_TRY(cp(near, g->near, (size_t)g->n_near * 4));
+  return PC_OK;
+}
+
+int pc_geom_permutation(const pc_geom* g, int32_t* perm, void* stream) {
+  if (!g || !perm) return fail(PC_ERR_INVALID_ARG, "pc_geom_permutation: null argument");
+  hipStream_t s = as_stream(stream);
+  if (g->perm)
+    PC_HIP_CHECK(hipMemcpyAsync(perm, g->perm, (size_t)g->M * 4, hipMemcpyDeviceToDevice, s));
+  else
+    hipLaunchKernelGGL(k_iota, dim3(nblocks(g->M, 256)), dim3(256), 0, s, perm, g->M);
+  PC_HIP_CHECK(hipGetLastError());
+  return PC_OK;
+}
+
+int pc_geom_permute(const pc_geom* g, int dtype, int ncomp, int to_internal, const void* src,
+                    void* dst, void* stream) {
+  if (!g || !src || !dst) return fail(PC_ERR_INVALID_ARG, "pc_geom_permute: null argument");
+  if (dtype != PC_F64 && dtype != PC_F32) return fail(PC_ERR_INVALID_ARG, "dtype");
+  if (ncomp < 1 || ncomp > 64) return fail(PC_ERR_INVALID_ARG, "ncomp must be in [1, 64]");
+  if (src == dst) return fail(PC_ERR_INVALID_ARG, "pc_geom_permute: src and dst must differ");
+  hipStream_t s = as_stream(stream);
+  const size_t es = dtype == PC_F64 ? 8 : 4;
+  if (!g->perm) {
+    PC_HIP_CHECK(hipMemcpyAsync(dst, src, (size_t)ncomp * g->M * es, hipMemcpyDeviceToDevice, s));
+    return PC_OK;
+  }
+  const int ti = to_internal ? 1 : 0;
+  if (dtype == PC_F64)
+    hipLaunchKernelGGL(k_permute<double>, dim3(nblocks(g->M, 256)), dim3(256), 0, s, g->perm, g->M,
+                       ncomp, ti, (const double*)src, (double*)dst);
+  else
+    hipLaunchKernelGGL(k_permute<float>, dim3(nblocks(g->M, 256)), dim3(256), 0, s, g->perm, g->M,
+                       ncomp, ti, (const float*)src, (float*)dst);
+  PC_HIP_CHECK(hipGetLastError());
   return PC_OK;
 }
 

@@ -46,7 +46,8 @@ EXPORTS = [
     "pc_geom_export", "pc_div_to_grid", "pc_grad_to_nodes", "pc_ib_update", "pc_project",
     "pc_workspace_create", "pc_workspace_destroy", "pc_workspace_bytes",
     "pc_pressure_correct", "pc_geom_export_self", "pc_momentum_predict", "pc_momentum_pressure",
-    "pc_set_allocator", "pc_geom_export_at", "pc_ib_update_noalloc",
+    "pc_set_allocator", "pc_geom_export_at", "pc_ib_update_noalloc", "pc_geom_permutation",
+    "pc_geom_permute",
 ]
 
 # pc_alloc_fn / pc_free_fn
@@ -65,7 +66,11 @@ class WlsOpts(ctypes.Structure):
     _fields_ = [("k_grid", ctypes.c_int32), ("k_node", ctypes.c_int32),
                 ("eps", ctypes.c_double), ("support", ctypes.c_double),
                 ("delta", ctypes.c_double), ("dtype_mask", ctypes.c_int32),
-                ("k_self", ctypes.c_int32)]
+                ("k_self", ctypes.c_int32), ("order", ctypes.c_int32)]
+
+
+PC_ORDER_CALLER, PC_ORDER_CELL = 0, 1
+ORDERS = {"caller": PC_ORDER_CALLER, "cell": PC_ORDER_CELL}
 
 
 PC_IB_FULL_TRANSFORMS = 1
@@ -118,6 +123,9 @@ def _load():
                                 ctypes.c_int),
         "pc_geom_export_self": ([vp, vp, vp, vp], ctypes.c_int),
         "pc_geom_export_at": ([vp, vp, i64, vp, vp, vp, i64, vp, vp, vp], ctypes.c_int),
+        "pc_geom_permutation": ([vp, vp, vp], ctypes.c_int),
+        "pc_geom_permute": ([vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp, vp],
+                            ctypes.c_int),
         "pc_momentum_predict": ([vp, ctypes.c_int, vp, vp, dbl, dbl, vp, vp, vp, vp],
                                 ctypes.c_int),
         "pc_momentum_pressure": ([vp, ctypes.c_int, vp, vp, vp, vp, dbl, vp, vp], ctypes.c_int),
@@ -274,9 +282,11 @@ def poisson_fft_solve(plan: Plan, b: torch.Tensor, phi: torch.Tensor, mode: int 
 
 def wls_build(plan: Plan, xyz: torch.Tensor, kind: torch.Tensor, k_grid: int = 0,
               k_node: int = 0, eps: float = 0.0, support: float = 0.0, delta: float = 0.0,
-              want_f32: bool = False, stream=None, k_self: int = 0) -> Geometry:
+              want_f32: bool = False, stream=None, k_self: int = 0,
+              order: str = "caller") -> Geometry:
     assert xyz.dtype == torch.float64 and kind.dtype == torch.uint8
-    opts = WlsOpts(k_grid, k_node, eps, support, delta, 1 if want_f32 else 0, k_self)
+    opts = WlsOpts(k_grid, k_node, eps, support, delta, 1 if want_f32 else 0, k_self,
+                   ORDERS[order] if isinstance(order, str) else int(order))
     out = ctypes.c_void_p()
     _check(_lib.pc_wls_build(plan.h_, _ptr(xyz), _ptr(kind), kind.numel(), ctypes.byref(opts),
                              _stream(stream), ctypes.byref(out)))
@@ -288,6 +298,21 @@ def geom_export(geom: Geometry, grid_idx=None, grid_coef=None, node_base=None,
     return _check(_lib.pc_geom_export(geom.h_, _ptr(grid_idx), _ptr(grid_coef),
                                       _ptr(node_base), _ptr(node_coef), _ptr(ib), _ptr(near),
                                       _stream(stream)))
+
+
+def geom_permutation(geom: Geometry, perm: torch.Tensor, stream=None) -> int:
+    """perm (int32 [M]): internal node i is the caller's node perm[i]."""
+    assert perm.dtype == torch.int32 and perm.numel() == geom.M
+    return _check(_lib.pc_geom_permutation(geom.h_, _ptr(perm), _stream(stream)))
+
+
+def geom_permute(geom: Geometry, src: torch.Tensor, dst: torch.Tensor, to_internal: bool = True,
+                 stream=None) -> int:
+    """[ncomp][M] node fields between the caller's order and the internal one."""
+    assert src.shape == dst.shape and src.dtype == dst.dtype and src.shape[-1] == geom.M
+    ncomp = src.numel() // geom.M
+    return _check(_lib.pc_geom_permute(geom.h_, _dtype_code(src), ncomp, 1 if to_internal else 0,
+                                       _ptr(src), _ptr(dst), _stream(stream)))
 
 
 def geom_export_at(geom: Geometry, grid_pts: Optional[torch.Tensor] = None, grid_idx=None,

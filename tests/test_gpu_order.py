@@ -1,0 +1,101 @@
+"""The library's own node order (pc_wls_opts.order = PC_ORDER_CELL): nodes
+handed over in any order are sorted by grid cell (then position, then
+caller index), so a cloud and a shuffled copy of it get the same internal
+order, the same stencils and the same sub-step bit for bit; the internal
+order matches the oracle run on the nodes in that order, and the caller
+order (PC_ORDER_CALLER) on the same cloud to rounding."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import projection as P
+from paper_2304_14690_amd import inputs
+from tests.helpers import rel_l2, to_np
+
+pytestmark = pytest.mark.gpu
+
+CASES = {
+    "2d": lambda: inputs.make_case("ord2", 2, 128, [inputs.Obstacle("circle", (0.4, 0.5), (0.1,))],
+                                   16, 16, 16, 71, 72),
+    "3d": lambda: inputs.make_case("ord3", 3, 24, [inputs.Obstacle("sphere", (0.5, 0.5, 0.5),
+                                                                   (0.2,))], 27, 27, 8, 73, 74),
+}
+
+
+def _run(pc, plan, geom, u_int, mode=1):
+    import torch
+    uo = torch.empty_like(u_int)
+    p = torch.empty(plan.G, dtype=u_int.dtype, device="cuda")
+    rc, st = pc.pressure_correct(geom, plan, mode, u_int, 1.0, uo, p)
+    torch.cuda.synchronize()
+    return rc, st, uo, p
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_cell_order_independent_of_input_order(name):
+    import torch
+    from paper_2304_14690_amd import pcorr as pc
+    c = CASES[name]()
+    rng = np.random.Generator(np.random.PCG64(5))
+    sh = rng.permutation(c.M)
+    xs, ks, us = (np.ascontiguousarray(c.x[:, sh]), np.ascontiguousarray(c.kind[sh]),
+                  np.ascontiguousarray(c.u[:, sh]))
+    plan = pc.Plan(c.d, c.n, c.h)
+    geoms, perms, outs = [], [], []
+    for x, k, u in ((c.x, c.kind, c.u), (xs, ks, us)):
+        g = pc.wls_build(plan, torch.from_numpy(x).cuda(), torch.from_numpy(k).cuda(), c.k_grid,
+                         c.k_node, order="cell", want_f32=True)
+        perm = torch.empty(c.M, dtype=torch.int32, device="cuda")
+        pc.geom_permutation(g, perm)
+        perm = to_np(perm).astype(np.int64)
+        assert np.array_equal(np.sort(perm), np.arange(c.M))
+        ut = torch.from_numpy(u).cuda()
+        ui = torch.empty_like(ut)
+        pc.geom_permute(g, ut, ui, to_internal=True)
+        back = torch.empty_like(ut)
+        pc.geom_permute(g, ui, back, to_internal=False)
+        torch.cuda.synchronize()
+        assert torch.equal(back, ut)
+        assert np.array_equal(to_np(ui), u[:, perm])
+        geoms.append(g)
+        perms.append(perm)
+        outs.append((_run(pc, plan, g, ui), _run(pc, plan, g, ui.float(), mode=pc.PC_F32)))
+    # the same internal cloud from both inputs
+    xa = c.x[:, perms[0]]
+    assert np.array_equal(xa, xs[:, perms[1]])
+    # cells non-decreasing along the internal order
+    cell = np.zeros(c.M, dtype=np.int64)
+    stride = 1
+    for a in range(c.d):
+        cell += np.clip(np.floor(xa[a] / c.h[a]), 0, c.n[a] - 1).astype(np.int64) * stride
+        stride *= c.n[a]
+    assert np.all(np.diff(cell) >= 0)
+    # bit for bit, float64 and float32
+    for m in range(2):
+        (rca, sta, uoa, pa), (rcb, stb, uob, pb) = outs[0][m], outs[1][m]
+        assert rca == rcb == 0 and sta["n_it"] == stb["n_it"]
+        assert torch.equal(uoa, uob) and torch.equal(pa, pb)
+
+    # parity: the oracle on the nodes in the internal order
+    ki = c.kind[perms[0]]
+    grid = oracle.Grid(c.d, c.n, c.h)
+    st = P.build_stencils(grid, xa.T.copy(), ki, c.k_grid, c.k_node)
+    ref = P.pressure_correct(st, c.u[:, perms[0]].T.copy())
+    (rc, stt, uo, p) = outs[0][0]
+    assert stt["n_it"] == ref["n_it"]
+    assert rel_l2(to_np(uo).T, ref["u_new"]) <= 1e-11
+    assert rel_l2(to_np(p), ref["p"]) <= 1e-11
+    ib = np.flatnonzero(ki != inputs.KIND_F)
+    assert np.all(to_np(uo)[:, ib] == 0.0)
+
+    # the caller's order on the shuffled cloud: the same sub-step to rounding
+    gc = pc.wls_build(plan, torch.from_numpy(xs).cuda(), torch.from_numpy(ks).cuda(), c.k_grid,
+                      c.k_node, order="caller")
+    rc, stc, uoc, pcc = _run(pc, plan, gc, torch.from_numpy(us).cuda())
+    assert stc["n_it"] == ref["n_it"]
+    # internal order of the shuffled build -> its caller order
+    uo_caller = torch.empty_like(uoc)
+    pc.geom_permute(geoms[1], outs[1][0][2], uo_caller, to_internal=False)
+    torch.cuda.synchronize()
+    assert rel_l2(to_np(uo_caller), to_np(uoc)) <= 1e-12
+    assert rel_l2(to_np(pcc), to_np(outs[1][0][3])) <= 1e-12
