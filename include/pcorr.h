@@ -337,6 +337,22 @@ int pc_geom_export(const pc_geom* geom, int32_t* grid_idx_dev, double* grid_coef
                    int32_t* node_base_dev, double* node_coef_dev, int32_t* ib_dev,
                    int32_t* near_dev, void* stream);
 
+/* Device memory a geometry would take, before it is built (for admission
+ * by memory, as a serving loop needs it): for M nodes of which n_ib are
+ * boundary/virtual points, with at most n_near near-IB grid points (the
+ * grid points whose stencil holds a B/V node, known exactly only after the
+ * build: pass a bound), and the options of pc_wls_build:
+ *   geom_bytes       the arrays the geometry keeps (pc_geom_info counts[5]
+ *                    after the build, when n_near is exact), an upper bound;
+ *   build_peak_bytes geom_bytes plus the scratch pc_wls_build holds at most
+ *                    at once (cell lists, flags);
+ *   ws_bytes[3]      pc_workspace_bytes of a workspace for PC_F64, PC_F32,
+ *                    PC_MIXED on that geometry.
+ * Any output pointer may be NULL.  Host only. */
+int pc_geom_footprint(const pc_plan* plan, int64_t M, int64_t n_ib, int64_t n_near,
+                      const pc_wls_opts* opts, int64_t* geom_bytes, int64_t* build_peak_bytes,
+                      int64_t* ws_bytes);
+
 /* The internal node order: perm_dev int32 [M], internal node i is the
  * caller's node perm_dev[i] (the identity for PC_ORDER_CALLER). */
 int pc_geom_permutation(const pc_geom* geom, int32_t* perm_dev, void* stream);

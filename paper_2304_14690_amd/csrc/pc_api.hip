@@ -309,26 +309,42 @@ int pc_plan_destroy(pc_plan* P) {
   return PC_OK;
 }
 
-int64_t pc_workspace_bytes(const pc_plan* P, const pc_geom* g, int mode) {
-  if (!P || check_mode(mode) != PC_OK) return -1;
+}  // extern "C"
+
+namespace pc {
+// Device bytes of a workspace of `mode` for a geometry with n_ib B+V nodes
+// and n_near near-IB points (geometry false: solve-only).  Every region is
+// rounded up to 256 bytes, as pc_workspace_create lays them out.
+int64_t workspace_bytes_for(const pc_plan* P, bool geometry, int64_t n_ib, int64_t n_near,
+                            int mode) {
   size_t s = mode == PC_F32 ? 4 : 8;
   int64_t bytes = 0;
   auto add = [&](int64_t b) { bytes += (b + 255) / 256 * 256; };
-  if (g) {
+  if (geometry) {
     add(P->G * (int64_t)s);              // b
     add(P->G * (int64_t)s);              // phi
-    add(g->n_near * (int64_t)s);         // bnear
-    for (int i = 0; i < 3; ++i) add((int64_t)g->d * g->n_ib * (int64_t)s);  // uib, gib, gradib
+    add(n_near * (int64_t)s);            // bnear
+    for (int i = 0; i < 3; ++i) add((int64_t)P->d * n_ib * (int64_t)s);  // uib, gib, gradib
   }
   if (mode == PC_MIXED) add(P->G * 4);   // w32
-  if (pc::resident_ok(P, g, mode)) {
+  if (geometry && pc::resident_possible(P, n_ib, mode)) {
     if (P->d == 3) add(P->G * (int64_t)s);             // w1b
     add(4 * pc::resident_tiles_max(P, s));            // tile lists
   }
-  add(8 * partial_doubles(g));           // partials
+  // reduction partials: 1024 blocks for grid means, two per 64-node block of
+  // the IB iteration kernel
+  add(8 * std::max<int64_t>(1024, geometry ? 2 * ((n_ib + 63) / 64) : 0));
   add(16 * 8);                           // scalars
   add(16 * 4);                           // flags
   return bytes;
+}
+}  // namespace pc
+
+extern "C" {
+
+int64_t pc_workspace_bytes(const pc_plan* P, const pc_geom* g, int mode) {
+  if (!P || check_mode(mode) != PC_OK) return -1;
+  return pc::workspace_bytes_for(P, g != nullptr, g ? g->n_ib : 0, g ? g->n_near : 0, mode);
 }
 
 }  // extern "C"

@@ -222,6 +222,10 @@ constexpr int RAD_VALUES = 8;
 int rad_tile_lines(const pc_plan* P, int axis, size_t elem);
 // Whether the resident IB-iteration transforms apply to this plan/geometry/mode.
 bool resident_ok(const pc_plan* P, const pc_geom* g, int mode);
+bool resident_possible(const pc_plan* P, int64_t n_ib, int mode);
+// Device bytes of a workspace (pc_workspace_bytes) from the geometry's counts.
+int64_t workspace_bytes_for(const pc_plan* P, bool geometry, int64_t n_ib, int64_t n_near,
+                            int mode);
 // Upper bound of the total length of the six tile lists.
 int64_t resident_tiles_max(const pc_plan* P, size_t elem);
 // Tile lists (host) of the resident transforms: near_pts are the near-IB

@@ -1160,11 +1160,15 @@ int remove_mean_f64(const pc_plan* P, double* phi, pc_workspace* ws, hipStream_t
 // is transformed exactly as in the full solve, so the result is the same
 // bit for bit.
 
-bool resident_ok(const pc_plan* P, const pc_geom* g, int mode) {
-  if (!g || g->n_ib == 0 || (mode != PC_F64 && mode != PC_F32)) return false;
+bool resident_possible(const pc_plan* P, int64_t n_ib, int mode) {
+  if (n_ib == 0 || (mode != PC_F64 && mode != PC_F32)) return false;
   for (int a = 0; a < P->d; ++a)
     if (P->n[a] < 32 || !pow2(P->n[a])) return false;
   return true;
+}
+
+bool resident_ok(const pc_plan* P, const pc_geom* g, int mode) {
+  return g && resident_possible(P, g->n_ib, mode);
 }
 
 int64_t resident_tiles_max(const pc_plan* P, size_t elem) {

@@ -1025,6 +1025,33 @@ struct Scratch {
   }
 };
 
+// Device bytes held by a geometry with these counts (the arrays of
+// pc_wls_build; the node permutation of PC_ORDER_CELL not included).
+int64_t geom_bytes_for(int d, int64_t G, int64_t M, int k_grid, int bn, int64_t n_ib,
+                       int64_t n_near, int near_w, bool want32, int k_self, int64_t n_v) {
+  const int64_t ms = (M + 63) / 64 * 64, ibs = (n_ib + 63) / 64 * 64;
+  const int64_t ell = n_near ? (int64_t)near_w * ((n_near + 63) / 64 * 64) : 0;
+  int64_t bytes = (int64_t)k_grid * G * 4 + (int64_t)d * k_grid * G * 8 + M * 4 +
+                  (int64_t)d * bn * ms * 8 + n_ib * 4 + n_near * 4 + ell * (4 + 8 * d) +
+                  n_ib * 4 + ibs * 8 * (int64_t)d * bn;
+  if (want32)
+    bytes += (int64_t)d * k_grid * G * 4 + (int64_t)d * bn * ms * 4 + ell * 4 * d +
+             ibs * 4 * (int64_t)d * bn;
+  bytes += (int64_t)k_self * ms * (4 + 8 * (d + 1)) + n_v * 4;
+  if (want32) bytes += (int64_t)k_self * ms * 4 * (d + 1);
+  return bytes;
+}
+
+// Scratch a build holds at most at once besides the geometry's own arrays:
+// the cell list (counts, starts, cursors, sorted nodes), flags, the scan
+// sums, the near flags and the slot map; PC_ORDER_CELL adds its own cell
+// list and the nodes in cell order.
+int64_t build_scratch_bytes(int d, int64_t G, int64_t M, bool cell_order) {
+  int64_t b = 4 * G + 4 * (G + 1) + 4 * G + 4 * M + 256 + G + 4 * M + 8 * ((G + 1023) / 1024);
+  if (cell_order) b += 4 * G + 4 * (G + 1) + 4 * G + 256 + 8 * (int64_t)d * M + M;
+  return b;
+}
+
 GridDesc grid_desc(const pc_plan* P) {
   GridDesc gd;
   gd.per = 0;
@@ -1309,16 +1336,8 @@ int build(const pc_plan* P, const double* xyz, const uint8_t* kind, int64_t M,
     PC_HIP_CHECK(hipGetLastError());
   }
   PC_HIP_CHECK(hipStreamSynchronize(s));
-  const int64_t ell = g->n_near ? (int64_t)g->near_w * g->nns : 0;
-  int64_t bytes = (int64_t)k_grid * G * 4 + (int64_t)d * k_grid * G * 8 + M * 4 +
-                  (int64_t)d * bn * g->ms * 8 + g->n_ib * 4 + g->n_near * 4 + ell * (4 + 8 * d) +
-                  g->n_ib * 4 + g->ibs * 8 * (int64_t)d * bn;
-  if (want32)
-    bytes += (int64_t)d * k_grid * G * 4 + (int64_t)d * bn * g->ms * 4 + ell * 4 * d +
-             g->ibs * 4 * (int64_t)d * bn;
-  bytes += (int64_t)k_self * g->ms * (4 + 8 * (d + 1)) + g->n_v * 4;
-  if (want32) bytes += (int64_t)k_self * g->ms * 4 * (d + 1);
-  g->bytes = bytes;
+  g->bytes = geom_bytes_for(d, G, M, k_grid, bn, g->n_ib, g->n_near, g->near_w, want32, k_self,
+                            g->n_v);
   return PC_OK;
 }
 
@@ -1420,6 +1439,37 @@ int pc_geom_export(const pc_geom* g, int32_t* gidx, double* gcoef, int32_t* nbas
                                   hipMemcpyDeviceToDevice, s));
   PC_TRY(cp(ib, g->ib, (size_t)g->n_ib * 4));
   PC_TRY(cp(near, g->near, (size_t)g->n_near * 4));
+  return PC_OK;
+}
+
+int pc_geom_footprint(const pc_plan* P, int64_t M, int64_t n_ib, int64_t n_near,
+                      const pc_wls_opts* o, int64_t* geom_bytes, int64_t* build_peak_bytes,
+                      int64_t* ws_bytes) {
+  if (!P) return fail(PC_ERR_INVALID_ARG, "pc_geom_footprint: null plan");
+  if (M <= 0 || n_ib < 0 || n_ib > M || n_near < 0 || n_near > P->G)
+    return fail(PC_ERR_INVALID_ARG, "pc_geom_footprint: counts out of range");
+  const int d = P->d;
+  const int k_grid = o && o->k_grid ? o->k_grid : 16;
+  const int k_node = o && o->k_node ? o->k_node : (d == 2 ? 16 : 27);
+  const bool want32 = o && (o->dtype_mask & 1);
+  const int k_self = o ? o->k_self : 0;
+  const bool cell = o && o->order == PC_ORDER_CELL;
+  int m = 1;
+  while ((int)std::pow(m, d) < k_node) ++m;
+  if (m < 3) m = 3;
+  int bn = 1;
+  for (int a = 0; a < d; ++a) bn *= m;
+  // the near table is as wide as the most B+V entries of a near point: at
+  // most k_grid, rounded up to the kernel's widths
+  const int near_w = k_grid <= 8 ? 8 : (k_grid <= 16 ? 16 : 32);
+  const int64_t gb = geom_bytes_for(d, P->G, M, k_grid, bn, n_ib, n_near, near_w, want32, k_self,
+                                    n_ib) + (cell ? M * 4 : 0);
+  if (geom_bytes) *geom_bytes = gb;
+  if (build_peak_bytes) *build_peak_bytes = gb + build_scratch_bytes(d, P->G, M, cell);
+  if (ws_bytes) {
+    const int modes[3] = {PC_F64, PC_F32, PC_MIXED};
+    for (int i = 0; i < 3; ++i) ws_bytes[i] = workspace_bytes_for(P, true, n_ib, n_near, modes[i]);
+  }
   return PC_OK;
 }
 

@@ -47,7 +47,7 @@ EXPORTS = [
     "pc_workspace_create", "pc_workspace_destroy", "pc_workspace_bytes",
     "pc_pressure_correct", "pc_geom_export_self", "pc_momentum_predict", "pc_momentum_pressure",
     "pc_set_allocator", "pc_geom_export_at", "pc_ib_update_noalloc", "pc_geom_permutation",
-    "pc_geom_permute",
+    "pc_geom_permute", "pc_geom_footprint",
 ]
 
 # pc_alloc_fn / pc_free_fn
@@ -124,6 +124,8 @@ def _load():
         "pc_geom_export_self": ([vp, vp, vp, vp], ctypes.c_int),
         "pc_geom_export_at": ([vp, vp, i64, vp, vp, vp, i64, vp, vp, vp], ctypes.c_int),
         "pc_geom_permutation": ([vp, vp, vp], ctypes.c_int),
+        "pc_geom_footprint": ([vp, i64, i64, i64, ctypes.POINTER(WlsOpts), vp, vp, vp],
+                              ctypes.c_int),
         "pc_geom_permute": ([vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp, vp],
                             ctypes.c_int),
         "pc_momentum_predict": ([vp, ctypes.c_int, vp, vp, dbl, dbl, vp, vp, vp, vp],
@@ -298,6 +300,21 @@ def geom_export(geom: Geometry, grid_idx=None, grid_coef=None, node_base=None,
     return _check(_lib.pc_geom_export(geom.h_, _ptr(grid_idx), _ptr(grid_coef),
                                       _ptr(node_base), _ptr(node_coef), _ptr(ib), _ptr(near),
                                       _stream(stream)))
+
+
+def geom_footprint(plan: Plan, M: int, n_ib: int, n_near: int, k_grid: int = 0,
+                   k_node: int = 0, want_f32: bool = False, k_self: int = 0,
+                   order: str = "caller"):
+    """(geometry bytes, build peak bytes, {mode: workspace bytes}) before a
+    build (pc_geom_footprint); n_near is a bound on the near-IB points."""
+    opts = WlsOpts(k_grid, k_node, 0.0, 0.0, 0.0, 1 if want_f32 else 0, k_self,
+                   ORDERS[order] if isinstance(order, str) else int(order))
+    gb, pk = ctypes.c_int64(), ctypes.c_int64()
+    ws = (ctypes.c_int64 * 3)()
+    _check(_lib.pc_geom_footprint(plan.h_, M, n_ib, n_near, ctypes.byref(opts),
+                                  ctypes.byref(gb), ctypes.byref(pk), ws))
+    return int(gb.value), int(pk.value), {PC_F64: int(ws[0]), PC_F32: int(ws[1]),
+                                          PC_MIXED: int(ws[2])}
 
 
 def geom_permutation(geom: Geometry, perm: torch.Tensor, stream=None) -> int:

@@ -131,10 +131,11 @@ class Scheduler:
         """Bytes admission must find for r: its stencils unless resident, a
         workspace unless one is pooled, and its output fields."""
         need = self.ex.field_bytes(r.key, r.mode)
-        if r.key not in self.geoms:
+        g = self.geoms.get(r.key)
+        if g is None:
             need += self.ex.geometry_bytes(r.key)
         if not self.ws_pool.get((r.key, r.mode)):
-            need += self.ex.workspace_bytes(r.key, r.mode)
+            need += self.ex.workspace_bytes(r.key, r.mode, g.handle if g is not None else None)
         return need
 
     def _evict_for(self, need: int, keep: GeomKey, keep_mode: int) -> bool:
@@ -258,7 +259,7 @@ class Scheduler:
                         if pool:
                             ws = pool.pop()
                         else:
-                            ws = _Resident(None, self.ex.workspace_bytes(r.key, r.mode))
+                            ws = _Resident(None, self.ex.workspace_bytes(r.key, r.mode, g.handle))
                         fb = self.ex.field_bytes(r.key, r.mode)
                         self.inflight_bytes += ws.bytes + fb
                         self.peak_bytes = max(self.peak_bytes, self._held())
@@ -395,24 +396,35 @@ class GpuExecutor:
                 self.plans[(d, N)] = self.pc.Plan(d, it["n"], it["h"])
             return self.plans[(d, N)]
 
-    # sizes used for admission (upper bounds before the objects exist)
-    def geometry_bytes(self, key) -> int:
-        d, N, _ = key
+    # Sizes used for admission, from the library's own accounting
+    # (pc_geom_footprint before a geometry exists, pc_workspace_bytes and
+    # pc_geom_info after).  The near-IB point count is known only after the
+    # build; admission bounds it by four times the B+V nodes (about one near
+    # point per B+V node for these obstacles: the grid points inside the body
+    # and a thin shell around it).
+    def _footprint(self, key):
         it = self.data[key]
-        G, M, k = N ** d, it["M"], it["k"]
-        m = math.ceil(round(k ** (1.0 / d), 9))
-        bn = m ** d
-        return int(G * k * (4 + 8 * d) + M * (4 + bn * d * 8) + 8 * M + 16 * G + (64 << 20))
+        if "footprint" not in it:
+            d, N, _ = key
+            n_ib = int((it["kind"] != 0).sum().item())
+            it["n_ib"] = n_ib
+            it["footprint"] = self.pc.geom_footprint(self.plan(d, N), it["M"], n_ib,
+                                                     min(N ** d, 4 * n_ib + 64), it["k"],
+                                                     it["k"])
+        return it["footprint"]
+
+    def geometry_bytes(self, key) -> int:
+        """Device bytes a build of key's stencils needs at its peak."""
+        return self._footprint(key)[1]
 
     def actual_geometry_bytes(self, handle, estimate) -> int:
         return int(handle.bytes)
 
-    def workspace_bytes(self, key, mode) -> int:
-        d, N, _ = key
-        G, M = N ** d, self.data[key]["M"]
-        s = 8
-        b = 3 * G * s + (G * 4 if mode == self.pc.PC_MIXED else 0)
-        return int(b + 6 * d * M // 8 + (8 << 20))
+    def workspace_bytes(self, key, mode, geom=None) -> int:
+        if geom is not None:
+            d, N, _ = key
+            return self.pc.workspace_bytes(self.plan(d, N), geom, mode)
+        return self._footprint(key)[2][mode]
 
     def field_bytes(self, key, mode) -> int:
         d, N, _ = key

@@ -73,3 +73,31 @@ def test_mix_equals_alone_and_oracle(data):
         assert eu <= tol and ep <= tol
     sch.release()
     sch1.release()
+
+
+def test_footprint_matches_the_built_geometry(data):
+    """pc_geom_footprint before a build against what the geometry and its
+    workspaces take afterwards: the same workspace bytes, geometry bytes
+    equal for the exact near-point count up to the near table's width, and
+    an upper bound for a larger near-point bound."""
+    import torch
+    from paper_2304_14690_amd import pcorr as pc
+    for key in [(2, 128, 0), (3, 32, 1)]:
+        it = data[key]
+        plan = pc.Plan(key[0], it["n"], it["h"])
+        for want_f32, order in ((False, "caller"), (True, "cell")):
+            g = pc.wls_build(plan, it["x"], it["kind"], it["k"], it["k"], want_f32=want_f32,
+                             order=order)
+            n_ib = int((it["kind"] != 0).sum().item())
+            assert g.n_ib == n_ib
+            gb, peak, ws = pc.geom_footprint(plan, it["M"], n_ib, g.n_near, it["k"], it["k"],
+                                             want_f32=want_f32, order=order)
+            wide = g.near_w != (8 if it["k"] <= 8 else (16 if it["k"] <= 16 else 32))
+            assert gb >= g.bytes and (wide or gb == g.bytes)
+            assert peak > gb
+            for mode in (pc.PC_F64, pc.PC_F32, pc.PC_MIXED):
+                assert ws[mode] == pc.workspace_bytes(plan, g, mode)
+            gb2, _, _ = pc.geom_footprint(plan, it["M"], n_ib, 4 * g.n_near, it["k"], it["k"],
+                                          want_f32=want_f32, order=order)
+            assert gb2 > gb
+            del g

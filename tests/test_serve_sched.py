@@ -38,7 +38,7 @@ class FakeExecutor:
     def actual_geometry_bytes(self, handle, estimate):
         return handle[1]
 
-    def workspace_bytes(self, key, mode):
+    def workspace_bytes(self, key, mode, geom=None):
         return self.sizes[key[:2]][1] * (2 if mode == MIXED else 1)
 
     def field_bytes(self, key, mode):
