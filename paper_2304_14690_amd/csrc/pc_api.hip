@@ -327,6 +327,7 @@ int64_t workspace_bytes_for(const pc_plan* P, bool geometry, int64_t n_ib, int64
     for (int i = 0; i < 3; ++i) add((int64_t)P->d * n_ib * (int64_t)s);  // uib, gib, gradib
   }
   if (mode == PC_MIXED) add(P->G * 4);   // w32
+  if (mode == PC_MIXED && geometry) add(8 * ((n_near + 255) / 256));  // part2
   if (geometry && pc::resident_possible(P, n_ib, mode)) {
     if (P->d == 3) add(P->G * (int64_t)s);             // w1b
     add(4 * pc::resident_tiles_max(P, s));            // tile lists
@@ -412,6 +413,7 @@ int pc_workspace_create(const pc_plan* P, const pc_geom* g, int mode, pc_workspa
     W->gradib = take((int64_t)g->d * g->n_ib * (int64_t)s);
   }
   if (mode == PC_MIXED) W->w32 = reinterpret_cast<float*>(take(P->G * 4));
+  if (mode == PC_MIXED && g) W->part2 = reinterpret_cast<double*>(take(8 * ((g->n_near + 255) / 256)));
   if (pc::resident_ok(P, g, mode)) {
     if (P->d == 3) W->w1b = take(P->G * (int64_t)s);
     W->tiles = reinterpret_cast<int32_t*>(take(4 * pc::resident_tiles_max(P, s)));

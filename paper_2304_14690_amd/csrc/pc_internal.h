@@ -111,7 +111,8 @@ struct pc_geom {
   int32_t* ib;          // [n_ib] node index
   int32_t* near;        // [n_near] grid index
   // near-IB stencils restricted to their B+V entries, ELL layout of width
-  // near_w (8, 16 or 32, at least the most B+V entries of any near point):
+  // near_w (8, 16, 27 or 32, at least the most B+V entries of any near
+  // point; 27, the 3D stencil of the workloads, only in 3D):
   // entry e of near point q at e*nns + q, slot -1 / coefficient 0 past the
   // point's last entry; nns = n_near rounded up to 64
   int near_w;
@@ -171,6 +172,7 @@ struct pc_workspace {
   void* gib;         // [d][n_ib] field dtype: IB force (times dt)
   void* gradib;      // [d][n_ib] field dtype
   double* partial;   // reduction partials
+  double* part2;     // PC_MIXED: block sums of the near-IB RHS update (mean of b)
   double* scal;      // small float64 scalars: [0] bmean, [1] num, [2] den, [3] mean phi
   int32_t* flag;     // [0] converged flag
   int32_t* hflag;    // pinned host mirror of the flag
@@ -211,7 +213,11 @@ int solve_f32(const pc_plan* P, const float* b, float* phi, double* bmean_dev,
 // of the corrections) for the caller to remove.
 int solve_mixed(const pc_plan* P, const double* b, double* phi, int sweeps, double* bmean_dev,
                 pc_workspace* ws, hipStream_t s, double sigma = 1.0,
-                const int32_t* skip = nullptr, bool warm = false, bool remove_mean = true);
+                const int32_t* skip = nullptr, bool warm = false, bool remove_mean = true,
+                bool bmean_given = false);
+// Mean of a float64 grid field (trapezoid-weighted on a vertex grid).
+int grid_mean_f64(const pc_plan* P, const double* x, double* partial, int nblk, double* out_dev,
+                  hipStream_t s, const int32_t* skip = nullptr);
 int remove_mean_f64(const pc_plan* P, double* phi, pc_workspace* ws, hipStream_t s,
                     const int32_t* skip = nullptr);
 int ensure_plan_ws(const pc_plan* P, pc_workspace** ws);

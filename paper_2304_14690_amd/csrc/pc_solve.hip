@@ -1122,11 +1122,11 @@ int solve_f32(const pc_plan* P, const float* b, float* phi, double* bmean_dev, p
 // dominate the float32 rounding of the much smaller residual.
 int solve_mixed(const pc_plan* P, const double* b, double* phi, int sweeps, double* bmean_dev,
                 pc_workspace* ws, hipStream_t s, double sigma, const int32_t* skip, bool warm,
-                bool remove_mean) {
+                bool remove_mean, bool bmean_given) {
   if (!ws || !ws->w32) return fail(PC_ERR_INVALID_ARG, "mixed solve needs a MIXED workspace");
   float* w = ws->w32;
   double* bm = bmean_dev ? bmean_dev : ws->scal;
-  PC_TRY(grid_mean_f64(P, b, ws->partial, ws->nblk, bm, s, skip));
+  if (!bmean_given) PC_TRY(grid_mean_f64(P, b, ws->partial, ws->nblk, bm, s, skip));
   if (!warm)
     PC_TRY((solve_passes<float, double, double, LD_PLAIN, ST_PLAIN>(
         P, P->ax32, b, phi, w, nullptr, nullptr, nullptr, s, bm, sigma, skip)));

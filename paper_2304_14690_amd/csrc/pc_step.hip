@@ -170,25 +170,13 @@ __device__ int ib_close_block(const IbClose& C, bool write) {
 // produced g (every block, identically; block 0 stores it), which saves the
 // criterion its own launch, and updates b only if that iteration has not
 // converged.
-template <typename T, int D, bool ADD, int WT, bool CLOSE>
-__global__ void __launch_bounds__(TPB) k_div_near(const int32_t* __restrict__ near, int64_t nnear,
-                                                  int64_t nns, const int32_t* __restrict__ nslot,
-                                                  const T* __restrict__ ncoef,
-                                                  const T* __restrict__ gib, int64_t nib,
-                                                  const T* __restrict__ base, T* __restrict__ b,
-                                                  const int32_t* __restrict__ skip, IbClose close) {
-  if (CLOSE) {
-    // block 0 may set the flag while other blocks start: read it once per
-    // block, so that no thread leaves before the criterion's barriers
-    __shared__ int sk;
-    if (threadIdx.x == 0) sk = skip ? *skip : 0;
-    __syncthreads();
-    if (sk || ib_close_block(close, blockIdx.x == 0)) return;
-  } else if (skip && *skip) {
-    return;
-  }
-  int64_t q = (int64_t)blockIdx.x * TPB + threadIdx.x;
-  if (q >= nnear) return;
+// b[near[q]] = base[q] (or b, ADD) + D(g) at near point q; returns D(g).
+template <typename T, int D, bool ADD, int WT>
+__device__ __forceinline__ T near_update(const int32_t* __restrict__ near, int64_t q, int64_t nns,
+                                         const int32_t* __restrict__ nslot,
+                                         const T* __restrict__ ncoef, const T* __restrict__ gib,
+                                         int64_t nib, const T* __restrict__ base,
+                                         T* __restrict__ b) {
   // WT is the table width itself (padding entries have slot -1 and
   // coefficient exactly 0), so every load is unconditional and all of them
   // are in flight together
@@ -206,6 +194,72 @@ __global__ void __launch_bounds__(TPB) k_div_near(const int32_t* __restrict__ ne
     b[p] += acc;
   else
     b[p] = base[q] + acc;
+  return acc;
+}
+
+// With MEAN each block also adds up its D(g) values (fixed order) into
+// part[blockIdx.x]: b changes only at the near points, so the mean of b is
+// the mean of b_u plus their sum over the grid size (k_mean_near).
+template <typename T, int D, bool ADD, int WT, bool CLOSE, bool MEAN>
+__global__ void __launch_bounds__(TPB) k_div_near(const int32_t* __restrict__ near, int64_t nnear,
+                                                  int64_t nns, const int32_t* __restrict__ nslot,
+                                                  const T* __restrict__ ncoef,
+                                                  const T* __restrict__ gib, int64_t nib,
+                                                  const T* __restrict__ base, T* __restrict__ b,
+                                                  const int32_t* __restrict__ skip, IbClose close,
+                                                  double* __restrict__ part) {
+  if (CLOSE) {
+    // block 0 may set the flag while other blocks start: read it once per
+    // block, so that no thread leaves before the criterion's barriers
+    __shared__ int sk;
+    if (threadIdx.x == 0) sk = skip ? *skip : 0;
+    __syncthreads();
+    if (sk || ib_close_block(close, blockIdx.x == 0)) return;
+  } else if (skip && *skip) {
+    return;
+  }
+  int64_t q = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  if (MEAN) {
+    // every thread of the block reaches the reduction
+    T acc = T(0);
+    if (q < nnear) acc = near_update<T, D, ADD, WT>(near, q, nns, nslot, ncoef, gib, nib, base, b);
+    __shared__ double red[TPB / 64];
+    double v = (double)acc;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t = red[0];
+#pragma unroll
+      for (int w = 1; w < TPB / 64; ++w) t += red[w];
+      part[blockIdx.x] = t;
+    }
+    return;
+  }
+  if (q >= nnear) return;
+  (void)near_update<T, D, ADD, WT>(near, q, nns, nslot, ncoef, gib, nib, base, b);
+}
+
+// out[0] = mean_u[0] + (sum of part[0..nb)) * inv_g, the sum in a fixed order.
+__global__ void __launch_bounds__(TPB) k_mean_near(const double* __restrict__ part, int nb,
+                                                   const double* __restrict__ mean_u,
+                                                   double inv_g, double* __restrict__ out,
+                                                   const int32_t* __restrict__ skip) {
+  if (skip && *skip) return;
+  __shared__ double red[TPB / 64];
+  double v = 0.0;
+  for (int i = threadIdx.x; i < nb; i += TPB) v += part[i];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = red[0];
+#pragma unroll
+    for (int w = 1; w < TPB / 64; ++w) t += red[w];
+    out[0] = mean_u[0] + t * inv_g;
+  }
 }
 
 // ---- grad_to_nodes (all nodes), optionally fused with the projection ---------
@@ -652,31 +706,40 @@ int launch_div_all(const pc_geom* g, const T* gcoef, const T* v, T* b, hipStream
 }
 
 // close (nullable): the criterion of the iteration that produced gib,
-// evaluated in the same launch (needs n_near > 0).
+// evaluated in the same launch (needs n_near > 0).  mean_part (nullable):
+// each block's sum of D(g) (k_div_near's MEAN), nblk(n_near) doubles.
 template <typename T>
 int launch_div_near(const pc_geom* g, const T* ncoefib, const T* gib, const T* base, T* b,
                     bool add, hipStream_t s, const int32_t* skip = nullptr,
-                    const IbClose* close = nullptr) {
+                    const IbClose* close = nullptr, double* mean_part = nullptr) {
   if (g->n_near == 0) return close ? fail(PC_ERR_INVALID_ARG, "criterion without near points")
                                    : PC_OK;
   dim3 grid(nblk(g->n_near)), block(TPB);
   const IbClose cl = close ? *close : IbClose{};
-#define DNL(D, ADD, WT)                                                                          \
-  do {                                                                                           \
-    if (close)                                                                                   \
-      hipLaunchKernelGGL((k_div_near<T, D, ADD, WT, true>), grid, block, 0, s, g->near,        \
-                         g->n_near, g->nns, g->nslot, ncoefib, gib, g->n_ib, base, b, skip, cl); \
-    else                                                                                         \
-      hipLaunchKernelGGL((k_div_near<T, D, ADD, WT, false>), grid, block, 0, s, g->near,       \
-                         g->n_near, g->nns, g->nslot, ncoefib, gib, g->n_ib, base, b, skip, cl); \
+#define DNM(D, ADD, WT, CL)                                                                    \
+  do {                                                                                         \
+    if (mean_part)                                                                             \
+      hipLaunchKernelGGL((k_div_near<T, D, ADD, WT, CL, true>), grid, block, 0, s, g->near,   \
+                         g->n_near, g->nns, g->nslot, ncoefib, gib, g->n_ib, base, b, skip, cl, \
+                         mean_part);                                                           \
+    else                                                                                       \
+      hipLaunchKernelGGL((k_div_near<T, D, ADD, WT, CL, false>), grid, block, 0, s, g->near,  \
+                         g->n_near, g->nns, g->nslot, ncoefib, gib, g->n_ib, base, b, skip, cl, \
+                         mean_part);                                                           \
+  } while (0)
+#define DNL(D, ADD, WT)                     \
+  do {                                      \
+    if (close) DNM(D, ADD, WT, true);       \
+    else DNM(D, ADD, WT, false);            \
   } while (0)
 #define DNW(D, ADD)                                 \
   do {                                              \
     if (g->near_w == 8) DNL(D, ADD, 8);             \
     else if (g->near_w == 16) DNL(D, ADD, 16);      \
+    else if (D == 3 && g->near_w == 27) DNL(D, ADD, 27); \
     else DNL(D, ADD, 32);                           \
   } while (0)
-  if (g->near_w != 8 && g->near_w != 16 && g->near_w != 32)
+  if (g->near_w != 8 && g->near_w != 16 && g->near_w != 32 && !(g->d == 3 && g->near_w == 27))
     return fail(PC_ERR_INVALID_ARG, "near-IB table width");
   if (g->d == 2) {
     if (add) DNW(2, true); else DNW(2, false);
@@ -685,6 +748,7 @@ int launch_div_near(const pc_geom* g, const T* ncoefib, const T* gib, const T* b
   }
 #undef DNW
 #undef DNL
+#undef DNM
   PC_HIP_CHECK(hipGetLastError());
   return PC_OK;
 }
@@ -876,6 +940,13 @@ int pressure_correct_t(const pc_geom* g, const pc_plan* P, int mode, const T* u,
                        g->n_near, (const T*)b, bnear);
     PC_HIP_CHECK(hipGetLastError());
   }
+  // PC_MIXED needs mean(b) before its first float32 pass in every
+  // iteration.  b changes only at the near points, so it is mean(b_u) (one
+  // pass, here) plus the near update's sum over G, which the update kernel
+  // adds up per block (cell-centred grids; a vertex grid's mean is
+  // weighted, and every iteration takes it over the grid).
+  const bool inc_mean = mode == PC_MIXED && !P->vertex && g->n_near > 0 && W->part2;
+  if (inc_mean) PC_TRY(grid_mean_f64(P, (const double*)b, W->partial, W->nblk, W->scal + 5, s));
 
   // One IB iteration (Sec. 2.3): RHS update near the IB, Poisson solve,
   // gradient at the B+V nodes, force update and criterion.  With `skip` set,
@@ -888,8 +959,16 @@ int pressure_correct_t(const pc_geom* g, const pc_plan* P, int mode, const T* u,
   auto iteration = [&](int it, const int32_t* skip, int32_t* host_flag, bool defer = false,
                        const IbClose* prev = nullptr) -> int {
     double* host_sums = host_flag ? W->hscal + 4 + 2 * (it & 1) : nullptr;
-    if (it > 1 || g_io)
-      PC_TRY(launch_div_near<T>(g, nci<T>(g), gib, bnear, b, false, s, skip, prev));
+    const bool upd = it > 1 || g_io;
+    if (upd)
+      PC_TRY(launch_div_near<T>(g, nci<T>(g), gib, bnear, b, false, s, skip, prev,
+                                inc_mean ? W->part2 : nullptr));
+    if (inc_mean) {
+      hipLaunchKernelGGL(k_mean_near, dim3(1), dim3(TPB), 0, s, (const double*)W->part2,
+                         upd ? (int)nblk(g->n_near) : 0, (const double*)(W->scal + 5),
+                         1.0 / (double)P->G, W->scal, skip);
+      PC_HIP_CHECK(hipGetLastError());
+    }
     if (resident && mode == PC_F64)
       PC_TRY(solve_resident_f64(P, (const double*)b, (double*)p, W->scal, W, s, sigma, skip,
                                 it > 1 ? 1 : 0));
@@ -905,7 +984,7 @@ int pressure_correct_t(const pc_geom* g, const pc_plan* P, int mode, const T* u,
       // iteration's pressure, whose right-hand side differs only near the
       // IB; the mean is removed once, after the last iteration
       PC_TRY(solve_mixed(P, (const double*)b, (double*)p, sweeps, W->scal, W, s, sigma, skip,
-                         it > 1, false));
+                         it > 1, false, inc_mean));
     if (nib)
       PC_TRY(launch_ib_step<T>(g, ibc<T>(g), p, (T)sigma, uib, gib, tol, W->partial, W->flag,
                                W->scal + 1, s, skip, host_flag, host_sums, !defer));

@@ -1293,7 +1293,7 @@ int build(const pc_plan* P, const double* xyz, const uint8_t* kind, int64_t M,
   g->n_near = (int64_t)hnear.size();
   g->n_near_entries = near_entries;
   // the ELL width is one of three compile-time bounds of the update kernel
-  near_w = near_w <= 8 ? 8 : (near_w <= 16 ? 16 : 32);
+  near_w = near_w <= 8 ? 8 : (near_w <= 16 ? 16 : (near_w <= 27 && d == 3 ? 27 : 32));
   g->near_w = near_w;
   g->nns = (g->n_near + 63) / 64 * 64;
   g->ibs = (g->n_ib + 63) / 64 * 64;
@@ -1461,7 +1461,7 @@ int pc_geom_footprint(const pc_plan* P, int64_t M, int64_t n_ib, int64_t n_near,
   for (int a = 0; a < d; ++a) bn *= m;
   // the near table is as wide as the most B+V entries of a near point: at
   // most k_grid, rounded up to the kernel's widths
-  const int near_w = k_grid <= 8 ? 8 : (k_grid <= 16 ? 16 : 32);
+  const int near_w = k_grid <= 8 ? 8 : (k_grid <= 16 ? 16 : (k_grid <= 27 && d == 3 ? 27 : 32));
   const int64_t gb = geom_bytes_for(d, P->G, M, k_grid, bn, n_ib, n_near, near_w, want32, k_self,
                                     n_ib) + (cell ? M * 4 : 0);
   if (geom_bytes) *geom_bytes = gb;
