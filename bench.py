@@ -62,6 +62,10 @@ WORKLOADS = {
     "3d256": {"d": 3, "N": 256, "modes": "f64,f32,mixed", "cpu_N": 64,
               "desc": "3D 256^3 grid, {M} jittered nodes, sphere r=0.1 at the centre, 27-NN "
                       "WLS, 64-mode velocity, Neumann box, cold IB start"},
+    "2d2000": {"d": 2, "N": 2000, "modes": "f64,f32,mixed", "cpu_N": 1000,
+               "desc": "2D 2000^2 grid (n/2 = 2^3 5^3: the mixed-radix transforms), {M} "
+                       "jittered nodes, cylinder r=0.05 at (0.3,0.5), 16-NN WLS, 32-mode "
+                       "velocity, Neumann box, cold IB start"},
     "2d2048p": {"d": 2, "N": 2048, "modes": "f64,f32,mixed", "cpu_N": 1024,
                 "bc": ("periodic", "neumann"),
                 "desc": "2D 2048^2 grid, {M} jittered nodes, cylinder r=0.05 at (0.3,0.5), "
@@ -178,7 +182,7 @@ def make_workload(name, N):
                              16, 16, 32, 3, 4, bc=bc)
         return {"d": 2, "n": c.n, "h": c.h, "x": c.x, "kind": c.kind, "k": c.k_grid,
                 "u": torch.from_numpy(c.u).cuda(), "bc": bc}
-    if name in ("2d2048", "2d2048p", "2d2048pp"):
+    if name in ("2d2048", "2d2000", "2d2048p", "2d2048pp"):
         c = inputs.make_case(name, 2, N, [inputs.Obstacle("circle", (0.3, 0.5), (0.05,))],
                              16, 16, 32, 3, 4, bc=bc)
         return {"d": 2, "n": c.n, "h": c.h, "x": c.x, "kind": c.kind, "k": c.k_grid,
@@ -690,7 +694,7 @@ def cpu_baseline(workload, N):
     elif workload == "2d400sq":
         c = inputs.make_case(workload, 2, N, [inputs.Obstacle("box", (0.45, 0.45), (0.55, 0.55))],
                              16, 16, 32, 3, 4, bc=bc)
-    elif workload in ("2d2048", "2d2048p", "2d2048pp"):
+    elif workload in ("2d2048", "2d2000", "2d2048p", "2d2048pp"):
         c = inputs.make_case(workload, 2, N, [inputs.Obstacle("circle", (0.3, 0.5), (0.05,))],
                              16, 16, 32, 3, 4, bc=bc)
     elif workload in ("3d256", "3d256p", "3d256pp"):

@@ -226,6 +226,14 @@ constexpr int RAD_VALUES = 8;
 // Lines per workgroup tile of the register transform along `axis` for
 // elements of `elem` bytes (0 when the axis uses the generic kernel).
 int rad_tile_lines(const pc_plan* P, int axis, size_t elem);
+// Tile geometry of a transform pass along an axis: lines per tile C, tiles
+// along x tx (strided passes number tile o * tx + i / C), and the tile count.
+struct PassTiles {
+  int C;
+  int64_t tx;
+  int64_t ntile;
+};
+PassTiles pass_tiles(const pc_plan* P, int axis, size_t elem);
 // Whether the resident IB-iteration transforms apply to this plan/geometry/mode.
 bool resident_ok(const pc_plan* P, const pc_geom* g, int mode);
 bool resident_possible(const pc_plan* P, int64_t n_ib, int mode);

@@ -218,7 +218,8 @@ __global__ void __launch_bounds__(1024) dct_lines(LineArgs<TC> A) {
   const int ls = N + A.pad;  // line stride in LDS (reals)
   TC* s2 = s + (size_t)C * ls;  // second buffer
   const int tid = threadIdx.x, nthr = blockDim.x;
-  const int t = A.axis == 0 ? blockIdx.x : xcd_tile(blockIdx.x, gridDim.x);
+  const int t = A.tiles ? A.tiles[blockIdx.x]
+                        : (A.axis == 0 ? blockIdx.x : xcd_tile(blockIdx.x, gridDim.x));
   const TI* __restrict__ in = reinterpret_cast<const TI*>(A.in);
   TO* __restrict__ out = reinterpret_cast<TO*>(A.out);
 
@@ -526,7 +527,8 @@ __global__ void __launch_bounds__(1024) rdft_lines(LineArgs<TC> A) {
   TC* s1 = s0 + (size_t)C * ls;
   TC* xs = s1 + (size_t)C * ls;
   const int tid = threadIdx.x, nthr = blockDim.x;
-  const int t = A.axis == 0 ? blockIdx.x : xcd_tile(blockIdx.x, gridDim.x);
+  const int t = A.tiles ? A.tiles[blockIdx.x]
+                        : (A.axis == 0 ? blockIdx.x : xcd_tile(blockIdx.x, gridDim.x));
   const TI* __restrict__ in = reinterpret_cast<const TI*>(A.in);
   TO* __restrict__ out = reinterpret_cast<TO*>(A.out);
   const AxisTables<TC>& Tb = A.tab;
@@ -829,6 +831,53 @@ int rad_tile_lines(const pc_plan* P, int axis, size_t elem) {
   return C;
 }
 
+// Lines per workgroup tile of the generic kernel for a Neumann axis (the
+// choice of tile_shape) and for a periodic axis (rdft_lines), for elements
+// of `elem` bytes.
+static int generic_tile_lines(const pc_plan* P, int axis, size_t elem, int* nthr, int* B) {
+  const int N = P->n[axis];
+  const int64_t lines = P->G / N;
+  int C = 1, t = 64, b = 1;
+  if (P->bc[axis] == PC_BC_PERIODIC) {
+    const size_t per_line = (size_t)3 * (N + 2) * elem;
+    const int cmax = (int)std::max<size_t>(1, (size_t)lds_limit() / per_line);
+    const int want = axis == 0 ? std::max(1, 2048 / N) : (int)(128 / elem);
+    while (2 * C <= std::min(want, cmax)) C <<= 1;
+    C = fill_device(C, axis == 0 ? (lines + C - 1) / C
+                                 : (int64_t)((P->n[0] + C - 1) / C) * (lines / P->n[0]));
+  } else if (elem == 8) {
+    tile_shape<double>(axis, N, axis == 0 ? (int)lines : P->n[0], axis == 0 ? 1 : lines / P->n[0],
+                       &C, &t, &b);
+  } else {
+    tile_shape<float>(axis, N, axis == 0 ? (int)lines : P->n[0], axis == 0 ? 1 : lines / P->n[0],
+                      &C, &t, &b);
+  }
+  if (nthr) *nthr = t;
+  if (B) *B = b;
+  return C;
+}
+
+// Tile geometry of a pass along `axis` as the tile lists of the resident
+// transforms number the tiles: C lines per tile, tx tiles along x (strided
+// passes: tile = o * tx + i / C), ntile tiles in all.  Register kernels take
+// whole tiles; the periodic generic kernel masks a partial last tile.
+PassTiles pass_tiles(const pc_plan* P, int axis, size_t elem) {
+  PassTiles pt{};
+  const int N = P->n[axis];
+  const int64_t lines = P->G / N;
+  const bool reg = N >= 32 && pow2(N);
+  const bool masked = !reg && P->bc[axis] == PC_BC_PERIODIC;
+  pt.C = reg ? rad_tile_lines(P, axis, elem) : generic_tile_lines(P, axis, elem, nullptr, nullptr);
+  if (axis == 0) {
+    pt.tx = 1;
+    pt.ntile = masked ? (lines + pt.C - 1) / pt.C : lines / pt.C;
+  } else {
+    pt.tx = masked ? (P->n[0] + pt.C - 1) / pt.C : P->n[0] / pt.C;
+    pt.ntile = pt.tx * (lines / P->n[0]);
+  }
+  return pt;
+}
+
 namespace {
 
 template <typename TC, typename TI, typename TO, int OP, int LD, int ST>
@@ -953,12 +1002,7 @@ int launch_pass(const pc_plan* P, int axis, const TI* in, TO* out, const AxisTab
     if (A.nrad < 0) return fail(PC_ERR_UNSUPPORTED_SIZE, "transform length has too many factors");
     A.pad = 2;
     const size_t per_line = (size_t)3 * (A.N + A.pad) * sizeof(TC);
-    const int cmax = (int)std::max<size_t>(1, (size_t)lds_limit() / per_line);
-    int C = 1;
-    const int want = axis == 0 ? std::max(1, 2048 / A.N) : (int)(128 / sizeof(TC));
-    while (2 * C <= std::min(want, cmax)) C <<= 1;
-    C = fill_device(C, axis == 0 ? (lines + C - 1) / C
-                                 : (int64_t)((P->n[0] + C - 1) / C) * (lines / P->n[0]));
+    const int C = generic_tile_lines(P, axis, sizeof(TC), nullptr, nullptr);
     if ((size_t)C * per_line > (size_t)lds_limit())
       return fail(PC_ERR_UNSUPPORTED_SIZE, "transform line does not fit in LDS");
     if ((int64_t)C * A.N >= (1 << 17))  // div_small's range (butterfly indices)
@@ -970,6 +1014,10 @@ int launch_pass(const pc_plan* P, int axis, const TI* in, TO* out, const AxisTab
     } else {
       A.tx = (P->n[0] + C - 1) / C;
       ntile = (int64_t)A.tx * (lines / P->n[0]);
+    }
+    if (tiles) {
+      if (ntiles <= 0) return PC_OK;
+      ntile = ntiles;
     }
     int nthr = std::min(1024, std::max(64, C * H / 2));
     nthr = (nthr + 63) / 64 * 64;
@@ -984,10 +1032,8 @@ int launch_pass(const pc_plan* P, int axis, const TI* in, TO* out, const AxisTab
   }
   A.nrad = generic_radices(H, A.rad);
   if (A.nrad < 0) return fail(PC_ERR_UNSUPPORTED_SIZE, "transform length has too many factors");
-  int C, nthr, B;
-
-  tile_shape<TC>(axis, A.N, axis == 0 ? (int)lines : P->n[0], axis == 0 ? 1 : lines / P->n[0],
-                 &C, &nthr, &B);
+  int nthr, B;
+  const int C = generic_tile_lines(P, axis, sizeof(TC), &nthr, &B);
   A.C = C;
   if (C > nthr) return fail(PC_ERR_UNSUPPORTED_SIZE, "transform tile has more lines than threads");
   if ((int64_t)C * A.N >= (1 << 17))  // div_small's range (butterfly indices)
@@ -999,6 +1045,10 @@ int launch_pass(const pc_plan* P, int axis, const TI* in, TO* out, const AxisTab
   } else {
     A.tx = P->n[0] / C;
     ntile = (int)(lines / C);
+  }
+  if (tiles) {
+    if (ntiles <= 0) return PC_OK;
+    ntile = ntiles;
   }
   // pad each LDS line by one complex when it fits (fewer bank conflicts)
   A.pad = ((size_t)C * (A.N + 2) * sizeof(TC) * 2 <= (size_t)lds_limit()) ? 2 : 0;
@@ -1160,11 +1210,12 @@ int remove_mean_f64(const pc_plan* P, double* phi, pc_workspace* ws, hipStream_t
 // is transformed exactly as in the full solve, so the result is the same
 // bit for bit.
 
+// Every kernel of a cell-centred grid takes tile lists (the register
+// kernels, and the generic ones for lengths that are short or not powers of
+// two); the vertex grid's DCT-I kernel does not.
 bool resident_possible(const pc_plan* P, int64_t n_ib, int mode) {
   if (n_ib == 0 || (mode != PC_F64 && mode != PC_F32)) return false;
-  for (int a = 0; a < P->d; ++a)
-    if (P->n[a] < 32 || !pow2(P->n[a])) return false;
-  return true;
+  return !P->vertex;
 }
 
 bool resident_ok(const pc_plan* P, const pc_geom* g, int mode) {
@@ -1172,13 +1223,8 @@ bool resident_ok(const pc_plan* P, const pc_geom* g, int mode) {
 }
 
 int64_t resident_tiles_max(const pc_plan* P, size_t elem) {
-  const int C0 = rad_tile_lines(P, 0, elem);
-  int64_t t0 = C0 > 0 ? P->G / P->n[0] / C0 : 0;
-  int64_t t1 = 0;
-  if (P->d == 3) {
-    const int C1 = rad_tile_lines(P, 1, elem);
-    t1 = C1 > 0 ? P->G / P->n[1] / C1 : 0;
-  }
+  const int64_t t0 = pass_tiles(P, 0, elem).ntile;
+  const int64_t t1 = P->d == 3 ? pass_tiles(P, 1, elem).ntile : 0;
   return 3 * (t0 + t1);
 }
 
@@ -1186,8 +1232,9 @@ void resident_tiles(const pc_plan* P, size_t elem, const std::vector<int32_t>& n
                     const std::vector<int32_t>& ib_base, int m, std::vector<int32_t> out[6]) {
   for (int l = 0; l < 6; ++l) out[l].clear();
   const int64_t n0 = P->n[0], n1 = P->n[1], n2 = P->d == 3 ? P->n[2] : 1;
-  const int C0 = rad_tile_lines(P, 0, elem);
-  const int64_t t0 = n1 * n2 / C0;  // x-line tiles: line j + n1 k, tile line / C0
+  const PassTiles p0 = pass_tiles(P, 0, elem);
+  const int C0 = p0.C;
+  const int64_t t0 = p0.ntile;  // x-line tiles: line j + n1 k, tile line / C0
   std::vector<char> f0(t0, 0), i0(t0, 0);
   for (int32_t q : near_pts) f0[(q / n0) / C0] = 1;
   // lines read by the B+V gradient: the m x m (x m) block at each corner
@@ -1209,12 +1256,12 @@ void resident_tiles(const pc_plan* P, size_t elem, const std::vector<int32_t>& n
     // the x-inverse runs in place on whole tiles, whose lines may reach into
     // further planes (C0 > n1): those planes need their y-inverse first
     if (i0[t])
-      for (int64_t l = t * C0; l < (t + 1) * C0; ++l) ibplane[l / n1] = 1;
+      for (int64_t l = t * C0; l < std::min((t + 1) * C0, n1 * n2); ++l) ibplane[l / n1] = 1;
   }
   if (P->d == 3) {
     // y-line tiles: C1 adjacent x positions of one plane k, tile = k * tx + i / C1
-    const int C1 = rad_tile_lines(P, 1, elem);
-    const int64_t tx = n0 / C1;
+    const PassTiles p1 = pass_tiles(P, 1, elem);
+    const int64_t tx = p1.tx;
     std::vector<char> nearplane(n2, 0);
     for (int32_t q : near_pts) nearplane[q / (n0 * n1)] = 1;
     for (int64_t k = 0; k < n2; ++k)

@@ -83,11 +83,7 @@ __global__ void __launch_bounds__(TPB) k_div_all(const int32_t* __restrict__ gid
 #pragma unroll
     for (int a = 0; a < D; ++a) ref[a] = v[a * M + j0];
   }
-  // fully unrolled for a compile-time k (4% faster at 512^3 than four
-  // entries at a time: every index load is issued up front)
-#pragma unroll
-  for (int i = 0; i < (K > 0 ? K : PC_MAX_K_GRID); ++i) {
-    if (K == 0 && i >= k) break;
+  auto entry = [&](int i) {
     int j = ldnt(gidx + (int64_t)i * G + p);
 #pragma unroll
     for (int a = 0; a < D; ++a) {
@@ -96,6 +92,15 @@ __global__ void __launch_bounds__(TPB) k_div_all(const int32_t* __restrict__ gid
       if (LOCALREF) val -= ref[a];
       acc += c * val;
     }
+  };
+  if constexpr (D == 3 && K > 0) {
+    // fully unrolled in 3D (4% faster at 512^3 than four entries at a time:
+    // every index load is issued up front)
+#pragma unroll
+    for (int i = 0; i < K; ++i) entry(i);
+  } else {
+#pragma unroll 4
+    for (int i = 0; i < k; ++i) entry(i);
   }
   b[p] = acc;
 }

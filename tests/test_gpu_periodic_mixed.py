@@ -154,3 +154,10 @@ def test_periodic_any_even_sub_step(pc, name):
     assert res[pc.PC_F64][1] <= 1e-11 and res[pc.PC_F64][2] <= 1e-11
     assert res[pc.PC_MIXED][1] <= 1e-10 and res[pc.PC_MIXED][2] <= 1e-10
     assert res[pc.PC_F32][1] <= 5e-5 and res[pc.PC_F32][2] <= 5e-5
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_periodic_any_even_resident_transforms_bitwise(pc, name):
+    from tests.test_gpu_mixed_radix import resident_bitwise
+    c, bc, grid, st = case(name)
+    resident_bitwise(pc, c, bc)
