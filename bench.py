@@ -93,7 +93,7 @@ WORKLOADS = {
                 "desc": "2D 1024^2 pressure grid under the 2048^2 workload's {M} jittered "
                         "nodes (node spacing 1/2048), cylinder r=0.05 at (0.3,0.5), 16-NN WLS, "
                         "32-mode velocity, Neumann box, cold IB start"},
-    "3d512": {"d": 3, "N": 512, "modes": "f64,mixed,mixed3", "cpu_N": 64,
+    "3d512": {"d": 3, "N": 512, "modes": "f64,mixed,mixed3,f32", "cpu_N": 64, "f32_own_geom": True,
               "cpu_note": "the oracle's stencils of the 512^3 workload need ~230 GB of host "
                           "memory and hours of build; 64^3 (same obstacles, k, modes) runs "
                           "in seconds",
@@ -310,9 +310,13 @@ def run_workload(args, name, N, modes_arg):
     plan = pc.Plan(d, case["n"], case["h"], bc=case["bc"])
     x = torch.from_numpy(case["x"]).cuda()
     kind = torch.from_numpy(case["kind"]).cuda()
-    case["x"] = None
     modes = [m for m in (modes_arg or wl["modes"]).split(",") if m]
-    want_f32 = "f32" in modes
+    # float32 on a float32-only geometry of its own, after the float64 modes
+    # (at 512^3 the two stencil precisions do not fit beside each other)
+    f32_own = wl.get("f32_own_geom", False) and "f32" in modes
+    x_host = case["x"] if f32_own else None
+    case["x"] = None
+    want_f32 = "f32" in modes and not f32_own
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     # whole time steps only on a box without faces (the first fractional step
@@ -331,7 +335,9 @@ def run_workload(args, name, N, modes_arg):
 
     results = {}
     ref = None
-    for mname in modes:
+
+    def run_mode(geom, mname):
+        nonlocal ref
         mode = pc.MODES["mixed" if mname == "mixed3" else mname]
         sweeps = 3 if mname == "mixed3" else 2
         dtype = torch.float32 if mode == pc.PC_F32 else torch.float64
@@ -379,7 +385,10 @@ def run_workload(args, name, N, modes_arg):
             results[mname]["vs_f64"] = {"u": rel_l2(uo, ref[0]), "p": rel_l2(p, ref[1]),
                                         "fixed_it": ref[2]}
         del ws, u, uo, p
-    del ref
+
+    for mname in modes:
+        if not (f32_own and mname == "f32"):
+            run_mode(geom, mname)
 
     # ---- per-kernel HIP-event timings (same kernels, same launch shapes) ----------
     def time_launches(fn, reps):
@@ -470,6 +479,23 @@ def run_workload(args, name, N, modes_arg):
         del ts, u, u2, r, us
         torch.cuda.synchronize()
 
+    info = {"G": G, "M": M, "k": k, "n_ib": geom.n_ib, "n_near": geom.n_near,
+            "build_s": round(t_build, 3), "gen_s": round(t_gen, 3)}
+    if f32_own:
+        del geom
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        x = torch.from_numpy(x_host).cuda()
+        kind = torch.from_numpy(case["kind"]).cuda()
+        t0 = time.perf_counter()
+        geom = pc.wls_build(plan, x, kind, case["k"], case["k"], f32_only=True,
+                            delta=case.get("delta", 0.0))
+        torch.cuda.synchronize()
+        info["build_f32_only_s"] = round(time.perf_counter() - t0, 3)
+        del x, kind, x_host
+        run_mode(geom, "f32")
+    del ref
+
     if args.copy_probe:
         src = torch.empty(1 << 27, dtype=torch.float64, device="cuda")  # 1 GiB
         dst = torch.empty_like(src)
@@ -478,8 +504,6 @@ def run_workload(args, name, N, modes_arg):
         torch.cuda.synchronize()
         del src, dst
 
-    info = {"G": G, "M": M, "k": k, "n_ib": geom.n_ib, "n_near": geom.n_near,
-            "build_s": round(t_build, 3), "gen_s": round(t_gen, 3)}
     del geom, plan, u64, b64, phi64, gr64, case
     torch.cuda.synchronize()
     torch.cuda.empty_cache()

@@ -122,8 +122,14 @@ typedef struct pc_wls_opts {
   double support;    /* support radius in mean spacings (default 3)         */
   double delta;      /* mean point spacing (default: the grid spacing, or   */
                      /* the geometric mean of the per-axis spacings)        */
-  int32_t dtype_mask;/* PC_F64 and/or PC_F32 stencil copies to keep; bit    */
-                     /* (1 << mode) for each mode; 0 = float64 only         */
+  int32_t dtype_mask;/* stencil precisions to keep: bit (1 << PC_F64)       */
+                     /* float64 (PC_F64 and PC_MIXED), bit (1 << PC_F32)    */
+                     /* float32 (PC_F32); 0 = float64 only.  A float32-only */
+                     /* geometry (1 << PC_F32) holds half the coefficient   */
+                     /* bytes (the 512^3 case of Sec. 3 fits only so in     */
+                     /* float32) and refuses float64 calls and coefficient  */
+                     /* exports with PC_ERR_INVALID_ARG; other bits: the    */
+                     /* same error                                          */
   int32_t k_self;    /* > 0: also build node-to-node stencils of k_self     */
                      /* other nodes for the first fractional step           */
                      /* (pc_momentum_predict); 0 = none                    */
@@ -183,7 +189,7 @@ typedef struct pc_stats {
 
 /* ---- library ------------------------------------------------------------ */
 
-/* ABI version (major*100 + minor): 114. */
+/* ABI version (major*100 + minor): 115. */
 int pc_version(void);
 
 /* Copies the calling thread's last error message into buf (NUL-terminated,

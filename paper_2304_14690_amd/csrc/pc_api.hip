@@ -182,7 +182,7 @@ using namespace pc;
 
 extern "C" {
 
-int pc_version(void) { return 114; }
+int pc_version(void) { return 115; }
 
 int pc_set_allocator(pc_alloc_fn alloc, pc_free_fn free_fn, void* user) {
   if ((alloc == nullptr) != (free_fn == nullptr))

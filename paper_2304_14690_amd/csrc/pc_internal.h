@@ -95,10 +95,12 @@ struct pc_geom {
   int bn;
   int64_t n_ib, n_near, n_near_entries;
   int device;
-  bool has32;
+  bool has32;   // float32 stencil copies (PC_F32)
+  bool has64;   // float64 stencils (PC_F64, PC_MIXED); a float32-only
+                // geometry keeps null float64 coefficient arrays
   // grid-target stencils
   int32_t* gidx;   // [k_grid][G]
-  double* gcoef;   // [d][k_grid][G]
+  double* gcoef;   // [d][k_grid][G] or null (float32 only)
   float* gcoef32;  // [d][k_grid][G] or null
   // node stencils (block order)
   int32_t* nbase;   // [M] flat index of the block's low corner; ~corner

@@ -668,6 +668,8 @@ int check_dtype(const pc_geom* g, int dtype) {
     return fail(PC_ERR_INVALID_ARG, "dtype must be PC_F64 or PC_F32");
   if (dtype == PC_F32 && !g->has32)
     return fail(PC_ERR_INVALID_ARG, "geometry was built without float32 stencils");
+  if (dtype == PC_F64 && !g->has64)
+    return fail(PC_ERR_INVALID_ARG, "geometry holds float32 stencils only");
   return PC_OK;
 }
 
@@ -1420,6 +1422,8 @@ int pc_pressure_correct(const pc_geom* g, const pc_plan* P, int mode, const void
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(PC_ERR_INVALID_ARG, "dt must be positive");
   if (mode == PC_F32 && !g->has32)
     return fail(PC_ERR_INVALID_ARG, "geometry was built without float32 stencils");
+  if (mode != PC_F32 && !g->has64)
+    return fail(PC_ERR_INVALID_ARG, "geometry holds float32 stencils only");
   PC_TRY(check_fields(u, u_out, p));
   if (g_io && !aligned16(g_io)) return fail(PC_ERR_ALIGN, "g must be 16-byte aligned");
   if (u == u_out) return fail(PC_ERR_INVALID_ARG, "u_out must not alias u");
@@ -1452,6 +1456,8 @@ int pc_momentum_predict(const pc_geom* g, int dtype, const void* u, const void* 
   if (dtype != PC_F64 && dtype != PC_F32) return fail(PC_ERR_INVALID_ARG, "dtype");
   if (dtype == PC_F32 && !g->scoef32)
     return fail(PC_ERR_INVALID_ARG, "geometry was built without float32 stencils");
+  if (dtype == PC_F64 && !g->scoef)
+    return fail(PC_ERR_INVALID_ARG, "geometry holds float32 stencils only");
   if (!(dt > 0.0) || !std::isfinite(dt) || !(nu >= 0.0) || !std::isfinite(nu))
     return fail(PC_ERR_INVALID_ARG, "dt must be positive and nu non-negative");
   if (ustar == u) return fail(PC_ERR_INVALID_ARG, "ustar must not alias u");

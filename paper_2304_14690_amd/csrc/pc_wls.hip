@@ -603,7 +603,7 @@ __global__ void __launch_bounds__(64) k_grid_stencils(GridStencilArgs GA) {
 #pragma unroll
         for (int r = 0; r < MU; ++r) t += y[a][r] * q[r];
         double cval = w * t * iht;
-        GA.gcoef[((int64_t)a * k + pos) * G + p] = cval;
+        if (GA.gcoef) GA.gcoef[((int64_t)a * k + pos) * G + p] = cval;
         if (GA.gcoef32) GA.gcoef32[((int64_t)a * k + pos) * G + p] = (float)cval;
       }
     }
@@ -748,7 +748,7 @@ __global__ void __launch_bounds__(64) k_node_stencils(NodeStencilArgs A) {
       }
 #pragma unroll
       for (int a = 0; a < D; ++a) {
-        A.ncoef[((int64_t)a * bn + o) * ms + n] = cv[a];
+        if (A.ncoef) A.ncoef[((int64_t)a * bn + o) * ms + n] = cv[a];
         if (A.ncoef32) A.ncoef32[((int64_t)a * bn + o) * ms + n] = (float)cv[a];
       }
     }
@@ -869,7 +869,7 @@ __global__ void __launch_bounds__(64) k_self_stencils(SelfStencilArgs SA) {
         for (int r = 0; r < MU; ++r) t += y[a][r] * q[r];
         // first derivatives scale by 1/h_t, the Laplacian by 1/h_t^2
         const double cval = a < D ? w * t * iht : w * t * (iht * iht);
-        SA.scoef[((int64_t)a * k + pos) * ms + n] = cval;
+        if (SA.scoef) SA.scoef[((int64_t)a * k + pos) * ms + n] = cval;
         if (SA.scoef32) SA.scoef32[((int64_t)a * k + pos) * ms + n] = (float)cval;
       }
     }
@@ -1028,18 +1028,31 @@ struct Scratch {
 // Device bytes held by a geometry with these counts (the arrays of
 // pc_wls_build; the node permutation of PC_ORDER_CELL not included).
 int64_t geom_bytes_for(int d, int64_t G, int64_t M, int k_grid, int bn, int64_t n_ib,
-                       int64_t n_near, int near_w, bool want32, int k_self, int64_t n_v) {
+                       int64_t n_near, int near_w, bool want64, bool want32, int k_self,
+                       int64_t n_v) {
   const int64_t ms = (M + 63) / 64 * 64, ibs = (n_ib + 63) / 64 * 64;
   const int64_t ell = n_near ? (int64_t)near_w * ((n_near + 63) / 64 * 64) : 0;
-  int64_t bytes = (int64_t)k_grid * G * 4 + (int64_t)d * k_grid * G * 8 + M * 4 +
-                  (int64_t)d * bn * ms * 8 + n_ib * 4 + n_near * 4 + ell * (4 + 8 * d) +
-                  n_ib * 4 + ibs * 8 * (int64_t)d * bn;
-  if (want32)
-    bytes += (int64_t)d * k_grid * G * 4 + (int64_t)d * bn * ms * 4 + ell * 4 * d +
-             ibs * 4 * (int64_t)d * bn;
-  bytes += (int64_t)k_self * ms * (4 + 8 * (d + 1)) + n_v * 4;
-  if (want32) bytes += (int64_t)k_self * ms * 4 * (d + 1);
+  // indices, bases and lists (every geometry)
+  int64_t bytes = (int64_t)k_grid * G * 4 + M * 4 + n_ib * 4 + n_near * 4 + ell * 4 +
+                  n_ib * 4 + (int64_t)k_self * ms * 4 + n_v * 4;
+  // coefficients, per kept precision (s bytes a value)
+  for (int s : {8, 4}) {
+    if (!(s == 8 ? want64 : want32)) continue;
+    bytes += ((int64_t)d * k_grid * G + (int64_t)d * bn * ms + ell * d + ibs * (int64_t)d * bn +
+              (int64_t)k_self * ms * (d + 1)) * s;
+  }
   return bytes;
+}
+
+// The stencil copies a build keeps, from pc_wls_opts.dtype_mask: bit
+// (1 << PC_F64) float64, bit (1 << PC_F32) float32; 0 means float64 only.
+int dtype_keep(const pc_wls_opts* o, bool* want64, bool* want32) {
+  const int mask = o ? o->dtype_mask : 0;
+  if (mask & ~((1 << PC_F64) | (1 << PC_F32)))
+    return fail(PC_ERR_INVALID_ARG, "dtype_mask takes the bits (1 << PC_F64) and (1 << PC_F32)");
+  *want64 = mask == 0 || (mask & (1 << PC_F64));
+  *want32 = (mask & (1 << PC_F32)) != 0;
+  return PC_OK;
 }
 
 // Scratch a build holds at most at once besides the geometry's own arrays:
@@ -1128,7 +1141,8 @@ int build(const pc_plan* P, const double* xyz, const uint8_t* kind, int64_t M,
   double eps = o && o->eps != 0.0 ? o->eps : 6.3;
   double support = o && o->support != 0.0 ? o->support : 3.0;
   double delta = o ? o->delta : 0.0;
-  bool want32 = o && (o->dtype_mask & 1);
+  bool want64 = true, want32 = false;
+  PC_TRY(dtype_keep(o, &want64, &want32));
   const int k_self = o ? o->k_self : 0;
   if (k_self != 0 && (k_self < (d == 2 ? 5 : 9) || k_self > KMAX))
     return fail(PC_ERR_INVALID_ARG, "k_self must be 0 or in [5 (2D) / 9 (3D), PC_MAX_K_GRID]");
@@ -1172,6 +1186,7 @@ int build(const pc_plan* P, const double* xyz, const uint8_t* kind, int64_t M,
   g->m_node = m;
   g->bn = bn;
   g->has32 = want32;
+  g->has64 = want64;
   const GridDesc gd = grid_desc(P);
   g->per = gd.per;
   g->vertex = P->vertex;
@@ -1204,7 +1219,8 @@ int build(const pc_plan* P, const double* xyz, const uint8_t* kind, int64_t M,
 
   // grid-target stencils
   PC_TRY(dev_alloc((void**)&g->gidx, (size_t)k_grid * G * 4, "grid stencil indices"));
-  PC_TRY(dev_alloc((void**)&g->gcoef, (size_t)d * k_grid * G * 8, "grid stencil coefficients"));
+  if (want64)
+    PC_TRY(dev_alloc((void**)&g->gcoef, (size_t)d * k_grid * G * 8, "grid stencil coefficients"));
   if (want32)
     PC_TRY(dev_alloc((void**)&g->gcoef32, (size_t)d * k_grid * G * 4, "grid stencil f32"));
   const RingArgs ring{xyz, M, gd, start, sorted};
@@ -1218,7 +1234,8 @@ int build(const pc_plan* P, const double* xyz, const uint8_t* kind, int64_t M,
   // node-target stencils
   PC_TRY(dev_alloc((void**)&g->nbase, (size_t)M * 4, "node stencil bases"));
   g->ms = (M + 63) / 64 * 64;
-  PC_TRY(dev_alloc((void**)&g->ncoef, (size_t)d * bn * g->ms * 8, "node stencil coefficients"));
+  if (want64)
+    PC_TRY(dev_alloc((void**)&g->ncoef, (size_t)d * bn * g->ms * 8, "node stencil coefficients"));
   if (want32)
     PC_TRY(dev_alloc((void**)&g->ncoef32, (size_t)d * bn * g->ms * 4, "node stencil f32"));
   NodeStencilArgs na{xyz, M, gd, m, bn, k_node, eps, support * delta, g->nbase, g->ms, g->ncoef,
@@ -1233,7 +1250,9 @@ int build(const pc_plan* P, const double* xyz, const uint8_t* kind, int64_t M,
   g->k_self = k_self;
   if (k_self) {
     PC_TRY(dev_alloc((void**)&g->sidx, (size_t)k_self * g->ms * 4, "node-node indices"));
-    PC_TRY(dev_alloc((void**)&g->scoef, (size_t)(d + 1) * k_self * g->ms * 8, "node-node coefs"));
+    if (want64)
+      PC_TRY(dev_alloc((void**)&g->scoef, (size_t)(d + 1) * k_self * g->ms * 8,
+                       "node-node coefs"));
     if (want32)
       PC_TRY(dev_alloc((void**)&g->scoef32, (size_t)(d + 1) * k_self * g->ms * 4,
                        "node-node coefs f32"));
@@ -1305,7 +1324,7 @@ int build(const pc_plan* P, const double* xyz, const uint8_t* kind, int64_t M,
     const int64_t ell = (int64_t)near_w * g->nns;
     PC_TRY(dev_alloc((void**)&g->near, (size_t)g->n_near * 4, "near list"));
     PC_TRY(dev_alloc((void**)&g->nslot, (size_t)ell * 4, "near slots"));
-    PC_TRY(dev_alloc((void**)&g->ncoefib, (size_t)d * ell * 8, "near coefs"));
+    if (want64) PC_TRY(dev_alloc((void**)&g->ncoefib, (size_t)d * ell * 8, "near coefs"));
     if (want32) PC_TRY(dev_alloc((void**)&g->ncoefib32, (size_t)d * ell * 4, "near coefs"));
     PC_HIP_CHECK(hipMemcpy(g->near, hnear.data(), (size_t)g->n_near * 4, hipMemcpyHostToDevice));
     int32_t* slot;
@@ -1313,9 +1332,10 @@ int build(const pc_plan* P, const double* xyz, const uint8_t* kind, int64_t M,
     PC_HIP_CHECK(hipMemsetAsync(slot, 0xff, (size_t)M * 4, s));
     hipLaunchKernelGGL(k_slot_map, dim3(nblocks(g->n_ib, 256)), dim3(256), 0, s, g->ib, g->n_ib,
                        slot);
-    hipLaunchKernelGGL(k_near_fill<double>, dim3(nblocks(g->n_near, 256)), dim3(256), 0, s,
-                       g->near, g->n_near, g->nns, near_w, g->gidx, g->gcoef, G, k_grid, d,
-                       slot, g->nslot, g->ncoefib);
+    if (want64)
+      hipLaunchKernelGGL(k_near_fill<double>, dim3(nblocks(g->n_near, 256)), dim3(256), 0, s,
+                         g->near, g->n_near, g->nns, near_w, g->gidx, g->gcoef, G, k_grid, d,
+                         slot, g->nslot, g->ncoefib);
     if (want32)
       hipLaunchKernelGGL(k_near_fill<float>, dim3(nblocks(g->n_near, 256)), dim3(256), 0, s,
                          g->near, g->n_near, g->nns, near_w, g->gidx, g->gcoef32, G, k_grid,
@@ -1324,20 +1344,24 @@ int build(const pc_plan* P, const double* xyz, const uint8_t* kind, int64_t M,
   }
   if (g->n_ib) {
     PC_TRY(dev_alloc((void**)&g->ibbase, (size_t)g->n_ib * 4, "IB bases"));
-    PC_TRY(dev_alloc((void**)&g->ibcoef, (size_t)d * bn * g->ibs * 8, "IB coefs"));
-    hipLaunchKernelGGL(k_ib_gather<double>, dim3(nblocks(g->n_ib, 256)), dim3(256), 0, s, g->ib,
-                       g->n_ib, g->nbase, g->ncoef, g->ms, d * bn, g->ibs, g->ibbase, g->ibcoef);
+    // the first gather also writes the bases
+    if (want64) {
+      PC_TRY(dev_alloc((void**)&g->ibcoef, (size_t)d * bn * g->ibs * 8, "IB coefs"));
+      hipLaunchKernelGGL(k_ib_gather<double>, dim3(nblocks(g->n_ib, 256)), dim3(256), 0, s,
+                         g->ib, g->n_ib, g->nbase, g->ncoef, g->ms, d * bn, g->ibs, g->ibbase,
+                         g->ibcoef);
+    }
     if (want32) {
       PC_TRY(dev_alloc((void**)&g->ibcoef32, (size_t)d * bn * g->ibs * 4, "IB coefs"));
       hipLaunchKernelGGL(k_ib_gather<float>, dim3(nblocks(g->n_ib, 256)), dim3(256), 0, s, g->ib,
-                         g->n_ib, g->nbase, g->ncoef32, g->ms, d * bn, g->ibs, (int32_t*)nullptr,
-                         g->ibcoef32);
+                         g->n_ib, g->nbase, g->ncoef32, g->ms, d * bn, g->ibs,
+                         want64 ? (int32_t*)nullptr : g->ibbase, g->ibcoef32);
     }
     PC_HIP_CHECK(hipGetLastError());
   }
   PC_HIP_CHECK(hipStreamSynchronize(s));
-  g->bytes = geom_bytes_for(d, G, M, k_grid, bn, g->n_ib, g->n_near, g->near_w, want32, k_self,
-                            g->n_v);
+  g->bytes = geom_bytes_for(d, G, M, k_grid, bn, g->n_ib, g->n_near, g->near_w, want64, want32,
+                            k_self, g->n_v);
   return PC_OK;
 }
 
@@ -1405,6 +1429,8 @@ int pc_geom_info(const pc_geom* g, int64_t* c) {
 int pc_geom_export_self(const pc_geom* g, int32_t* idx, double* coef, void* stream) {
   if (!g) return fail(PC_ERR_INVALID_ARG, "pc_geom_export_self: null geometry");
   if (!g->k_self) return fail(PC_ERR_INVALID_ARG, "the geometry has no node-to-node stencils");
+  if (coef && !g->has64)
+    return fail(PC_ERR_INVALID_ARG, "the geometry holds float32 stencils only");
   hipStream_t s = as_stream(stream);
   if (idx)
     PC_HIP_CHECK(hipMemcpy2DAsync(idx, (size_t)g->M * 4, g->sidx, (size_t)g->ms * 4,
@@ -1420,6 +1446,8 @@ int pc_geom_export_self(const pc_geom* g, int32_t* idx, double* coef, void* stre
 int pc_geom_export(const pc_geom* g, int32_t* gidx, double* gcoef, int32_t* nbase,
                    double* ncoef, int32_t* ib, int32_t* near, void* stream) {
   if (!g) return fail(PC_ERR_INVALID_ARG, "pc_geom_export: null geometry");
+  if ((gcoef || ncoef) && !g->has64)
+    return fail(PC_ERR_INVALID_ARG, "the geometry holds float32 stencils only");
   hipStream_t s = as_stream(stream);
   auto cp = [&](void* dst, const void* src, size_t bytes) -> int {
     if (dst && src && bytes)
@@ -1451,7 +1479,8 @@ int pc_geom_footprint(const pc_plan* P, int64_t M, int64_t n_ib, int64_t n_near,
   const int d = P->d;
   const int k_grid = o && o->k_grid ? o->k_grid : 16;
   const int k_node = o && o->k_node ? o->k_node : (d == 2 ? 16 : 27);
-  const bool want32 = o && (o->dtype_mask & 1);
+  bool want64 = true, want32 = false;
+  PC_TRY(dtype_keep(o, &want64, &want32));
   const int k_self = o ? o->k_self : 0;
   const bool cell = o && o->order == PC_ORDER_CELL;
   int m = 1;
@@ -1462,8 +1491,8 @@ int pc_geom_footprint(const pc_plan* P, int64_t M, int64_t n_ib, int64_t n_near,
   // the near table is as wide as the most B+V entries of a near point: at
   // most k_grid, rounded up to the kernel's widths
   const int near_w = k_grid <= 8 ? 8 : (k_grid <= 16 ? 16 : (k_grid <= 27 && d == 3 ? 27 : 32));
-  const int64_t gb = geom_bytes_for(d, P->G, M, k_grid, bn, n_ib, n_near, near_w, want32, k_self,
-                                    n_ib) + (cell ? M * 4 : 0);
+  const int64_t gb = geom_bytes_for(d, P->G, M, k_grid, bn, n_ib, n_near, near_w, want64, want32,
+                                    k_self, n_ib) + (cell ? M * 4 : 0);
   if (geom_bytes) *geom_bytes = gb;
   if (build_peak_bytes) *build_peak_bytes = gb + build_scratch_bytes(d, P->G, M, cell);
   if (ws_bytes) {
@@ -1513,6 +1542,8 @@ int pc_geom_export_at(const pc_geom* g, const int64_t* grid_pts, int64_t n_grid,
   if (!g) return fail(PC_ERR_INVALID_ARG, "pc_geom_export_at: null geometry");
   if (n_grid < 0 || n_nodes < 0 || (n_grid && !grid_pts) || (n_nodes && !nodes))
     return fail(PC_ERR_INVALID_ARG, "pc_geom_export_at: bad target list");
+  if ((grid_coef || node_coef) && !g->has64)
+    return fail(PC_ERR_INVALID_ARG, "the geometry holds float32 stencils only");
   const int64_t n = std::max(n_grid, n_nodes);
   if (n == 0) return PC_OK;
   hipStream_t s = as_stream(stream);

@@ -73,6 +73,14 @@ PC_ORDER_CALLER, PC_ORDER_CELL = 0, 1
 ORDERS = {"caller": PC_ORDER_CALLER, "cell": PC_ORDER_CELL}
 
 
+def _dtype_mask(want_f32: bool, f32_only: bool) -> int:
+    """pc_wls_opts.dtype_mask: float64 stencils unless f32_only, float32
+    copies if want_f32 or f32_only."""
+    if f32_only:
+        return 1 << PC_F32
+    return (1 << PC_F64) | ((1 << PC_F32) if want_f32 else 0)
+
+
 PC_IB_FULL_TRANSFORMS = 1
 
 
@@ -285,9 +293,9 @@ def poisson_fft_solve(plan: Plan, b: torch.Tensor, phi: torch.Tensor, mode: int 
 def wls_build(plan: Plan, xyz: torch.Tensor, kind: torch.Tensor, k_grid: int = 0,
               k_node: int = 0, eps: float = 0.0, support: float = 0.0, delta: float = 0.0,
               want_f32: bool = False, stream=None, k_self: int = 0,
-              order: str = "caller") -> Geometry:
+              order: str = "caller", f32_only: bool = False) -> Geometry:
     assert xyz.dtype == torch.float64 and kind.dtype == torch.uint8
-    opts = WlsOpts(k_grid, k_node, eps, support, delta, 1 if want_f32 else 0, k_self,
+    opts = WlsOpts(k_grid, k_node, eps, support, delta, _dtype_mask(want_f32, f32_only), k_self,
                    ORDERS[order] if isinstance(order, str) else int(order))
     out = ctypes.c_void_p()
     _check(_lib.pc_wls_build(plan.h_, _ptr(xyz), _ptr(kind), kind.numel(), ctypes.byref(opts),
@@ -304,10 +312,10 @@ def geom_export(geom: Geometry, grid_idx=None, grid_coef=None, node_base=None,
 
 def geom_footprint(plan: Plan, M: int, n_ib: int, n_near: int, k_grid: int = 0,
                    k_node: int = 0, want_f32: bool = False, k_self: int = 0,
-                   order: str = "caller"):
+                   order: str = "caller", f32_only: bool = False):
     """(geometry bytes, build peak bytes, {mode: workspace bytes}) before a
     build (pc_geom_footprint); n_near is a bound on the near-IB points."""
-    opts = WlsOpts(k_grid, k_node, 0.0, 0.0, 0.0, 1 if want_f32 else 0, k_self,
+    opts = WlsOpts(k_grid, k_node, 0.0, 0.0, 0.0, _dtype_mask(want_f32, f32_only), k_self,
                    ORDERS[order] if isinstance(order, str) else int(order))
     gb, pk = ctypes.c_int64(), ctypes.c_int64()
     ws = (ctypes.c_int64 * 3)()

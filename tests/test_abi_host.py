@@ -35,7 +35,7 @@ def test_library_exports_every_declared_symbol():
 def test_host_side_validation():
     from paper_2304_14690_amd import pcorr
     lib = pcorr.lib()
-    assert lib.pc_version() == 114
+    assert lib.pc_version() == 115
     out = ctypes.c_void_p()
     n = (ctypes.c_int32 * 3)(64, 64, 1)
     h = (ctypes.c_double * 3)(1 / 64, 1 / 64, 1.0)

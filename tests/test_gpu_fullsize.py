@@ -223,3 +223,25 @@ def test_full_size_sampled_parity(name):
                                          sweeps=sweeps)
             assert stm["n_it"] == n_it and stm["converged"] == 1
         del wsm, um, uom, pm
+
+    if big:
+        # float32 on a float32-only geometry: at 512^3 the two stencil
+        # precisions do not fit on the device beside each other
+        del ws, geom
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        xt = torch.from_numpy(np.ascontiguousarray(xs.T)).cuda()
+        geom32 = pc.wls_build(plan, xt, torch.from_numpy(kind).cuda(), k, k, f32_only=True)
+        del xt
+        assert geom32.n_ib == nib and geom32.n_near == nnear
+        u32 = u.to(torch.float32)
+        uo32 = torch.empty_like(u32)
+        p32 = torch.empty(G, dtype=torch.float32, device="cuda")
+        _, st32 = pc.pressure_correct(geom32, plan, pc.PC_F32, u32, 1.0, uo32, p32,
+                                      fixed_it=n_it)
+        torch.cuda.synchronize()
+        eu, ep = rel_l2(uo32.cpu().numpy(), uoh), rel_l2(p32.cpu().numpy(), ph / SIGMA)
+        print(f"{name}: float32-only geometry, f32 vs f64: u {eu:.2e} p {ep:.2e}")
+        assert eu <= 5e-5 and ep <= 5e-5
+        with pytest.raises(pc.PcError):
+            pc.pressure_correct(geom32, plan, pc.PC_F64, u, 1.0, uo, p)
