@@ -223,8 +223,10 @@ int grid_mean_f64(const pc_plan* P, const double* x, double* partial, int nblk, 
 int remove_mean_f64(const pc_plan* P, double* phi, pc_workspace* ws, hipStream_t s,
                     const int32_t* skip = nullptr);
 int ensure_plan_ws(const pc_plan* P, pc_workspace** ws);
-// Complex values per thread of the register transform (radix-8 plan).
-constexpr int RAD_VALUES = 8;
+// Complex values per thread of the register transform of an axis of N
+// points: 8 (radix-8 plan, N a power of two from 32 to 4096), 10 (radix-10
+// plan, N = 200, 400, 1000 or 2000), 0 (the generic kernel).
+int rad_values(int N);
 // Lines per workgroup tile of the register transform along `axis` for
 // elements of `elem` bytes (0 when the axis uses the generic kernel).
 int rad_tile_lines(const pc_plan* P, int axis, size_t elem);

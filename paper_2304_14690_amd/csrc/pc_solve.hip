@@ -45,43 +45,6 @@ __device__ __forceinline__ int div_small(int n, int d, float rinv) {
   return q;
 }
 
-// DFT of length 3 and 5 (forward exp(-2 pi i / r), inverse the conjugate).
-template <typename TC, bool INV>
-__device__ __forceinline__ void dft3(cplx<TC>* v) {
-  constexpr double S3 = 0.86602540378443864676;  // sin(2 pi / 3)
-  const cplx<TC> t = cadd(v[1], v[2]);
-  const cplx<TC> m = {v[0].re - TC(0.5) * t.re, v[0].im - TC(0.5) * t.im};
-  const cplx<TC> d = {TC(S3) * (v[1].re - v[2].re), TC(S3) * (v[1].im - v[2].im)};
-  const cplx<TC> id = INV ? cplx<TC>{-d.im, d.re} : cplx<TC>{d.im, -d.re};  // -+ i d
-  v[0] = cadd(v[0], t);
-  v[1] = cadd(m, id);
-  v[2] = csub(m, id);
-}
-
-template <typename TC, bool INV>
-__device__ __forceinline__ void dft5(cplx<TC>* v) {
-  constexpr double C1 = 0.30901699437494742410;   // cos(2 pi / 5)
-  constexpr double C2 = -0.80901699437494742410;  // cos(4 pi / 5)
-  constexpr double S1 = 0.95105651629515357212;   // sin(2 pi / 5)
-  constexpr double S2 = 0.58778525229247312917;   // sin(4 pi / 5)
-  const cplx<TC> t1 = cadd(v[1], v[4]), t2 = cadd(v[2], v[3]);
-  const cplx<TC> t3 = csub(v[1], v[4]), t4 = csub(v[2], v[3]);
-  const cplx<TC> a1 = {v[0].re + TC(C1) * t1.re + TC(C2) * t2.re,
-                       v[0].im + TC(C1) * t1.im + TC(C2) * t2.im};
-  const cplx<TC> a2 = {v[0].re + TC(C2) * t1.re + TC(C1) * t2.re,
-                       v[0].im + TC(C2) * t1.im + TC(C1) * t2.im};
-  const cplx<TC> b1 = {TC(S1) * t3.re + TC(S2) * t4.re, TC(S1) * t3.im + TC(S2) * t4.im};
-  const cplx<TC> b2 = {TC(S2) * t3.re - TC(S1) * t4.re, TC(S2) * t3.im - TC(S1) * t4.im};
-  // -+ i b
-  const cplx<TC> ib1 = INV ? cplx<TC>{-b1.im, b1.re} : cplx<TC>{b1.im, -b1.re};
-  const cplx<TC> ib2 = INV ? cplx<TC>{-b2.im, b2.re} : cplx<TC>{b2.im, -b2.re};
-  v[0] = cadd(v[0], cadd(t1, t2));
-  v[1] = cadd(a1, ib1);
-  v[4] = csub(a1, ib1);
-  v[2] = cadd(a2, ib2);
-  v[3] = csub(a2, ib2);
-}
-
 // One Stockham butterfly of compile-time radix R: inputs x[g + nb s],
 // twiddles w^(k s) = twH[tstep k s] (w = exp(-+2 pi i / (L R))), a length-R
 // DFT, outputs y[s' L] (y already offset by (g - k) R + k).
@@ -810,25 +773,44 @@ int generic_radices(int H, int* rad) {
 
 bool pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
 
+int rad_values(int N) {
+  if (N >= 32 && N <= 4096 && pow2(N)) return 8;
+  if (N == 200 || N == 400 || N == 1000 || N == 2000) return 10;
+  return 0;
+}
+
+namespace {
+// Largest power of two not above v (v >= 1).
+int floor_pow2(int v) {
+  int c = 1;
+  while (2 * c <= v) c <<= 1;
+  return c;
+}
+}  // namespace
+
 // Lines per workgroup tile of the register transform along `axis` (0 when
 // the axis uses the generic kernel: N < 32 or not a power of two).
 int rad_tile_lines(const pc_plan* P, int axis, size_t elem) {
   const int N = P->n[axis];
-  if (N < 32 || !pow2(N)) return 0;
-  const int H = N / 2, T = H / RAD_VALUES, LS = H + H / 16 + 1;
+  const int RT = rad_values(N);
+  if (!RT) return 0;
+  const int H = N / 2, T = H / RT, LS = H + H / 16 + 1;
   const int64_t lines = P->G / N;
   int C;
-  // C divides the row count (rows) or the x extent (strided lines), which
-  // need not be powers of two when another axis is not
+  // C (a power of two) divides the row count (rows) or the x extent
+  // (strided lines), which need not be powers of two when another axis is
+  // not
   if (axis == 0) {
-    C = std::max(1, ROW_THREADS / T);
+    C = floor_pow2(std::max(1, ROW_THREADS / T));
     while (C > 1 && ((int64_t)C > lines || lines % C)) C >>= 1;
   } else {
     C = (int)(128 / elem);
     while (C > 1 && (C * T > COL_MAX_THREADS || C > P->n[0] || P->n[0] % C)) C >>= 1;
   }
   while (C > 1 && (size_t)C * LS * 2 * elem > (size_t)lds_limit()) C >>= 1;
-  return C;
+  // small grids (the 400 x 400 grid of Sec. 3): fewer lines per group, so
+  // that every compute unit gets work
+  return fill_device(C, lines / C);
 }
 
 // Lines per workgroup tile of the generic kernel for a Neumann axis (the
@@ -865,7 +847,7 @@ PassTiles pass_tiles(const pc_plan* P, int axis, size_t elem) {
   PassTiles pt{};
   const int N = P->n[axis];
   const int64_t lines = P->G / N;
-  const bool reg = N >= 32 && pow2(N);
+  const bool reg = rad_values(N) != 0;
   const bool masked = !reg && P->bc[axis] == PC_BC_PERIODIC;
   pt.C = reg ? rad_tile_lines(P, axis, elem) : generic_tile_lines(P, axis, elem, nullptr, nullptr);
   if (axis == 0) {
@@ -969,9 +951,8 @@ int launch_pass(const pc_plan* P, int axis, const TI* in, TO* out, const AxisTab
     PC_HIP_CHECK(hipGetLastError());
     return PC_OK;
   }
-  if (A.N >= 32 && pow2(A.N)) {
+  if (const int RT = rad_values(A.N)) {
     // register kernel: T = H/RT threads per line, C lines per group
-    constexpr int RT = RAD_VALUES;
     const int T = H / RT;
     const int LS = H + H / 16 + 1;
     const int C = rad_tile_lines(P, axis, sizeof(TC));
@@ -991,7 +972,7 @@ int launch_pass(const pc_plan* P, int axis, const TI* in, TO* out, const AxisTab
       ntile = ntiles;
     }
     size_t lds = (size_t)C * LS * 2 * sizeof(TC);
-    const int key = logH * 32 + RT;
+    const int key = (RT == 8 ? logH : H) * 32 + RT;
     if (P->bc[axis] == PC_BC_PERIODIC)
       return rad_launch<TC, TI, TO, OP, LD, ST, true>(A, key, dim3(ntile), dim3(C * T), lds, s);
     return rad_launch<TC, TI, TO, OP, LD, ST, false>(A, key, dim3(ntile), dim3(C * T), lds, s);

@@ -198,8 +198,79 @@ __device__ __forceinline__ void dft8(cplx<TC>* a) {  // a[0..7], natural order i
   for (int i = 0; i < 8; ++i) a[i] = o[i];
 }
 
+// DFT of length 3 and 5 (forward exp(-2 pi i / r), inverse the conjugate).
+template <typename TC, bool INV>
+__device__ __forceinline__ void dft3(cplx<TC>* v) {
+  constexpr double S3 = 0.86602540378443864676;  // sin(2 pi / 3)
+  const cplx<TC> t = cadd(v[1], v[2]);
+  const cplx<TC> m = {v[0].re - TC(0.5) * t.re, v[0].im - TC(0.5) * t.im};
+  const cplx<TC> d = {TC(S3) * (v[1].re - v[2].re), TC(S3) * (v[1].im - v[2].im)};
+  const cplx<TC> id = INV ? cplx<TC>{-d.im, d.re} : cplx<TC>{d.im, -d.re};  // -+ i d
+  v[0] = cadd(v[0], t);
+  v[1] = cadd(m, id);
+  v[2] = csub(m, id);
+}
+
+template <typename TC, bool INV>
+__device__ __forceinline__ void dft5(cplx<TC>* v) {
+  constexpr double C1 = 0.30901699437494742410;   // cos(2 pi / 5)
+  constexpr double C2 = -0.80901699437494742410;  // cos(4 pi / 5)
+  constexpr double S1 = 0.95105651629515357212;   // sin(2 pi / 5)
+  constexpr double S2 = 0.58778525229247312917;   // sin(4 pi / 5)
+  const cplx<TC> t1 = cadd(v[1], v[4]), t2 = cadd(v[2], v[3]);
+  const cplx<TC> t3 = csub(v[1], v[4]), t4 = csub(v[2], v[3]);
+  const cplx<TC> a1 = {v[0].re + TC(C1) * t1.re + TC(C2) * t2.re,
+                       v[0].im + TC(C1) * t1.im + TC(C2) * t2.im};
+  const cplx<TC> a2 = {v[0].re + TC(C2) * t1.re + TC(C1) * t2.re,
+                       v[0].im + TC(C2) * t1.im + TC(C1) * t2.im};
+  const cplx<TC> b1 = {TC(S1) * t3.re + TC(S2) * t4.re, TC(S1) * t3.im + TC(S2) * t4.im};
+  const cplx<TC> b2 = {TC(S2) * t3.re - TC(S1) * t4.re, TC(S2) * t3.im - TC(S1) * t4.im};
+  // -+ i b
+  const cplx<TC> ib1 = INV ? cplx<TC>{-b1.im, b1.re} : cplx<TC>{b1.im, -b1.re};
+  const cplx<TC> ib2 = INV ? cplx<TC>{-b2.im, b2.re} : cplx<TC>{b2.im, -b2.re};
+  v[0] = cadd(v[0], cadd(t1, t2));
+  v[1] = cadd(a1, ib1);
+  v[4] = csub(a1, ib1);
+  v[2] = cadd(a2, ib2);
+  v[3] = csub(a2, ib2);
+}
+
+// DFT of length 10 (natural order in and out) as two of length 5: E and O
+// over the even and odd inputs, X[k] = E[k] + W10^k O[k] and
+// X[k+5] = E[k] - W10^k O[k], W10 = exp(-+2 pi i / 10).
+template <typename TC, bool INV>
+__device__ __forceinline__ void dft10(cplx<TC>* a) {
+  constexpr double C1 = 0.80901699437494742410;  // cos(pi/5)
+  constexpr double S1 = 0.58778525229247312917;  // sin(pi/5)
+  constexpr double C2 = 0.30901699437494742410;  // cos(2 pi/5)
+  constexpr double S2 = 0.95105651629515357212;  // sin(2 pi/5)
+  cplx<TC> e[5], o[5];
+#pragma unroll
+  for (int i = 0; i < 5; ++i) {
+    e[i] = a[2 * i];
+    o[i] = a[2 * i + 1];
+  }
+  dft5<TC, INV>(e);
+  dft5<TC, INV>(o);
+  // W10^k = c_k -+ i s_k for k = 1..4 (s_k >= 0)
+  const TC sg = INV ? TC(1) : TC(-1);
+  const cplx<TC> w1 = {(TC)C1, sg * (TC)S1}, w2 = {(TC)C2, sg * (TC)S2},
+                 w3 = {(TC)-C2, sg * (TC)S2}, w4 = {(TC)-C1, sg * (TC)S1};
+  o[1] = cmul(o[1], w1);
+  o[2] = cmul(o[2], w2);
+  o[3] = cmul(o[3], w3);
+  o[4] = cmul(o[4], w4);
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    a[k] = cadd(e[k], o[k]);
+    a[k + 5] = csub(e[k], o[k]);
+  }
+}
+
 template <typename TC, bool INV, int R>
 __device__ __forceinline__ void dftR(cplx<TC>* a) {
+  if (R == 10) dft10<TC, INV>(a);
+  if (R == 5) dft5<TC, INV>(a);
   if (R == 8) dft8<TC, INV>(a);
   if (R == 4) dft4<TC, INV>(a[0], a[1], a[2], a[3]);
   if (R == 2) {
@@ -235,13 +306,14 @@ __device__ __forceinline__ int lpad_tq(int t, int lt, int q) {
 // of r L.
 __device__ __forceinline__ int lpad_scatter(int lb, int rl) { return lb + rl + (rl >> 4); }
 
-// Synchronisation of the threads of one line.  A line of T <= 64 threads
+// Synchronisation of the threads of one line.  When T divides 64 a line
 // lies inside one wavefront, whose LDS accesses execute in issue order, so
-// wavefront-scope fences (compiler ordering only) are enough; longer lines
-// span several wavefronts and need the workgroup barrier.
+// wavefront-scope fences (compiler ordering only) are enough; longer lines,
+// and lines of a T that does not divide 64 (the radix-10 plan), span
+// several wavefronts and need the workgroup barrier.
 template <int T>
 __device__ __forceinline__ void line_sync() {
-  if (T <= 64) {
+  if (T <= 64 && 64 % T == 0) {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -350,11 +422,107 @@ __device__ __forceinline__ void r8_fft(cplx<TC>* a, int t, const R8Tw<TC>& tw,
   if (RR == 2) rad_final<TC, INV, 8, 2>(a, T, tw.fin, twH);
 }
 
-template <typename TC, bool INV, int LOGH, int RT>
+// ---- radix-10 plan (10 values per thread, T = H/10 threads per line) ----------
+// For H = 10^s f with f = 1, 2 or 5 (the n/2 = 200 and 1000 of the 400 and
+// 2000 point grids of Sec. 3): s radix-10 Stockham stages (L = 1, 10, 100),
+// then, for f > 1, a final in-place stage of radix f.  The twiddle state
+// (R8Tw) holds the stage bases for L = 10 (s1) and L = 100 (s2) and twH[t]
+// (fin).  LDS indices carry one pad slot per 16 complex values (lpad).
+
+template <int H>
+struct R10Plan {
+  static constexpr int S = H % 1000 == 0 ? 3 : (H % 100 == 0 ? 2 : 1);  // radix-10 stages
+  static constexpr int F = H / (S == 3 ? 1000 : (S == 2 ? 100 : 10));    // final radix
+  static_assert(F == 1 || F == 2 || F == 5, "H = 10^s f with f in {1, 2, 5}");
+};
+
+// v[r] *= w^r, r = 1..9, the powers by products of at most four factors.
+template <typename TC, bool INV>
+__device__ __forceinline__ void twiddle_r10(cplx<TC>* v, cplx<TC> w) {
+  cplx<TC> p[10];
+  p[1] = w;
+  p[2] = cmul(w, w);
+  p[3] = cmul(p[2], w);
+  p[4] = cmul(p[2], p[2]);
+  p[5] = cmul(p[4], w);
+  p[6] = cmul(p[3], p[3]);
+  p[7] = cmul(p[6], w);
+  p[8] = cmul(p[4], p[4]);
+  p[9] = cmul(p[8], w);
+#pragma unroll
+  for (int r = 1; r < 10; ++r) v[r] = INV ? cmulc(v[r], p[r]) : cmul(v[r], p[r]);
+}
+
+// One radix-10 Stockham stage of sub-transform length L: butterfly j = t,
+// k = t mod L, inputs the thread's own values (j + T r), twiddles w^(k r),
+// a 10-point DFT, outputs to (j - k) 10 + k + r L through LDS and back as
+// the next stage's inputs t + T q (in place for the last stage).
+template <typename TC, bool INV, bool LAST, int T, int L>
+__device__ __forceinline__ void r10_stage(cplx<TC>* a, int t, cplx<TC> w, cplx<TC>* z) {
+  cplx<TC> v[10];
+#pragma unroll
+  for (int r = 0; r < 10; ++r) v[r] = a[r];
+  if (L > 1) twiddle_r10<TC, INV>(v, w);
+  dft10<TC, INV>(v);
+  if (LAST) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) a[r] = v[r];
+  } else {
+    const int k = t % L;
+    const int b = (t - k) * 10 + k;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) z[lpad(b + r * L)] = v[r];
+    line_sync<T>();
+#pragma unroll
+    for (int q = 0; q < 10; ++q) a[q] = z[lpad(t + T * q)];
+    line_sync<T>();
+  }
+}
+
+template <typename TC, bool INV, int H>
+__device__ __forceinline__ void r10_fft(cplx<TC>* a, int t, const R8Tw<TC>& tw,
+                                        const cplx<TC>* __restrict__ twH, cplx<TC>* z) {
+  constexpr int T = H / 10;
+  constexpr int S = R10Plan<H>::S, F = R10Plan<H>::F;
+  r10_stage<TC, INV, (S == 1 && F == 1), T, 1>(a, t, tw.s1, z);
+  if constexpr (S >= 2) r10_stage<TC, INV, (S == 2 && F == 1), T, 10>(a, t, tw.s1, z);
+  if constexpr (S >= 3) r10_stage<TC, INV, (F == 1), T, 100>(a, t, tw.s2, z);
+  if constexpr (F == 2) rad_final<TC, INV, 10, 2>(a, T, tw.fin, twH);
+  if constexpr (F == 5) rad_final<TC, INV, 10, 5>(a, T, tw.fin, twH);
+}
+
+// The register kernels' half-length H from the length code HL of their
+// template: log2(H) for the radix-8 plan, H itself for the radix-10 plan.
+template <int HL, int RT>
+struct RadLen {
+  static constexpr int H = RT == 8 ? (1 << HL) : HL;
+};
+
+// Twiddle state of either plan for thread t of a line.
+template <typename TC, int H, int RT>
+__device__ __forceinline__ R8Tw<TC> rad_twiddles(const cplx<TC>* __restrict__ twH, int t) {
+  R8Tw<TC> tw;
+  if constexpr (RT == 8) {
+    if (H >= 64) tw.s1 = twH[(H / 64) * (t & 7)];
+    if (H >= 512) tw.s2 = twH[(H / 512) * (t & 63)];
+    if (__builtin_ctz(H) % 3) tw.fin = twH[t];
+  } else {
+    constexpr int S = R10Plan<H>::S, F = R10Plan<H>::F;
+    if (S >= 2) tw.s1 = twH[(H / 100) * (t % 10)];
+    if (S >= 3) tw.s2 = twH[(H / 1000) * (t % 100)];
+    if (F > 1) tw.fin = twH[t];
+  }
+  return tw;
+}
+
+template <typename TC, bool INV, int H, int RT>
 __device__ __forceinline__ void rad_fft(cplx<TC>* a, int t, const R8Tw<TC>& tw8,
                                         const cplx<TC>* __restrict__ twH, cplx<TC>* z) {
-  static_assert(RT == 8, "the register kernel runs the radix-8 plan");
-  r8_fft<TC, INV, LOGH>(a, t, tw8, twH, z);
+  static_assert(RT == 8 || RT == 10, "the register kernels run radix-8 or radix-10 plans");
+  if constexpr (RT == 8)
+    r8_fft<TC, INV, __builtin_ctz(H)>(a, t, tw8, twH, z);
+  else
+    r10_fft<TC, INV, H>(a, t, tw8, twH, z);
 }
 
 // exp(-i pi (H-k) / (2N)) = exp(-i pi / 4) conj(exp(-i pi k / (2N))), N = 2H
@@ -435,8 +603,8 @@ __device__ __forceinline__ int xpad(int r) { return r + 2 * (r >> 5); }
 
 // One pass of the line transforms over a tile of C lines: forward (OP_FWD),
 // inverse (OP_INV), or forward, division by the eigenvalues and inverse
-// along the last axis (OP_FDI).  RT = 8 complex values per thread,
-// T = H / RT threads per line.
+// along the last axis (OP_FDI).  RT = 8 (radix-8 plan) or 10 (radix-10
+// plan) complex values per thread, T = H / RT threads per line.
 //   PER = false: DCT-II forward, DCT-III / (2N) inverse (Neumann axis).
 //   PER = true:  packed real DFT of a periodic axis, in the same slots:
 //                slot k = Re X_k (k < H), slot N-k = Im X_k (0 < k < H),
@@ -446,16 +614,18 @@ __device__ __forceinline__ int xpad(int r) { return r + 2 * (r >> 5); }
 // combine freely.
 // The kernel asks for four wavefronts per SIMD (at most 128 VGPRs), which
 // the float64 fused pass would otherwise exceed by a few registers.
-template <typename TC, typename TI, typename TO, int OP, int LD, int ST, int LOGH, int RT,
+template <typename TC, typename TI, typename TO, int OP, int LD, int ST, int HL, int RT,
           bool PER>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4)))
 dct_rad(LineArgs<TC> A) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   if (A.skip && *A.skip) return;
-  constexpr int H = 1 << LOGH;
+  constexpr int H = RadLen<HL, RT>::H;
   constexpr int N = 2 * H;
   constexpr int T = H / RT;
   constexpr int NV = 2 * RT;  // reals per thread
+  constexpr int RB = NV % 8 == 0 ? 8 : 10;  // points per batch of the residual loader
+  static_assert(NV % RB == 0, "residual batches cover the thread's points");
   const int LS = H + H / 16 + 1;  // complex slots per line in LDS
   const int C = A.C;
   const bool rows = A.axis == 0;
@@ -482,10 +652,7 @@ dct_rad(LineArgs<TC> A) {
   const AxisTables<TC>& Tb = A.tab;
 
   // twiddle state (issued first; in flight with the data loads)
-  R8Tw<TC> tw8;
-  if (LOGH >= 6) tw8.s1 = Tb.twH[(H / 64) * (t & 7)];
-  if (LOGH >= 9) tw8.s2 = Tb.twH[(H / 512) * (t & 63)];
-  if (LOGH % 3) tw8.fin = Tb.twH[t];
+  R8Tw<TC> tw8 = rad_twiddles<TC, H, RT>(Tb.twH, t);
   const cplx<TC> tNb = Tb.tN[t];
   const cplx<TC> t4b = Tb.t4N[t];
 
@@ -517,13 +684,13 @@ dct_rad(LineArgs<TC> A) {
     const int64_t dp = (int64_t)T * st;
     TC* zl = zr0 + 2 * tcc * LS;
     if (LD == LD_RESID) {
-      // the residual reads 5-7 values per point: batches of 8 points, the
-      // batch loop kept rolled so that the kernel stays small
+      // the residual reads 5-7 values per point: batches of RB points (RB
+      // divides NV), the batch loop kept rolled so that the kernel stays small
 #pragma unroll 1
-      for (int r0 = 0; r0 < NV; r0 += 8) {
-        TC v[8];
+      for (int r0 = 0; r0 < NV; r0 += RB) {
+        TC v[RB];
 #pragma unroll
-        for (int r = 0; r < 8; ++r) {
+        for (int r = 0; r < RB; ++r) {
           // strided line along axis 1 (y) or 2 (z) at x position ti_x, the
           // other coordinate to
           const int pn = tn0 + (r0 + r) * T;
@@ -534,7 +701,7 @@ dct_rad(LineArgs<TC> A) {
           v[r] = (TC)x;
         }
 #pragma unroll
-        for (int r = 0; r < 8; ++r) zl[pos(tn0 + (r0 + r) * T)] = v[r];
+        for (int r = 0; r < RB; ++r) zl[pos(tn0 + (r0 + r) * T)] = v[r];
       }
     } else {
       TC v[NV];
@@ -556,15 +723,15 @@ dct_rad(LineArgs<TC> A) {
   cplx<TC> a[RT];
   if (OP != OP_INV) {
     if (rows && LD == LD_RESID) {
-      // the residual reads 5-7 values per point: batches of 8 points, the
-      // batch loop kept rolled so that the kernel stays small
+      // the residual reads 5-7 values per point: batches of RB points (RB
+      // divides NV), the batch loop kept rolled so that the kernel stays small
 #pragma unroll 1
-      for (int i0 = 0; i0 < NV; i0 += 8) {
-        TC xv[8];
+      for (int i0 = 0; i0 < NV; i0 += RB) {
+        TC xv[RB];
 #pragma unroll
-        for (int i = 0; i < 8; ++i) xv[i] = load(t + T * (i0 + i));
+        for (int i = 0; i < RB; ++i) xv[i] = load(t + T * (i0 + i));
 #pragma unroll
-        for (int i = 0; i < 8; ++i) zr[vpad(line_pos<PER>(t + T * (i0 + i), N))] = xv[i];
+        for (int i = 0; i < RB; ++i) zr[vpad(line_pos<PER>(t + T * (i0 + i), N))] = xv[i];
       }
       line_sync<T>();
     } else if (rows) {
@@ -581,7 +748,7 @@ dct_rad(LineArgs<TC> A) {
 #pragma unroll
     for (int q = 0; q < RT; ++q) a[q] = z[lpad_tq<T>(t, lpad(t), q)];
     line_sync<T>();
-    rad_fft<TC, false, LOGH, RT>(a, t, tw8, Tb.twH, z);
+    rad_fft<TC, false, H, RT>(a, t, tw8, Tb.twH, z);
     // partner exchange: Z[H-k] next to Z[k]
 #pragma unroll
     for (int q = 0; q < RT; ++q) z[lpad_tq<T>(t, lpad(t), q)] = a[q];
@@ -597,7 +764,7 @@ dct_rad(LineArgs<TC> A) {
     for (int q = 0; q < RT; ++q) {
       const int k = t + T * q;
       cplx<TC> Zk = a[q];
-      cplx<TC> Zc = conj_(z[lpad((H - k) & (H - 1))]);
+      cplx<TC> Zc = conj_(z[lpad(RT == 8 ? (H - k) & (H - 1) : (k ? H - k : 0))]);
       // twice the even/odd split E, D (and O = -i D): the cosine transform's
       // factor 2 absorbs the halving (scaling by powers of two is exact; the
       // results differ from halving first only where the compiler fuses
@@ -771,7 +938,7 @@ dct_rad(LineArgs<TC> A) {
   asm volatile("" : "+v"(zoff));
   // from the LDS base itself, so that the accesses stay LDS instructions
   cplx<TC>* zi = reinterpret_cast<cplx<TC>*>(smem_raw) + zoff;
-  rad_fft<TC, true, LOGH, RT>(a, ti, tw8, Tb.twH, zi);
+  rad_fft<TC, true, H, RT>(a, ti, tw8, Tb.twH, zi);
   const TC sc = A.outscale * (PER ? TC(0.5) : TC(0.25));  // undoes pre_own*_x2/_x4
   // The stores hit the same addresses as the loads; opaque copies of the
   // line base and stride make the compiler recompute them here instead of
@@ -811,7 +978,8 @@ dct_rad(LineArgs<TC> A) {
 }
 
 // Launches dct_rad<..., PER> for the transform length and radix of `key`
-// (log2(H) * 32 + RT) on `grid` workgroups of `block` threads.
+// (HL * 32 + RT, HL = log2(H) for RT = 8 and H for RT = 10) on `grid`
+// workgroups of `block` threads.
 template <typename TC, typename TI, typename TO, int OP, int LD, int ST, bool PER>
 int rad_launch(const LineArgs<TC>& A, int key, dim3 grid, dim3 block, size_t lds,
                hipStream_t s) {
@@ -821,6 +989,7 @@ int rad_launch(const LineArgs<TC>& A, int key, dim3 grid, dim3 block, size_t lds
     case LH * 32 + R: fn = (const void*)dct_rad<TC, TI, TO, OP, LD, ST, LH, R, PER>; break;
     PC_RAD_CASE(4, 8) PC_RAD_CASE(5, 8) PC_RAD_CASE(6, 8) PC_RAD_CASE(7, 8)
     PC_RAD_CASE(8, 8) PC_RAD_CASE(9, 8) PC_RAD_CASE(10, 8) PC_RAD_CASE(11, 8)
+    PC_RAD_CASE(100, 10) PC_RAD_CASE(200, 10) PC_RAD_CASE(500, 10) PC_RAD_CASE(1000, 10)
 #undef PC_RAD_CASE
     default: return fail(PC_ERR_UNSUPPORTED_SIZE, "transform length");
   }
@@ -833,6 +1002,7 @@ int rad_launch(const LineArgs<TC>& A, int key, dim3 grid, dim3 block, size_t lds
       break;
     PC_RAD_LAUNCH(4, 8) PC_RAD_LAUNCH(5, 8) PC_RAD_LAUNCH(6, 8) PC_RAD_LAUNCH(7, 8)
     PC_RAD_LAUNCH(8, 8) PC_RAD_LAUNCH(9, 8) PC_RAD_LAUNCH(10, 8) PC_RAD_LAUNCH(11, 8)
+    PC_RAD_LAUNCH(100, 10) PC_RAD_LAUNCH(200, 10) PC_RAD_LAUNCH(500, 10) PC_RAD_LAUNCH(1000, 10)
 #undef PC_RAD_LAUNCH
   }
   PC_HIP_CHECK(hipGetLastError());
