@@ -151,7 +151,13 @@ typedef struct pc_wls_opts {
  *                    the IB force and lists, the momentum fields, exported
  *                    node stencils -- is in that internal order.
  *                    pc_geom_permutation gives the order, pc_geom_permute
- *                    moves fields between the two orders. */
+ *                    moves fields between the two orders.
+ * The k nearest nodes are chosen by (d^2, node index) in the geometry's own
+ * order: with PC_ORDER_CELL the stencils, and so the results bit for bit,
+ * depend only on the point set, not on the caller's numbering.  Where two
+ * candidates lie exactly equally far (points on an obstacle face that runs
+ * along a grid line, for one), the two orders may choose different, equally
+ * valid stencils. */
 #define PC_ORDER_CALLER 0
 #define PC_ORDER_CELL 1
 
@@ -316,8 +322,8 @@ int pc_geom_destroy(pc_geom* geom);
 /* Sizes of a geometry: counts[0] = M, [1] = number of B+V nodes, [2] =
  * number of near-IB grid points, [3] = k_grid, [4] = k_node block size
  * m^d, [5] = device bytes held by the geometry, [6] = number of B+V entries
- * over all near-IB stencils, [7] = width of the near-IB table (8, 16 or
- * 32).  counts8 holds 8 values. */
+ * over all near-IB stencils, [7] = width of the near-IB table (8, 16, 27
+ * (3D only) or 32).  counts8 holds 8 values. */
 int pc_geom_info(const pc_geom* geom, int64_t* counts8);
 
 /* Copies the stencils out (for inspection and tests).

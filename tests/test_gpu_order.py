@@ -99,3 +99,60 @@ def test_cell_order_independent_of_input_order(name):
     torch.cuda.synchronize()
     assert rel_l2(to_np(uo_caller), to_np(uoc)) <= 1e-12
     assert rel_l2(to_np(pcc), to_np(outs[1][0][3])) <= 1e-12
+
+
+def test_equidistant_candidates():
+    """The square obstacle of Sec. 3 on a 200^2 periodic grid: its surface
+    points lie on grid lines, so some grid points have two candidates at the
+    same distance for their last stencil entry, which the node index decides.
+    The cell order decides by its internal index, a function of the point
+    set: a shuffled cloud gives the same sub-step bit for bit, and it matches
+    the oracle on the nodes in the internal order; the caller order decides by
+    the caller's index and matches the oracle on the caller's numbering."""
+    import torch
+    from paper_2304_14690_amd import pcorr as pc
+    bc = ("periodic", "periodic")
+    c = inputs.make_case("sq", 2, 200, [inputs.Obstacle("box", (0.45, 0.45), (0.55, 0.55))],
+                         16, 16, 16, 3, 4, bc=bc)
+    rng = np.random.Generator(np.random.PCG64(11))
+    sh = rng.permutation(c.M)
+    xs, ks, us = (np.ascontiguousarray(c.x[:, sh]), np.ascontiguousarray(c.kind[sh]),
+                  np.ascontiguousarray(c.u[:, sh]))
+    grid = oracle.Grid(c.d, c.n, c.h, bc)
+    # ties exist: the oracle's stencil sets depend on the node numbering
+    st0 = P.build_stencils(grid, c.x.T.copy(), c.kind, c.k_grid, c.k_node)
+    st1 = P.build_stencils(grid, xs.T.copy(), ks, c.k_grid, c.k_node)
+    differ = (np.sort(st0.grid_idx, 1) != np.sort(sh[st1.grid_idx], 1)).any(1).sum()
+    print(f"grid points whose stencil depends on the numbering: {differ}")
+    assert differ > 0
+    plan = pc.Plan(c.d, c.n, c.h, bc=bc)
+    # the caller's order (shuffled) against the oracle on the same numbering
+    ref1 = P.pressure_correct(st1, us.T.copy())
+    gc = pc.wls_build(plan, torch.from_numpy(xs).cuda(), torch.from_numpy(ks).cuda(), c.k_grid,
+                      c.k_node, order="caller")
+    rc, stc, uoc, pcc = _run(pc, plan, gc, torch.from_numpy(us).cuda())
+    assert rc == 0 and stc["n_it"] == ref1["n_it"]
+    assert rel_l2(to_np(uoc).T, ref1["u_new"]) <= 1e-11
+    assert rel_l2(to_np(pcc), ref1["p"]) <= 1e-11
+    # the cell order from both numberings: bit for bit, and the oracle on
+    # the nodes in the internal order
+    outs, perms = [], []
+    for x, k, u in ((c.x, c.kind, c.u), (xs, ks, us)):
+        g = pc.wls_build(plan, torch.from_numpy(x).cuda(), torch.from_numpy(k).cuda(), c.k_grid,
+                         c.k_node, order="cell")
+        perm = torch.empty(c.M, dtype=torch.int32, device="cuda")
+        pc.geom_permutation(g, perm)
+        ut = torch.from_numpy(u).cuda()
+        ui = torch.empty_like(ut)
+        pc.geom_permute(g, ut, ui, to_internal=True)
+        outs.append(_run(pc, plan, g, ui))
+        perms.append(to_np(perm).astype(np.int64))
+    (ra, sa, ua, pa), (rb, sb, ub, pb) = outs
+    assert ra == rb == 0 and sa["n_it"] == sb["n_it"]
+    assert torch.equal(ua, ub) and torch.equal(pa, pb)
+    xi = c.x[:, perms[0]]
+    sti = P.build_stencils(grid, xi.T.copy(), c.kind[perms[0]], c.k_grid, c.k_node)
+    refi = P.pressure_correct(sti, c.u[:, perms[0]].T.copy())
+    assert sa["n_it"] == refi["n_it"]
+    assert rel_l2(to_np(ua).T, refi["u_new"]) <= 1e-11
+    assert rel_l2(to_np(pa), refi["p"]) <= 1e-11
