@@ -1,6 +1,8 @@
 """Every length of the register line transform (N = 32 ... 4096, half
 lengths 16 ... 2048: one to three radix-8 stages and a final stage of radix
-1, 2 or 4) on each axis of a 2D box, as a cosine transform (homogeneous
+1, 2 or 4; and the radix-10 plan's N = 200, 400, 1000, 2000: two or three
+radix-10 stages and a final stage of radix 1, 2 or 5) on each axis of a 2D
+box, as a cosine transform (homogeneous
 Neumann axis, Eq. 7) and as a packed real DFT (periodic axis), in float64,
 float32 and float32 transforms with float64 defect correction, against the
 oracle's solve (float64 to 1e-11, float32 to 5e-5, the correction to 1e-10,
@@ -17,7 +19,7 @@ from tests.helpers import rel_l2, to_np
 pytestmark = pytest.mark.gpu
 
 P, NE = "periodic", "neumann"
-LENGTHS = [32, 64, 128, 256, 512, 1024, 2048, 4096]
+LENGTHS = [32, 64, 128, 256, 512, 1024, 2048, 4096, 200, 400, 1000, 2000]
 CASES = []
 for N in LENGTHS:
     for bc in (NE, P):

@@ -136,12 +136,18 @@ def resident_bitwise(pc, c, bc=None):
                 assert np.array_equal(xa, xb)
 
 
-@pytest.mark.parametrize("name", list(CASES) + ["3d_16x32x24"])
+@pytest.mark.parametrize("name", list(CASES) + ["3d_16x32x24", "2d_200x1000", "2d_2000x400"])
 def test_mixed_radix_resident_transforms_bitwise(pc, name):
     if name == "3d_16x32x24":
         # a short axis (generic kernel) between two others, one not a power of two
         c = custom_case((16, 32, 24), [inputs.Obstacle("sphere", (0.5, 0.5, 0.5), (0.25,))],
                         27, 27)
+    elif name == "2d_200x1000":
+        # radix-10 plans on both axes: 10^2 and 10^2 * 5
+        c = custom_case((200, 1000), [inputs.Obstacle("circle", (0.4, 0.5), (0.08,))], 16, 16)
+    elif name == "2d_2000x400":
+        # three radix-10 stages on the rows, two and a radix-2 stage on the columns
+        c = custom_case((2000, 400), [inputs.Obstacle("circle", (0.5, 0.5), (0.2,))], 16, 16)
     else:
         c = CASES[name]()
     resident_bitwise(pc, c)
