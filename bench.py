@@ -207,31 +207,67 @@ def rel_l2(a, b):
     return float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
 
 
-def bytes_solve_mode(G, d, mode, sweeps):
+def bytes_solve_mode(G, d, mode, sweeps, warm=False, near_lines=(0.0, 0.0)):
     """Algorithmic bytes of one Poisson solve: 2d - 1 passes, each reading and
-    writing the grid once.  In the correction mode the first pass reads the
-    float64 right-hand side and writes float32, the last reads float32 and
-    writes float64; each sweep's first pass reads b and phi (float64) and
-    writes float32, its last pass reads float32 and phi and writes phi."""
+    writing the grid once.  In the correction mode a cold solve's first pass
+    reads the float64 right-hand side and writes float32, its last reads
+    float32 and writes float64; each sweep's first pass reads b and phi
+    (float64) and writes float32, its last pass reads float32 and phi and
+    writes phi.  A warm solve (IB iterations after the first) starts from
+    the previous phi, and its first sweep transforms the change of the
+    right-hand side forward only on the lines holding near-IB points (the
+    fractions near_lines of the x rows and, in 3D, of the y lines: float64
+    in, float32 out, then float32 in and out), then runs the last-axis pass,
+    the middle inverse (3D) and the accumulating inverse over the grid."""
     if mode == "f64":
         return bytes_solve(G, d, 8)
     if mode == "f32":
         return bytes_solve(G, d, 4)
     mid = 8 * (2 * d - 3)
+    if warm:
+        fwd = near_lines[0] * 12 + (near_lines[1] * 8 if d == 3 else 0.0)
+        return int(G * (fwd + 8 * (d - 1) + 20 + (sweeps - 1) * (20 + mid + 20)))
     return G * ((12 + mid + 12) + sweeps * (20 + mid + 20))
 
 
-def bytes_step(G, M, k, bn, d, mode, sweeps, n_it, n_near, near_entries, n_ib):
+def bytes_step(G, M, k, bn, d, mode, sweeps, n_it, n_near, near_entries, n_ib,
+               near_lines=(0.0, 0.0)):
     """Algorithmic bytes of one sub-step: the RHS transfer at every grid
     point, n_it solves, the near-IB RHS update in every iteration after the
     first (the B+V entries of the near stencils, b_u read and b written at
-    each near point), the IB step (gradient at the B+V nodes, force update)
-    in every iteration, and the final gradient fused with the projection."""
+    each near point; in the correction mode also the old b read and the
+    change written), the IB step (gradient at the B+V nodes, force update)
+    in every iteration, and the final gradient fused with the projection.
+    The correction mode also takes mean(b_u) once and removes mean(phi) at
+    the end (8 + 24 bytes per grid point)."""
     s = 4 if mode == "f32" else 8
-    near = near_entries * (4 + d * s) + n_near * 2 * s
+    near = near_entries * (4 + d * s) + n_near * (2 + (2 if mode == "mixed" else 0)) * s
     ibstep = n_ib * (bn * d * s + 4 + 3 * d * s)
+    solves = bytes_solve_mode(G, d, mode, sweeps)
+    if mode == "mixed":
+        solves += (n_it - 1) * bytes_solve_mode(G, d, mode, sweeps, True, near_lines)
+        solves += 32 * G
+    else:
+        solves *= n_it
     return (bytes_div_all(G, M, k, d, s) + bytes_grad_project(G, M, bn, d, s)
-            + n_it * (bytes_solve_mode(G, d, mode, sweeps) + ibstep) + (n_it - 1) * near)
+            + solves + n_it * ibstep + (n_it - 1) * near)
+
+
+def near_line_fractions(geom, n, d):
+    """Fractions of the x rows and (3D) of the y lines that hold a near-IB
+    grid point: the lines the correction mode's first warm sweep transforms."""
+    import torch
+    from paper_2304_14690_amd import pcorr as pc
+    if geom.n_near == 0:
+        return (0.0, 0.0)
+    near = torch.empty(geom.n_near, dtype=torch.int32, device="cuda")
+    pc.geom_export(geom, near=near)
+    q = near.cpu().numpy().astype(np.int64)
+    rows = np.unique(q // n[0]).size / (int(np.prod(n)) // n[0])
+    if d == 2:
+        return (rows, 0.0)
+    planes = np.unique(q // (n[0] * n[1])).size / n[2]
+    return (rows, planes)
 
 
 def run_shuffled(args, name, N):
@@ -335,6 +371,7 @@ def run_workload(args, name, N, modes_arg):
 
     results = {}
     ref = None
+    near_lines = near_line_fractions(geom, case["n"], d)
 
     def run_mode(geom, mname):
         nonlocal ref
@@ -361,7 +398,8 @@ def run_workload(args, name, N, modes_arg):
         lat_ms = sorted(1e3 * v for v in lat)
         sec = total / args.steps
         nb = bytes_step(G, M, geom.k_grid, geom.bn, d, "mixed" if mname == "mixed3" else mname,
-                        sweeps, stats["n_it"], geom.n_near, geom.near_entries, geom.n_ib)
+                        sweeps, stats["n_it"], geom.n_near, geom.near_entries, geom.n_ib,
+                        near_lines)
         results[mname] = {
             "value": G / sec,
             "ms_per_step": 1e3 * sec,

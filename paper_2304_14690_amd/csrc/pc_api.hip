@@ -332,6 +332,11 @@ int64_t workspace_bytes_for(const pc_plan* P, bool geometry, int64_t n_ib, int64
     if (P->d == 3) add(P->G * (int64_t)s);             // w1b
     add(4 * pc::resident_tiles_max(P, s));            // tile lists
   }
+  if (geometry && pc::delta_possible(P, n_ib, mode)) {
+    add(P->G * 8);                                    // dgrid
+    for (int a = 0; a < P->d - 1; ++a) add(P->G * 4);  // dspec
+    add(4 * pc::resident_tiles_max(P, 4));            // tile lists
+  }
   // reduction partials: 1024 blocks for grid means, two per 64-node block of
   // the IB iteration kernel
   add(8 * std::max<int64_t>(1024, geometry ? 2 * ((n_ib + 63) / 64) : 0));
@@ -419,6 +424,12 @@ int pc_workspace_create(const pc_plan* P, const pc_geom* g, int mode, pc_workspa
     W->tiles = reinterpret_cast<int32_t*>(take(4 * pc::resident_tiles_max(P, s)));
     W->resident = 1;
   }
+  if (g && pc::delta_possible(P, g->n_ib, mode)) {
+    W->dgrid = reinterpret_cast<double*>(take(P->G * 8));
+    for (int a = 0; a < P->d - 1; ++a) W->dspec[a] = reinterpret_cast<float*>(take(P->G * 4));
+    W->tiles = reinterpret_cast<int32_t*>(take(4 * pc::resident_tiles_max(P, 4)));
+    W->delta = 1;
+  }
   W->partial = reinterpret_cast<double*>(take(8 * partial_doubles(g)));
   W->scal = reinterpret_cast<double*>(take(16 * 8));
   W->flag = reinterpret_cast<int32_t*>(take(16 * 4));
@@ -437,11 +448,23 @@ int pc_workspace_create(const pc_plan* P, const pc_geom* g, int mode, pc_workspa
     return fail(PC_ERR_OOM, "pinned host scalars");
   }
   W->hflag = reinterpret_cast<int32_t*>(W->hscal + 16);
-  if (W->resident) {
-    int rc2 = resident_setup(P, g, s, W);
+  if (W->resident || W->delta) {
+    int rc2 = resident_setup(P, g, W->delta ? 4 : s, W);
     if (rc2 != PC_OK) {
       pc_workspace_destroy(W);
       return rc2;
+    }
+  }
+  if (W->delta) {
+    // zero outside the near points and their lines, for good: every later
+    // write lands on those (the same lists every iteration)
+    hipError_t e = hipMemset(W->dgrid, 0, (size_t)P->G * 8);
+    for (int a = 0; a < P->d - 1 && e == hipSuccess; ++a)
+      e = hipMemset(W->dspec[a], 0, (size_t)P->G * 4);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      pc_workspace_destroy(W);
+      return fail(PC_ERR_HIP, "workspace clear failed");
     }
   }
   for (int i = 0; i < 2; ++i) {

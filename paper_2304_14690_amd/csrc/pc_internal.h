@@ -191,6 +191,14 @@ struct pc_workspace {
   int32_t* tiles;    // device tile lists, list l at tl[l]
   int32_t* tl[6];
   int ntl[6];
+  // PC_MIXED with a geometry: the first correction sweep of every IB
+  // iteration after the first solves the change of the right-hand side,
+  // which is nonzero only at the near-IB points, through the forward
+  // transforms of the lines holding them (tile lists above, float32 tiles).
+  int delta;
+  double* dgrid;     // [G] b_it - b_(it-1) at the near points, 0 elsewhere
+  float* dspec[2];   // [G] forward transforms of dgrid along axis 0 (and 1 in
+                     // 3D) on those lines; 0 on every other line
 };
 
 namespace pc {
@@ -216,7 +224,7 @@ int solve_f32(const pc_plan* P, const float* b, float* phi, double* bmean_dev,
 int solve_mixed(const pc_plan* P, const double* b, double* phi, int sweeps, double* bmean_dev,
                 pc_workspace* ws, hipStream_t s, double sigma = 1.0,
                 const int32_t* skip = nullptr, bool warm = false, bool remove_mean = true,
-                bool bmean_given = false);
+                bool bmean_given = false, bool delta = false);
 // Mean of a float64 grid field (trapezoid-weighted on a vertex grid).
 int grid_mean_f64(const pc_plan* P, const double* x, double* partial, int nblk, double* out_dev,
                   hipStream_t s, const int32_t* skip = nullptr);
@@ -241,6 +249,8 @@ PassTiles pass_tiles(const pc_plan* P, int axis, size_t elem);
 // Whether the resident IB-iteration transforms apply to this plan/geometry/mode.
 bool resident_ok(const pc_plan* P, const pc_geom* g, int mode);
 bool resident_possible(const pc_plan* P, int64_t n_ib, int mode);
+// The MIXED counterpart: the change-of-RHS sweep (pc_workspace.delta).
+bool delta_possible(const pc_plan* P, int64_t n_ib, int mode);
 // Device bytes of a workspace (pc_workspace_bytes) from the geometry's counts.
 int64_t workspace_bytes_for(const pc_plan* P, bool geometry, int64_t n_ib, int64_t n_near,
                             int mode);

@@ -1153,7 +1153,7 @@ int solve_f32(const pc_plan* P, const float* b, float* phi, double* bmean_dev, p
 // dominate the float32 rounding of the much smaller residual.
 int solve_mixed(const pc_plan* P, const double* b, double* phi, int sweeps, double* bmean_dev,
                 pc_workspace* ws, hipStream_t s, double sigma, const int32_t* skip, bool warm,
-                bool remove_mean, bool bmean_given) {
+                bool remove_mean, bool bmean_given, bool delta) {
   if (!ws || !ws->w32) return fail(PC_ERR_INVALID_ARG, "mixed solve needs a MIXED workspace");
   float* w = ws->w32;
   double* bm = bmean_dev ? bmean_dev : ws->scal;
@@ -1161,7 +1161,35 @@ int solve_mixed(const pc_plan* P, const double* b, double* phi, int sweeps, doub
   if (!warm)
     PC_TRY((solve_passes<float, double, double, LD_PLAIN, ST_PLAIN>(
         P, P->ax32, b, phi, w, nullptr, nullptr, nullptr, s, bm, sigma, skip)));
-  for (int it = 0; it < sweeps; ++it) {
+  int first = 0;
+  if (warm && delta && ws->delta) {
+    // First sweep of a warm start: the residual of the previous solution is
+    // the change of the right-hand side (the previous residual left after
+    // its sweeps is below the float32 solve's own error), nonzero only at
+    // the near-IB points, so only the lines holding them are transformed
+    // forward; the division drops the mean (mode 0).  The inverse runs on
+    // every line and adds the correction to phi.
+    const int d = P->d;
+    PC_TRY((launch_pass<float, double, float, OP_FWD, LD_PLAIN, ST_PLAIN>(
+        P, 0, ws->dgrid, ws->dspec[0], P->ax32, nullptr, nullptr, nullptr, s, nullptr, 1.0, skip,
+        ws->tl[TL_FWD0], ws->ntl[TL_FWD0])));
+    const float* spec = ws->dspec[0];
+    if (d == 3) {
+      PC_TRY((launch_pass<float, float, float, OP_FWD, LD_PLAIN, ST_PLAIN>(
+          P, 1, ws->dspec[0], ws->dspec[1], P->ax32, nullptr, nullptr, nullptr, s, nullptr, 1.0,
+          skip, ws->tl[TL_FWD1], ws->ntl[TL_FWD1])));
+      spec = ws->dspec[1];
+    }
+    PC_TRY((launch_pass<float, float, float, OP_FDI, LD_PLAIN, ST_PLAIN>(
+        P, d - 1, spec, w, P->ax32, nullptr, nullptr, nullptr, s, nullptr, sigma, skip)));
+    if (d == 3)
+      PC_TRY((launch_pass<float, float, float, OP_INV, LD_PLAIN, ST_PLAIN>(
+          P, 1, w, w, P->ax32, nullptr, nullptr, nullptr, s, nullptr, 1.0, skip)));
+    PC_TRY((launch_pass<float, float, double, OP_INV, LD_PLAIN, ST_ACCUM>(
+        P, 0, w, phi, P->ax32, nullptr, phi, nullptr, s, nullptr, 1.0, skip)));
+    first = 1;
+  }
+  for (int it = first; it < sweeps; ++it) {
     PC_TRY((solve_passes<float, double, double, LD_RESID, ST_ACCUM>(
         P, P->ax32, b, phi, w, b, phi, nullptr, s, bm, sigma, skip)));
   }
@@ -1197,6 +1225,10 @@ int remove_mean_f64(const pc_plan* P, double* phi, pc_workspace* ws, hipStream_t
 bool resident_possible(const pc_plan* P, int64_t n_ib, int mode) {
   if (n_ib == 0 || (mode != PC_F64 && mode != PC_F32)) return false;
   return !P->vertex;
+}
+
+bool delta_possible(const pc_plan* P, int64_t n_ib, int mode) {
+  return mode == PC_MIXED && n_ib > 0 && !P->vertex;
 }
 
 bool resident_ok(const pc_plan* P, const pc_geom* g, int mode) {

@@ -178,7 +178,7 @@ __device__ __forceinline__ T near_update(const int32_t* __restrict__ near, int64
                                          const int32_t* __restrict__ nslot,
                                          const T* __restrict__ ncoef, const T* __restrict__ gib,
                                          int64_t nib, const T* __restrict__ base,
-                                         T* __restrict__ b) {
+                                         T* __restrict__ b, T* __restrict__ dgrid) {
   // WT is the table width itself (padding entries have slot -1 and
   // coefficient exactly 0), so every load is unconditional and all of them
   // are in flight together
@@ -192,10 +192,16 @@ __device__ __forceinline__ T near_update(const int32_t* __restrict__ near, int64
     for (int a = 0; a < D; ++a) acc += ncoef[((int64_t)a * WT + e) * nns + q] * gib[a * nib + s[e]];
   }
   int64_t p = near[q];
-  if (ADD)
+  if (ADD) {
     b[p] += acc;
-  else
+  } else if (dgrid) {
+    // the change of b at this point, for the float32 correction of PC_MIXED
+    const T nb = base[q] + acc;
+    dgrid[p] = nb - b[p];
+    b[p] = nb;
+  } else {
     b[p] = base[q] + acc;
+  }
   return acc;
 }
 
@@ -209,7 +215,8 @@ __global__ void __launch_bounds__(TPB) k_div_near(const int32_t* __restrict__ ne
                                                   const T* __restrict__ gib, int64_t nib,
                                                   const T* __restrict__ base, T* __restrict__ b,
                                                   const int32_t* __restrict__ skip, IbClose close,
-                                                  double* __restrict__ part) {
+                                                  double* __restrict__ part,
+                                                  T* __restrict__ dgrid) {
   if (CLOSE) {
     // block 0 may set the flag while other blocks start: read it once per
     // block, so that no thread leaves before the criterion's barriers
@@ -224,7 +231,7 @@ __global__ void __launch_bounds__(TPB) k_div_near(const int32_t* __restrict__ ne
   if (MEAN) {
     // every thread of the block reaches the reduction
     T acc = T(0);
-    if (q < nnear) acc = near_update<T, D, ADD, WT>(near, q, nns, nslot, ncoef, gib, nib, base, b);
+    if (q < nnear) acc = near_update<T, D, ADD, WT>(near, q, nns, nslot, ncoef, gib, nib, base, b, dgrid);
     __shared__ double red[TPB / 64];
     double v = (double)acc;
 #pragma unroll
@@ -240,7 +247,7 @@ __global__ void __launch_bounds__(TPB) k_div_near(const int32_t* __restrict__ ne
     return;
   }
   if (q >= nnear) return;
-  (void)near_update<T, D, ADD, WT>(near, q, nns, nslot, ncoef, gib, nib, base, b);
+  (void)near_update<T, D, ADD, WT>(near, q, nns, nslot, ncoef, gib, nib, base, b, dgrid);
 }
 
 // out[0] = mean_u[0] + (sum of part[0..nb)) * inv_g, the sum in a fixed order.
@@ -721,7 +728,8 @@ int launch_div_all(const pc_geom* g, const T* gcoef, const T* v, T* b, hipStream
 template <typename T>
 int launch_div_near(const pc_geom* g, const T* ncoefib, const T* gib, const T* base, T* b,
                     bool add, hipStream_t s, const int32_t* skip = nullptr,
-                    const IbClose* close = nullptr, double* mean_part = nullptr) {
+                    const IbClose* close = nullptr, double* mean_part = nullptr,
+                    T* dgrid = nullptr) {
   if (g->n_near == 0) return close ? fail(PC_ERR_INVALID_ARG, "criterion without near points")
                                    : PC_OK;
   dim3 grid(nblk(g->n_near)), block(TPB);
@@ -731,11 +739,11 @@ int launch_div_near(const pc_geom* g, const T* ncoefib, const T* gib, const T* b
     if (mean_part)                                                                             \
       hipLaunchKernelGGL((k_div_near<T, D, ADD, WT, CL, true>), grid, block, 0, s, g->near,   \
                          g->n_near, g->nns, g->nslot, ncoefib, gib, g->n_ib, base, b, skip, cl, \
-                         mean_part);                                                           \
+                         mean_part, dgrid);                                                    \
     else                                                                                       \
       hipLaunchKernelGGL((k_div_near<T, D, ADD, WT, CL, false>), grid, block, 0, s, g->near,  \
                          g->n_near, g->nns, g->nslot, ncoefib, gib, g->n_ib, base, b, skip, cl, \
-                         mean_part);                                                           \
+                         mean_part, dgrid);                                                    \
   } while (0)
 #define DNL(D, ADD, WT)                     \
   do {                                      \
@@ -930,6 +938,9 @@ int pressure_correct_t(const pc_geom* g, const pc_plan* P, int mode, const T* u,
   const int gauge = o ? o->gauge : 0;
   const bool resident = W->resident && !(o && (o->flags & PC_IB_FULL_TRANSFORMS)) &&
                         mode != PC_MIXED;
+  // PC_MIXED: the first correction sweep of later iterations on the change
+  // of the right-hand side (near-IB lines only)
+  const bool delta = W->delta && mode == PC_MIXED && !(o && (o->flags & PC_IB_FULL_TRANSFORMS));
   // the solve returns p = phi / sigma directly; the gradient of phi is
   // sigma * grad p
   const double sigma = 1.5 * dt;
@@ -972,7 +983,8 @@ int pressure_correct_t(const pc_geom* g, const pc_plan* P, int mode, const T* u,
     const bool upd = it > 1 || g_io;
     if (upd)
       PC_TRY(launch_div_near<T>(g, nci<T>(g), gib, bnear, b, false, s, skip, prev,
-                                inc_mean ? W->part2 : nullptr));
+                                inc_mean ? W->part2 : nullptr,
+                                delta ? reinterpret_cast<T*>(W->dgrid) : nullptr));
     if (inc_mean) {
       hipLaunchKernelGGL(k_mean_near, dim3(1), dim3(TPB), 0, s, (const double*)W->part2,
                          upd ? (int)nblk(g->n_near) : 0, (const double*)(W->scal + 5),
@@ -994,7 +1006,7 @@ int pressure_correct_t(const pc_geom* g, const pc_plan* P, int mode, const T* u,
       // iteration's pressure, whose right-hand side differs only near the
       // IB; the mean is removed once, after the last iteration
       PC_TRY(solve_mixed(P, (const double*)b, (double*)p, sweeps, W->scal, W, s, sigma, skip,
-                         it > 1, false, inc_mean));
+                         it > 1, false, inc_mean, delta));
     if (nib)
       PC_TRY(launch_ib_step<T>(g, ibc<T>(g), p, (T)sigma, uib, gib, tol, W->partial, W->flag,
                                W->scal + 1, s, skip, host_flag, host_sums, !defer));
