@@ -170,18 +170,24 @@ typedef struct pc_ib_opts {
                      /* (default 2): the first iteration corrects a        */
                      /* float32 solve, later ones start from the previous  */
                      /* iteration's pressure (its right-hand side differs  */
-                     /* only near the IB); mean(p) is removed at the end   */
+                     /* only near the IB), the first of their sweeps on    */
+                     /* that change; mean(p) is removed at the end         */
   int32_t gauge;     /* 0: zero-mean pressure; 1: zero at the first cell    */
   int32_t flags;     /* PC_IB_* bits below                                  */
 } pc_ib_opts;
 
 /* pc_ib_opts.flags: transform every grid line in every IB iteration.  By
- * default (PC_F64, PC_F32, every n[a] >= 32) iterations after the first
+ * default (PC_F64, PC_F32, cell-centred grids) iterations after the first
  * redo the forward transforms only on the grid lines that hold near-IB
  * points (the only ones whose right-hand side changes, Sec. 2.3) and run
  * the inverse transforms only on the lines the B+V gradient reads; the
  * remaining lines are completed after the last iteration.  The results are
- * identical bit for bit; this flag exists to show that. */
+ * identical bit for bit; this flag exists to show that.  PC_MIXED: by
+ * default the first correction sweep of each iteration after the first
+ * solves the change of the right-hand side (transformed forward on those
+ * lines only) instead of the whole residual; with the flag every sweep
+ * takes the whole residual (the results agree within the mode's
+ * tolerance, not bit for bit). */
 #define PC_IB_FULL_TRANSFORMS 1
 
 typedef struct pc_stats {

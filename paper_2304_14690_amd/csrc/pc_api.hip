@@ -461,6 +461,9 @@ int pc_workspace_create(const pc_plan* P, const pc_geom* g, int mode, pc_workspa
     hipError_t e = hipMemset(W->dgrid, 0, (size_t)P->G * 8);
     for (int a = 0; a < P->d - 1 && e == hipSuccess; ++a)
       e = hipMemset(W->dspec[a], 0, (size_t)P->G * 4);
+    // complete before the caller's streams (which need not synchronise with
+    // the null stream) use the workspace
+    if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
       (void)hipGetLastError();
       pc_workspace_destroy(W);
