@@ -1,9 +1,10 @@
 """Parity at the full sizes the benchmark times: the 2048^2 workload (k = 16),
-the 256^3 workload (k = 27), the 512^3 workload (134M nodes, a sphere plus a
-box, k = 27; float32 transforms with 2 and 3 float64 correction sweeps
-against float64), and the variants with periodic axes (2048^2 periodic in x;
-256^3 periodic in x and z), through pc_pressure_correct with its own
-workspace, as bench.py runs it.
+the same cloud on the paper's 2000^2 grid (radix-10 transforms), the 256^3
+workload (k = 27), the 512^3 workload (134M nodes, a sphere plus a box,
+k = 27; float32 transforms with 2 and 3 float64 correction sweeps against
+float64), and the variants with periodic axes (2048^2 periodic in x; 256^3
+periodic in x and z), through pc_pressure_correct with its own workspace, as
+bench.py runs it.
 
 The oracle cannot build every stencil of these sizes within a test, so it is
 compared on outputs it computes one by one at sampled targets (random, next
@@ -22,8 +23,8 @@ to the obstacle, on the box faces), and on properties that hold at any size:
     float32 within 5e-5 of the float64 sub-step (which the oracle pins here
     and at smaller sizes); the correction mode stops after as many IB
     iterations as float64.  At 512^3 float64 stencils alone take 189 GB, so
-    no float32 copy is built there and the all-float32 mode is checked at
-    the smaller sizes only.
+    the all-float32 mode runs there on a float32-only geometry built after
+    the float64 one is freed.
 
 Stencils are read back only at the sampled targets (pc_geom_export_at): a
 whole export would not fit next to the 512^3 geometry.
@@ -44,14 +45,16 @@ SIGMA = 1.5  # phi = (3 dt / 2) p with dt = 1
 
 
 BCS = {"2d2048": None, "3d256": None, "2d2048p": ("periodic", "neumann"),
-       "3d256p": ("periodic", "neumann", "periodic"), "3d512": None}
+       "3d256p": ("periodic", "neumann", "periodic"), "2d2000": None, "3d512": None}
 
 
 def _workload(name):
     import torch
     bc = BCS[name]
     if name.startswith("2d"):
-        c = inputs.make_case(name, 2, 2048, [inputs.Obstacle("circle", (0.3, 0.5), (0.05,))],
+        # 2000^2: the paper's grid size, on the radix-10 transforms
+        N = 2000 if name == "2d2000" else 2048
+        c = inputs.make_case(name, 2, N, [inputs.Obstacle("circle", (0.3, 0.5), (0.05,))],
                              16, 16, 32, 3, 4, bc=bc)
         return c.d, c.n, c.h, c.x, c.kind, c.k_grid, torch.from_numpy(c.u).cuda()
     if name == "3d512":
