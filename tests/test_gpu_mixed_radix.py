@@ -108,7 +108,9 @@ def resident_bitwise(pc, c, bc=None):
     """The sub-step with resident transforms (later IB iterations transform
     only the lines whose right-hand side changed and invert only the lines
     the B+V gradient reads) against every line transformed in every
-    iteration: equal bit for bit, float64 and float32, cold and warm."""
+    iteration: equal bit for bit, float64 and float32, cold and warm; and
+    the correction mode with its change-of-RHS sweeps and with full
+    residual sweeps, both within 1e-10 of float64."""
     import torch
     plan = pc.Plan(c.d, c.n, c.h, bc=bc)
     geom = pc.wls_build(plan, torch.from_numpy(c.x).cuda(), torch.from_numpy(c.kind).cuda(),
@@ -134,9 +136,24 @@ def resident_bitwise(pc, c, bc=None):
             assert ra[0] == rb[0] and ra[1] == rb[1]
             for xa, xb in zip(ra[2:], rb[2:]):
                 assert np.array_equal(xa, xb)
+    # PC_MIXED: the change-of-RHS first sweep of later iterations (default)
+    # against full residual sweeps (the flag), within the mode's tolerance,
+    # both against float64
+    ut = torch.from_numpy(c.u).cuda()
+    res = []
+    for mode, full in ((pc.PC_F64, False), (pc.PC_MIXED, False), (pc.PC_MIXED, True)):
+        uo = torch.empty_like(ut)
+        p = torch.empty(G, dtype=torch.float64, device="cuda")
+        rc, st = pc.pressure_correct(geom, plan, mode, ut, 1.0, uo, p, full_transforms=full)
+        torch.cuda.synchronize()
+        res.append((st["n_it"], to_np(uo), to_np(p)))
+    for n_it, uo, p in res[1:]:
+        assert n_it == res[0][0]
+        assert rel_l2(uo, res[0][1]) <= 1e-10 and rel_l2(p, res[0][2]) <= 1e-10
 
 
-@pytest.mark.parametrize("name", list(CASES) + ["3d_16x32x24", "2d_200x1000", "2d_2000x400"])
+@pytest.mark.parametrize("name", list(CASES) + ["3d_16x32x24", "2d_200x1000", "2d_2000x400",
+                                                 "3d_40x200x32"])
 def test_mixed_radix_resident_transforms_bitwise(pc, name):
     if name == "3d_16x32x24":
         # a short axis (generic kernel) between two others, one not a power of two
@@ -145,6 +162,10 @@ def test_mixed_radix_resident_transforms_bitwise(pc, name):
     elif name == "2d_200x1000":
         # radix-10 plans on both axes: 10^2 and 10^2 * 5
         c = custom_case((200, 1000), [inputs.Obstacle("circle", (0.4, 0.5), (0.08,))], 16, 16)
+    elif name == "3d_40x200x32":
+        # the radix-10 plan on the middle (strided) axis of a 3D box
+        c = custom_case((40, 200, 32), [inputs.Obstacle("sphere", (0.5, 0.5, 0.5), (0.25,))],
+                        27, 27)
     elif name == "2d_2000x400":
         # three radix-10 stages on the rows, two and a radix-2 stage on the columns
         c = custom_case((2000, 400), [inputs.Obstacle("circle", (0.5, 0.5), (0.2,))], 16, 16)
