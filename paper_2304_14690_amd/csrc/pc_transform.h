@@ -7,6 +7,8 @@
 // their own boundary condition.
 #pragma once
 
+#include <type_traits>
+
 #include "pc_internal.h"
 
 namespace pc {
@@ -125,6 +127,54 @@ __device__ __forceinline__ double resid_ijk(const double* __restrict__ b,
     lap += ((zp - c) - (c - zm)) * ih2[2];
   }
   return b[p] - rscale * lap;
+}
+
+// The residuals, less sb, of RB points of one line along x (cell grid), at
+// x = n + q dn (q < RB) of the line at (j, k) that starts at flat index lb:
+// the arithmetic of resid_ijk.  The y and z neighbour offsets are the line's
+// own and the dimension is a template argument, so the batch has no branch
+// and all its loads are issued before the first is used (resid_ijk point by
+// point waits for each point's loads in turn, which left a 512^3 residual
+// pass waiting on memory most of its time).
+template <int D, int RB>
+__device__ __forceinline__ void resid_row(const double* __restrict__ b,
+                                          const double* __restrict__ phi, int64_t lb, int n,
+                                          int dn, int j, int k, int32_t n0, int32_t n1,
+                                          int32_t n2, int perm, const double* ih2,
+                                          double rscale, double sb, double* r) {
+  const int64_t s1 = n0, s2 = (int64_t)n0 * n1;
+  const int64_t oym = j > 0 ? -s1 : ((perm & 2) ? (int64_t)(n1 - 1) * s1 : 0);
+  const int64_t oyp = j < n1 - 1 ? s1 : ((perm & 2) ? -(int64_t)(n1 - 1) * s1 : 0);
+  int64_t ozm = 0, ozp = 0;
+  if (D == 3) {
+    ozm = k > 0 ? -s2 : ((perm & 4) ? (int64_t)(n2 - 1) * s2 : 0);
+    ozp = k < n2 - 1 ? s2 : ((perm & 4) ? -(int64_t)(n2 - 1) * s2 : 0);
+  }
+  double c[RB], xm[RB], xp[RB], ym[RB], yp[RB], zm[RB], zp[RB], bb[RB];
+#pragma unroll
+  for (int q = 0; q < RB; ++q) {
+    const int i = n + q * dn;
+    const int64_t p = lb + i;
+    const int64_t pxm = i > 0 ? p - 1 : ((perm & 1) ? p + (n0 - 1) : p);
+    const int64_t pxp = i < n0 - 1 ? p + 1 : ((perm & 1) ? p - (n0 - 1) : p);
+    c[q] = phi[p];
+    xm[q] = phi[pxm];
+    xp[q] = phi[pxp];
+    ym[q] = phi[p + oym];
+    yp[q] = phi[p + oyp];
+    if (D == 3) {
+      zm[q] = phi[p + ozm];
+      zp[q] = phi[p + ozp];
+    }
+    bb[q] = b[p];
+  }
+#pragma unroll
+  for (int q = 0; q < RB; ++q) {
+    double lap = ((xp[q] - c[q]) - (c[q] - xm[q])) * ih2[0] +
+                 ((yp[q] - c[q]) - (c[q] - ym[q])) * ih2[1];
+    if (D == 3) lap += ((zp[q] - c[q]) - (c[q] - zm[q])) * ih2[2];
+    r[q] = (bb[q] - rscale * lap) - sb;
+  }
 }
 
 // The same residual at flat index p (coordinates by division).
@@ -723,16 +773,27 @@ dct_rad(LineArgs<TC> A) {
   cplx<TC> a[RT];
   if (OP != OP_INV) {
     if (rows && LD == LD_RESID) {
-      // the residual reads 5-7 values per point: batches of RB points (RB
-      // divides NV), the batch loop kept rolled so that the kernel stays small
+      // the residual reads 6-8 values per point: batches of RR points (RR
+      // divides NV) whose loads are in flight together, the batch loop kept
+      // rolled so that the kernel stays small
+      const double sb = A.sub ? *A.sub : 0.0;  // r - 0 is r exactly
+      auto rows_resid = [&](auto dim) {
+        constexpr int D = decltype(dim)::value;
+        constexpr int RR = D == 3 ? 4 : 4;
+        static_assert(NV % RR == 0, "residual batches cover the thread's points");
 #pragma unroll 1
-      for (int i0 = 0; i0 < NV; i0 += RB) {
-        TC xv[RB];
+        for (int i0 = 0; i0 < NV; i0 += RR) {
+          double rv[RR];
+          resid_row<D, RR>(A.rb, A.rphi, lb, t + T * i0, T, lj, lk, A.n0, A.n1, A.n2, A.perm,
+                           A.ih2, A.rscale, sb, rv);
 #pragma unroll
-        for (int i = 0; i < RB; ++i) xv[i] = load(t + T * (i0 + i));
-#pragma unroll
-        for (int i = 0; i < RB; ++i) zr[vpad(line_pos<PER>(t + T * (i0 + i), N))] = xv[i];
-      }
+          for (int i = 0; i < RR; ++i) zr[vpad(line_pos<PER>(t + T * (i0 + i), N))] = (TC)rv[i];
+        }
+      };
+      if (A.d == 3)
+        rows_resid(std::integral_constant<int, 3>{});
+      else
+        rows_resid(std::integral_constant<int, 2>{});
       line_sync<T>();
     } else if (rows) {
       // coalesced loads, reordered into Makhoul order through LDS
@@ -825,8 +886,16 @@ dct_rad(LineArgs<TC> A) {
         TC l_a = (rest + e_a) * ls_;
         TC l_b = (rest + e_b) * ls_;
         if (k == 0) x0 = xa;
-        ya[q] = l_a != TC(0) ? xa / l_a : TC(0);
-        yb[q] = xb / l_b;
+        if constexpr (sizeof(TC) == 4) {
+          // float32: the hardware reciprocal (1 ulp) instead of the
+          // correctly rounded division sequence, about ten instructions
+          // each; the quotient is within 2 ulp
+          ya[q] = l_a != TC(0) ? xa * __builtin_amdgcn_rcpf(l_a) : TC(0);
+          yb[q] = xb * __builtin_amdgcn_rcpf(l_b);
+        } else {
+          ya[q] = l_a != TC(0) ? xa / l_a : TC(0);
+          yb[q] = xb / l_b;
+        }
       }
     }
     if (OP == OP_FWD) {
