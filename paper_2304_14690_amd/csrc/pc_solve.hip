@@ -972,6 +972,9 @@ int launch_pass(const pc_plan* P, int axis, const TI* in, TO* out, const AxisTab
       ntile = ntiles;
     }
     size_t lds = (size_t)C * LS * 2 * sizeof(TC);
+    // the row residual loader stages the tile's float64 phi in the same LDS
+    if (LD == LD_RESID && axis == 0) lds = std::max(lds, (size_t)C * A.N * sizeof(double));
+    if (lds > (size_t)lds_limit()) return fail(PC_ERR_UNSUPPORTED_SIZE, "transform tile does not fit in LDS");
     const int key = (RT == 8 ? logH : H) * 32 + RT;
     if (P->bc[axis] == PC_BC_PERIODIC)
       return rad_launch<TC, TI, TO, OP, LD, ST, true>(A, key, dim3(ntile), dim3(C * T), lds, s);

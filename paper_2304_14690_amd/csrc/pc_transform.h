@@ -130,49 +130,67 @@ __device__ __forceinline__ double resid_ijk(const double* __restrict__ b,
 }
 
 // The residuals, less sb, of RB points of one line along x (cell grid), at
-// x = n + q dn (q < RB) of the line at (j, k) that starts at flat index lb:
-// the arithmetic of resid_ijk.  The y and z neighbour offsets are the line's
-// own and the dimension is a template argument, so the batch has no branch
-// and all its loads are issued before the first is used (resid_ijk point by
-// point waits for each point's loads in turn, which left a 512^3 residual
-// pass waiting on memory most of its time).
+// x = n + q dn (q < RB) of line c of a tile of C lines whose phi is staged
+// in LDS (ph0: line cc at ph0 + cc n0); the line is at (j, k) and starts at
+// flat index lb.  The arithmetic of resid_ijk: x neighbours, and y
+// neighbours whose line is in the tile, come from LDS; z neighbours, b and
+// y neighbours outside the tile from memory.  The dimension is a template
+// argument and the y and z offsets are the line's own, so a batch's memory
+// loads are issued before the first is used.
 template <int D, int RB>
 __device__ __forceinline__ void resid_row(const double* __restrict__ b,
-                                          const double* __restrict__ phi, int64_t lb, int n,
-                                          int dn, int j, int k, int32_t n0, int32_t n1,
-                                          int32_t n2, int perm, const double* ih2,
-                                          double rscale, double sb, double* r) {
+                                          const double* __restrict__ phi, const double* ph0,
+                                          int c, int C, int64_t lb, int n, int dn, int j, int k,
+                                          int32_t n0, int32_t n1, int32_t n2, int perm,
+                                          const double* ih2, double rscale, double sb, double* r) {
   const int64_t s1 = n0, s2 = (int64_t)n0 * n1;
-  const int64_t oym = j > 0 ? -s1 : ((perm & 2) ? (int64_t)(n1 - 1) * s1 : 0);
-  const int64_t oyp = j < n1 - 1 ? s1 : ((perm & 2) ? -(int64_t)(n1 - 1) * s1 : 0);
+  // y neighbour lines as line offsets: -1 / +1 inside, the mirror (0) or the
+  // wrap-around at the ends
+  const int dym = j > 0 ? -1 : ((perm & 2) ? n1 - 1 : 0);
+  const int dyp = j < n1 - 1 ? 1 : ((perm & 2) ? -(n1 - 1) : 0);
   int64_t ozm = 0, ozp = 0;
   if (D == 3) {
     ozm = k > 0 ? -s2 : ((perm & 4) ? (int64_t)(n2 - 1) * s2 : 0);
     ozp = k < n2 - 1 ? s2 : ((perm & 4) ? -(int64_t)(n2 - 1) * s2 : 0);
   }
-  double c[RB], xm[RB], xp[RB], ym[RB], yp[RB], zm[RB], zp[RB], bb[RB];
+  const double* ph = ph0 + (int64_t)c * n0;
+  const bool in_m = (unsigned)(c + dym) < (unsigned)C, in_p = (unsigned)(c + dyp) < (unsigned)C;
+  double cv[RB], xm[RB], xp[RB], ym[RB], yp[RB], zm[RB], zp[RB], bb[RB];
 #pragma unroll
   for (int q = 0; q < RB; ++q) {
-    const int i = n + q * dn;
-    const int64_t p = lb + i;
-    const int64_t pxm = i > 0 ? p - 1 : ((perm & 1) ? p + (n0 - 1) : p);
-    const int64_t pxp = i < n0 - 1 ? p + 1 : ((perm & 1) ? p - (n0 - 1) : p);
-    c[q] = phi[p];
-    xm[q] = phi[pxm];
-    xp[q] = phi[pxp];
-    ym[q] = phi[p + oym];
-    yp[q] = phi[p + oyp];
+    const int64_t p = lb + n + q * dn;
     if (D == 3) {
       zm[q] = phi[p + ozm];
       zp[q] = phi[p + ozp];
     }
     bb[q] = b[p];
   }
+  if (in_m) {
+#pragma unroll
+    for (int q = 0; q < RB; ++q) ym[q] = ph[(int64_t)dym * n0 + n + q * dn];
+  } else {
+#pragma unroll
+    for (int q = 0; q < RB; ++q) ym[q] = phi[lb + n + q * dn + dym * s1];
+  }
+  if (in_p) {
+#pragma unroll
+    for (int q = 0; q < RB; ++q) yp[q] = ph[(int64_t)dyp * n0 + n + q * dn];
+  } else {
+#pragma unroll
+    for (int q = 0; q < RB; ++q) yp[q] = phi[lb + n + q * dn + dyp * s1];
+  }
 #pragma unroll
   for (int q = 0; q < RB; ++q) {
-    double lap = ((xp[q] - c[q]) - (c[q] - xm[q])) * ih2[0] +
-                 ((yp[q] - c[q]) - (c[q] - ym[q])) * ih2[1];
-    if (D == 3) lap += ((zp[q] - c[q]) - (c[q] - zm[q])) * ih2[2];
+    const int i = n + q * dn;
+    cv[q] = ph[i];
+    xm[q] = ph[i > 0 ? i - 1 : ((perm & 1) ? n0 - 1 : i)];
+    xp[q] = ph[i < n0 - 1 ? i + 1 : ((perm & 1) ? 0 : i)];
+  }
+#pragma unroll
+  for (int q = 0; q < RB; ++q) {
+    double lap = ((xp[q] - cv[q]) - (cv[q] - xm[q])) * ih2[0] +
+                 ((yp[q] - cv[q]) - (cv[q] - ym[q])) * ih2[1];
+    if (D == 3) lap += ((zp[q] - cv[q]) - (cv[q] - zm[q])) * ih2[2];
     r[q] = (bb[q] - rscale * lap) - sb;
   }
 }
@@ -773,27 +791,40 @@ dct_rad(LineArgs<TC> A) {
   cplx<TC> a[RT];
   if (OP != OP_INV) {
     if (rows && LD == LD_RESID) {
-      // the residual reads 6-8 values per point: batches of RR points (RR
-      // divides NV) whose loads are in flight together, the batch loop kept
-      // rolled so that the kernel stays small
+      // phi of the tile's C lines (C N contiguous doubles) is staged in LDS
+      // once, so that a point reads 3-5 values from memory instead of 6-8;
+      // the float residuals stay in registers until every thread is done
+      // with the staged lines, which the transform's LDS area overlaps
+      double* const ph0 = reinterpret_cast<double*>(smem_raw);
+      {
+        const int CT = C * T;
+        const double* src = A.rphi + lbase[0];
+#pragma unroll
+        for (int r = 0; r < NV; ++r) ph0[threadIdx.x + r * CT] = src[threadIdx.x + r * CT];
+      }
+      __syncthreads();
       const double sb = A.sub ? *A.sub : 0.0;  // r - 0 is r exactly
+      TC rv[NV];
       auto rows_resid = [&](auto dim) {
         constexpr int D = decltype(dim)::value;
-        constexpr int RR = D == 3 ? 4 : 4;
+        constexpr int RR = 4;
         static_assert(NV % RR == 0, "residual batches cover the thread's points");
-#pragma unroll 1
-        for (int i0 = 0; i0 < NV; i0 += RR) {
-          double rv[RR];
-          resid_row<D, RR>(A.rb, A.rphi, lb, t + T * i0, T, lj, lk, A.n0, A.n1, A.n2, A.perm,
-                           A.ih2, A.rscale, sb, rv);
 #pragma unroll
-          for (int i = 0; i < RR; ++i) zr[vpad(line_pos<PER>(t + T * (i0 + i), N))] = (TC)rv[i];
+        for (int i0 = 0; i0 < NV; i0 += RR) {
+          double rb4[RR];
+          resid_row<D, RR>(A.rb, A.rphi, ph0, c, C, lb, t + T * i0, T, lj, lk, A.n0, A.n1, A.n2,
+                           A.perm, A.ih2, A.rscale, sb, rb4);
+#pragma unroll
+          for (int i = 0; i < RR; ++i) rv[i0 + i] = (TC)rb4[i];
         }
       };
       if (A.d == 3)
         rows_resid(std::integral_constant<int, 3>{});
       else
         rows_resid(std::integral_constant<int, 2>{});
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < NV; ++i) zr[vpad(line_pos<PER>(t + T * i, N))] = rv[i];
       line_sync<T>();
     } else if (rows) {
       // coalesced loads, reordered into Makhoul order through LDS
