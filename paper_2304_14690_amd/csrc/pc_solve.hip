@@ -609,10 +609,18 @@ __global__ void __launch_bounds__(256) partial_sum_f64(const double* __restrict_
                                                        const int32_t* __restrict__ skip) {
   __shared__ double red[256];
   if (skip && *skip) return;
-  double acc = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
-    acc += x[i];
-  red[threadIdx.x] = acc;
+  // four partial sums per thread, so that four loads are in flight
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  for (; i + 3 * stride < n; i += 4 * stride) {
+    a0 += x[i];
+    a1 += x[i + stride];
+    a2 += x[i + 2 * stride];
+    a3 += x[i + 3 * stride];
+  }
+  for (; i < n; i += stride) a0 += x[i];
+  red[threadIdx.x] = (a0 + a1) + (a2 + a3);
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
     if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
@@ -668,9 +676,18 @@ __global__ void __launch_bounds__(256) sub_scalar_f64(double* __restrict__ x, in
                                                       const double* __restrict__ m,
                                                       const int32_t* __restrict__ skip) {
   if (skip && *skip) return;
-  double mv = m[0];
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
-    x[i] -= mv;
+  const double mv = m[0];
+  // four elements per thread and step, their loads in flight together
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  for (; i + 3 * stride < n; i += 4 * stride) {
+    const double v0 = x[i], v1 = x[i + stride], v2 = x[i + 2 * stride], v3 = x[i + 3 * stride];
+    x[i] = v0 - mv;
+    x[i + stride] = v1 - mv;
+    x[i + 2 * stride] = v2 - mv;
+    x[i + 3 * stride] = v3 - mv;
+  }
+  for (; i < n; i += stride) x[i] -= mv;
 }
 
 __global__ void __launch_bounds__(256) zero_bytes(uint32_t* __restrict__ p, int64_t nwords) {

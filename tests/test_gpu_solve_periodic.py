@@ -107,3 +107,38 @@ def test_periodic_eigenfunction_invariant(pc, n, h, bc, ks, ph):
     err = rel_l2(to_np(bt), v / lam)
     print(f"eigenfunction {n} {bc} {ks}: rel L2 {err:.2e} (bound {bound:.2e})")
     assert err <= max(1e-13, bound)
+
+
+# The float64 residual of the MIXED sweeps is fused into the row pass, which
+# stages the phi of its tile of C consecutive x-lines in LDS and reads a y
+# neighbour from there when that line is in the tile.  On these grids the
+# tiles (C = 16, 8 and 16 lines) run across z-planes (n1 = 8, 10, 12), so the
+# neighbour of a line at the plane's first or last y row is the mirror, a
+# wrap-around line in the same tile, or a line of another tile.
+ROW_TILE_CASES = [
+    ((32, 8, 1024), (0.03, 0.05, 1 / 1024), (NE, P, NE)),
+    ((32, 10, 820), (0.03, 0.05, 1 / 820), (NE, NE, P)),
+    ((64, 12, 688), (1 / 64, 0.05, 1 / 688), (P, P, NE)),
+]
+RT_IDS = ["x".join(map(str, n)) + "-" + "".join(b[0] for b in bc) for n, _, bc in ROW_TILE_CASES]
+
+
+@pytest.mark.parametrize("n,h,bc", ROW_TILE_CASES, ids=RT_IDS)
+@pytest.mark.parametrize("sweeps", [2, 3])
+def test_mixed_residual_row_tiles(pc, n, h, bc, sweeps):
+    import torch
+    grid = Grid(len(n), n, h, bc)
+    plan = pc.Plan(len(n), n, h, bc=bc)
+    b = _rhs(grid.G, 23)
+    phi_ref, _ = poisson.solve(grid, b)
+    bt = torch.from_numpy(b).cuda()
+    ws = pc.Workspace(plan, None, pc.PC_MIXED)
+    phim = torch.empty_like(bt)
+    pc.poisson_fft_solve(plan, bt, phim, pc.PC_MIXED, sweeps=sweeps, ws=ws)
+    phi64 = torch.empty_like(bt)
+    pc.poisson_fft_solve(plan, bt, phi64, pc.PC_F64)
+    torch.cuda.synchronize()
+    em = rel_l2(to_np(phim), phi_ref)
+    e64 = rel_l2(to_np(phim), to_np(phi64))
+    print(f"{n} {bc} S={sweeps}: mixed vs oracle {em:.2e}, vs f64 {e64:.2e}")
+    assert em <= 1e-10 and e64 <= 1e-10
