@@ -442,9 +442,17 @@ def run_workload(args, name, N, modes_arg):
         return e0.elapsed_time(e1) / reps * 1e-3  # seconds per launch
 
     u64 = case["u"]
-    b64 = torch.empty(G, dtype=torch.float64, device="cuda")
-    phi64 = torch.empty(G, dtype=torch.float64, device="cuda")
-    gr64 = torch.empty((d, M), dtype=torch.float64, device="cuda")
+    # the outputs of these launches in one allocation, 256-byte aligned
+    # regions, as the sub-step's workspace holds b and phi: the large
+    # gathers' speed depends on where their output lands (k_div_all writing
+    # into a separate 1 GiB allocation at 512^3 takes 22.8 ms, into a region
+    # of a larger block 20.8 ms, inside the sub-step 20.9 ms)
+    def aligned(n):
+        return (n + 31) // 32 * 32
+    blk = torch.empty(2 * aligned(G) + aligned(d * M), dtype=torch.float64, device="cuda")
+    b64 = blk[:G]
+    phi64 = blk[aligned(G):aligned(G) + G]
+    gr64 = blk[2 * aligned(G):2 * aligned(G) + d * M].view(d, M)
     pc.div_to_grid(geom, u64, b64)
     pc.poisson_fft_solve(plan, b64, phi64, pc.PC_F64)
     reps = args.kernel_reps
@@ -542,7 +550,7 @@ def run_workload(args, name, N, modes_arg):
         torch.cuda.synchronize()
         del src, dst
 
-    del geom, plan, u64, b64, phi64, gr64, case
+    del geom, plan, u64, b64, phi64, gr64, blk, case
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
     f64 = results.get("f64") or next(iter(results.values()))
