@@ -112,13 +112,18 @@ def test_periodic_eigenfunction_invariant(pc, n, h, bc, ks, ph):
 # The float64 residual of the MIXED sweeps is fused into the row pass, which
 # stages the phi of its tile of C consecutive x-lines in LDS and reads a y
 # neighbour from there when that line is in the tile.  On these grids the
-# tiles (C = 16, 8 and 16 lines) run across z-planes (n1 = 8, 10, 12), so the
+# tiles (C = 16, 8, 16, 8 and 8 lines) run across z-planes (n1 = 8, 10, 12,
+# 10, 12), so the
 # neighbour of a line at the plane's first or last y row is the mirror, a
 # wrap-around line in the same tile, or a line of another tile.
 ROW_TILE_CASES = [
     ((32, 8, 1024), (0.03, 0.05, 1 / 1024), (NE, P, NE)),
     ((32, 10, 820), (0.03, 0.05, 1 / 820), (NE, NE, P)),
     ((64, 12, 688), (1 / 64, 0.05, 1 / 688), (P, P, NE)),
+    # radix-10 rows (lines of 10 and 20 threads, tiles of 80 and 160 threads
+    # that end inside a wavefront), 8 lines per tile
+    ((200, 10, 820), (1 / 200, 0.05, 1 / 820), (NE, P, NE)),
+    ((400, 12, 688), (1 / 400, 0.05, 1 / 688), (P, NE, P)),
 ]
 RT_IDS = ["x".join(map(str, n)) + "-" + "".join(b[0] for b in bc) for n, _, bc in ROW_TILE_CASES]
 
