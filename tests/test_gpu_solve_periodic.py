@@ -113,9 +113,8 @@ def test_periodic_eigenfunction_invariant(pc, n, h, bc, ks, ph):
 # stages the phi of its tile of C consecutive x-lines in LDS and reads a y
 # neighbour from there when that line is in the tile.  On these grids the
 # tiles (C = 16, 8, 16, 8 and 8 lines) run across z-planes (n1 = 8, 10, 12,
-# 10, 12), so the
-# neighbour of a line at the plane's first or last y row is the mirror, a
-# wrap-around line in the same tile, or a line of another tile.
+# 10, 12), so the neighbour of a line at the plane's first or last y row is
+# the mirror, a wrap-around line in the same tile, or a line of another tile.
 ROW_TILE_CASES = [
     ((32, 8, 1024), (0.03, 0.05, 1 / 1024), (NE, P, NE)),
     ((32, 10, 820), (0.03, 0.05, 1 / 820), (NE, NE, P)),
